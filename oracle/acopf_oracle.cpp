@@ -1,0 +1,1240 @@
+// Serial FP64 CPU oracle for the component-wise two-level ADMM for ACOPF
+// (Kim & Kim, "Accelerated Computation and Tracking of AC Optimal Power Flow
+// Solutions Using GPUs", PSCC 2022).
+//
+// TEST INFRASTRUCTURE ONLY. This file is the plain, slow reference that the
+// GPU path is checked against. Only the test suite, the smoke check and the
+// CPU-baseline leg of the benchmark may load it. It shares no code, header or
+// constant with the HIP library: it is written from the paper (and from Lin &
+// More 1999 for the trust-region Newton method) on its own.
+//
+// Build: g++ -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, IEEE
+// division and square root; sin/cos from the C library).
+//
+// Layout of the coupling vectors (canonical order, shared with the library's
+// get_state only as a documented convention): generator g owns couplings
+// 2g (p_g) and 2g+1 (q_g); branch l owns 2*n_gen + 8l + k for
+// k = 0..7: p_ij, q_ij, p_ji, q_ji, w_i(ij), theta_i(ij), w_j(ij), theta_j(ij).
+// Each coupling reads u_k - v_k + z_k = 0 with u the generator/branch side
+// and v the bus side (Section II-B, II-C).
+//
+// Parity status per function (what the CPU tests pin it to) is listed in the
+// test files; nothing here is "parity unpinned" except the warm-start load
+// perturbation, which has no closed form.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Counting scalar: wraps a double and counts + - * / sqrt (1 each) and sin,
+// cos (separately). Used to obtain the exact algorithmic flop count of a
+// branch solve; the doubles it carries are bit-identical to plain double
+// evaluation of the same expressions.
+// ---------------------------------------------------------------------------
+struct FlopTally {
+  long long addsub = 0, mul = 0, div = 0, sqrt_ = 0, trig = 0;
+  long long total() const { return addsub + mul + div + sqrt_; }
+};
+thread_local FlopTally g_tally;
+
+struct CR {
+  double v;
+  CR() : v(0.0) {}
+  CR(double d) : v(d) {}  // NOLINT: implicit on purpose
+  CR& operator+=(CR o) { ++g_tally.addsub; v += o.v; return *this; }
+  CR& operator-=(CR o) { ++g_tally.addsub; v -= o.v; return *this; }
+  CR& operator*=(CR o) { ++g_tally.mul; v *= o.v; return *this; }
+  CR& operator/=(CR o) { ++g_tally.div; v /= o.v; return *this; }
+};
+inline CR operator+(CR a, CR b) { ++g_tally.addsub; return CR(a.v + b.v); }
+inline CR operator-(CR a, CR b) { ++g_tally.addsub; return CR(a.v - b.v); }
+inline CR operator*(CR a, CR b) { ++g_tally.mul; return CR(a.v * b.v); }
+inline CR operator/(CR a, CR b) { ++g_tally.div; return CR(a.v / b.v); }
+inline CR operator-(CR a) { return CR(-a.v); }
+inline bool operator<(CR a, CR b) { return a.v < b.v; }
+inline bool operator>(CR a, CR b) { return a.v > b.v; }
+inline bool operator<=(CR a, CR b) { return a.v <= b.v; }
+inline bool operator>=(CR a, CR b) { return a.v >= b.v; }
+inline bool operator==(CR a, CR b) { return a.v == b.v; }
+inline bool operator!=(CR a, CR b) { return a.v != b.v; }
+inline CR sqrt(CR a) { ++g_tally.sqrt_; return CR(std::sqrt(a.v)); }
+inline CR sin(CR a) { ++g_tally.trig; return CR(std::sin(a.v)); }
+inline CR cos(CR a) { ++g_tally.trig; return CR(std::cos(a.v)); }
+inline double val(CR a) { return a.v; }
+inline double val(double a) { return a; }
+
+template <class R> inline R rabs(R a) { return a < R(0.0) ? -a : a; }
+template <class R> inline R rmin(R a, R b) { return b < a ? b : a; }
+template <class R> inline R rmax(R a, R b) { return a < b ? b : a; }
+template <class R> inline R rsqrt_(R a) { using std::sqrt; return sqrt(a); }
+template <class R> inline R rsin(R a) { using std::sin; return sin(a); }
+template <class R> inline R rcos(R a) { using std::cos; return cos(a); }
+
+constexpr int NMAX = 8;
+constexpr double TWO_PI = 6.283185307179586476925286766559;
+constexpr double INF = std::numeric_limits<double>::infinity();
+
+}  // namespace
+
+extern "C" {
+
+// Parameters of the method. Defaults live in the Python binding.
+typedef struct {
+  double rho_pq, rho_va;      // ADMM penalties (Table 1: power / voltage)
+  double obj_scale;           // objective scaling inside the ADMM (Sec. IV-A)
+  double rate_scale;          // line-limit tightening, 0.99 (Sec. IV-A)
+  double beta0, beta_gamma, beta_omega, beta_max, lambda_max;  // outer level
+  double eps_pri, eps_dual, eps_z;                             // termination
+  int32_t max_outer, max_inner;
+  double tron_gtol, tron_ftol;
+  int32_t tron_maxit;
+  double al_rho0, al_rho_growth, al_rho_max, al_tol, al_shrink;
+  int32_t al_maxit;
+} ora_params;
+
+// Event counters of branch solves (summed over calls).
+typedef struct {
+  long long branch_solves, tron_calls, tron_iters, n_fgh, n_f, cauchy_trials,
+      cg_iters, chol_attempts, ps_trials, al_iters, tron_converged,
+      tron_maxit, tron_stall, flops, trig;
+} ora_stats;
+
+}  // extern "C"
+
+namespace {
+
+enum { TRON_CONVERGED = 0, TRON_MAXIT = 1, TRON_STALL = 2 };
+
+// ---------------------------------------------------------------------------
+// Trust-region Newton method for  min f(x)  s.t.  lo <= x <= hi  (n <= NMAX)
+// after Lin & More (1999), as used for the branch subproblems (Sec. III-B):
+// a generalized Cauchy step along the projected gradient, then subspace
+// steps by preconditioned conjugate gradients with Steihaug's treatment of
+// negative curvature and the trust-region boundary, each followed by a
+// projected search; the trust-region ratio test decides acceptance.
+// Dense Cholesky of the scaled free Hessian (shifted when not positive
+// definite) is the preconditioner: for n <= 6 the incomplete factorization
+// of Lin & More is the complete one.
+// ---------------------------------------------------------------------------
+struct TronConst {
+  double eta0 = 1e-4, eta1 = 0.25, eta2 = 0.75;
+  double sigma1 = 0.25, sigma2 = 0.5, sigma3 = 4.0;
+  double mu0 = 0.01, interpf = 0.1, extrapf = 10.0;
+  int max_trials = 20;
+  double cgtol = 0.1;
+  double shift_min = 1e-3;
+  int max_chol = 20;
+};
+
+template <class R>
+inline R clampd(R t, double lo, double hi) {
+  if (t < R(lo)) return R(lo);
+  if (t > R(hi)) return R(hi);
+  return t;
+}
+
+// q(s) = g's + 1/2 s'Hs
+template <class R>
+R model_q(int n, const R* g, const R* H, const R* s) {
+  R gs = R(0.0), sHs = R(0.0);
+  for (int i = 0; i < n; ++i) {
+    gs = gs + g[i] * s[i];
+    R hi = R(0.0);
+    for (int j = 0; j < n; ++j) hi = hi + H[i * n + j] * s[j];
+    sHs = sHs + s[i] * hi;
+  }
+  return gs + R(0.5) * sHs;
+}
+
+template <class R>
+R dotv(int n, const R* a, const R* b) {
+  R t = R(0.0);
+  for (int i = 0; i < n; ++i) t = t + a[i] * b[i];
+  return t;
+}
+
+// Step from a to the sphere ||a + tau p|| = delta, tau >= 0.
+template <class R>
+R to_boundary(int n, const R* a, const R* p, R delta) {
+  R ap = dotv(n, a, p), pp = dotv(n, p, p), aa = dotv(n, a, a);
+  R dd = delta * delta - aa;
+  if (dd < R(0.0)) dd = R(0.0);
+  R rad = ap * ap + pp * dd;
+  R sq = rsqrt_(rad);
+  R tau;
+  if (ap >= R(0.0)) {
+    R den = ap + sq;
+    tau = den > R(0.0) ? dd / den : R(0.0);
+  } else {
+    tau = (sq - ap) / pp;
+  }
+  return tau;
+}
+
+// Generalized Cauchy point (Lin & More, Sec. 3).
+template <class R>
+void cauchy_step(int n, const R* x, const R* g, const R* H, const double* lo,
+                 const double* hi, R delta, R& alpha, R* w, ora_stats* st,
+                 const TronConst& C) {
+  // largest breakpoint of the projected path x(alpha) = P(x - alpha g)
+  R brpt = R(0.0);
+  for (int i = 0; i < n; ++i) {
+    R bp = R(0.0);
+    if (g[i] > R(0.0)) {
+      bp = lo[i] == -INF ? R(INF) : (x[i] - R(lo[i])) / g[i];
+    } else if (g[i] < R(0.0)) {
+      bp = hi[i] == INF ? R(INF) : (x[i] - R(hi[i])) / g[i];
+    }
+    brpt = rmax(brpt, bp);
+  }
+  R s[NMAX], wt[NMAX], st2[NMAX];
+  auto trial = [&](R a, R* wout, R* sout) {
+    for (int i = 0; i < n; ++i) {
+      wout[i] = clampd(x[i] - a * g[i], lo[i], hi[i]);
+      sout[i] = wout[i] - x[i];
+    }
+  };
+  auto accept = [&](const R* sv) {
+    R sn = rsqrt_(dotv(n, sv, sv));
+    if (sn > delta) return false;
+    R q = model_q(n, g, H, sv);
+    return q <= R(C.mu0) * dotv(n, g, sv);
+  };
+  trial(alpha, w, s);
+  ++st->cauchy_trials;
+  if (accept(s)) {
+    // extrapolate while the conditions hold and the path still bends
+    for (int t = 0; t < C.max_trials; ++t) {
+      if (alpha > brpt) break;
+      R a2 = alpha * R(C.extrapf);
+      trial(a2, wt, st2);
+      ++st->cauchy_trials;
+      if (!accept(st2)) break;
+      alpha = a2;
+      for (int i = 0; i < n; ++i) w[i] = wt[i];
+    }
+  } else {
+    for (int t = 0; t < C.max_trials; ++t) {
+      alpha = alpha * R(C.interpf);
+      trial(alpha, w, s);
+      ++st->cauchy_trials;
+      if (accept(s)) break;
+    }
+  }
+}
+
+// Dense Cholesky A = L L' (lower, row-major, m x m). Returns false when a
+// pivot is not positive.
+template <class R>
+bool cholesky(int m, const R* A, R* L) {
+  for (int i = 0; i < m * m; ++i) L[i] = R(0.0);
+  for (int j = 0; j < m; ++j) {
+    R d = A[j * m + j];
+    for (int k = 0; k < j; ++k) d = d - L[j * m + k] * L[j * m + k];
+    if (!(d > R(0.0))) return false;
+    R ljj = rsqrt_(d);
+    L[j * m + j] = ljj;
+    for (int i = j + 1; i < m; ++i) {
+      R t = A[i * m + j];
+      for (int k = 0; k < j; ++k) t = t - L[i * m + k] * L[j * m + k];
+      L[i * m + j] = t / ljj;
+    }
+  }
+  return true;
+}
+
+// z = M^{-1} r with M = D^{-1} L L' D^{-1}
+template <class R>
+void precond(int m, const R* L, const R* D, const R* r, R* z) {
+  R t[NMAX];
+  for (int i = 0; i < m; ++i) {
+    R a = D[i] * r[i];
+    for (int k = 0; k < i; ++k) a = a - L[i * m + k] * t[k];
+    t[i] = a / L[i * m + i];
+  }
+  for (int i = m - 1; i >= 0; --i) {
+    R a = t[i];
+    for (int k = i + 1; k < m; ++k) a = a - L[k * m + i] * z[k];
+    z[i] = a / L[i * m + i];
+  }
+  for (int i = 0; i < m; ++i) z[i] = D[i] * z[i];
+}
+
+// Subspace steps from the Cauchy point w (in/out). s = w - x on exit.
+template <class R>
+void subspace_step(int n, const R* x, const R* g, const R* H, const double* lo,
+                   const double* hi, R delta, R* w, ora_stats* st,
+                   const TronConst& C) {
+  R s[NMAX];
+  for (int i = 0; i < n; ++i) s[i] = w[i] - x[i];
+  for (int pass = 0; pass < n; ++pass) {
+    int F[NMAX], nf = 0;
+    for (int i = 0; i < n; ++i)
+      if (w[i] > R(lo[i]) && w[i] < R(hi[i])) F[nf++] = i;
+    if (nf == 0) break;
+    // gradient of the model at w
+    R gq[NMAX];
+    for (int i = 0; i < n; ++i) {
+      R t = g[i];
+      for (int j = 0; j < n; ++j) t = t + H[i * n + j] * s[j];
+      gq[i] = t;
+    }
+    R r[NMAX], B[NMAX * NMAX];
+    for (int a = 0; a < nf; ++a) {
+      r[a] = -gq[F[a]];
+      for (int b = 0; b < nf; ++b) B[a * nf + b] = H[F[a] * n + F[b]];
+    }
+    R rnorm0 = rsqrt_(dotv(nf, r, r));
+    if (!(rnorm0 > R(0.0))) break;
+    // preconditioner: Cholesky of D B D + shift I, D = diag(1/sqrt|B_aa|)
+    R D[NMAX], Bs[NMAX * NMAX], L[NMAX * NMAX];
+    for (int a = 0; a < nf; ++a) {
+      R baa = rabs(B[a * nf + a]);
+      D[a] = baa > R(0.0) ? R(1.0) / rsqrt_(baa) : R(1.0);
+    }
+    R mind = R(INF);
+    for (int a = 0; a < nf; ++a) {
+      for (int b = 0; b < nf; ++b) Bs[a * nf + b] = D[a] * B[a * nf + b] * D[b];
+      mind = rmin(mind, Bs[a * nf + a]);
+    }
+    R shift = mind > R(0.0) ? R(0.0) : R(C.shift_min) - mind;
+    bool ok = false;
+    for (int att = 0; att < C.max_chol; ++att) {
+      R A[NMAX * NMAX];
+      for (int q = 0; q < nf * nf; ++q) A[q] = Bs[q];
+      for (int a = 0; a < nf; ++a) A[a * nf + a] = A[a * nf + a] + shift;
+      ++st->chol_attempts;
+      if (cholesky(nf, A, L)) { ok = true; break; }
+      shift = rmax(R(2.0) * shift, R(C.shift_min));
+    }
+    if (!ok) {
+      for (int q = 0; q < nf * nf; ++q) L[q] = R(0.0);
+      for (int a = 0; a < nf; ++a) { L[a * nf + a] = R(1.0); D[a] = R(1.0); }
+    }
+    // Steihaug PCG on min 1/2 d'Bd - r'd  s.t. ||s + d|| <= delta
+    R d[NMAX], res[NMAX], zz[NMAX], p[NMAX], Bp[NMAX];
+    for (int a = 0; a < nf; ++a) { d[a] = R(0.0); res[a] = r[a]; }
+    precond(nf, L, D, res, zz);
+    for (int a = 0; a < nf; ++a) p[a] = zz[a];
+    R rz = dotv(nf, res, zz);
+    bool boundary = false;
+    for (int k = 0; k < nf; ++k) {
+      ++st->cg_iters;
+      for (int a = 0; a < nf; ++a) {
+        R t = R(0.0);
+        for (int b = 0; b < nf; ++b) t = t + B[a * nf + b] * p[b];
+        Bp[a] = t;
+      }
+      R pBp = dotv(nf, p, Bp);
+      // full-space vectors for the trust-region test
+      R sd[NMAX], pf[NMAX];
+      for (int i = 0; i < n; ++i) { sd[i] = s[i]; pf[i] = R(0.0); }
+      for (int a = 0; a < nf; ++a) { sd[F[a]] = s[F[a]] + d[a]; pf[F[a]] = p[a]; }
+      if (!(pBp > R(0.0))) {
+        R tau = to_boundary(n, sd, pf, delta);
+        for (int a = 0; a < nf; ++a) d[a] = d[a] + tau * p[a];
+        boundary = true;
+        break;
+      }
+      R alpha = rz / pBp;
+      R tr[NMAX];
+      for (int i = 0; i < n; ++i) tr[i] = sd[i] + alpha * pf[i];
+      if (rsqrt_(dotv(n, tr, tr)) >= delta) {
+        R tau = to_boundary(n, sd, pf, delta);
+        for (int a = 0; a < nf; ++a) d[a] = d[a] + tau * p[a];
+        boundary = true;
+        break;
+      }
+      for (int a = 0; a < nf; ++a) {
+        d[a] = d[a] + alpha * p[a];
+        res[a] = res[a] - alpha * Bp[a];
+      }
+      if (rsqrt_(dotv(nf, res, res)) <= R(C.cgtol) * rnorm0) break;
+      precond(nf, L, D, res, zz);
+      R rzn = dotv(nf, res, zz);
+      R bcg = rzn / rz;
+      rz = rzn;
+      for (int a = 0; a < nf; ++a) p[a] = zz[a] + bcg * p[a];
+    }
+    // projected search along d from w
+    R qw = model_q(n, g, H, s);
+    R beta = R(1.0);
+    bool acc = false;
+    R wt[NMAX], stv[NMAX];
+    for (int t = 0; t < C.max_trials; ++t) {
+      ++st->ps_trials;
+      for (int i = 0; i < n; ++i) wt[i] = w[i];
+      for (int a = 0; a < nf; ++a) {
+        int i = F[a];
+        wt[i] = clampd(w[i] + beta * d[a], lo[i], hi[i]);
+      }
+      for (int i = 0; i < n; ++i) stv[i] = wt[i] - x[i];
+      R dw[NMAX];
+      for (int i = 0; i < n; ++i) dw[i] = wt[i] - w[i];
+      R qt = model_q(n, g, H, stv);
+      if (qt <= qw + R(C.mu0) * dotv(n, gq, dw)) { acc = true; break; }
+      beta = beta * R(0.5);
+    }
+    if (!acc) break;
+    bool hit = false;
+    for (int a = 0; a < nf; ++a) {
+      int i = F[a];
+      if (wt[i] == R(lo[i]) || wt[i] == R(hi[i])) hit = true;
+    }
+    for (int i = 0; i < n; ++i) { w[i] = wt[i]; s[i] = stv[i]; }
+    if (boundary || !hit) break;
+  }
+}
+
+// Problem interface: f(x) and (f, g, H)(x) with H dense row-major n x n.
+template <class R, class P>
+int tron(P& prob, int n, R* x, const double* lo, const double* hi,
+         const ora_params& prm, ora_stats* st, const TronConst& C) {
+  ++st->tron_calls;
+  for (int i = 0; i < n; ++i) x[i] = clampd(x[i], lo[i], hi[i]);
+  R f, g[NMAX], H[NMAX * NMAX];
+  prob.fgh(x, f, g, H);
+  ++st->n_fgh;
+  R pg2 = R(0.0);
+  for (int i = 0; i < n; ++i) {
+    R t = clampd(x[i] - g[i], lo[i], hi[i]) - x[i];
+    pg2 = pg2 + t * t;
+  }
+  R delta = rsqrt_(pg2);
+  if (!(delta > R(0.0))) delta = R(1.0);
+  R alphac = R(1.0);
+  int status = TRON_MAXIT;
+  for (int it = 0; it < prm.tron_maxit; ++it) {
+    R pginf = R(0.0);
+    for (int i = 0; i < n; ++i)
+      pginf = rmax(pginf, rabs(clampd(x[i] - g[i], lo[i], hi[i]) - x[i]));
+    if (pginf <= R(prm.tron_gtol)) { status = TRON_CONVERGED; break; }
+    ++st->tron_iters;
+    R w[NMAX], s[NMAX];
+    cauchy_step(n, x, g, H, lo, hi, delta, alphac, w, st, C);
+    subspace_step(n, x, g, H, lo, hi, delta, w, st, C);
+    for (int i = 0; i < n; ++i) s[i] = w[i] - x[i];
+    R prered = -model_q(n, g, H, s);
+    R snorm = rsqrt_(dotv(n, s, s));
+    if (!(prered > R(0.0))) { status = TRON_STALL; break; }
+    // a full (interior) Newton-type step whose predicted decrease is at
+    // the rounding level of f: accept it and stop
+    if (snorm < delta &&
+        prered <= R(prm.tron_ftol) * (R(1.0) + rabs(f))) {
+      for (int i = 0; i < n; ++i) x[i] = w[i];
+      status = TRON_CONVERGED;
+      break;
+    }
+    R fw = prob.f(w);
+    ++st->n_f;
+    R actred = f - fw;
+    R ratio = actred / prered;
+    if (ratio <= R(C.eta0)) {
+      delta = R(C.sigma2) * rmin(snorm, delta);
+    } else if (ratio <= R(C.eta1)) {
+      delta = rmax(R(C.sigma1) * delta, R(C.sigma2) * rmin(snorm, delta));
+    } else if (ratio >= R(C.eta2)) {
+      delta = rmin(R(C.sigma3) * delta, rmax(delta, R(C.sigma3) * snorm));
+    }
+    if (ratio > R(C.eta0)) {
+      for (int i = 0; i < n; ++i) x[i] = w[i];
+      prob.fgh(x, f, g, H);
+      ++st->n_fgh;
+    }
+    R xn = rsqrt_(dotv(n, x, x));
+    if (delta <= R(1e-15) * rmax(R(1.0), xn)) { status = TRON_STALL; break; }
+  }
+  if (status == TRON_CONVERGED) ++st->tron_converged;
+  else if (status == TRON_MAXIT) ++st->tron_maxit;
+  else ++st->tron_stall;
+  return status;
+}
+
+// ---------------------------------------------------------------------------
+// Branch subproblem, eq. (branch): variables x = (v_i, v_j, theta_i(ij),
+// theta_j(ij)[, s_ij, s_ji]); flows from eqs. (pij)-(qji) with
+// w^R = v_i v_j cos(theta_i - theta_j), w^I = v_i v_j sin(theta_i - theta_j).
+// ---------------------------------------------------------------------------
+struct BranchData {
+  double gii, bii, gij, bij, gji, bji, gjj, bjj;
+  double lo[6], hi[6];
+  int n;  // 4 or 6
+  double vb[8], z[8], y[8], rho[8];
+  double ltil[2], rtil;
+};
+
+// Values, gradients and Hessians (in the 4 voltage variables) of the eight
+// branch-side coupling quantities a_k(x).
+template <class R>
+void branch_terms(const BranchData& d, const R* x, R* a, R (*ga)[4],
+                  R (*Ha)[4][4], bool derivs) {
+  R vi = x[0], vj = x[1], ti = x[2], tj = x[3];
+  R dt = ti - tj;
+  R cs = rcos(dt), sn = rsin(dt);
+  R vv = vi * vj;
+  R WR = vv * cs, WI = vv * sn;
+  R wi = vi * vi, wj = vj * vj;
+  R gii = d.gii, bii = d.bii, gij = d.gij, bij = d.bij, gji = d.gji,
+    bji = d.bji, gjj = d.gjj, bjj = d.bjj;
+  a[0] = gii * wi + gij * WR + bij * WI;
+  a[1] = -bii * wi - bij * WR + gij * WI;
+  a[2] = gjj * wj + gji * WR - bji * WI;
+  a[3] = -bjj * wj - bji * WR - gji * WI;
+  a[4] = wi;
+  a[5] = ti;
+  a[6] = wj;
+  a[7] = tj;
+  if (!derivs) return;
+  // first derivatives of w_i, w_j, w^R, w^I
+  R dwi[4] = {R(2.0) * vi, R(0.0), R(0.0), R(0.0)};
+  R dwj[4] = {R(0.0), R(2.0) * vj, R(0.0), R(0.0)};
+  R dWR[4] = {vj * cs, vi * cs, -WI, WI};
+  R dWI[4] = {vj * sn, vi * sn, WR, -WR};
+  // second derivatives
+  R hWR[4][4] = {{R(0.0), cs, -vj * sn, vj * sn},
+                 {cs, R(0.0), -vi * sn, vi * sn},
+                 {-vj * sn, -vi * sn, -WR, WR},
+                 {vj * sn, vi * sn, WR, -WR}};
+  R hWI[4][4] = {{R(0.0), sn, vj * cs, -vj * cs},
+                 {sn, R(0.0), vi * cs, -vi * cs},
+                 {vj * cs, vi * cs, -WI, WI},
+                 {-vj * cs, -vi * cs, WI, -WI}};
+  // coefficients (cw, cR, cI) of each flow in (w_own, w^R, w^I)
+  R coef[4][3] = {{gii, gij, bij}, {-bii, -bij, gij},
+                  {gjj, gji, -bji}, {-bjj, -bji, -gji}};
+  for (int k = 0; k < 4; ++k) {
+    const R* dw = (k < 2) ? dwi : dwj;
+    int own = (k < 2) ? 0 : 1;
+    for (int p = 0; p < 4; ++p)
+      ga[k][p] = coef[k][0] * dw[p] + coef[k][1] * dWR[p] + coef[k][2] * dWI[p];
+    for (int p = 0; p < 4; ++p)
+      for (int q = 0; q < 4; ++q) {
+        R hw = (p == own && q == own) ? R(2.0) * coef[k][0] : R(0.0);
+        Ha[k][p][q] = hw + coef[k][1] * hWR[p][q] + coef[k][2] * hWI[p][q];
+      }
+  }
+  for (int k = 4; k < 8; ++k)
+    for (int p = 0; p < 4; ++p) {
+      ga[k][p] = R(0.0);
+      for (int q = 0; q < 4; ++q) Ha[k][p][q] = R(0.0);
+    }
+  ga[4][0] = R(2.0) * vi;
+  Ha[4][0][0] = R(2.0);
+  ga[5][2] = R(1.0);
+  ga[6][1] = R(2.0) * vj;
+  Ha[6][1][1] = R(2.0);
+  ga[7][3] = R(1.0);
+}
+
+template <class R>
+struct BranchProblem {
+  const BranchData& d;
+  explicit BranchProblem(const BranchData& dd) : d(dd) {}
+
+  // F(x) = sum_k y_k r_k + rho_k/2 r_k^2 + sum_e ltil_e c_e + rtil/2 c_e^2
+  // with r_k = a_k(x) - v_k + z_k and c_e = p_e^2 + q_e^2 + s_e.
+  R f(const R* x) {
+    R a[8];
+    branch_terms<R>(d, x, a, nullptr, nullptr, false);
+    R F = R(0.0);
+    for (int k = 0; k < 8; ++k) {
+      R r = a[k] - R(d.vb[k]) + R(d.z[k]);
+      F = F + R(d.y[k]) * r + R(0.5) * R(d.rho[k]) * r * r;
+    }
+    if (d.n == 6) {
+      for (int e = 0; e < 2; ++e) {
+        R c = a[2 * e] * a[2 * e] + a[2 * e + 1] * a[2 * e + 1] + x[4 + e];
+        F = F + R(d.ltil[e]) * c + R(0.5) * R(d.rtil) * c * c;
+      }
+    }
+    return F;
+  }
+
+  void fgh(const R* x, R& F, R* g, R* H) {
+    const int n = d.n;
+    R a[8], ga[8][4], Ha[8][4][4];
+    branch_terms<R>(d, x, a, ga, Ha, true);
+    F = R(0.0);
+    for (int i = 0; i < n; ++i) {
+      g[i] = R(0.0);
+      for (int j = 0; j < n; ++j) H[i * n + j] = R(0.0);
+    }
+    for (int k = 0; k < 8; ++k) {
+      R r = a[k] - R(d.vb[k]) + R(d.z[k]);
+      F = F + R(d.y[k]) * r + R(0.5) * R(d.rho[k]) * r * r;
+      R m = R(d.y[k]) + R(d.rho[k]) * r;  // dF/da_k
+      for (int p = 0; p < 4; ++p) {
+        g[p] = g[p] + m * ga[k][p];
+        for (int q = 0; q < 4; ++q)
+          H[p * n + q] = H[p * n + q] + R(d.rho[k]) * ga[k][p] * ga[k][q] +
+                         m * Ha[k][p][q];
+      }
+    }
+    if (n == 6) {
+      for (int e = 0; e < 2; ++e) {
+        int kp = 2 * e, kq = 2 * e + 1, sidx = 4 + e;
+        R c = a[kp] * a[kp] + a[kq] * a[kq] + x[sidx];
+        F = F + R(d.ltil[e]) * c + R(0.5) * R(d.rtil) * c * c;
+        R m = R(d.ltil[e]) + R(d.rtil) * c;  // dF/dc
+        // grad c over all six variables
+        R gc[6];
+        for (int p = 0; p < 4; ++p)
+          gc[p] = R(2.0) * a[kp] * ga[kp][p] + R(2.0) * a[kq] * ga[kq][p];
+        gc[4] = R(0.0);
+        gc[5] = R(0.0);
+        gc[sidx] = R(1.0);
+        for (int p = 0; p < 6; ++p) {
+          g[p] = g[p] + m * gc[p];
+          for (int q = 0; q < 6; ++q) {
+            R hc = R(0.0);
+            if (p < 4 && q < 4)
+              hc = R(2.0) * ga[kp][p] * ga[kp][q] + R(2.0) * a[kp] * Ha[kp][p][q] +
+                   R(2.0) * ga[kq][p] * ga[kq][q] + R(2.0) * a[kq] * Ha[kq][p][q];
+            H[p * 6 + q] = H[p * 6 + q] + R(d.rtil) * gc[p] * gc[q] + m * hc;
+          }
+        }
+      }
+    }
+  }
+};
+
+// Branch solve (Sec. II-C, III-B): one TRON solve for unrated branches; for
+// rated ones an augmented-Lagrangian loop on p^2 + q^2 + s = 0 around TRON.
+// x (6), ltil (2), rtil are the persistent branch state; u (8) receives the
+// branch-side coupling values a_k(x).
+template <class R>
+void branch_solve_t(BranchData& d, double* x6, double* ltil, double* rtil,
+                    double* u8, const ora_params& prm, ora_stats* st) {
+  TronConst C;
+  ++st->branch_solves;
+  R x[NMAX];
+  for (int i = 0; i < d.n; ++i) x[i] = R(x6[i]);
+  if (d.n == 4) {
+    BranchProblem<R> P(d);
+    tron<R>(P, 4, x, d.lo, d.hi, prm, st, C);
+  } else {
+    d.ltil[0] = ltil[0];
+    d.ltil[1] = ltil[1];
+    d.rtil = *rtil;
+    R cprev = R(INF);
+    for (int t = 0; t < prm.al_maxit; ++t) {
+      ++st->al_iters;
+      BranchProblem<R> P(d);
+      tron<R>(P, 6, x, d.lo, d.hi, prm, st, C);
+      R a[8];
+      branch_terms<R>(d, x, a, nullptr, nullptr, false);
+      R c0 = a[0] * a[0] + a[1] * a[1] + x[4];
+      R c1 = a[2] * a[2] + a[3] * a[3] + x[5];
+      R cn = rmax(rabs(c0), rabs(c1));
+      if (cn <= R(prm.al_tol)) break;
+      d.ltil[0] = val(R(d.ltil[0]) + R(d.rtil) * c0);
+      d.ltil[1] = val(R(d.ltil[1]) + R(d.rtil) * c1);
+      if (cn > R(prm.al_shrink) * cprev)
+        d.rtil = val(rmin(R(d.rtil) * R(prm.al_rho_growth), R(prm.al_rho_max)));
+      cprev = cn;
+    }
+    ltil[0] = d.ltil[0];
+    ltil[1] = d.ltil[1];
+    *rtil = d.rtil;
+  }
+  R a[8];
+  branch_terms<R>(d, x, a, nullptr, nullptr, false);
+  for (int k = 0; k < 8; ++k) u8[k] = val(a[k]);
+  for (int i = 0; i < d.n; ++i) x6[i] = val(x[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Whole-grid state
+// ---------------------------------------------------------------------------
+struct Oracle {
+  ora_params p;
+  int nb, ng, nl, ref, m;
+  double base;
+  std::vector<double> pd, qd, gs, bs, vmin, vmax;
+  std::vector<int> gbus;
+  std::vector<double> pmin, pmax, qmin, qmax, c2, c1, c0;
+  std::vector<int> from, to;
+  // admittances (Sec. II-A, below eq. acopf) and squared scaled ratings
+  std::vector<double> gii, bii, gij, bij, gji, bji, gjj, bjj, rate2;
+  std::vector<int> rated;
+  // couplings
+  std::vector<double> u, v, z, y, lam, rho, vprev;
+  // branch state
+  std::vector<double> bx, ltil, rtil;
+  // per-bus incidence: gens, branches as from, branches as to
+  std::vector<std::vector<int>> bus_gens, bus_from, bus_to;
+  // outer-level scalars (Algorithm 1)
+  double beta = 0, znorm_prev = INF, r_pri = 0, r_dual = 0, r_z = 0;
+  int outer = 0, inner_total = 0, inner_in_outer = 0, status = 1;
+  bool solved_once = false;
+  std::vector<double> hist;  // per inner iteration: r_pri r_dual r_z obj beta outer
+  ora_stats st{};
+  bool count_flops = false;
+};
+
+int coupling_gen(int g, int k) { return 2 * g + k; }
+
+}  // namespace
+
+extern "C" {
+
+typedef struct {
+  int32_t n_bus, n_gen, n_branch, ref_bus;
+  double base_mva;
+  const double *pd, *qd, *gs, *bs, *vmin, *vmax;
+  const int32_t* gen_bus;
+  const double *pmin, *pmax, *qmin, *qmax, *c2, *c1, *c0;
+  const int32_t *br_from, *br_to;
+  const double *r, *x, *b, *tap, *shift, *rate;
+} ora_grid;
+
+// Returns nullptr on invalid input.
+void* ora_create(const ora_grid* G, const ora_params* P) {
+  auto* o = new Oracle();
+  o->p = *P;
+  o->nb = G->n_bus;
+  o->ng = G->n_gen;
+  o->nl = G->n_branch;
+  o->ref = G->ref_bus;
+  o->base = G->base_mva;
+  o->m = 2 * o->ng + 8 * o->nl;
+  auto cp = [](const double* s, int n) { return std::vector<double>(s, s + n); };
+  o->pd = cp(G->pd, o->nb); o->qd = cp(G->qd, o->nb);
+  o->gs = cp(G->gs, o->nb); o->bs = cp(G->bs, o->nb);
+  o->vmin = cp(G->vmin, o->nb); o->vmax = cp(G->vmax, o->nb);
+  o->gbus.assign(G->gen_bus, G->gen_bus + o->ng);
+  o->pmin = cp(G->pmin, o->ng); o->pmax = cp(G->pmax, o->ng);
+  o->qmin = cp(G->qmin, o->ng); o->qmax = cp(G->qmax, o->ng);
+  o->c2 = cp(G->c2, o->ng); o->c1 = cp(G->c1, o->ng); o->c0 = cp(G->c0, o->ng);
+  o->from.assign(G->br_from, G->br_from + o->nl);
+  o->to.assign(G->br_to, G->br_to + o->nl);
+  const int nl = o->nl;
+  o->gii.resize(nl); o->bii.resize(nl); o->gij.resize(nl); o->bij.resize(nl);
+  o->gji.resize(nl); o->bji.resize(nl); o->gjj.resize(nl); o->bjj.resize(nl);
+  o->rate2.resize(nl); o->rated.resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    // series admittance y = 1/(r + jx), shunt j b/2 per end, a = tap e^{j shift}
+    double r = G->r[l], xx = G->x[l];
+    double den = r * r + xx * xx;
+    double yr = r / den, yi = -xx / den;
+    double tap = G->tap[l], sh = G->shift[l];
+    double ar = tap * std::cos(sh), ai = tap * std::sin(sh);
+    double a2 = tap * tap;
+    // (y + j b/2)/|a|^2
+    o->gii[l] = yr / a2;
+    o->bii[l] = (yi + 0.5 * G->b[l]) / a2;
+    // -y / conj(a) = -y a / |a|^2
+    o->gij[l] = -(yr * ar - yi * ai) / a2;
+    o->bij[l] = -(yr * ai + yi * ar) / a2;
+    // -y / a = -y conj(a) / |a|^2
+    o->gji[l] = -(yr * ar + yi * ai) / a2;
+    o->bji[l] = -(yi * ar - yr * ai) / a2;
+    // y + j b/2
+    o->gjj[l] = yr;
+    o->bjj[l] = yi + 0.5 * G->b[l];
+    double rs = G->rate[l] * P->rate_scale;
+    o->rated[l] = G->rate[l] > 0.0 ? 1 : 0;
+    o->rate2[l] = o->rated[l] ? rs * rs : 0.0;
+  }
+  o->bus_gens.assign(o->nb, {});
+  o->bus_from.assign(o->nb, {});
+  o->bus_to.assign(o->nb, {});
+  for (int g = 0; g < o->ng; ++g) o->bus_gens[o->gbus[g]].push_back(g);
+  for (int l = 0; l < nl; ++l) {
+    o->bus_from[o->from[l]].push_back(l);
+    o->bus_to[o->to[l]].push_back(l);
+  }
+  o->u.assign(o->m, 0.0); o->v.assign(o->m, 0.0); o->z.assign(o->m, 0.0);
+  o->y.assign(o->m, 0.0); o->lam.assign(o->m, 0.0); o->rho.assign(o->m, 0.0);
+  o->vprev.assign(o->m, 0.0);
+  for (int g = 0; g < o->ng; ++g) {
+    o->rho[2 * g] = P->rho_pq;
+    o->rho[2 * g + 1] = P->rho_pq;
+  }
+  for (int l = 0; l < nl; ++l) {
+    int b0 = 2 * o->ng + 8 * l;
+    for (int k = 0; k < 4; ++k) o->rho[b0 + k] = P->rho_pq;
+    for (int k = 4; k < 8; ++k) o->rho[b0 + k] = P->rho_va;
+  }
+  o->bx.assign(6 * nl, 0.0);
+  o->ltil.assign(2 * nl, 0.0);
+  o->rtil.assign(nl, P->al_rho0);
+  return o;
+}
+
+void ora_destroy(void* h) { delete static_cast<Oracle*>(h); }
+
+static void fill_branch_data(const Oracle* o, int l, BranchData& d) {
+  d.gii = o->gii[l]; d.bii = o->bii[l]; d.gij = o->gij[l]; d.bij = o->bij[l];
+  d.gji = o->gji[l]; d.bji = o->bji[l]; d.gjj = o->gjj[l]; d.bjj = o->bjj[l];
+  int i = o->from[l], j = o->to[l];
+  d.lo[0] = o->vmin[i]; d.hi[0] = o->vmax[i];
+  d.lo[1] = o->vmin[j]; d.hi[1] = o->vmax[j];
+  d.lo[2] = -TWO_PI; d.hi[2] = TWO_PI;
+  d.lo[3] = -TWO_PI; d.hi[3] = TWO_PI;
+  d.lo[4] = -o->rate2[l]; d.hi[4] = 0.0;
+  d.lo[5] = -o->rate2[l]; d.hi[5] = 0.0;
+  d.n = o->rated[l] ? 6 : 4;
+  int b0 = 2 * o->ng + 8 * l;
+  for (int k = 0; k < 8; ++k) {
+    d.vb[k] = o->v[b0 + k];
+    d.z[k] = o->z[b0 + k];
+    d.y[k] = o->y[b0 + k];
+    d.rho[k] = o->rho[b0 + k];
+  }
+  d.ltil[0] = o->ltil[2 * l];
+  d.ltil[1] = o->ltil[2 * l + 1];
+  d.rtil = o->rtil[l];
+}
+
+// Cold start (Sec. IV-B): p, q, v at the midpoints of their bounds, angles
+// zero, flows from the initial voltages; bus copies equal the component
+// values; z = y = lambda = 0; beta = beta0.
+void ora_cold_init(void* h) {
+  auto* o = static_cast<Oracle*>(h);
+  for (int g = 0; g < o->ng; ++g) {
+    o->u[2 * g] = 0.5 * (o->pmin[g] + o->pmax[g]);
+    o->u[2 * g + 1] = 0.5 * (o->qmin[g] + o->qmax[g]);
+  }
+  for (int l = 0; l < o->nl; ++l) {
+    int i = o->from[l], j = o->to[l];
+    double* x = &o->bx[6 * l];
+    x[0] = 0.5 * (o->vmin[i] + o->vmax[i]);
+    x[1] = 0.5 * (o->vmin[j] + o->vmax[j]);
+    x[2] = 0.0;
+    x[3] = 0.0;
+    BranchData d;
+    fill_branch_data(o, l, d);
+    double a[8];
+    branch_terms<double>(d, x, a, nullptr, nullptr, false);
+    if (o->rated[l]) {
+      double f0 = -(a[0] * a[0] + a[1] * a[1]);
+      double f1 = -(a[2] * a[2] + a[3] * a[3]);
+      x[4] = f0 < -o->rate2[l] ? -o->rate2[l] : (f0 > 0.0 ? 0.0 : f0);
+      x[5] = f1 < -o->rate2[l] ? -o->rate2[l] : (f1 > 0.0 ? 0.0 : f1);
+    } else {
+      x[4] = 0.0;
+      x[5] = 0.0;
+    }
+    int b0 = 2 * o->ng + 8 * l;
+    for (int k = 0; k < 8; ++k) o->u[b0 + k] = a[k];
+    o->ltil[2 * l] = 0.0;
+    o->ltil[2 * l + 1] = 0.0;
+    o->rtil[l] = o->p.al_rho0;
+  }
+  for (int k = 0; k < o->m; ++k) {
+    o->v[k] = o->u[k];
+    o->z[k] = 0.0;
+    o->y[k] = 0.0;
+    o->lam[k] = 0.0;
+  }
+  // the bus angle copies start at zero; the reference angle is zero
+  o->beta = o->p.beta0;
+  o->znorm_prev = INF;
+  o->outer = 0;
+  o->inner_total = 0;
+  o->inner_in_outer = 0;
+  o->status = 1;
+  o->hist.clear();
+}
+
+// Generator step, eq. (qp-bound): min 1/2 Q x^2 - c x on [l, u] gives
+// x = max(l, min(u, c/Q)); Q and c collect the scaled quadratic cost
+// (MW based) and the coupling penalty terms.
+void ora_gen_step(void* h) {
+  auto* o = static_cast<Oracle*>(h);
+  const double B = o->base, s = o->p.obj_scale;
+  for (int g = 0; g < o->ng; ++g) {
+    int kp = 2 * g, kq = 2 * g + 1;
+    double Qp = 2.0 * s * o->c2[g] * B * B + o->rho[kp];
+    double cpv = o->rho[kp] * (o->v[kp] - o->z[kp]) - o->y[kp] - s * o->c1[g] * B;
+    double xp = cpv / Qp;
+    o->u[kp] = std::max(o->pmin[g], std::min(o->pmax[g], xp));
+    double Qq = o->rho[kq];
+    double cq = o->rho[kq] * (o->v[kq] - o->z[kq]) - o->y[kq];
+    double xq = cq / Qq;
+    o->u[kq] = std::max(o->qmin[g], std::min(o->qmax[g], xq));
+  }
+}
+
+void ora_branch_step(void* h) {
+  auto* o = static_cast<Oracle*>(h);
+  for (int l = 0; l < o->nl; ++l) {
+    BranchData d;
+    fill_branch_data(o, l, d);
+    double* u8 = &o->u[2 * o->ng + 8 * l];
+    if (o->count_flops) {
+      FlopTally before = g_tally;
+      branch_solve_t<CR>(d, &o->bx[6 * l], &o->ltil[2 * l], &o->rtil[l], u8,
+                         o->p, &o->st);
+      o->st.flops += g_tally.total() - before.total();
+      o->st.trig += g_tally.trig - before.trig;
+    } else {
+      branch_solve_t<double>(d, &o->bx[6 * l], &o->ltil[2 * l], &o->rtil[l],
+                             u8, o->p, &o->st);
+    }
+  }
+}
+
+// Bus step, eq. (qp-bus): min 1/2 x'Qx - c'x s.t. Ax = b with the two rows of
+// eqs. (pg)-(qg); mu = (A Q^-1 A')^-1 (A Q^-1 c - b), x = Q^-1 (c - A' mu).
+// x holds the bus copies of generator outputs, the bus copies of the flows
+// leaving the bus (p_ij, q_ij on from-ends, p_ji, q_ji on to-ends) and w_i.
+// The angle theta_i enters no constraint: theta = c_theta / Q_theta, and the
+// reference angle is fixed at zero.
+void ora_bus_step(void* h) {
+  auto* o = static_cast<Oracle*>(h);
+  const int ng = o->ng;
+  for (int i = 0; i < o->nb; ++i) {
+    // variable list: index into couplings, row-P coefficient, row-Q coefficient
+    std::vector<int> kidx;
+    std::vector<double> aP, aQ, Qd, cv;
+    for (int g : o->bus_gens[i]) {
+      int kp = coupling_gen(g, 0), kq = coupling_gen(g, 1);
+      kidx.push_back(kp); aP.push_back(1.0); aQ.push_back(0.0);
+      kidx.push_back(kq); aP.push_back(0.0); aQ.push_back(1.0);
+    }
+    for (int l : o->bus_from[i]) {
+      int b0 = 2 * ng + 8 * l;
+      kidx.push_back(b0 + 0); aP.push_back(-1.0); aQ.push_back(0.0);
+      kidx.push_back(b0 + 1); aP.push_back(0.0); aQ.push_back(-1.0);
+    }
+    for (int l : o->bus_to[i]) {
+      int b0 = 2 * ng + 8 * l;
+      kidx.push_back(b0 + 2); aP.push_back(-1.0); aQ.push_back(0.0);
+      kidx.push_back(b0 + 3); aP.push_back(0.0); aQ.push_back(-1.0);
+    }
+    const int K = static_cast<int>(kidx.size());
+    for (int t = 0; t < K; ++t) {
+      int k = kidx[t];
+      Qd.push_back(o->rho[k]);
+      cv.push_back(o->rho[k] * (o->u[k] + o->z[k]) + o->y[k]);
+    }
+    // w_i: one shared variable over all w-couplings of the incident branches
+    double Qw = 0.0, cw = 0.0;
+    double Qt = 0.0, ct = 0.0;
+    for (int l : o->bus_from[i]) {
+      int kw = 2 * ng + 8 * l + 4, kt = kw + 1;
+      Qw += o->rho[kw]; cw += o->rho[kw] * (o->u[kw] + o->z[kw]) + o->y[kw];
+      Qt += o->rho[kt]; ct += o->rho[kt] * (o->u[kt] + o->z[kt]) + o->y[kt];
+    }
+    for (int l : o->bus_to[i]) {
+      int kw = 2 * ng + 8 * l + 6, kt = kw + 1;
+      Qw += o->rho[kw]; cw += o->rho[kw] * (o->u[kw] + o->z[kw]) + o->y[kw];
+      Qt += o->rho[kt]; ct += o->rho[kt] * (o->u[kt] + o->z[kt]) + o->y[kt];
+    }
+    double awP = -o->gs[i], awQ = o->bs[i];
+    // M = A Q^-1 A'
+    double M00 = awP * awP / Qw, M01 = awP * awQ / Qw, M11 = awQ * awQ / Qw;
+    // A Q^-1 c - b
+    double r0 = awP * cw / Qw - o->pd[i], r1 = awQ * cw / Qw - o->qd[i];
+    for (int t = 0; t < K; ++t) {
+      M00 += aP[t] * aP[t] / Qd[t];
+      M01 += aP[t] * aQ[t] / Qd[t];
+      M11 += aQ[t] * aQ[t] / Qd[t];
+      r0 += aP[t] * cv[t] / Qd[t];
+      r1 += aQ[t] * cv[t] / Qd[t];
+    }
+    double det = M00 * M11 - M01 * M01;
+    double mu0 = (M11 * r0 - M01 * r1) / det;
+    double mu1 = (M00 * r1 - M01 * r0) / det;
+    for (int t = 0; t < K; ++t)
+      o->v[kidx[t]] = (cv[t] - aP[t] * mu0 - aQ[t] * mu1) / Qd[t];
+    double w = (cw - awP * mu0 - awQ * mu1) / Qw;
+    double th = (i == o->ref) ? 0.0 : ct / Qt;
+    for (int l : o->bus_from[i]) {
+      int kw = 2 * ng + 8 * l + 4;
+      o->v[kw] = w;
+      o->v[kw + 1] = th;
+    }
+    for (int l : o->bus_to[i]) {
+      int kw = 2 * ng + 8 * l + 6;
+      o->v[kw] = w;
+      o->v[kw + 1] = th;
+    }
+  }
+}
+
+// z step, eq. (qp-bound) with (l, u) = (-inf, inf): minimizer of
+// lambda z + beta/2 z^2 + y (u - v + z) + rho/2 (u - v + z)^2.
+void ora_z_step(void* h) {
+  auto* o = static_cast<Oracle*>(h);
+  for (int k = 0; k < o->m; ++k)
+    o->z[k] = -(o->lam[k] + o->y[k] + o->rho[k] * (o->u[k] - o->v[k])) /
+              (o->beta + o->rho[k]);
+}
+
+// Inner multiplier update y <- y + rho (Ax + B xbar + z) (Sec. III-B).
+void ora_y_step(void* h) {
+  auto* o = static_cast<Oracle*>(h);
+  for (int k = 0; k < o->m; ++k)
+    o->y[k] = o->y[k] + o->rho[k] * (o->u[k] - o->v[k] + o->z[k]);
+}
+
+// Infinity norms: primal ||u - v + z||, dual ||v - v_prev||, ||z||.
+void ora_residuals(void* h) {
+  auto* o = static_cast<Oracle*>(h);
+  double rp = 0.0, rd = 0.0, rz = 0.0;
+  for (int k = 0; k < o->m; ++k) {
+    rp = std::max(rp, std::fabs(o->u[k] - o->v[k] + o->z[k]));
+    rd = std::max(rd, std::fabs(o->v[k] - o->vprev[k]));
+    rz = std::max(rz, std::fabs(o->z[k]));
+  }
+  o->r_pri = rp;
+  o->r_dual = rd;
+  o->r_z = rz;
+}
+
+// Outer update (Algorithm 1): lambda <- proj(lambda + beta z) onto
+// [-lambda_max, lambda_max]; beta grows by gamma when ||z|| did not shrink by
+// the factor omega since the previous outer update.
+void ora_outer_step(void* h) {
+  auto* o = static_cast<Oracle*>(h);
+  for (int k = 0; k < o->m; ++k) {
+    double t = o->lam[k] + o->beta * o->z[k];
+    o->lam[k] = std::max(-o->p.lambda_max, std::min(o->p.lambda_max, t));
+  }
+  if (o->r_z > o->p.beta_omega * o->znorm_prev)
+    o->beta = std::min(o->p.beta_gamma * o->beta, o->p.beta_max);
+  o->znorm_prev = o->r_z;
+  o->outer += 1;
+  o->inner_in_outer = 0;
+}
+
+double ora_objective(void* h) {
+  auto* o = static_cast<Oracle*>(h);
+  double f = 0.0;
+  for (int g = 0; g < o->ng; ++g) {
+    double P = o->base * o->u[2 * g];
+    f += o->c2[g] * P * P + o->c1[g] * P + o->c0[g];
+  }
+  return f;
+}
+
+// One inner iteration of Algorithm 1 plus its control. Returns 1 when the
+// whole solve has terminated (never in fixed-iteration mode).
+int ora_iterate(void* h, int fixed) {
+  auto* o = static_cast<Oracle*>(h);
+  o->vprev = o->v;
+  ora_gen_step(h);
+  ora_branch_step(h);
+  ora_bus_step(h);
+  ora_z_step(h);
+  ora_y_step(h);
+  ora_residuals(h);
+  o->inner_total += 1;
+  o->inner_in_outer += 1;
+  double obj = ora_objective(h);
+  o->hist.push_back(o->r_pri);
+  o->hist.push_back(o->r_dual);
+  o->hist.push_back(o->r_z);
+  o->hist.push_back(obj);
+  o->hist.push_back(o->beta);
+  o->hist.push_back(static_cast<double>(o->outer));
+  bool inner_ok = o->r_pri <= o->p.eps_pri && o->r_dual <= o->p.eps_dual;
+  if (!fixed && inner_ok && o->r_z <= o->p.eps_z) {
+    o->status = 0;
+    return 1;
+  }
+  if (inner_ok || o->inner_in_outer >= o->p.max_inner) {
+    ora_outer_step(h);
+    if (!fixed && o->outer >= o->p.max_outer) {
+      o->status = 1;
+      return 1;
+    }
+  }
+  return 0;
+}
+
+// Warm start (Sec. IV-C): new loads, all primal and dual state kept; beta,
+// the outer counter and the ||z|| history restart.
+void ora_update_loads(void* h, const double* pd, const double* qd) {
+  auto* o = static_cast<Oracle*>(h);
+  for (int i = 0; i < o->nb; ++i) {
+    o->pd[i] = pd[i];
+    o->qd[i] = qd[i];
+  }
+}
+
+void ora_warm_reset(void* h) {
+  auto* o = static_cast<Oracle*>(h);
+  o->beta = o->p.beta0;
+  o->znorm_prev = INF;
+  o->outer = 0;
+  o->inner_in_outer = 0;
+  o->inner_total = 0;
+  o->status = 1;
+  o->hist.clear();
+}
+
+// Runs Algorithm 1: fixed > 0 runs exactly that many inner iterations.
+int ora_solve(void* h, int fixed) {
+  auto* o = static_cast<Oracle*>(h);
+  if (fixed > 0) {
+    for (int t = 0; t < fixed; ++t) ora_iterate(h, 1);
+    o->status = 1;
+    return o->inner_total;
+  }
+  const long long cap = static_cast<long long>(o->p.max_outer) * o->p.max_inner;
+  for (long long t = 0; t < cap; ++t)
+    if (ora_iterate(h, 0)) break;
+  return o->inner_total;
+}
+
+// --- state access (copies) -------------------------------------------------
+// what: 0 u, 1 v, 2 z, 3 y, 4 lam, 5 rho, 6 bx (6 nl), 7 ltil (2 nl),
+// 8 rtil (nl), 9 vprev, 10 pd, 11 qd
+static std::vector<double>* pick(Oracle* o, int what) {
+  switch (what) {
+    case 0: return &o->u;
+    case 1: return &o->v;
+    case 2: return &o->z;
+    case 3: return &o->y;
+    case 4: return &o->lam;
+    case 5: return &o->rho;
+    case 6: return &o->bx;
+    case 7: return &o->ltil;
+    case 8: return &o->rtil;
+    case 9: return &o->vprev;
+    case 10: return &o->pd;
+    case 11: return &o->qd;
+    default: return nullptr;
+  }
+}
+
+int ora_get(void* h, int what, double* out, int64_t n) {
+  auto* v = pick(static_cast<Oracle*>(h), what);
+  if (!v || static_cast<int64_t>(v->size()) != n) return -1;
+  std::memcpy(out, v->data(), sizeof(double) * n);
+  return 0;
+}
+
+int ora_set(void* h, int what, const double* in, int64_t n) {
+  auto* v = pick(static_cast<Oracle*>(h), what);
+  if (!v || static_cast<int64_t>(v->size()) != n) return -1;
+  std::memcpy(v->data(), in, sizeof(double) * n);
+  return 0;
+}
+
+// scalars: [beta, znorm_prev, r_pri, r_dual, r_z, outer, inner_total,
+// inner_in_outer, status]
+void ora_get_scalars(void* h, double* out9) {
+  auto* o = static_cast<Oracle*>(h);
+  out9[0] = o->beta; out9[1] = o->znorm_prev; out9[2] = o->r_pri;
+  out9[3] = o->r_dual; out9[4] = o->r_z; out9[5] = o->outer;
+  out9[6] = o->inner_total; out9[7] = o->inner_in_outer; out9[8] = o->status;
+}
+
+void ora_set_scalars(void* h, const double* in9) {
+  auto* o = static_cast<Oracle*>(h);
+  o->beta = in9[0]; o->znorm_prev = in9[1]; o->r_pri = in9[2];
+  o->r_dual = in9[3]; o->r_z = in9[4];
+  o->outer = static_cast<int>(in9[5]);
+  o->inner_total = static_cast<int>(in9[6]);
+  o->inner_in_outer = static_cast<int>(in9[7]);
+  o->status = static_cast<int>(in9[8]);
+}
+
+int64_t ora_hist_len(void* h) {
+  return static_cast<int64_t>(static_cast<Oracle*>(h)->hist.size());
+}
+
+void ora_get_hist(void* h, double* out) {
+  auto* o = static_cast<Oracle*>(h);
+  std::memcpy(out, o->hist.data(), sizeof(double) * o->hist.size());
+}
+
+void ora_get_admittance(void* h, double* out9nl) {
+  auto* o = static_cast<Oracle*>(h);
+  for (int l = 0; l < o->nl; ++l) {
+    double* t = out9nl + 9 * l;
+    t[0] = o->gii[l]; t[1] = o->bii[l]; t[2] = o->gij[l]; t[3] = o->bij[l];
+    t[4] = o->gji[l]; t[5] = o->bji[l]; t[6] = o->gjj[l]; t[7] = o->bjj[l];
+    t[8] = o->rate2[l];
+  }
+}
+
+void ora_get_stats(void* h, ora_stats* out) { *out = static_cast<Oracle*>(h)->st; }
+void ora_reset_stats(void* h) { static_cast<Oracle*>(h)->st = ora_stats{}; }
+void ora_set_count_flops(void* h, int on) { static_cast<Oracle*>(h)->count_flops = on != 0; }
+
+// --- single-branch entry points for tests ----------------------------------
+// data layout (doubles): [gii bii gij bij gji bji gjj bjj, lo[6], hi[6],
+// vb[8], z[8], y[8], rho[8]] ; n = 4 or 6
+static void unpack_branch(const double* in, int n, BranchData& d) {
+  d.gii = in[0]; d.bii = in[1]; d.gij = in[2]; d.bij = in[3];
+  d.gji = in[4]; d.bji = in[5]; d.gjj = in[6]; d.bjj = in[7];
+  for (int i = 0; i < 6; ++i) { d.lo[i] = in[8 + i]; d.hi[i] = in[14 + i]; }
+  for (int k = 0; k < 8; ++k) {
+    d.vb[k] = in[20 + k];
+    d.z[k] = in[28 + k];
+    d.y[k] = in[36 + k];
+    d.rho[k] = in[44 + k];
+  }
+  d.n = n;
+}
+
+// f, g (n), H (n*n) of the branch objective at x with multipliers ltil, rtil.
+void ora_branch_eval(const double* data, int n, const double* ltil,
+                     double rtil, const double* x, double* f, double* g,
+                     double* H, double* a8) {
+  BranchData d;
+  unpack_branch(data, n, d);
+  d.ltil[0] = ltil[0];
+  d.ltil[1] = ltil[1];
+  d.rtil = rtil;
+  BranchProblem<double> P(d);
+  double F;
+  P.fgh(x, F, g, H);
+  *f = F;
+  if (a8) branch_terms<double>(d, x, a8, nullptr, nullptr, false);
+}
+
+void ora_branch_solve(const double* data, int n, double* x6, double* ltil,
+                      double* rtil, double* u8, const ora_params* P,
+                      ora_stats* st, int count) {
+  BranchData d;
+  unpack_branch(data, n, d);
+  d.ltil[0] = ltil[0];
+  d.ltil[1] = ltil[1];
+  d.rtil = *rtil;
+  if (count) {
+    FlopTally before = g_tally;
+    branch_solve_t<CR>(d, x6, ltil, rtil, u8, *P, st);
+    st->flops += g_tally.total() - before.total();
+    st->trig += g_tally.trig - before.trig;
+  } else {
+    branch_solve_t<double>(d, x6, ltil, rtil, u8, *P, st);
+  }
+}
+
+// Generic bound-constrained TRON through callbacks (tests on quadratics,
+// Rosenbrock and other closed-form problems).
+typedef double (*ora_f_cb)(const double* x, void* ctx);
+typedef void (*ora_fgh_cb)(const double* x, double* f, double* g, double* H,
+                           void* ctx);
+
+struct CbProblem {
+  ora_f_cb fcb;
+  ora_fgh_cb gcb;
+  void* ctx;
+  double f(const double* x) { return fcb(x, ctx); }
+  void fgh(const double* x, double& F, double* g, double* H) { gcb(x, &F, g, H, ctx); }
+};
+
+int ora_tron(int n, double* x, const double* lo, const double* hi,
+             ora_f_cb fcb, ora_fgh_cb gcb, void* ctx, const ora_params* P,
+             ora_stats* st) {
+  if (n < 1 || n > NMAX) return -1;
+  CbProblem prob{fcb, gcb, ctx};
+  TronConst C;
+  return tron<double>(prob, n, x, lo, hi, *P, st, C);
+}
+
+}  // extern "C"

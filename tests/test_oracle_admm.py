@@ -1,0 +1,309 @@
+"""Pins of the oracle's closed-form ADMM steps and of the whole iteration.
+
+* generator step (eq. qp-bound): a bounded scalar minimizer (scipy) of the
+  generator's augmented Lagrangian;
+* bus step (eq. qp-bus): the full KKT system [Q A'; A 0] solved by
+  numpy.linalg.solve, and the power balance rows (eqs. pg, qg) holding after
+  the step;
+* z and y (two-level scheme, multiplier updates): stationarity of the z
+  subproblem and the y recursion;
+* outer step: projection of lambda and the beta rule;
+* invariants of Algorithm 1: cold start has u = v and z = 0, bounds hold at
+  every iterate;
+* whole ADMM on a 3-bus grid: converges to the solution of the dense NLP
+  (scipy SLSQP on polar power flow).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize, minimize_scalar
+
+import oracle as O
+from paper_2110_06879_amd.gridgen import Grid, config_grid, gridgen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def randomize_state(o, rng, scale=1.0):
+    m = o.m
+    o.set("v", o.get("v") + rng.normal(0, 0.05 * scale, m))
+    o.set("z", rng.normal(0, 0.02 * scale, m))
+    o.set("y", rng.normal(0, 20 * scale, m))
+    o.set("lam", rng.normal(0, 5 * scale, m))
+    o.set("u", o.get("u") + rng.normal(0, 0.05 * scale, m))
+
+
+def test_generator_step_matches_scalar_minimizer():
+    g = config_grid("c1_30bus")
+    for s in (1.0, 0.3):
+        o = O.Oracle(g, O.OracleParams(obj_scale=s))
+        randomize_state(o, np.random.default_rng(3), scale=10)
+        v, z, y, rho = o.get("v"), o.get("z"), o.get("y"), o.get("rho")
+        o.gen_step()
+        u = o.get("u")
+        B = g.base_mva
+        for k in range(g.n_gen):
+            kp, kq = 2 * k, 2 * k + 1
+
+            def fp(p):
+                P = B * p
+                r = p - v[kp] + z[kp]
+                return s * (g.c2[k] * P * P + g.c1[k] * P + g.c0[k]) + y[kp] * r + 0.5 * rho[kp] * r * r
+
+            def fq(q):
+                r = q - v[kq] + z[kq]
+                return y[kq] * r + 0.5 * rho[kq] * r * r
+
+            rp = minimize_scalar(fp, bounds=(g.pmin[k], g.pmax[k]), method="bounded",
+                                 options=dict(xatol=1e-12))
+            rq = minimize_scalar(fq, bounds=(g.qmin[k], g.qmax[k]), method="bounded",
+                                 options=dict(xatol=1e-12))
+            assert abs(u[kp] - rp.x) < 1e-7
+            assert abs(u[kq] - rq.x) < 1e-7
+            # exact at a bound when the bound is active
+            assert g.pmin[k] <= u[kp] <= g.pmax[k]
+
+
+def bus_kkt_reference(g, o, i):
+    """Build eq. (qp-bus) for bus i from the raw arrays and solve the KKT."""
+    ng = g.n_gen
+    u, z, y, rho = o.get("u"), o.get("z"), o.get("y"), o.get("rho")
+    vars_, aP, aQ = [], [], []
+    for k in range(ng):
+        if g.gen_bus[k] == i:
+            vars_ += [2 * k, 2 * k + 1]
+            aP += [1, 0]
+            aQ += [0, 1]
+    for l in range(g.n_branch):
+        b0 = 2 * ng + 8 * l
+        if g.br_from[l] == i:
+            vars_ += [b0, b0 + 1]
+            aP += [-1, 0]
+            aQ += [0, -1]
+        if g.br_to[l] == i:
+            vars_ += [b0 + 2, b0 + 3]
+            aP += [-1, 0]
+            aQ += [0, -1]
+    wk = [2 * ng + 8 * l + 4 for l in range(g.n_branch) if g.br_from[l] == i] + \
+         [2 * ng + 8 * l + 6 for l in range(g.n_branch) if g.br_to[l] == i]
+    K = len(vars_)
+    n = K + 1
+    Q = np.zeros((n, n))
+    c = np.zeros(n)
+    for t, k in enumerate(vars_):
+        Q[t, t] = rho[k]
+        c[t] = rho[k] * (u[k] + z[k]) + y[k]
+    for k in wk:
+        Q[K, K] += rho[k]
+        c[K] += rho[k] * (u[k] + z[k]) + y[k]
+    A = np.zeros((2, n))
+    A[0, :K] = aP
+    A[1, :K] = aQ
+    A[0, K] = -g.gs[i]
+    A[1, K] = g.bs[i]
+    b = np.array([g.pd[i], g.qd[i]])
+    KKT = np.block([[Q, A.T], [A, np.zeros((2, 2))]])
+    sol = np.linalg.solve(KKT, np.concatenate([c, b]))
+    return vars_, wk, sol[:n], A, b
+
+
+def test_bus_step_matches_kkt_solve_and_balances():
+    g = gridgen(40, 8, 55, 1.0, 21)
+    rng = np.random.default_rng(5)
+    g.gs = rng.uniform(0, 0.05, g.n_bus)
+    g.bs = rng.uniform(-0.05, 0.05, g.n_bus)
+    o = O.Oracle(g)
+    randomize_state(o, rng)
+    o.bus_step()
+    v = o.get("v")
+    for i in range(g.n_bus):
+        vars_, wk, x, A, b = bus_kkt_reference(g, o, i)
+        np.testing.assert_allclose(v[vars_], x[:-1], rtol=1e-10, atol=1e-11)
+        for k in wk:
+            assert abs(v[k] - x[-1]) < 1e-11
+        # Ax = b with the step's own output
+        xx = np.concatenate([v[vars_], [v[wk[0]]]])
+        np.testing.assert_allclose(A @ xx, b, atol=1e-12)
+
+
+def test_bus_angle_average_and_reference():
+    g = config_grid("c1_30bus")
+    o = O.Oracle(g)
+    rng = np.random.default_rng(8)
+    randomize_state(o, rng)
+    o.bus_step()
+    u, z, y, rho, v = (o.get(k) for k in ("u", "z", "y", "rho", "v"))
+    ng = g.n_gen
+    for i in range(g.n_bus):
+        ks = [2 * ng + 8 * l + 5 for l in range(g.n_branch) if g.br_from[l] == i] + \
+             [2 * ng + 8 * l + 7 for l in range(g.n_branch) if g.br_to[l] == i]
+        # argmin of sum_k y_k (u_k - t + z_k) + rho_k/2 (u_k - t + z_k)^2
+        res = minimize_scalar(lambda t: sum(y[k] * (u[k] - t + z[k]) + 0.5 * rho[k] * (u[k] - t + z[k]) ** 2 for k in ks))
+        want = 0.0 if i == g.ref_bus else res.x
+        for k in ks:
+            assert abs(v[k] - want) < 1e-7
+
+
+def test_z_and_y_steps_stationarity():
+    g = config_grid("c1_30bus")
+    o = O.Oracle(g)
+    rng = np.random.default_rng(4)
+    randomize_state(o, rng)
+    beta = o.scalars()["beta"]
+    y0 = o.get("y")
+    o.z_step()
+    u, v, z, lam, rho = (o.get(k) for k in ("u", "v", "z", "lam", "rho"))
+    stat = lam + beta * z + y0 + rho * (u - v + z)
+    assert np.abs(stat).max() < 1e-12 * (1 + np.abs(y0).max())
+    o.y_step()
+    np.testing.assert_allclose(o.get("y"), y0 + rho * (u - v + z), rtol=1e-15, atol=1e-13)
+
+
+def test_outer_step_projection_and_beta_rule():
+    g = config_grid("c1_30bus")
+    p = O.OracleParams(lambda_max=3.0, beta0=10.0, beta_gamma=6.0, beta_omega=0.8)
+    o = O.Oracle(g, p)
+    rng = np.random.default_rng(1)
+    z = rng.normal(0, 0.5, o.m)
+    lam = rng.normal(0, 2.0, o.m)
+    o.set("z", z)
+    o.set("lam", lam)
+    o.residuals()
+    o.outer_step()
+    np.testing.assert_allclose(o.get("lam"), np.clip(lam + 10.0 * z, -3, 3), rtol=0, atol=1e-15)
+    s = o.scalars()
+    assert s["beta"] == 10.0  # first outer step: no previous ||z||
+    # ||z|| not reduced by omega: beta grows by gamma
+    o.set("z", z * 0.9)
+    o.residuals()
+    o.outer_step()
+    assert o.scalars()["beta"] == 60.0
+    # ||z|| reduced enough: beta kept
+    o.set("z", z * 0.1)
+    o.residuals()
+    o.outer_step()
+    assert o.scalars()["beta"] == 60.0
+
+
+def test_cold_start_and_bounds_invariants():
+    g = config_grid("c1_30bus")
+    o = O.Oracle(g)
+    u, v, z = o.get("u"), o.get("v"), o.get("z")
+    assert np.array_equal(u, v) and not z.any()
+    ng = g.n_gen
+    # bus-side angle copies start at zero, w copies equal v^2 of the midpoint
+    a = u[2 * ng:].reshape(-1, 8)
+    assert not a[:, 5].any() and not a[:, 7].any()
+    np.testing.assert_allclose(a[:, 4], 1.0, atol=1e-15)
+    rate2 = (0.99 * g.rate) ** 2
+    for _ in range(30):
+        o.iterate(fixed=True)
+        u, bx = o.get("u"), o.get("bx").reshape(-1, 6)
+        assert np.all(u[0:2 * ng:2] >= g.pmin) and np.all(u[0:2 * ng:2] <= g.pmax)
+        assert np.all(u[1:2 * ng:2] >= g.qmin) and np.all(u[1:2 * ng:2] <= g.qmax)
+        assert np.all(bx[:, 0] >= g.vmin[g.br_from]) and np.all(bx[:, 0] <= g.vmax[g.br_from])
+        assert np.all(bx[:, 1] >= g.vmin[g.br_to]) and np.all(bx[:, 1] <= g.vmax[g.br_to])
+        assert np.all(np.abs(bx[:, 2:4]) <= 2 * np.pi)
+        assert np.all(bx[:, 4] >= -rate2) and np.all(bx[:, 4] <= 0)
+        # bus balance holds exactly after every bus step
+        v = o.get("v")
+        for i in range(g.n_bus):
+            P = sum(v[2 * k] for k in range(ng) if g.gen_bus[k] == i)
+            P -= sum(v[2 * ng + 8 * l] for l in range(g.n_branch) if g.br_from[l] == i)
+            P -= sum(v[2 * ng + 8 * l + 2] for l in range(g.n_branch) if g.br_to[l] == i)
+            assert abs(P - g.pd[i]) < 1e-12
+
+
+def load_three_bus():
+    with open(os.path.join(GOLDEN, "three_bus.json")) as f:
+        d = json.load(f)
+    nb, ng, nl = len(d["pd"]), len(d["gen_bus"]), len(d["br_from"])
+    A = lambda k, t=np.float64: np.asarray(d[k], dtype=t)  # noqa: E731
+    return Grid(name="three_bus", base_mva=d["base_mva"], ref_bus=d["ref_bus"],
+                pd=A("pd"), qd=A("qd"), gs=np.zeros(nb), bs=np.zeros(nb),
+                vmin=A("vmin"), vmax=A("vmax"), gen_bus=A("gen_bus", np.int32),
+                pmin=A("pmin"), pmax=A("pmax"), qmin=A("qmin"), qmax=A("qmax"),
+                c2=A("c2"), c1=A("c1"), c0=A("c0"),
+                br_from=A("br_from", np.int32), br_to=A("br_to", np.int32),
+                r=A("r"), x=A("x"), b=A("b"), tap=np.ones(nl), shift=np.zeros(nl),
+                rate=A("rate"))
+
+
+def dense_acopf(g, rate_scale=0.99):
+    """ACOPF (eq. acopf) in polar form, solved by scipy SLSQP."""
+    nb, ng = g.n_bus, g.n_gen
+    Y = np.zeros((nb, nb), dtype=complex)
+    Ysh = []
+    for l in range(g.n_branch):
+        i, j = g.br_from[l], g.br_to[l]
+        ys = 1 / (g.r[l] + 1j * g.x[l])
+        yff, yft, ytf, ytt = ys + 0.5j * g.b[l], -ys, -ys, ys + 0.5j * g.b[l]
+        Y[i, i] += yff; Y[i, j] += yft; Y[j, i] += ytf; Y[j, j] += ytt
+        Ysh.append((i, j, yff, yft, ytf, ytt))
+    B = g.base_mva
+
+    def unpack(z):
+        return z[:ng], z[ng:2 * ng], z[2 * ng:2 * ng + nb], z[2 * ng + nb:]
+
+    def obj(z):
+        p = unpack(z)[0] * B
+        return float(np.sum(g.c2 * p * p + g.c1 * p + g.c0))
+
+    def balance(z):
+        p, q, vm, va = unpack(z)
+        V = vm * np.exp(1j * va)
+        S = V * np.conj(Y @ V)
+        Sg = np.zeros(nb, dtype=complex)
+        for k in range(ng):
+            Sg[g.gen_bus[k]] += p[k] + 1j * q[k]
+        mis = Sg - (g.pd + 1j * g.qd) - S
+        return np.concatenate([mis.real, mis.imag, [va[g.ref_bus]]])
+
+    def limits(z):
+        _, _, vm, va = unpack(z)
+        V = vm * np.exp(1j * va)
+        out = []
+        for l, (i, j, yff, yft, ytf, ytt) in enumerate(Ysh):
+            r2 = (rate_scale * g.rate[l]) ** 2
+            Sij = V[i] * np.conj(yff * V[i] + yft * V[j])
+            Sji = V[j] * np.conj(ytf * V[i] + ytt * V[j])
+            out += [r2 - abs(Sij) ** 2, r2 - abs(Sji) ** 2]
+        return np.array(out)
+
+    z0 = np.concatenate([(g.pmin + g.pmax) / 2, (g.qmin + g.qmax) / 2,
+                         (g.vmin + g.vmax) / 2, np.zeros(nb)])
+    bounds = list(zip(g.pmin, g.pmax)) + list(zip(g.qmin, g.qmax)) + \
+        list(zip(g.vmin, g.vmax)) + [(-2 * np.pi, 2 * np.pi)] * nb
+    res = minimize(obj, z0, method="SLSQP", bounds=bounds,
+                   constraints=[{"type": "eq", "fun": balance},
+                                {"type": "ineq", "fun": limits}],
+                   options=dict(ftol=1e-14, maxiter=500))
+    assert res.success, res.message
+    return unpack(res.x)
+
+
+@pytest.mark.slow
+def test_three_bus_admm_converges_to_dense_acopf():
+    g = load_three_bus()
+    p_ref, q_ref, vm_ref, va_ref = dense_acopf(g)
+    p = O.OracleParams(rho_pq=400.0, rho_va=4000.0, obj_scale=0.01,
+                       eps_pri=1e-7, eps_dual=1e-7, eps_z=1e-7,
+                       max_inner=20000, max_outer=40)
+    o = O.Oracle(g, p)
+    o.solve(0)
+    s = o.scalars()
+    assert s["status"] == 0, s
+    u, v = o.get("u"), o.get("v")
+    ng = g.n_gen
+    np.testing.assert_allclose(u[0:2 * ng:2], p_ref, atol=1e-4)
+    # bus voltage magnitudes from the bus-side w copies
+    vm = np.zeros(g.n_bus)
+    for l in range(g.n_branch):
+        vm[g.br_from[l]] = np.sqrt(v[2 * ng + 8 * l + 4])
+        vm[g.br_to[l]] = np.sqrt(v[2 * ng + 8 * l + 6])
+    np.testing.assert_allclose(vm, vm_ref, atol=1e-4)
+    f_admm = o.objective()
+    f_ref = float(np.sum(g.c2 * (100 * p_ref) ** 2 + g.c1 * 100 * p_ref))
+    assert abs(f_admm - f_ref) <= 1e-5 * f_ref
