@@ -1,0 +1,189 @@
+/*
+ * acopf.h -- C ABI of the MI355X (gfx950) two-level component ADMM for AC
+ * optimal power flow (Kim & Kim, "Accelerated Computation and Tracking of AC
+ * Optimal Power Flow Solutions Using GPUs", PSCC 2022).
+ *
+ * The problem is eq. (acopf) of Sec. II-A: minimize the sum of generator
+ * costs subject to the bus power balances (eqs. pg, qg), line limits
+ * (eqs. ij-limit, ji-limit), generator and voltage bounds, with branch flows
+ * given by eqs. (pij)-(qji). It is decomposed by components (Sec. II-B/II-C)
+ * and solved by Algorithm 1 (Sec. III): an inner ADMM over generators and
+ * branches (x), buses (xbar), artificial variables (z) and multipliers (y),
+ * inside an outer augmented-Lagrangian loop on z = 0 (lambda, beta).
+ *
+ * All per-element arrays are host pointers in structure-of-arrays form,
+ * FP64 unless noted, per unit on base_mva. Every step of the iteration runs
+ * in HIP kernels on the device given to acopf_create; host<->device copies
+ * happen only in create/update_loads/get_state/set_state and a readback of a
+ * few control words per chunk of iterations inside acopf_solve.
+ *
+ * Return codes: 0 on success, a negative ACOPF_E* value on error, with a
+ * message available from acopf_last_error() (thread-local). Non-convergence
+ * is not an error: it is reported in acopf_result.status.
+ */
+#ifndef ACOPF_H
+#define ACOPF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ACOPF_OK = 0,
+  ACOPF_EINVAL = -1,  /* invalid argument or grid data (NaN/Inf, bad index,
+                         empty bound interval, r = x = 0, isolated bus)     */
+  ACOPF_ENOMEM = -2,  /* device or host allocation failed                  */
+  ACOPF_EDEVICE = -3, /* a HIP runtime call failed (text in last_error)     */
+  ACOPF_ESTATE = -4   /* call not valid in the handle's current state       */
+};
+
+enum { /* acopf_result.status */
+  ACOPF_CONVERGED = 0, /* inner test and ||z||_inf <= eps_z both hold       */
+  ACOPF_MAX_ITER = 1,  /* max_outer reached, or fixed-iteration mode ended   */
+  ACOPF_NUMERICAL = 2  /* a residual became NaN or Inf                       */
+};
+
+enum { /* acopf_solve mode */
+  ACOPF_COLD = 0,     /* cold start of Sec. IV-B, then Algorithm 1           */
+  ACOPF_WARM = 1,     /* keep the primal/dual state (tracking, Sec. IV-C);
+                         restart beta, the outer counter and ||z|| history  */
+  ACOPF_CONTINUE = 2  /* keep everything, counters included                 */
+};
+
+enum { /* acopf_get_state / acopf_set_state: what */
+  ACOPF_U = 0,         /* [m] generator/branch-side coupling values          */
+  ACOPF_V = 1,         /* [m] bus-side copies                                */
+  ACOPF_Z = 2,         /* [m] artificial variables                           */
+  ACOPF_Y = 3,         /* [m] inner multipliers                              */
+  ACOPF_LAMBDA = 4,    /* [m] outer multipliers                              */
+  ACOPF_BRANCH_X = 5,  /* [6 n_branch] (v_i, v_j, th_i, th_j, s_ij, s_ji)    */
+  ACOPF_BRANCH_LTIL = 6, /* [2 n_branch] line-limit AL multipliers           */
+  ACOPF_BRANCH_RTIL = 7, /* [n_branch] line-limit AL penalties               */
+  ACOPF_SCALARS = 8,   /* [9] beta, ||z|| at the last outer step, r_pri,
+                          r_dual, r_z, outer, inner_total, inner_in_outer,
+                          status                                             */
+  ACOPF_PD = 9,        /* [n_bus] */
+  ACOPF_QD = 10,       /* [n_bus] */
+  ACOPF_HISTORY = 11,  /* get only: [6 inner_total] per inner iteration of
+                          the last solve: r_pri, r_dual, r_z, 0, beta, outer */
+  ACOPF_STATS = 12     /* get only: [16] branch-solve event counters summed
+                          over all solves (see acopf_stats_names)            */
+};
+
+/* Coupling order (m = 2 n_gen + 8 n_branch), the same in every vector:
+ * generator g owns entries 2g (p_g) and 2g+1 (q_g); branch l owns
+ * 2 n_gen + 8 l + k, k = 0..7: p_ij, q_ij, p_ji, q_ji, w_i(ij), th_i(ij),
+ * w_j(ij), th_j(ij) (Sec. II-B). Each coupling reads u - v + z = 0.      */
+
+typedef struct {
+  int32_t n_bus, n_gen, n_branch, ref_bus;
+  double base_mva;                            /* MVA, > 0                  */
+  const double *pd, *qd;                      /* [n_bus] loads             */
+  const double *gs, *bs;                      /* [n_bus] bus shunts        */
+  const double *vmin, *vmax;                  /* [n_bus] |V| bounds        */
+  const int32_t *gen_bus;                     /* [n_gen] 0-based bus       */
+  const double *pmin, *pmax, *qmin, *qmax;    /* [n_gen] output bounds     */
+  const double *c2, *c1, *c0;                 /* [n_gen] cost on MW: c2 P^2
+                                                 + c1 P + c0, P = base_mva p */
+  const int32_t *br_from, *br_to;             /* [n_branch] 0-based buses  */
+  const double *r, *x, *b;                    /* [n_branch] series r + jx,
+                                                 total line charging b      */
+  const double *tap, *shift;                  /* [n_branch] a = tap e^{j shift}
+                                                 (tap > 0, shift in rad)    */
+  const double *rate;                         /* [n_branch] MVA/base limit;
+                                                 <= 0 means unlimited       */
+} acopf_grid;
+
+typedef struct {
+  double rho_pq, rho_va;     /* ADMM penalties on power / voltage couplings
+                                (Table 1)                                   */
+  double obj_scale;          /* objective scaling inside the ADMM (Sec. IV-A) */
+  double rate_scale;         /* line-limit tightening (Sec. IV-A: 0.99)     */
+  double beta0, beta_gamma, beta_omega, beta_max; /* outer penalty: beta *=
+                                gamma when ||z|| > omega ||z||_prev, capped */
+  double lambda_max;         /* projection bound of lambda                  */
+  double eps_pri, eps_dual, eps_z; /* termination on inf-norms             */
+  int32_t max_outer, max_inner;
+  double tron_gtol, tron_ftol; /* branch TRON stopping tolerances           */
+  int32_t tron_maxit;
+  double al_rho0, al_rho_growth, al_rho_max, al_tol, al_shrink; /* branch
+                                line-limit augmented Lagrangian            */
+  int32_t al_maxit;
+} acopf_params;
+
+typedef struct {
+  int32_t status;            /* ACOPF_CONVERGED / MAX_ITER / NUMERICAL      */
+  int32_t inner_iters;       /* cumulative inner iterations of this solve   */
+  int32_t outer_iters;
+  int32_t branch_failures;   /* TRON exits by iteration cap or stall        */
+  double objective;          /* sum of generator costs at the generator-side
+                                p_g (Sec. IV-A), $/h, c0 included          */
+  double r_pri, r_dual, r_z; /* final inf-norm residuals                    */
+  double beta;
+  double seconds;            /* wall time of the solve call                 */
+} acopf_result;
+
+typedef struct acopf_s* acopf_handle;
+
+/* Fill *p with the library defaults. */
+void acopf_default_params(acopf_params* p);
+
+/* Validate and lay out n_grids grids on device `device`, then cold-start
+ * them. Grids are independent problems batched into the same launches and
+ * share `params`. `hip_stream` is the hipStream_t to run on, or NULL for a
+ * library-owned stream. Input arrays are borrowed for the call only; the
+ * handle owns all device memory until acopf_destroy.
+ * Errors: EINVAL (bad data, n_grids < 1), ENOMEM, EDEVICE. */
+int acopf_create(const acopf_grid* grids, int32_t n_grids,
+                 const acopf_params* params, int32_t device,
+                 void* hip_stream, acopf_handle* out);
+
+/* Run Algorithm 1 on every grid of the handle. mode: ACOPF_COLD, ACOPF_WARM
+ * or ACOPF_CONTINUE. fixed_iters > 0 runs exactly that many inner
+ * iterations (termination tests off; outer updates still happen when the
+ * inner test passes). results: [n_grids], may be NULL.
+ * Errors: EINVAL (mode), ESTATE (WARM/CONTINUE before any solve), EDEVICE. */
+int acopf_solve(acopf_handle h, int32_t mode, int32_t fixed_iters,
+                acopf_result* results);
+
+/* Replace the loads of grid `grid` (H2D copy of 2 n_bus doubles); the next
+ * ACOPF_WARM solve tracks the new optimum from the resident state (Sec. IV-C).
+ * Errors: EINVAL (index, NaN/Inf), EDEVICE. */
+int acopf_update_loads(acopf_handle h, int32_t grid, const double* pd,
+                       const double* qd);
+
+/* Copy one state vector of grid `grid` to the host buffer out[n] (n must
+ * equal the size listed with the ACOPF_* `what` codes, in canonical order).
+ * Errors: EINVAL (index, size, code), EDEVICE. */
+int acopf_get_state(acopf_handle h, int32_t grid, int32_t what, double* out,
+                    int64_t n);
+
+/* Overwrite one state vector (checkpoint/resume); HISTORY and STATS are
+ * read-only. Errors: EINVAL, EDEVICE. */
+int acopf_set_state(acopf_handle h, int32_t grid, int32_t what,
+                    const double* in, int64_t n);
+
+/* Number of grids, buses, generators, branches of grid `grid` (out[4]). */
+int acopf_get_sizes(acopf_handle h, int32_t grid, int64_t* out4);
+
+/* Average device time (ms) per launch of each kernel of the last solve,
+ * measured with HIP events on the solve stream: out[0] generator step,
+ * out[1] branch step (6-variable), out[2] branch step (4-variable),
+ * out[3] bus/z/y/residual step, out[4] control, out[5] outer update,
+ * out[6] number of timed iterations. Timing is taken only when
+ * ACOPF_PROFILE=1 is set in the environment at create time. */
+int acopf_get_timing(acopf_handle h, double* out7);
+
+/* Free everything the handle owns. NULL is a no-op. */
+void acopf_destroy(acopf_handle h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* acopf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACOPF_H */

@@ -144,6 +144,7 @@ def load() -> C.CDLL:
     lib.ora_get_admittance.argtypes = [vp, dp]
     lib.ora_get_stats.argtypes = [vp, C.POINTER(_Stats)]
     lib.ora_set_count_flops.argtypes = [vp, ip]
+    lib.ora_sincos.argtypes = [C.c_double, dp, dp]
     lib.ora_branch_eval.argtypes = [dp, ip, dp, C.c_double, dp, dp, dp, dp, dp]
     lib.ora_branch_solve.argtypes = [dp, ip, dp, dp, dp, dp, C.POINTER(_Params),
                                      C.POINTER(_Stats), ip]
@@ -332,6 +333,15 @@ def branch_solve(data: np.ndarray, n: int, x6, ltil, rtil: float,
     lib.ora_branch_solve(_dp(data), n, _dp(x), _dp(lt), _dp(rt), _dp(u),
                          C.byref(p), C.byref(st), int(count))
     return x, lt, rt[0], u, st.as_dict()
+
+
+def sincos(x: float):
+    """The oracle's series sin/cos of a branch angle."""
+    lib = load()
+    s = C.c_double()
+    c = C.c_double()
+    lib.ora_sincos(float(x), C.byref(s), C.byref(c))
+    return s.value, c.value
 
 
 _F_CB = C.CFUNCTYPE(C.c_double, C.POINTER(C.c_double), C.c_void_p)

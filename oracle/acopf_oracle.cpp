@@ -9,7 +9,7 @@
 // More 1999 for the trust-region Newton method) on its own.
 //
 // Build: g++ -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, IEEE
-// division and square root; sin/cos from the C library).
+// division and square root; sin/cos of branch angles by the series below).
 //
 // Layout of the coupling vectors (canonical order, shared with the library's
 // get_state only as a documented convention): generator g owns couplings
@@ -64,17 +64,55 @@ inline bool operator>=(CR a, CR b) { return a.v >= b.v; }
 inline bool operator==(CR a, CR b) { return a.v == b.v; }
 inline bool operator!=(CR a, CR b) { return a.v != b.v; }
 inline CR sqrt(CR a) { ++g_tally.sqrt_; return CR(std::sqrt(a.v)); }
-inline CR sin(CR a) { ++g_tally.trig; return CR(std::sin(a.v)); }
-inline CR cos(CR a) { ++g_tally.trig; return CR(std::cos(a.v)); }
 inline double val(CR a) { return a.v; }
 inline double val(double a) { return a; }
+
+// sin and cos of the branch angle difference: Cody-Waite reduction by pi/2
+// (pi/2 split into a 33-bit head and a tail, so k * head is exact) followed
+// by the Taylor series of sin and cos on |r| <= pi/4, truncated after r^17
+// and r^18 (remainders below 1e-19), evaluated by Horner's rule. Written out
+// here rather than taken from the C library so that the result is a fixed
+// sequence of IEEE operations.
+constexpr double kPio2Hi = 1.5707963267341256;       // 0x1.921fb544p+0
+constexpr double kPio2Lo = 6.077100506506192e-11;    // pi/2 - kPio2Hi
+constexpr double kTwoOverPi = 0.6366197723675814;
+// (-1)^j / (2j+1)!, j = 1..8  and  (-1)^j / (2j)!, j = 1..9
+constexpr double kSinC[8] = {-0.16666666666666666, 0.008333333333333333,
+                             -0.0001984126984126984, 2.7557319223985893e-06,
+                             -2.505210838544172e-08, 1.6059043836821613e-10,
+                             -7.647163731819816e-13, 2.8114572543455206e-15};
+constexpr double kCosC[9] = {-0.5, 0.041666666666666664, -0.001388888888888889,
+                             2.48015873015873e-05, -2.755731922398589e-07,
+                             2.08767569878681e-09, -1.1470745597729725e-11,
+                             4.779477332387385e-14, -1.5619206968586225e-16};
+
+inline void series_sincos(double x, double* s, double* c) {
+  const double k = std::nearbyint(x * kTwoOverPi);
+  const double r = (x - k * kPio2Hi) - k * kPio2Lo;
+  const double r2 = r * r;
+  double ps = kSinC[7];
+  for (int j = 6; j >= 0; --j) ps = kSinC[j] + r2 * ps;
+  double pc = kCosC[8];
+  for (int j = 7; j >= 0; --j) pc = kCosC[j] + r2 * pc;
+  const double sr = r + r * (r2 * ps);
+  const double cr = 1.0 + r2 * pc;
+  const long long q = static_cast<long long>(k) & 3;
+  if (q == 0) { *s = sr; *c = cr; }
+  else if (q == 1) { *s = cr; *c = -sr; }
+  else if (q == 2) { *s = -sr; *c = -cr; }
+  else { *s = -cr; *c = sr; }
+}
+
+inline void rsincos(double x, double& s, double& c) { series_sincos(x, &s, &c); }
+inline void rsincos(CR x, CR& s, CR& c) {
+  g_tally.trig += 2;
+  series_sincos(x.v, &s.v, &c.v);
+}
 
 template <class R> inline R rabs(R a) { return a < R(0.0) ? -a : a; }
 template <class R> inline R rmin(R a, R b) { return b < a ? b : a; }
 template <class R> inline R rmax(R a, R b) { return a < b ? b : a; }
 template <class R> inline R rsqrt_(R a) { using std::sqrt; return sqrt(a); }
-template <class R> inline R rsin(R a) { using std::sin; return sin(a); }
-template <class R> inline R rcos(R a) { using std::cos; return cos(a); }
 
 constexpr int NMAX = 8;
 constexpr double TWO_PI = 6.283185307179586476925286766559;
@@ -469,14 +507,15 @@ struct BranchData {
   double ltil[2], rtil;
 };
 
-// Values, gradients and Hessians (in the 4 voltage variables) of the eight
-// branch-side coupling quantities a_k(x).
+// Values a_k(x) of the eight branch-side coupling quantities: flows p_ij,
+// q_ij, p_ji, q_ji (eqs. pij-qji), then w_i = v_i^2, theta_i, w_j = v_j^2,
+// theta_j. aux receives (cos, sin, w^R, w^I) when non-null.
 template <class R>
-void branch_terms(const BranchData& d, const R* x, R* a, R (*ga)[4],
-                  R (*Ha)[4][4], bool derivs) {
+void branch_values(const BranchData& d, const R* x, R* a, R* aux) {
   R vi = x[0], vj = x[1], ti = x[2], tj = x[3];
   R dt = ti - tj;
-  R cs = rcos(dt), sn = rsin(dt);
+  R cs, sn;
+  rsincos(dt, sn, cs);
   R vv = vi * vj;
   R WR = vv * cs, WI = vv * sn;
   R wi = vi * vi, wj = vj * vj;
@@ -490,46 +529,52 @@ void branch_terms(const BranchData& d, const R* x, R* a, R (*ga)[4],
   a[5] = ti;
   a[6] = wj;
   a[7] = tj;
-  if (!derivs) return;
-  // first derivatives of w_i, w_j, w^R, w^I
-  R dwi[4] = {R(2.0) * vi, R(0.0), R(0.0), R(0.0)};
-  R dwj[4] = {R(0.0), R(2.0) * vj, R(0.0), R(0.0)};
-  R dWR[4] = {vj * cs, vi * cs, -WI, WI};
-  R dWI[4] = {vj * sn, vi * sn, WR, -WR};
-  // second derivatives
-  R hWR[4][4] = {{R(0.0), cs, -vj * sn, vj * sn},
-                 {cs, R(0.0), -vi * sn, vi * sn},
-                 {-vj * sn, -vi * sn, -WR, WR},
-                 {vj * sn, vi * sn, WR, -WR}};
-  R hWI[4][4] = {{R(0.0), sn, vj * cs, -vj * cs},
-                 {sn, R(0.0), vi * cs, -vi * cs},
-                 {vj * cs, vi * cs, -WI, WI},
-                 {-vj * cs, -vi * cs, WI, -WI}};
-  // coefficients (cw, cR, cI) of each flow in (w_own, w^R, w^I)
-  R coef[4][3] = {{gii, gij, bij}, {-bii, -bij, gij},
-                  {gjj, gji, -bji}, {-bjj, -bji, -gji}};
-  for (int k = 0; k < 4; ++k) {
-    const R* dw = (k < 2) ? dwi : dwj;
-    int own = (k < 2) ? 0 : 1;
-    for (int p = 0; p < 4; ++p)
-      ga[k][p] = coef[k][0] * dw[p] + coef[k][1] * dWR[p] + coef[k][2] * dWI[p];
-    for (int p = 0; p < 4; ++p)
-      for (int q = 0; q < 4; ++q) {
-        R hw = (p == own && q == own) ? R(2.0) * coef[k][0] : R(0.0);
-        Ha[k][p][q] = hw + coef[k][1] * hWR[p][q] + coef[k][2] * hWI[p][q];
-      }
+  if (aux) {
+    aux[0] = cs;
+    aux[1] = sn;
+    aux[2] = WR;
+    aux[3] = WI;
   }
-  for (int k = 4; k < 8; ++k)
+}
+
+// Upper triangle of a symmetric 4x4 matrix, row by row.
+constexpr int UT_P[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+constexpr int UT_Q[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+
+// Gradients (over v_i, v_j, theta_i, theta_j) and upper-triangular Hessians
+// of the four flows. A flow is cw w_own + cR w^R + cI w^I with
+// w^R = v_i v_j cos(theta_i - theta_j) and w^I = v_i v_j sin(...).
+template <class R>
+void flow_derivs(const BranchData& d, const R* x, const R* aux, R (*ga)[4],
+                 R (*Ha)[10]) {
+  R vi = x[0], vj = x[1];
+  R cs = aux[0], sn = aux[1], WR = aux[2], WI = aux[3];
+  R jc = vj * cs, ic = vi * cs, js = vj * sn, is = vi * sn;
+  R twvi = R(2.0) * vi, twvj = R(2.0) * vj;
+  R dWR[4] = {jc, ic, -WI, WI};
+  R dWI[4] = {js, is, WR, -WR};
+  R hWR[10] = {R(0.0), cs, -js, js, R(0.0), -is, is, -WR, WR, -WR};
+  R hWI[10] = {R(0.0), sn, jc, -jc, R(0.0), ic, -ic, -WI, WI, -WI};
+  R coef[4][3] = {{R(d.gii), R(d.gij), R(d.bij)},
+                  {-R(d.bii), -R(d.bij), R(d.gij)},
+                  {R(d.gjj), R(d.gji), -R(d.bji)},
+                  {-R(d.bjj), -R(d.bji), -R(d.gji)}};
+  for (int k = 0; k < 4; ++k) {
+    int own = k < 2 ? 0 : 1;
+    R tw = k < 2 ? twvi : twvj;
     for (int p = 0; p < 4; ++p) {
-      ga[k][p] = R(0.0);
-      for (int q = 0; q < 4; ++q) Ha[k][p][q] = R(0.0);
+      if (p == own)
+        ga[k][p] = coef[k][0] * tw + coef[k][1] * dWR[p] + coef[k][2] * dWI[p];
+      else
+        ga[k][p] = coef[k][1] * dWR[p] + coef[k][2] * dWI[p];
     }
-  ga[4][0] = R(2.0) * vi;
-  Ha[4][0][0] = R(2.0);
-  ga[5][2] = R(1.0);
-  ga[6][1] = R(2.0) * vj;
-  Ha[6][1][1] = R(2.0);
-  ga[7][3] = R(1.0);
+    for (int t = 0; t < 10; ++t) {
+      if (t == 0 || t == 4)  // (0,0), (1,1): only the w_own term
+        Ha[k][t] = (t == 0) == (own == 0) ? R(2.0) * coef[k][0] : R(0.0);
+      else
+        Ha[k][t] = coef[k][1] * hWR[t] + coef[k][2] * hWI[t];
+    }
+  }
 }
 
 template <class R>
@@ -541,7 +586,7 @@ struct BranchProblem {
   // with r_k = a_k(x) - v_k + z_k and c_e = p_e^2 + q_e^2 + s_e.
   R f(const R* x) {
     R a[8];
-    branch_terms<R>(d, x, a, nullptr, nullptr, false);
+    branch_values<R>(d, x, a, nullptr);
     R F = R(0.0);
     for (int k = 0; k < 8; ++k) {
       R r = a[k] - R(d.vb[k]) + R(d.z[k]);
@@ -556,51 +601,70 @@ struct BranchProblem {
     return F;
   }
 
+  // F, its gradient and its Hessian (dense row-major n x n). With
+  // m_k = y_k + rho_k r_k:  grad F = sum_k m_k grad a_k + AL terms and
+  // hess F = sum_k rho_k grad a_k grad a_k' + m_k hess a_k + AL terms.
   void fgh(const R* x, R& F, R* g, R* H) {
     const int n = d.n;
-    R a[8], ga[8][4], Ha[8][4][4];
-    branch_terms<R>(d, x, a, ga, Ha, true);
+    R a[8], aux[4], ga[4][4], Ha[4][10];
+    branch_values<R>(d, x, a, aux);
+    flow_derivs<R>(d, x, aux, ga, Ha);
     F = R(0.0);
     for (int i = 0; i < n; ++i) {
       g[i] = R(0.0);
       for (int j = 0; j < n; ++j) H[i * n + j] = R(0.0);
     }
-    for (int k = 0; k < 8; ++k) {
+    // the four flow couplings
+    for (int k = 0; k < 4; ++k) {
       R r = a[k] - R(d.vb[k]) + R(d.z[k]);
       F = F + R(d.y[k]) * r + R(0.5) * R(d.rho[k]) * r * r;
-      R m = R(d.y[k]) + R(d.rho[k]) * r;  // dF/da_k
-      for (int p = 0; p < 4; ++p) {
-        g[p] = g[p] + m * ga[k][p];
-        for (int q = 0; q < 4; ++q)
-          H[p * n + q] = H[p * n + q] + R(d.rho[k]) * ga[k][p] * ga[k][q] +
-                         m * Ha[k][p][q];
+      R m = R(d.y[k]) + R(d.rho[k]) * r;
+      for (int p = 0; p < 4; ++p) g[p] = g[p] + m * ga[k][p];
+      for (int t = 0; t < 10; ++t) {
+        int p = UT_P[t], q = UT_Q[t];
+        H[p * n + q] = H[p * n + q] + R(d.rho[k]) * ga[k][p] * ga[k][q] + m * Ha[k][t];
       }
     }
+    // w_i = v_i^2 (variable 0), theta_i (2), w_j = v_j^2 (1), theta_j (3)
+    const int var[4] = {0, 2, 1, 3};
+    for (int k = 4; k < 8; ++k) {
+      int p = var[k - 4];
+      R r = a[k] - R(d.vb[k]) + R(d.z[k]);
+      F = F + R(d.y[k]) * r + R(0.5) * R(d.rho[k]) * r * r;
+      R m = R(d.y[k]) + R(d.rho[k]) * r;
+      if (k == 4 || k == 6) {  // d(v^2)/dv = 2v, d2(v^2)/dv2 = 2
+        R gv = R(2.0) * x[p];
+        g[p] = g[p] + m * gv;
+        H[p * n + p] = H[p * n + p] + R(d.rho[k]) * gv * gv + m * R(2.0);
+      } else {  // angle copy: gradient 1, no curvature
+        g[p] = g[p] + m;
+        H[p * n + p] = H[p * n + p] + R(d.rho[k]);
+      }
+    }
+    // augmented Lagrangian on the line limits (eq. branch, last two lines)
     if (n == 6) {
       for (int e = 0; e < 2; ++e) {
-        int kp = 2 * e, kq = 2 * e + 1, sidx = 4 + e;
-        R c = a[kp] * a[kp] + a[kq] * a[kq] + x[sidx];
+        int kp = 2 * e, kq = 2 * e + 1, s = 4 + e;
+        R c = a[kp] * a[kp] + a[kq] * a[kq] + x[s];
         F = F + R(d.ltil[e]) * c + R(0.5) * R(d.rtil) * c * c;
-        R m = R(d.ltil[e]) + R(d.rtil) * c;  // dF/dc
-        // grad c over all six variables
-        R gc[6];
+        R m = R(d.ltil[e]) + R(d.rtil) * c;
+        R gc[4];
         for (int p = 0; p < 4; ++p)
-          gc[p] = R(2.0) * a[kp] * ga[kp][p] + R(2.0) * a[kq] * ga[kq][p];
-        gc[4] = R(0.0);
-        gc[5] = R(0.0);
-        gc[sidx] = R(1.0);
-        for (int p = 0; p < 6; ++p) {
-          g[p] = g[p] + m * gc[p];
-          for (int q = 0; q < 6; ++q) {
-            R hc = R(0.0);
-            if (p < 4 && q < 4)
-              hc = R(2.0) * ga[kp][p] * ga[kp][q] + R(2.0) * a[kp] * Ha[kp][p][q] +
-                   R(2.0) * ga[kq][p] * ga[kq][q] + R(2.0) * a[kq] * Ha[kq][p][q];
-            H[p * 6 + q] = H[p * 6 + q] + R(d.rtil) * gc[p] * gc[q] + m * hc;
-          }
+          gc[p] = R(2.0) * (a[kp] * ga[kp][p] + a[kq] * ga[kq][p]);
+        for (int p = 0; p < 4; ++p) g[p] = g[p] + m * gc[p];
+        g[s] = g[s] + m;
+        for (int t = 0; t < 10; ++t) {
+          int p = UT_P[t], q = UT_Q[t];
+          R hc = R(2.0) * (ga[kp][p] * ga[kp][q] + a[kp] * Ha[kp][t] +
+                           ga[kq][p] * ga[kq][q] + a[kq] * Ha[kq][t]);
+          H[p * 6 + q] = H[p * 6 + q] + R(d.rtil) * gc[p] * gc[q] + m * hc;
         }
+        for (int p = 0; p < 4; ++p) H[p * 6 + s] = H[p * 6 + s] + R(d.rtil) * gc[p];
+        H[s * 6 + s] = H[s * 6 + s] + R(d.rtil);
       }
     }
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) H[q * n + p] = H[p * n + q];
   }
 };
 
@@ -628,7 +692,7 @@ void branch_solve_t(BranchData& d, double* x6, double* ltil, double* rtil,
       BranchProblem<R> P(d);
       tron<R>(P, 6, x, d.lo, d.hi, prm, st, C);
       R a[8];
-      branch_terms<R>(d, x, a, nullptr, nullptr, false);
+      branch_values<R>(d, x, a, nullptr);
       R c0 = a[0] * a[0] + a[1] * a[1] + x[4];
       R c1 = a[2] * a[2] + a[3] * a[3] + x[5];
       R cn = rmax(rabs(c0), rabs(c1));
@@ -644,7 +708,7 @@ void branch_solve_t(BranchData& d, double* x6, double* ltil, double* rtil,
     *rtil = d.rtil;
   }
   R a[8];
-  branch_terms<R>(d, x, a, nullptr, nullptr, false);
+  branch_values<R>(d, x, a, nullptr);
   for (int k = 0; k < 8; ++k) u8[k] = val(a[k]);
   for (int i = 0; i < d.n; ++i) x6[i] = val(x[i]);
 }
@@ -693,6 +757,8 @@ typedef struct {
   const int32_t *br_from, *br_to;
   const double *r, *x, *b, *tap, *shift, *rate;
 } ora_grid;
+
+void ora_sincos(double x, double* s, double* c) { series_sincos(x, s, c); }
 
 // Returns nullptr on invalid input.
 void* ora_create(const ora_grid* G, const ora_params* P) {
@@ -812,7 +878,7 @@ void ora_cold_init(void* h) {
     BranchData d;
     fill_branch_data(o, l, d);
     double a[8];
-    branch_terms<double>(d, x, a, nullptr, nullptr, false);
+    branch_values<double>(d, x, a, nullptr);
     if (o->rated[l]) {
       double f0 = -(a[0] * a[0] + a[1] * a[1]);
       double f1 = -(a[2] * a[2] + a[3] * a[3]);
@@ -1193,7 +1259,7 @@ void ora_branch_eval(const double* data, int n, const double* ltil,
   double F;
   P.fgh(x, F, g, H);
   *f = F;
-  if (a8) branch_terms<double>(d, x, a8, nullptr, nullptr, false);
+  if (a8) branch_values<double>(d, x, a8, nullptr);
 }
 
 void ora_branch_solve(const double* data, int n, double* x6, double* ltil,

@@ -1,0 +1,249 @@
+"""Python binding of the HIP library ``libacopf.so`` (C ABI in include/acopf.h).
+
+Argument marshalling only: every step of the ADMM iteration runs in the HIP
+kernels behind the C ABI. There is no CPU fallback; if the library has not
+been built, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import asdict, dataclass
+
+import numpy as np
+
+from .gridgen import Grid
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libacopf.so")
+
+COLD, WARM, CONTINUE = 0, 1, 2
+CONVERGED, MAX_ITER, NUMERICAL = 0, 1, 2
+U, V, Z, Y, LAMBDA, BRANCH_X, BRANCH_LTIL, BRANCH_RTIL, SCALARS, PD, QD, HISTORY, STATS = range(13)
+STATE_CODES = {"u": U, "v": V, "z": Z, "y": Y, "lam": LAMBDA, "bx": BRANCH_X,
+               "ltil": BRANCH_LTIL, "rtil": BRANCH_RTIL, "scalars": SCALARS,
+               "pd": PD, "qd": QD}
+STATS_NAMES = ("branch_solves", "flops", "trig", "tron_calls", "tron_iters", "n_fgh",
+               "n_f", "cauchy_trials", "cg_iters", "chol_attempts", "ps_trials",
+               "al_iters", "tron_converged", "tron_maxit", "tron_stall", "reserved")
+SCALAR_NAMES = ("beta", "znorm_prev", "r_pri", "r_dual", "r_z", "outer",
+                "inner_total", "inner_in_outer", "status")
+EXPORTS = ("acopf_default_params", "acopf_create", "acopf_solve", "acopf_update_loads",
+           "acopf_get_state", "acopf_set_state", "acopf_get_sizes", "acopf_get_timing",
+           "acopf_destroy", "acopf_last_error")
+
+
+class AcopfError(RuntimeError):
+    pass
+
+
+class _Grid(C.Structure):
+    _fields_ = [
+        ("n_bus", C.c_int32), ("n_gen", C.c_int32), ("n_branch", C.c_int32),
+        ("ref_bus", C.c_int32), ("base_mva", C.c_double),
+    ] + [(n, C.c_void_p) for n in (
+        "pd", "qd", "gs", "bs", "vmin", "vmax", "gen_bus", "pmin", "pmax", "qmin",
+        "qmax", "c2", "c1", "c0", "br_from", "br_to", "r", "x", "b", "tap",
+        "shift", "rate")]
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("rho_pq", C.c_double), ("rho_va", C.c_double), ("obj_scale", C.c_double),
+        ("rate_scale", C.c_double), ("beta0", C.c_double), ("beta_gamma", C.c_double),
+        ("beta_omega", C.c_double), ("beta_max", C.c_double), ("lambda_max", C.c_double),
+        ("eps_pri", C.c_double), ("eps_dual", C.c_double), ("eps_z", C.c_double),
+        ("max_outer", C.c_int32), ("max_inner", C.c_int32),
+        ("tron_gtol", C.c_double), ("tron_ftol", C.c_double), ("tron_maxit", C.c_int32),
+        ("al_rho0", C.c_double), ("al_rho_growth", C.c_double), ("al_rho_max", C.c_double),
+        ("al_tol", C.c_double), ("al_shrink", C.c_double), ("al_maxit", C.c_int32),
+    ]
+
+
+class _Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("inner_iters", C.c_int32),
+                ("outer_iters", C.c_int32), ("branch_failures", C.c_int32),
+                ("objective", C.c_double), ("r_pri", C.c_double), ("r_dual", C.c_double),
+                ("r_z", C.c_double), ("beta", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+@dataclass
+class Params:
+    """Method parameters; field names and order follow acopf_params."""
+    rho_pq: float = 400.0
+    rho_va: float = 40000.0
+    obj_scale: float = 1.0
+    rate_scale: float = 0.99
+    beta0: float = 1e3
+    beta_gamma: float = 6.0
+    beta_omega: float = 0.8
+    beta_max: float = 1e20
+    lambda_max: float = 1e12
+    eps_pri: float = 1e-4
+    eps_dual: float = 1e-4
+    eps_z: float = 1e-4
+    max_outer: int = 20
+    max_inner: int = 1000
+    tron_gtol: float = 1e-8
+    tron_ftol: float = 1e-14
+    tron_maxit: int = 50
+    al_rho0: float = 10.0
+    al_rho_growth: float = 10.0
+    al_rho_max: float = 1e8
+    al_tol: float = 1e-8
+    al_shrink: float = 0.25
+    al_maxit: int = 20
+
+    def c(self) -> _Params:
+        return _Params(**asdict(self))
+
+
+_lib = None
+
+
+def load(path: str | None = None) -> C.CDLL:
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise AcopfError(f"{p} not built: run __graft_entry__.build() or "
+                         "python -m paper_2110_06879_amd.build")
+    lib = C.CDLL(p)
+    vp, dp, i32, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int64
+    lib.acopf_default_params.argtypes = [C.POINTER(_Params)]
+    lib.acopf_default_params.restype = None
+    lib.acopf_create.argtypes = [C.POINTER(_Grid), i32, C.POINTER(_Params), i32, vp,
+                                 C.POINTER(vp)]
+    lib.acopf_solve.argtypes = [vp, i32, i32, C.POINTER(_Result)]
+    lib.acopf_update_loads.argtypes = [vp, i32, dp, dp]
+    lib.acopf_get_state.argtypes = [vp, i32, i32, dp, i64]
+    lib.acopf_set_state.argtypes = [vp, i32, i32, dp, i64]
+    lib.acopf_get_sizes.argtypes = [vp, i32, C.POINTER(C.c_int64)]
+    lib.acopf_get_timing.argtypes = [vp, dp]
+    lib.acopf_destroy.argtypes = [vp]
+    lib.acopf_destroy.restype = None
+    lib.acopf_last_error.restype = C.c_char_p
+    for name in ("acopf_create", "acopf_solve", "acopf_update_loads", "acopf_get_state",
+                 "acopf_set_state", "acopf_get_sizes", "acopf_get_timing"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def default_params() -> dict:
+    p = _Params()
+    load().acopf_default_params(C.byref(p))
+    return {n: getattr(p, n) for n, _ in p._fields_}
+
+
+class Solver:
+    """A handle over one or more grids resident on one GPU."""
+
+    def __init__(self, grids: Grid | list[Grid], params: Params | None = None,
+                 device: int = 0, stream=None):
+        self.lib = load()
+        self.grids = [grids] if isinstance(grids, Grid) else list(grids)
+        self.params = params or Params()
+        self._keep = []
+        cg = (_Grid * len(self.grids))()
+        for k, g in enumerate(self.grids):
+            arrs = {}
+            for n in ("pd", "qd", "gs", "bs", "vmin", "vmax", "pmin", "pmax", "qmin",
+                      "qmax", "c2", "c1", "c0", "r", "x", "b", "tap", "shift", "rate"):
+                arrs[n] = np.ascontiguousarray(getattr(g, n), dtype=np.float64)
+            for n in ("gen_bus", "br_from", "br_to"):
+                arrs[n] = np.ascontiguousarray(getattr(g, n), dtype=np.int32)
+            self._keep.append(arrs)
+            cg[k] = _Grid(n_bus=g.n_bus, n_gen=g.n_gen, n_branch=g.n_branch,
+                          ref_bus=g.ref_bus, base_mva=g.base_mva,
+                          **{n: a.ctypes.data for n, a in arrs.items()})
+        sp = None
+        if stream is not None:
+            sp = C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+        self._p = self.params.c()
+        h = C.c_void_p()
+        rc = self.lib.acopf_create(cg, len(self.grids), C.byref(self._p), device, sp,
+                                   C.byref(h))
+        self._check(rc)
+        self.h = h
+        self._keep = None
+
+    def _check(self, rc: int):
+        if rc != 0:
+            raise AcopfError(f"acopf error {rc}: {self.lib.acopf_last_error().decode()}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.acopf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def solve(self, mode: int = COLD, fixed_iters: int = 0) -> list[dict]:
+        res = (_Result * len(self.grids))()
+        self._check(self.lib.acopf_solve(self.h, mode, fixed_iters, res))
+        return [r.as_dict() for r in res]
+
+    def update_loads(self, grid: int, pd, qd):
+        pd = np.ascontiguousarray(pd, dtype=np.float64)
+        qd = np.ascontiguousarray(qd, dtype=np.float64)
+        self._check(self.lib.acopf_update_loads(self.h, grid, _dp(pd), _dp(qd)))
+
+    def _size(self, grid: int, code: int) -> int:
+        g = self.grids[grid]
+        m = 2 * g.n_gen + 8 * g.n_branch
+        return {U: m, V: m, Z: m, Y: m, LAMBDA: m, BRANCH_X: 6 * g.n_branch,
+                BRANCH_LTIL: 2 * g.n_branch, BRANCH_RTIL: g.n_branch, SCALARS: 9,
+                PD: g.n_bus, QD: g.n_bus, STATS: 16}[code]
+
+    def get(self, name: str, grid: int = 0) -> np.ndarray:
+        code = STATE_CODES[name]
+        out = np.empty(self._size(grid, code))
+        self._check(self.lib.acopf_get_state(self.h, grid, code, _dp(out), out.size))
+        return out
+
+    def set(self, name: str, val, grid: int = 0):
+        code = STATE_CODES[name]
+        a = np.ascontiguousarray(val, dtype=np.float64)
+        self._check(self.lib.acopf_set_state(self.h, grid, code, _dp(a), a.size))
+
+    def scalars(self, grid: int = 0) -> dict:
+        return dict(zip(SCALAR_NAMES, self.get("scalars", grid).tolist()))
+
+    def history(self, grid: int = 0) -> np.ndarray:
+        n = int(min(self.scalars(grid)["inner_total"], 1 << 15))
+        out = np.empty(6 * n)
+        self._check(self.lib.acopf_get_state(self.h, grid, HISTORY, _dp(out), out.size))
+        return out.reshape(-1, 6)
+
+    def stats(self) -> dict:
+        out = np.empty(16)
+        self._check(self.lib.acopf_get_state(self.h, 0, STATS, _dp(out), 16))
+        return {n: int(v) for n, v in zip(STATS_NAMES, out)}
+
+    def timing(self) -> dict:
+        out = np.zeros(7)
+        self._check(self.lib.acopf_get_timing(self.h, _dp(out)))
+        keys = ("gen_ms", "branch6_ms", "branch4_ms", "bus_ms", "ctl_ms", "outer_ms")
+        d = dict(zip(keys, out[:6].tolist()))
+        d["iters"] = int(out[6])
+        return d

@@ -1,0 +1,1216 @@
+// Host runtime and the closed-form kernels of the two-level component ADMM
+// for ACOPF (Kim & Kim, PSCC 2022) on gfx950, behind the C ABI of acopf.h.
+//
+// One inner iteration of Algorithm 1 is five launches on one stream:
+//   gen_kernel      generator closed form, eq. (qp-bound)          lane/gen
+//   branch_kernel   branch subproblems, eq. (branch), TRON + AL     lane/branch
+//   bus_kernel      bus closed form eq. (qp-bus), then z and y and
+//                   the residual maxima of every coupling it owns  lane/bus
+//   ctl_kernel      termination tests and the outer beta rule       lane/grid
+//   outer_kernel    lambda <- proj(lambda + beta z) when flagged    lane/coupling
+// The generator and branch steps read only the previous iteration's v, z, y
+// and so could run in any order; the bus step owns each coupling exactly once
+// (every coupling has one bus side), which makes the z and y updates and the
+// residual maxima a fused, race-free pass. Residual maxima are combined with
+// 64-bit integer atomicMax on the bit patterns of non-negative doubles, which
+// is exact and independent of order. Kernels return at once for grids that
+// have finished, so a chunk of launches can overshoot convergence harmlessly;
+// the host reads the per-grid control words once per chunk.
+//
+// Device layout (structure of arrays, FP64):
+//   couplings [m]: generator p [n_gen], generator q [n_gen], then for each
+//     branch kind k = 0..7 (p_ij q_ij p_ji q_ji w_i th_i w_j th_j) [n_branch];
+//   branches: rated (6-variable) ones first, then unlimited (4-variable);
+//   buses: CSR lists of generators and of branch ends (from-ends, then
+//     to-ends, in input order).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/acopf.h"
+#include "device_common.h"
+
+using acopf_dev::BranchArgs;
+using acopf_dev::GridCtl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return fail(ACOPF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kHistCap = 1 << 15;  // per grid, inner iterations kept in history
+constexpr int kStats = 16;
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+struct GenArgs {
+  int64_t ng;
+  const int* gen_grid;
+  const GridCtl* ctl;
+  const double *pmin, *pmax, *qmin, *qmax;
+  const double *c2q, *c1l;  // 2 s c2 B^2 and s c1 B
+  const double *v, *z, *y;
+  double* u;
+  double rho;
+};
+
+// eq. (qp-bound): x = max(l, min(u, c/Q)) with Q, c from the cost and the
+// coupling penalty; p and q of generator g are couplings g and n_gen + g.
+__global__ __launch_bounds__(256) void gen_kernel(GenArgs A) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= A.ng) return;
+  if (A.ctl[A.gen_grid[g]].done) return;
+  const int64_t kp = g, kq = A.ng + g;
+  const double rho = A.rho;
+  const double Qp = A.c2q[g] + rho;
+  const double cp = rho * (A.v[kp] - A.z[kp]) - A.y[kp] - A.c1l[g];
+  const double xp = cp / Qp;
+  A.u[kp] = fmax(A.pmin[g], fmin(A.pmax[g], xp));
+  const double cq = rho * (A.v[kq] - A.z[kq]) - A.y[kq];
+  const double xq = cq / rho;
+  A.u[kq] = fmax(A.qmin[g], fmin(A.qmax[g], xq));
+}
+
+struct BusArgs {
+  int64_t nb, ng, nl;
+  const int* bus_grid;
+  GridCtl* ctl;
+  const int *gptr, *gidx, *eptr, *eidx;
+  const double *pd, *qd, *gs, *bs;
+  const int* isref;
+  const double* u;
+  const double* lam;
+  double *v, *z, *y;
+  double rho_pq, rho_va;
+  unsigned long long* rmax;  // [3 G]
+};
+
+__device__ inline unsigned long long dbits(double a) {
+  return (unsigned long long)__double_as_longlong(a);
+}
+
+// eq. (qp-bus) for one bus: minimize sum_k rho_k/2 (x_k - x0_k)^2 over the
+// bus copies (generator outputs, flows leaving the bus, w) subject to the two
+// balance rows of eqs. (pg)-(qg); closed form through the 2x2 matrix
+// M = A Q^-1 A'. Then z (eq. qp-bound with no bounds) and y for every
+// coupling of the bus, and their residual maxima.
+__global__ __launch_bounds__(256) void bus_kernel(BusArgs A) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double rp = 0.0, rd = 0.0, rz = 0.0;
+  int grid = -1;
+  bool act = i < A.nb;
+  if (act) {
+    grid = A.bus_grid[i];
+    act = A.ctl[grid].done == 0;
+  }
+  if (act) {
+    const int64_t ng = A.ng, nl = A.nl, cb = 2 * ng;
+    const double rpq = A.rho_pq, rva = A.rho_va;
+    const int g0 = A.gptr[i], g1 = A.gptr[i + 1];
+    const int e0 = A.eptr[i], e1 = A.eptr[i + 1];
+    // shared w and theta of the bus
+    double Qw = 0.0, cw = 0.0, Qt = 0.0, ct = 0.0;
+    for (int e = e0; e < e1; ++e) {
+      const int code = A.eidx[e];
+      const int64_t l = code >> 1;
+      const int64_t kw = cb + ((code & 1) ? 6 : 4) * nl + l, kt = kw + nl;
+      Qw += rva;
+      cw += rva * (A.u[kw] + A.z[kw]) + A.y[kw];
+      Qt += rva;
+      ct += rva * (A.u[kt] + A.z[kt]) + A.y[kt];
+    }
+    const double awP = -A.gs[i], awQ = A.bs[i];
+    double M00 = awP * awP / Qw, M01 = awP * awQ / Qw, M11 = awQ * awQ / Qw;
+    double r0 = awP * cw / Qw - A.pd[i], r1 = awQ * cw / Qw - A.qd[i];
+    const double inv_pq = 1.0 / rpq;
+    for (int t = g0; t < g1; ++t) {
+      const int64_t g = A.gidx[t];
+      const double cvp = rpq * (A.u[g] + A.z[g]) + A.y[g];
+      M00 += inv_pq;
+      r0 += cvp / rpq;
+      const int64_t gq = ng + g;
+      const double cvq = rpq * (A.u[gq] + A.z[gq]) + A.y[gq];
+      M11 += inv_pq;
+      r1 += cvq / rpq;
+    }
+    for (int e = e0; e < e1; ++e) {
+      const int code = A.eidx[e];
+      const int64_t l = code >> 1;
+      const int64_t kp = cb + ((code & 1) ? 2 : 0) * nl + l, kq = kp + nl;
+      const double cvp = rpq * (A.u[kp] + A.z[kp]) + A.y[kp];
+      M00 += inv_pq;
+      r0 += -cvp / rpq;
+      const double cvq = rpq * (A.u[kq] + A.z[kq]) + A.y[kq];
+      M11 += inv_pq;
+      r1 += -cvq / rpq;
+    }
+    const double det = M00 * M11 - M01 * M01;
+    const double mu0 = (M11 * r0 - M01 * r1) / det;
+    const double mu1 = (M00 * r1 - M01 * r0) / det;
+    const double w = (cw - awP * mu0 - awQ * mu1) / Qw;
+    const double th = A.isref[i] ? 0.0 : ct / Qt;
+    const double beta = A.ctl[grid].beta;
+    // bus copies, then z, y and residuals of every coupling of the bus
+    auto finish = [&](int64_t k, double vnew, double rho) {
+      const double vold = A.v[k];
+      const double uk = A.u[k];
+      const double zk = -(A.lam[k] + A.y[k] + rho * (uk - vnew)) / (beta + rho);
+      const double yk = A.y[k] + rho * (uk - vnew + zk);
+      A.v[k] = vnew;
+      A.z[k] = zk;
+      A.y[k] = yk;
+      rp = fmax(rp, fabs(uk - vnew + zk));
+      rd = fmax(rd, fabs(vnew - vold));
+      rz = fmax(rz, fabs(zk));
+    };
+    for (int t = g0; t < g1; ++t) {
+      const int64_t g = A.gidx[t], gq = ng + g;
+      const double cvp = rpq * (A.u[g] + A.z[g]) + A.y[g];
+      const double cvq = rpq * (A.u[gq] + A.z[gq]) + A.y[gq];
+      finish(g, (cvp - mu0) / rpq, rpq);
+      finish(gq, (cvq - mu1) / rpq, rpq);
+    }
+    for (int e = e0; e < e1; ++e) {
+      const int code = A.eidx[e];
+      const int64_t l = code >> 1;
+      const int side = code & 1;
+      const int64_t kp = cb + (side ? 2 : 0) * nl + l, kq = kp + nl;
+      const double cvp = rpq * (A.u[kp] + A.z[kp]) + A.y[kp];
+      const double cvq = rpq * (A.u[kq] + A.z[kq]) + A.y[kq];
+      finish(kp, (cvp + mu0) / rpq, rpq);
+      finish(kq, (cvq + mu1) / rpq, rpq);
+      const int64_t kw = cb + (side ? 6 : 4) * nl + l, kt = kw + nl;
+      finish(kw, w, rva);
+      finish(kt, th, rva);
+    }
+  }
+  // wavefront max, one atomic per grid segment of the wavefront
+  const int lane = threadIdx.x & 63;
+  const int g_first = __shfl(grid, 0, 64);
+  bool uniform = true;
+  {
+    int other = grid < 0 ? g_first : grid;
+    unsigned long long ball = __ballot(other != g_first);
+    uniform = ball == 0;
+  }
+  if (uniform) {
+    for (int off = 32; off > 0; off >>= 1) {
+      rp = fmax(rp, __shfl_xor(rp, off, 64));
+      rd = fmax(rd, __shfl_xor(rd, off, 64));
+      rz = fmax(rz, __shfl_xor(rz, off, 64));
+    }
+    if (lane == 0 && g_first >= 0) {
+      atomicMax(&A.rmax[3 * g_first + 0], dbits(rp));
+      atomicMax(&A.rmax[3 * g_first + 1], dbits(rd));
+      atomicMax(&A.rmax[3 * g_first + 2], dbits(rz));
+    }
+  } else if (grid >= 0) {
+    atomicMax(&A.rmax[3 * grid + 0], dbits(rp));
+    atomicMax(&A.rmax[3 * grid + 1], dbits(rd));
+    atomicMax(&A.rmax[3 * grid + 2], dbits(rz));
+  }
+}
+
+struct CtlArgs {
+  int G;
+  GridCtl* ctl;
+  unsigned long long* rmax;
+  double* hist;  // [G][kHistCap][6]
+  double eps_pri, eps_dual, eps_z, beta_gamma, beta_omega, beta_max;
+  int max_outer, max_inner, fixed;
+};
+
+// Control of Algorithm 1 per grid: inner test (r_pri, r_dual), overall test
+// (plus ||z||), outer step decision and the beta rule.
+__global__ void ctl_kernel(CtlArgs A) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= A.G) return;
+  GridCtl& c = A.ctl[g];
+  c.do_outer = 0;
+  if (c.done) return;
+  unsigned long long* rm = A.rmax + 3 * g;
+  const double rp = __longlong_as_double((long long)rm[0]);
+  const double rd = __longlong_as_double((long long)rm[1]);
+  const double rz = __longlong_as_double((long long)rm[2]);
+  rm[0] = 0;
+  rm[1] = 0;
+  rm[2] = 0;
+  c.r_pri = rp;
+  c.r_dual = rd;
+  c.r_z = rz;
+  if (c.inner_total < kHistCap) {
+    double* h = A.hist + ((int64_t)g * kHistCap + c.inner_total) * 6;
+    h[0] = rp;
+    h[1] = rd;
+    h[2] = rz;
+    h[3] = 0.0;
+    h[4] = c.beta;
+    h[5] = (double)c.outer;
+  }
+  c.inner_total += 1;
+  c.inner_in_outer += 1;
+  if (!isfinite(rp) || !isfinite(rd) || !isfinite(rz)) {
+    c.status = ACOPF_NUMERICAL;
+    c.done = 1;
+    return;
+  }
+  const bool inner_ok = rp <= A.eps_pri && rd <= A.eps_dual;
+  if (!A.fixed && inner_ok && rz <= A.eps_z) {
+    c.status = ACOPF_CONVERGED;
+    c.done = 1;
+    return;
+  }
+  if (inner_ok || c.inner_in_outer >= A.max_inner) {
+    c.do_outer = 1;
+    c.beta_lam = c.beta;
+    if (rz > A.beta_omega * c.znorm_prev) {
+      const double b = A.beta_gamma * c.beta;
+      c.beta = b < A.beta_max ? b : A.beta_max;
+    }
+    c.znorm_prev = rz;
+    c.outer += 1;
+    c.inner_in_outer = 0;
+    if (!A.fixed && c.outer >= A.max_outer) {
+      c.status = ACOPF_MAX_ITER;
+      c.done = 1;
+    }
+  }
+  if (A.fixed && c.inner_total >= c.fixed_target) {
+    c.status = ACOPF_MAX_ITER;
+    c.done = 1;
+  }
+}
+
+struct OuterArgs {
+  int64_t m, ng, nl;
+  const int *gen_grid, *br_grid;
+  const GridCtl* ctl;
+  const double* z;
+  double* lam;
+  double lambda_max;
+};
+
+__device__ inline int coupling_grid(int64_t k, int64_t ng, int64_t nl, const int* gen_grid,
+                                    const int* br_grid) {
+  if (k < 2 * ng) return gen_grid[k < ng ? k : k - ng];
+  return br_grid[(k - 2 * ng) % nl];
+}
+
+// lambda <- proj_[-lmax, lmax](lambda + beta z) (multiplier updates, Sec. III-B)
+__global__ __launch_bounds__(256) void outer_kernel(OuterArgs A) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= A.m) return;
+  const int g = coupling_grid(k, A.ng, A.nl, A.gen_grid, A.br_grid);
+  const GridCtl& c = A.ctl[g];
+  if (!c.do_outer) return;
+  const double t = A.lam[k] + c.beta_lam * A.z[k];
+  A.lam[k] = fmax(-A.lambda_max, fmin(A.lambda_max, t));
+}
+
+struct ColdArgs {
+  int64_t ng, nl, m;
+  const int *gen_grid, *br_grid;
+  const double *pmin, *pmax, *qmin, *qmax;
+  const double* adm;
+  const double *vlo_i, *vhi_i, *vlo_j, *vhi_j, *rate2;
+  int64_t n6;
+  double *u, *v, *z, *y, *lam, *bx, *ltil, *rtil;
+  double al_rho0;
+};
+
+// Cold start (Sec. IV-B): p, q, |V| at the midpoints of their bounds, angles
+// 0, flows from the initial voltages, bus copies equal to the component
+// values, z = y = lambda = 0. Slacks start at -(p^2 + q^2) clipped to range.
+__global__ __launch_bounds__(256) void cold_kernel(ColdArgs A) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  auto setk = [&](int64_t k, double val) {
+    A.u[k] = val;
+    A.v[k] = val;
+    A.z[k] = 0.0;
+    A.y[k] = 0.0;
+    A.lam[k] = 0.0;
+  };
+  if (t < A.ng) {
+    setk(t, 0.5 * (A.pmin[t] + A.pmax[t]));
+    setk(A.ng + t, 0.5 * (A.qmin[t] + A.qmax[t]));
+    return;
+  }
+  const int64_t l = t - A.ng;
+  if (l >= A.nl) return;
+  const int64_t nl = A.nl;
+  const double vi = 0.5 * (A.vlo_i[l] + A.vhi_i[l]);
+  const double vj = 0.5 * (A.vlo_j[l] + A.vhi_j[l]);
+  // angles are zero: w^R = vi vj, w^I = 0
+  const double* Y = A.adm;
+  const double wi = vi * vi, wj = vj * vj, WR = vi * vj * 1.0, WI = vi * vj * 0.0;
+  const double a0 = Y[0 * nl + l] * wi + Y[2 * nl + l] * WR + Y[3 * nl + l] * WI;
+  const double a1 = -Y[1 * nl + l] * wi - Y[3 * nl + l] * WR + Y[2 * nl + l] * WI;
+  const double a2 = Y[6 * nl + l] * wj + Y[4 * nl + l] * WR - Y[5 * nl + l] * WI;
+  const double a3 = -Y[7 * nl + l] * wj - Y[5 * nl + l] * WR - Y[4 * nl + l] * WI;
+  const double a[8] = {a0, a1, a2, a3, wi, 0.0, wj, 0.0};
+  const int64_t cb = 2 * A.ng;
+  for (int k = 0; k < 8; ++k) setk(cb + k * nl + l, a[k]);
+  A.bx[0 * nl + l] = vi;
+  A.bx[1 * nl + l] = vj;
+  A.bx[2 * nl + l] = 0.0;
+  A.bx[3 * nl + l] = 0.0;
+  double s0 = 0.0, s1 = 0.0;
+  if (l < A.n6) {
+    const double r2 = A.rate2[l];
+    const double f0 = -(a0 * a0 + a1 * a1), f1 = -(a2 * a2 + a3 * a3);
+    s0 = f0 < -r2 ? -r2 : (f0 > 0.0 ? 0.0 : f0);
+    s1 = f1 < -r2 ? -r2 : (f1 > 0.0 ? 0.0 : f1);
+  }
+  A.bx[4 * nl + l] = s0;
+  A.bx[5 * nl + l] = s1;
+  A.ltil[l] = 0.0;
+  A.ltil[nl + l] = 0.0;
+  A.rtil[l] = A.al_rho0;
+}
+
+// Reset of the per-grid control words at the start of a solve.
+__global__ void ctl_start_kernel(GridCtl* ctl, int G, int mode, int fixed,
+                                 double beta0, unsigned long long* rmax, int* failures) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  GridCtl& c = ctl[g];
+  if (mode != ACOPF_CONTINUE) {
+    c.beta = beta0;
+    c.beta_lam = beta0;
+    c.znorm_prev = __longlong_as_double(0x7ff0000000000000ll);
+    c.outer = 0;
+    c.inner_total = 0;
+    c.inner_in_outer = 0;
+  }
+  c.status = ACOPF_MAX_ITER;
+  c.done = 0;
+  c.do_outer = 0;
+  c.numerical = 0;
+  c.fixed_target = fixed > 0 ? c.inner_total + fixed : 0x7fffffff;
+  failures[g] = 0;
+  rmax[3 * g + 0] = 0;
+  rmax[3 * g + 1] = 0;
+  rmax[3 * g + 2] = 0;
+}
+
+// Objective sum_g c2 P^2 + c1 P + c0 with P = base p_g (Sec. IV-A), one block
+// per grid, fixed-order tree reduction.
+__global__ __launch_bounds__(256) void objective_kernel(const int64_t* gen_off,
+                                                       const double* c2, const double* c1,
+                                                       const double* c0, const double* u,
+                                                       const double* base, double* out) {
+  __shared__ double sh[256];
+  const int g = blockIdx.x;
+  const int64_t a = gen_off[g], b = gen_off[g + 1];
+  double t = 0.0;
+  for (int64_t k = a + threadIdx.x; k < b; k += blockDim.x) {
+    const double P = base[g] * u[k];
+    t += c2[k] * P * P + c1[k] * P + c0[k];
+  }
+  sh[threadIdx.x] = t;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[g] = sh[0];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+struct HostGrid {
+  int64_t nb, ng, nl;
+  int64_t bus_off, gen_off;
+  std::vector<int64_t> br_dev;  // canonical branch -> device index
+  int ref;
+};
+
+struct DevBuf {
+  std::vector<void*> ptrs;
+  template <class T>
+  hipError_t alloc(T** p, size_t n) {
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
+    if (e == hipSuccess) ptrs.push_back(*p);
+    return e;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+bool finite_all(const double* a, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+struct acopf_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  acopf_params P{};
+  int G = 0;
+  int64_t nb = 0, ng = 0, nl = 0, n6 = 0, m = 0;
+  std::vector<HostGrid> grids;
+  DevBuf buf;
+  // device arrays
+  int *gen_grid = nullptr, *br_grid = nullptr, *bus_grid = nullptr;
+  double *pmin, *pmax, *qmin, *qmax, *c2q, *c1l, *c2, *c1, *c0;
+  double *adm, *vlo_i, *vhi_i, *vlo_j, *vhi_j, *rate2;
+  double *u, *v, *z, *y, *lam, *bx, *ltil, *rtil;
+  int *gptr, *gidx, *eptr, *eidx, *isref;
+  double *pd, *qd, *gs, *bs;
+  GridCtl* ctl;
+  GridCtl* h_ctl = nullptr;  // pinned
+  unsigned long long *rmax, *stats;
+  int* failures;
+  double* hist;
+  int64_t* gen_off_d;
+  double *base_d, *obj_d;
+  bool solved = false;
+  bool profile = false;
+  std::vector<hipEvent_t> ev;
+  double t_ms[6] = {0, 0, 0, 0, 0, 0};
+  int64_t t_iters = 0;
+};
+
+namespace {
+
+BranchArgs branch_args(const acopf_s* h) {
+  BranchArgs A{};
+  A.nl = h->nl;
+  A.br_coupling_base = 2 * h->ng;
+  A.br_grid = h->br_grid;
+  A.ctl = h->ctl;
+  A.adm = h->adm;
+  A.vlo_i = h->vlo_i;
+  A.vhi_i = h->vhi_i;
+  A.vlo_j = h->vlo_j;
+  A.vhi_j = h->vhi_j;
+  A.rate2 = h->rate2;
+  A.v = h->v;
+  A.z = h->z;
+  A.y = h->y;
+  A.u = h->u;
+  A.bx = h->bx;
+  A.ltil = h->ltil;
+  A.rtil = h->rtil;
+  A.rho_pq = h->P.rho_pq;
+  A.rho_va = h->P.rho_va;
+  A.tron_gtol = h->P.tron_gtol;
+  A.tron_ftol = h->P.tron_ftol;
+  A.al_tol = h->P.al_tol;
+  A.al_shrink = h->P.al_shrink;
+  A.al_rho_growth = h->P.al_rho_growth;
+  A.al_rho_max = h->P.al_rho_max;
+  A.tron_maxit = h->P.tron_maxit;
+  A.al_maxit = h->P.al_maxit;
+  A.failures = h->failures;
+  A.stats = h->stats;
+  return A;
+}
+
+int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
+
+// Launch one inner iteration; with profiling, events bracket each launch.
+void launch_iteration(acopf_s* h, int fixed, int slot) {
+  hipStream_t s = h->stream;
+  hipEvent_t* E = h->profile ? &h->ev[(size_t)slot * 12] : nullptr;
+  auto mark = [&](int k) {
+    if (E) (void)hipEventRecord(E[k], s);
+  };
+  GenArgs ga{h->ng, h->gen_grid, h->ctl, h->pmin, h->pmax, h->qmin, h->qmax,
+             h->c2q, h->c1l, h->v, h->z, h->y, h->u, h->P.rho_pq};
+  mark(0);
+  if (h->ng > 0) hipLaunchKernelGGL(gen_kernel, dim3(blocks_for(h->ng, 256)), dim3(256), 0, s, ga);
+  mark(1);
+  BranchArgs ba = branch_args(h);
+  acopf_dev::launch_branch(ba, 0, (int)h->n6, 6, s);
+  mark(2);
+  acopf_dev::launch_branch(ba, (int)h->n6, (int)(h->nl - h->n6), 4, s);
+  mark(3);
+  BusArgs bu{h->nb, h->ng, h->nl, h->bus_grid, h->ctl, h->gptr, h->gidx, h->eptr, h->eidx,
+             h->pd, h->qd, h->gs, h->bs, h->isref, h->u, h->lam, h->v, h->z, h->y,
+             h->P.rho_pq, h->P.rho_va, h->rmax};
+  hipLaunchKernelGGL(bus_kernel, dim3(blocks_for(h->nb, 256)), dim3(256), 0, s, bu);
+  mark(4);
+  CtlArgs ca{h->G, h->ctl, h->rmax, h->hist, h->P.eps_pri, h->P.eps_dual, h->P.eps_z,
+             h->P.beta_gamma, h->P.beta_omega, h->P.beta_max, h->P.max_outer,
+             h->P.max_inner, fixed};
+  hipLaunchKernelGGL(ctl_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, s, ca);
+  mark(5);
+  OuterArgs oa{h->m, h->ng, h->nl, h->gen_grid, h->br_grid, h->ctl, h->z, h->lam,
+               h->P.lambda_max};
+  hipLaunchKernelGGL(outer_kernel, dim3(blocks_for(h->m, 256)), dim3(256), 0, s, oa);
+  mark(6);
+}
+
+int validate_grid(const acopf_grid& g, int idx) {
+  std::string p = "grid " + std::to_string(idx) + ": ";
+  if (g.n_bus < 1 || g.n_branch < 1 || g.n_gen < 0)
+    return fail(ACOPF_EINVAL, p + "need n_bus >= 1, n_branch >= 1, n_gen >= 0");
+  if (!(g.base_mva > 0.0) || !std::isfinite(g.base_mva))
+    return fail(ACOPF_EINVAL, p + "base_mva must be positive");
+  if (g.ref_bus < 0 || g.ref_bus >= g.n_bus) return fail(ACOPF_EINVAL, p + "ref_bus out of range");
+  const void* need[] = {g.pd, g.qd, g.gs, g.bs, g.vmin, g.vmax, g.br_from, g.br_to,
+                        g.r, g.x, g.b, g.tap, g.shift, g.rate};
+  for (const void* q : need)
+    if (!q) return fail(ACOPF_EINVAL, p + "null array");
+  if (g.n_gen > 0) {
+    const void* needg[] = {g.gen_bus, g.pmin, g.pmax, g.qmin, g.qmax, g.c2, g.c1, g.c0};
+    for (const void* q : needg)
+      if (!q) return fail(ACOPF_EINVAL, p + "null generator array");
+  }
+  const double* bus_arrs[] = {g.pd, g.qd, g.gs, g.bs, g.vmin, g.vmax};
+  for (const double* a : bus_arrs)
+    if (!finite_all(a, g.n_bus)) return fail(ACOPF_EINVAL, p + "non-finite bus data");
+  for (int i = 0; i < g.n_bus; ++i)
+    if (!(g.vmin[i] > 0.0) || g.vmin[i] > g.vmax[i])
+      return fail(ACOPF_EINVAL, p + "need 0 < vmin <= vmax at bus " + std::to_string(i));
+  if (g.n_gen > 0) {
+    const double* gen_arrs[] = {g.pmin, g.pmax, g.qmin, g.qmax, g.c2, g.c1, g.c0};
+    for (const double* a : gen_arrs)
+      if (!finite_all(a, g.n_gen)) return fail(ACOPF_EINVAL, p + "non-finite generator data");
+    for (int k = 0; k < g.n_gen; ++k) {
+      if (g.gen_bus[k] < 0 || g.gen_bus[k] >= g.n_bus)
+        return fail(ACOPF_EINVAL, p + "gen_bus out of range");
+      if (g.pmin[k] > g.pmax[k] || g.qmin[k] > g.qmax[k])
+        return fail(ACOPF_EINVAL, p + "empty generator bound interval");
+      if (g.c2[k] < 0.0) return fail(ACOPF_EINVAL, p + "negative quadratic cost");
+    }
+  }
+  const double* br_arrs[] = {g.r, g.x, g.b, g.tap, g.shift, g.rate};
+  for (const double* a : br_arrs)
+    if (!finite_all(a, g.n_branch)) return fail(ACOPF_EINVAL, p + "non-finite branch data");
+  std::vector<int> deg(g.n_bus, 0);
+  for (int l = 0; l < g.n_branch; ++l) {
+    const int i = g.br_from[l], j = g.br_to[l];
+    if (i < 0 || i >= g.n_bus || j < 0 || j >= g.n_bus || i == j)
+      return fail(ACOPF_EINVAL, p + "bad branch end at branch " + std::to_string(l));
+    if (g.r[l] == 0.0 && g.x[l] == 0.0)
+      return fail(ACOPF_EINVAL, p + "r = x = 0 at branch " + std::to_string(l));
+    if (!(g.tap[l] > 0.0)) return fail(ACOPF_EINVAL, p + "tap must be positive");
+    ++deg[i];
+    ++deg[j];
+  }
+  for (int i = 0; i < g.n_bus; ++i)
+    if (deg[i] == 0) return fail(ACOPF_EINVAL, p + "isolated bus " + std::to_string(i));
+  return ACOPF_OK;
+}
+
+int validate_params(const acopf_params& P) {
+  if (!(P.rho_pq > 0) || !(P.rho_va > 0)) return fail(ACOPF_EINVAL, "rho must be positive");
+  if (!(P.beta0 > 0) || !(P.beta_max >= P.beta0) || !(P.beta_gamma >= 1.0))
+    return fail(ACOPF_EINVAL, "need beta0 > 0, beta_max >= beta0, beta_gamma >= 1");
+  if (!(P.obj_scale >= 0) || !(P.rate_scale > 0)) return fail(ACOPF_EINVAL, "bad scales");
+  if (P.max_outer < 1 || P.max_inner < 1 || P.tron_maxit < 1 || P.al_maxit < 1)
+    return fail(ACOPF_EINVAL, "iteration caps must be >= 1");
+  if (!(P.al_rho0 > 0) || !(P.al_rho_max >= P.al_rho0) || !(P.lambda_max > 0))
+    return fail(ACOPF_EINVAL, "bad AL or lambda parameters");
+  return ACOPF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void acopf_default_params(acopf_params* p) {
+  if (!p) return;
+  p->rho_pq = 400.0;
+  p->rho_va = 40000.0;
+  p->obj_scale = 1.0;
+  p->rate_scale = 0.99;
+  p->beta0 = 1e3;
+  p->beta_gamma = 6.0;
+  p->beta_omega = 0.8;
+  p->beta_max = 1e20;
+  p->lambda_max = 1e12;
+  p->eps_pri = 1e-4;
+  p->eps_dual = 1e-4;
+  p->eps_z = 1e-4;
+  p->max_outer = 20;
+  p->max_inner = 1000;
+  p->tron_gtol = 1e-8;
+  p->tron_ftol = 1e-14;
+  p->tron_maxit = 50;
+  p->al_rho0 = 10.0;
+  p->al_rho_growth = 10.0;
+  p->al_rho_max = 1e8;
+  p->al_tol = 1e-8;
+  p->al_shrink = 0.25;
+  p->al_maxit = 20;
+}
+
+const char* acopf_last_error(void) { return g_err.c_str(); }
+
+void acopf_destroy(acopf_handle h) {
+  if (!h) return;
+  if (h->device >= 0) (void)hipSetDevice(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  h->buf.release();
+  if (h->h_ctl) (void)hipHostFree(h->h_ctl);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_params* params,
+                       int32_t device, void* hip_stream, acopf_s* h) {
+  if (!grids || n_grids < 1 || !params) return fail(ACOPF_EINVAL, "need grids, n_grids >= 1, params");
+  int rc = validate_params(*params);
+  if (rc) return rc;
+  for (int g = 0; g < n_grids; ++g) {
+    rc = validate_grid(grids[g], g);
+    if (rc) return rc;
+  }
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(ACOPF_EINVAL, "device index out of range");
+  HIP_TRY(hipSetDevice(device));
+  h->device = device;
+  h->P = *params;
+  h->G = n_grids;
+  if (hip_stream) {
+    h->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    HIP_TRY(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+    h->own_stream = true;
+  }
+  const char* prof = std::getenv("ACOPF_PROFILE");
+  h->profile = prof && prof[0] == '1';
+
+  // ---- sizes and orders
+  h->grids.resize(n_grids);
+  int64_t nb = 0, ng = 0, nl = 0, n6 = 0;
+  for (int g = 0; g < n_grids; ++g) {
+    const acopf_grid& G = grids[g];
+    HostGrid& H = h->grids[g];
+    H.nb = G.n_bus;
+    H.ng = G.n_gen;
+    H.nl = G.n_branch;
+    H.bus_off = nb;
+    H.gen_off = ng;
+    H.ref = G.ref_bus;
+    nb += G.n_bus;
+    ng += G.n_gen;
+    nl += G.n_branch;
+    for (int l = 0; l < G.n_branch; ++l) n6 += G.rate[l] > 0.0 ? 1 : 0;
+  }
+  h->nb = nb;
+  h->ng = ng;
+  h->nl = nl;
+  h->n6 = n6;
+  h->m = 2 * ng + 8 * nl;
+  if (nl >= (int64_t(1) << 30) || nb >= (int64_t(1) << 31))
+    return fail(ACOPF_EINVAL, "problem too large for 32-bit element indices");
+  // device branch order: rated first, then unlimited; each by (grid, index)
+  std::vector<int> dev_grid(nl), dev_canon(nl);
+  {
+    int64_t r6 = 0, r4 = n6;
+    for (int g = 0; g < n_grids; ++g) {
+      const acopf_grid& G = grids[g];
+      h->grids[g].br_dev.resize(G.n_branch);
+      for (int l = 0; l < G.n_branch; ++l) {
+        const int64_t d = G.rate[l] > 0.0 ? r6++ : r4++;
+        h->grids[g].br_dev[l] = d;
+        dev_grid[d] = g;
+        dev_canon[d] = l;
+      }
+    }
+  }
+  // ---- host arrays in device order
+  std::vector<int> gen_grid(ng), bus_grid(nb), isref(nb, 0);
+  std::vector<double> pmin(ng), pmax(ng), qmin(ng), qmax(ng), c2q(ng), c1l(ng), c2(ng),
+      c1(ng), c0(ng);
+  std::vector<double> adm(8 * nl), vlo_i(nl), vhi_i(nl), vlo_j(nl), vhi_j(nl), rate2(nl);
+  std::vector<double> pd(nb), qd(nb), gs(nb), bs(nb);
+  std::vector<int> gptr(nb + 1, 0), eptr(nb + 1, 0);
+  std::vector<int64_t> gen_off(n_grids + 1, 0);
+  std::vector<double> base(n_grids);
+  const double s = params->obj_scale;
+  for (int g = 0; g < n_grids; ++g) {
+    const acopf_grid& G = grids[g];
+    const HostGrid& H = h->grids[g];
+    const double B = G.base_mva;
+    base[g] = B;
+    gen_off[g] = H.gen_off;
+    gen_off[g + 1] = H.gen_off + H.ng;
+    for (int k = 0; k < G.n_gen; ++k) {
+      const int64_t d = H.gen_off + k;
+      gen_grid[d] = g;
+      pmin[d] = G.pmin[k];
+      pmax[d] = G.pmax[k];
+      qmin[d] = G.qmin[k];
+      qmax[d] = G.qmax[k];
+      c2[d] = G.c2[k];
+      c1[d] = G.c1[k];
+      c0[d] = G.c0[k];
+      c2q[d] = 2.0 * s * G.c2[k] * B * B;
+      c1l[d] = s * G.c1[k] * B;
+    }
+    for (int i = 0; i < G.n_bus; ++i) {
+      const int64_t d = H.bus_off + i;
+      bus_grid[d] = g;
+      pd[d] = G.pd[i];
+      qd[d] = G.qd[i];
+      gs[d] = G.gs[i];
+      bs[d] = G.bs[i];
+      isref[d] = i == G.ref_bus;
+    }
+    for (int l = 0; l < G.n_branch; ++l) {
+      const int64_t d = H.br_dev[l];
+      // pi model (below eq. acopf): series y = 1/(r + jx) = yr + j yi,
+      // charging j b/2 at each end, turns ratio a = tap e^{j shift} = ar + j ai:
+      //   (y + j b/2)/|a|^2,  -y/conj(a) = -y a/|a|^2,  -y/a = -y conj(a)/|a|^2,
+      //   y + j b/2, expanded in real arithmetic.
+      const double r = G.r[l], xx = G.x[l];
+      const double den = r * r + xx * xx;
+      const double yr = r / den, yi = -xx / den;
+      const double ar = G.tap[l] * std::cos(G.shift[l]);
+      const double ai = G.tap[l] * std::sin(G.shift[l]);
+      const double a2 = G.tap[l] * G.tap[l];
+      const double hb = 0.5 * G.b[l];
+      adm[0 * nl + d] = yr / a2;
+      adm[1 * nl + d] = (yi + hb) / a2;
+      adm[2 * nl + d] = -(yr * ar - yi * ai) / a2;
+      adm[3 * nl + d] = -(yr * ai + yi * ar) / a2;
+      adm[4 * nl + d] = -(yr * ar + yi * ai) / a2;
+      adm[5 * nl + d] = -(yi * ar - yr * ai) / a2;
+      adm[6 * nl + d] = yr;
+      adm[7 * nl + d] = yi + hb;
+      const int i = G.br_from[l], j = G.br_to[l];
+      vlo_i[d] = G.vmin[i];
+      vhi_i[d] = G.vmax[i];
+      vlo_j[d] = G.vmin[j];
+      vhi_j[d] = G.vmax[j];
+      const double rs = G.rate[l] * params->rate_scale;
+      rate2[d] = G.rate[l] > 0.0 ? rs * rs : 0.0;
+    }
+  }
+  // CSR: generators per bus, and branch ends per bus (from-ends then to-ends)
+  std::vector<int> gidx(ng), eidx(2 * nl);
+  {
+    std::vector<int> gcount(nb, 0), fcount(nb, 0), tcount(nb, 0);
+    for (int g = 0; g < n_grids; ++g) {
+      const acopf_grid& G = grids[g];
+      const HostGrid& H = h->grids[g];
+      for (int k = 0; k < G.n_gen; ++k) ++gcount[H.bus_off + G.gen_bus[k]];
+      for (int l = 0; l < G.n_branch; ++l) {
+        ++fcount[H.bus_off + G.br_from[l]];
+        ++tcount[H.bus_off + G.br_to[l]];
+      }
+    }
+    for (int64_t b = 0; b < nb; ++b) {
+      gptr[b + 1] = gptr[b] + gcount[b];
+      eptr[b + 1] = eptr[b] + fcount[b] + tcount[b];
+    }
+    std::vector<int> gpos(gptr.begin(), gptr.end() - 1), fpos(nb), tpos(nb);
+    for (int64_t b = 0; b < nb; ++b) {
+      fpos[b] = eptr[b];
+      tpos[b] = eptr[b] + fcount[b];
+    }
+    for (int g = 0; g < n_grids; ++g) {
+      const acopf_grid& G = grids[g];
+      const HostGrid& H = h->grids[g];
+      for (int k = 0; k < G.n_gen; ++k) gidx[gpos[H.bus_off + G.gen_bus[k]]++] = (int)(H.gen_off + k);
+      for (int l = 0; l < G.n_branch; ++l) {
+        const int d = (int)H.br_dev[l];
+        eidx[fpos[H.bus_off + G.br_from[l]]++] = d * 2 + 0;
+        eidx[tpos[H.bus_off + G.br_to[l]]++] = d * 2 + 1;
+      }
+    }
+  }
+  // ---- device allocation and upload
+  DevBuf& D = h->buf;
+  const int64_t m = h->m;
+  HIP_TRY(D.alloc(&h->gen_grid, ng));
+  HIP_TRY(D.alloc(&h->br_grid, nl));
+  HIP_TRY(D.alloc(&h->bus_grid, nb));
+  double** gen_d[] = {&h->pmin, &h->pmax, &h->qmin, &h->qmax, &h->c2q, &h->c1l, &h->c2, &h->c1, &h->c0};
+  for (double** p : gen_d) HIP_TRY(D.alloc(p, ng));
+  HIP_TRY(D.alloc(&h->adm, 8 * nl));
+  double** br_d[] = {&h->vlo_i, &h->vhi_i, &h->vlo_j, &h->vhi_j, &h->rate2, &h->rtil};
+  for (double** p : br_d) HIP_TRY(D.alloc(p, nl));
+  HIP_TRY(D.alloc(&h->bx, 6 * nl));
+  HIP_TRY(D.alloc(&h->ltil, 2 * nl));
+  double** cp_d[] = {&h->u, &h->v, &h->z, &h->y, &h->lam};
+  for (double** p : cp_d) HIP_TRY(D.alloc(p, m));
+  HIP_TRY(D.alloc(&h->gptr, nb + 1));
+  HIP_TRY(D.alloc(&h->gidx, ng));
+  HIP_TRY(D.alloc(&h->eptr, nb + 1));
+  HIP_TRY(D.alloc(&h->eidx, 2 * nl));
+  HIP_TRY(D.alloc(&h->isref, nb));
+  double** bus_d[] = {&h->pd, &h->qd, &h->gs, &h->bs};
+  for (double** p : bus_d) HIP_TRY(D.alloc(p, nb));
+  HIP_TRY(D.alloc(&h->ctl, n_grids));
+  HIP_TRY(D.alloc(&h->rmax, 3 * n_grids));
+  HIP_TRY(D.alloc(&h->stats, kStats));
+  HIP_TRY(D.alloc(&h->failures, n_grids));
+  HIP_TRY(D.alloc(&h->hist, (size_t)n_grids * kHistCap * 6));
+  HIP_TRY(D.alloc(&h->gen_off_d, n_grids + 1));
+  HIP_TRY(D.alloc(&h->base_d, n_grids));
+  HIP_TRY(D.alloc(&h->obj_d, n_grids));
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->h_ctl), sizeof(GridCtl) * n_grids,
+                        hipHostMallocDefault));
+  hipStream_t st = h->stream;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  HIP_TRY(up(h->gen_grid, gen_grid.data(), sizeof(int) * ng));
+  HIP_TRY(up(h->br_grid, dev_grid.data(), sizeof(int) * nl));
+  HIP_TRY(up(h->bus_grid, bus_grid.data(), sizeof(int) * nb));
+  const std::vector<double>* gen_h[] = {&pmin, &pmax, &qmin, &qmax, &c2q, &c1l, &c2, &c1, &c0};
+  for (int q = 0; q < 9; ++q) HIP_TRY(up(*gen_d[q], gen_h[q]->data(), sizeof(double) * ng));
+  HIP_TRY(up(h->adm, adm.data(), sizeof(double) * 8 * nl));
+  HIP_TRY(up(h->vlo_i, vlo_i.data(), sizeof(double) * nl));
+  HIP_TRY(up(h->vhi_i, vhi_i.data(), sizeof(double) * nl));
+  HIP_TRY(up(h->vlo_j, vlo_j.data(), sizeof(double) * nl));
+  HIP_TRY(up(h->vhi_j, vhi_j.data(), sizeof(double) * nl));
+  HIP_TRY(up(h->rate2, rate2.data(), sizeof(double) * nl));
+  HIP_TRY(up(h->gptr, gptr.data(), sizeof(int) * (nb + 1)));
+  HIP_TRY(up(h->gidx, gidx.data(), sizeof(int) * ng));
+  HIP_TRY(up(h->eptr, eptr.data(), sizeof(int) * (nb + 1)));
+  HIP_TRY(up(h->eidx, eidx.data(), sizeof(int) * 2 * nl));
+  HIP_TRY(up(h->isref, isref.data(), sizeof(int) * nb));
+  HIP_TRY(up(h->pd, pd.data(), sizeof(double) * nb));
+  HIP_TRY(up(h->qd, qd.data(), sizeof(double) * nb));
+  HIP_TRY(up(h->gs, gs.data(), sizeof(double) * nb));
+  HIP_TRY(up(h->bs, bs.data(), sizeof(double) * nb));
+  HIP_TRY(up(h->gen_off_d, gen_off.data(), sizeof(int64_t) * (n_grids + 1)));
+  HIP_TRY(up(h->base_d, base.data(), sizeof(double) * n_grids));
+  HIP_TRY(hipMemsetAsync(h->stats, 0, sizeof(unsigned long long) * kStats, st));
+  HIP_TRY(hipMemsetAsync(h->hist, 0, sizeof(double) * (size_t)n_grids * kHistCap * 6, st));
+  HIP_TRY(hipMemsetAsync(h->ctl, 0, sizeof(GridCtl) * n_grids, st));
+  if (h->profile) {
+    h->ev.resize(12 * 64);
+    for (auto& e : h->ev) HIP_TRY(hipEventCreate(&e));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  return ACOPF_OK;
+}
+
+int acopf_create(const acopf_grid* grids, int32_t n_grids, const acopf_params* params,
+                 int32_t device, void* hip_stream, acopf_handle* out) {
+  if (!out) return fail(ACOPF_EINVAL, "out is null");
+  *out = nullptr;
+  auto* h = new (std::nothrow) acopf_s();
+  if (!h) return fail(ACOPF_ENOMEM, "host allocation failed");
+  h->device = -1;
+  int rc = create_impl(grids, n_grids, params, device, hip_stream, h);
+  if (rc) {
+    std::string msg = g_err;
+    acopf_destroy(h);
+    g_err = msg;
+    return rc == ACOPF_EDEVICE && msg.find("hipMalloc") != std::string::npos ? ACOPF_ENOMEM : rc;
+  }
+  // cold state so that get_state is meaningful before the first solve
+  ColdArgs ca{h->ng, h->nl, h->m, h->gen_grid, h->br_grid, h->pmin, h->pmax, h->qmin, h->qmax,
+              h->adm, h->vlo_i, h->vhi_i, h->vlo_j, h->vhi_j, h->rate2, h->n6,
+              h->u, h->v, h->z, h->y, h->lam, h->bx, h->ltil, h->rtil, h->P.al_rho0};
+  hipLaunchKernelGGL(cold_kernel, dim3(blocks_for(h->ng + h->nl, 256)), dim3(256), 0, h->stream, ca);
+  hipLaunchKernelGGL(ctl_start_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, h->stream,
+                     h->ctl, h->G, (int)ACOPF_COLD, 0, h->P.beta0, h->rmax, h->failures);
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    acopf_destroy(h);
+    return fail(ACOPF_EDEVICE, std::string("cold start: ") + hipGetErrorString(e));
+  }
+  *out = h;
+  return ACOPF_OK;
+}
+
+static void accumulate_timing(acopf_s* h, int used) {
+  for (int s = 0; s < used; ++s) {
+    hipEvent_t* E = &h->ev[(size_t)s * 12];
+    for (int k = 0; k < 6; ++k) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, E[k], E[k + 1]) == hipSuccess) h->t_ms[k] += ms;
+    }
+  }
+  h->t_iters += used;
+}
+
+int acopf_solve(acopf_handle h, int32_t mode, int32_t fixed_iters, acopf_result* results) {
+  if (!h) return fail(ACOPF_EINVAL, "null handle");
+  if (mode != ACOPF_COLD && mode != ACOPF_WARM && mode != ACOPF_CONTINUE)
+    return fail(ACOPF_EINVAL, "mode must be COLD, WARM or CONTINUE");
+  if (fixed_iters < 0) return fail(ACOPF_EINVAL, "fixed_iters must be >= 0");
+  if (mode != ACOPF_COLD && !h->solved)
+    return fail(ACOPF_ESTATE, "warm or continued solve before any solve");
+  HIP_TRY(hipSetDevice(h->device));
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = h->stream;
+  if (mode == ACOPF_COLD) {
+    ColdArgs ca{h->ng, h->nl, h->m, h->gen_grid, h->br_grid, h->pmin, h->pmax, h->qmin,
+                h->qmax, h->adm, h->vlo_i, h->vhi_i, h->vlo_j, h->vhi_j, h->rate2, h->n6,
+                h->u, h->v, h->z, h->y, h->lam, h->bx, h->ltil, h->rtil, h->P.al_rho0};
+    hipLaunchKernelGGL(cold_kernel, dim3(blocks_for(h->ng + h->nl, 256)), dim3(256), 0, st, ca);
+  }
+  hipLaunchKernelGGL(ctl_start_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, st, h->ctl,
+                     h->G, (int)mode, (int)fixed_iters, h->P.beta0, h->rmax, h->failures);
+  HIP_TRY(hipGetLastError());
+  if (h->profile) {
+    for (double& t : h->t_ms) t = 0.0;
+    h->t_iters = 0;
+  }
+  const int64_t cap = fixed_iters > 0
+                          ? fixed_iters
+                          : (int64_t)h->P.max_outer * h->P.max_inner + 1;
+  int64_t issued = 0;
+  const int chunk = 16;
+  bool all_done = false;
+  while (!all_done && issued < cap) {
+    const int k = (int)std::min<int64_t>(chunk, cap - issued);
+    for (int c = 0; c < k; ++c) launch_iteration(h, fixed_iters, c);
+    issued += k;
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(GridCtl) * h->G, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h->profile) accumulate_timing(h, k);
+    all_done = true;
+    for (int g = 0; g < h->G; ++g) all_done = all_done && h->h_ctl[g].done;
+  }
+  h->solved = true;
+  // objective and failure counts
+  hipLaunchKernelGGL(objective_kernel, dim3(h->G), dim3(256), 0, st, h->gen_off_d, h->c2,
+                     h->c1, h->c0, h->u, h->base_d, h->obj_d);
+  std::vector<double> obj(h->G);
+  std::vector<int> fails(h->G);
+  HIP_TRY(hipMemcpyAsync(obj.data(), h->obj_d, sizeof(double) * h->G, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(fails.data(), h->failures, sizeof(int) * h->G, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(GridCtl) * h->G, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const double secs =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (results) {
+    for (int g = 0; g < h->G; ++g) {
+      const GridCtl& c = h->h_ctl[g];
+      acopf_result& r = results[g];
+      r.status = c.done ? c.status : ACOPF_MAX_ITER;
+      r.inner_iters = c.inner_total;
+      r.outer_iters = c.outer;
+      r.branch_failures = fails[g];
+      r.objective = obj[g];
+      r.r_pri = c.r_pri;
+      r.r_dual = c.r_dual;
+      r.r_z = c.r_z;
+      r.beta = c.beta;
+      r.seconds = secs;
+    }
+  }
+  return ACOPF_OK;
+}
+
+int acopf_update_loads(acopf_handle h, int32_t grid, const double* pd, const double* qd) {
+  if (!h) return fail(ACOPF_EINVAL, "null handle");
+  if (grid < 0 || grid >= h->G) return fail(ACOPF_EINVAL, "grid index out of range");
+  if (!pd || !qd) return fail(ACOPF_EINVAL, "null load array");
+  const HostGrid& H = h->grids[grid];
+  if (!finite_all(pd, H.nb) || !finite_all(qd, H.nb))
+    return fail(ACOPF_EINVAL, "non-finite load");
+  HIP_TRY(hipSetDevice(h->device));
+  HIP_TRY(hipMemcpyAsync(h->pd + H.bus_off, pd, sizeof(double) * H.nb, hipMemcpyHostToDevice,
+                         h->stream));
+  HIP_TRY(hipMemcpyAsync(h->qd + H.bus_off, qd, sizeof(double) * H.nb, hipMemcpyHostToDevice,
+                         h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return ACOPF_OK;
+}
+
+static int64_t state_size(const HostGrid& H, int what) {
+  const int64_t m = 2 * H.ng + 8 * H.nl;
+  switch (what) {
+    case ACOPF_U: case ACOPF_V: case ACOPF_Z: case ACOPF_Y: case ACOPF_LAMBDA: return m;
+    case ACOPF_BRANCH_X: return 6 * H.nl;
+    case ACOPF_BRANCH_LTIL: return 2 * H.nl;
+    case ACOPF_BRANCH_RTIL: return H.nl;
+    case ACOPF_SCALARS: return 9;
+    case ACOPF_PD: case ACOPF_QD: return H.nb;
+    case ACOPF_STATS: return kStats;
+    default: return -1;
+  }
+}
+
+// canonical <-> device permutations of the per-grid vectors
+static int copy_state(acopf_s* h, int grid, int what, double* host, int64_t n, bool to_host) {
+  const HostGrid& H = h->grids[grid];
+  hipStream_t st = h->stream;
+  auto pull = [&](const double* dsrc, int64_t count, std::vector<double>& tmp) {
+    tmp.resize(count);
+    return hipMemcpyAsync(tmp.data(), dsrc, sizeof(double) * count, hipMemcpyDeviceToHost, st);
+  };
+  auto push = [&](double* ddst, const std::vector<double>& tmp) {
+    return hipMemcpyAsync(ddst, tmp.data(), sizeof(double) * tmp.size(), hipMemcpyHostToDevice, st);
+  };
+  const int64_t ng = h->ng, nl = h->nl;
+  if (what <= ACOPF_LAMBDA) {
+    double* base = what == ACOPF_U ? h->u : what == ACOPF_V ? h->v : what == ACOPF_Z ? h->z
+                   : what == ACOPF_Y ? h->y : h->lam;
+    std::vector<double> all;
+    // whole vector round trip (state vectors are small next to HBM bandwidth)
+    HIP_TRY(pull(base, h->m, all));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t k = 0; k < H.ng; ++k) {
+      double* p0 = &all[H.gen_off + k];
+      double* p1 = &all[ng + H.gen_off + k];
+      if (to_host) { host[2 * k] = *p0; host[2 * k + 1] = *p1; }
+      else { *p0 = host[2 * k]; *p1 = host[2 * k + 1]; }
+    }
+    for (int64_t l = 0; l < H.nl; ++l) {
+      const int64_t d = H.br_dev[l];
+      for (int k = 0; k < 8; ++k) {
+        double* p = &all[2 * ng + k * nl + d];
+        double* q = &host[2 * H.ng + 8 * l + k];
+        if (to_host) *q = *p; else *p = *q;
+      }
+    }
+    if (!to_host) {
+      HIP_TRY(push(base, all));
+      HIP_TRY(hipStreamSynchronize(st));
+    }
+    return ACOPF_OK;
+  }
+  if (what == ACOPF_BRANCH_X || what == ACOPF_BRANCH_LTIL || what == ACOPF_BRANCH_RTIL) {
+    const int rows = what == ACOPF_BRANCH_X ? 6 : what == ACOPF_BRANCH_LTIL ? 2 : 1;
+    double* base = what == ACOPF_BRANCH_X ? h->bx : what == ACOPF_BRANCH_LTIL ? h->ltil : h->rtil;
+    std::vector<double> all;
+    HIP_TRY(pull(base, rows * nl, all));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t l = 0; l < H.nl; ++l) {
+      const int64_t d = H.br_dev[l];
+      for (int r = 0; r < rows; ++r) {
+        double* p = &all[r * nl + d];
+        double* q = &host[rows * l + r];
+        if (to_host) *q = *p; else *p = *q;
+      }
+    }
+    if (!to_host) {
+      HIP_TRY(push(base, all));
+      HIP_TRY(hipStreamSynchronize(st));
+    }
+    return ACOPF_OK;
+  }
+  if (what == ACOPF_PD || what == ACOPF_QD) {
+    double* base = (what == ACOPF_PD ? h->pd : h->qd) + H.bus_off;
+    if (to_host)
+      HIP_TRY(hipMemcpyAsync(host, base, sizeof(double) * H.nb, hipMemcpyDeviceToHost, st));
+    else
+      HIP_TRY(hipMemcpyAsync(base, host, sizeof(double) * H.nb, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return ACOPF_OK;
+  }
+  if (what == ACOPF_SCALARS) {
+    GridCtl c;
+    HIP_TRY(hipMemcpyAsync(&c, h->ctl + grid, sizeof(GridCtl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (to_host) {
+      const double vals[9] = {c.beta, c.znorm_prev, c.r_pri, c.r_dual, c.r_z, (double)c.outer,
+                              (double)c.inner_total, (double)c.inner_in_outer, (double)c.status};
+      std::memcpy(host, vals, sizeof(vals));
+    } else {
+      c.beta = host[0];
+      c.znorm_prev = host[1];
+      c.r_pri = host[2];
+      c.r_dual = host[3];
+      c.r_z = host[4];
+      c.outer = (int)host[5];
+      c.inner_total = (int)host[6];
+      c.inner_in_outer = (int)host[7];
+      c.status = (int)host[8];
+      HIP_TRY(hipMemcpyAsync(h->ctl + grid, &c, sizeof(GridCtl), hipMemcpyHostToDevice, st));
+      HIP_TRY(hipStreamSynchronize(st));
+    }
+    return ACOPF_OK;
+  }
+  if (what == ACOPF_STATS && to_host) {
+    unsigned long long s[kStats];
+    HIP_TRY(hipMemcpyAsync(s, h->stats, sizeof(s), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int q = 0; q < kStats; ++q) host[q] = (double)s[q];
+    return ACOPF_OK;
+  }
+  return fail(ACOPF_EINVAL, "unsupported state code for this direction");
+}
+
+int acopf_get_state(acopf_handle h, int32_t grid, int32_t what, double* out, int64_t n) {
+  if (!h) return fail(ACOPF_EINVAL, "null handle");
+  if (grid < 0 || grid >= h->G) return fail(ACOPF_EINVAL, "grid index out of range");
+  if (!out) return fail(ACOPF_EINVAL, "null output");
+  HIP_TRY(hipSetDevice(h->device));
+  if (what == ACOPF_HISTORY) {
+    GridCtl c;
+    HIP_TRY(hipMemcpy(&c, h->ctl + grid, sizeof(GridCtl), hipMemcpyDeviceToHost));
+    const int64_t len = (int64_t)std::min(c.inner_total, kHistCap) * 6;
+    if (n != len) return fail(ACOPF_EINVAL, "history size must be 6 * min(inner_total, cap) = " + std::to_string(len));
+    HIP_TRY(hipMemcpy(out, h->hist + (int64_t)grid * kHistCap * 6, sizeof(double) * len,
+                      hipMemcpyDeviceToHost));
+    return ACOPF_OK;
+  }
+  const int64_t need = state_size(h->grids[grid], what);
+  if (need < 0) return fail(ACOPF_EINVAL, "unknown state code");
+  if (n != need) return fail(ACOPF_EINVAL, "buffer size mismatch: need " + std::to_string(need));
+  return copy_state(h, grid, what, out, n, true);
+}
+
+int acopf_set_state(acopf_handle h, int32_t grid, int32_t what, const double* in, int64_t n) {
+  if (!h) return fail(ACOPF_EINVAL, "null handle");
+  if (grid < 0 || grid >= h->G) return fail(ACOPF_EINVAL, "grid index out of range");
+  if (!in) return fail(ACOPF_EINVAL, "null input");
+  if (what == ACOPF_HISTORY || what == ACOPF_STATS) return fail(ACOPF_EINVAL, "read-only state");
+  const int64_t need = state_size(h->grids[grid], what);
+  if (need < 0) return fail(ACOPF_EINVAL, "unknown state code");
+  if (n != need) return fail(ACOPF_EINVAL, "buffer size mismatch: need " + std::to_string(need));
+  if (!finite_all(in, n) && what != ACOPF_SCALARS) return fail(ACOPF_EINVAL, "non-finite state");
+  HIP_TRY(hipSetDevice(h->device));
+  h->solved = true;
+  return copy_state(h, grid, what, const_cast<double*>(in), n, false);
+}
+
+int acopf_get_sizes(acopf_handle h, int32_t grid, int64_t* out4) {
+  if (!h || !out4) return fail(ACOPF_EINVAL, "null argument");
+  if (grid < 0 || grid >= h->G) return fail(ACOPF_EINVAL, "grid index out of range");
+  const HostGrid& H = h->grids[grid];
+  out4[0] = h->G;
+  out4[1] = H.nb;
+  out4[2] = H.ng;
+  out4[3] = H.nl;
+  return ACOPF_OK;
+}
+
+int acopf_get_timing(acopf_handle h, double* out7) {
+  if (!h || !out7) return fail(ACOPF_EINVAL, "null argument");
+  const double n = h->t_iters > 0 ? (double)h->t_iters : 1.0;
+  for (int k = 0; k < 6; ++k) out7[k] = h->t_ms[k] / n;
+  out7[6] = (double)h->t_iters;
+  return ACOPF_OK;
+}
+
+}  // extern "C"

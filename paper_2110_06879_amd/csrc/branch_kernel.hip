@@ -1,0 +1,864 @@
+// Branch x-step of the component ADMM on gfx950: every branch subproblem
+// (eq. branch, Sec. II-C) solved by a trust-region Newton method (Lin & More
+// 1999) inside an augmented-Lagrangian loop on the line limits, all in FP64.
+//
+// Launch layout: one lane per branch, 64 branches per wavefront. The whole
+// solve state of a branch (x, gradient, Hessian, Cholesky factor, trust
+// region) lives in that lane's registers; the variable count N (4 for
+// unlimited lines, 6 for rated lines with the two slacks) is a template
+// constant so every small dense loop unrolls into register code. Rated and
+// unlimited branches sit in separate contiguous ranges, so a wavefront never
+// mixes the two shapes. Branch data and coupling vectors are structure-of-
+// arrays: lane l reads element l of each array, so every load and store of a
+// wavefront is a contiguous 512-byte access.
+//
+// The free set of a subspace step is handled with a mask over all N
+// variables instead of compressed indices (fixed rows and columns act as
+// identity), which keeps indexing static; the nonzero arithmetic is the same
+// as on the compressed system.
+//
+// Each lane also counts the algorithmic flops of the method as the plain
+// serial algorithm performs them (+ - * / sqrt one each, sin and cos apart),
+// step by step, so that achieved FP64 throughput can be reported exactly.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace acopf_dev {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// Trust-region constants (Lin & More 1999, Sec. 2-4 and the choices of the
+// branch solver): acceptance and radius thresholds, Cauchy search factors,
+// projected-search backtracking, CG tolerance, Cholesky shift.
+constexpr double kEta0 = 1e-4, kEta1 = 0.25, kEta2 = 0.75;
+constexpr double kSig1 = 0.25, kSig2 = 0.5, kSig3 = 4.0;
+constexpr double kMu0 = 0.01, kInterp = 0.1, kExtrap = 10.0;
+constexpr int kMaxTrials = 20;
+constexpr double kCgTol = 0.1;
+constexpr double kShiftMin = 1e-3;
+constexpr int kMaxChol = 20;
+
+struct Counters {
+  uint64_t flops, trig;
+  uint32_t tron_calls, tron_iters, n_fgh, n_f, cauchy, cg, chol, ps, al,
+      conv, maxit, stall;
+};
+
+#define FL(n) (cnt.flops += (uint64_t)(n))
+
+// Symmetric N x N matrix stored full (both triangles written).
+template <int N>
+struct Sym {
+  double a[N][N];
+};
+
+template <int N>
+struct BranchIn {
+  double gii, bii, gij, bij, gji, bji, gjj, bjj;
+  double vb[8], zc[8], yc[8];
+  double rpq, rva;
+  double lt0, lt1, rt;
+  __device__ double rho(int k) const { return k < 4 ? rpq : rva; }
+};
+
+// sin and cos of an angle difference as a fixed sequence of IEEE operations
+// (the library is built without floating-point contraction): reduction by
+// pi/2 with a two-part constant (33-bit head, so k * head is exact), then the
+// Taylor series of sin and cos on |r| <= pi/4 in Horner form, truncated after
+// r^17 and r^18 (truncation error below 1e-19 there).
+__device__ inline void series_sincos(double x, double* s, double* c) {
+  constexpr double kHead = 1.5707963267341256;      // 0x1.921fb544p+0
+  constexpr double kTail = 6.077100506506192e-11;   // pi/2 - kHead
+  constexpr double kInvPio2 = 0.6366197723675814;   // 2/pi
+  const double k = rint(x * kInvPio2);
+  const double r = (x - k * kHead) - k * kTail;
+  const double r2 = r * r;
+  // odd coefficients (-1)^j/(2j+1)!, even coefficients (-1)^j/(2j)!
+  double ps = 2.8114572543455206e-15;
+  ps = -7.647163731819816e-13 + r2 * ps;
+  ps = 1.6059043836821613e-10 + r2 * ps;
+  ps = -2.505210838544172e-08 + r2 * ps;
+  ps = 2.7557319223985893e-06 + r2 * ps;
+  ps = -0.0001984126984126984 + r2 * ps;
+  ps = 0.008333333333333333 + r2 * ps;
+  ps = -0.16666666666666666 + r2 * ps;
+  double pc = -1.5619206968586225e-16;
+  pc = 4.779477332387385e-14 + r2 * pc;
+  pc = -1.1470745597729725e-11 + r2 * pc;
+  pc = 2.08767569878681e-09 + r2 * pc;
+  pc = -2.755731922398589e-07 + r2 * pc;
+  pc = 2.48015873015873e-05 + r2 * pc;
+  pc = -0.001388888888888889 + r2 * pc;
+  pc = 0.041666666666666664 + r2 * pc;
+  pc = -0.5 + r2 * pc;
+  const double sr = r + r * (r2 * ps);
+  const double cr = 1.0 + r2 * pc;
+  const int q = (int)(((long long)k) & 3);
+  const double sv[4] = {sr, cr, -sr, -cr};
+  const double cv[4] = {cr, -sr, -cr, sr};
+  *s = q == 0 ? sv[0] : q == 1 ? sv[1] : q == 2 ? sv[2] : sv[3];
+  *c = q == 0 ? cv[0] : q == 1 ? cv[1] : q == 2 ? cv[2] : cv[3];
+}
+
+__device__ inline double clampd(double t, double lo, double hi) {
+  return t < lo ? lo : (t > hi ? hi : t);
+}
+
+// Flows and coupling values a_k(x); aux = (cos, sin, w^R, w^I).
+template <int N>
+__device__ inline void values(const BranchIn<N>& B, const double* x, double* a,
+                              double* aux, Counters& cnt) {
+  const double vi = x[0], vj = x[1], ti = x[2], tj = x[3];
+  const double dt = ti - tj;
+  double sn, cs;
+  series_sincos(dt, &sn, &cs);
+  const double vv = vi * vj;
+  const double WR = vv * cs, WI = vv * sn;
+  const double wi = vi * vi, wj = vj * vj;
+  a[0] = B.gii * wi + B.gij * WR + B.bij * WI;
+  a[1] = -B.bii * wi - B.bij * WR + B.gij * WI;
+  a[2] = B.gjj * wj + B.gji * WR - B.bji * WI;
+  a[3] = -B.bjj * wj - B.bji * WR - B.gji * WI;
+  a[4] = wi;
+  a[5] = ti;
+  a[6] = wj;
+  a[7] = tj;
+  aux[0] = cs;
+  aux[1] = sn;
+  aux[2] = WR;
+  aux[3] = WI;
+  FL(26);
+  cnt.trig += 2;
+}
+
+template <int N>
+__device__ double fval(const BranchIn<N>& B, const double* x, Counters& cnt) {
+  double a[8], aux[4];
+  values<N>(B, x, a, aux, cnt);
+  double F = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const double r = (a[k] - B.vb[k]) + B.zc[k];
+    F = F + B.yc[k] * r + 0.5 * B.rho(k) * r * r;
+  }
+  FL(64);
+  if (N == 6) {
+    const double c0 = a[0] * a[0] + a[1] * a[1] + x[4];
+    F = F + B.lt0 * c0 + 0.5 * B.rt * c0 * c0;
+    const double c1 = a[2] * a[2] + a[3] * a[3] + x[5];
+    F = F + B.lt1 * c1 + 0.5 * B.rt * c1 * c1;
+    FL(20);
+  }
+  ++cnt.n_f;
+  return F;
+}
+
+// Upper-triangle enumeration of a 4x4 block.
+__device__ constexpr int kUP[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+__device__ constexpr int kUQ[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
+
+template <int N>
+__device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
+                    double* g, Sym<N>& H, Counters& cnt) {
+  double a[8], aux[4];
+  values<N>(B, x, a, aux, cnt);
+  const double vi = x[0], vj = x[1];
+  const double cs = aux[0], sn = aux[1], WR = aux[2], WI = aux[3];
+  const double jc = vj * cs, ic = vi * cs, js = vj * sn, is = vi * sn;
+  const double twvi = 2.0 * vi, twvj = 2.0 * vj;
+  const double dWR[4] = {jc, ic, -WI, WI};
+  const double dWI[4] = {js, is, WR, -WR};
+  const double hWR[10] = {0.0, cs, -js, js, 0.0, -is, is, -WR, WR, -WR};
+  const double hWI[10] = {0.0, sn, jc, -jc, 0.0, ic, -ic, -WI, WI, -WI};
+  const double cw[4] = {B.gii, -B.bii, B.gjj, -B.bjj};
+  const double cR[4] = {B.gij, -B.bij, B.gji, -B.bji};
+  const double cI[4] = {B.bij, B.gij, -B.bji, -B.gji};
+  double ga[4][4], Ha[4][10];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int own = k < 2 ? 0 : 1;
+    const double tw = k < 2 ? twvi : twvj;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      double t = cR[k] * dWR[p] + cI[k] * dWI[p];
+      if (p == own) t = cw[k] * tw + cR[k] * dWR[p] + cI[k] * dWI[p];
+      ga[k][p] = t;
+    }
+#pragma unroll
+    for (int t = 0; t < 10; ++t) {
+      if (t == 0 || t == 4)
+        Ha[k][t] = ((t == 0) == (own == 0)) ? 2.0 * cw[k] : 0.0;
+      else
+        Ha[k][t] = cR[k] * hWR[t] + cI[k] * hWI[t];
+    }
+  }
+  FL(162);
+  F = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    g[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) H.a[i][j] = 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double rk = B.rho(k);
+    const double r = (a[k] - B.vb[k]) + B.zc[k];
+    F = F + B.yc[k] * r + 0.5 * rk * r * r;
+    const double m = B.yc[k] + rk * r;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) g[p] = g[p] + m * ga[k][p];
+#pragma unroll
+    for (int t = 0; t < 10; ++t) {
+      const int p = kUP[t], q = kUQ[t];
+      H.a[p][q] = H.a[p][q] + rk * ga[k][p] * ga[k][q] + m * Ha[k][t];
+    }
+  }
+  FL(272);
+  {  // voltage-magnitude and angle couplings: w_i, th_i, w_j, th_j
+    const int var[4] = {0, 2, 1, 3};
+#pragma unroll
+    for (int k = 4; k < 8; ++k) {
+      const int p = var[k - 4];
+      const double rk = B.rva;
+      const double r = (a[k] - B.vb[k]) + B.zc[k];
+      F = F + B.yc[k] * r + 0.5 * rk * r * r;
+      const double m = B.yc[k] + rk * r;
+      if (k == 4 || k == 6) {
+        const double gv = 2.0 * x[p];
+        g[p] = g[p] + m * gv;
+        H.a[p][p] = H.a[p][p] + rk * gv * gv + m * 2.0;
+      } else {
+        g[p] = g[p] + m;
+        H.a[p][p] = H.a[p][p] + rk;
+      }
+    }
+    FL(60);
+  }
+  if (N == 6) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int kp = 2 * e, kq = 2 * e + 1, s = 4 + e;
+      const double lt = e == 0 ? B.lt0 : B.lt1;
+      const double c = a[kp] * a[kp] + a[kq] * a[kq] + x[s];
+      F = F + lt * c + 0.5 * B.rt * c * c;
+      const double m = lt + B.rt * c;
+      double gc[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) gc[p] = 2.0 * (a[kp] * ga[kp][p] + a[kq] * ga[kq][p]);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) g[p] = g[p] + m * gc[p];
+      g[s] = g[s] + m;
+#pragma unroll
+      for (int t = 0; t < 10; ++t) {
+        const int p = kUP[t], q = kUQ[t];
+        const double hc = 2.0 * (ga[kp][p] * ga[kp][q] + a[kp] * Ha[kp][t] +
+                                 ga[kq][p] * ga[kq][q] + a[kq] * Ha[kq][t]);
+        H.a[p][q] = H.a[p][q] + B.rt * gc[p] * gc[q] + m * hc;
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p) H.a[p][s] = H.a[p][s] + B.rt * gc[p];
+      H.a[s][s] = H.a[s][s] + B.rt;
+    }
+    FL(352);
+  }
+#pragma unroll
+  for (int p = 0; p < N; ++p)
+#pragma unroll
+    for (int q = p + 1; q < N; ++q) H.a[q][p] = H.a[p][q];
+  ++cnt.n_fgh;
+}
+
+template <int N>
+__device__ inline double dotN(const double* a, const double* b) {
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) t = t + a[i] * b[i];
+  return t;
+}
+
+// q(s) = g's + 1/2 s'Hs ; counted as 2N^2 + 4N + 2
+template <int N>
+__device__ inline double model(const double* g, const Sym<N>& H, const double* s,
+                               Counters& cnt) {
+  double gs = 0.0, sHs = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    gs = gs + g[i] * s[i];
+    double hi = 0.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) hi = hi + H.a[i][j] * s[j];
+    sHs = sHs + s[i] * hi;
+  }
+  FL(2 * N * N + 4 * N + 2);
+  return gs + 0.5 * sHs;
+}
+
+// tau >= 0 with ||a + tau p|| = delta
+template <int N>
+__device__ inline double to_boundary(const double* a, const double* p, double delta,
+                                     Counters& cnt) {
+  const double ap = dotN<N>(a, p), pp = dotN<N>(p, p), aa = dotN<N>(a, a);
+  double dd = delta * delta - aa;
+  if (dd < 0.0) dd = 0.0;
+  const double rad = ap * ap + pp * dd;
+  const double sq = sqrt(rad);
+  FL(6 * N + 6);
+  double tau;
+  if (ap >= 0.0) {
+    const double den = ap + sq;
+    FL(1);
+    if (den > 0.0) {
+      tau = dd / den;
+      FL(1);
+    } else {
+      tau = 0.0;
+    }
+  } else {
+    tau = (sq - ap) / pp;
+    FL(2);
+  }
+  return tau;
+}
+
+// Cauchy-search acceptance: ||s|| <= delta and q(s) <= mu0 g's.
+template <int N>
+__device__ inline bool cauchy_ok(const double* g, const Sym<N>& H, const double* s,
+                                 double delta, Counters& cnt) {
+  const double sn = sqrt(dotN<N>(s, s));
+  FL(2 * N + 1);
+  if (sn > delta) return false;
+  const double q = model<N>(g, H, s, cnt);
+  const double gts = dotN<N>(g, s);
+  FL(2 * N + 1);
+  return q <= kMu0 * gts;
+}
+
+template <int N>
+__device__ inline void cauchy_trial(const double* x, const double* g, const double* lo,
+                                    const double* hi, double a, double* w, double* s,
+                                    Counters& cnt) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    w[i] = clampd(x[i] - a * g[i], lo[i], hi[i]);
+    s[i] = w[i] - x[i];
+  }
+  FL(3 * N);
+}
+
+template <int N>
+__device__ void cauchy(const double* x, const double* g, const Sym<N>& H,
+                       const double* lo, const double* hi, double delta,
+                       double& alpha, double* w, Counters& cnt) {
+  double brpt = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double bp = 0.0;
+    if (g[i] > 0.0) {
+      bp = (x[i] - lo[i]) / g[i];
+      FL(2);
+    } else if (g[i] < 0.0) {
+      bp = (x[i] - hi[i]) / g[i];
+      FL(2);
+    }
+    brpt = brpt < bp ? bp : brpt;
+  }
+  double s[N], wt[N], st[N];
+  cauchy_trial<N>(x, g, lo, hi, alpha, w, s, cnt);
+  ++cnt.cauchy;
+  if (cauchy_ok<N>(g, H, s, delta, cnt)) {
+    for (int t = 0; t < kMaxTrials; ++t) {
+      if (alpha > brpt) break;
+      const double a2 = alpha * kExtrap;
+      FL(1);
+      cauchy_trial<N>(x, g, lo, hi, a2, wt, st, cnt);
+      ++cnt.cauchy;
+      if (!cauchy_ok<N>(g, H, st, delta, cnt)) break;
+      alpha = a2;
+#pragma unroll
+      for (int i = 0; i < N; ++i) w[i] = wt[i];
+    }
+  } else {
+    for (int t = 0; t < kMaxTrials; ++t) {
+      alpha = alpha * kInterp;
+      FL(1);
+      cauchy_trial<N>(x, g, lo, hi, alpha, w, s, cnt);
+      ++cnt.cauchy;
+      if (cauchy_ok<N>(g, H, s, delta, cnt)) break;
+    }
+  }
+}
+
+// Preconditioner application on the free variables (mask fr):
+// z = D L^-T L^-1 D r ; counted as 2 nf^2 + 2 nf.
+template <int N>
+__device__ inline void precond(const Sym<N>& L, const double* D, const bool* fr,
+                               const double* r, double* z) {
+  double t[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double a = D[i] * r[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) a = a - L.a[i][k] * t[k];
+    t[i] = fr[i] ? a / L.a[i][i] : 0.0;
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    double a = t[i];
+#pragma unroll
+    for (int k = i + 1; k < N; ++k) a = a - L.a[k][i] * z[k];
+    z[i] = fr[i] ? a / L.a[i][i] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) z[i] = D[i] * z[i];
+}
+
+// Dense Cholesky of the masked matrix A (fixed rows/cols identity). Returns
+// false at the first non-positive free pivot; flops are counted as on the
+// compressed nf x nf matrix.
+template <int N>
+__device__ inline bool cholesky(const Sym<N>& A, const bool* fr, int nf, Sym<N>& L,
+                                Counters& cnt) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) L.a[i][j] = 0.0;
+  int jc = 0;  // compressed column index
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    if (!fr[j]) {
+      L.a[j][j] = 1.0;
+      continue;
+    }
+    double d = A.a[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d = d - L.a[j][k] * L.a[j][k];
+    FL(2 * jc);
+    if (!(d > 0.0)) return false;
+    const double ljj = sqrt(d);
+    L.a[j][j] = ljj;
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      if (!fr[i]) continue;
+      double t = A.a[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t = t - L.a[i][k] * L.a[j][k];
+      L.a[i][j] = t / ljj;
+    }
+    FL(1 + (nf - 1 - jc) * (2 * jc + 1));
+    ++jc;
+  }
+  return true;
+}
+
+// Subspace steps from the Cauchy point w (in/out), Lin & More Sec. 4:
+// Steihaug PCG on the free variables, projected search, repeat while a new
+// bound becomes active and CG ended inside the trust region.
+template <int N>
+__device__ void subspace(const double* x, const double* g, const Sym<N>& H,
+                         const double* lo, const double* hi, double delta,
+                         double* w, Counters& cnt) {
+  double s[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) s[i] = w[i] - x[i];
+  FL(N);
+  for (int pass = 0; pass < N; ++pass) {
+    bool fr[N];
+    int nf = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      fr[i] = w[i] > lo[i] && w[i] < hi[i];
+      nf += fr[i] ? 1 : 0;
+    }
+    if (nf == 0) break;
+    double gq[N], r[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double t = g[i];
+#pragma unroll
+      for (int j = 0; j < N; ++j) t = t + H.a[i][j] * s[j];
+      gq[i] = t;
+      r[i] = fr[i] ? -t : 0.0;
+    }
+    FL(2 * N * N);
+    const double rnorm0 = sqrt(dotN<N>(r, r));
+    FL(2 * nf + 1);
+    if (!(rnorm0 > 0.0)) break;
+    double D[N];
+    double mind = 1.0 / 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      D[i] = 1.0;
+      if (fr[i]) {
+        const double b = fabs(H.a[i][i]);
+        if (b > 0.0) {
+          D[i] = 1.0 / sqrt(b);
+          FL(2);
+        }
+      }
+    }
+    Sym<N> A;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+        A.a[i][j] = (fr[i] && fr[j]) ? D[i] * H.a[i][j] * D[j] : (i == j ? 1.0 : 0.0);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (fr[i]) mind = A.a[i][i] < mind ? A.a[i][i] : mind;
+    FL(2 * nf * nf);
+    double shift = 0.0;
+    if (!(mind > 0.0)) {
+      shift = kShiftMin - mind;
+      FL(1);
+    }
+    Sym<N> L;
+    bool ok = false;
+    for (int att = 0; att < kMaxChol; ++att) {
+      Sym<N> As = A;
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+        if (fr[i]) As.a[i][i] = As.a[i][i] + shift;
+      FL(nf);
+      ++cnt.chol;
+      if (cholesky<N>(As, fr, nf, L, cnt)) {
+        ok = true;
+        break;
+      }
+      shift = 2.0 * shift > kShiftMin ? 2.0 * shift : kShiftMin;
+      FL(1);
+    }
+    if (!ok) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        D[i] = 1.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) L.a[i][j] = i == j ? 1.0 : 0.0;
+      }
+    }
+    // Steihaug PCG on min 1/2 d'Bd - r'd s.t. ||s + d|| <= delta
+    double d[N], res[N], zz[N], p[N], Bp[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      d[i] = 0.0;
+      res[i] = r[i];
+    }
+    precond<N>(L, D, fr, res, zz);
+    FL(2 * nf * nf + 2 * nf);
+#pragma unroll
+    for (int i = 0; i < N; ++i) p[i] = zz[i];
+    double rz = dotN<N>(res, zz);
+    FL(2 * nf);
+    bool boundary = false;
+    for (int k = 0; k < nf; ++k) {
+      ++cnt.cg;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) t = t + (fr[j] ? H.a[i][j] * p[j] : 0.0);
+        Bp[i] = fr[i] ? t : 0.0;
+      }
+      const double pBp = dotN<N>(p, Bp);
+      FL(2 * nf * nf + 2 * nf);
+      double sd[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) sd[i] = s[i] + d[i];
+      FL(nf);
+      if (!(pBp > 0.0)) {
+        const double tau = to_boundary<N>(sd, p, delta, cnt);
+#pragma unroll
+        for (int i = 0; i < N; ++i) d[i] = d[i] + tau * p[i];
+        FL(2 * nf);
+        boundary = true;
+        break;
+      }
+      const double alpha = rz / pBp;
+      double tr[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) tr[i] = sd[i] + alpha * p[i];
+      const double trn = sqrt(dotN<N>(tr, tr));
+      FL(1 + 2 * N + 2 * N + 1);
+      if (trn >= delta) {
+        const double tau = to_boundary<N>(sd, p, delta, cnt);
+#pragma unroll
+        for (int i = 0; i < N; ++i) d[i] = d[i] + tau * p[i];
+        FL(2 * nf);
+        boundary = true;
+        break;
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        d[i] = d[i] + alpha * p[i];
+        res[i] = res[i] - alpha * Bp[i];
+      }
+      const double rn = sqrt(dotN<N>(res, res));
+      FL(4 * nf + 2 * nf + 2);
+      if (rn <= kCgTol * rnorm0) break;
+      precond<N>(L, D, fr, res, zz);
+      const double rzn = dotN<N>(res, zz);
+      const double bcg = rzn / rz;
+      rz = rzn;
+#pragma unroll
+      for (int i = 0; i < N; ++i) p[i] = zz[i] + bcg * p[i];
+      FL(2 * nf * nf + 2 * nf + 2 * nf + 1 + 2 * nf);
+    }
+    // projected search along d from w
+    const double qw = model<N>(g, H, s, cnt);
+    double beta = 1.0;
+    bool acc = false;
+    double wt[N], stv[N];
+    for (int t = 0; t < kMaxTrials; ++t) {
+      ++cnt.ps;
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+        wt[i] = fr[i] ? clampd(w[i] + beta * d[i], lo[i], hi[i]) : w[i];
+      double dw[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        stv[i] = wt[i] - x[i];
+        dw[i] = wt[i] - w[i];
+      }
+      FL(2 * nf + 2 * N);
+      const double qt = model<N>(g, H, stv, cnt);
+      const double lhs = qw + kMu0 * dotN<N>(gq, dw);
+      FL(2 * N + 2);
+      if (qt <= lhs) {
+        acc = true;
+        break;
+      }
+      beta = beta * 0.5;
+      FL(1);
+    }
+    if (!acc) break;
+    bool hit = false;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (fr[i] && (wt[i] == lo[i] || wt[i] == hi[i])) hit = true;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      w[i] = wt[i];
+      s[i] = stv[i];
+    }
+    if (boundary || !hit) break;
+  }
+}
+
+enum { kConv = 0, kMaxit = 1, kStall = 2 };
+
+template <int N>
+__device__ int tron(const BranchIn<N>& B, double* x, const double* lo, const double* hi,
+                    double gtol, double ftol, int maxit, Counters& cnt) {
+  ++cnt.tron_calls;
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = clampd(x[i], lo[i], hi[i]);
+  double f, g[N];
+  Sym<N> H;
+  fgh<N>(B, x, f, g, H, cnt);
+  double pg2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const double t = clampd(x[i] - g[i], lo[i], hi[i]) - x[i];
+    pg2 = pg2 + t * t;
+  }
+  double delta = sqrt(pg2);
+  FL(4 * N + 1);
+  if (!(delta > 0.0)) delta = 1.0;
+  double alphac = 1.0;
+  int status = kMaxit;
+  for (int it = 0; it < maxit; ++it) {
+    double pginf = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const double t = fabs(clampd(x[i] - g[i], lo[i], hi[i]) - x[i]);
+      pginf = pginf < t ? t : pginf;
+    }
+    FL(2 * N);
+    if (pginf <= gtol) {
+      status = kConv;
+      break;
+    }
+    ++cnt.tron_iters;
+    double w[N], s[N];
+    cauchy<N>(x, g, H, lo, hi, delta, alphac, w, cnt);
+    subspace<N>(x, g, H, lo, hi, delta, w, cnt);
+#pragma unroll
+    for (int i = 0; i < N; ++i) s[i] = w[i] - x[i];
+    FL(N);
+    const double prered = -model<N>(g, H, s, cnt);
+    const double snorm = sqrt(dotN<N>(s, s));
+    FL(2 * N + 1);
+    if (!(prered > 0.0)) {
+      status = kStall;
+      break;
+    }
+    if (snorm < delta) {
+      FL(2);
+      if (prered <= ftol * (1.0 + fabs(f))) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) x[i] = w[i];
+        status = kConv;
+        break;
+      }
+    }
+    const double fw = fval<N>(B, w, cnt);
+    const double actred = f - fw;
+    const double ratio = actred / prered;
+    FL(2);
+    if (ratio <= kEta0) {
+      delta = kSig2 * (snorm < delta ? snorm : delta);
+      FL(1);
+    } else if (ratio <= kEta1) {
+      const double a = kSig1 * delta, b = kSig2 * (snorm < delta ? snorm : delta);
+      delta = a < b ? b : a;
+      FL(2);
+    } else if (ratio >= kEta2) {
+      const double a = kSig3 * delta, b0 = kSig3 * snorm;
+      const double b = delta < b0 ? b0 : delta;
+      delta = b < a ? b : a;
+      FL(2);
+    }
+    if (ratio > kEta0) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) x[i] = w[i];
+      fgh<N>(B, x, f, g, H, cnt);
+    }
+    const double xn = sqrt(dotN<N>(x, x));
+    FL(2 * N + 2);
+    if (delta <= 1e-15 * (xn > 1.0 ? xn : 1.0)) {
+      status = kStall;
+      break;
+    }
+  }
+  if (status == kConv) ++cnt.conv;
+  else if (status == kMaxit) ++cnt.maxit;
+  else ++cnt.stall;
+  return status;
+}
+
+#undef FL
+
+// One lane per branch over [first, first + count) of the device branch order.
+template <int N>
+__global__ __launch_bounds__(64) void branch_kernel(BranchArgs A, int first, int count) {
+  const int lane_id = blockIdx.x * blockDim.x + threadIdx.x;
+  Counters cnt = {};
+  bool active = lane_id < count;
+  int l = first + lane_id;
+  int grid = 0;
+  if (active) {
+    grid = A.br_grid[l];
+    active = A.ctl[grid].done == 0;
+  }
+  if (active) {
+    const int64_t nl = A.nl;
+    BranchIn<N> B;
+    B.gii = A.adm[0 * nl + l];
+    B.bii = A.adm[1 * nl + l];
+    B.gij = A.adm[2 * nl + l];
+    B.bij = A.adm[3 * nl + l];
+    B.gji = A.adm[4 * nl + l];
+    B.bji = A.adm[5 * nl + l];
+    B.gjj = A.adm[6 * nl + l];
+    B.bjj = A.adm[7 * nl + l];
+    double lo[N], hi[N];
+    lo[0] = A.vlo_i[l];
+    hi[0] = A.vhi_i[l];
+    lo[1] = A.vlo_j[l];
+    hi[1] = A.vhi_j[l];
+    lo[2] = -kTwoPi;
+    hi[2] = kTwoPi;
+    lo[3] = -kTwoPi;
+    hi[3] = kTwoPi;
+    if (N == 6) {
+      lo[4] = -A.rate2[l];
+      hi[4] = 0.0;
+      lo[5] = -A.rate2[l];
+      hi[5] = 0.0;
+    }
+    const int64_t cb = A.br_coupling_base;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int64_t c = cb + k * nl + l;
+      B.vb[k] = A.v[c];
+      B.zc[k] = A.z[c];
+      B.yc[k] = A.y[c];
+    }
+    B.rpq = A.rho_pq;
+    B.rva = A.rho_va;
+    double x[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = A.bx[i * nl + l];
+    B.lt0 = 0.0;
+    B.lt1 = 0.0;
+    B.rt = 0.0;
+    int failures = 0;
+    if (N == 4) {
+      failures += tron<N>(B, x, lo, hi, A.tron_gtol, A.tron_ftol, A.tron_maxit, cnt) != kConv;
+    } else {
+      B.lt0 = A.ltil[l];
+      B.lt1 = A.ltil[nl + l];
+      B.rt = A.rtil[l];
+      double cprev = 1.0 / 0.0;
+      for (int t = 0; t < A.al_maxit; ++t) {
+        ++cnt.al;
+        failures += tron<N>(B, x, lo, hi, A.tron_gtol, A.tron_ftol, A.tron_maxit, cnt) != kConv;
+        double a[8], aux[4];
+        values<N>(B, x, a, aux, cnt);
+        const double c0 = a[0] * a[0] + a[1] * a[1] + x[4];
+        const double c1 = a[2] * a[2] + a[3] * a[3] + x[5];
+        cnt.flops += 8;
+        const double cn = fabs(c0) > fabs(c1) ? fabs(c0) : fabs(c1);
+        if (cn <= A.al_tol) break;
+        B.lt0 = B.lt0 + B.rt * c0;
+        B.lt1 = B.lt1 + B.rt * c1;
+        cnt.flops += 5;
+        if (cn > A.al_shrink * cprev) {
+          const double gr = B.rt * A.al_rho_growth;
+          B.rt = gr < A.al_rho_max ? gr : A.al_rho_max;
+          cnt.flops += 1;
+        }
+        cprev = cn;
+      }
+      A.ltil[l] = B.lt0;
+      A.ltil[nl + l] = B.lt1;
+      A.rtil[l] = B.rt;
+    }
+    double a[8], aux[4];
+    values<N>(B, x, a, aux, cnt);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) A.u[cb + k * nl + l] = a[k];
+#pragma unroll
+    for (int i = 0; i < N; ++i) A.bx[i * nl + l] = x[i];
+    if (failures) atomicAdd(&A.failures[grid], failures);
+  }
+  // wave-level reduction of the counters, one atomic per counter per wavefront
+  uint64_t v[15] = {active ? 1ull : 0ull, cnt.flops, cnt.trig, cnt.tron_calls,
+                    cnt.tron_iters, cnt.n_fgh, cnt.n_f, cnt.cauchy, cnt.cg, cnt.chol,
+                    cnt.ps, cnt.al, cnt.conv, cnt.maxit, cnt.stall};
+#pragma unroll
+  for (int q = 0; q < 15; ++q) {
+    uint64_t t = v[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    v[q] = t;
+  }
+  if ((threadIdx.x & 63) == 0 && v[0] != 0) {
+#pragma unroll
+    for (int q = 0; q < 15; ++q) atomicAdd(&A.stats[q], (unsigned long long)v[q]);
+  }
+}
+
+void launch_branch(const BranchArgs& A, int first, int count, int nvar, hipStream_t s) {
+  if (count <= 0) return;
+  const int blocks = (count + 63) / 64;
+  if (nvar == 6)
+    hipLaunchKernelGGL(branch_kernel<6>, dim3(blocks), dim3(64), 0, s, A, first, count);
+  else
+    hipLaunchKernelGGL(branch_kernel<4>, dim3(blocks), dim3(64), 0, s, A, first, count);
+}
+
+}  // namespace acopf_dev

@@ -1,0 +1,40 @@
+// Device-side data shared by the host runtime and the kernels of the ADMM
+// library (internal; not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace acopf_dev {
+
+// Per-grid control block of Algorithm 1, updated by the control kernel.
+struct GridCtl {
+  double beta;        // outer penalty
+  double beta_lam;    // beta used by a pending lambda update
+  double znorm_prev;  // ||z||_inf at the previous outer update (inf at start)
+  double r_pri, r_dual, r_z;
+  int outer, inner_total, inner_in_outer, status;
+  int done, do_outer, fixed_target, branch_failures;
+  int numerical, pad0, pad1, pad2;
+};
+
+struct BranchArgs {
+  int64_t nl;                // branches in the handle
+  int64_t br_coupling_base;  // offset of branch couplings (2 n_gen)
+  const int* br_grid;
+  const GridCtl* ctl;
+  const double* adm;         // [8][nl] gii bii gij bij gji bji gjj bjj
+  const double *vlo_i, *vhi_i, *vlo_j, *vhi_j, *rate2;
+  const double *v, *z, *y;
+  double* u;
+  double *bx, *ltil, *rtil;  // [6][nl], [2][nl], [nl]
+  double rho_pq, rho_va, tron_gtol, tron_ftol;
+  double al_tol, al_shrink, al_rho_growth, al_rho_max;
+  int tron_maxit, al_maxit;
+  int* failures;             // [G]
+  unsigned long long* stats; // [16]
+};
+
+void launch_branch(const BranchArgs& A, int first, int count, int nvar, hipStream_t s);
+
+}  // namespace acopf_dev

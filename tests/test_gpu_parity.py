@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the
+same seeded inputs.
+
+Bar (norm-wise, per vector): ||X_gpu - X_oracle||_inf / ||X_oracle||_inf
+<= 1e-9 after a fixed number of inner iterations, for u, v, z, y, lambda,
+branch x and the line-limit multipliers; the objective at the same
+iteration count within 1e-6 relative. Event counts of the branch solves
+(TRON iterations, evaluations, ...) and the algorithmic flop count must match
+the oracle's exactly when both sides take the same path.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2110_06879_amd import acopf as A
+from paper_2110_06879_amd.gridgen import config_grid, gridgen, perturb_loads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+VECS = ("u", "v", "z", "y", "lam", "bx", "ltil")
+
+
+def oparams(p: A.Params) -> O.OracleParams:
+    from dataclasses import asdict
+    return O.OracleParams(**asdict(p))
+
+
+def relerr(a, b):
+    den = max(np.abs(b).max(), 1e-30)
+    return float(np.abs(a - b).max() / den)
+
+
+def compare(solver, orc, grid=0, tol=TOL, label=""):
+    errs = {}
+    for k in VECS:
+        errs[k] = relerr(solver.get(k, grid), orc.get(k))
+    print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, e in errs.items():
+        assert e <= tol, (label, k, e)
+    return errs
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("name,iters", [("c1_30bus", 50), ("c2_2kbus", 50)])
+def test_fixed_iterations_match_oracle(name, iters):
+    note(f"parity {name} cold {iters} fixed iterations")
+    g = config_grid(name)
+    p = A.Params(rho_pq=400.0, rho_va=400.0 if name == "c1_30bus" else 40000.0)
+    orc = O.Oracle(g, oparams(p))
+    orc.count_flops(True)
+    orc.solve(iters)
+    with A.Solver(g, p) as s:
+        res = s.solve(A.COLD, iters)[0]
+        assert res["inner_iters"] == iters
+        compare(s, orc, label=name)
+        # residual history, iteration by iteration
+        hg, ho = s.history(), orc.history()
+        assert hg.shape == ho.shape
+        np.testing.assert_allclose(hg[:, [0, 1, 2]], ho[:, [0, 1, 2]], rtol=1e-7, atol=1e-12)
+        np.testing.assert_array_equal(hg[:, 5], ho[:, 5])
+        # objective at the same iteration
+        assert abs(res["objective"] - orc.objective()) <= 1e-6 * max(1.0, abs(orc.objective()))
+        sg, so = s.stats(), orc.stats()
+        note(f"gpu stats {sg}")
+        note(f"oracle stats {so}")
+        for k in ("branch_solves", "tron_calls", "tron_iters", "n_fgh", "n_f",
+                  "cauchy_trials", "cg_iters", "chol_attempts", "ps_trials", "al_iters",
+                  "trig"):
+            assert sg[k] == so[k], (k, sg[k], so[k])
+        assert sg["flops"] == so["flops"]
+
+
+def test_c1_200_iterations_objective():
+    note("parity c1 200 iterations objective")
+    g = config_grid("c1_30bus")
+    p = A.Params(rho_pq=400.0, rho_va=400.0)
+    orc = O.Oracle(g, oparams(p))
+    orc.solve(200)
+    with A.Solver(g, p) as s:
+        res = s.solve(A.COLD, 200)[0]
+        compare(s, orc, tol=1e-8, label="c1x200")
+        assert abs(res["objective"] - orc.objective()) <= 1e-6 * max(1.0, abs(orc.objective()))
+
+
+def test_continue_equals_one_run_and_determinism():
+    note("continue/determinism c1")
+    g = config_grid("c1_30bus")
+    p = A.Params(rho_pq=400.0, rho_va=400.0)
+    with A.Solver(g, p) as s1, A.Solver(g, p) as s2:
+        s1.solve(A.COLD, 40)
+        s2.solve(A.COLD, 25)
+        s2.solve(A.CONTINUE, 15)
+        for k in VECS + ("rtil",):
+            np.testing.assert_array_equal(s1.get(k), s2.get(k))
+        a = s1.get("u")
+        s1.solve(A.COLD, 40)
+        np.testing.assert_array_equal(a, s1.get("u"))
+
+
+def test_edge_grids_match_oracle():
+    note("edge grids")
+    cases = []
+    # two buses, one branch, one generator; ragged sizes; shunts and taps
+    g = gridgen(2, 1, 1, 1.0, 31)
+    cases.append(("2bus", g))
+    g = gridgen(67, 9, 70, 0.5, 32)
+    rng = np.random.default_rng(0)
+    g.gs = rng.uniform(0, 0.02, g.n_bus)
+    g.bs = rng.uniform(-0.02, 0.02, g.n_bus)
+    g.tap = rng.uniform(0.95, 1.05, g.n_branch)
+    g.shift = rng.uniform(-0.1, 0.1, g.n_branch)
+    cases.append(("ragged_taps_shunts", g))
+    g = gridgen(130, 20, 200, 0.0, 33)
+    cases.append(("all_unrated", g))
+    for name, g in cases:
+        p = A.Params(rho_pq=400.0, rho_va=4000.0)
+        orc = O.Oracle(g, oparams(p))
+        orc.solve(30)
+        with A.Solver(g, p) as s:
+            s.solve(A.COLD, 30)
+            compare(s, orc, tol=1e-9, label=name)
+
+
+def test_batch_equals_alone():
+    note("batch vs alone")
+    gs = [gridgen(50 + 13 * k, 8 + k, 70 + 17 * k, 0.6, 40 + k) for k in range(3)]
+    p = A.Params(rho_pq=400.0, rho_va=4000.0)
+    with A.Solver(gs, p) as sb:
+        sb.solve(A.COLD, 25)
+        for k, g in enumerate(gs):
+            with A.Solver(g, p) as sa:
+                sa.solve(A.COLD, 25)
+                for name in VECS + ("rtil",):
+                    np.testing.assert_array_equal(sa.get(name), sb.get(name, k))
+
+
+def test_warm_start_matches_oracle():
+    note("warm start c2")
+    g = config_grid("c2_2kbus")
+    p = A.Params(rho_pq=400.0, rho_va=40000.0)
+    orc = O.Oracle(g, oparams(p))
+    orc.solve(40)
+    pd, qd = perturb_loads(g, 0.05, 1001)
+    orc.update_loads(pd, qd)
+    orc.solve(30)
+    with A.Solver(g, p) as s:
+        s.solve(A.COLD, 40)
+        s.update_loads(0, pd, qd)
+        s.solve(A.WARM, 30)
+        compare(s, orc, tol=1e-9, label="warm")
+        np.testing.assert_array_equal(s.get("pd"), pd)
+
+
+def test_70k_one_iteration_from_gpu_state():
+    """Full-size grid: GPU state after 3 iterations is loaded into the oracle;
+    one more iteration on both sides must agree on every vector."""
+    note("parity c3 70k: one iteration from GPU state")
+    g = config_grid("c3_70kbus")
+    p = A.Params(rho_pq=400.0, rho_va=40000.0)
+    with A.Solver(g, p) as s:
+        s.solve(A.COLD, 3)
+        orc = O.Oracle(g, oparams(p))
+        for k in VECS + ("rtil",):
+            orc.set(k, s.get(k))
+        sc = s.scalars()
+        orc.set_scalars(sc)
+        s.solve(A.CONTINUE, 1)
+        orc.solve(1)
+        compare(s, orc, tol=1e-9, label="70k+1")

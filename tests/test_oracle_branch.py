@@ -246,3 +246,22 @@ def test_counting_mode_is_bitwise_identical():
             assert np.array_equal(np.asarray(a), np.asarray(b))
         assert r2[4]["flops"] > 0 and r2[4]["trig"] > 0
         assert r1[4]["flops"] == 0
+
+
+def test_series_sincos_accuracy():
+    """The oracle's series sin/cos against the C library on [-4 pi, 4 pi]
+    (branch angle differences lie in this range: each angle is in
+    [-2 pi, 2 pi]), including quadrant boundaries and tiny arguments."""
+    import math
+    rng = np.random.default_rng(123)
+    xs = list(rng.uniform(-4 * np.pi, 4 * np.pi, 20000))
+    xs += [k * np.pi / 4 + d for k in range(-16, 17) for d in (-1e-9, 0.0, 1e-9)]
+    xs += [0.0, 1e-300, -1e-12, 1e-8, 0.5, -0.5]
+    worst = 0.0
+    for x in xs:
+        s, c = O.sincos(x)
+        es, ec = math.sin(x), math.cos(x)
+        worst = max(worst, abs(s - es), abs(c - ec))
+        assert abs(s - es) <= 4e-16 * max(1.0, abs(x)) and abs(c - ec) <= 4e-16 * max(1.0, abs(x)), x
+        assert abs(s * s + c * c - 1.0) < 1e-15
+    assert worst < 2e-15
