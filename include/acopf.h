@@ -168,13 +168,16 @@ int acopf_set_state(acopf_handle h, int32_t grid, int32_t what,
 /* Number of grids, buses, generators, branches of grid `grid` (out[4]). */
 int acopf_get_sizes(acopf_handle h, int32_t grid, int64_t* out4);
 
-/* Average device time (ms) per launch of each kernel of the last solve,
- * measured with HIP events on the solve stream: out[0] generator step,
- * out[1] branch step (6-variable), out[2] branch step (4-variable),
- * out[3] bus/z/y/residual step, out[4] control, out[5] outer update,
- * out[6] number of timed iterations. Timing is taken only when
- * ACOPF_PROFILE=1 is set in the environment at create time. */
-int acopf_get_timing(acopf_handle h, double* out7);
+/* Turn per-kernel timing on or off. While on, every launch of a solve is
+ * bracketed by HIP events on the handle's stream (a small overhead).
+ * Errors: EINVAL, EDEVICE. */
+int acopf_set_profiling(acopf_handle h, int32_t on);
+
+/* Average device time (ms) per launch over the last solve run with
+ * profiling on: out[0] x-step (generators and branches), out[1] bus/z/y/
+ * residual step, out[2] control, out[3] outer update; out[4] = number of
+ * iterations timed. Errors: EINVAL. */
+int acopf_get_timing(acopf_handle h, double* out5);
 
 /* Free everything the handle owns. NULL is a no-op. */
 void acopf_destroy(acopf_handle h);

@@ -78,13 +78,13 @@ class _Grid(C.Structure):
 class OracleParams:
     """Parameters of the method (readings of the paper where it is silent)."""
     rho_pq: float = 400.0
-    rho_va: float = 400.0
-    obj_scale: float = 1.0
+    rho_va: float = 4000.0
+    obj_scale: float = 0.01
     rate_scale: float = 0.99
-    beta0: float = 1e3
+    beta0: float = 1e4
     beta_gamma: float = 6.0
     beta_omega: float = 0.8
-    beta_max: float = 1e20
+    beta_max: float = 1e4
     lambda_max: float = 1e12
     eps_pri: float = 1e-4
     eps_dual: float = 1e-4

@@ -29,8 +29,8 @@ STATS_NAMES = ("branch_solves", "flops", "trig", "tron_calls", "tron_iters", "n_
 SCALAR_NAMES = ("beta", "znorm_prev", "r_pri", "r_dual", "r_z", "outer",
                 "inner_total", "inner_in_outer", "status")
 EXPORTS = ("acopf_default_params", "acopf_create", "acopf_solve", "acopf_update_loads",
-           "acopf_get_state", "acopf_set_state", "acopf_get_sizes", "acopf_get_timing",
-           "acopf_destroy", "acopf_last_error")
+           "acopf_get_state", "acopf_set_state", "acopf_get_sizes", "acopf_set_profiling",
+           "acopf_get_timing", "acopf_destroy", "acopf_last_error")
 
 
 class AcopfError(RuntimeError):
@@ -74,13 +74,13 @@ class _Result(C.Structure):
 class Params:
     """Method parameters; field names and order follow acopf_params."""
     rho_pq: float = 400.0
-    rho_va: float = 40000.0
-    obj_scale: float = 1.0
+    rho_va: float = 4000.0
+    obj_scale: float = 0.01
     rate_scale: float = 0.99
-    beta0: float = 1e3
+    beta0: float = 1e4
     beta_gamma: float = 6.0
     beta_omega: float = 0.8
-    beta_max: float = 1e20
+    beta_max: float = 1e4
     lambda_max: float = 1e12
     eps_pri: float = 1e-4
     eps_dual: float = 1e-4
@@ -125,11 +125,13 @@ def load(path: str | None = None) -> C.CDLL:
     lib.acopf_set_state.argtypes = [vp, i32, i32, dp, i64]
     lib.acopf_get_sizes.argtypes = [vp, i32, C.POINTER(C.c_int64)]
     lib.acopf_get_timing.argtypes = [vp, dp]
+    lib.acopf_set_profiling.argtypes = [vp, i32]
     lib.acopf_destroy.argtypes = [vp]
     lib.acopf_destroy.restype = None
     lib.acopf_last_error.restype = C.c_char_p
     for name in ("acopf_create", "acopf_solve", "acopf_update_loads", "acopf_get_state",
-                 "acopf_set_state", "acopf_get_sizes", "acopf_get_timing"):
+                 "acopf_set_state", "acopf_get_sizes", "acopf_get_timing",
+                 "acopf_set_profiling"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -240,10 +242,13 @@ class Solver:
         self._check(self.lib.acopf_get_state(self.h, 0, STATS, _dp(out), 16))
         return {n: int(v) for n, v in zip(STATS_NAMES, out)}
 
+    def set_profiling(self, on: bool = True):
+        self._check(self.lib.acopf_set_profiling(self.h, int(on)))
+
     def timing(self) -> dict:
-        out = np.zeros(7)
+        out = np.zeros(5)
         self._check(self.lib.acopf_get_timing(self.h, _dp(out)))
-        keys = ("gen_ms", "branch6_ms", "branch4_ms", "bus_ms", "ctl_ms", "outer_ms")
-        d = dict(zip(keys, out[:6].tolist()))
-        d["iters"] = int(out[6])
+        keys = ("xstep_ms", "bus_ms", "ctl_ms", "outer_ms")
+        d = dict(zip(keys, out[:4].tolist()))
+        d["iters"] = int(out[4])
         return d

@@ -1,9 +1,9 @@
 // Host runtime and the closed-form kernels of the two-level component ADMM
 // for ACOPF (Kim & Kim, PSCC 2022) on gfx950, behind the C ABI of acopf.h.
 //
-// One inner iteration of Algorithm 1 is five launches on one stream:
-//   gen_kernel      generator closed form, eq. (qp-bound)          lane/gen
-//   branch_kernel   branch subproblems, eq. (branch), TRON + AL     lane/branch
+// One inner iteration of Algorithm 1 is four launches on one stream:
+//   xstep_kernel    branch subproblems, eq. (branch), TRON + AL     lane/branch
+//                   and the generator closed form, eq. (qp-bound)   lane/gen
 //   bus_kernel      bus closed form eq. (qp-bus), then z and y and
 //                   the residual maxima of every coupling it owns  lane/bus
 //   ctl_kernel      termination tests and the outer beta rule       lane/grid
@@ -60,38 +60,13 @@ int fail(int code, const std::string& msg) {
 
 constexpr int kHistCap = 1 << 15;  // per grid, inner iterations kept in history
 constexpr int kStats = 16;
+constexpr int kEvPerIter = 5;   // events per profiled iteration
+constexpr int kTimed = 4;       // kernels timed per iteration
+constexpr int kChunk = 16;      // iterations between control readbacks
 
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-
-struct GenArgs {
-  int64_t ng;
-  const int* gen_grid;
-  const GridCtl* ctl;
-  const double *pmin, *pmax, *qmin, *qmax;
-  const double *c2q, *c1l;  // 2 s c2 B^2 and s c1 B
-  const double *v, *z, *y;
-  double* u;
-  double rho;
-};
-
-// eq. (qp-bound): x = max(l, min(u, c/Q)) with Q, c from the cost and the
-// coupling penalty; p and q of generator g are couplings g and n_gen + g.
-__global__ __launch_bounds__(256) void gen_kernel(GenArgs A) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= A.ng) return;
-  if (A.ctl[A.gen_grid[g]].done) return;
-  const int64_t kp = g, kq = A.ng + g;
-  const double rho = A.rho;
-  const double Qp = A.c2q[g] + rho;
-  const double cp = rho * (A.v[kp] - A.z[kp]) - A.y[kp] - A.c1l[g];
-  const double xp = cp / Qp;
-  A.u[kp] = fmax(A.pmin[g], fmin(A.pmax[g], xp));
-  const double cq = rho * (A.v[kq] - A.z[kq]) - A.y[kq];
-  const double xq = cq / rho;
-  A.u[kq] = fmax(A.qmin[g], fmin(A.qmax[g], xq));
-}
 
 struct BusArgs {
   int64_t nb, ng, nl;
@@ -498,7 +473,7 @@ struct acopf_s {
   bool solved = false;
   bool profile = false;
   std::vector<hipEvent_t> ev;
-  double t_ms[6] = {0, 0, 0, 0, 0, 0};
+  double t_ms[kTimed] = {0, 0, 0, 0};
   int64_t t_iters = 0;
 };
 
@@ -535,6 +510,14 @@ BranchArgs branch_args(const acopf_s* h) {
   A.al_maxit = h->P.al_maxit;
   A.failures = h->failures;
   A.stats = h->stats;
+  A.ng = h->ng;
+  A.gen_grid = h->gen_grid;
+  A.pmin = h->pmin;
+  A.pmax = h->pmax;
+  A.qmin = h->qmin;
+  A.qmax = h->qmax;
+  A.c2q = h->c2q;
+  A.c1l = h->c1l;
   return A;
 }
 
@@ -543,34 +526,28 @@ int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 // Launch one inner iteration; with profiling, events bracket each launch.
 void launch_iteration(acopf_s* h, int fixed, int slot) {
   hipStream_t s = h->stream;
-  hipEvent_t* E = h->profile ? &h->ev[(size_t)slot * 12] : nullptr;
+  hipEvent_t* E = h->profile ? &h->ev[(size_t)slot * kEvPerIter] : nullptr;
   auto mark = [&](int k) {
     if (E) (void)hipEventRecord(E[k], s);
   };
-  GenArgs ga{h->ng, h->gen_grid, h->ctl, h->pmin, h->pmax, h->qmin, h->qmax,
-             h->c2q, h->c1l, h->v, h->z, h->y, h->u, h->P.rho_pq};
-  mark(0);
-  if (h->ng > 0) hipLaunchKernelGGL(gen_kernel, dim3(blocks_for(h->ng, 256)), dim3(256), 0, s, ga);
-  mark(1);
   BranchArgs ba = branch_args(h);
-  acopf_dev::launch_branch(ba, 0, (int)h->n6, 6, s);
-  mark(2);
-  acopf_dev::launch_branch(ba, (int)h->n6, (int)(h->nl - h->n6), 4, s);
-  mark(3);
+  mark(0);
+  acopf_dev::launch_xstep(ba, h->n6, s);
+  mark(1);
   BusArgs bu{h->nb, h->ng, h->nl, h->bus_grid, h->ctl, h->gptr, h->gidx, h->eptr, h->eidx,
              h->pd, h->qd, h->gs, h->bs, h->isref, h->u, h->lam, h->v, h->z, h->y,
              h->P.rho_pq, h->P.rho_va, h->rmax};
   hipLaunchKernelGGL(bus_kernel, dim3(blocks_for(h->nb, 256)), dim3(256), 0, s, bu);
-  mark(4);
+  mark(2);
   CtlArgs ca{h->G, h->ctl, h->rmax, h->hist, h->P.eps_pri, h->P.eps_dual, h->P.eps_z,
              h->P.beta_gamma, h->P.beta_omega, h->P.beta_max, h->P.max_outer,
              h->P.max_inner, fixed};
   hipLaunchKernelGGL(ctl_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, s, ca);
-  mark(5);
+  mark(3);
   OuterArgs oa{h->m, h->ng, h->nl, h->gen_grid, h->br_grid, h->ctl, h->z, h->lam,
                h->P.lambda_max};
   hipLaunchKernelGGL(outer_kernel, dim3(blocks_for(h->m, 256)), dim3(256), 0, s, oa);
-  mark(6);
+  mark(4);
 }
 
 int validate_grid(const acopf_grid& g, int idx) {
@@ -645,13 +622,13 @@ extern "C" {
 void acopf_default_params(acopf_params* p) {
   if (!p) return;
   p->rho_pq = 400.0;
-  p->rho_va = 40000.0;
-  p->obj_scale = 1.0;
+  p->rho_va = 4000.0;
+  p->obj_scale = 0.01;
   p->rate_scale = 0.99;
-  p->beta0 = 1e3;
+  p->beta0 = 1e4;
   p->beta_gamma = 6.0;
   p->beta_omega = 0.8;
-  p->beta_max = 1e20;
+  p->beta_max = 1e4;
   p->lambda_max = 1e12;
   p->eps_pri = 1e-4;
   p->eps_dual = 1e-4;
@@ -704,8 +681,6 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
     HIP_TRY(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
     h->own_stream = true;
   }
-  const char* prof = std::getenv("ACOPF_PROFILE");
-  h->profile = prof && prof[0] == '1';
 
   // ---- sizes and orders
   h->grids.resize(n_grids);
@@ -909,10 +884,6 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(hipMemsetAsync(h->stats, 0, sizeof(unsigned long long) * kStats, st));
   HIP_TRY(hipMemsetAsync(h->hist, 0, sizeof(double) * (size_t)n_grids * kHistCap * 6, st));
   HIP_TRY(hipMemsetAsync(h->ctl, 0, sizeof(GridCtl) * n_grids, st));
-  if (h->profile) {
-    h->ev.resize(12 * 64);
-    for (auto& e : h->ev) HIP_TRY(hipEventCreate(&e));
-  }
   HIP_TRY(hipStreamSynchronize(st));
   return ACOPF_OK;
 }
@@ -949,8 +920,8 @@ int acopf_create(const acopf_grid* grids, int32_t n_grids, const acopf_params* p
 
 static void accumulate_timing(acopf_s* h, int used) {
   for (int s = 0; s < used; ++s) {
-    hipEvent_t* E = &h->ev[(size_t)s * 12];
-    for (int k = 0; k < 6; ++k) {
+    hipEvent_t* E = &h->ev[(size_t)s * kEvPerIter];
+    for (int k = 0; k < kTimed; ++k) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, E[k], E[k + 1]) == hipSuccess) h->t_ms[k] += ms;
     }
@@ -985,10 +956,9 @@ int acopf_solve(acopf_handle h, int32_t mode, int32_t fixed_iters, acopf_result*
                           ? fixed_iters
                           : (int64_t)h->P.max_outer * h->P.max_inner + 1;
   int64_t issued = 0;
-  const int chunk = 16;
   bool all_done = false;
   while (!all_done && issued < cap) {
-    const int k = (int)std::min<int64_t>(chunk, cap - issued);
+    const int k = (int)std::min<int64_t>(kChunk, cap - issued);
     for (int c = 0; c < k; ++c) launch_iteration(h, fixed_iters, c);
     issued += k;
     HIP_TRY(hipGetLastError());
@@ -1205,11 +1175,22 @@ int acopf_get_sizes(acopf_handle h, int32_t grid, int64_t* out4) {
   return ACOPF_OK;
 }
 
-int acopf_get_timing(acopf_handle h, double* out7) {
-  if (!h || !out7) return fail(ACOPF_EINVAL, "null argument");
+int acopf_set_profiling(acopf_handle h, int32_t on) {
+  if (!h) return fail(ACOPF_EINVAL, "null handle");
+  HIP_TRY(hipSetDevice(h->device));
+  if (on && h->ev.empty()) {
+    h->ev.resize((size_t)kEvPerIter * kChunk);
+    for (auto& e : h->ev) HIP_TRY(hipEventCreate(&e));
+  }
+  h->profile = on != 0;
+  return ACOPF_OK;
+}
+
+int acopf_get_timing(acopf_handle h, double* out5) {
+  if (!h || !out5) return fail(ACOPF_EINVAL, "null argument");
   const double n = h->t_iters > 0 ? (double)h->t_iters : 1.0;
-  for (int k = 0; k < 6; ++k) out7[k] = h->t_ms[k] / n;
-  out7[6] = (double)h->t_iters;
+  for (int k = 0; k < kTimed; ++k) out5[k] = h->t_ms[k] / n;
+  out5[kTimed] = (double)h->t_iters;
   return ACOPF_OK;
 }
 

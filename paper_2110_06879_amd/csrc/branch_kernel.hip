@@ -741,19 +741,10 @@ __device__ int tron(const BranchIn<N>& B, double* x, const double* lo, const dou
 
 #undef FL
 
-// One lane per branch over [first, first + count) of the device branch order.
+// Branch l of the device order with N variables: solve, write u and state.
 template <int N>
-__global__ __launch_bounds__(64) void branch_kernel(BranchArgs A, int first, int count) {
-  const int lane_id = blockIdx.x * blockDim.x + threadIdx.x;
-  Counters cnt = {};
-  bool active = lane_id < count;
-  int l = first + lane_id;
-  int grid = 0;
-  if (active) {
-    grid = A.br_grid[l];
-    active = A.ctl[grid].done == 0;
-  }
-  if (active) {
+__device__ void solve_branch(const BranchArgs& A, int64_t l, int grid, Counters& cnt) {
+  {
     const int64_t nl = A.nl;
     BranchIn<N> B;
     B.gii = A.adm[0 * nl + l];
@@ -835,6 +826,42 @@ __global__ __launch_bounds__(64) void branch_kernel(BranchArgs A, int first, int
     for (int i = 0; i < N; ++i) A.bx[i * nl + l] = x[i];
     if (failures) atomicAdd(&A.failures[grid], failures);
   }
+}
+
+// eq. (qp-bound) for generator g: p and q are couplings g and n_gen + g.
+__device__ inline void solve_generator(const BranchArgs& A, int64_t g) {
+  const int64_t kp = g, kq = A.ng + g;
+  const double rho = A.rho_pq;
+  const double Qp = A.c2q[g] + rho;
+  const double cp = rho * (A.v[kp] - A.z[kp]) - A.y[kp] - A.c1l[g];
+  const double xp = cp / Qp;
+  A.u[kp] = fmax(A.pmin[g], fmin(A.pmax[g], xp));
+  const double cq = rho * (A.v[kq] - A.z[kq]) - A.y[kq];
+  const double xq = cq / rho;
+  A.u[kq] = fmax(A.qmin[g], fmin(A.qmax[g], xq));
+}
+
+__global__ __launch_bounds__(64) void xstep_kernel(BranchArgs A, int64_t n6, int b6, int b4) {
+  Counters cnt = {};
+  bool active = false;
+  const int b = blockIdx.x;
+  if (b < b6 + b4) {
+    const bool six = b < b6;
+    const int64_t l = six ? (int64_t)b * 64 + threadIdx.x
+                          : n6 + (int64_t)(b - b6) * 64 + threadIdx.x;
+    if (six ? l < n6 : l < A.nl) {
+      const int grid = A.br_grid[l];
+      if (A.ctl[grid].done == 0) {
+        active = true;
+        if (six) solve_branch<6>(A, l, grid, cnt);
+        else solve_branch<4>(A, l, grid, cnt);
+      }
+    }
+  } else {
+    const int64_t g = (int64_t)(b - b6 - b4) * 64 + threadIdx.x;
+    if (g < A.ng && A.ctl[A.gen_grid[g]].done == 0) solve_generator(A, g);
+    return;  // whole block is generators: no branch counters
+  }
   // wave-level reduction of the counters, one atomic per counter per wavefront
   uint64_t v[15] = {active ? 1ull : 0ull, cnt.flops, cnt.trig, cnt.tron_calls,
                     cnt.tron_iters, cnt.n_fgh, cnt.n_f, cnt.cauchy, cnt.cg, cnt.chol,
@@ -852,13 +879,12 @@ __global__ __launch_bounds__(64) void branch_kernel(BranchArgs A, int first, int
   }
 }
 
-void launch_branch(const BranchArgs& A, int first, int count, int nvar, hipStream_t s) {
-  if (count <= 0) return;
-  const int blocks = (count + 63) / 64;
-  if (nvar == 6)
-    hipLaunchKernelGGL(branch_kernel<6>, dim3(blocks), dim3(64), 0, s, A, first, count);
-  else
-    hipLaunchKernelGGL(branch_kernel<4>, dim3(blocks), dim3(64), 0, s, A, first, count);
+void launch_xstep(const BranchArgs& A, int64_t n6, hipStream_t s) {
+  const int b6 = (int)((n6 + 63) / 64);
+  const int b4 = (int)((A.nl - n6 + 63) / 64);
+  const int bg = (int)((A.ng + 63) / 64);
+  if (b6 + b4 + bg == 0) return;
+  hipLaunchKernelGGL(xstep_kernel, dim3(b6 + b4 + bg), dim3(64), 0, s, A, n6, b6, b4);
 }
 
 }  // namespace acopf_dev

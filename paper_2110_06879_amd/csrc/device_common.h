@@ -33,8 +33,15 @@ struct BranchArgs {
   int tron_maxit, al_maxit;
   int* failures;             // [G]
   unsigned long long* stats; // [16]
+  // generator step, fused into the same launch
+  int64_t ng;
+  const int* gen_grid;
+  const double *pmin, *pmax, *qmin, *qmax, *c2q, *c1l;
 };
 
-void launch_branch(const BranchArgs& A, int first, int count, int nvar, hipStream_t s);
+// One launch for the whole x-step: blocks [0, b6) solve rated branches
+// [0, n6), blocks [b6, b6 + b4) unlimited branches [n6, nl), the remaining
+// blocks the generators.
+void launch_xstep(const BranchArgs& A, int64_t n6, hipStream_t s);
 
 }  // namespace acopf_dev

@@ -19,9 +19,12 @@ one ``numpy.random.default_rng(seed)`` per grid):
    Pmin = 0, Pmax ~ U(0.5, 3), Q limits = +-Pmax, cost
    c2 ~ U(0.01, 0.1) $/MW^2h, c1 ~ U(10, 40) $/MWh, c0 = 0 (MATPOWER
    convention: cost on MW with baseMVA = 100).
-4. Loads at every bus: Pd ~ U(0, 0.5), Qd = 0.3 Pd. Feasibility guard: if
-   sum(Pd) > 0.75 sum(Pmax), Pd and Qd are scaled so that the ratio is 0.75
-   (the factor is returned).
+4. Loads at every bus: Pd ~ load_factor * U(0, 0.5), Qd = 0.3 Pd. The five
+   workloads use load_factor = 0.2: at the full U(0, 0.5) level these weak
+   synthetic networks (x up to 0.2 p.u., a generator on one bus in five) are
+   voltage-infeasible in remote radial pockets. Guard: if sum(Pd) > 0.75
+   sum(Pmax), Pd and Qd are scaled so that the ratio is 0.75 (the factor is
+   returned).
 5. |V| in [0.94, 1.06], bus shunts 0, baseMVA 100.
 """
 from __future__ import annotations
@@ -130,7 +133,7 @@ def _topology(rng: np.random.Generator, n_b: int, n_l: int):
 
 def gridgen(n_bus: int, n_gen: int, n_branch: int, rated_frac: float,
             seed: int, name: str | None = None,
-            load_guard: float = 0.75) -> Grid:
+            load_guard: float = 0.75, load_factor: float = 1.0) -> Grid:
     """Draw one synthetic grid (recipe in the module docstring)."""
     if not (1 <= n_gen <= n_bus):
         raise ValueError("need 1 <= n_gen <= n_bus")
@@ -149,7 +152,7 @@ def gridgen(n_bus: int, n_gen: int, n_branch: int, rated_frac: float,
     pmax = rng.uniform(0.5, 3.0, n_gen)
     c2 = rng.uniform(0.01, 0.1, n_gen)
     c1 = rng.uniform(10.0, 40.0, n_gen)
-    pd = rng.uniform(0.0, 0.5, n_bus)
+    pd = load_factor * rng.uniform(0.0, 0.5, n_bus)
     qd = 0.3 * pd
     ratio = pd.sum() / pmax.sum()
     scale = 1.0
@@ -181,11 +184,16 @@ def perturb_loads(grid: Grid, frac: float, seed: int):
     return grid.pd * (1.0 + d), grid.qd * (1.0 + d)
 
 
+LOAD_FACTOR = 0.2
+
 # The five workloads: 30-bus plain, 2k-bus, 70k-bus, 64-grid batch, serving.
 CONFIGS = {
-    "c1_30bus": dict(n_bus=30, n_gen=6, n_branch=41, rated_frac=1.0, seed=1),
-    "c2_2kbus": dict(n_bus=2000, n_gen=400, n_branch=2600, rated_frac=1.0, seed=2),
-    "c3_70kbus": dict(n_bus=70000, n_gen=10000, n_branch=88000, rated_frac=0.3, seed=3),
+    "c1_30bus": dict(n_bus=30, n_gen=6, n_branch=41, rated_frac=1.0, seed=1,
+                     load_factor=LOAD_FACTOR),
+    "c2_2kbus": dict(n_bus=2000, n_gen=400, n_branch=2600, rated_frac=1.0, seed=2,
+                     load_factor=LOAD_FACTOR),
+    "c3_70kbus": dict(n_bus=70000, n_gen=10000, n_branch=88000, rated_frac=0.3, seed=3,
+                      load_factor=LOAD_FACTOR),
 }
 
 
@@ -203,7 +211,7 @@ def batch_grids(n_grids: int = 64, seed: int = 4, lo: int = 500,
         ng = max(1, int(round(0.2 * nb)))
         nl = int(round(1.3 * nb))
         out.append(gridgen(nb, ng, nl, 1.0, first_grid_seed + k,
-                           name=f"batch{k}_{nb}"))
+                           name=f"batch{k}_{nb}", load_factor=LOAD_FACTOR))
     return out
 
 
@@ -224,5 +232,5 @@ def serving_grids(n_grids: int = 16, seed: int = 5, lo: int = 2000,
         nl = int(round(1.3 * nb))
         rf = 0.3 if nb > 20000 else 1.0
         out.append(gridgen(nb, ng, nl, rf, first_grid_seed + k,
-                           name=f"serve{k}_{nb}"))
+                           name=f"serve{k}_{nb}", load_factor=LOAD_FACTOR))
     return out
