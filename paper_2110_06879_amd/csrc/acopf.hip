@@ -17,12 +17,17 @@
 // have finished, so a chunk of launches can overshoot convergence harmlessly;
 // the host reads the per-grid control words once per chunk.
 //
-// Device layout (structure of arrays, FP64):
-//   couplings [m]: generator p [n_gen], generator q [n_gen], then for each
-//     branch kind k = 0..7 (p_ij q_ij p_ji q_ji w_i th_i w_j th_j) [n_branch];
-//   branches: rated (6-variable) ones first, then unlimited (4-variable);
-//   buses: CSR lists of generators and of branch ends (from-ends, then
-//     to-ends, in input order).
+// Device layout (structure of arrays, FP64), chosen for the HBM-bound bus
+// step: every bus owns a contiguous range of generators and of branch ends,
+// so the bus kernel streams its couplings; the compute-bound branch step does
+// the scattered accesses instead (24 loads and 8 stores per branch solve).
+//   generators: sorted by (grid, bus, input index), range gptr[b]..gptr[b+1];
+//   branch ends: bus CSR order (per bus: from-ends, then to-ends, each in
+//     input order), range eptr[b]..eptr[b+1];
+//   couplings [m]: generator p [n_gen], generator q [n_gen], then end blocks
+//     p, q, w, theta of 2 n_branch each;
+//   branches: rated (6-variable) first, then unlimited (4-variable), each by
+//     (grid, from bus, input index); ef[l], et[l] locate their two ends.
 
 #include <hip/hip_runtime.h>
 
@@ -69,10 +74,10 @@ constexpr int kChunk = 16;      // iterations between control readbacks
 // ---------------------------------------------------------------------------
 
 struct BusArgs {
-  int64_t nb, ng, nl;
+  int64_t nb, ng, ne;
   const int* bus_grid;
   GridCtl* ctl;
-  const int *gptr, *gidx, *eptr, *eidx;
+  const int *gptr, *eptr;
   const double *pd, *qd, *gs, *bs;
   const int* isref;
   const double* u;
@@ -101,16 +106,15 @@ __global__ __launch_bounds__(256) void bus_kernel(BusArgs A) {
     act = A.ctl[grid].done == 0;
   }
   if (act) {
-    const int64_t ng = A.ng, nl = A.nl, cb = 2 * ng;
+    const int64_t ng = A.ng, ne = A.ne;
+    const int64_t kP = 2 * ng, kQ = kP + ne, kW = kQ + ne, kT = kW + ne;
     const double rpq = A.rho_pq, rva = A.rho_va;
     const int g0 = A.gptr[i], g1 = A.gptr[i + 1];
     const int e0 = A.eptr[i], e1 = A.eptr[i + 1];
     // shared w and theta of the bus
     double Qw = 0.0, cw = 0.0, Qt = 0.0, ct = 0.0;
     for (int e = e0; e < e1; ++e) {
-      const int code = A.eidx[e];
-      const int64_t l = code >> 1;
-      const int64_t kw = cb + ((code & 1) ? 6 : 4) * nl + l, kt = kw + nl;
+      const int64_t kw = kW + e, kt = kT + e;
       Qw += rva;
       cw += rva * (A.u[kw] + A.z[kw]) + A.y[kw];
       Qt += rva;
@@ -121,19 +125,16 @@ __global__ __launch_bounds__(256) void bus_kernel(BusArgs A) {
     double r0 = awP * cw / Qw - A.pd[i], r1 = awQ * cw / Qw - A.qd[i];
     const double inv_pq = 1.0 / rpq;
     for (int t = g0; t < g1; ++t) {
-      const int64_t g = A.gidx[t];
-      const double cvp = rpq * (A.u[g] + A.z[g]) + A.y[g];
+      const int64_t gp = t, gq = ng + t;
+      const double cvp = rpq * (A.u[gp] + A.z[gp]) + A.y[gp];
       M00 += inv_pq;
       r0 += cvp / rpq;
-      const int64_t gq = ng + g;
       const double cvq = rpq * (A.u[gq] + A.z[gq]) + A.y[gq];
       M11 += inv_pq;
       r1 += cvq / rpq;
     }
     for (int e = e0; e < e1; ++e) {
-      const int code = A.eidx[e];
-      const int64_t l = code >> 1;
-      const int64_t kp = cb + ((code & 1) ? 2 : 0) * nl + l, kq = kp + nl;
+      const int64_t kp = kP + e, kq = kQ + e;
       const double cvp = rpq * (A.u[kp] + A.z[kp]) + A.y[kp];
       M00 += inv_pq;
       r0 += -cvp / rpq;
@@ -161,24 +162,20 @@ __global__ __launch_bounds__(256) void bus_kernel(BusArgs A) {
       rz = fmax(rz, fabs(zk));
     };
     for (int t = g0; t < g1; ++t) {
-      const int64_t g = A.gidx[t], gq = ng + g;
-      const double cvp = rpq * (A.u[g] + A.z[g]) + A.y[g];
+      const int64_t gp = t, gq = ng + t;
+      const double cvp = rpq * (A.u[gp] + A.z[gp]) + A.y[gp];
       const double cvq = rpq * (A.u[gq] + A.z[gq]) + A.y[gq];
-      finish(g, (cvp - mu0) / rpq, rpq);
+      finish(gp, (cvp - mu0) / rpq, rpq);
       finish(gq, (cvq - mu1) / rpq, rpq);
     }
     for (int e = e0; e < e1; ++e) {
-      const int code = A.eidx[e];
-      const int64_t l = code >> 1;
-      const int side = code & 1;
-      const int64_t kp = cb + (side ? 2 : 0) * nl + l, kq = kp + nl;
+      const int64_t kp = kP + e, kq = kQ + e;
       const double cvp = rpq * (A.u[kp] + A.z[kp]) + A.y[kp];
       const double cvq = rpq * (A.u[kq] + A.z[kq]) + A.y[kq];
       finish(kp, (cvp + mu0) / rpq, rpq);
       finish(kq, (cvq + mu1) / rpq, rpq);
-      const int64_t kw = cb + (side ? 6 : 4) * nl + l, kt = kw + nl;
-      finish(kw, w, rva);
-      finish(kt, th, rva);
+      finish(kW + e, w, rva);
+      finish(kT + e, th, rva);
     }
   }
   // wavefront max, one atomic per grid segment of the wavefront
@@ -279,25 +276,25 @@ __global__ void ctl_kernel(CtlArgs A) {
 }
 
 struct OuterArgs {
-  int64_t m, ng, nl;
-  const int *gen_grid, *br_grid;
+  int64_t m, ng, ne;
+  const int *gen_grid, *end_grid;
   const GridCtl* ctl;
   const double* z;
   double* lam;
   double lambda_max;
 };
 
-__device__ inline int coupling_grid(int64_t k, int64_t ng, int64_t nl, const int* gen_grid,
-                                    const int* br_grid) {
+__device__ inline int coupling_grid(int64_t k, int64_t ng, int64_t ne, const int* gen_grid,
+                                    const int* end_grid) {
   if (k < 2 * ng) return gen_grid[k < ng ? k : k - ng];
-  return br_grid[(k - 2 * ng) % nl];
+  return end_grid[(k - 2 * ng) % ne];
 }
 
 // lambda <- proj_[-lmax, lmax](lambda + beta z) (multiplier updates, Sec. III-B)
 __global__ __launch_bounds__(256) void outer_kernel(OuterArgs A) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= A.m) return;
-  const int g = coupling_grid(k, A.ng, A.nl, A.gen_grid, A.br_grid);
+  const int g = coupling_grid(k, A.ng, A.ne, A.gen_grid, A.end_grid);
   const GridCtl& c = A.ctl[g];
   if (!c.do_outer) return;
   const double t = A.lam[k] + c.beta_lam * A.z[k];
@@ -305,7 +302,8 @@ __global__ __launch_bounds__(256) void outer_kernel(OuterArgs A) {
 }
 
 struct ColdArgs {
-  int64_t ng, nl, m;
+  int64_t ng, nl, ne, m;
+  const int *ef, *et;
   const int *gen_grid, *br_grid;
   const double *pmin, *pmax, *qmin, *qmax;
   const double* adm;
@@ -345,8 +343,15 @@ __global__ __launch_bounds__(256) void cold_kernel(ColdArgs A) {
   const double a2 = Y[6 * nl + l] * wj + Y[4 * nl + l] * WR - Y[5 * nl + l] * WI;
   const double a3 = -Y[7 * nl + l] * wj - Y[5 * nl + l] * WR - Y[4 * nl + l] * WI;
   const double a[8] = {a0, a1, a2, a3, wi, 0.0, wj, 0.0};
-  const int64_t cb = 2 * A.ng;
-  for (int k = 0; k < 8; ++k) setk(cb + k * nl + l, a[k]);
+  const int64_t ef = A.ef[l], et = A.et[l];
+  setk(acopf_dev::end_coupling(A.ng, A.ne, 0, ef), a0);
+  setk(acopf_dev::end_coupling(A.ng, A.ne, 1, ef), a1);
+  setk(acopf_dev::end_coupling(A.ng, A.ne, 0, et), a2);
+  setk(acopf_dev::end_coupling(A.ng, A.ne, 1, et), a3);
+  setk(acopf_dev::end_coupling(A.ng, A.ne, 2, ef), a[4]);
+  setk(acopf_dev::end_coupling(A.ng, A.ne, 3, ef), a[5]);
+  setk(acopf_dev::end_coupling(A.ng, A.ne, 2, et), a[6]);
+  setk(acopf_dev::end_coupling(A.ng, A.ne, 3, et), a[7]);
   A.bx[0 * nl + l] = vi;
   A.bx[1 * nl + l] = vj;
   A.bx[2 * nl + l] = 0.0;
@@ -420,7 +425,9 @@ __global__ __launch_bounds__(256) void objective_kernel(const int64_t* gen_off,
 struct HostGrid {
   int64_t nb, ng, nl;
   int64_t bus_off, gen_off;
-  std::vector<int64_t> br_dev;  // canonical branch -> device index
+  std::vector<int64_t> br_dev;   // input branch -> device branch index
+  std::vector<int64_t> gen_dev;  // input generator -> device generator index
+  std::vector<int64_t> end_f, end_t;  // input branch -> device end positions
   int ref;
 };
 
@@ -457,11 +464,13 @@ struct acopf_s {
   std::vector<HostGrid> grids;
   DevBuf buf;
   // device arrays
-  int *gen_grid = nullptr, *br_grid = nullptr, *bus_grid = nullptr;
+  int64_t ne = 0;
+  int *gen_grid = nullptr, *br_grid = nullptr, *bus_grid = nullptr, *end_grid = nullptr;
+  int *ef = nullptr, *et = nullptr;
   double *pmin, *pmax, *qmin, *qmax, *c2q, *c1l, *c2, *c1, *c0;
   double *adm, *vlo_i, *vhi_i, *vlo_j, *vhi_j, *rate2;
   double *u, *v, *z, *y, *lam, *bx, *ltil, *rtil;
-  int *gptr, *gidx, *eptr, *eidx, *isref;
+  int *gptr, *eptr, *isref;
   double *pd, *qd, *gs, *bs;
   GridCtl* ctl;
   GridCtl* h_ctl = nullptr;  // pinned
@@ -482,7 +491,9 @@ namespace {
 BranchArgs branch_args(const acopf_s* h) {
   BranchArgs A{};
   A.nl = h->nl;
-  A.br_coupling_base = 2 * h->ng;
+  A.ne = h->ne;
+  A.ef = h->ef;
+  A.et = h->et;
   A.br_grid = h->br_grid;
   A.ctl = h->ctl;
   A.adm = h->adm;
@@ -534,7 +545,7 @@ void launch_iteration(acopf_s* h, int fixed, int slot) {
   mark(0);
   acopf_dev::launch_xstep(ba, h->n6, s);
   mark(1);
-  BusArgs bu{h->nb, h->ng, h->nl, h->bus_grid, h->ctl, h->gptr, h->gidx, h->eptr, h->eidx,
+  BusArgs bu{h->nb, h->ng, h->ne, h->bus_grid, h->ctl, h->gptr, h->eptr,
              h->pd, h->qd, h->gs, h->bs, h->isref, h->u, h->lam, h->v, h->z, h->y,
              h->P.rho_pq, h->P.rho_va, h->rmax};
   hipLaunchKernelGGL(bus_kernel, dim3(blocks_for(h->nb, 256)), dim3(256), 0, s, bu);
@@ -544,7 +555,7 @@ void launch_iteration(acopf_s* h, int fixed, int slot) {
              h->P.max_inner, fixed};
   hipLaunchKernelGGL(ctl_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, s, ca);
   mark(3);
-  OuterArgs oa{h->m, h->ng, h->nl, h->gen_grid, h->br_grid, h->ctl, h->z, h->lam,
+  OuterArgs oa{h->m, h->ng, h->ne, h->gen_grid, h->end_grid, h->ctl, h->z, h->lam,
                h->P.lambda_max};
   hipLaunchKernelGGL(outer_kernel, dim3(blocks_for(h->m, 256)), dim3(256), 0, s, oa);
   mark(4);
@@ -702,24 +713,78 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   h->nb = nb;
   h->ng = ng;
   h->nl = nl;
+  h->ne = 2 * nl;
   h->n6 = n6;
   h->m = 2 * ng + 8 * nl;
   if (nl >= (int64_t(1) << 30) || nb >= (int64_t(1) << 31))
     return fail(ACOPF_EINVAL, "problem too large for 32-bit element indices");
-  // device branch order: rated first, then unlimited; each by (grid, index)
-  std::vector<int> dev_grid(nl), dev_canon(nl);
+  // ---- per-bus counts -> CSR offsets of generators and branch ends
+  std::vector<int> gptr(nb + 1, 0), eptr(nb + 1, 0);
+  std::vector<int> fcount(nb, 0), tcount(nb, 0);
+  for (int g = 0; g < n_grids; ++g) {
+    const acopf_grid& G = grids[g];
+    const HostGrid& H = h->grids[g];
+    for (int k = 0; k < G.n_gen; ++k) ++gptr[H.bus_off + G.gen_bus[k] + 1];
+    for (int l = 0; l < G.n_branch; ++l) {
+      ++fcount[H.bus_off + G.br_from[l]];
+      ++tcount[H.bus_off + G.br_to[l]];
+    }
+  }
+  for (int64_t b = 0; b < nb; ++b) {
+    gptr[b + 1] += gptr[b];
+    eptr[b + 1] = eptr[b] + fcount[b] + tcount[b];
+  }
+  // generators: device order sorted by (grid, bus, input index); ends: per bus,
+  // from-ends then to-ends, each in input order
+  std::vector<int> end_grid(2 * nl);
   {
-    int64_t r6 = 0, r4 = n6;
+    std::vector<int> gpos(gptr.begin(), gptr.end() - 1), fpos(nb), tpos(nb);
+    for (int64_t b = 0; b < nb; ++b) {
+      fpos[b] = eptr[b];
+      tpos[b] = eptr[b] + fcount[b];
+    }
     for (int g = 0; g < n_grids; ++g) {
       const acopf_grid& G = grids[g];
-      h->grids[g].br_dev.resize(G.n_branch);
+      HostGrid& H = h->grids[g];
+      H.gen_dev.resize(G.n_gen);
+      for (int k = 0; k < G.n_gen; ++k) H.gen_dev[k] = gpos[H.bus_off + G.gen_bus[k]]++;
+      H.end_f.resize(G.n_branch);
+      H.end_t.resize(G.n_branch);
       for (int l = 0; l < G.n_branch; ++l) {
-        const int64_t d = G.rate[l] > 0.0 ? r6++ : r4++;
-        h->grids[g].br_dev[l] = d;
-        dev_grid[d] = g;
-        dev_canon[d] = l;
+        H.end_f[l] = fpos[H.bus_off + G.br_from[l]]++;
+        H.end_t[l] = tpos[H.bus_off + G.br_to[l]]++;
+        end_grid[H.end_f[l]] = g;
+        end_grid[H.end_t[l]] = g;
+      }
+      // each grid's generators occupy [gen_off, gen_off + ng) of the device order
+    }
+  }
+  // branches: rated first, then unlimited; each by (grid, from bus, input index)
+  std::vector<int> dev_grid(nl), ef(nl), et(nl);
+  {
+    std::vector<std::pair<int64_t, std::pair<int, int>>> r6, r4;  // (key, (grid, l))
+    for (int g = 0; g < n_grids; ++g) {
+      const acopf_grid& G = grids[g];
+      const HostGrid& H = h->grids[g];
+      for (int l = 0; l < G.n_branch; ++l) {
+        const int64_t key = (H.bus_off + G.br_from[l]) * (int64_t)(1 << 30) + l;
+        (G.rate[l] > 0.0 ? r6 : r4).push_back({key, {g, l}});
       }
     }
+    std::sort(r6.begin(), r6.end());
+    std::sort(r4.begin(), r4.end());
+    int64_t d = 0;
+    for (auto* lst : {&r6, &r4})
+      for (auto& it : *lst) {
+        const int g = it.second.first, l = it.second.second;
+        HostGrid& H = h->grids[g];
+        if (H.br_dev.empty()) H.br_dev.assign(H.nl, -1);
+        H.br_dev[l] = d;
+        dev_grid[d] = g;
+        ef[d] = (int)H.end_f[l];
+        et[d] = (int)H.end_t[l];
+        ++d;
+      }
   }
   // ---- host arrays in device order
   std::vector<int> gen_grid(ng), bus_grid(nb), isref(nb, 0);
@@ -727,7 +792,6 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
       c1(ng), c0(ng);
   std::vector<double> adm(8 * nl), vlo_i(nl), vhi_i(nl), vlo_j(nl), vhi_j(nl), rate2(nl);
   std::vector<double> pd(nb), qd(nb), gs(nb), bs(nb);
-  std::vector<int> gptr(nb + 1, 0), eptr(nb + 1, 0);
   std::vector<int64_t> gen_off(n_grids + 1, 0);
   std::vector<double> base(n_grids);
   const double s = params->obj_scale;
@@ -739,7 +803,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
     gen_off[g] = H.gen_off;
     gen_off[g + 1] = H.gen_off + H.ng;
     for (int k = 0; k < G.n_gen; ++k) {
-      const int64_t d = H.gen_off + k;
+      const int64_t d = H.gen_dev[k];
       gen_grid[d] = g;
       pmin[d] = G.pmin[k];
       pmax[d] = G.pmax[k];
@@ -790,45 +854,15 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
       rate2[d] = G.rate[l] > 0.0 ? rs * rs : 0.0;
     }
   }
-  // CSR: generators per bus, and branch ends per bus (from-ends then to-ends)
-  std::vector<int> gidx(ng), eidx(2 * nl);
-  {
-    std::vector<int> gcount(nb, 0), fcount(nb, 0), tcount(nb, 0);
-    for (int g = 0; g < n_grids; ++g) {
-      const acopf_grid& G = grids[g];
-      const HostGrid& H = h->grids[g];
-      for (int k = 0; k < G.n_gen; ++k) ++gcount[H.bus_off + G.gen_bus[k]];
-      for (int l = 0; l < G.n_branch; ++l) {
-        ++fcount[H.bus_off + G.br_from[l]];
-        ++tcount[H.bus_off + G.br_to[l]];
-      }
-    }
-    for (int64_t b = 0; b < nb; ++b) {
-      gptr[b + 1] = gptr[b] + gcount[b];
-      eptr[b + 1] = eptr[b] + fcount[b] + tcount[b];
-    }
-    std::vector<int> gpos(gptr.begin(), gptr.end() - 1), fpos(nb), tpos(nb);
-    for (int64_t b = 0; b < nb; ++b) {
-      fpos[b] = eptr[b];
-      tpos[b] = eptr[b] + fcount[b];
-    }
-    for (int g = 0; g < n_grids; ++g) {
-      const acopf_grid& G = grids[g];
-      const HostGrid& H = h->grids[g];
-      for (int k = 0; k < G.n_gen; ++k) gidx[gpos[H.bus_off + G.gen_bus[k]]++] = (int)(H.gen_off + k);
-      for (int l = 0; l < G.n_branch; ++l) {
-        const int d = (int)H.br_dev[l];
-        eidx[fpos[H.bus_off + G.br_from[l]]++] = d * 2 + 0;
-        eidx[tpos[H.bus_off + G.br_to[l]]++] = d * 2 + 1;
-      }
-    }
-  }
   // ---- device allocation and upload
   DevBuf& D = h->buf;
   const int64_t m = h->m;
   HIP_TRY(D.alloc(&h->gen_grid, ng));
   HIP_TRY(D.alloc(&h->br_grid, nl));
   HIP_TRY(D.alloc(&h->bus_grid, nb));
+  HIP_TRY(D.alloc(&h->end_grid, 2 * nl));
+  HIP_TRY(D.alloc(&h->ef, nl));
+  HIP_TRY(D.alloc(&h->et, nl));
   double** gen_d[] = {&h->pmin, &h->pmax, &h->qmin, &h->qmax, &h->c2q, &h->c1l, &h->c2, &h->c1, &h->c0};
   for (double** p : gen_d) HIP_TRY(D.alloc(p, ng));
   HIP_TRY(D.alloc(&h->adm, 8 * nl));
@@ -839,9 +873,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   double** cp_d[] = {&h->u, &h->v, &h->z, &h->y, &h->lam};
   for (double** p : cp_d) HIP_TRY(D.alloc(p, m));
   HIP_TRY(D.alloc(&h->gptr, nb + 1));
-  HIP_TRY(D.alloc(&h->gidx, ng));
   HIP_TRY(D.alloc(&h->eptr, nb + 1));
-  HIP_TRY(D.alloc(&h->eidx, 2 * nl));
   HIP_TRY(D.alloc(&h->isref, nb));
   double** bus_d[] = {&h->pd, &h->qd, &h->gs, &h->bs};
   for (double** p : bus_d) HIP_TRY(D.alloc(p, nb));
@@ -862,6 +894,9 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(up(h->gen_grid, gen_grid.data(), sizeof(int) * ng));
   HIP_TRY(up(h->br_grid, dev_grid.data(), sizeof(int) * nl));
   HIP_TRY(up(h->bus_grid, bus_grid.data(), sizeof(int) * nb));
+  HIP_TRY(up(h->end_grid, end_grid.data(), sizeof(int) * 2 * nl));
+  HIP_TRY(up(h->ef, ef.data(), sizeof(int) * nl));
+  HIP_TRY(up(h->et, et.data(), sizeof(int) * nl));
   const std::vector<double>* gen_h[] = {&pmin, &pmax, &qmin, &qmax, &c2q, &c1l, &c2, &c1, &c0};
   for (int q = 0; q < 9; ++q) HIP_TRY(up(*gen_d[q], gen_h[q]->data(), sizeof(double) * ng));
   HIP_TRY(up(h->adm, adm.data(), sizeof(double) * 8 * nl));
@@ -871,9 +906,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(up(h->vhi_j, vhi_j.data(), sizeof(double) * nl));
   HIP_TRY(up(h->rate2, rate2.data(), sizeof(double) * nl));
   HIP_TRY(up(h->gptr, gptr.data(), sizeof(int) * (nb + 1)));
-  HIP_TRY(up(h->gidx, gidx.data(), sizeof(int) * ng));
   HIP_TRY(up(h->eptr, eptr.data(), sizeof(int) * (nb + 1)));
-  HIP_TRY(up(h->eidx, eidx.data(), sizeof(int) * 2 * nl));
   HIP_TRY(up(h->isref, isref.data(), sizeof(int) * nb));
   HIP_TRY(up(h->pd, pd.data(), sizeof(double) * nb));
   HIP_TRY(up(h->qd, qd.data(), sizeof(double) * nb));
@@ -903,7 +936,7 @@ int acopf_create(const acopf_grid* grids, int32_t n_grids, const acopf_params* p
     return rc == ACOPF_EDEVICE && msg.find("hipMalloc") != std::string::npos ? ACOPF_ENOMEM : rc;
   }
   // cold state so that get_state is meaningful before the first solve
-  ColdArgs ca{h->ng, h->nl, h->m, h->gen_grid, h->br_grid, h->pmin, h->pmax, h->qmin, h->qmax,
+  ColdArgs ca{h->ng, h->nl, h->ne, h->m, h->ef, h->et, h->gen_grid, h->br_grid, h->pmin, h->pmax, h->qmin, h->qmax,
               h->adm, h->vlo_i, h->vhi_i, h->vlo_j, h->vhi_j, h->rate2, h->n6,
               h->u, h->v, h->z, h->y, h->lam, h->bx, h->ltil, h->rtil, h->P.al_rho0};
   hipLaunchKernelGGL(cold_kernel, dim3(blocks_for(h->ng + h->nl, 256)), dim3(256), 0, h->stream, ca);
@@ -940,7 +973,7 @@ int acopf_solve(acopf_handle h, int32_t mode, int32_t fixed_iters, acopf_result*
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t st = h->stream;
   if (mode == ACOPF_COLD) {
-    ColdArgs ca{h->ng, h->nl, h->m, h->gen_grid, h->br_grid, h->pmin, h->pmax, h->qmin,
+    ColdArgs ca{h->ng, h->nl, h->ne, h->m, h->ef, h->et, h->gen_grid, h->br_grid, h->pmin, h->pmax, h->qmin,
                 h->qmax, h->adm, h->vlo_i, h->vhi_i, h->vlo_j, h->vhi_j, h->rate2, h->n6,
                 h->u, h->v, h->z, h->y, h->lam, h->bx, h->ltil, h->rtil, h->P.al_rho0};
     hipLaunchKernelGGL(cold_kernel, dim3(blocks_for(h->ng + h->nl, 256)), dim3(256), 0, st, ca);
@@ -1049,15 +1082,24 @@ static int copy_state(acopf_s* h, int grid, int what, double* host, int64_t n, b
     HIP_TRY(pull(base, h->m, all));
     HIP_TRY(hipStreamSynchronize(st));
     for (int64_t k = 0; k < H.ng; ++k) {
-      double* p0 = &all[H.gen_off + k];
-      double* p1 = &all[ng + H.gen_off + k];
+      double* p0 = &all[H.gen_dev[k]];
+      double* p1 = &all[ng + H.gen_dev[k]];
       if (to_host) { host[2 * k] = *p0; host[2 * k + 1] = *p1; }
       else { *p0 = host[2 * k]; *p1 = host[2 * k + 1]; }
     }
+    const int64_t ne = h->ne;
     for (int64_t l = 0; l < H.nl; ++l) {
-      const int64_t d = H.br_dev[l];
+      const int64_t ef = H.end_f[l], et = H.end_t[l];
+      const int64_t pos[8] = {acopf_dev::end_coupling(ng, ne, 0, ef),
+                              acopf_dev::end_coupling(ng, ne, 1, ef),
+                              acopf_dev::end_coupling(ng, ne, 0, et),
+                              acopf_dev::end_coupling(ng, ne, 1, et),
+                              acopf_dev::end_coupling(ng, ne, 2, ef),
+                              acopf_dev::end_coupling(ng, ne, 3, ef),
+                              acopf_dev::end_coupling(ng, ne, 2, et),
+                              acopf_dev::end_coupling(ng, ne, 3, et)};
       for (int k = 0; k < 8; ++k) {
-        double* p = &all[2 * ng + k * nl + d];
+        double* p = &all[pos[k]];
         double* q = &host[2 * H.ng + 8 * l + k];
         if (to_host) *q = *p; else *p = *q;
       }

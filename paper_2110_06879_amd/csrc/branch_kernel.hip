@@ -42,17 +42,24 @@ constexpr double kShiftMin = 1e-3;
 constexpr int kMaxChol = 20;
 
 struct Counters {
-  uint64_t flops, trig;
+  uint32_t flops, trig;  // per branch solve: far below 2^32
   uint32_t tron_calls, tron_iters, n_fgh, n_f, cauchy, cg, chol, ps, al,
       conv, maxit, stall;
 };
 
-#define FL(n) (cnt.flops += (uint64_t)(n))
+#define FL(n) (cnt.flops += (uint32_t)(n))
 
-// Symmetric N x N matrix stored full (both triangles written).
+// Symmetric N x N matrix, or a lower-triangular factor, in packed lower
+// storage; (i, j) and (j, i) name the same element. Indices are compile-time
+// constants after unrolling, so the storage stays in registers.
 template <int N>
 struct Sym {
-  double a[N][N];
+  double t[N * (N + 1) / 2];
+  __device__ static constexpr int idx(int i, int j) {
+    return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
+  }
+  __device__ double& operator()(int i, int j) { return t[idx(i, j)]; }
+  __device__ double operator()(int i, int j) const { return t[idx(i, j)]; }
 };
 
 template <int N>
@@ -198,11 +205,9 @@ __device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
   FL(162);
   F = 0.0;
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    g[i] = 0.0;
+  for (int i = 0; i < N; ++i) g[i] = 0.0;
 #pragma unroll
-    for (int j = 0; j < N; ++j) H.a[i][j] = 0.0;
-  }
+  for (int q = 0; q < N * (N + 1) / 2; ++q) H.t[q] = 0.0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const double rk = B.rho(k);
@@ -214,7 +219,7 @@ __device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
 #pragma unroll
     for (int t = 0; t < 10; ++t) {
       const int p = kUP[t], q = kUQ[t];
-      H.a[p][q] = H.a[p][q] + rk * ga[k][p] * ga[k][q] + m * Ha[k][t];
+      H(p, q) = H(p, q) + rk * ga[k][p] * ga[k][q] + m * Ha[k][t];
     }
   }
   FL(272);
@@ -230,10 +235,10 @@ __device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
       if (k == 4 || k == 6) {
         const double gv = 2.0 * x[p];
         g[p] = g[p] + m * gv;
-        H.a[p][p] = H.a[p][p] + rk * gv * gv + m * 2.0;
+        H(p, p) = H(p, p) + rk * gv * gv + m * 2.0;
       } else {
         g[p] = g[p] + m;
-        H.a[p][p] = H.a[p][p] + rk;
+        H(p, p) = H(p, p) + rk;
       }
     }
     FL(60);
@@ -257,18 +262,14 @@ __device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
         const int p = kUP[t], q = kUQ[t];
         const double hc = 2.0 * (ga[kp][p] * ga[kp][q] + a[kp] * Ha[kp][t] +
                                  ga[kq][p] * ga[kq][q] + a[kq] * Ha[kq][t]);
-        H.a[p][q] = H.a[p][q] + B.rt * gc[p] * gc[q] + m * hc;
+        H(p, q) = H(p, q) + B.rt * gc[p] * gc[q] + m * hc;
       }
 #pragma unroll
-      for (int p = 0; p < 4; ++p) H.a[p][s] = H.a[p][s] + B.rt * gc[p];
-      H.a[s][s] = H.a[s][s] + B.rt;
+      for (int p = 0; p < 4; ++p) H(p, s) = H(p, s) + B.rt * gc[p];
+      H(s, s) = H(s, s) + B.rt;
     }
     FL(352);
   }
-#pragma unroll
-  for (int p = 0; p < N; ++p)
-#pragma unroll
-    for (int q = p + 1; q < N; ++q) H.a[q][p] = H.a[p][q];
   ++cnt.n_fgh;
 }
 
@@ -290,7 +291,7 @@ __device__ inline double model(const double* g, const Sym<N>& H, const double* s
     gs = gs + g[i] * s[i];
     double hi = 0.0;
 #pragma unroll
-    for (int j = 0; j < N; ++j) hi = hi + H.a[i][j] * s[j];
+    for (int j = 0; j < N; ++j) hi = hi + H(i, j) * s[j];
     sHs = sHs + s[i] * hi;
   }
   FL(2 * N * N + 4 * N + 2);
@@ -370,6 +371,7 @@ __device__ void cauchy(const double* x, const double* g, const Sym<N>& H,
   cauchy_trial<N>(x, g, lo, hi, alpha, w, s, cnt);
   ++cnt.cauchy;
   if (cauchy_ok<N>(g, H, s, delta, cnt)) {
+    // extrapolate while the conditions hold and the path still bends
     for (int t = 0; t < kMaxTrials; ++t) {
       if (alpha > brpt) break;
       const double a2 = alpha * kExtrap;
@@ -402,51 +404,50 @@ __device__ inline void precond(const Sym<N>& L, const double* D, const bool* fr,
   for (int i = 0; i < N; ++i) {
     double a = D[i] * r[i];
 #pragma unroll
-    for (int k = 0; k < i; ++k) a = a - L.a[i][k] * t[k];
-    t[i] = fr[i] ? a / L.a[i][i] : 0.0;
+    for (int k = 0; k < i; ++k) a = a - L(i, k) * t[k];
+    t[i] = fr[i] ? a / L(i, i) : 0.0;
   }
 #pragma unroll
   for (int i = N - 1; i >= 0; --i) {
     double a = t[i];
 #pragma unroll
-    for (int k = i + 1; k < N; ++k) a = a - L.a[k][i] * z[k];
-    z[i] = fr[i] ? a / L.a[i][i] : 0.0;
+    for (int k = i + 1; k < N; ++k) a = a - L(k, i) * z[k];
+    z[i] = fr[i] ? a / L(i, i) : 0.0;
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) z[i] = D[i] * z[i];
 }
 
-// Dense Cholesky of the masked matrix A (fixed rows/cols identity). Returns
-// false at the first non-positive free pivot; flops are counted as on the
-// compressed nf x nf matrix.
+// Dense Cholesky of the scaled, shifted free Hessian D H D + shift I (fixed
+// rows/columns act as identity), formed element by element as the
+// factorization needs it. Returns false at the first non-positive free pivot;
+// flops are counted as on the compressed nf x nf matrix.
 template <int N>
-__device__ inline bool cholesky(const Sym<N>& A, const bool* fr, int nf, Sym<N>& L,
-                                Counters& cnt) {
+__device__ inline bool cholesky(const Sym<N>& H, const double* D, double shift,
+                                const bool* fr, int nf, Sym<N>& L, Counters& cnt) {
 #pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int j = 0; j < N; ++j) L.a[i][j] = 0.0;
+  for (int q = 0; q < N * (N + 1) / 2; ++q) L.t[q] = 0.0;
   int jc = 0;  // compressed column index
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     if (!fr[j]) {
-      L.a[j][j] = 1.0;
+      L(j, j) = 1.0;
       continue;
     }
-    double d = A.a[j][j];
+    double d = D[j] * H(j, j) * D[j] + shift;
 #pragma unroll
-    for (int k = 0; k < j; ++k) d = d - L.a[j][k] * L.a[j][k];
+    for (int k = 0; k < j; ++k) d = d - L(j, k) * L(j, k);
     FL(2 * jc);
     if (!(d > 0.0)) return false;
     const double ljj = sqrt(d);
-    L.a[j][j] = ljj;
+    L(j, j) = ljj;
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {
       if (!fr[i]) continue;
-      double t = A.a[i][j];
+      double t = D[i] * H(i, j) * D[j];
 #pragma unroll
-      for (int k = 0; k < j; ++k) t = t - L.a[i][k] * L.a[j][k];
-      L.a[i][j] = t / ljj;
+      for (int k = 0; k < j; ++k) t = t - L(i, k) * L(j, k);
+      L(i, j) = t / ljj;
     }
     FL(1 + (nf - 1 - jc) * (2 * jc + 1));
     ++jc;
@@ -479,7 +480,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
     for (int i = 0; i < N; ++i) {
       double t = g[i];
 #pragma unroll
-      for (int j = 0; j < N; ++j) t = t + H.a[i][j] * s[j];
+      for (int j = 0; j < N; ++j) t = t + H(i, j) * s[j];
       gq[i] = t;
       r[i] = fr[i] ? -t : 0.0;
     }
@@ -493,22 +494,19 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
     for (int i = 0; i < N; ++i) {
       D[i] = 1.0;
       if (fr[i]) {
-        const double b = fabs(H.a[i][i]);
+        const double b = fabs(H(i, i));
         if (b > 0.0) {
           D[i] = 1.0 / sqrt(b);
           FL(2);
         }
       }
     }
-    Sym<N> A;
 #pragma unroll
     for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int j = 0; j < N; ++j)
-        A.a[i][j] = (fr[i] && fr[j]) ? D[i] * H.a[i][j] * D[j] : (i == j ? 1.0 : 0.0);
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-      if (fr[i]) mind = A.a[i][i] < mind ? A.a[i][i] : mind;
+      if (fr[i]) {
+        const double aii = D[i] * H(i, i) * D[i];
+        mind = aii < mind ? aii : mind;
+      }
     FL(2 * nf * nf);
     double shift = 0.0;
     if (!(mind > 0.0)) {
@@ -518,13 +516,9 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
     Sym<N> L;
     bool ok = false;
     for (int att = 0; att < kMaxChol; ++att) {
-      Sym<N> As = A;
-#pragma unroll
-      for (int i = 0; i < N; ++i)
-        if (fr[i]) As.a[i][i] = As.a[i][i] + shift;
       FL(nf);
       ++cnt.chol;
-      if (cholesky<N>(As, fr, nf, L, cnt)) {
+      if (cholesky<N>(H, D, shift, fr, nf, L, cnt)) {
         ok = true;
         break;
       }
@@ -536,7 +530,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       for (int i = 0; i < N; ++i) {
         D[i] = 1.0;
 #pragma unroll
-        for (int j = 0; j < N; ++j) L.a[i][j] = i == j ? 1.0 : 0.0;
+        for (int j = 0; j <= i; ++j) L(i, j) = i == j ? 1.0 : 0.0;
       }
     }
     // Steihaug PCG on min 1/2 d'Bd - r'd s.t. ||s + d|| <= delta
@@ -559,7 +553,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       for (int i = 0; i < N; ++i) {
         double t = 0.0;
 #pragma unroll
-        for (int j = 0; j < N; ++j) t = t + (fr[j] ? H.a[i][j] * p[j] : 0.0);
+        for (int j = 0; j < N; ++j) t = t + (fr[j] ? H(i, j) * p[j] : 0.0);
         Bp[i] = fr[i] ? t : 0.0;
       }
       const double pBp = dotN<N>(p, Bp);
@@ -770,13 +764,24 @@ __device__ void solve_branch(const BranchArgs& A, int64_t l, int grid, Counters&
       lo[5] = -A.rate2[l];
       hi[5] = 0.0;
     }
-    const int64_t cb = A.br_coupling_base;
+    // couplings k = 0..7: p_ij q_ij p_ji q_ji w_i th_i w_j th_j
+    int64_t cidx[8];
+    {
+      const int64_t ef = A.ef[l], et = A.et[l];
+      cidx[0] = end_coupling(A.ng, A.ne, 0, ef);
+      cidx[1] = end_coupling(A.ng, A.ne, 1, ef);
+      cidx[2] = end_coupling(A.ng, A.ne, 0, et);
+      cidx[3] = end_coupling(A.ng, A.ne, 1, et);
+      cidx[4] = end_coupling(A.ng, A.ne, 2, ef);
+      cidx[5] = end_coupling(A.ng, A.ne, 3, ef);
+      cidx[6] = end_coupling(A.ng, A.ne, 2, et);
+      cidx[7] = end_coupling(A.ng, A.ne, 3, et);
+    }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int64_t c = cb + k * nl + l;
-      B.vb[k] = A.v[c];
-      B.zc[k] = A.z[c];
-      B.yc[k] = A.y[c];
+      B.vb[k] = A.v[cidx[k]];
+      B.zc[k] = A.z[cidx[k]];
+      B.yc[k] = A.y[cidx[k]];
     }
     B.rpq = A.rho_pq;
     B.rva = A.rho_va;
@@ -821,7 +826,7 @@ __device__ void solve_branch(const BranchArgs& A, int64_t l, int grid, Counters&
     double a[8], aux[4];
     values<N>(B, x, a, aux, cnt);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) A.u[cb + k * nl + l] = a[k];
+    for (int k = 0; k < 8; ++k) A.u[cidx[k]] = a[k];
 #pragma unroll
     for (int i = 0; i < N; ++i) A.bx[i * nl + l] = x[i];
     if (failures) atomicAdd(&A.failures[grid], failures);
@@ -841,7 +846,12 @@ __device__ inline void solve_generator(const BranchArgs& A, int64_t g) {
   A.u[kq] = fmax(A.qmin[g], fmin(A.qmax[g], xq));
 }
 
-__global__ __launch_bounds__(64) void xstep_kernel(BranchArgs A, int64_t n6, int b6, int b4) {
+#ifndef ACOPF_XSTEP_WAVES_PER_EU
+#define ACOPF_XSTEP_WAVES_PER_EU 1
+#endif
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ACOPF_XSTEP_WAVES_PER_EU)))
+void xstep_kernel(BranchArgs A, int64_t n6, int b6, int b4) {
   Counters cnt = {};
   bool active = false;
   const int b = blockIdx.x;
@@ -863,7 +873,7 @@ __global__ __launch_bounds__(64) void xstep_kernel(BranchArgs A, int64_t n6, int
     return;  // whole block is generators: no branch counters
   }
   // wave-level reduction of the counters, one atomic per counter per wavefront
-  uint64_t v[15] = {active ? 1ull : 0ull, cnt.flops, cnt.trig, cnt.tron_calls,
+  uint64_t v[15] = {active ? 1ull : 0ull, (uint64_t)cnt.flops, (uint64_t)cnt.trig, cnt.tron_calls,
                     cnt.tron_iters, cnt.n_fgh, cnt.n_f, cnt.cauchy, cnt.cg, cnt.chol,
                     cnt.ps, cnt.al, cnt.conv, cnt.maxit, cnt.stall};
 #pragma unroll

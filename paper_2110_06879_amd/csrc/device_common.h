@@ -18,9 +18,19 @@ struct GridCtl {
   int numerical, pad0, pad1, pad2;
 };
 
+// Coupling vectors (u, v, z, y, lambda) are laid out bus-major: generator
+// p [n_gen], generator q [n_gen] (generators sorted by bus), then for the
+// 2 n_branch branch ends in bus CSR order four blocks p, q, w, theta of
+// 2 n_branch each. A branch finds its eight couplings through the positions
+// ef (from end) and et (to end) of its two ends.
+__host__ __device__ inline int64_t end_coupling(int64_t ng, int64_t ne, int kind, int64_t e) {
+  return 2 * ng + (int64_t)kind * ne + e;  // kind 0 p, 1 q, 2 w, 3 theta
+}
+
 struct BranchArgs {
   int64_t nl;                // branches in the handle
-  int64_t br_coupling_base;  // offset of branch couplings (2 n_gen)
+  int64_t ne;                // branch ends, 2 nl
+  const int *ef, *et;        // [nl] end positions of each branch
   const int* br_grid;
   const GridCtl* ctl;
   const double* adm;         // [8][nl] gii bii gij bij gji bji gjj bjj
