@@ -125,6 +125,16 @@ typedef struct {
   double seconds;            /* wall time of the solve call                 */
 } acopf_result;
 
+/* Launch shape of the iteration (see acopf_set_tuning / acopf_autotune). */
+typedef struct {
+  int32_t xstep_block; /* threads per block of the branch/generator kernel:
+                          64, 128 or 256 (one lane per branch)              */
+  int32_t bus_block;   /* threads per block of the bus kernel: 64..1024,
+                          a multiple of 64                                  */
+  int32_t chunk;       /* inner iterations between control readbacks, 1..64 */
+  int32_t use_graph;   /* 1: replay each chunk as one captured hipGraph     */
+} acopf_tuning;
+
 typedef struct acopf_s* acopf_handle;
 
 /* Fill *p with the library defaults. */
@@ -153,6 +163,39 @@ int acopf_solve(acopf_handle h, int32_t mode, int32_t fixed_iters,
  * Errors: EINVAL (index, NaN/Inf), EDEVICE. */
 int acopf_update_loads(acopf_handle h, int32_t grid, const double* pd,
                        const double* qd);
+
+/* Continuous batching. acopf_start begins a solve of one grid without
+ * touching the others (mode and fixed_iters as in acopf_solve); acopf_run
+ * iterates every running grid in the same launches until at least one of
+ * them finishes or max_iters inner iterations have run, and reports how many
+ * are still running; acopf_poll reads one grid's state and, once finished,
+ * its result (seconds = host time from start to the readback that saw it
+ * finish). Grids that are not running cost nothing in the launches.
+ * Errors: EINVAL, ESTATE (grid already running, or WARM/CONTINUE on a grid
+ * never solved), EDEVICE. */
+int acopf_start(acopf_handle h, int32_t grid, int32_t mode, int32_t fixed_iters);
+int acopf_run(acopf_handle h, int32_t max_iters, int32_t* running);
+int acopf_poll(acopf_handle h, int32_t grid, int32_t* is_running, acopf_result* out);
+
+/* Device-side copy of the complete state of grid src into grid dst (ADMM
+ * vectors, branch state, loads, control block). Both must hold the same grid
+ * data (same arrays passed to acopf_create). Errors: EINVAL, ESTATE (dst
+ * running), EDEVICE. */
+int acopf_copy_grid(acopf_handle h, int32_t src, int32_t dst);
+
+/* Device-side snapshot of the whole handle's state: what = 0 saves, 1
+ * restores the last save (first save allocates a second copy of the state).
+ * Errors: EINVAL, ESTATE (restore without save), ENOMEM, EDEVICE. */
+int acopf_snapshot(acopf_handle h, int32_t what);
+
+/* Launch shape: set explicitly, read back, or pick by timing `iters` inner
+ * iterations of every candidate from the current state (the state is saved
+ * before and restored after, so tuning leaves the solve unchanged).
+ * Candidates: xstep_block {64, 128, 256} x bus_block {64, 128, 256, 512} x
+ * chunk {8, 16, 32}, graphs on. Errors: EINVAL, ENOMEM, EDEVICE. */
+int acopf_set_tuning(acopf_handle h, const acopf_tuning* t);
+int acopf_get_tuning(acopf_handle h, acopf_tuning* t);
+int acopf_autotune(acopf_handle h, int32_t iters, acopf_tuning* out);
 
 /* Copy one state vector of grid `grid` to the host buffer out[n] (n must
  * equal the size listed with the ACOPF_* `what` codes, in canonical order).

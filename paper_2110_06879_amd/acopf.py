@@ -30,7 +30,9 @@ SCALAR_NAMES = ("beta", "znorm_prev", "r_pri", "r_dual", "r_z", "outer",
                 "inner_total", "inner_in_outer", "status")
 EXPORTS = ("acopf_default_params", "acopf_create", "acopf_solve", "acopf_update_loads",
            "acopf_get_state", "acopf_set_state", "acopf_get_sizes", "acopf_set_profiling",
-           "acopf_get_timing", "acopf_destroy", "acopf_last_error")
+           "acopf_get_timing", "acopf_destroy", "acopf_last_error", "acopf_start",
+           "acopf_run", "acopf_poll", "acopf_copy_grid", "acopf_snapshot",
+           "acopf_set_tuning", "acopf_get_tuning", "acopf_autotune")
 
 
 class AcopfError(RuntimeError):
@@ -58,6 +60,14 @@ class _Params(C.Structure):
         ("al_rho0", C.c_double), ("al_rho_growth", C.c_double), ("al_rho_max", C.c_double),
         ("al_tol", C.c_double), ("al_shrink", C.c_double), ("al_maxit", C.c_int32),
     ]
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("xstep_block", C.c_int32), ("bus_block", C.c_int32),
+                ("chunk", C.c_int32), ("use_graph", C.c_int32)]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
 class _Result(C.Structure):
@@ -126,12 +136,22 @@ def load(path: str | None = None) -> C.CDLL:
     lib.acopf_get_sizes.argtypes = [vp, i32, C.POINTER(C.c_int64)]
     lib.acopf_get_timing.argtypes = [vp, dp]
     lib.acopf_set_profiling.argtypes = [vp, i32]
+    lib.acopf_start.argtypes = [vp, i32, i32, i32]
+    lib.acopf_run.argtypes = [vp, i32, C.POINTER(i32)]
+    lib.acopf_poll.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(_Result)]
+    lib.acopf_copy_grid.argtypes = [vp, i32, i32]
+    lib.acopf_snapshot.argtypes = [vp, i32]
+    lib.acopf_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
+    lib.acopf_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
+    lib.acopf_autotune.argtypes = [vp, i32, C.POINTER(_Tuning)]
     lib.acopf_destroy.argtypes = [vp]
     lib.acopf_destroy.restype = None
     lib.acopf_last_error.restype = C.c_char_p
     for name in ("acopf_create", "acopf_solve", "acopf_update_loads", "acopf_get_state",
                  "acopf_set_state", "acopf_get_sizes", "acopf_get_timing",
-                 "acopf_set_profiling"):
+                 "acopf_set_profiling", "acopf_start", "acopf_run", "acopf_poll",
+                 "acopf_copy_grid", "acopf_snapshot", "acopf_set_tuning",
+                 "acopf_get_tuning", "acopf_autotune"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -241,6 +261,47 @@ class Solver:
         out = np.empty(16)
         self._check(self.lib.acopf_get_state(self.h, 0, STATS, _dp(out), 16))
         return {n: int(v) for n, v in zip(STATS_NAMES, out)}
+
+    # continuous batching -------------------------------------------------
+    def start(self, grid: int, mode: int = WARM, fixed_iters: int = 0):
+        self._check(self.lib.acopf_start(self.h, grid, mode, fixed_iters))
+
+    def run(self, max_iters: int = 1 << 20) -> int:
+        n = C.c_int32()
+        self._check(self.lib.acopf_run(self.h, max_iters, C.byref(n)))
+        return int(n.value)
+
+    def poll(self, grid: int):
+        """(is_running, result dict)."""
+        r = _Result()
+        n = C.c_int32()
+        self._check(self.lib.acopf_poll(self.h, grid, C.byref(n), C.byref(r)))
+        return bool(n.value), r.as_dict()
+
+    def is_running(self, grid: int) -> bool:
+        n = C.c_int32()
+        self._check(self.lib.acopf_poll(self.h, grid, C.byref(n), None))
+        return bool(n.value)
+
+    def copy_grid(self, src: int, dst: int):
+        self._check(self.lib.acopf_copy_grid(self.h, src, dst))
+
+    def snapshot(self, restore: bool = False):
+        self._check(self.lib.acopf_snapshot(self.h, 1 if restore else 0))
+
+    def set_tuning(self, **kw):
+        t = _Tuning(**{**self.tuning(), **kw})
+        self._check(self.lib.acopf_set_tuning(self.h, C.byref(t)))
+
+    def tuning(self) -> dict:
+        t = _Tuning()
+        self._check(self.lib.acopf_get_tuning(self.h, C.byref(t)))
+        return t.as_dict()
+
+    def autotune(self, iters: int = 32) -> dict:
+        t = _Tuning()
+        self._check(self.lib.acopf_autotune(self.h, iters, C.byref(t)))
+        return t.as_dict()
 
     def set_profiling(self, on: bool = True):
         self._check(self.lib.acopf_set_profiling(self.h, int(on)))

@@ -1,0 +1,99 @@
+"""Batched and served workloads on one GPU, each against the plain
+one-grid-per-launch method on the same device and inputs.
+
+  python -m paper_2110_06879_amd.bench_systems --batch   # 64 uneven grids, cold, to 1e-4
+  python -m paper_2110_06879_amd.bench_systems --serve   # Poisson tracking requests
+
+Prints one JSON line per experiment.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import acopf as A
+from . import serve as S
+from .gridgen import batch_grids, serving_grids
+
+
+def batch(n_grids: int, tune_iters: int) -> dict:
+    grids = batch_grids(n_grids)
+    sizes = [g.n_bus for g in grids]
+    params = A.Params()
+    # batched: every grid in one handle, one set of launches per iteration
+    s = A.Solver(grids, params)
+    tuning = s.autotune(tune_iters) if tune_iters > 0 else s.tuning()
+    t0 = time.perf_counter()
+    res = s.solve(A.COLD)
+    tb = time.perf_counter() - t0
+    s.close()
+    conv_b = sum(1 for r in res if r["status"] == A.CONVERGED)
+    solves_b = sum(r["inner_iters"] * g.n_branch for r, g in zip(res, grids))
+    worst_b = max(max(r["r_pri"], r["r_dual"], r["r_z"]) for r in res)
+    # plain: one handle and one launch sequence per grid, one grid at a time
+    tp = 0.0
+    solves_p = 0
+    conv_p = 0
+    worst_p = 0.0
+    for g in grids:
+        with A.Solver(g, params) as sp:
+            t1 = time.perf_counter()
+            r = sp.solve(A.COLD)[0]
+            tp += time.perf_counter() - t1
+            solves_p += r["inner_iters"] * g.n_branch
+            conv_p += r["status"] == A.CONVERGED
+            worst_p = max(worst_p, r["r_pri"], r["r_dual"], r["r_z"])
+    return {"experiment": "batched", "grids": n_grids, "total_buses": int(sum(sizes)),
+            "total_branches": int(sum(g.n_branch for g in grids)),
+            "min_buses": int(min(sizes)), "max_buses": int(max(sizes)), "tuning": tuning,
+            "batched": {"seconds": tb, "branch_solves_per_s": solves_b / tb,
+                        "converged": conv_b, "worst_residual": worst_b,
+                        "max_iters": int(max(r["inner_iters"] for r in res))},
+            "one_grid_per_launch": {"seconds": tp, "branch_solves_per_s": solves_p / tp,
+                                    "converged": conv_p, "worst_residual": worst_p},
+            "speedup": tp / tb}
+
+
+def serve(duration: float, rate: float, with_70k: bool, baseline: bool) -> dict:
+    grids = serving_grids(with_70k=with_70k)
+    reqs = S.poisson_requests(grids, rate, duration)
+    srv = S.TrackingServer(grids)
+    tuning = srv.solver.tuning()
+    out = srv.serve(reqs, realtime=True)
+    slots = srv.slots_per_grid
+    srv.close()
+    out.pop("done")
+    res = {"experiment": "served", "grids": len(grids),
+           "buses": [g.n_bus for g in grids], "rate_per_s": rate, "duration_s": duration,
+           "slots_per_grid": slots, "tuning": tuning, "continuous_batching": out}
+    if baseline:
+        reqs2 = S.poisson_requests(grids, rate, duration)
+        b = S.serve_one_at_a_time(grids, reqs2, realtime=True)
+        res["one_request_at_a_time"] = b
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--batch", action="store_true")
+    ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--grids", type=int, default=64)
+    ap.add_argument("--tune-iters", type=int, default=16)
+    ap.add_argument("--duration", type=float, default=10.0)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--no-70k", action="store_true")
+    ap.add_argument("--no-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.batch:
+        print(json.dumps(batch(args.grids, args.tune_iters)), flush=True)
+    if args.serve:
+        print(json.dumps(serve(args.duration, args.rate, not args.no_70k,
+                               not args.no_baseline)), flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -96,7 +96,7 @@ __device__ inline unsigned long long dbits(double a) {
 // balance rows of eqs. (pg)-(qg); closed form through the 2x2 matrix
 // M = A Q^-1 A'. Then z (eq. qp-bound with no bounds) and y for every
 // coupling of the bus, and their residual maxima.
-__global__ __launch_bounds__(256) void bus_kernel(BusArgs A) {
+__global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double rp = 0.0, rd = 0.0, rz = 0.0;
   int grid = -1;
@@ -211,7 +211,7 @@ struct CtlArgs {
   unsigned long long* rmax;
   double* hist;  // [G][kHistCap][6]
   double eps_pri, eps_dual, eps_z, beta_gamma, beta_omega, beta_max;
-  int max_outer, max_inner, fixed;
+  int max_outer, max_inner;
 };
 
 // Control of Algorithm 1 per grid: inner test (r_pri, r_dual), overall test
@@ -249,7 +249,8 @@ __global__ void ctl_kernel(CtlArgs A) {
     return;
   }
   const bool inner_ok = rp <= A.eps_pri && rd <= A.eps_dual;
-  if (!A.fixed && inner_ok && rz <= A.eps_z) {
+  const bool fixed = c.fixed_mode != 0;
+  if (!fixed && inner_ok && rz <= A.eps_z) {
     c.status = ACOPF_CONVERGED;
     c.done = 1;
     return;
@@ -264,12 +265,12 @@ __global__ void ctl_kernel(CtlArgs A) {
     c.znorm_prev = rz;
     c.outer += 1;
     c.inner_in_outer = 0;
-    if (!A.fixed && c.outer >= A.max_outer) {
+    if (!fixed && c.outer >= A.max_outer) {
       c.status = ACOPF_MAX_ITER;
       c.done = 1;
     }
   }
-  if (A.fixed && c.inner_total >= c.fixed_target) {
+  if (fixed && c.inner_total >= c.fixed_target) {
     c.status = ACOPF_MAX_ITER;
     c.done = 1;
   }
@@ -302,6 +303,7 @@ __global__ __launch_bounds__(256) void outer_kernel(OuterArgs A) {
 }
 
 struct ColdArgs {
+  int only;  // grid to initialize, or -1 for all
   int64_t ng, nl, ne, m;
   const int *ef, *et;
   const int *gen_grid, *br_grid;
@@ -326,12 +328,14 @@ __global__ __launch_bounds__(256) void cold_kernel(ColdArgs A) {
     A.lam[k] = 0.0;
   };
   if (t < A.ng) {
+    if (A.only >= 0 && A.gen_grid[t] != A.only) return;
     setk(t, 0.5 * (A.pmin[t] + A.pmax[t]));
     setk(A.ng + t, 0.5 * (A.qmin[t] + A.qmax[t]));
     return;
   }
   const int64_t l = t - A.ng;
   if (l >= A.nl) return;
+  if (A.only >= 0 && A.br_grid[l] != A.only) return;
   const int64_t nl = A.nl;
   const double vi = 0.5 * (A.vlo_i[l] + A.vhi_i[l]);
   const double vj = 0.5 * (A.vlo_j[l] + A.vhi_j[l]);
@@ -370,11 +374,12 @@ __global__ __launch_bounds__(256) void cold_kernel(ColdArgs A) {
   A.rtil[l] = A.al_rho0;
 }
 
-// Reset of the per-grid control words at the start of a solve.
-__global__ void ctl_start_kernel(GridCtl* ctl, int G, int mode, int fixed,
+// Reset of the per-grid control words at the start of a solve of grid `only`
+// (all grids when only < 0).
+__global__ void ctl_start_kernel(GridCtl* ctl, int G, int only, int mode, int fixed,
                                  double beta0, unsigned long long* rmax, int* failures) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= G) return;
+  if (g >= G || (only >= 0 && g != only)) return;
   GridCtl& c = ctl[g];
   if (mode != ACOPF_CONTINUE) {
     c.beta = beta0;
@@ -388,11 +393,21 @@ __global__ void ctl_start_kernel(GridCtl* ctl, int G, int mode, int fixed,
   c.done = 0;
   c.do_outer = 0;
   c.numerical = 0;
+  c.fixed_mode = fixed > 0 ? 1 : 0;
   c.fixed_target = fixed > 0 ? c.inner_total + fixed : 0x7fffffff;
   failures[g] = 0;
   rmax[3 * g + 0] = 0;
   rmax[3 * g + 1] = 0;
   rmax[3 * g + 2] = 0;
+}
+
+// Marks every grid idle (done) without touching its state.
+__global__ void ctl_idle_kernel(GridCtl* ctl, int G) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < G) {
+    ctl[g].done = 1;
+    ctl[g].do_outer = 0;
+  }
 }
 
 // Objective sum_g c2 P^2 + c1 P + c0 with P = base p_g (Sec. IV-A), one block
@@ -428,6 +443,8 @@ struct HostGrid {
   std::vector<int64_t> br_dev;   // input branch -> device branch index
   std::vector<int64_t> gen_dev;  // input generator -> device generator index
   std::vector<int64_t> end_f, end_t;  // input branch -> device end positions
+  int64_t e0 = 0, e1 = 0;             // device end range
+  int64_t r6b = 0, r6e = 0, r4b = 0, r4e = 0;  // device branch ranges per class
   int ref;
 };
 
@@ -481,6 +498,14 @@ struct acopf_s {
   double *base_d, *obj_d;
   bool solved = false;
   bool profile = false;
+  acopf_tuning tune{64, 256, 16, 1};
+  hipGraphExec_t graph = nullptr;
+  int graph_chunk = 0;
+  std::vector<double> t_start;         // host clock at each grid's start
+  std::vector<double> t_end;           // host clock when it finished
+  std::vector<char> running;           // started and not yet seen finished
+  std::vector<char> started_once;
+  std::vector<void*> snap;             // device snapshot buffers (lazy)
   std::vector<hipEvent_t> ev;
   double t_ms[kTimed] = {0, 0, 0, 0};
   int64_t t_iters = 0;
@@ -534,8 +559,13 @@ BranchArgs branch_args(const acopf_s* h) {
 
 int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
 // Launch one inner iteration; with profiling, events bracket each launch.
-void launch_iteration(acopf_s* h, int fixed, int slot) {
+void launch_iteration(acopf_s* h, int slot) {
   hipStream_t s = h->stream;
   hipEvent_t* E = h->profile ? &h->ev[(size_t)slot * kEvPerIter] : nullptr;
   auto mark = [&](int k) {
@@ -543,16 +573,17 @@ void launch_iteration(acopf_s* h, int fixed, int slot) {
   };
   BranchArgs ba = branch_args(h);
   mark(0);
-  acopf_dev::launch_xstep(ba, h->n6, s);
+  acopf_dev::launch_xstep(ba, h->n6, h->tune.xstep_block, s);
   mark(1);
   BusArgs bu{h->nb, h->ng, h->ne, h->bus_grid, h->ctl, h->gptr, h->eptr,
              h->pd, h->qd, h->gs, h->bs, h->isref, h->u, h->lam, h->v, h->z, h->y,
              h->P.rho_pq, h->P.rho_va, h->rmax};
-  hipLaunchKernelGGL(bus_kernel, dim3(blocks_for(h->nb, 256)), dim3(256), 0, s, bu);
+  const int bb = h->tune.bus_block;
+  hipLaunchKernelGGL(bus_kernel, dim3(blocks_for(h->nb, bb)), dim3(bb), 0, s, bu);
   mark(2);
   CtlArgs ca{h->G, h->ctl, h->rmax, h->hist, h->P.eps_pri, h->P.eps_dual, h->P.eps_z,
              h->P.beta_gamma, h->P.beta_omega, h->P.beta_max, h->P.max_outer,
-             h->P.max_inner, fixed};
+             h->P.max_inner};
   hipLaunchKernelGGL(ctl_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, s, ca);
   mark(3);
   OuterArgs oa{h->m, h->ng, h->ne, h->gen_grid, h->end_grid, h->ctl, h->z, h->lam,
@@ -664,6 +695,8 @@ void acopf_destroy(acopf_handle h) {
   if (h->device >= 0) (void)hipSetDevice(h->device);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  for (void* p : h->snap) (void)hipFree(p);
   h->buf.release();
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -774,17 +807,31 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
     std::sort(r6.begin(), r6.end());
     std::sort(r4.begin(), r4.end());
     int64_t d = 0;
-    for (auto* lst : {&r6, &r4})
-      for (auto& it : *lst) {
+    for (int cls = 0; cls < 2; ++cls) {
+      auto& lst = cls == 0 ? r6 : r4;
+      for (int g = 0; g < n_grids; ++g) {
+        HostGrid& H = h->grids[g];
+        (cls == 0 ? H.r6b : H.r4b) = d;
+        (cls == 0 ? H.r6e : H.r4e) = d;
+      }
+      for (auto& it : lst) {
         const int g = it.second.first, l = it.second.second;
         HostGrid& H = h->grids[g];
         if (H.br_dev.empty()) H.br_dev.assign(H.nl, -1);
+        if ((cls == 0 ? H.r6e : H.r4e) == (cls == 0 ? H.r6b : H.r4b)) (cls == 0 ? H.r6b : H.r4b) = d;
         H.br_dev[l] = d;
         dev_grid[d] = g;
         ef[d] = (int)H.end_f[l];
         et[d] = (int)H.end_t[l];
         ++d;
+        (cls == 0 ? H.r6e : H.r4e) = d;
       }
+    }
+    for (int g = 0; g < n_grids; ++g) {
+      HostGrid& H = h->grids[g];
+      H.e0 = eptr[H.bus_off];
+      H.e1 = eptr[H.bus_off + H.nb];
+    }
   }
   // ---- host arrays in device order
   std::vector<int> gen_grid(ng), bus_grid(nb), isref(nb, 0);
@@ -936,12 +983,18 @@ int acopf_create(const acopf_grid* grids, int32_t n_grids, const acopf_params* p
     return rc == ACOPF_EDEVICE && msg.find("hipMalloc") != std::string::npos ? ACOPF_ENOMEM : rc;
   }
   // cold state so that get_state is meaningful before the first solve
-  ColdArgs ca{h->ng, h->nl, h->ne, h->m, h->ef, h->et, h->gen_grid, h->br_grid, h->pmin, h->pmax, h->qmin, h->qmax,
+  ColdArgs ca{-1, h->ng, h->nl, h->ne, h->m, h->ef, h->et, h->gen_grid, h->br_grid, h->pmin, h->pmax, h->qmin, h->qmax,
               h->adm, h->vlo_i, h->vhi_i, h->vlo_j, h->vhi_j, h->rate2, h->n6,
               h->u, h->v, h->z, h->y, h->lam, h->bx, h->ltil, h->rtil, h->P.al_rho0};
   hipLaunchKernelGGL(cold_kernel, dim3(blocks_for(h->ng + h->nl, 256)), dim3(256), 0, h->stream, ca);
   hipLaunchKernelGGL(ctl_start_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, h->stream,
-                     h->ctl, h->G, (int)ACOPF_COLD, 0, h->P.beta0, h->rmax, h->failures);
+                     h->ctl, h->G, -1, (int)ACOPF_COLD, 0, h->P.beta0, h->rmax, h->failures);
+  hipLaunchKernelGGL(ctl_idle_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, h->stream,
+                     h->ctl, h->G);
+  h->t_start.assign(h->G, 0.0);
+  h->t_end.assign(h->G, 0.0);
+  h->running.assign(h->G, 0);
+  h->started_once.assign(h->G, 0);
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     acopf_destroy(h);
@@ -962,6 +1015,114 @@ static void accumulate_timing(acopf_s* h, int used) {
   h->t_iters += used;
 }
 
+static void drop_graph(acopf_s* h) {
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  h->graph = nullptr;
+  h->graph_chunk = 0;
+}
+
+// k inner iterations: one replay of the captured chunk when k equals the
+// tuned chunk and timing is off, else plain launches.
+static int launch_chunk(acopf_s* h, int k) {
+  if (!h->profile && h->tune.use_graph && k == h->tune.chunk) {
+    if (!h->graph || h->graph_chunk != k) {
+      drop_graph(h);
+      hipGraph_t g = nullptr;
+      HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      for (int c = 0; c < k; ++c) launch_iteration(h, c);
+      HIP_TRY(hipStreamEndCapture(h->stream, &g));
+      hipError_t e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        h->graph = nullptr;
+        return fail(ACOPF_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      }
+      h->graph_chunk = k;
+    }
+    HIP_TRY(hipGraphLaunch(h->graph, h->stream));
+    return ACOPF_OK;
+  }
+  for (int c = 0; c < k; ++c) launch_iteration(h, c);
+  HIP_TRY(hipGetLastError());
+  return ACOPF_OK;
+}
+
+static int start_impl(acopf_s* h, int grid, int mode, int fixed_iters) {
+  hipStream_t st = h->stream;
+  if (mode == ACOPF_COLD) {
+    ColdArgs ca{grid, h->ng, h->nl, h->ne, h->m, h->ef, h->et, h->gen_grid, h->br_grid,
+                h->pmin, h->pmax, h->qmin, h->qmax, h->adm, h->vlo_i, h->vhi_i, h->vlo_j,
+                h->vhi_j, h->rate2, h->n6, h->u, h->v, h->z, h->y, h->lam, h->bx, h->ltil,
+                h->rtil, h->P.al_rho0};
+    hipLaunchKernelGGL(cold_kernel, dim3(blocks_for(h->ng + h->nl, 256)), dim3(256), 0, st, ca);
+  }
+  hipLaunchKernelGGL(ctl_start_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, st, h->ctl,
+                     h->G, grid, mode, fixed_iters, h->P.beta0, h->rmax, h->failures);
+  HIP_TRY(hipGetLastError());
+  const double t = now_s();
+  for (int g = 0; g < h->G; ++g)
+    if (grid < 0 || g == grid) {
+      h->running[g] = 1;
+      h->started_once[g] = 1;
+      h->t_start[g] = t;
+    }
+  return ACOPF_OK;
+}
+
+// Iterate until some running grid finishes (stop_on_first) or all have
+// finished, or max_iters iterations ran. Returns the iterations issued.
+static int run_impl(acopf_s* h, int64_t max_iters, bool stop_on_first, int64_t* issued_out) {
+  int64_t issued = 0;
+  while (issued < max_iters) {
+    int nrun = 0;
+    for (int g = 0; g < h->G; ++g) nrun += h->running[g];
+    if (nrun == 0) break;
+    const int k = (int)std::min<int64_t>(h->tune.chunk, max_iters - issued);
+    int rc = launch_chunk(h, k);
+    if (rc) return rc;
+    issued += k;
+    HIP_TRY(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(GridCtl) * h->G, hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (h->profile) accumulate_timing(h, k);
+    const double t = now_s();
+    bool finished_one = false;
+    for (int g = 0; g < h->G; ++g)
+      if (h->running[g] && h->h_ctl[g].done) {
+        h->running[g] = 0;
+        h->t_end[g] = t;
+        finished_one = true;
+      }
+    if (stop_on_first && finished_one) break;
+  }
+  if (issued_out) *issued_out = issued;
+  return ACOPF_OK;
+}
+
+static int result_impl(acopf_s* h, int g, acopf_result* r) {
+  hipStream_t st = h->stream;
+  hipLaunchKernelGGL(objective_kernel, dim3(h->G), dim3(256), 0, st, h->gen_off_d, h->c2,
+                     h->c1, h->c0, h->u, h->base_d, h->obj_d);
+  double obj = 0.0;
+  int fails = 0;
+  GridCtl c;
+  HIP_TRY(hipMemcpyAsync(&obj, h->obj_d + g, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&fails, h->failures + g, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&c, h->ctl + g, sizeof(GridCtl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  r->status = c.done ? c.status : ACOPF_MAX_ITER;
+  r->inner_iters = c.inner_total;
+  r->outer_iters = c.outer;
+  r->branch_failures = fails;
+  r->objective = obj;
+  r->r_pri = c.r_pri;
+  r->r_dual = c.r_dual;
+  r->r_z = c.r_z;
+  r->beta = c.beta;
+  r->seconds = (h->running[g] ? now_s() : h->t_end[g]) - h->t_start[g];
+  return ACOPF_OK;
+}
+
 int acopf_solve(acopf_handle h, int32_t mode, int32_t fixed_iters, acopf_result* results) {
   if (!h) return fail(ACOPF_EINVAL, "null handle");
   if (mode != ACOPF_COLD && mode != ACOPF_WARM && mode != ACOPF_CONTINUE)
@@ -970,17 +1131,8 @@ int acopf_solve(acopf_handle h, int32_t mode, int32_t fixed_iters, acopf_result*
   if (mode != ACOPF_COLD && !h->solved)
     return fail(ACOPF_ESTATE, "warm or continued solve before any solve");
   HIP_TRY(hipSetDevice(h->device));
-  const auto t0 = std::chrono::steady_clock::now();
-  hipStream_t st = h->stream;
-  if (mode == ACOPF_COLD) {
-    ColdArgs ca{h->ng, h->nl, h->ne, h->m, h->ef, h->et, h->gen_grid, h->br_grid, h->pmin, h->pmax, h->qmin,
-                h->qmax, h->adm, h->vlo_i, h->vhi_i, h->vlo_j, h->vhi_j, h->rate2, h->n6,
-                h->u, h->v, h->z, h->y, h->lam, h->bx, h->ltil, h->rtil, h->P.al_rho0};
-    hipLaunchKernelGGL(cold_kernel, dim3(blocks_for(h->ng + h->nl, 256)), dim3(256), 0, st, ca);
-  }
-  hipLaunchKernelGGL(ctl_start_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, st, h->ctl,
-                     h->G, (int)mode, (int)fixed_iters, h->P.beta0, h->rmax, h->failures);
-  HIP_TRY(hipGetLastError());
+  int rc = start_impl(h, -1, mode, fixed_iters);
+  if (rc) return rc;
   if (h->profile) {
     for (double& t : h->t_ms) t = 0.0;
     h->t_iters = 0;
@@ -988,46 +1140,51 @@ int acopf_solve(acopf_handle h, int32_t mode, int32_t fixed_iters, acopf_result*
   const int64_t cap = fixed_iters > 0
                           ? fixed_iters
                           : (int64_t)h->P.max_outer * h->P.max_inner + 1;
-  int64_t issued = 0;
-  bool all_done = false;
-  while (!all_done && issued < cap) {
-    const int k = (int)std::min<int64_t>(kChunk, cap - issued);
-    for (int c = 0; c < k; ++c) launch_iteration(h, fixed_iters, c);
-    issued += k;
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(GridCtl) * h->G, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (h->profile) accumulate_timing(h, k);
-    all_done = true;
-    for (int g = 0; g < h->G; ++g) all_done = all_done && h->h_ctl[g].done;
-  }
+  rc = run_impl(h, cap, false, nullptr);
+  if (rc) return rc;
   h->solved = true;
-  // objective and failure counts
-  hipLaunchKernelGGL(objective_kernel, dim3(h->G), dim3(256), 0, st, h->gen_off_d, h->c2,
-                     h->c1, h->c0, h->u, h->base_d, h->obj_d);
-  std::vector<double> obj(h->G);
-  std::vector<int> fails(h->G);
-  HIP_TRY(hipMemcpyAsync(obj.data(), h->obj_d, sizeof(double) * h->G, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(fails.data(), h->failures, sizeof(int) * h->G, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(GridCtl) * h->G, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  const double secs =
-      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  if (results) {
+  if (results)
     for (int g = 0; g < h->G; ++g) {
-      const GridCtl& c = h->h_ctl[g];
-      acopf_result& r = results[g];
-      r.status = c.done ? c.status : ACOPF_MAX_ITER;
-      r.inner_iters = c.inner_total;
-      r.outer_iters = c.outer;
-      r.branch_failures = fails[g];
-      r.objective = obj[g];
-      r.r_pri = c.r_pri;
-      r.r_dual = c.r_dual;
-      r.r_z = c.r_z;
-      r.beta = c.beta;
-      r.seconds = secs;
+      rc = result_impl(h, g, &results[g]);
+      if (rc) return rc;
     }
+  return ACOPF_OK;
+}
+
+int acopf_start(acopf_handle h, int32_t grid, int32_t mode, int32_t fixed_iters) {
+  if (!h) return fail(ACOPF_EINVAL, "null handle");
+  if (grid < 0 || grid >= h->G) return fail(ACOPF_EINVAL, "grid index out of range");
+  if (mode != ACOPF_COLD && mode != ACOPF_WARM && mode != ACOPF_CONTINUE)
+    return fail(ACOPF_EINVAL, "mode must be COLD, WARM or CONTINUE");
+  if (fixed_iters < 0) return fail(ACOPF_EINVAL, "fixed_iters must be >= 0");
+  if (mode != ACOPF_COLD && !h->started_once[grid] && !h->solved)
+    return fail(ACOPF_ESTATE, "warm or continued start of a grid never solved");
+  if (h->running[grid]) return fail(ACOPF_ESTATE, "grid is already running");
+  HIP_TRY(hipSetDevice(h->device));
+  return start_impl(h, grid, mode, fixed_iters);
+}
+
+int acopf_run(acopf_handle h, int32_t max_iters, int32_t* running) {
+  if (!h) return fail(ACOPF_EINVAL, "null handle");
+  if (max_iters < 1) return fail(ACOPF_EINVAL, "max_iters must be >= 1");
+  HIP_TRY(hipSetDevice(h->device));
+  int rc = run_impl(h, max_iters, true, nullptr);
+  if (rc) return rc;
+  if (running) {
+    int n = 0;
+    for (int g = 0; g < h->G; ++g) n += h->running[g];
+    *running = n;
+  }
+  return ACOPF_OK;
+}
+
+int acopf_poll(acopf_handle h, int32_t grid, int32_t* is_running, acopf_result* out) {
+  if (!h) return fail(ACOPF_EINVAL, "null handle");
+  if (grid < 0 || grid >= h->G) return fail(ACOPF_EINVAL, "grid index out of range");
+  if (is_running) *is_running = h->running[grid];
+  if (out) {
+    HIP_TRY(hipSetDevice(h->device));
+    return result_impl(h, grid, out);
   }
   return ACOPF_OK;
 }
@@ -1202,7 +1359,9 @@ int acopf_set_state(acopf_handle h, int32_t grid, int32_t what, const double* in
   if (n != need) return fail(ACOPF_EINVAL, "buffer size mismatch: need " + std::to_string(need));
   if (!finite_all(in, n) && what != ACOPF_SCALARS) return fail(ACOPF_EINVAL, "non-finite state");
   HIP_TRY(hipSetDevice(h->device));
+  if (h->running[grid]) return fail(ACOPF_ESTATE, "grid is running");
   h->solved = true;
+  h->started_once[grid] = 1;
   return copy_state(h, grid, what, const_cast<double*>(in), n, false);
 }
 
@@ -1214,6 +1373,165 @@ int acopf_get_sizes(acopf_handle h, int32_t grid, int64_t* out4) {
   out4[1] = H.nb;
   out4[2] = H.ng;
   out4[3] = H.nl;
+  return ACOPF_OK;
+}
+
+// Device arrays that make up the iteration state, with their lengths.
+static std::vector<std::pair<void*, size_t>> state_arrays(acopf_s* h) {
+  const size_t d = sizeof(double);
+  return {{h->u, h->m * d},      {h->v, h->m * d},      {h->z, h->m * d},
+          {h->y, h->m * d},      {h->lam, h->m * d},    {h->bx, 6 * h->nl * d},
+          {h->ltil, 2 * h->nl * d}, {h->rtil, h->nl * d}, {h->pd, h->nb * d},
+          {h->qd, h->nb * d},    {h->ctl, h->G * sizeof(GridCtl)}};
+}
+
+int acopf_snapshot(acopf_handle h, int32_t what) {
+  if (!h) return fail(ACOPF_EINVAL, "null handle");
+  if (what != 0 && what != 1) return fail(ACOPF_EINVAL, "what must be 0 (save) or 1 (restore)");
+  HIP_TRY(hipSetDevice(h->device));
+  auto arrs = state_arrays(h);
+  if (what == 1 && h->snap.empty()) return fail(ACOPF_ESTATE, "restore without a saved snapshot");
+  if (h->snap.empty()) {
+    for (auto& a : arrs) {
+      void* p = nullptr;
+      if (hipMalloc(&p, a.second) != hipSuccess) {
+        for (void* q : h->snap) (void)hipFree(q);
+        h->snap.clear();
+        return fail(ACOPF_ENOMEM, "snapshot allocation failed");
+      }
+      h->snap.push_back(p);
+    }
+  }
+  for (size_t i = 0; i < arrs.size(); ++i) {
+    if (what == 0)
+      HIP_TRY(hipMemcpyAsync(h->snap[i], arrs[i].first, arrs[i].second, hipMemcpyDeviceToDevice,
+                             h->stream));
+    else
+      HIP_TRY(hipMemcpyAsync(arrs[i].first, h->snap[i], arrs[i].second, hipMemcpyDeviceToDevice,
+                             h->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (what == 1) {
+    // the restored control blocks decide which grids are running
+    HIP_TRY(hipMemcpy(h->h_ctl, h->ctl, sizeof(GridCtl) * h->G, hipMemcpyDeviceToHost));
+    for (int g = 0; g < h->G; ++g) h->running[g] = h->h_ctl[g].done ? 0 : 1;
+  }
+  return ACOPF_OK;
+}
+
+int acopf_copy_grid(acopf_handle h, int32_t src, int32_t dst) {
+  if (!h) return fail(ACOPF_EINVAL, "null handle");
+  if (src < 0 || src >= h->G || dst < 0 || dst >= h->G)
+    return fail(ACOPF_EINVAL, "grid index out of range");
+  if (src == dst) return ACOPF_OK;
+  const HostGrid& A = h->grids[src];
+  const HostGrid& B = h->grids[dst];
+  if (A.nb != B.nb || A.ng != B.ng || A.nl != B.nl || A.r6e - A.r6b != B.r6e - B.r6b)
+    return fail(ACOPF_EINVAL, "grids differ in size");
+  if (h->running[dst]) return fail(ACOPF_ESTATE, "destination grid is running");
+  HIP_TRY(hipSetDevice(h->device));
+  hipStream_t st = h->stream;
+  auto cp = [&](double* base, int64_t from, int64_t to, int64_t n) {
+    if (n <= 0) return hipSuccess;
+    return hipMemcpyAsync(base + to, base + from, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+  };
+  const int64_t ng = h->ng, ne = h->ne, nl = h->nl;
+  double* vecs[] = {h->u, h->v, h->z, h->y, h->lam};
+  for (double* v : vecs) {
+    HIP_TRY(cp(v, A.gen_off, B.gen_off, A.ng));
+    HIP_TRY(cp(v, ng + A.gen_off, ng + B.gen_off, A.ng));
+    for (int k = 0; k < 4; ++k)
+      HIP_TRY(cp(v, 2 * ng + k * ne + A.e0, 2 * ng + k * ne + B.e0, A.e1 - A.e0));
+  }
+  for (int r = 0; r < 6; ++r) {
+    HIP_TRY(cp(h->bx, r * nl + A.r6b, r * nl + B.r6b, A.r6e - A.r6b));
+    HIP_TRY(cp(h->bx, r * nl + A.r4b, r * nl + B.r4b, A.r4e - A.r4b));
+  }
+  for (int r = 0; r < 2; ++r) {
+    HIP_TRY(cp(h->ltil, r * nl + A.r6b, r * nl + B.r6b, A.r6e - A.r6b));
+    HIP_TRY(cp(h->ltil, r * nl + A.r4b, r * nl + B.r4b, A.r4e - A.r4b));
+  }
+  HIP_TRY(cp(h->rtil, A.r6b, B.r6b, A.r6e - A.r6b));
+  HIP_TRY(cp(h->rtil, A.r4b, B.r4b, A.r4e - A.r4b));
+  HIP_TRY(cp(h->pd, A.bus_off, B.bus_off, A.nb));
+  HIP_TRY(cp(h->qd, A.bus_off, B.bus_off, A.nb));
+  HIP_TRY(hipMemcpyAsync(h->ctl + dst, h->ctl + src, sizeof(GridCtl), hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(ctl_idle_kernel, dim3(1), dim3(64), 0, st, h->ctl + dst, 1);
+  HIP_TRY(hipStreamSynchronize(st));
+  h->started_once[dst] = h->started_once[src] || h->solved;
+  return ACOPF_OK;
+}
+
+static int check_tuning(const acopf_tuning& t) {
+  if (t.xstep_block != 64 && t.xstep_block != 128 && t.xstep_block != 256)
+    return fail(ACOPF_EINVAL, "xstep_block must be 64, 128 or 256");
+  if (t.bus_block < 64 || t.bus_block > 1024 || t.bus_block % 64)
+    return fail(ACOPF_EINVAL, "bus_block must be a multiple of 64 in [64, 1024]");
+  if (t.chunk < 1 || t.chunk > kChunk * 4) return fail(ACOPF_EINVAL, "chunk must be in [1, 64]");
+  return ACOPF_OK;
+}
+
+int acopf_set_tuning(acopf_handle h, const acopf_tuning* t) {
+  if (!h || !t) return fail(ACOPF_EINVAL, "null argument");
+  int rc = check_tuning(*t);
+  if (rc) return rc;
+  h->tune = *t;
+  drop_graph(h);
+  return ACOPF_OK;
+}
+
+int acopf_get_tuning(acopf_handle h, acopf_tuning* t) {
+  if (!h || !t) return fail(ACOPF_EINVAL, "null argument");
+  *t = h->tune;
+  return ACOPF_OK;
+}
+
+int acopf_autotune(acopf_handle h, int32_t iters, acopf_tuning* out) {
+  if (!h) return fail(ACOPF_EINVAL, "null handle");
+  if (iters < 1) return fail(ACOPF_EINVAL, "iters must be >= 1");
+  HIP_TRY(hipSetDevice(h->device));
+  const bool prof = h->profile;
+  h->profile = false;
+  int rc = acopf_snapshot(h, 0);
+  if (rc) return rc;
+  const std::vector<char> run0 = h->running, once0 = h->started_once;
+  const std::vector<double> ts0 = h->t_start, te0 = h->t_end;
+  acopf_tuning best = h->tune;
+  double best_t = 1e300;
+  const int xs[3] = {64, 128, 256}, bs[4] = {64, 128, 256, 512}, cs[3] = {8, 16, 32};
+  for (int xi : xs)
+    for (int bi : bs)
+      for (int ci : cs) {
+        acopf_tuning t{xi, bi, ci, 1};
+        h->tune = t;
+        drop_graph(h);
+        double tmin = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {  // first pass also captures the graph
+          rc = acopf_snapshot(h, 1);
+          if (rc) return rc;
+          rc = start_impl(h, -1, ACOPF_CONTINUE, iters);
+          if (rc) return rc;
+          HIP_TRY(hipStreamSynchronize(h->stream));
+          const double t0 = now_s();
+          rc = run_impl(h, iters, false, nullptr);
+          if (rc) return rc;
+          tmin = std::min(tmin, now_s() - t0);
+        }
+        if (tmin < best_t) {
+          best_t = tmin;
+          best = t;
+        }
+      }
+  h->tune = best;
+  drop_graph(h);
+  rc = acopf_snapshot(h, 1);
+  if (rc) return rc;
+  h->running = run0;
+  h->started_once = once0;
+  h->t_start = ts0;
+  h->t_end = te0;
+  h->profile = prof;
+  if (out) *out = best;
   return ACOPF_OK;
 }
 

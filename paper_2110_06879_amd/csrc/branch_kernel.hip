@@ -850,15 +850,16 @@ __device__ inline void solve_generator(const BranchArgs& A, int64_t g) {
 #define ACOPF_XSTEP_WAVES_PER_EU 1
 #endif
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ACOPF_XSTEP_WAVES_PER_EU)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ACOPF_XSTEP_WAVES_PER_EU)))
 void xstep_kernel(BranchArgs A, int64_t n6, int b6, int b4) {
   Counters cnt = {};
   bool active = false;
   const int b = blockIdx.x;
+  const int bs = blockDim.x;
   if (b < b6 + b4) {
     const bool six = b < b6;
-    const int64_t l = six ? (int64_t)b * 64 + threadIdx.x
-                          : n6 + (int64_t)(b - b6) * 64 + threadIdx.x;
+    const int64_t l = six ? (int64_t)b * bs + threadIdx.x
+                          : n6 + (int64_t)(b - b6) * bs + threadIdx.x;
     if (six ? l < n6 : l < A.nl) {
       const int grid = A.br_grid[l];
       if (A.ctl[grid].done == 0) {
@@ -868,7 +869,7 @@ void xstep_kernel(BranchArgs A, int64_t n6, int b6, int b4) {
       }
     }
   } else {
-    const int64_t g = (int64_t)(b - b6 - b4) * 64 + threadIdx.x;
+    const int64_t g = (int64_t)(b - b6 - b4) * bs + threadIdx.x;
     if (g < A.ng && A.ctl[A.gen_grid[g]].done == 0) solve_generator(A, g);
     return;  // whole block is generators: no branch counters
   }
@@ -889,12 +890,12 @@ void xstep_kernel(BranchArgs A, int64_t n6, int b6, int b4) {
   }
 }
 
-void launch_xstep(const BranchArgs& A, int64_t n6, hipStream_t s) {
-  const int b6 = (int)((n6 + 63) / 64);
-  const int b4 = (int)((A.nl - n6 + 63) / 64);
-  const int bg = (int)((A.ng + 63) / 64);
+void launch_xstep(const BranchArgs& A, int64_t n6, int block, hipStream_t s) {
+  const int b6 = (int)((n6 + block - 1) / block);
+  const int b4 = (int)((A.nl - n6 + block - 1) / block);
+  const int bg = (int)((A.ng + block - 1) / block);
   if (b6 + b4 + bg == 0) return;
-  hipLaunchKernelGGL(xstep_kernel, dim3(b6 + b4 + bg), dim3(64), 0, s, A, n6, b6, b4);
+  hipLaunchKernelGGL(xstep_kernel, dim3(b6 + b4 + bg), dim3(block), 0, s, A, n6, b6, b4);
 }
 
 }  // namespace acopf_dev

@@ -15,7 +15,7 @@ struct GridCtl {
   double r_pri, r_dual, r_z;
   int outer, inner_total, inner_in_outer, status;
   int done, do_outer, fixed_target, branch_failures;
-  int numerical, pad0, pad1, pad2;
+  int numerical, fixed_mode, running, pad2;  // fixed_mode: stop only at fixed_target
 };
 
 // Coupling vectors (u, v, z, y, lambda) are laid out bus-major: generator
@@ -49,9 +49,9 @@ struct BranchArgs {
   const double *pmin, *pmax, *qmin, *qmax, *c2q, *c1l;
 };
 
-// One launch for the whole x-step: blocks [0, b6) solve rated branches
-// [0, n6), blocks [b6, b6 + b4) unlimited branches [n6, nl), the remaining
-// blocks the generators.
-void launch_xstep(const BranchArgs& A, int64_t n6, hipStream_t s);
+// One launch for the whole x-step with `block` threads per block (a multiple
+// of 64): blocks [0, b6) solve rated branches [0, n6), blocks [b6, b6 + b4)
+// unlimited branches [n6, nl), the remaining blocks the generators.
+void launch_xstep(const BranchArgs& A, int64_t n6, int block, hipStream_t s);
 
 }  // namespace acopf_dev

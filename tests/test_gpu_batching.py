@@ -1,0 +1,139 @@
+"""GPU tests of the driver: hipGraph chunks, continuous batching (per-grid
+start/run/poll), device-side state copies and snapshots, the autotuner, and
+the serving loop's alone-versus-mix equality. All comparisons are bitwise:
+grids are independent problems, so their arithmetic cannot depend on the
+launch shape or on the other grids in the batch."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2110_06879_amd import acopf as A
+from paper_2110_06879_amd import serve as S
+from paper_2110_06879_amd.gridgen import config_grid, gridgen, perturb_loads
+
+pytestmark = pytest.mark.gpu
+VECS = ("u", "v", "z", "y", "lam", "bx", "ltil", "rtil")
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def states(s, grid=0):
+    return {k: s.get(k, grid) for k in VECS}
+
+
+def assert_same(a, b):
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+def test_graph_replay_equals_plain_launches():
+    note("graph vs plain, 2k grid, 48 iterations")
+    g = config_grid("c2_2kbus")
+    with A.Solver(g) as s1, A.Solver(g) as s2:
+        s1.set_tuning(use_graph=1, chunk=16)
+        s2.set_tuning(use_graph=0, chunk=16)
+        s1.solve(A.COLD, 48)
+        s2.solve(A.COLD, 48)
+        assert_same(states(s1), states(s2))
+        s1.set_tuning(use_graph=1, chunk=8, xstep_block=128, bus_block=512)
+        s1.solve(A.CONTINUE, 40)
+        s2.solve(A.CONTINUE, 40)
+        assert_same(states(s1), states(s2))
+
+
+def test_staggered_starts_equal_alone():
+    note("continuous batching: staggered starts")
+    gs = [gridgen(300 + 50 * k, 60 + 10 * k, 390 + 60 * k, 1.0, 60 + k, load_factor=0.2)
+          for k in range(3)]
+    with A.Solver(gs) as sb:
+        sb.start(0, A.COLD, 60)
+        sb.run(16)
+        sb.start(1, A.COLD, 60)
+        sb.run(16)
+        sb.start(2, A.COLD, 60)
+        while sb.run(64) > 0:
+            pass
+        for k, g in enumerate(gs):
+            running, res = sb.poll(k)
+            assert not running and res["inner_iters"] == 60
+            with A.Solver(g) as sa:
+                sa.solve(A.COLD, 60)
+                assert_same(states(sa), states(sb, k))
+
+
+def test_copy_grid_and_snapshot_roundtrip():
+    note("copy_grid and snapshot")
+    g = gridgen(400, 80, 520, 1.0, 71, load_factor=0.2)
+    with A.Solver([g, g]) as s:
+        s.start(0, A.COLD, 30)
+        while s.run(64) > 0:
+            pass
+        s.copy_grid(0, 1)
+        assert_same(states(s, 0), states(s, 1))
+        s.snapshot()
+        base = states(s, 0)
+        s.start(0, A.CONTINUE, 20)
+        s.start(1, A.CONTINUE, 20)
+        while s.run(64) > 0:
+            pass
+        assert_same(states(s, 0), states(s, 1))
+        s.snapshot(restore=True)
+        assert_same(states(s, 0), base)
+
+
+def test_autotune_leaves_state_unchanged():
+    note("autotune")
+    g = config_grid("c2_2kbus")
+    with A.Solver(g) as s:
+        s.solve(A.COLD, 20)
+        before = states(s)
+        t = s.autotune(8)
+        assert t["xstep_block"] in (64, 128, 256) and t["chunk"] in (8, 16, 32)
+        assert_same(states(s), before)
+        s.solve(A.CONTINUE, 10)
+        with A.Solver(g) as r:
+            r.solve(A.COLD, 30)
+            assert_same(states(s), states(r))
+
+
+def test_serving_results_same_alone_and_in_mix():
+    note("serving: alone vs mix")
+    gs = [gridgen(250 + 40 * k, 50 + 8 * k, 325 + 52 * k, 1.0, 80 + k, load_factor=0.2)
+          for k in range(3)]
+    reqs = []
+    for k in range(3):
+        for t in range(2):
+            pd, qd = perturb_loads(gs[k], 0.02, 900 + 10 * k + t)
+            reqs.append(S.Request(len(reqs), k, 0.0, pd, qd))
+    srv = S.TrackingServer(gs, max_slots_per_grid=2)
+    out = srv.serve(reqs, realtime=False)
+    srv.close()
+    assert out["requests"] == len(reqs)
+    mix = {r.rid: r for r in out["done"]}
+    for r in reqs:
+        alone = S.TrackingServer(gs, max_slots_per_grid=2)
+        one = S.Request(r.rid, r.grid, 0.0, r.pd, r.qd)
+        o = alone.serve([one], realtime=False)["done"][0]
+        got = {k: alone.solver.get(k, r.grid) for k in ("u", "v", "z", "y", "bx")}
+        alone.close()
+        assert o.result["inner_iters"] == mix[r.rid].result["inner_iters"]
+        assert o.result["objective"] == mix[r.rid].result["objective"]
+        assert o.result["r_pri"] == mix[r.rid].result["r_pri"]
+
+
+def test_serving_budget_without_slots_runs_on_home():
+    note("serving: budget allows no slots")
+    gs = [gridgen(200, 40, 260, 1.0, 90, load_factor=0.2)]
+    budget = S.instance_bytes(gs[0]) * 1.5
+    srv = S.TrackingServer(gs, hbm_budget_bytes=budget)
+    assert srv.slots_per_grid == [0]
+    reqs = [S.Request(i, 0, 0.0, *perturb_loads(gs[0], 0.02, 950 + i)) for i in range(3)]
+    out = srv.serve(reqs, realtime=False)
+    srv.close()
+    assert out["requests"] == 3 and out["converged"] == 3
+    with pytest.raises(ValueError):
+        S.TrackingServer(gs, hbm_budget_bytes=budget * 0.1)
