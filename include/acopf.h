@@ -133,6 +133,12 @@ typedef struct {
                           a multiple of 64                                  */
   int32_t chunk;       /* inner iterations between control readbacks, 1..64 */
   int32_t use_graph;   /* 1: replay each chunk as one captured hipGraph     */
+  int32_t xstep_waves; /* 0: the branch kernel above, one lane per branch;
+                          1..4: persistent branch kernel instead, with this
+                          many 64-lane wavefronts per SIMD of the device;
+                          each lane takes branches from a shared counter and
+                          advances one TRON iteration per loop trip, so lanes
+                          that finish early take more work (same results) */
 } acopf_tuning;
 
 typedef struct acopf_s* acopf_handle;
@@ -191,7 +197,8 @@ int acopf_snapshot(acopf_handle h, int32_t what);
 /* Launch shape: set explicitly, read back, or pick by timing `iters` inner
  * iterations of every candidate from the current state (the state is saved
  * before and restored after, so tuning leaves the solve unchanged).
- * Candidates: xstep_block {64, 128, 256} x bus_block {64, 128, 256, 512} x
+ * Candidates: x-step {lane per branch at xstep_block 64, 128, 256;
+ * persistent at xstep_waves 1, 2} x bus_block {64, 128, 256, 512} x
  * chunk {8, 16, 32}, graphs on. Errors: EINVAL, ENOMEM, EDEVICE. */
 int acopf_set_tuning(acopf_handle h, const acopf_tuning* t);
 int acopf_get_tuning(acopf_handle h, acopf_tuning* t);

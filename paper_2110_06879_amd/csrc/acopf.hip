@@ -493,12 +493,14 @@ struct acopf_s {
   GridCtl* h_ctl = nullptr;  // pinned
   unsigned long long *rmax, *stats;
   int* failures;
+  unsigned* pool;  // persistent x-step pool counters
+  int n_cu = 0;
   double* hist;
   int64_t* gen_off_d;
   double *base_d, *obj_d;
   bool solved = false;
   bool profile = false;
-  acopf_tuning tune{64, 256, 16, 1};
+  acopf_tuning tune{64, 256, 16, 1, 0};
   hipGraphExec_t graph = nullptr;
   int graph_chunk = 0;
   std::vector<double> t_start;         // host clock at each grid's start
@@ -546,6 +548,7 @@ BranchArgs branch_args(const acopf_s* h) {
   A.al_maxit = h->P.al_maxit;
   A.failures = h->failures;
   A.stats = h->stats;
+  A.pool = h->pool;
   A.ng = h->ng;
   A.gen_grid = h->gen_grid;
   A.pmin = h->pmin;
@@ -573,7 +576,10 @@ void launch_iteration(acopf_s* h, int slot) {
   };
   BranchArgs ba = branch_args(h);
   mark(0);
-  acopf_dev::launch_xstep(ba, h->n6, h->tune.xstep_block, s);
+  if (h->tune.xstep_waves > 0)
+    acopf_dev::launch_xstep_persistent(ba, h->n6, h->tune.xstep_waves * 4 * h->n_cu, s);
+  else
+    acopf_dev::launch_xstep(ba, h->n6, h->tune.xstep_block, s);
   mark(1);
   BusArgs bu{h->nb, h->ng, h->ne, h->bus_grid, h->ctl, h->gptr, h->eptr,
              h->pd, h->qd, h->gs, h->bs, h->isref, h->u, h->lam, h->v, h->z, h->y,
@@ -717,6 +723,8 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   if (device < 0 || device >= ndev) return fail(ACOPF_EINVAL, "device index out of range");
   HIP_TRY(hipSetDevice(device));
   h->device = device;
+  HIP_TRY(hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, device));
+  if (h->n_cu < 1) h->n_cu = 1;
   h->P = *params;
   h->G = n_grids;
   if (hip_stream) {
@@ -928,6 +936,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(D.alloc(&h->rmax, 3 * n_grids));
   HIP_TRY(D.alloc(&h->stats, kStats));
   HIP_TRY(D.alloc(&h->failures, n_grids));
+  HIP_TRY(D.alloc(&h->pool, 3));
   HIP_TRY(D.alloc(&h->hist, (size_t)n_grids * kHistCap * 6));
   HIP_TRY(D.alloc(&h->gen_off_d, n_grids + 1));
   HIP_TRY(D.alloc(&h->base_d, n_grids));
@@ -962,6 +971,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(up(h->gen_off_d, gen_off.data(), sizeof(int64_t) * (n_grids + 1)));
   HIP_TRY(up(h->base_d, base.data(), sizeof(double) * n_grids));
   HIP_TRY(hipMemsetAsync(h->stats, 0, sizeof(unsigned long long) * kStats, st));
+  HIP_TRY(hipMemsetAsync(h->pool, 0, sizeof(unsigned) * 3, st));
   HIP_TRY(hipMemsetAsync(h->hist, 0, sizeof(double) * (size_t)n_grids * kHistCap * 6, st));
   HIP_TRY(hipMemsetAsync(h->ctl, 0, sizeof(GridCtl) * n_grids, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -1468,6 +1478,8 @@ static int check_tuning(const acopf_tuning& t) {
   if (t.bus_block < 64 || t.bus_block > 1024 || t.bus_block % 64)
     return fail(ACOPF_EINVAL, "bus_block must be a multiple of 64 in [64, 1024]");
   if (t.chunk < 1 || t.chunk > kChunk * 4) return fail(ACOPF_EINVAL, "chunk must be in [1, 64]");
+  if (t.xstep_waves < 0 || t.xstep_waves > 4)
+    return fail(ACOPF_EINVAL, "xstep_waves must be in [0, 4]");
   return ACOPF_OK;
 }
 
@@ -1498,11 +1510,14 @@ int acopf_autotune(acopf_handle h, int32_t iters, acopf_tuning* out) {
   const std::vector<double> ts0 = h->t_start, te0 = h->t_end;
   acopf_tuning best = h->tune;
   double best_t = 1e300;
-  const int xs[3] = {64, 128, 256}, bs[4] = {64, 128, 256, 512}, cs[3] = {8, 16, 32};
-  for (int xi : xs)
+  // x-step variants: one lane per branch at three block sizes, or the
+  // persistent kernel at one or two wavefronts per SIMD
+  const int xs[5][2] = {{64, 0}, {128, 0}, {256, 0}, {64, 1}, {64, 2}};
+  const int bs[4] = {64, 128, 256, 512}, cs[3] = {8, 16, 32};
+  for (const auto& xi : xs)
     for (int bi : bs)
       for (int ci : cs) {
-        acopf_tuning t{xi, bi, ci, 1};
+        acopf_tuning t{xi[0], bi, ci, 1, xi[1]};
         h->tune = t;
         drop_graph(h);
         double tmin = 1e300;

@@ -733,6 +733,131 @@ __device__ int tron(const BranchIn<N>& B, double* x, const double* lo, const dou
   return status;
 }
 
+// ---------------------------------------------------------------------------
+// Resumable TRON for the persistent x-step: the same iteration, split so a
+// lane can advance its solve by one iteration per trip of a loop that all
+// lanes of the wavefront share. tron_begin + repeated tron_advance performs
+// exactly the operations of tron() in the same order.
+// ---------------------------------------------------------------------------
+template <int N>
+struct TronState {
+  double x[N];
+  double f, g[N];
+  Sym<N> H;
+  double delta, alphac;
+  int it, status;
+  bool eval, first;
+};
+
+template <int N>
+__device__ inline void tron_begin(TronState<N>& S, const double* lo, const double* hi,
+                                  Counters& cnt) {
+  ++cnt.tron_calls;
+#pragma unroll
+  for (int i = 0; i < N; ++i) S.x[i] = clampd(S.x[i], lo[i], hi[i]);
+  S.it = 0;
+  S.status = kMaxit;
+  S.eval = true;
+  S.first = true;
+  S.alphac = 1.0;
+  S.delta = 1.0;
+}
+
+// Returns true when the solve has ended (S.status is then set).
+template <int N>
+__device__ bool tron_advance(TronState<N>& S, const BranchIn<N>& B, const double* lo,
+                             const double* hi, double gtol, double ftol, int maxit,
+                             Counters& cnt) {
+  if (S.eval) {
+    fgh<N>(B, S.x, S.f, S.g, S.H, cnt);
+    S.eval = false;
+    if (S.first) {
+      double pg2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const double t = clampd(S.x[i] - S.g[i], lo[i], hi[i]) - S.x[i];
+        pg2 = pg2 + t * t;
+      }
+      S.delta = sqrt(pg2);
+      FL(4 * N + 1);
+      if (!(S.delta > 0.0)) S.delta = 1.0;
+      S.first = false;
+    }
+  }
+  if (S.it > 0) {
+    const double xn = sqrt(dotN<N>(S.x, S.x));
+    FL(2 * N + 2);
+    if (S.delta <= 1e-15 * (xn > 1.0 ? xn : 1.0)) {
+      S.status = kStall;
+      return true;
+    }
+  }
+  if (S.it >= maxit) {
+    S.status = kMaxit;
+    return true;
+  }
+  double pginf = 0.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const double t = fabs(clampd(S.x[i] - S.g[i], lo[i], hi[i]) - S.x[i]);
+    pginf = pginf < t ? t : pginf;
+  }
+  FL(2 * N);
+  if (pginf <= gtol) {
+    S.status = kConv;
+    return true;
+  }
+  ++cnt.tron_iters;
+  double w[N], s[N];
+  cauchy<N>(S.x, S.g, S.H, lo, hi, S.delta, S.alphac, w, cnt);
+  subspace<N>(S.x, S.g, S.H, lo, hi, S.delta, w, cnt);
+#pragma unroll
+  for (int i = 0; i < N; ++i) s[i] = w[i] - S.x[i];
+  FL(N);
+  const double prered = -model<N>(S.g, S.H, s, cnt);
+  const double snorm = sqrt(dotN<N>(s, s));
+  FL(2 * N + 1);
+  if (!(prered > 0.0)) {
+    S.status = kStall;
+    return true;
+  }
+  if (snorm < S.delta) {
+    FL(2);
+    if (prered <= ftol * (1.0 + fabs(S.f))) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) S.x[i] = w[i];
+      S.status = kConv;
+      return true;
+    }
+  }
+  const double fw = fval<N>(B, w, cnt);
+  const double actred = S.f - fw;
+  const double ratio = actred / prered;
+  FL(2);
+  double delta = S.delta;
+  if (ratio <= kEta0) {
+    delta = kSig2 * (snorm < delta ? snorm : delta);
+    FL(1);
+  } else if (ratio <= kEta1) {
+    const double a = kSig1 * delta, b = kSig2 * (snorm < delta ? snorm : delta);
+    delta = a < b ? b : a;
+    FL(2);
+  } else if (ratio >= kEta2) {
+    const double a = kSig3 * delta, b0 = kSig3 * snorm;
+    const double b = delta < b0 ? b0 : delta;
+    delta = b < a ? b : a;
+    FL(2);
+  }
+  S.delta = delta;
+  if (ratio > kEta0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) S.x[i] = w[i];
+    S.eval = true;
+  }
+  ++S.it;
+  return false;
+}
+
 #undef FL
 
 // Branch l of the device order with N variables: solve, write u and state.
@@ -844,6 +969,212 @@ __device__ inline void solve_generator(const BranchArgs& A, int64_t g) {
   const double cq = rho * (A.v[kq] - A.z[kq]) - A.y[kq];
   const double xq = cq / rho;
   A.u[kq] = fmax(A.qmin[g], fmin(A.qmax[g], xq));
+}
+
+// Coupling positions k = 0..7 of branch l: p_ij q_ij p_ji q_ji w_i th_i w_j th_j.
+__device__ inline void branch_couplings(const BranchArgs& A, int64_t l, int64_t* cidx) {
+  const int64_t ef = A.ef[l], et = A.et[l];
+  cidx[0] = end_coupling(A.ng, A.ne, 0, ef);
+  cidx[1] = end_coupling(A.ng, A.ne, 1, ef);
+  cidx[2] = end_coupling(A.ng, A.ne, 0, et);
+  cidx[3] = end_coupling(A.ng, A.ne, 1, et);
+  cidx[4] = end_coupling(A.ng, A.ne, 2, ef);
+  cidx[5] = end_coupling(A.ng, A.ne, 3, ef);
+  cidx[6] = end_coupling(A.ng, A.ne, 2, et);
+  cidx[7] = end_coupling(A.ng, A.ne, 3, et);
+}
+
+// Loads branch l: data, bounds, coupling values and the persistent state.
+template <int N>
+__device__ inline void load_branch(const BranchArgs& A, int64_t l, BranchIn<N>& B, double* lo,
+                                   double* hi, double* x) {
+  const int64_t nl = A.nl;
+  B.gii = A.adm[0 * nl + l];
+  B.bii = A.adm[1 * nl + l];
+  B.gij = A.adm[2 * nl + l];
+  B.bij = A.adm[3 * nl + l];
+  B.gji = A.adm[4 * nl + l];
+  B.bji = A.adm[5 * nl + l];
+  B.gjj = A.adm[6 * nl + l];
+  B.bjj = A.adm[7 * nl + l];
+  lo[0] = A.vlo_i[l];
+  hi[0] = A.vhi_i[l];
+  lo[1] = A.vlo_j[l];
+  hi[1] = A.vhi_j[l];
+  lo[2] = -kTwoPi;
+  hi[2] = kTwoPi;
+  lo[3] = -kTwoPi;
+  hi[3] = kTwoPi;
+  if (N == 6) {
+    lo[4] = -A.rate2[l];
+    hi[4] = 0.0;
+    lo[5] = -A.rate2[l];
+    hi[5] = 0.0;
+  }
+  int64_t cidx[8];
+  branch_couplings(A, l, cidx);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    B.vb[k] = A.v[cidx[k]];
+    B.zc[k] = A.z[cidx[k]];
+    B.yc[k] = A.y[cidx[k]];
+  }
+  B.rpq = A.rho_pq;
+  B.rva = A.rho_va;
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = A.bx[i * nl + l];
+  B.lt0 = 0.0;
+  B.lt1 = 0.0;
+  B.rt = 0.0;
+  if (N == 6) {
+    B.lt0 = A.ltil[l];
+    B.lt1 = A.ltil[nl + l];
+    B.rt = A.rtil[l];
+  }
+}
+
+// Persistent lanes over the branch pool [begin, end): every lane owns at most
+// one branch solve at a time, advances it by one TRON iteration per trip and,
+// when it ends, takes the next branch index from the pool counter (one atomic
+// per wavefront per trip). The loop ends when the pool is exhausted and every
+// lane of the wavefront has finished.
+template <int N>
+__device__ void run_pool(const BranchArgs& A, int64_t begin, int64_t end, unsigned* ctr,
+                         Counters& cnt, uint32_t& solves, uint64_t& flops) {
+  const int lane = threadIdx.x & 63;
+  enum { kFetch = 0, kRun = 1, kDone = 2 };
+  int phase = kFetch;
+  int64_t l = -1;
+  int grid = 0, failures = 0, t_al = 0;
+  double cprev = 0.0;
+  BranchIn<N> B;
+  double lo[N], hi[N];
+  TronState<N> S;
+  while (true) {
+    const bool need = phase == kFetch;
+    const unsigned long long m = __ballot(need);
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      unsigned base = 0;
+      if (lane == leader) base = atomicAdd(ctr, (unsigned)__popcll(m));
+      base = __shfl(base, leader, 64);
+      if (need) {
+        const int rank = __popcll(m & ((1ull << lane) - 1ull));
+        const int64_t idx = begin + (int64_t)base + rank;
+        if (idx >= end) {
+          phase = kDone;
+        } else {
+          l = idx;
+          grid = A.br_grid[l];
+          if (A.ctl[grid].done == 0) {
+            load_branch<N>(A, l, B, lo, hi, S.x);
+            failures = 0;
+            t_al = 0;
+            cprev = 1.0 / 0.0;
+            if (N == 6) ++cnt.al;
+            tron_begin<N>(S, lo, hi, cnt);
+            phase = kRun;
+          }
+        }
+      }
+    }
+    if (__ballot(phase != kDone) == 0ull) break;
+    if (phase != kRun) continue;
+    if (!tron_advance<N>(S, B, lo, hi, A.tron_gtol, A.tron_ftol, A.tron_maxit, cnt)) continue;
+    if (S.status == kConv) ++cnt.conv;
+    else if (S.status == kMaxit) ++cnt.maxit;
+    else ++cnt.stall;
+    failures += S.status != kConv;
+    bool finished = true;
+    if (N == 6) {
+      double a[8], aux[4];
+      values<N>(B, S.x, a, aux, cnt);
+      const double c0 = a[0] * a[0] + a[1] * a[1] + S.x[4];
+      const double c1 = a[2] * a[2] + a[3] * a[3] + S.x[5];
+      cnt.flops += 8;
+      const double cn = fabs(c0) > fabs(c1) ? fabs(c0) : fabs(c1);
+      if (!(cn <= A.al_tol)) {
+        B.lt0 = B.lt0 + B.rt * c0;
+        B.lt1 = B.lt1 + B.rt * c1;
+        cnt.flops += 5;
+        if (cn > A.al_shrink * cprev) {
+          const double gr = B.rt * A.al_rho_growth;
+          B.rt = gr < A.al_rho_max ? gr : A.al_rho_max;
+          cnt.flops += 1;
+        }
+        cprev = cn;
+        ++t_al;
+        if (t_al < A.al_maxit) {
+          ++cnt.al;
+          tron_begin<N>(S, lo, hi, cnt);
+          finished = false;
+        }
+      }
+    }
+    if (!finished) continue;
+    const int64_t nl = A.nl;
+    if (N == 6) {
+      A.ltil[l] = B.lt0;
+      A.ltil[nl + l] = B.lt1;
+      A.rtil[l] = B.rt;
+    }
+    double a[8], aux[4];
+    values<N>(B, S.x, a, aux, cnt);
+    int64_t cidx[8];
+    branch_couplings(A, l, cidx);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) A.u[cidx[k]] = a[k];
+#pragma unroll
+    for (int i = 0; i < N; ++i) A.bx[i * nl + l] = S.x[i];
+    if (failures) atomicAdd(&A.failures[grid], failures);
+    ++solves;
+    flops += cnt.flops;  // a lane may solve many branches: keep the sum in 64 bits
+    cnt.flops = 0;
+    phase = kFetch;
+  }
+}
+
+// Persistent x-step: a fixed number of 64-lane blocks drain the rated pool,
+// then the unlimited pool, then the generators (pool counters are reset by
+// the control kernel of the same iteration).
+__global__ __launch_bounds__(64) void xstep_persistent_kernel(BranchArgs A, int64_t n6) {
+  Counters cnt = {};
+  uint32_t solves = 0;
+  uint64_t flops = 0;
+  run_pool<6>(A, 0, n6, &A.pool[0], cnt, solves, flops);
+  run_pool<4>(A, n6, A.nl, &A.pool[1], cnt, solves, flops);
+  const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < A.ng; g += nthreads)
+    if (A.ctl[A.gen_grid[g]].done == 0) solve_generator(A, g);
+  uint64_t v[15] = {(uint64_t)solves, flops + cnt.flops, (uint64_t)cnt.trig, cnt.tron_calls,
+                    cnt.tron_iters, cnt.n_fgh, cnt.n_f, cnt.cauchy, cnt.cg, cnt.chol,
+                    cnt.ps, cnt.al, cnt.conv, cnt.maxit, cnt.stall};
+#pragma unroll
+  for (int q = 0; q < 15; ++q) {
+    uint64_t t = v[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    v[q] = t;
+  }
+  if (threadIdx.x == 0) {
+    if (v[0] != 0) {
+#pragma unroll
+      for (int q = 0; q < 15; ++q) atomicAdd(&A.stats[q], (unsigned long long)v[q]);
+    }
+    // the last block to finish rearms the pools for the next launch: every
+    // other block has taken its final index before it counted itself done
+    __threadfence();
+    if (atomicAdd(&A.pool[2], 1u) == gridDim.x - 1) {
+      atomicExch(&A.pool[0], 0u);
+      atomicExch(&A.pool[1], 0u);
+      atomicExch(&A.pool[2], 0u);
+    }
+  }
+}
+
+void launch_xstep_persistent(const BranchArgs& A, int64_t n6, int blocks, hipStream_t s) {
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(xstep_persistent_kernel, dim3(blocks), dim3(64), 0, s, A, n6);
 }
 
 #ifndef ACOPF_XSTEP_WAVES_PER_EU

@@ -43,6 +43,8 @@ struct BranchArgs {
   int tron_maxit, al_maxit;
   int* failures;             // [G]
   unsigned long long* stats; // [16]
+  unsigned* pool;            // [3] next rated / unlimited branch, finished blocks
+                             //     (persistent x-step; zero between launches)
   // generator step, fused into the same launch
   int64_t ng;
   const int* gen_grid;
@@ -53,5 +55,9 @@ struct BranchArgs {
 // of 64): blocks [0, b6) solve rated branches [0, n6), blocks [b6, b6 + b4)
 // unlimited branches [n6, nl), the remaining blocks the generators.
 void launch_xstep(const BranchArgs& A, int64_t n6, int block, hipStream_t s);
+
+// Persistent x-step on `blocks` 64-lane blocks; the pool counters must be
+// zero at launch and are zero again when it ends.
+void launch_xstep_persistent(const BranchArgs& A, int64_t n6, int blocks, hipStream_t s);
 
 }  // namespace acopf_dev

@@ -45,6 +45,29 @@ def test_graph_replay_equals_plain_launches():
         assert_same(states(s1), states(s2))
 
 
+@pytest.mark.parametrize("waves", [1, 2])
+def test_persistent_xstep_equals_lane_per_branch(waves):
+    """The pool kernel reorders which lane solves which branch, never the
+    arithmetic of a solve: states, per-grid results and every event and flop
+    count are bitwise those of the lane-per-branch kernel, also while grids of
+    the batch finish at different iterations."""
+    note(f"persistent x-step (waves {waves}) vs lane per branch, 4-grid batch to convergence")
+    gs = [gridgen(200 + 90 * k, 40 + 9 * k, 260 + 120 * k, 0.3 * k, 70 + k, load_factor=0.2)
+          for k in range(4)]
+    with A.Solver(gs) as s1, A.Solver(gs) as s2:
+        s1.set_tuning(xstep_waves=0)
+        s2.set_tuning(xstep_waves=waves)
+        r1 = s1.solve(A.COLD)
+        r2 = s2.solve(A.COLD)
+        for a, b in zip(r1, r2):
+            for k in ("status", "inner_iters", "outer_iters", "branch_failures", "objective",
+                      "r_pri", "r_dual", "r_z"):
+                assert a[k] == b[k], (k, a[k], b[k])
+        for k in range(len(gs)):
+            assert_same(states(s1, k), states(s2, k))
+        assert s1.stats() == s2.stats()
+
+
 def test_staggered_starts_equal_alone():
     note("continuous batching: staggered starts")
     gs = [gridgen(300 + 50 * k, 60 + 10 * k, 390 + 60 * k, 1.0, 60 + k, load_factor=0.2)
