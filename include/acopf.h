@@ -130,7 +130,8 @@ typedef struct {
   int32_t xstep_block; /* threads per block of the branch/generator kernel:
                           64, 128 or 256 (one lane per branch)              */
   int32_t bus_block;   /* threads per block of the bus kernel: 64..1024,
-                          a multiple of 64                                  */
+                          a multiple of 64; a block takes a tile of up to
+                          bus_block / 4 consecutive buses of one grid       */
   int32_t chunk;       /* inner iterations between control readbacks, 1..64 */
   int32_t use_graph;   /* 1: replay each chunk as one captured hipGraph     */
   int32_t xstep_waves; /* 0: the branch kernel above, one lane per branch;
@@ -198,7 +199,7 @@ int acopf_snapshot(acopf_handle h, int32_t what);
  * iterations of every candidate from the current state (the state is saved
  * before and restored after, so tuning leaves the solve unchanged).
  * Candidates: x-step {lane per branch at xstep_block 64, 128, 256;
- * persistent at xstep_waves 1, 2} x bus_block {64, 128, 256, 512} x
+ * persistent at xstep_waves 1, 2} x bus_block {128, 256, 512, 1024} x
  * chunk {8, 16, 32}, graphs on. Errors: EINVAL, ENOMEM, EDEVICE. */
 int acopf_set_tuning(acopf_handle h, const acopf_tuning* t);
 int acopf_get_tuning(acopf_handle h, acopf_tuning* t);

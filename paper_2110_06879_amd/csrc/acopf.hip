@@ -5,15 +5,17 @@
 //   xstep_kernel    branch subproblems, eq. (branch), TRON + AL     lane/branch
 //                   and the generator closed form, eq. (qp-bound)   lane/gen
 //   bus_kernel      bus closed form eq. (qp-bus), then z and y and
-//                   the residual maxima of every coupling it owns  lane/bus
-//   ctl_kernel      termination tests and the outer beta rule       lane/grid
+//                   the residual maxima of every coupling it owns  block/tile
+//                                                                  of buses
+//   ctl_kernel      termination tests and the outer beta rule       block/grid
 //   outer_kernel    lambda <- proj(lambda + beta z) when flagged    lane/coupling
 // The generator and branch steps read only the previous iteration's v, z, y
 // and so could run in any order; the bus step owns each coupling exactly once
 // (every coupling has one bus side), which makes the z and y updates and the
-// residual maxima a fused, race-free pass. Residual maxima are combined with
-// 64-bit integer atomicMax on the bit patterns of non-negative doubles, which
-// is exact and independent of order. Kernels return at once for grids that
+// residual maxima a fused, race-free pass. Each bus tile writes its residual
+// maxima to a slot of its own and the control kernel takes the maximum over
+// a grid's tiles: exact and independent of order, with no atomics contending
+// on one address. Kernels return at once for grids that
 // have finished, so a chunk of launches can overshoot convergence harmlessly;
 // the host reads the per-grid control words once per chunk.
 //
@@ -75,6 +77,7 @@ constexpr int kChunk = 16;      // iterations between control readbacks
 
 struct BusArgs {
   int64_t nb, ng, ne;
+  const int* tile;  // [n_tiles + 1] bus ranges; a tile never spans two grids
   const int* bus_grid;
   GridCtl* ctl;
   const int *gptr, *eptr;
@@ -84,151 +87,228 @@ struct BusArgs {
   const double* lam;
   double *v, *z, *y;
   double rho_pq, rho_va;
-  unsigned long long* rmax;  // [3 G]
+  double* tmax;              // [n_tiles][3] residual maxima of each tile
+  int ecap, gcap;            // branch ends / generators of a tile staged in LDS
+  int tbmax;                 // buses per tile at most (a quarter of the block)
 };
 
-__device__ inline unsigned long long dbits(double a) {
-  return (unsigned long long)__double_as_longlong(a);
+// LDS bytes of one bus tile of at most `tb` buses and the given capacities.
+__host__ __device__ inline size_t bus_lds_bytes(int tb, int ecap, int gcap) {
+  return sizeof(double) * (4 * (size_t)ecap + 2 * (size_t)gcap + 4 * (size_t)tb) +
+         sizeof(unsigned short) * ((size_t)ecap + gcap);
 }
 
-// eq. (qp-bus) for one bus: minimize sum_k rho_k/2 (x_k - x0_k)^2 over the
-// bus copies (generator outputs, flows leaving the bus, w) subject to the two
-// balance rows of eqs. (pg)-(qg); closed form through the 2x2 matrix
-// M = A Q^-1 A'. Then z (eq. qp-bound with no bounds) and y for every
-// coupling of the bus, and their residual maxima.
-__global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double rp = 0.0, rd = 0.0, rz = 0.0;
-  int grid = -1;
-  bool act = i < A.nb;
-  if (act) {
-    grid = A.bus_grid[i];
-    act = A.ctl[grid].done == 0;
+// Local bus (0-based in the tile) of local element `e` of a CSR range.
+__device__ inline int tile_bus_of(const int* ptr, int b0, int nbt, int base, int e) {
+  int lo = 0, hi = nbt - 1;  // largest local bus with ptr[b0 + bus] - base <= e
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ptr[b0 + mid] - base <= e) lo = mid;
+    else hi = mid - 1;
   }
-  if (act) {
-    const int64_t ng = A.ng, ne = A.ne;
-    const int64_t kP = 2 * ng, kQ = kP + ne, kW = kQ + ne, kT = kW + ne;
-    const double rpq = A.rho_pq, rva = A.rho_va;
-    const int g0 = A.gptr[i], g1 = A.gptr[i + 1];
-    const int e0 = A.eptr[i], e1 = A.eptr[i + 1];
+  return lo;
+}
+
+// eq. (qp-bus) for every bus of one tile of consecutive buses: minimize
+// sum_k rho_k/2 (x_k - x0_k)^2 over the bus copies (generator outputs, flows
+// leaving the bus, w) subject to the two balance rows of eqs. (pg)-(qg);
+// closed form through the 2x2 matrix M = A Q^-1 A'. Then z (eq. qp-bound
+// with no bounds) and y for every coupling of the tile, and their residual
+// maxima. Three phases over one workgroup of four lanes per bus:
+//   1. lane per branch end / generator: the prox targets
+//      c_k = rho_k (u_k + z_k) + y_k of the tile's couplings into LDS
+//      (coalesced: the tile's couplings are contiguous in every block);
+//   2. lane per bus: the sums over its couplings in their fixed order, read
+//      from LDS, and the 2x2 solve;
+//   3. lane per branch end / generator: new v, z, y and the residuals.
+// Ends or generators beyond the LDS capacity (a bus of very high degree) are
+// recomputed from global memory with the same operations.
+__global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
+  extern __shared__ double sm[];
+  const int t = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int b0 = A.tile[t], b1 = A.tile[t + 1], nbt = b1 - b0;
+  const int grid = A.bus_grid[b0];
+  if (A.ctl[grid].done) return;  // uniform: the tile lies in one grid
+  const int ecap = A.ecap, gcap = A.gcap, tb = A.tbmax;
+  double* cE = sm;              // [4][ecap] targets of end blocks p, q, w, theta
+  double* cG = cE + 4 * ecap;   // [2][gcap] targets of generator p, q
+  double* bv = cG + 2 * gcap;   // [4][tb]   mu0, mu1, w, theta per bus
+  unsigned short* emap = reinterpret_cast<unsigned short*>(bv + 4 * tb);  // [ecap]
+  unsigned short* gmap = emap + ecap;                                     // [gcap]
+  const int64_t ng = A.ng, ne = A.ne;
+  const int64_t kP = 2 * ng, kQ = kP + ne, kW = kQ + ne, kT = kW + ne;
+  const double rpq = A.rho_pq, rva = A.rho_va;
+  const int E0 = A.eptr[b0], E1 = A.eptr[b1];
+  const int G0 = A.gptr[b0], G1 = A.gptr[b1];
+  const int net = E1 - E0, ngt = G1 - G0;
+  auto target = [&](int64_t k, double rho) { return rho * (A.u[k] + A.z[k]) + A.y[k]; };
+  // ---- phase 1
+  for (int e = tid; e < net && e < ecap; e += nt) {
+    const int64_t k = E0 + e;
+    cE[0 * ecap + e] = target(kP + k, rpq);
+    cE[1 * ecap + e] = target(kQ + k, rpq);
+    cE[2 * ecap + e] = target(kW + k, rva);
+    cE[3 * ecap + e] = target(kT + k, rva);
+  }
+  for (int g = tid; g < ngt && g < gcap; g += nt) {
+    cG[g] = target(G0 + g, rpq);
+    cG[gcap + g] = target(ng + G0 + g, rpq);
+  }
+  __syncthreads();
+  auto cend = [&](int blk, int e) {
+    if (e < ecap) return cE[blk * ecap + e];
+    const int64_t base = blk == 0 ? kP : blk == 1 ? kQ : blk == 2 ? kW : kT;
+    return target(base + E0 + e, blk < 2 ? rpq : rva);
+  };
+  auto cgen = [&](int blk, int g) {
+    if (g < gcap) return cG[blk * gcap + g];
+    return target((blk ? ng : 0) + G0 + g, rpq);
+  };
+  // ---- phase 2
+  if (tid < nbt) {
+    const int i = b0 + tid;
+    const int e0 = A.eptr[i] - E0, e1 = A.eptr[i + 1] - E0;
+    const int g0 = A.gptr[i] - G0, g1 = A.gptr[i + 1] - G0;
     // shared w and theta of the bus
     double Qw = 0.0, cw = 0.0, Qt = 0.0, ct = 0.0;
     for (int e = e0; e < e1; ++e) {
-      const int64_t kw = kW + e, kt = kT + e;
       Qw += rva;
-      cw += rva * (A.u[kw] + A.z[kw]) + A.y[kw];
+      cw += cend(2, e);
       Qt += rva;
-      ct += rva * (A.u[kt] + A.z[kt]) + A.y[kt];
+      ct += cend(3, e);
+      if (e < ecap) emap[e] = (unsigned short)tid;
     }
     const double awP = -A.gs[i], awQ = A.bs[i];
     double M00 = awP * awP / Qw, M01 = awP * awQ / Qw, M11 = awQ * awQ / Qw;
     double r0 = awP * cw / Qw - A.pd[i], r1 = awQ * cw / Qw - A.qd[i];
     const double inv_pq = 1.0 / rpq;
-    for (int t = g0; t < g1; ++t) {
-      const int64_t gp = t, gq = ng + t;
-      const double cvp = rpq * (A.u[gp] + A.z[gp]) + A.y[gp];
+    for (int g = g0; g < g1; ++g) {
       M00 += inv_pq;
-      r0 += cvp / rpq;
-      const double cvq = rpq * (A.u[gq] + A.z[gq]) + A.y[gq];
+      r0 += cgen(0, g) / rpq;
       M11 += inv_pq;
-      r1 += cvq / rpq;
+      r1 += cgen(1, g) / rpq;
+      if (g < gcap) gmap[g] = (unsigned short)tid;
     }
     for (int e = e0; e < e1; ++e) {
-      const int64_t kp = kP + e, kq = kQ + e;
-      const double cvp = rpq * (A.u[kp] + A.z[kp]) + A.y[kp];
       M00 += inv_pq;
-      r0 += -cvp / rpq;
-      const double cvq = rpq * (A.u[kq] + A.z[kq]) + A.y[kq];
+      r0 += -cend(0, e) / rpq;
       M11 += inv_pq;
-      r1 += -cvq / rpq;
+      r1 += -cend(1, e) / rpq;
     }
     const double det = M00 * M11 - M01 * M01;
     const double mu0 = (M11 * r0 - M01 * r1) / det;
     const double mu1 = (M00 * r1 - M01 * r0) / det;
-    const double w = (cw - awP * mu0 - awQ * mu1) / Qw;
-    const double th = A.isref[i] ? 0.0 : ct / Qt;
-    const double beta = A.ctl[grid].beta;
-    // bus copies, then z, y and residuals of every coupling of the bus
-    auto finish = [&](int64_t k, double vnew, double rho) {
-      const double vold = A.v[k];
-      const double uk = A.u[k];
-      const double zk = -(A.lam[k] + A.y[k] + rho * (uk - vnew)) / (beta + rho);
-      const double yk = A.y[k] + rho * (uk - vnew + zk);
-      A.v[k] = vnew;
-      A.z[k] = zk;
-      A.y[k] = yk;
-      rp = fmax(rp, fabs(uk - vnew + zk));
-      rd = fmax(rd, fabs(vnew - vold));
-      rz = fmax(rz, fabs(zk));
-    };
-    for (int t = g0; t < g1; ++t) {
-      const int64_t gp = t, gq = ng + t;
-      const double cvp = rpq * (A.u[gp] + A.z[gp]) + A.y[gp];
-      const double cvq = rpq * (A.u[gq] + A.z[gq]) + A.y[gq];
-      finish(gp, (cvp - mu0) / rpq, rpq);
-      finish(gq, (cvq - mu1) / rpq, rpq);
-    }
-    for (int e = e0; e < e1; ++e) {
-      const int64_t kp = kP + e, kq = kQ + e;
-      const double cvp = rpq * (A.u[kp] + A.z[kp]) + A.y[kp];
-      const double cvq = rpq * (A.u[kq] + A.z[kq]) + A.y[kq];
-      finish(kp, (cvp + mu0) / rpq, rpq);
-      finish(kq, (cvq + mu1) / rpq, rpq);
-      finish(kW + e, w, rva);
-      finish(kT + e, th, rva);
-    }
+    bv[tid] = mu0;
+    bv[tb + tid] = mu1;
+    bv[2 * tb + tid] = (cw - awP * mu0 - awQ * mu1) / Qw;
+    bv[3 * tb + tid] = A.isref[i] ? 0.0 : ct / Qt;
   }
-  // wavefront max, one atomic per grid segment of the wavefront
-  const int lane = threadIdx.x & 63;
-  const int g_first = __shfl(grid, 0, 64);
-  bool uniform = true;
-  {
-    int other = grid < 0 ? g_first : grid;
-    unsigned long long ball = __ballot(other != g_first);
-    uniform = ball == 0;
+  __syncthreads();
+  // ---- phase 3
+  const double beta = A.ctl[grid].beta;
+  double rp = 0.0, rd = 0.0, rz = 0.0;
+  auto finish = [&](int64_t k, double vnew, double rho) {
+    const double vold = A.v[k];
+    const double uk = A.u[k];
+    const double yold = A.y[k];
+    const double zk = -(A.lam[k] + yold + rho * (uk - vnew)) / (beta + rho);
+    const double yk = yold + rho * (uk - vnew + zk);
+    A.v[k] = vnew;
+    A.z[k] = zk;
+    A.y[k] = yk;
+    rp = fmax(rp, fabs(uk - vnew + zk));
+    rd = fmax(rd, fabs(vnew - vold));
+    rz = fmax(rz, fabs(zk));
+  };
+  for (int g = tid; g < ngt; g += nt) {
+    const int b = g < gcap ? gmap[g] : tile_bus_of(A.gptr, b0, nbt, G0, g);
+    finish(G0 + g, (cgen(0, g) - bv[b]) / rpq, rpq);
+    finish(ng + G0 + g, (cgen(1, g) - bv[tb + b]) / rpq, rpq);
   }
-  if (uniform) {
-    for (int off = 32; off > 0; off >>= 1) {
-      rp = fmax(rp, __shfl_xor(rp, off, 64));
-      rd = fmax(rd, __shfl_xor(rd, off, 64));
-      rz = fmax(rz, __shfl_xor(rz, off, 64));
+  for (int e = tid; e < net; e += nt) {
+    const int b = e < ecap ? emap[e] : tile_bus_of(A.eptr, b0, nbt, E0, e);
+    const int64_t k = E0 + e;
+    finish(kP + k, (cend(0, e) + bv[b]) / rpq, rpq);
+    finish(kQ + k, (cend(1, e) + bv[tb + b]) / rpq, rpq);
+    finish(kW + k, bv[2 * tb + b], rva);
+    finish(kT + k, bv[3 * tb + b], rva);
+  }
+  // tile maxima (wavefront, then across the block's wavefronts), written to
+  // the tile's own slot: no atomics, and the control kernel reduces a grid's
+  // tiles. Maxima are exact, so the order of reduction does not matter.
+  __shared__ double red[3][16];
+  for (int off = 32; off > 0; off >>= 1) {
+    rp = fmax(rp, __shfl_xor(rp, off, 64));
+    rd = fmax(rd, __shfl_xor(rd, off, 64));
+    rz = fmax(rz, __shfl_xor(rz, off, 64));
+  }
+  const int wv = tid >> 6, nw = (nt + 63) >> 6;
+  if ((tid & 63) == 0) {
+    red[0][wv] = rp;
+    red[1][wv] = rd;
+    red[2][wv] = rz;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < nw; ++w) {
+      rp = fmax(rp, red[0][w]);
+      rd = fmax(rd, red[1][w]);
+      rz = fmax(rz, red[2][w]);
     }
-    if (lane == 0 && g_first >= 0) {
-      atomicMax(&A.rmax[3 * g_first + 0], dbits(rp));
-      atomicMax(&A.rmax[3 * g_first + 1], dbits(rd));
-      atomicMax(&A.rmax[3 * g_first + 2], dbits(rz));
-    }
-  } else if (grid >= 0) {
-    atomicMax(&A.rmax[3 * grid + 0], dbits(rp));
-    atomicMax(&A.rmax[3 * grid + 1], dbits(rd));
-    atomicMax(&A.rmax[3 * grid + 2], dbits(rz));
+    A.tmax[3 * t + 0] = rp;
+    A.tmax[3 * t + 1] = rd;
+    A.tmax[3 * t + 2] = rz;
   }
 }
 
 struct CtlArgs {
   int G;
   GridCtl* ctl;
-  unsigned long long* rmax;
+  const double* tmax;     // [n_tiles][3] residual maxima per bus tile
+  const int* grid_tile;   // [G + 1] tiles of each grid
   double* hist;  // [G][kHistCap][6]
   double eps_pri, eps_dual, eps_z, beta_gamma, beta_omega, beta_max;
   int max_outer, max_inner;
 };
 
-// Control of Algorithm 1 per grid: inner test (r_pri, r_dual), overall test
-// (plus ||z||), outer step decision and the beta rule.
-__global__ void ctl_kernel(CtlArgs A) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= A.G) return;
+// Control of Algorithm 1 per grid, one block of kCtlBlock lanes per grid:
+// the residual maxima over the grid's bus tiles, then the inner test (r_pri,
+// r_dual), the overall test (plus ||z||), the outer step decision and the
+// beta rule.
+constexpr int kCtlBlock = 1024;
+__global__ __launch_bounds__(kCtlBlock) void ctl_kernel(CtlArgs A) {
+  const int g = blockIdx.x;
+  const int tid = threadIdx.x;
   GridCtl& c = A.ctl[g];
+  if (c.done) {
+    if (tid == 0) c.do_outer = 0;
+    return;
+  }
+  double rp = 0.0, rd = 0.0, rz = 0.0;
+  for (int t = A.grid_tile[g] + tid; t < A.grid_tile[g + 1]; t += kCtlBlock) {
+    rp = fmax(rp, A.tmax[3 * t + 0]);
+    rd = fmax(rd, A.tmax[3 * t + 1]);
+    rz = fmax(rz, A.tmax[3 * t + 2]);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    rp = fmax(rp, __shfl_xor(rp, off, 64));
+    rd = fmax(rd, __shfl_xor(rd, off, 64));
+    rz = fmax(rz, __shfl_xor(rz, off, 64));
+  }
+  __shared__ double red[3][kCtlBlock / 64];
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = rp;
+    red[1][tid >> 6] = rd;
+    red[2][tid >> 6] = rz;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  for (int w = 1; w < kCtlBlock / 64; ++w) {
+    rp = fmax(rp, red[0][w]);
+    rd = fmax(rd, red[1][w]);
+    rz = fmax(rz, red[2][w]);
+  }
   c.do_outer = 0;
-  if (c.done) return;
-  unsigned long long* rm = A.rmax + 3 * g;
-  const double rp = __longlong_as_double((long long)rm[0]);
-  const double rd = __longlong_as_double((long long)rm[1]);
-  const double rz = __longlong_as_double((long long)rm[2]);
-  rm[0] = 0;
-  rm[1] = 0;
-  rm[2] = 0;
   c.r_pri = rp;
   c.r_dual = rd;
   c.r_z = rz;
@@ -377,7 +457,7 @@ __global__ __launch_bounds__(256) void cold_kernel(ColdArgs A) {
 // Reset of the per-grid control words at the start of a solve of grid `only`
 // (all grids when only < 0).
 __global__ void ctl_start_kernel(GridCtl* ctl, int G, int only, int mode, int fixed,
-                                 double beta0, unsigned long long* rmax, int* failures) {
+                                 double beta0, int* failures) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G || (only >= 0 && g != only)) return;
   GridCtl& c = ctl[g];
@@ -396,9 +476,6 @@ __global__ void ctl_start_kernel(GridCtl* ctl, int G, int only, int mode, int fi
   c.fixed_mode = fixed > 0 ? 1 : 0;
   c.fixed_target = fixed > 0 ? c.inner_total + fixed : 0x7fffffff;
   failures[g] = 0;
-  rmax[3 * g + 0] = 0;
-  rmax[3 * g + 1] = 0;
-  rmax[3 * g + 2] = 0;
 }
 
 // Marks every grid idle (done) without touching its state.
@@ -488,10 +565,15 @@ struct acopf_s {
   double *adm, *vlo_i, *vhi_i, *vlo_j, *vhi_j, *rate2;
   double *u, *v, *z, *y, *lam, *bx, *ltil, *rtil;
   int *gptr, *eptr, *isref;
+  std::vector<int> gptr_h, eptr_h;  // host copies, for the bus tiles
+  int* tile = nullptr;               // [nb + 1] bus tiles of the bus kernel
+  int n_tiles = 0, tile_block = 0, ecap = 0, gcap = 0, tbmax = 0;
   double *pd, *qd, *gs, *bs;
   GridCtl* ctl;
   GridCtl* h_ctl = nullptr;  // pinned
-  unsigned long long *rmax, *stats;
+  unsigned long long* stats;
+  double* tmax;          // [nb + 1][3] residual maxima per bus tile
+  int* grid_tile;        // [G + 1] tile range of each grid
   int* failures;
   unsigned* pool;  // persistent x-step pool counters
   int n_cu = 0;
@@ -567,6 +649,47 @@ double now_s() {
       .count();
 }
 
+// Bus tiles for workgroups of `block` lanes: runs of consecutive buses of one
+// grid, at most block / 4 buses (four lanes per bus in the per-coupling
+// phases), whose branch ends and generators fit the LDS capacities (a single
+// bus beyond them gets a tile of its own and the kernel's global-memory
+// path). LDS per tile stays within 64 KiB.
+int build_tiles(acopf_s* h, int block) {
+  const int tb = std::max(1, block / 4);
+  const int budget = 65536 - 4 * 8 * tb;  // minus the per-bus results
+  const int gcap = std::max(16, tb);
+  int ecap = (budget - gcap * (16 + 2)) / (32 + 2);
+  ecap = std::max(1, std::min(ecap, 8 * tb));
+  std::vector<int> tiles, grid_tile;
+  tiles.reserve(h->nb / 8 + h->G + 1);
+  for (const HostGrid& H : h->grids) {
+    grid_tile.push_back((int)tiles.size());
+    int64_t b = H.bus_off;
+    const int64_t bend = H.bus_off + H.nb;
+    while (b < bend) {
+      tiles.push_back((int)b);
+      int64_t c = b;
+      while (c < bend && c - b < tb &&
+             h->eptr_h[c + 1] - h->eptr_h[b] <= ecap && h->gptr_h[c + 1] - h->gptr_h[b] <= gcap)
+        ++c;
+      b = std::max(c, b + 1);
+    }
+  }
+  grid_tile.push_back((int)tiles.size());
+  tiles.push_back((int)h->nb);
+  HIP_TRY(hipMemcpyAsync(h->tile, tiles.data(), sizeof(int) * tiles.size(),
+                         hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(h->grid_tile, grid_tile.data(), sizeof(int) * grid_tile.size(),
+                         hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->n_tiles = (int)tiles.size() - 1;
+  h->tile_block = block;
+  h->ecap = ecap;
+  h->gcap = gcap;
+  h->tbmax = tb;
+  return ACOPF_OK;
+}
+
 // Launch one inner iteration; with profiling, events bracket each launch.
 void launch_iteration(acopf_s* h, int slot) {
   hipStream_t s = h->stream;
@@ -581,16 +704,17 @@ void launch_iteration(acopf_s* h, int slot) {
   else
     acopf_dev::launch_xstep(ba, h->n6, h->tune.xstep_block, s);
   mark(1);
-  BusArgs bu{h->nb, h->ng, h->ne, h->bus_grid, h->ctl, h->gptr, h->eptr,
+  BusArgs bu{h->nb, h->ng, h->ne, h->tile, h->bus_grid, h->ctl, h->gptr, h->eptr,
              h->pd, h->qd, h->gs, h->bs, h->isref, h->u, h->lam, h->v, h->z, h->y,
-             h->P.rho_pq, h->P.rho_va, h->rmax};
-  const int bb = h->tune.bus_block;
-  hipLaunchKernelGGL(bus_kernel, dim3(blocks_for(h->nb, bb)), dim3(bb), 0, s, bu);
+             h->P.rho_pq, h->P.rho_va, h->tmax, h->ecap, h->gcap, h->tbmax};
+  const int bb = h->tile_block;
+  hipLaunchKernelGGL(bus_kernel, dim3(h->n_tiles), dim3(bb),
+                     bus_lds_bytes(h->tbmax, h->ecap, h->gcap), s, bu);
   mark(2);
-  CtlArgs ca{h->G, h->ctl, h->rmax, h->hist, h->P.eps_pri, h->P.eps_dual, h->P.eps_z,
+  CtlArgs ca{h->G, h->ctl, h->tmax, h->grid_tile, h->hist, h->P.eps_pri, h->P.eps_dual, h->P.eps_z,
              h->P.beta_gamma, h->P.beta_omega, h->P.beta_max, h->P.max_outer,
              h->P.max_inner};
-  hipLaunchKernelGGL(ctl_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, s, ca);
+  hipLaunchKernelGGL(ctl_kernel, dim3(h->G), dim3(kCtlBlock), 0, s, ca);
   mark(3);
   OuterArgs oa{h->m, h->ng, h->ne, h->gen_grid, h->end_grid, h->ctl, h->z, h->lam,
                h->P.lambda_max};
@@ -928,12 +1052,14 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   double** cp_d[] = {&h->u, &h->v, &h->z, &h->y, &h->lam};
   for (double** p : cp_d) HIP_TRY(D.alloc(p, m));
   HIP_TRY(D.alloc(&h->gptr, nb + 1));
+  HIP_TRY(D.alloc(&h->tile, nb + 1));
   HIP_TRY(D.alloc(&h->eptr, nb + 1));
   HIP_TRY(D.alloc(&h->isref, nb));
   double** bus_d[] = {&h->pd, &h->qd, &h->gs, &h->bs};
   for (double** p : bus_d) HIP_TRY(D.alloc(p, nb));
   HIP_TRY(D.alloc(&h->ctl, n_grids));
-  HIP_TRY(D.alloc(&h->rmax, 3 * n_grids));
+  HIP_TRY(D.alloc(&h->tmax, 3 * (nb + 1)));
+  HIP_TRY(D.alloc(&h->grid_tile, n_grids + 1));
   HIP_TRY(D.alloc(&h->stats, kStats));
   HIP_TRY(D.alloc(&h->failures, n_grids));
   HIP_TRY(D.alloc(&h->pool, 3));
@@ -962,6 +1088,8 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(up(h->vhi_j, vhi_j.data(), sizeof(double) * nl));
   HIP_TRY(up(h->rate2, rate2.data(), sizeof(double) * nl));
   HIP_TRY(up(h->gptr, gptr.data(), sizeof(int) * (nb + 1)));
+  h->gptr_h = gptr;
+  h->eptr_h = eptr;
   HIP_TRY(up(h->eptr, eptr.data(), sizeof(int) * (nb + 1)));
   HIP_TRY(up(h->isref, isref.data(), sizeof(int) * nb));
   HIP_TRY(up(h->pd, pd.data(), sizeof(double) * nb));
@@ -975,7 +1103,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(hipMemsetAsync(h->hist, 0, sizeof(double) * (size_t)n_grids * kHistCap * 6, st));
   HIP_TRY(hipMemsetAsync(h->ctl, 0, sizeof(GridCtl) * n_grids, st));
   HIP_TRY(hipStreamSynchronize(st));
-  return ACOPF_OK;
+  return build_tiles(h, h->tune.bus_block);
 }
 
 int acopf_create(const acopf_grid* grids, int32_t n_grids, const acopf_params* params,
@@ -998,7 +1126,7 @@ int acopf_create(const acopf_grid* grids, int32_t n_grids, const acopf_params* p
               h->u, h->v, h->z, h->y, h->lam, h->bx, h->ltil, h->rtil, h->P.al_rho0};
   hipLaunchKernelGGL(cold_kernel, dim3(blocks_for(h->ng + h->nl, 256)), dim3(256), 0, h->stream, ca);
   hipLaunchKernelGGL(ctl_start_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, h->stream,
-                     h->ctl, h->G, -1, (int)ACOPF_COLD, 0, h->P.beta0, h->rmax, h->failures);
+                     h->ctl, h->G, -1, (int)ACOPF_COLD, 0, h->P.beta0, h->failures);
   hipLaunchKernelGGL(ctl_idle_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, h->stream,
                      h->ctl, h->G);
   h->t_start.assign(h->G, 0.0);
@@ -1067,7 +1195,7 @@ static int start_impl(acopf_s* h, int grid, int mode, int fixed_iters) {
     hipLaunchKernelGGL(cold_kernel, dim3(blocks_for(h->ng + h->nl, 256)), dim3(256), 0, st, ca);
   }
   hipLaunchKernelGGL(ctl_start_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, st, h->ctl,
-                     h->G, grid, mode, fixed_iters, h->P.beta0, h->rmax, h->failures);
+                     h->G, grid, mode, fixed_iters, h->P.beta0, h->failures);
   HIP_TRY(hipGetLastError());
   const double t = now_s();
   for (int g = 0; g < h->G; ++g)
@@ -1483,13 +1611,22 @@ static int check_tuning(const acopf_tuning& t) {
   return ACOPF_OK;
 }
 
+static int apply_tuning(acopf_s* h, const acopf_tuning& t) {
+  drop_graph(h);
+  if (t.bus_block != h->tile_block) {
+    int rc = build_tiles(h, t.bus_block);
+    if (rc) return rc;
+  }
+  h->tune = t;
+  return ACOPF_OK;
+}
+
 int acopf_set_tuning(acopf_handle h, const acopf_tuning* t) {
   if (!h || !t) return fail(ACOPF_EINVAL, "null argument");
   int rc = check_tuning(*t);
   if (rc) return rc;
-  h->tune = *t;
-  drop_graph(h);
-  return ACOPF_OK;
+  HIP_TRY(hipSetDevice(h->device));
+  return apply_tuning(h, *t);
 }
 
 int acopf_get_tuning(acopf_handle h, acopf_tuning* t) {
@@ -1513,13 +1650,13 @@ int acopf_autotune(acopf_handle h, int32_t iters, acopf_tuning* out) {
   // x-step variants: one lane per branch at three block sizes, or the
   // persistent kernel at one or two wavefronts per SIMD
   const int xs[5][2] = {{64, 0}, {128, 0}, {256, 0}, {64, 1}, {64, 2}};
-  const int bs[4] = {64, 128, 256, 512}, cs[3] = {8, 16, 32};
+  const int bs[4] = {128, 256, 512, 1024}, cs[3] = {8, 16, 32};
   for (const auto& xi : xs)
     for (int bi : bs)
       for (int ci : cs) {
         acopf_tuning t{xi[0], bi, ci, 1, xi[1]};
-        h->tune = t;
-        drop_graph(h);
+        rc = apply_tuning(h, t);
+        if (rc) return rc;
         double tmin = 1e300;
         for (int rep = 0; rep < 2; ++rep) {  // first pass also captures the graph
           rc = acopf_snapshot(h, 1);
@@ -1537,8 +1674,8 @@ int acopf_autotune(acopf_handle h, int32_t iters, acopf_tuning* out) {
           best = t;
         }
       }
-  h->tune = best;
-  drop_graph(h);
+  rc = apply_tuning(h, best);
+  if (rc) return rc;
   rc = acopf_snapshot(h, 1);
   if (rc) return rc;
   h->running = run0;

@@ -134,6 +134,35 @@ def test_edge_grids_match_oracle(waves):
             compare(s, orc, tol=1e-9, label=name)
 
 
+def star_grid(n_leaf: int, n_gen: int, seed: int):
+    """One hub bus joined to n_leaf leaves, with every generator on the hub:
+    at a bus block of 64 lanes the hub's branch ends and generators exceed the
+    bus kernel's LDS capacities, so its global-memory path runs."""
+    g = gridgen(n_leaf + 1, n_gen, n_leaf, 0.3, seed, load_factor=0.2)
+    g.br_from = np.zeros(n_leaf, dtype=g.br_from.dtype)
+    g.br_to = np.arange(1, n_leaf + 1, dtype=g.br_to.dtype)
+    g.gen_bus = np.zeros(n_gen, dtype=g.gen_bus.dtype)
+    g.ref_bus = 0
+    return g
+
+
+def test_high_degree_bus_matches_oracle():
+    note("star grid: hub of degree 300 with 40 generators, bus blocks 64 and 256")
+    g = star_grid(300, 40, 35)
+    p = A.Params(rho_pq=400.0, rho_va=4000.0)
+    orc = O.Oracle(g, oparams(p))
+    orc.solve(30)
+    out = []
+    for bb in (64, 256):
+        with A.Solver(g, p) as s:
+            s.set_tuning(bus_block=bb)
+            s.solve(A.COLD, 30)
+            compare(s, orc, tol=1e-9, label=f"star bus_block {bb}")
+            out.append({k: s.get(k) for k in VECS + ("rtil",)})
+    for k in out[0]:
+        np.testing.assert_array_equal(out[0][k], out[1][k])
+
+
 def test_batch_equals_alone():
     note("batch vs alone")
     gs = [gridgen(50 + 13 * k, 8 + k, 70 + 17 * k, 0.6, 40 + k) for k in range(3)]
