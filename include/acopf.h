@@ -224,9 +224,11 @@ int acopf_get_sizes(acopf_handle h, int32_t grid, int64_t* out4);
  * Errors: EINVAL, EDEVICE. */
 int acopf_set_profiling(acopf_handle h, int32_t on);
 
-/* Average device time (ms) per launch over the last solve run with
- * profiling on: out[0] x-step (generators and branches), out[1] bus/z/y/
- * residual step, out[2] control, out[3] outer update; out[4] = number of
+/* Average device time (ms) per launch over every iteration run with
+ * profiling on since the handle was created: out[0] x-step (generators and
+ * branches), out[1] bus/z/y/residual step, out[2] control (which also
+ * applies the outer multiplier step when one ends), out[3] = 0 (kept for
+ * layout: the outer step has no launch of its own); out[4] = number of
  * iterations timed. Errors: EINVAL. */
 int acopf_get_timing(acopf_handle h, double* out5);
 

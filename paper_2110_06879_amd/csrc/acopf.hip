@@ -1,14 +1,15 @@
 // Host runtime and the closed-form kernels of the two-level component ADMM
 // for ACOPF (Kim & Kim, PSCC 2022) on gfx950, behind the C ABI of acopf.h.
 //
-// One inner iteration of Algorithm 1 is four launches on one stream:
+// One inner iteration of Algorithm 1 is three launches on one stream:
 //   xstep_kernel    branch subproblems, eq. (branch), TRON + AL     lane/branch
 //                   and the generator closed form, eq. (qp-bound)   lane/gen
 //   bus_kernel      bus closed form eq. (qp-bus), then z and y and
 //                   the residual maxima of every coupling it owns  block/tile
 //                                                                  of buses
 //   ctl_kernel      termination tests and the outer beta rule       block/grid
-//   outer_kernel    lambda <- proj(lambda + beta z) when flagged    lane/coupling
+//                   and, when an outer step ends, lambda <- proj(lambda
+//                   + beta z) over the grid's couplings
 // The generator and branch steps read only the previous iteration's v, z, y
 // and so could run in any order; the bus step owns each coupling exactly once
 // (every coupling has one bus side), which makes the z and y updates and the
@@ -67,8 +68,8 @@ int fail(int code, const std::string& msg) {
 
 constexpr int kHistCap = 1 << 15;  // per grid, inner iterations kept in history
 constexpr int kStats = 16;
-constexpr int kEvPerIter = 5;   // events per profiled iteration
-constexpr int kTimed = 4;       // kernels timed per iteration
+constexpr int kEvPerIter = 4;   // events per profiled iteration
+constexpr int kTimed = 3;       // kernels timed per iteration (x-step, bus, ctl)
 constexpr int kChunk = 16;      // iterations between control readbacks
 
 // ---------------------------------------------------------------------------
@@ -266,15 +267,74 @@ struct CtlArgs {
   GridCtl* ctl;
   const double* tmax;     // [n_tiles][3] residual maxima per bus tile
   const int* grid_tile;   // [G + 1] tiles of each grid
+  const int64_t* gen_off; // [G + 1] generators of each grid
+  const int64_t* end_off; // [G + 1] branch ends of each grid
+  int64_t ng, ne;
+  const double* z;
+  double* lam;
+  double lambda_max;
   double* hist;  // [G][kHistCap][6]
   double eps_pri, eps_dual, eps_z, beta_gamma, beta_omega, beta_max;
   int max_outer, max_inner;
 };
 
+// Termination tests, outer step decision and beta rule of Algorithm 1 for
+// grid g, given its residual maxima; returns whether the outer step is due.
+__device__ int ctl_decide(const CtlArgs& A, int g, GridCtl& c, double rp, double rd, double rz) {
+  c.do_outer = 0;
+  c.r_pri = rp;
+  c.r_dual = rd;
+  c.r_z = rz;
+  if (c.inner_total < kHistCap) {
+    double* h = A.hist + ((int64_t)g * kHistCap + c.inner_total) * 6;
+    h[0] = rp;
+    h[1] = rd;
+    h[2] = rz;
+    h[3] = 0.0;
+    h[4] = c.beta;
+    h[5] = (double)c.outer;
+  }
+  c.inner_total += 1;
+  c.inner_in_outer += 1;
+  if (!isfinite(rp) || !isfinite(rd) || !isfinite(rz)) {
+    c.status = ACOPF_NUMERICAL;
+    c.done = 1;
+    return 0;
+  }
+  const bool inner_ok = rp <= A.eps_pri && rd <= A.eps_dual;
+  const bool fixed = c.fixed_mode != 0;
+  if (!fixed && inner_ok && rz <= A.eps_z) {
+    c.status = ACOPF_CONVERGED;
+    c.done = 1;
+    return 0;
+  }
+  if (inner_ok || c.inner_in_outer >= A.max_inner) {
+    c.do_outer = 1;
+    c.beta_lam = c.beta;
+    if (rz > A.beta_omega * c.znorm_prev) {
+      const double b = A.beta_gamma * c.beta;
+      c.beta = b < A.beta_max ? b : A.beta_max;
+    }
+    c.znorm_prev = rz;
+    c.outer += 1;
+    c.inner_in_outer = 0;
+    if (!fixed && c.outer >= A.max_outer) {
+      c.status = ACOPF_MAX_ITER;
+      c.done = 1;
+    }
+  }
+  if (fixed && c.inner_total >= c.fixed_target) {
+    c.status = ACOPF_MAX_ITER;
+    c.done = 1;
+  }
+  return c.do_outer;
+}
+
 // Control of Algorithm 1 per grid, one block of kCtlBlock lanes per grid:
-// the residual maxima over the grid's bus tiles, then the inner test (r_pri,
-// r_dual), the overall test (plus ||z||), the outer step decision and the
-// beta rule.
+// the residual maxima over the grid's bus tiles, the decisions above, and,
+// on the (rare) iterations that end an outer step, the multiplier update
+// lambda <- proj_[-lmax, lmax](lambda + beta z) of Sec. III-B over the grid's
+// couplings by the same block, so no launch is spent on it otherwise.
 constexpr int kCtlBlock = 1024;
 __global__ __launch_bounds__(kCtlBlock) void ctl_kernel(CtlArgs A) {
   const int g = blockIdx.x;
@@ -296,90 +356,36 @@ __global__ __launch_bounds__(kCtlBlock) void ctl_kernel(CtlArgs A) {
     rz = fmax(rz, __shfl_xor(rz, off, 64));
   }
   __shared__ double red[3][kCtlBlock / 64];
+  __shared__ int s_outer;
+  __shared__ double s_beta;
   if ((tid & 63) == 0) {
     red[0][tid >> 6] = rp;
     red[1][tid >> 6] = rd;
     red[2][tid >> 6] = rz;
   }
   __syncthreads();
-  if (tid != 0) return;
-  for (int w = 1; w < kCtlBlock / 64; ++w) {
-    rp = fmax(rp, red[0][w]);
-    rd = fmax(rd, red[1][w]);
-    rz = fmax(rz, red[2][w]);
-  }
-  c.do_outer = 0;
-  c.r_pri = rp;
-  c.r_dual = rd;
-  c.r_z = rz;
-  if (c.inner_total < kHistCap) {
-    double* h = A.hist + ((int64_t)g * kHistCap + c.inner_total) * 6;
-    h[0] = rp;
-    h[1] = rd;
-    h[2] = rz;
-    h[3] = 0.0;
-    h[4] = c.beta;
-    h[5] = (double)c.outer;
-  }
-  c.inner_total += 1;
-  c.inner_in_outer += 1;
-  if (!isfinite(rp) || !isfinite(rd) || !isfinite(rz)) {
-    c.status = ACOPF_NUMERICAL;
-    c.done = 1;
-    return;
-  }
-  const bool inner_ok = rp <= A.eps_pri && rd <= A.eps_dual;
-  const bool fixed = c.fixed_mode != 0;
-  if (!fixed && inner_ok && rz <= A.eps_z) {
-    c.status = ACOPF_CONVERGED;
-    c.done = 1;
-    return;
-  }
-  if (inner_ok || c.inner_in_outer >= A.max_inner) {
-    c.do_outer = 1;
-    c.beta_lam = c.beta;
-    if (rz > A.beta_omega * c.znorm_prev) {
-      const double b = A.beta_gamma * c.beta;
-      c.beta = b < A.beta_max ? b : A.beta_max;
+  if (tid == 0) {
+    for (int w = 1; w < kCtlBlock / 64; ++w) {
+      rp = fmax(rp, red[0][w]);
+      rd = fmax(rd, red[1][w]);
+      rz = fmax(rz, red[2][w]);
     }
-    c.znorm_prev = rz;
-    c.outer += 1;
-    c.inner_in_outer = 0;
-    if (!fixed && c.outer >= A.max_outer) {
-      c.status = ACOPF_MAX_ITER;
-      c.done = 1;
-    }
+    s_outer = ctl_decide(A, g, c, rp, rd, rz);
+    s_beta = c.beta_lam;
   }
-  if (fixed && c.inner_total >= c.fixed_target) {
-    c.status = ACOPF_MAX_ITER;
-    c.done = 1;
+  __syncthreads();
+  if (!s_outer) return;
+  const double bl = s_beta, lm = A.lambda_max;
+  auto update = [&](int64_t k) {
+    const double t = A.lam[k] + bl * A.z[k];
+    A.lam[k] = fmax(-lm, fmin(lm, t));
+  };
+  for (int64_t k = A.gen_off[g] + tid; k < A.gen_off[g + 1]; k += kCtlBlock) {
+    update(k);
+    update(A.ng + k);
   }
-}
-
-struct OuterArgs {
-  int64_t m, ng, ne;
-  const int *gen_grid, *end_grid;
-  const GridCtl* ctl;
-  const double* z;
-  double* lam;
-  double lambda_max;
-};
-
-__device__ inline int coupling_grid(int64_t k, int64_t ng, int64_t ne, const int* gen_grid,
-                                    const int* end_grid) {
-  if (k < 2 * ng) return gen_grid[k < ng ? k : k - ng];
-  return end_grid[(k - 2 * ng) % ne];
-}
-
-// lambda <- proj_[-lmax, lmax](lambda + beta z) (multiplier updates, Sec. III-B)
-__global__ __launch_bounds__(256) void outer_kernel(OuterArgs A) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= A.m) return;
-  const int g = coupling_grid(k, A.ng, A.ne, A.gen_grid, A.end_grid);
-  const GridCtl& c = A.ctl[g];
-  if (!c.do_outer) return;
-  const double t = A.lam[k] + c.beta_lam * A.z[k];
-  A.lam[k] = fmax(-A.lambda_max, fmin(A.lambda_max, t));
+  for (int64_t e = A.end_off[g] + tid; e < A.end_off[g + 1]; e += kCtlBlock)
+    for (int b = 0; b < 4; ++b) update(2 * A.ng + b * A.ne + e);
 }
 
 struct ColdArgs {
@@ -579,6 +585,7 @@ struct acopf_s {
   int n_cu = 0;
   double* hist;
   int64_t* gen_off_d;
+  int64_t* end_off_d;  // [G + 1] branch-end range of each grid
   double *base_d, *obj_d;
   bool solved = false;
   bool profile = false;
@@ -591,7 +598,7 @@ struct acopf_s {
   std::vector<char> started_once;
   std::vector<void*> snap;             // device snapshot buffers (lazy)
   std::vector<hipEvent_t> ev;
-  double t_ms[kTimed] = {0, 0, 0, 0};
+  double t_ms[kTimed] = {0, 0, 0};
   int64_t t_iters = 0;
 };
 
@@ -711,15 +718,12 @@ void launch_iteration(acopf_s* h, int slot) {
   hipLaunchKernelGGL(bus_kernel, dim3(h->n_tiles), dim3(bb),
                      bus_lds_bytes(h->tbmax, h->ecap, h->gcap), s, bu);
   mark(2);
-  CtlArgs ca{h->G, h->ctl, h->tmax, h->grid_tile, h->hist, h->P.eps_pri, h->P.eps_dual, h->P.eps_z,
+  CtlArgs ca{h->G, h->ctl, h->tmax, h->grid_tile, h->gen_off_d, h->end_off_d, h->ng, h->ne,
+             h->z, h->lam, h->P.lambda_max, h->hist, h->P.eps_pri, h->P.eps_dual, h->P.eps_z,
              h->P.beta_gamma, h->P.beta_omega, h->P.beta_max, h->P.max_outer,
              h->P.max_inner};
   hipLaunchKernelGGL(ctl_kernel, dim3(h->G), dim3(kCtlBlock), 0, s, ca);
   mark(3);
-  OuterArgs oa{h->m, h->ng, h->ne, h->gen_grid, h->end_grid, h->ctl, h->z, h->lam,
-               h->P.lambda_max};
-  hipLaunchKernelGGL(outer_kernel, dim3(blocks_for(h->m, 256)), dim3(256), 0, s, oa);
-  mark(4);
 }
 
 int validate_grid(const acopf_grid& g, int idx) {
@@ -1065,6 +1069,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(D.alloc(&h->pool, 3));
   HIP_TRY(D.alloc(&h->hist, (size_t)n_grids * kHistCap * 6));
   HIP_TRY(D.alloc(&h->gen_off_d, n_grids + 1));
+  HIP_TRY(D.alloc(&h->end_off_d, n_grids + 1));
   HIP_TRY(D.alloc(&h->base_d, n_grids));
   HIP_TRY(D.alloc(&h->obj_d, n_grids));
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->h_ctl), sizeof(GridCtl) * n_grids,
@@ -1097,6 +1102,10 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(up(h->gs, gs.data(), sizeof(double) * nb));
   HIP_TRY(up(h->bs, bs.data(), sizeof(double) * nb));
   HIP_TRY(up(h->gen_off_d, gen_off.data(), sizeof(int64_t) * (n_grids + 1)));
+  std::vector<int64_t> end_off(n_grids + 1);
+  for (int g = 0; g < n_grids; ++g) end_off[g] = h->grids[g].e0;
+  end_off[n_grids] = 2 * nl;
+  HIP_TRY(up(h->end_off_d, end_off.data(), sizeof(int64_t) * (n_grids + 1)));
   HIP_TRY(up(h->base_d, base.data(), sizeof(double) * n_grids));
   HIP_TRY(hipMemsetAsync(h->stats, 0, sizeof(unsigned long long) * kStats, st));
   HIP_TRY(hipMemsetAsync(h->pool, 0, sizeof(unsigned) * 3, st));
@@ -1702,7 +1711,8 @@ int acopf_get_timing(acopf_handle h, double* out5) {
   if (!h || !out5) return fail(ACOPF_EINVAL, "null argument");
   const double n = h->t_iters > 0 ? (double)h->t_iters : 1.0;
   for (int k = 0; k < kTimed; ++k) out5[k] = h->t_ms[k] / n;
-  out5[kTimed] = (double)h->t_iters;
+  out5[3] = 0.0;  // the outer multiplier step runs inside ctl_kernel
+  out5[4] = (double)h->t_iters;
   return ACOPF_OK;
 }
 

@@ -81,6 +81,23 @@ def test_fixed_iterations_match_oracle(name, iters, waves):
         assert sg["flops"] == so["flops"]
 
 
+def test_outer_steps_match_oracle():
+    """max_inner = 10 forces an outer step (lambda and beta update of
+    Algorithm 1) every ten inner iterations: 55 iterations cross five."""
+    note("parity c2 with an outer step every 10 inner iterations")
+    g = config_grid("c2_2kbus")
+    p = A.Params(max_inner=10)
+    orc = O.Oracle(g, oparams(p))
+    orc.solve(55)
+    assert orc.history()[-1, 5] == 5
+    with A.Solver(g, p) as s:
+        s.solve(A.COLD, 55)
+        compare(s, orc, label="c2 outer")
+        assert np.abs(orc.get("lam")).max() > 0
+        np.testing.assert_array_equal(s.history()[:, 5], orc.history()[:, 5])
+        np.testing.assert_array_equal(s.history()[:, 4], orc.history()[:, 4])
+
+
 def test_c1_200_iterations_objective():
     note("parity c1 200 iterations objective")
     g = config_grid("c1_30bus")
