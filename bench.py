@@ -67,6 +67,7 @@ def main():
     g = config_grid("c3_70kbus")
     params = A.Params()
     s = A.Solver(g, params, device=0)
+    tuning = s.tuning()
     n_branch = g.n_branch
 
     # ---- warmup, then the timed region: K inner iterations
@@ -98,9 +99,12 @@ def main():
     x_ms = tim["xstep_ms"]
     flops_per_launch = flops / max(launches, 1)
     achieved_tflops = flops_per_launch / (x_ms * 1e-3) / 1e12
-    # algorithmic bytes of the bus/z/y step (HBM bound), per launch
+    # algorithmic bytes of the bus/z/y step (HBM bound), per launch: every
+    # coupling reads u, z, y, v, lambda and writes v, z, y (64 B); every bus
+    # reads p_d, q_d, g_s, b_s, its reference flag, grid id and two CSR
+    # offsets (48 B)
     m = g.n_coupling
-    bus_bytes = 64 * m + 4 * m + 4 * g.n_bus + 32 * g.n_bus
+    bus_bytes = 64 * m + 48 * g.n_bus
     bus_gbs = bus_bytes / (tim["bus_ms"] * 1e-3) / 1e9
 
     # ---- cold solve to convergence and warm-start latency
@@ -159,7 +163,8 @@ def main():
         "config": {"workload": "synthetic 70k-bus grid: 70,000 buses, 10,000 generators, "
                                "88,000 branches (26,400 with line limits), load factor 0.2",
                    "n_bus": g.n_bus, "n_gen": g.n_gen, "n_branch": n_branch,
-                   "n_rated": g.n_rated, "step": "one inner ADMM iteration (all kernels)"},
+                   "n_rated": g.n_rated, "step": "one inner ADMM iteration (all kernels)",
+                   "tuning": tuning},
         "roofline": {"bound": "alu", "kernel": "xstep_kernel (branch TRON + generators)",
                      "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / FP64_PEAK_TFLOPS, "traffic": None,
