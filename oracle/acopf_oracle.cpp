@@ -64,13 +64,22 @@ inline bool operator>=(CR a, CR b) { return a.v >= b.v; }
 inline bool operator==(CR a, CR b) { return a.v == b.v; }
 inline bool operator!=(CR a, CR b) { return a.v != b.v; }
 inline CR sqrt(CR a) { ++g_tally.sqrt_; return CR(std::sqrt(a.v)); }
+// Fused multiply-add a*b + c with one rounding (IEEE 754 fusedMultiplyAdd),
+// counted as one multiplication and one addition.
+inline CR rfma(CR a, CR b, CR c) {
+  ++g_tally.mul;
+  ++g_tally.addsub;
+  return CR(std::fma(a.v, b.v, c.v));
+}
+inline double rfma(double a, double b, double c) { return std::fma(a, b, c); }
 inline double val(CR a) { return a.v; }
 inline double val(double a) { return a; }
 
 // sin and cos of the branch angle difference: Cody-Waite reduction by pi/2
 // (pi/2 split into a 33-bit head and a tail, so k * head is exact) followed
 // by the Taylor series of sin and cos on |r| <= pi/4, truncated after r^17
-// and r^18 (remainders below 1e-19), evaluated by Horner's rule. Written out
+// and r^18 (remainders below 1e-19), evaluated by Horner's rule with fused
+// multiply-adds. Written out
 // here rather than taken from the C library so that the result is a fixed
 // sequence of IEEE operations.
 constexpr double kPio2Hi = 1.5707963267341256;       // 0x1.921fb544p+0
@@ -88,14 +97,14 @@ constexpr double kCosC[9] = {-0.5, 0.041666666666666664, -0.001388888888888889,
 
 inline void series_sincos(double x, double* s, double* c) {
   const double k = std::nearbyint(x * kTwoOverPi);
-  const double r = (x - k * kPio2Hi) - k * kPio2Lo;
+  const double r = std::fma(-k, kPio2Lo, std::fma(-k, kPio2Hi, x));
   const double r2 = r * r;
   double ps = kSinC[7];
-  for (int j = 6; j >= 0; --j) ps = kSinC[j] + r2 * ps;
+  for (int j = 6; j >= 0; --j) ps = std::fma(r2, ps, kSinC[j]);
   double pc = kCosC[8];
-  for (int j = 7; j >= 0; --j) pc = kCosC[j] + r2 * pc;
-  const double sr = r + r * (r2 * ps);
-  const double cr = 1.0 + r2 * pc;
+  for (int j = 7; j >= 0; --j) pc = std::fma(r2, pc, kCosC[j]);
+  const double sr = std::fma(r, r2 * ps, r);
+  const double cr = std::fma(r2, pc, 1.0);
   const long long q = static_cast<long long>(k) & 3;
   if (q == 0) { *s = sr; *c = cr; }
   else if (q == 1) { *s = cr; *c = -sr; }
@@ -182,18 +191,18 @@ template <class R>
 R model_q(int n, const R* g, const R* H, const R* s) {
   R gs = R(0.0), sHs = R(0.0);
   for (int i = 0; i < n; ++i) {
-    gs = gs + g[i] * s[i];
+    gs = rfma(g[i], s[i], gs);
     R hi = R(0.0);
-    for (int j = 0; j < n; ++j) hi = hi + H[i * n + j] * s[j];
-    sHs = sHs + s[i] * hi;
+    for (int j = 0; j < n; ++j) hi = rfma(H[i * n + j], s[j], hi);
+    sHs = rfma(s[i], hi, sHs);
   }
-  return gs + R(0.5) * sHs;
+  return rfma(R(0.5), sHs, gs);
 }
 
 template <class R>
 R dotv(int n, const R* a, const R* b) {
   R t = R(0.0);
-  for (int i = 0; i < n; ++i) t = t + a[i] * b[i];
+  for (int i = 0; i < n; ++i) t = rfma(a[i], b[i], t);
   return t;
 }
 
@@ -234,7 +243,7 @@ void cauchy_step(int n, const R* x, const R* g, const R* H, const double* lo,
   R s[NMAX], wt[NMAX], st2[NMAX];
   auto trial = [&](R a, R* wout, R* sout) {
     for (int i = 0; i < n; ++i) {
-      wout[i] = clampd(x[i] - a * g[i], lo[i], hi[i]);
+      wout[i] = clampd(rfma(-a, g[i], x[i]), lo[i], hi[i]);
       sout[i] = wout[i] - x[i];
     }
   };
@@ -274,13 +283,13 @@ bool cholesky(int m, const R* A, R* L) {
   for (int i = 0; i < m * m; ++i) L[i] = R(0.0);
   for (int j = 0; j < m; ++j) {
     R d = A[j * m + j];
-    for (int k = 0; k < j; ++k) d = d - L[j * m + k] * L[j * m + k];
+    for (int k = 0; k < j; ++k) d = rfma(-L[j * m + k], L[j * m + k], d);
     if (!(d > R(0.0))) return false;
     R ljj = rsqrt_(d);
     L[j * m + j] = ljj;
     for (int i = j + 1; i < m; ++i) {
       R t = A[i * m + j];
-      for (int k = 0; k < j; ++k) t = t - L[i * m + k] * L[j * m + k];
+      for (int k = 0; k < j; ++k) t = rfma(-L[i * m + k], L[j * m + k], t);
       L[i * m + j] = t / ljj;
     }
   }
@@ -293,12 +302,12 @@ void precond(int m, const R* L, const R* D, const R* r, R* z) {
   R t[NMAX];
   for (int i = 0; i < m; ++i) {
     R a = D[i] * r[i];
-    for (int k = 0; k < i; ++k) a = a - L[i * m + k] * t[k];
+    for (int k = 0; k < i; ++k) a = rfma(-L[i * m + k], t[k], a);
     t[i] = a / L[i * m + i];
   }
   for (int i = m - 1; i >= 0; --i) {
     R a = t[i];
-    for (int k = i + 1; k < m; ++k) a = a - L[k * m + i] * z[k];
+    for (int k = i + 1; k < m; ++k) a = rfma(-L[k * m + i], z[k], a);
     z[i] = a / L[i * m + i];
   }
   for (int i = 0; i < m; ++i) z[i] = D[i] * z[i];
@@ -320,7 +329,7 @@ void subspace_step(int n, const R* x, const R* g, const R* H, const double* lo,
     R gq[NMAX];
     for (int i = 0; i < n; ++i) {
       R t = g[i];
-      for (int j = 0; j < n; ++j) t = t + H[i * n + j] * s[j];
+      for (int j = 0; j < n; ++j) t = rfma(H[i * n + j], s[j], t);
       gq[i] = t;
     }
     R r[NMAX], B[NMAX * NMAX];
@@ -366,7 +375,7 @@ void subspace_step(int n, const R* x, const R* g, const R* H, const double* lo,
       ++st->cg_iters;
       for (int a = 0; a < nf; ++a) {
         R t = R(0.0);
-        for (int b = 0; b < nf; ++b) t = t + B[a * nf + b] * p[b];
+        for (int b = 0; b < nf; ++b) t = rfma(B[a * nf + b], p[b], t);
         Bp[a] = t;
       }
       R pBp = dotv(nf, p, Bp);
@@ -376,29 +385,29 @@ void subspace_step(int n, const R* x, const R* g, const R* H, const double* lo,
       for (int a = 0; a < nf; ++a) { sd[F[a]] = s[F[a]] + d[a]; pf[F[a]] = p[a]; }
       if (!(pBp > R(0.0))) {
         R tau = to_boundary(n, sd, pf, delta);
-        for (int a = 0; a < nf; ++a) d[a] = d[a] + tau * p[a];
+        for (int a = 0; a < nf; ++a) d[a] = rfma(tau, p[a], d[a]);
         boundary = true;
         break;
       }
       R alpha = rz / pBp;
       R tr[NMAX];
-      for (int i = 0; i < n; ++i) tr[i] = sd[i] + alpha * pf[i];
+      for (int i = 0; i < n; ++i) tr[i] = rfma(alpha, pf[i], sd[i]);
       if (rsqrt_(dotv(n, tr, tr)) >= delta) {
         R tau = to_boundary(n, sd, pf, delta);
-        for (int a = 0; a < nf; ++a) d[a] = d[a] + tau * p[a];
+        for (int a = 0; a < nf; ++a) d[a] = rfma(tau, p[a], d[a]);
         boundary = true;
         break;
       }
       for (int a = 0; a < nf; ++a) {
-        d[a] = d[a] + alpha * p[a];
-        res[a] = res[a] - alpha * Bp[a];
+        d[a] = rfma(alpha, p[a], d[a]);
+        res[a] = rfma(-alpha, Bp[a], res[a]);
       }
       if (rsqrt_(dotv(nf, res, res)) <= R(C.cgtol) * rnorm0) break;
       precond(nf, L, D, res, zz);
       R rzn = dotv(nf, res, zz);
       R bcg = rzn / rz;
       rz = rzn;
-      for (int a = 0; a < nf; ++a) p[a] = zz[a] + bcg * p[a];
+      for (int a = 0; a < nf; ++a) p[a] = rfma(bcg, p[a], zz[a]);
     }
     // projected search along d from w
     R qw = model_q(n, g, H, s);
@@ -410,13 +419,13 @@ void subspace_step(int n, const R* x, const R* g, const R* H, const double* lo,
       for (int i = 0; i < n; ++i) wt[i] = w[i];
       for (int a = 0; a < nf; ++a) {
         int i = F[a];
-        wt[i] = clampd(w[i] + beta * d[a], lo[i], hi[i]);
+        wt[i] = clampd(rfma(beta, d[a], w[i]), lo[i], hi[i]);
       }
       for (int i = 0; i < n; ++i) stv[i] = wt[i] - x[i];
       R dw[NMAX];
       for (int i = 0; i < n; ++i) dw[i] = wt[i] - w[i];
       R qt = model_q(n, g, H, stv);
-      if (qt <= qw + R(C.mu0) * dotv(n, gq, dw)) { acc = true; break; }
+      if (qt <= rfma(R(C.mu0), dotv(n, gq, dw), qw)) { acc = true; break; }
       beta = beta * R(0.5);
     }
     if (!acc) break;
@@ -442,7 +451,7 @@ int tron(P& prob, int n, R* x, const double* lo, const double* hi,
   R pg2 = R(0.0);
   for (int i = 0; i < n; ++i) {
     R t = clampd(x[i] - g[i], lo[i], hi[i]) - x[i];
-    pg2 = pg2 + t * t;
+    pg2 = rfma(t, t, pg2);
   }
   R delta = rsqrt_(pg2);
   if (!(delta > R(0.0))) delta = R(1.0);
@@ -521,10 +530,10 @@ void branch_values(const BranchData& d, const R* x, R* a, R* aux) {
   R wi = vi * vi, wj = vj * vj;
   R gii = d.gii, bii = d.bii, gij = d.gij, bij = d.bij, gji = d.gji,
     bji = d.bji, gjj = d.gjj, bjj = d.bjj;
-  a[0] = gii * wi + gij * WR + bij * WI;
-  a[1] = -bii * wi - bij * WR + gij * WI;
-  a[2] = gjj * wj + gji * WR - bji * WI;
-  a[3] = -bjj * wj - bji * WR - gji * WI;
+  a[0] = rfma(bij, WI, rfma(gij, WR, gii * wi));
+  a[1] = rfma(gij, WI, rfma(-bij, WR, -bii * wi));
+  a[2] = rfma(-bji, WI, rfma(gji, WR, gjj * wj));
+  a[3] = rfma(-gji, WI, rfma(-bji, WR, -bjj * wj));
   a[4] = wi;
   a[5] = ti;
   a[6] = wj;
@@ -564,15 +573,15 @@ void flow_derivs(const BranchData& d, const R* x, const R* aux, R (*ga)[4],
     R tw = k < 2 ? twvi : twvj;
     for (int p = 0; p < 4; ++p) {
       if (p == own)
-        ga[k][p] = coef[k][0] * tw + coef[k][1] * dWR[p] + coef[k][2] * dWI[p];
+        ga[k][p] = rfma(coef[k][2], dWI[p], rfma(coef[k][1], dWR[p], coef[k][0] * tw));
       else
-        ga[k][p] = coef[k][1] * dWR[p] + coef[k][2] * dWI[p];
+        ga[k][p] = rfma(coef[k][2], dWI[p], coef[k][1] * dWR[p]);
     }
     for (int t = 0; t < 10; ++t) {
       if (t == 0 || t == 4)  // (0,0), (1,1): only the w_own term
         Ha[k][t] = (t == 0) == (own == 0) ? R(2.0) * coef[k][0] : R(0.0);
       else
-        Ha[k][t] = coef[k][1] * hWR[t] + coef[k][2] * hWI[t];
+        Ha[k][t] = rfma(coef[k][2], hWI[t], coef[k][1] * hWR[t]);
     }
   }
 }
@@ -590,12 +599,12 @@ struct BranchProblem {
     R F = R(0.0);
     for (int k = 0; k < 8; ++k) {
       R r = a[k] - R(d.vb[k]) + R(d.z[k]);
-      F = F + R(d.y[k]) * r + R(0.5) * R(d.rho[k]) * r * r;
+      F = rfma(R(0.5) * R(d.rho[k]) * r, r, rfma(R(d.y[k]), r, F));
     }
     if (d.n == 6) {
       for (int e = 0; e < 2; ++e) {
-        R c = a[2 * e] * a[2 * e] + a[2 * e + 1] * a[2 * e + 1] + x[4 + e];
-        F = F + R(d.ltil[e]) * c + R(0.5) * R(d.rtil) * c * c;
+        R c = rfma(a[2 * e], a[2 * e], a[2 * e + 1] * a[2 * e + 1]) + x[4 + e];
+        F = rfma(R(0.5) * R(d.rtil) * c, c, rfma(R(d.ltil[e]), c, F));
       }
     }
     return F;
@@ -617,12 +626,12 @@ struct BranchProblem {
     // the four flow couplings
     for (int k = 0; k < 4; ++k) {
       R r = a[k] - R(d.vb[k]) + R(d.z[k]);
-      F = F + R(d.y[k]) * r + R(0.5) * R(d.rho[k]) * r * r;
-      R m = R(d.y[k]) + R(d.rho[k]) * r;
-      for (int p = 0; p < 4; ++p) g[p] = g[p] + m * ga[k][p];
+      F = rfma(R(0.5) * R(d.rho[k]) * r, r, rfma(R(d.y[k]), r, F));
+      R m = rfma(R(d.rho[k]), r, R(d.y[k]));
+      for (int p = 0; p < 4; ++p) g[p] = rfma(m, ga[k][p], g[p]);
       for (int t = 0; t < 10; ++t) {
         int p = UT_P[t], q = UT_Q[t];
-        H[p * n + q] = H[p * n + q] + R(d.rho[k]) * ga[k][p] * ga[k][q] + m * Ha[k][t];
+        H[p * n + q] = rfma(m, Ha[k][t], rfma(R(d.rho[k]) * ga[k][p], ga[k][q], H[p * n + q]));
       }
     }
     // w_i = v_i^2 (variable 0), theta_i (2), w_j = v_j^2 (1), theta_j (3)
@@ -630,12 +639,12 @@ struct BranchProblem {
     for (int k = 4; k < 8; ++k) {
       int p = var[k - 4];
       R r = a[k] - R(d.vb[k]) + R(d.z[k]);
-      F = F + R(d.y[k]) * r + R(0.5) * R(d.rho[k]) * r * r;
-      R m = R(d.y[k]) + R(d.rho[k]) * r;
+      F = rfma(R(0.5) * R(d.rho[k]) * r, r, rfma(R(d.y[k]), r, F));
+      R m = rfma(R(d.rho[k]), r, R(d.y[k]));
       if (k == 4 || k == 6) {  // d(v^2)/dv = 2v, d2(v^2)/dv2 = 2
         R gv = R(2.0) * x[p];
-        g[p] = g[p] + m * gv;
-        H[p * n + p] = H[p * n + p] + R(d.rho[k]) * gv * gv + m * R(2.0);
+        g[p] = rfma(m, gv, g[p]);
+        H[p * n + p] = rfma(m, R(2.0), rfma(R(d.rho[k]) * gv, gv, H[p * n + p]));
       } else {  // angle copy: gradient 1, no curvature
         g[p] = g[p] + m;
         H[p * n + p] = H[p * n + p] + R(d.rho[k]);
@@ -645,21 +654,22 @@ struct BranchProblem {
     if (n == 6) {
       for (int e = 0; e < 2; ++e) {
         int kp = 2 * e, kq = 2 * e + 1, s = 4 + e;
-        R c = a[kp] * a[kp] + a[kq] * a[kq] + x[s];
-        F = F + R(d.ltil[e]) * c + R(0.5) * R(d.rtil) * c * c;
-        R m = R(d.ltil[e]) + R(d.rtil) * c;
+        R c = rfma(a[kp], a[kp], a[kq] * a[kq]) + x[s];
+        F = rfma(R(0.5) * R(d.rtil) * c, c, rfma(R(d.ltil[e]), c, F));
+        R m = rfma(R(d.rtil), c, R(d.ltil[e]));
         R gc[4];
         for (int p = 0; p < 4; ++p)
-          gc[p] = R(2.0) * (a[kp] * ga[kp][p] + a[kq] * ga[kq][p]);
-        for (int p = 0; p < 4; ++p) g[p] = g[p] + m * gc[p];
+          gc[p] = R(2.0) * rfma(a[kp], ga[kp][p], a[kq] * ga[kq][p]);
+        for (int p = 0; p < 4; ++p) g[p] = rfma(m, gc[p], g[p]);
         g[s] = g[s] + m;
         for (int t = 0; t < 10; ++t) {
           int p = UT_P[t], q = UT_Q[t];
-          R hc = R(2.0) * (ga[kp][p] * ga[kp][q] + a[kp] * Ha[kp][t] +
-                           ga[kq][p] * ga[kq][q] + a[kq] * Ha[kq][t]);
-          H[p * 6 + q] = H[p * 6 + q] + R(d.rtil) * gc[p] * gc[q] + m * hc;
+          R hc = R(2.0) * rfma(a[kq], Ha[kq][t],
+                               rfma(ga[kq][p], ga[kq][q],
+                                    rfma(a[kp], Ha[kp][t], ga[kp][p] * ga[kp][q])));
+          H[p * 6 + q] = rfma(m, hc, rfma(R(d.rtil) * gc[p], gc[q], H[p * 6 + q]));
         }
-        for (int p = 0; p < 4; ++p) H[p * 6 + s] = H[p * 6 + s] + R(d.rtil) * gc[p];
+        for (int p = 0; p < 4; ++p) H[p * 6 + s] = rfma(R(d.rtil), gc[p], H[p * 6 + s]);
         H[s * 6 + s] = H[s * 6 + s] + R(d.rtil);
       }
     }
@@ -693,8 +703,8 @@ void branch_solve_t(BranchData& d, double* x6, double* ltil, double* rtil,
       tron<R>(P, 6, x, d.lo, d.hi, prm, st, C);
       R a[8];
       branch_values<R>(d, x, a, nullptr);
-      R c0 = a[0] * a[0] + a[1] * a[1] + x[4];
-      R c1 = a[2] * a[2] + a[3] * a[3] + x[5];
+      R c0 = rfma(a[0], a[0], a[1] * a[1]) + x[4];
+      R c1 = rfma(a[2], a[2], a[3] * a[3]) + x[5];
       R cn = rmax(rabs(c0), rabs(c1));
       if (cn <= R(prm.al_tol)) break;
       d.ltil[0] = val(R(d.ltil[0]) + R(d.rtil) * c0);

@@ -428,10 +428,11 @@ __global__ __launch_bounds__(256) void cold_kernel(ColdArgs A) {
   // angles are zero: w^R = vi vj, w^I = 0
   const double* Y = A.adm;
   const double wi = vi * vi, wj = vj * vj, WR = vi * vj * 1.0, WI = vi * vj * 0.0;
-  const double a0 = Y[0 * nl + l] * wi + Y[2 * nl + l] * WR + Y[3 * nl + l] * WI;
-  const double a1 = -Y[1 * nl + l] * wi - Y[3 * nl + l] * WR + Y[2 * nl + l] * WI;
-  const double a2 = Y[6 * nl + l] * wj + Y[4 * nl + l] * WR - Y[5 * nl + l] * WI;
-  const double a3 = -Y[7 * nl + l] * wj - Y[5 * nl + l] * WR - Y[4 * nl + l] * WI;
+  // flows as in the branch evaluation (fused multiply-adds in the same places)
+  const double a0 = fma(Y[3 * nl + l], WI, fma(Y[2 * nl + l], WR, Y[0 * nl + l] * wi));
+  const double a1 = fma(Y[2 * nl + l], WI, fma(-Y[3 * nl + l], WR, -Y[1 * nl + l] * wi));
+  const double a2 = fma(-Y[5 * nl + l], WI, fma(Y[4 * nl + l], WR, Y[6 * nl + l] * wj));
+  const double a3 = fma(-Y[4 * nl + l], WI, fma(-Y[5 * nl + l], WR, -Y[7 * nl + l] * wj));
   const double a[8] = {a0, a1, a2, a3, wi, 0.0, wj, 0.0};
   const int64_t ef = A.ef[l], et = A.et[l];
   setk(acopf_dev::end_coupling(A.ng, A.ne, 0, ef), a0);

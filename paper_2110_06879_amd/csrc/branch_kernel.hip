@@ -72,37 +72,38 @@ struct BranchIn {
 };
 
 // sin and cos of an angle difference as a fixed sequence of IEEE operations
-// (the library is built without floating-point contraction): reduction by
-// pi/2 with a two-part constant (33-bit head, so k * head is exact), then the
-// Taylor series of sin and cos on |r| <= pi/4 in Horner form, truncated after
-// r^17 and r^18 (truncation error below 1e-19 there).
+// (the library is built without floating-point contraction; every fused
+// multiply-add is written out): reduction by pi/2 with a two-part constant
+// (33-bit head), then the Taylor series of sin and cos on |r| <= pi/4 in
+// Horner form with fused multiply-adds, truncated after r^17 and r^18
+// (truncation error below 1e-19 there).
 __device__ inline void series_sincos(double x, double* s, double* c) {
   constexpr double kHead = 1.5707963267341256;      // 0x1.921fb544p+0
   constexpr double kTail = 6.077100506506192e-11;   // pi/2 - kHead
   constexpr double kInvPio2 = 0.6366197723675814;   // 2/pi
   const double k = rint(x * kInvPio2);
-  const double r = (x - k * kHead) - k * kTail;
+  const double r = fma(-k, kTail, fma(-k, kHead, x));
   const double r2 = r * r;
   // odd coefficients (-1)^j/(2j+1)!, even coefficients (-1)^j/(2j)!
   double ps = 2.8114572543455206e-15;
-  ps = -7.647163731819816e-13 + r2 * ps;
-  ps = 1.6059043836821613e-10 + r2 * ps;
-  ps = -2.505210838544172e-08 + r2 * ps;
-  ps = 2.7557319223985893e-06 + r2 * ps;
-  ps = -0.0001984126984126984 + r2 * ps;
-  ps = 0.008333333333333333 + r2 * ps;
-  ps = -0.16666666666666666 + r2 * ps;
+  ps = fma(r2, ps, -7.647163731819816e-13);
+  ps = fma(r2, ps, 1.6059043836821613e-10);
+  ps = fma(r2, ps, -2.505210838544172e-08);
+  ps = fma(r2, ps, 2.7557319223985893e-06);
+  ps = fma(r2, ps, -0.0001984126984126984);
+  ps = fma(r2, ps, 0.008333333333333333);
+  ps = fma(r2, ps, -0.16666666666666666);
   double pc = -1.5619206968586225e-16;
-  pc = 4.779477332387385e-14 + r2 * pc;
-  pc = -1.1470745597729725e-11 + r2 * pc;
-  pc = 2.08767569878681e-09 + r2 * pc;
-  pc = -2.755731922398589e-07 + r2 * pc;
-  pc = 2.48015873015873e-05 + r2 * pc;
-  pc = -0.001388888888888889 + r2 * pc;
-  pc = 0.041666666666666664 + r2 * pc;
-  pc = -0.5 + r2 * pc;
-  const double sr = r + r * (r2 * ps);
-  const double cr = 1.0 + r2 * pc;
+  pc = fma(r2, pc, 4.779477332387385e-14);
+  pc = fma(r2, pc, -1.1470745597729725e-11);
+  pc = fma(r2, pc, 2.08767569878681e-09);
+  pc = fma(r2, pc, -2.755731922398589e-07);
+  pc = fma(r2, pc, 2.48015873015873e-05);
+  pc = fma(r2, pc, -0.001388888888888889);
+  pc = fma(r2, pc, 0.041666666666666664);
+  pc = fma(r2, pc, -0.5);
+  const double sr = fma(r, r2 * ps, r);
+  const double cr = fma(r2, pc, 1.0);
   const int q = (int)(((long long)k) & 3);
   const double sv[4] = {sr, cr, -sr, -cr};
   const double cv[4] = {cr, -sr, -cr, sr};
@@ -125,10 +126,10 @@ __device__ inline void values(const BranchIn<N>& B, const double* x, double* a,
   const double vv = vi * vj;
   const double WR = vv * cs, WI = vv * sn;
   const double wi = vi * vi, wj = vj * vj;
-  a[0] = B.gii * wi + B.gij * WR + B.bij * WI;
-  a[1] = -B.bii * wi - B.bij * WR + B.gij * WI;
-  a[2] = B.gjj * wj + B.gji * WR - B.bji * WI;
-  a[3] = -B.bjj * wj - B.bji * WR - B.gji * WI;
+  a[0] = fma(B.bij, WI, fma(B.gij, WR, B.gii * wi));
+  a[1] = fma(B.gij, WI, fma(-B.bij, WR, -B.bii * wi));
+  a[2] = fma(-B.bji, WI, fma(B.gji, WR, B.gjj * wj));
+  a[3] = fma(-B.gji, WI, fma(-B.bji, WR, -B.bjj * wj));
   a[4] = wi;
   a[5] = ti;
   a[6] = wj;
@@ -149,14 +150,14 @@ __device__ double fval(const BranchIn<N>& B, const double* x, Counters& cnt) {
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const double r = (a[k] - B.vb[k]) + B.zc[k];
-    F = F + B.yc[k] * r + 0.5 * B.rho(k) * r * r;
+    F = fma(0.5 * B.rho(k) * r, r, fma(B.yc[k], r, F));
   }
   FL(64);
   if (N == 6) {
-    const double c0 = a[0] * a[0] + a[1] * a[1] + x[4];
-    F = F + B.lt0 * c0 + 0.5 * B.rt * c0 * c0;
-    const double c1 = a[2] * a[2] + a[3] * a[3] + x[5];
-    F = F + B.lt1 * c1 + 0.5 * B.rt * c1 * c1;
+    const double c0 = fma(a[0], a[0], a[1] * a[1]) + x[4];
+    F = fma(0.5 * B.rt * c0, c0, fma(B.lt0, c0, F));
+    const double c1 = fma(a[2], a[2], a[3] * a[3]) + x[5];
+    F = fma(0.5 * B.rt * c1, c1, fma(B.lt1, c1, F));
     FL(20);
   }
   ++cnt.n_f;
@@ -189,17 +190,15 @@ __device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
     const int own = k < 2 ? 0 : 1;
     const double tw = k < 2 ? twvi : twvj;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      double t = cR[k] * dWR[p] + cI[k] * dWI[p];
-      if (p == own) t = cw[k] * tw + cR[k] * dWR[p] + cI[k] * dWI[p];
-      ga[k][p] = t;
-    }
+    for (int p = 0; p < 4; ++p)
+      ga[k][p] = p == own ? fma(cI[k], dWI[p], fma(cR[k], dWR[p], cw[k] * tw))
+                          : fma(cI[k], dWI[p], cR[k] * dWR[p]);
 #pragma unroll
     for (int t = 0; t < 10; ++t) {
       if (t == 0 || t == 4)
         Ha[k][t] = ((t == 0) == (own == 0)) ? 2.0 * cw[k] : 0.0;
       else
-        Ha[k][t] = cR[k] * hWR[t] + cI[k] * hWI[t];
+        Ha[k][t] = fma(cI[k], hWI[t], cR[k] * hWR[t]);
     }
   }
   FL(162);
@@ -212,14 +211,14 @@ __device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
   for (int k = 0; k < 4; ++k) {
     const double rk = B.rho(k);
     const double r = (a[k] - B.vb[k]) + B.zc[k];
-    F = F + B.yc[k] * r + 0.5 * rk * r * r;
-    const double m = B.yc[k] + rk * r;
+    F = fma(0.5 * rk * r, r, fma(B.yc[k], r, F));
+    const double m = fma(rk, r, B.yc[k]);
 #pragma unroll
-    for (int p = 0; p < 4; ++p) g[p] = g[p] + m * ga[k][p];
+    for (int p = 0; p < 4; ++p) g[p] = fma(m, ga[k][p], g[p]);
 #pragma unroll
     for (int t = 0; t < 10; ++t) {
       const int p = kUP[t], q = kUQ[t];
-      H(p, q) = H(p, q) + rk * ga[k][p] * ga[k][q] + m * Ha[k][t];
+      H(p, q) = fma(m, Ha[k][t], fma(rk * ga[k][p], ga[k][q], H(p, q)));
     }
   }
   FL(272);
@@ -230,12 +229,12 @@ __device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
       const int p = var[k - 4];
       const double rk = B.rva;
       const double r = (a[k] - B.vb[k]) + B.zc[k];
-      F = F + B.yc[k] * r + 0.5 * rk * r * r;
-      const double m = B.yc[k] + rk * r;
+      F = fma(0.5 * rk * r, r, fma(B.yc[k], r, F));
+      const double m = fma(rk, r, B.yc[k]);
       if (k == 4 || k == 6) {
         const double gv = 2.0 * x[p];
-        g[p] = g[p] + m * gv;
-        H(p, p) = H(p, p) + rk * gv * gv + m * 2.0;
+        g[p] = fma(m, gv, g[p]);
+        H(p, p) = fma(m, 2.0, fma(rk * gv, gv, H(p, p)));
       } else {
         g[p] = g[p] + m;
         H(p, p) = H(p, p) + rk;
@@ -248,24 +247,25 @@ __device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
     for (int e = 0; e < 2; ++e) {
       const int kp = 2 * e, kq = 2 * e + 1, s = 4 + e;
       const double lt = e == 0 ? B.lt0 : B.lt1;
-      const double c = a[kp] * a[kp] + a[kq] * a[kq] + x[s];
-      F = F + lt * c + 0.5 * B.rt * c * c;
-      const double m = lt + B.rt * c;
+      const double c = fma(a[kp], a[kp], a[kq] * a[kq]) + x[s];
+      F = fma(0.5 * B.rt * c, c, fma(lt, c, F));
+      const double m = fma(B.rt, c, lt);
       double gc[4];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) gc[p] = 2.0 * (a[kp] * ga[kp][p] + a[kq] * ga[kq][p]);
+      for (int p = 0; p < 4; ++p) gc[p] = 2.0 * fma(a[kp], ga[kp][p], a[kq] * ga[kq][p]);
 #pragma unroll
-      for (int p = 0; p < 4; ++p) g[p] = g[p] + m * gc[p];
+      for (int p = 0; p < 4; ++p) g[p] = fma(m, gc[p], g[p]);
       g[s] = g[s] + m;
 #pragma unroll
       for (int t = 0; t < 10; ++t) {
         const int p = kUP[t], q = kUQ[t];
-        const double hc = 2.0 * (ga[kp][p] * ga[kp][q] + a[kp] * Ha[kp][t] +
-                                 ga[kq][p] * ga[kq][q] + a[kq] * Ha[kq][t]);
-        H(p, q) = H(p, q) + B.rt * gc[p] * gc[q] + m * hc;
+        const double hc = 2.0 * fma(a[kq], Ha[kq][t],
+                                    fma(ga[kq][p], ga[kq][q],
+                                        fma(a[kp], Ha[kp][t], ga[kp][p] * ga[kp][q])));
+        H(p, q) = fma(m, hc, fma(B.rt * gc[p], gc[q], H(p, q)));
       }
 #pragma unroll
-      for (int p = 0; p < 4; ++p) H(p, s) = H(p, s) + B.rt * gc[p];
+      for (int p = 0; p < 4; ++p) H(p, s) = fma(B.rt, gc[p], H(p, s));
       H(s, s) = H(s, s) + B.rt;
     }
     FL(352);
@@ -277,7 +277,7 @@ template <int N>
 __device__ inline double dotN(const double* a, const double* b) {
   double t = 0.0;
 #pragma unroll
-  for (int i = 0; i < N; ++i) t = t + a[i] * b[i];
+  for (int i = 0; i < N; ++i) t = fma(a[i], b[i], t);
   return t;
 }
 
@@ -288,14 +288,14 @@ __device__ inline double model(const double* g, const Sym<N>& H, const double* s
   double gs = 0.0, sHs = 0.0;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    gs = gs + g[i] * s[i];
+    gs = fma(g[i], s[i], gs);
     double hi = 0.0;
 #pragma unroll
-    for (int j = 0; j < N; ++j) hi = hi + H(i, j) * s[j];
-    sHs = sHs + s[i] * hi;
+    for (int j = 0; j < N; ++j) hi = fma(H(i, j), s[j], hi);
+    sHs = fma(s[i], hi, sHs);
   }
   FL(2 * N * N + 4 * N + 2);
-  return gs + 0.5 * sHs;
+  return fma(0.5, sHs, gs);
 }
 
 // tau >= 0 with ||a + tau p|| = delta
@@ -344,7 +344,7 @@ __device__ inline void cauchy_trial(const double* x, const double* g, const doub
                                     Counters& cnt) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    w[i] = clampd(x[i] - a * g[i], lo[i], hi[i]);
+    w[i] = clampd(fma(-a, g[i], x[i]), lo[i], hi[i]);
     s[i] = w[i] - x[i];
   }
   FL(3 * N);
@@ -404,14 +404,14 @@ __device__ inline void precond(const Sym<N>& L, const double* D, const bool* fr,
   for (int i = 0; i < N; ++i) {
     double a = D[i] * r[i];
 #pragma unroll
-    for (int k = 0; k < i; ++k) a = a - L(i, k) * t[k];
+    for (int k = 0; k < i; ++k) a = fma(-L(i, k), t[k], a);
     t[i] = fr[i] ? a / L(i, i) : 0.0;
   }
 #pragma unroll
   for (int i = N - 1; i >= 0; --i) {
     double a = t[i];
 #pragma unroll
-    for (int k = i + 1; k < N; ++k) a = a - L(k, i) * z[k];
+    for (int k = i + 1; k < N; ++k) a = fma(-L(k, i), z[k], a);
     z[i] = fr[i] ? a / L(i, i) : 0.0;
   }
 #pragma unroll
@@ -436,7 +436,7 @@ __device__ inline bool cholesky(const Sym<N>& H, const double* D, double shift,
     }
     double d = D[j] * H(j, j) * D[j] + shift;
 #pragma unroll
-    for (int k = 0; k < j; ++k) d = d - L(j, k) * L(j, k);
+    for (int k = 0; k < j; ++k) d = fma(-L(j, k), L(j, k), d);
     FL(2 * jc);
     if (!(d > 0.0)) return false;
     const double ljj = sqrt(d);
@@ -446,7 +446,7 @@ __device__ inline bool cholesky(const Sym<N>& H, const double* D, double shift,
       if (!fr[i]) continue;
       double t = D[i] * H(i, j) * D[j];
 #pragma unroll
-      for (int k = 0; k < j; ++k) t = t - L(i, k) * L(j, k);
+      for (int k = 0; k < j; ++k) t = fma(-L(i, k), L(j, k), t);
       L(i, j) = t / ljj;
     }
     FL(1 + (nf - 1 - jc) * (2 * jc + 1));
@@ -480,7 +480,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
     for (int i = 0; i < N; ++i) {
       double t = g[i];
 #pragma unroll
-      for (int j = 0; j < N; ++j) t = t + H(i, j) * s[j];
+      for (int j = 0; j < N; ++j) t = fma(H(i, j), s[j], t);
       gq[i] = t;
       r[i] = fr[i] ? -t : 0.0;
     }
@@ -553,7 +553,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       for (int i = 0; i < N; ++i) {
         double t = 0.0;
 #pragma unroll
-        for (int j = 0; j < N; ++j) t = t + (fr[j] ? H(i, j) * p[j] : 0.0);
+        for (int j = 0; j < N; ++j) t = fr[j] ? fma(H(i, j), p[j], t) : t;
         Bp[i] = fr[i] ? t : 0.0;
       }
       const double pBp = dotN<N>(p, Bp);
@@ -565,7 +565,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       if (!(pBp > 0.0)) {
         const double tau = to_boundary<N>(sd, p, delta, cnt);
 #pragma unroll
-        for (int i = 0; i < N; ++i) d[i] = d[i] + tau * p[i];
+        for (int i = 0; i < N; ++i) d[i] = fma(tau, p[i], d[i]);
         FL(2 * nf);
         boundary = true;
         break;
@@ -573,21 +573,21 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       const double alpha = rz / pBp;
       double tr[N];
 #pragma unroll
-      for (int i = 0; i < N; ++i) tr[i] = sd[i] + alpha * p[i];
+      for (int i = 0; i < N; ++i) tr[i] = fma(alpha, p[i], sd[i]);
       const double trn = sqrt(dotN<N>(tr, tr));
       FL(1 + 2 * N + 2 * N + 1);
       if (trn >= delta) {
         const double tau = to_boundary<N>(sd, p, delta, cnt);
 #pragma unroll
-        for (int i = 0; i < N; ++i) d[i] = d[i] + tau * p[i];
+        for (int i = 0; i < N; ++i) d[i] = fma(tau, p[i], d[i]);
         FL(2 * nf);
         boundary = true;
         break;
       }
 #pragma unroll
       for (int i = 0; i < N; ++i) {
-        d[i] = d[i] + alpha * p[i];
-        res[i] = res[i] - alpha * Bp[i];
+        d[i] = fma(alpha, p[i], d[i]);
+        res[i] = fma(-alpha, Bp[i], res[i]);
       }
       const double rn = sqrt(dotN<N>(res, res));
       FL(4 * nf + 2 * nf + 2);
@@ -597,7 +597,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       const double bcg = rzn / rz;
       rz = rzn;
 #pragma unroll
-      for (int i = 0; i < N; ++i) p[i] = zz[i] + bcg * p[i];
+      for (int i = 0; i < N; ++i) p[i] = fma(bcg, p[i], zz[i]);
       FL(2 * nf * nf + 2 * nf + 2 * nf + 1 + 2 * nf);
     }
     // projected search along d from w
@@ -609,7 +609,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       ++cnt.ps;
 #pragma unroll
       for (int i = 0; i < N; ++i)
-        wt[i] = fr[i] ? clampd(w[i] + beta * d[i], lo[i], hi[i]) : w[i];
+        wt[i] = fr[i] ? clampd(fma(beta, d[i], w[i]), lo[i], hi[i]) : w[i];
       double dw[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) {
@@ -618,7 +618,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       }
       FL(2 * nf + 2 * N);
       const double qt = model<N>(g, H, stv, cnt);
-      const double lhs = qw + kMu0 * dotN<N>(gq, dw);
+      const double lhs = fma(kMu0, dotN<N>(gq, dw), qw);
       FL(2 * N + 2);
       if (qt <= lhs) {
         acc = true;
@@ -656,7 +656,7 @@ __device__ int tron(const BranchIn<N>& B, double* x, const double* lo, const dou
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     const double t = clampd(x[i] - g[i], lo[i], hi[i]) - x[i];
-    pg2 = pg2 + t * t;
+    pg2 = fma(t, t, pg2);
   }
   double delta = sqrt(pg2);
   FL(4 * N + 1);
@@ -776,7 +776,7 @@ __device__ bool tron_advance(TronState<N>& S, const BranchIn<N>& B, const double
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         const double t = clampd(S.x[i] - S.g[i], lo[i], hi[i]) - S.x[i];
-        pg2 = pg2 + t * t;
+        pg2 = fma(t, t, pg2);
       }
       S.delta = sqrt(pg2);
       FL(4 * N + 1);
@@ -929,8 +929,8 @@ __device__ void solve_branch(const BranchArgs& A, int64_t l, int grid, Counters&
         failures += tron<N>(B, x, lo, hi, A.tron_gtol, A.tron_ftol, A.tron_maxit, cnt) != kConv;
         double a[8], aux[4];
         values<N>(B, x, a, aux, cnt);
-        const double c0 = a[0] * a[0] + a[1] * a[1] + x[4];
-        const double c1 = a[2] * a[2] + a[3] * a[3] + x[5];
+        const double c0 = fma(a[0], a[0], a[1] * a[1]) + x[4];
+        const double c1 = fma(a[2], a[2], a[3] * a[3]) + x[5];
         cnt.flops += 8;
         const double cn = fabs(c0) > fabs(c1) ? fabs(c0) : fabs(c1);
         if (cn <= A.al_tol) break;
@@ -1089,8 +1089,8 @@ __device__ void run_pool(const BranchArgs& A, int64_t begin, int64_t end, unsign
     if (N == 6) {
       double a[8], aux[4];
       values<N>(B, S.x, a, aux, cnt);
-      const double c0 = a[0] * a[0] + a[1] * a[1] + S.x[4];
-      const double c1 = a[2] * a[2] + a[3] * a[3] + S.x[5];
+      const double c0 = fma(a[0], a[0], a[1] * a[1]) + S.x[4];
+      const double c1 = fma(a[2], a[2], a[3] * a[3]) + S.x[5];
       cnt.flops += 8;
       const double cn = fabs(c0) > fabs(c1) ? fabs(c0) : fabs(c1);
       if (!(cn <= A.al_tol)) {
