@@ -248,8 +248,7 @@ void cauchy_step(int n, const R* x, const R* g, const R* H, const double* lo,
     }
   };
   auto accept = [&](const R* sv) {
-    R sn = rsqrt_(dotv(n, sv, sv));
-    if (sn > delta) return false;
+    if (dotv(n, sv, sv) > delta * delta) return false;
     R q = model_q(n, g, H, sv);
     return q <= R(C.mu0) * dotv(n, g, sv);
   };
@@ -276,10 +275,12 @@ void cauchy_step(int n, const R* x, const R* g, const R* H, const double* lo,
   }
 }
 
-// Dense Cholesky A = L L' (lower, row-major, m x m). Returns false when a
-// pivot is not positive.
+// Dense Cholesky A = L L' (lower, row-major, m x m), column by column; as in
+// LAPACK's unblocked factorization the column below a pivot is scaled by the
+// pivot's reciprocal, which is kept in rd for the triangular solves. Returns
+// false when a pivot is not positive.
 template <class R>
-bool cholesky(int m, const R* A, R* L) {
+bool cholesky(int m, const R* A, R* L, R* rd) {
   for (int i = 0; i < m * m; ++i) L[i] = R(0.0);
   for (int j = 0; j < m; ++j) {
     R d = A[j * m + j];
@@ -287,28 +288,30 @@ bool cholesky(int m, const R* A, R* L) {
     if (!(d > R(0.0))) return false;
     R ljj = rsqrt_(d);
     L[j * m + j] = ljj;
+    R rj = R(1.0) / ljj;
+    rd[j] = rj;
     for (int i = j + 1; i < m; ++i) {
       R t = A[i * m + j];
       for (int k = 0; k < j; ++k) t = rfma(-L[i * m + k], L[j * m + k], t);
-      L[i * m + j] = t / ljj;
+      L[i * m + j] = t * rj;
     }
   }
   return true;
 }
 
-// z = M^{-1} r with M = D^{-1} L L' D^{-1}
+// z = M^{-1} r with M = D^{-1} L L' D^{-1}; rd holds the reciprocal pivots.
 template <class R>
-void precond(int m, const R* L, const R* D, const R* r, R* z) {
+void precond(int m, const R* L, const R* rd, const R* D, const R* r, R* z) {
   R t[NMAX];
   for (int i = 0; i < m; ++i) {
     R a = D[i] * r[i];
     for (int k = 0; k < i; ++k) a = rfma(-L[i * m + k], t[k], a);
-    t[i] = a / L[i * m + i];
+    t[i] = a * rd[i];
   }
   for (int i = m - 1; i >= 0; --i) {
     R a = t[i];
     for (int k = i + 1; k < m; ++k) a = rfma(-L[k * m + i], z[k], a);
-    z[i] = a / L[i * m + i];
+    z[i] = a * rd[i];
   }
   for (int i = 0; i < m; ++i) z[i] = D[i] * z[i];
 }
@@ -337,10 +340,10 @@ void subspace_step(int n, const R* x, const R* g, const R* H, const double* lo,
       r[a] = -gq[F[a]];
       for (int b = 0; b < nf; ++b) B[a * nf + b] = H[F[a] * n + F[b]];
     }
-    R rnorm0 = rsqrt_(dotv(nf, r, r));
-    if (!(rnorm0 > R(0.0))) break;
+    R rr0 = dotv(nf, r, r);  // squared norm of the initial residual
+    if (!(rr0 > R(0.0))) break;
     // preconditioner: Cholesky of D B D + shift I, D = diag(1/sqrt|B_aa|)
-    R D[NMAX], Bs[NMAX * NMAX], L[NMAX * NMAX];
+    R D[NMAX], Bs[NMAX * NMAX], L[NMAX * NMAX], rd[NMAX];
     for (int a = 0; a < nf; ++a) {
       R baa = rabs(B[a * nf + a]);
       D[a] = baa > R(0.0) ? R(1.0) / rsqrt_(baa) : R(1.0);
@@ -357,17 +360,17 @@ void subspace_step(int n, const R* x, const R* g, const R* H, const double* lo,
       for (int q = 0; q < nf * nf; ++q) A[q] = Bs[q];
       for (int a = 0; a < nf; ++a) A[a * nf + a] = A[a * nf + a] + shift;
       ++st->chol_attempts;
-      if (cholesky(nf, A, L)) { ok = true; break; }
+      if (cholesky(nf, A, L, rd)) { ok = true; break; }
       shift = rmax(R(2.0) * shift, R(C.shift_min));
     }
     if (!ok) {
       for (int q = 0; q < nf * nf; ++q) L[q] = R(0.0);
-      for (int a = 0; a < nf; ++a) { L[a * nf + a] = R(1.0); D[a] = R(1.0); }
+      for (int a = 0; a < nf; ++a) { L[a * nf + a] = R(1.0); rd[a] = R(1.0); D[a] = R(1.0); }
     }
     // Steihaug PCG on min 1/2 d'Bd - r'd  s.t. ||s + d|| <= delta
     R d[NMAX], res[NMAX], zz[NMAX], p[NMAX], Bp[NMAX];
     for (int a = 0; a < nf; ++a) { d[a] = R(0.0); res[a] = r[a]; }
-    precond(nf, L, D, res, zz);
+    precond(nf, L, rd, D, res, zz);
     for (int a = 0; a < nf; ++a) p[a] = zz[a];
     R rz = dotv(nf, res, zz);
     bool boundary = false;
@@ -392,7 +395,7 @@ void subspace_step(int n, const R* x, const R* g, const R* H, const double* lo,
       R alpha = rz / pBp;
       R tr[NMAX];
       for (int i = 0; i < n; ++i) tr[i] = rfma(alpha, pf[i], sd[i]);
-      if (rsqrt_(dotv(n, tr, tr)) >= delta) {
+      if (dotv(n, tr, tr) >= delta * delta) {
         R tau = to_boundary(n, sd, pf, delta);
         for (int a = 0; a < nf; ++a) d[a] = rfma(tau, p[a], d[a]);
         boundary = true;
@@ -402,8 +405,8 @@ void subspace_step(int n, const R* x, const R* g, const R* H, const double* lo,
         d[a] = rfma(alpha, p[a], d[a]);
         res[a] = rfma(-alpha, Bp[a], res[a]);
       }
-      if (rsqrt_(dotv(nf, res, res)) <= R(C.cgtol) * rnorm0) break;
-      precond(nf, L, D, res, zz);
+      if (dotv(nf, res, res) <= R(C.cgtol * C.cgtol) * rr0) break;
+      precond(nf, L, rd, D, res, zz);
       R rzn = dotv(nf, res, zz);
       R bcg = rzn / rz;
       rz = rzn;
@@ -494,8 +497,9 @@ int tron(P& prob, int n, R* x, const double* lo, const double* hi,
       prob.fgh(x, f, g, H);
       ++st->n_fgh;
     }
-    R xn = rsqrt_(dotv(n, x, x));
-    if (delta <= R(1e-15) * rmax(R(1.0), xn)) { status = TRON_STALL; break; }
+    // Delta <= 1e-15 max(1, ||x||), compared in squares
+    R xx = dotv(n, x, x);
+    if (delta * delta <= R(1e-30) * rmax(R(1.0), xx)) { status = TRON_STALL; break; }
   }
   if (status == TRON_CONVERGED) ++st->tron_converged;
   else if (status == TRON_MAXIT) ++st->tron_maxit;

@@ -329,9 +329,9 @@ __device__ inline double to_boundary(const double* a, const double* p, double de
 template <int N>
 __device__ inline bool cauchy_ok(const double* g, const Sym<N>& H, const double* s,
                                  double delta, Counters& cnt) {
-  const double sn = sqrt(dotN<N>(s, s));
+  const double ss = dotN<N>(s, s);  // ||s|| <= delta, compared in squares
   FL(2 * N + 1);
-  if (sn > delta) return false;
+  if (ss > delta * delta) return false;
   const double q = model<N>(g, H, s, cnt);
   const double gts = dotN<N>(g, s);
   FL(2 * N + 1);
@@ -395,24 +395,24 @@ __device__ void cauchy(const double* x, const double* g, const Sym<N>& H,
 }
 
 // Preconditioner application on the free variables (mask fr):
-// z = D L^-T L^-1 D r ; counted as 2 nf^2 + 2 nf.
+// z = D L^-T L^-1 D r with the reciprocal pivots rd; counted as 2 nf^2 + 2 nf.
 template <int N>
-__device__ inline void precond(const Sym<N>& L, const double* D, const bool* fr,
-                               const double* r, double* z) {
+__device__ inline void precond(const Sym<N>& L, const double* rd, const double* D,
+                               const bool* fr, const double* r, double* z) {
   double t[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     double a = D[i] * r[i];
 #pragma unroll
     for (int k = 0; k < i; ++k) a = fma(-L(i, k), t[k], a);
-    t[i] = fr[i] ? a / L(i, i) : 0.0;
+    t[i] = fr[i] ? a * rd[i] : 0.0;
   }
 #pragma unroll
   for (int i = N - 1; i >= 0; --i) {
     double a = t[i];
 #pragma unroll
     for (int k = i + 1; k < N; ++k) a = fma(-L(k, i), z[k], a);
-    z[i] = fr[i] ? a / L(i, i) : 0.0;
+    z[i] = fr[i] ? a * rd[i] : 0.0;
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) z[i] = D[i] * z[i];
@@ -420,11 +420,14 @@ __device__ inline void precond(const Sym<N>& L, const double* D, const bool* fr,
 
 // Dense Cholesky of the scaled, shifted free Hessian D H D + shift I (fixed
 // rows/columns act as identity), formed element by element as the
-// factorization needs it. Returns false at the first non-positive free pivot;
-// flops are counted as on the compressed nf x nf matrix.
+// factorization needs it; the column below a pivot is scaled by the pivot's
+// reciprocal (kept in rd for the triangular solves), as in LAPACK's unblocked
+// factorization. Returns false at the first non-positive free pivot; flops
+// are counted as on the compressed nf x nf matrix.
 template <int N>
 __device__ inline bool cholesky(const Sym<N>& H, const double* D, double shift,
-                                const bool* fr, int nf, Sym<N>& L, Counters& cnt) {
+                                const bool* fr, int nf, Sym<N>& L, double* rd,
+                                Counters& cnt) {
 #pragma unroll
   for (int q = 0; q < N * (N + 1) / 2; ++q) L.t[q] = 0.0;
   int jc = 0;  // compressed column index
@@ -432,6 +435,7 @@ __device__ inline bool cholesky(const Sym<N>& H, const double* D, double shift,
   for (int j = 0; j < N; ++j) {
     if (!fr[j]) {
       L(j, j) = 1.0;
+      rd[j] = 1.0;
       continue;
     }
     double d = D[j] * H(j, j) * D[j] + shift;
@@ -441,15 +445,17 @@ __device__ inline bool cholesky(const Sym<N>& H, const double* D, double shift,
     if (!(d > 0.0)) return false;
     const double ljj = sqrt(d);
     L(j, j) = ljj;
+    const double rj = 1.0 / ljj;
+    rd[j] = rj;
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {
       if (!fr[i]) continue;
       double t = D[i] * H(i, j) * D[j];
 #pragma unroll
       for (int k = 0; k < j; ++k) t = fma(-L(i, k), L(j, k), t);
-      L(i, j) = t / ljj;
+      L(i, j) = t * rj;
     }
-    FL(1 + (nf - 1 - jc) * (2 * jc + 1));
+    FL(2 + (nf - 1 - jc) * (2 * jc + 1));
     ++jc;
   }
   return true;
@@ -485,9 +491,9 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       r[i] = fr[i] ? -t : 0.0;
     }
     FL(2 * N * N);
-    const double rnorm0 = sqrt(dotN<N>(r, r));
-    FL(2 * nf + 1);
-    if (!(rnorm0 > 0.0)) break;
+    const double rr0 = dotN<N>(r, r);  // squared norm of the initial residual
+    FL(2 * nf);
+    if (!(rr0 > 0.0)) break;
     double D[N];
     double mind = 1.0 / 0.0;
 #pragma unroll
@@ -514,11 +520,12 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       FL(1);
     }
     Sym<N> L;
+    double rd[N];
     bool ok = false;
     for (int att = 0; att < kMaxChol; ++att) {
       FL(nf);
       ++cnt.chol;
-      if (cholesky<N>(H, D, shift, fr, nf, L, cnt)) {
+      if (cholesky<N>(H, D, shift, fr, nf, L, rd, cnt)) {
         ok = true;
         break;
       }
@@ -529,6 +536,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         D[i] = 1.0;
+        rd[i] = 1.0;
 #pragma unroll
         for (int j = 0; j <= i; ++j) L(i, j) = i == j ? 1.0 : 0.0;
       }
@@ -540,7 +548,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       d[i] = 0.0;
       res[i] = r[i];
     }
-    precond<N>(L, D, fr, res, zz);
+    precond<N>(L, rd, D, fr, res, zz);
     FL(2 * nf * nf + 2 * nf);
 #pragma unroll
     for (int i = 0; i < N; ++i) p[i] = zz[i];
@@ -574,9 +582,9 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       double tr[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) tr[i] = fma(alpha, p[i], sd[i]);
-      const double trn = sqrt(dotN<N>(tr, tr));
+      const double trr = dotN<N>(tr, tr);  // ||s + d|| >= delta, in squares
       FL(1 + 2 * N + 2 * N + 1);
-      if (trn >= delta) {
+      if (trr >= delta * delta) {
         const double tau = to_boundary<N>(sd, p, delta, cnt);
 #pragma unroll
         for (int i = 0; i < N; ++i) d[i] = fma(tau, p[i], d[i]);
@@ -589,10 +597,10 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
         d[i] = fma(alpha, p[i], d[i]);
         res[i] = fma(-alpha, Bp[i], res[i]);
       }
-      const double rn = sqrt(dotN<N>(res, res));
-      FL(4 * nf + 2 * nf + 2);
-      if (rn <= kCgTol * rnorm0) break;
-      precond<N>(L, D, fr, res, zz);
+      const double rr = dotN<N>(res, res);  // ||r|| <= tol ||r0||, in squares
+      FL(4 * nf + 2 * nf + 1);
+      if (rr <= (kCgTol * kCgTol) * rr0) break;
+      precond<N>(L, rd, D, fr, res, zz);
       const double rzn = dotN<N>(res, zz);
       const double bcg = rzn / rz;
       rz = rzn;
@@ -720,9 +728,9 @@ __device__ int tron(const BranchIn<N>& B, double* x, const double* lo, const dou
       for (int i = 0; i < N; ++i) x[i] = w[i];
       fgh<N>(B, x, f, g, H, cnt);
     }
-    const double xn = sqrt(dotN<N>(x, x));
+    const double xx = dotN<N>(x, x);  // delta <= 1e-15 max(1, ||x||), in squares
     FL(2 * N + 2);
-    if (delta <= 1e-15 * (xn > 1.0 ? xn : 1.0)) {
+    if (delta * delta <= 1e-30 * (xx > 1.0 ? xx : 1.0)) {
       status = kStall;
       break;
     }
@@ -785,9 +793,9 @@ __device__ bool tron_advance(TronState<N>& S, const BranchIn<N>& B, const double
     }
   }
   if (S.it > 0) {
-    const double xn = sqrt(dotN<N>(S.x, S.x));
+    const double xx = dotN<N>(S.x, S.x);
     FL(2 * N + 2);
-    if (S.delta <= 1e-15 * (xn > 1.0 ? xn : 1.0)) {
+    if (S.delta * S.delta <= 1e-30 * (xx > 1.0 ? xx : 1.0)) {
       S.status = kStall;
       return true;
     }
