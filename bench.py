@@ -12,8 +12,10 @@ Prints one JSON line. Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -24,6 +26,32 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector peak (spec sheet)
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2110_06879_amd/csrc/acopf.hip", "paper_2110_06879_amd/csrc/branch_kernel.hip",
+                  "paper_2110_06879_amd/csrc/device_common.h")
+COUNTERS_MD = os.path.join(ROOT, "profiles", "kernels_70k_hbm_counters.md")
+
+
+def sources_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per x-step launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated on a copy kernel), or None
+    when the kernel sources changed since the counters were taken."""
+    try:
+        txt = open(COUNTERS_MD).read()
+    except OSError:
+        return None
+    m_hash = re.search(r"sha256\[:16\] = `([0-9a-f]{16})`", txt)
+    m_val = re.search(r"xstep_kernel HBM bytes per launch: (\d+)", txt)
+    if not m_hash or not m_val or m_hash.group(1) != sources_hash():
+        return None
+    return int(m_val.group(1))
 
 
 def percentile(a, q):
@@ -81,12 +109,17 @@ def main():
     ms_per_step = secs / args.steps * 1e3
     value = n_branch * args.steps / secs
     if args.profile_only:
+        # exactly the launches of the timed region (cold start, W warmup, K
+        # timed): a kernel trace of this run averages its last K launches of
+        # each kernel over the same iterations as the roofline pass below
         s.close()
         print(json.dumps({"profile_only": True, "steps": args.steps, "warmup": args.warmup,
                           "ms_per_step": ms_per_step, "value": value}), flush=True)
         return
 
-    # ---- roofline pass: same number of iterations with per-kernel HIP events
+    # ---- roofline pass: the same iterations again (cold start, W warmup,
+    # then K iterations) with per-kernel HIP events on the solver's stream
+    s.solve(A.COLD, args.warmup)
     st0 = s.stats()
     s.set_profiling(True)
     s.solve(A.CONTINUE, args.steps)
@@ -167,7 +200,8 @@ def main():
                    "tuning": tuning},
         "roofline": {"bound": "alu", "kernel": "xstep_kernel (branch TRON + generators)",
                      "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved_tflops / FP64_PEAK_TFLOPS, "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch", "kernel_sources": sources_hash(),
                      "flops_per_launch": flops_per_launch, "launch_ms": x_ms,
                      "launches": launches, "branch_solves_per_launch": solves / max(launches, 1)},
         "per_kernel_ms": tim,
