@@ -140,6 +140,10 @@ typedef struct {
                           each lane takes branches from a shared counter and
                           advances one TRON iteration per loop trip, so lanes
                           that finish early take more work (same results) */
+  int32_t xstep_per_lane; /* lane-per-branch kernel: unlimited branches
+                          solved one after another by each lane, 1..8; 0:
+                          automatic, the fewest for which every branch
+                          wavefront fits the device's SIMDs at once        */
 } acopf_tuning;
 
 typedef struct acopf_s* acopf_handle;
@@ -198,8 +202,9 @@ int acopf_snapshot(acopf_handle h, int32_t what);
 /* Launch shape: set explicitly, read back, or pick by timing `iters` inner
  * iterations of every candidate from the current state (the state is saved
  * before and restored after, so tuning leaves the solve unchanged).
- * Candidates: x-step {lane per branch at xstep_block 64, 128, 256;
- * persistent at xstep_waves 1, 2} x bus_block {128, 256, 512, 1024} x
+ * Candidates: x-step {lane per branch at xstep_block 64, 128, 256 with
+ * xstep_per_lane automatic or 1; persistent at xstep_waves 1, 2} x
+ * bus_block {128, 256, 512, 1024} x
  * chunk {8, 16, 32}, graphs on. Errors: EINVAL, ENOMEM, EDEVICE. */
 int acopf_set_tuning(acopf_handle h, const acopf_tuning* t);
 int acopf_get_tuning(acopf_handle h, acopf_tuning* t);

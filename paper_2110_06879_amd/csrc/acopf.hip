@@ -590,7 +590,7 @@ struct acopf_s {
   double *base_d, *obj_d;
   bool solved = false;
   bool profile = false;
-  acopf_tuning tune{64, 256, 16, 1, 0};
+  acopf_tuning tune{64, 256, 16, 1, 0, 0};
   hipGraphExec_t graph = nullptr;
   int graph_chunk = 0;
   std::vector<double> t_start;         // host clock at each grid's start
@@ -710,7 +710,8 @@ void launch_iteration(acopf_s* h, int slot) {
   if (h->tune.xstep_waves > 0)
     acopf_dev::launch_xstep_persistent(ba, h->n6, h->tune.xstep_waves * 4 * h->n_cu, s);
   else
-    acopf_dev::launch_xstep(ba, h->n6, h->tune.xstep_block, s);
+    acopf_dev::launch_xstep(ba, h->n6, h->tune.xstep_block, h->tune.xstep_per_lane,
+                            4 * h->n_cu, s);
   mark(1);
   BusArgs bu{h->nb, h->ng, h->ne, h->tile, h->bus_grid, h->ctl, h->gptr, h->eptr,
              h->pd, h->qd, h->gs, h->bs, h->isref, h->u, h->lam, h->v, h->z, h->y,
@@ -1618,6 +1619,8 @@ static int check_tuning(const acopf_tuning& t) {
   if (t.chunk < 1 || t.chunk > kChunk * 4) return fail(ACOPF_EINVAL, "chunk must be in [1, 64]");
   if (t.xstep_waves < 0 || t.xstep_waves > 4)
     return fail(ACOPF_EINVAL, "xstep_waves must be in [0, 4]");
+  if (t.xstep_per_lane < 0 || t.xstep_per_lane > 8)
+    return fail(ACOPF_EINVAL, "xstep_per_lane must be in [0, 8]");
   return ACOPF_OK;
 }
 
@@ -1657,14 +1660,16 @@ int acopf_autotune(acopf_handle h, int32_t iters, acopf_tuning* out) {
   const std::vector<double> ts0 = h->t_start, te0 = h->t_end;
   acopf_tuning best = h->tune;
   double best_t = 1e300;
-  // x-step variants: one lane per branch at three block sizes, or the
-  // persistent kernel at one or two wavefronts per SIMD
-  const int xs[5][2] = {{64, 0}, {128, 0}, {256, 0}, {64, 1}, {64, 2}};
+  // x-step variants {block, persistent waves, unlimited branches per lane}:
+  // lane per branch at three block sizes (branches per lane automatic, or
+  // one), or the persistent kernel at one or two wavefronts per SIMD
+  const int xs[7][3] = {{64, 0, 0}, {64, 0, 1}, {128, 0, 0}, {256, 0, 0},
+                        {64, 1, 0}, {64, 2, 0}, {128, 0, 1}};
   const int bs[4] = {128, 256, 512, 1024}, cs[3] = {8, 16, 32};
   for (const auto& xi : xs)
     for (int bi : bs)
       for (int ci : cs) {
-        acopf_tuning t{xi[0], bi, ci, 1, xi[1]};
+        acopf_tuning t{xi[0], bi, ci, 1, xi[1], xi[2]};
         rc = apply_tuning(h, t);
         if (rc) return rc;
         double tmin = 1e300;

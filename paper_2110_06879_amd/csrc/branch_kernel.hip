@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace acopf_dev {
@@ -1189,31 +1191,48 @@ void launch_xstep_persistent(const BranchArgs& A, int64_t n6, int blocks, hipStr
 #define ACOPF_XSTEP_WAVES_PER_EU 1
 #endif
 
+// Lane-per-branch x-step. Blocks [0, bg) take the generators (short, so
+// their SIMD slots free up at once), blocks [bg, bg + b6) one rated branch per
+// lane, and the remaining b4 blocks k4 unlimited branches per lane, one after
+// the other (branch base + j * b4 * blockDim for j < k4). With k4 chosen so
+// that every branch wavefront is resident from the start, the cheap unlimited
+// branches finish inside the span of the expensive rated ones instead of
+// waiting for a second round of SIMD slots.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ACOPF_XSTEP_WAVES_PER_EU)))
-void xstep_kernel(BranchArgs A, int64_t n6, int b6, int b4) {
+void xstep_kernel(BranchArgs A, int64_t n6, int bg, int b6, int b4, int k4) {
   Counters cnt = {};
-  bool active = false;
+  uint32_t solves = 0;
   const int b = blockIdx.x;
   const int bs = blockDim.x;
-  if (b < b6 + b4) {
-    const bool six = b < b6;
-    const int64_t l = six ? (int64_t)b * bs + threadIdx.x
-                          : n6 + (int64_t)(b - b6) * bs + threadIdx.x;
-    if (six ? l < n6 : l < A.nl) {
-      const int grid = A.br_grid[l];
-      if (A.ctl[grid].done == 0) {
-        active = true;
-        if (six) solve_branch<6>(A, l, grid, cnt);
-        else solve_branch<4>(A, l, grid, cnt);
-      }
-    }
-  } else {
-    const int64_t g = (int64_t)(b - b6 - b4) * bs + threadIdx.x;
+  if (b < bg) {
+    const int64_t g = (int64_t)b * bs + threadIdx.x;
     if (g < A.ng && A.ctl[A.gen_grid[g]].done == 0) solve_generator(A, g);
     return;  // whole block is generators: no branch counters
   }
+  if (b < bg + b6) {
+    const int64_t l = (int64_t)(b - bg) * bs + threadIdx.x;
+    if (l < n6) {
+      const int grid = A.br_grid[l];
+      if (A.ctl[grid].done == 0) {
+        ++solves;
+        solve_branch<6>(A, l, grid, cnt);
+      }
+    }
+  } else {
+    const int64_t base = n6 + (int64_t)(b - bg - b6) * bs + threadIdx.x;
+    const int64_t stride = (int64_t)b4 * bs;
+    for (int j = 0; j < k4; ++j) {
+      const int64_t l = base + j * stride;
+      if (l >= A.nl) break;
+      const int grid = A.br_grid[l];
+      if (A.ctl[grid].done == 0) {
+        ++solves;
+        solve_branch<4>(A, l, grid, cnt);
+      }
+    }
+  }
   // wave-level reduction of the counters, one atomic per counter per wavefront
-  uint64_t v[15] = {active ? 1ull : 0ull, (uint64_t)cnt.flops, (uint64_t)cnt.trig, cnt.tron_calls,
+  uint64_t v[15] = {(uint64_t)solves, (uint64_t)cnt.flops, (uint64_t)cnt.trig, cnt.tron_calls,
                     cnt.tron_iters, cnt.n_fgh, cnt.n_f, cnt.cauchy, cnt.cg, cnt.chol,
                     cnt.ps, cnt.al, cnt.conv, cnt.maxit, cnt.stall};
 #pragma unroll
@@ -1229,12 +1248,24 @@ void xstep_kernel(BranchArgs A, int64_t n6, int b6, int b4) {
   }
 }
 
-void launch_xstep(const BranchArgs& A, int64_t n6, int block, hipStream_t s) {
-  const int b6 = (int)((n6 + block - 1) / block);
-  const int b4 = (int)((A.nl - n6 + block - 1) / block);
+void launch_xstep(const BranchArgs& A, int64_t n6, int block, int per_lane, int slots,
+                  hipStream_t s) {
+  const int64_t n4 = A.nl - n6;
   const int bg = (int)((A.ng + block - 1) / block);
-  if (b6 + b4 + bg == 0) return;
-  hipLaunchKernelGGL(xstep_kernel, dim3(b6 + b4 + bg), dim3(block), 0, s, A, n6, b6, b4);
+  const int b6 = (int)((n6 + block - 1) / block);
+  int k4 = per_lane;
+  if (k4 <= 0) {
+    // automatic: as many unlimited branches per lane as it takes for every
+    // branch wavefront to be resident at once (one per SIMD slot)
+    const int64_t waves6 = (int64_t)b6 * ((block + 63) / 64);
+    const int64_t free_lanes = ((int64_t)slots - waves6) * 64;
+    k4 = 1;
+    if (free_lanes >= (int64_t)slots * 8)
+      k4 = (int)std::min<int64_t>(8, std::max<int64_t>(1, (n4 + free_lanes - 1) / free_lanes));
+  }
+  const int b4 = (int)((n4 + (int64_t)block * k4 - 1) / ((int64_t)block * k4));
+  if (bg + b6 + b4 == 0) return;
+  hipLaunchKernelGGL(xstep_kernel, dim3(bg + b6 + b4), dim3(block), 0, s, A, n6, bg, b6, b4, k4);
 }
 
 }  // namespace acopf_dev

@@ -54,7 +54,10 @@ struct BranchArgs {
 // One launch for the whole x-step with `block` threads per block (a multiple
 // of 64): blocks [0, b6) solve rated branches [0, n6), blocks [b6, b6 + b4)
 // unlimited branches [n6, nl), the remaining blocks the generators.
-void launch_xstep(const BranchArgs& A, int64_t n6, int block, hipStream_t s);
+// Lane-per-branch x-step; per_lane unlimited branches per lane (0: choose it
+// so that every branch wavefront fits the device's `slots` SIMD slots).
+void launch_xstep(const BranchArgs& A, int64_t n6, int block, int per_lane, int slots,
+                  hipStream_t s);
 
 // Persistent x-step on `blocks` 64-lane blocks; the pool counters must be
 // zero at launch and are zero again when it ends.

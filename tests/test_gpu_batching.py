@@ -45,18 +45,19 @@ def test_graph_replay_equals_plain_launches():
         assert_same(states(s1), states(s2))
 
 
-@pytest.mark.parametrize("waves", [1, 2])
-def test_persistent_xstep_equals_lane_per_branch(waves):
-    """The pool kernel reorders which lane solves which branch, never the
-    arithmetic of a solve: states, per-grid results and every event and flop
-    count are bitwise those of the lane-per-branch kernel, also while grids of
-    the batch finish at different iterations."""
-    note(f"persistent x-step (waves {waves}) vs lane per branch, 4-grid batch to convergence")
+@pytest.mark.parametrize("variant", [dict(xstep_waves=1), dict(xstep_waves=2),
+                                     dict(xstep_per_lane=3), dict(xstep_per_lane=8, xstep_block=128)])
+def test_xstep_variants_equal_lane_per_branch(variant):
+    """The pool kernel and several branches per lane change which lane solves
+    which branch, never the arithmetic of a solve: states, per-grid results
+    and every event and flop count are bitwise those of one branch per lane,
+    also while grids of the batch finish at different iterations."""
+    note(f"x-step {variant} vs one branch per lane, 4-grid batch to convergence")
     gs = [gridgen(200 + 90 * k, 40 + 9 * k, 260 + 120 * k, 0.3 * k, 70 + k, load_factor=0.2)
           for k in range(4)]
     with A.Solver(gs) as s1, A.Solver(gs) as s2:
-        s1.set_tuning(xstep_waves=0)
-        s2.set_tuning(xstep_waves=waves)
+        s1.set_tuning(xstep_waves=0, xstep_per_lane=1)
+        s2.set_tuning(**variant)
         r1 = s1.solve(A.COLD)
         r2 = s2.solve(A.COLD)
         for a, b in zip(r1, r2):

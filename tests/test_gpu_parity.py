@@ -49,18 +49,23 @@ def note(msg):
     sys.stdout.flush()
 
 
-# xstep_waves 0: one lane per branch; 1: the persistent pool kernel
-@pytest.mark.parametrize("waves", [0, 1])
+# x-step kernels: lane per branch (unlimited branches per lane automatic, or
+# three per lane), and the persistent pool kernel
+XSTEP = {"lane": dict(xstep_waves=0, xstep_per_lane=0), "lane3": dict(xstep_waves=0, xstep_per_lane=3),
+         "pool": dict(xstep_waves=1, xstep_per_lane=0)}
+
+
+@pytest.mark.parametrize("waves", list(XSTEP))
 @pytest.mark.parametrize("name,iters", [("c1_30bus", 50), ("c2_2kbus", 50)])
 def test_fixed_iterations_match_oracle(name, iters, waves):
-    note(f"parity {name} cold {iters} fixed iterations, xstep_waves {waves}")
+    note(f"parity {name} cold {iters} fixed iterations, x-step {waves}")
     g = config_grid(name)
     p = A.Params(rho_pq=400.0, rho_va=400.0 if name == "c1_30bus" else 40000.0)
     orc = O.Oracle(g, oparams(p))
     orc.count_flops(True)
     orc.solve(iters)
     with A.Solver(g, p) as s:
-        s.set_tuning(xstep_waves=waves)
+        s.set_tuning(**XSTEP[waves])
         res = s.solve(A.COLD, iters)[0]
         assert res["inner_iters"] == iters
         compare(s, orc, label=name)
@@ -125,9 +130,9 @@ def test_continue_equals_one_run_and_determinism():
         np.testing.assert_array_equal(a, s1.get("u"))
 
 
-@pytest.mark.parametrize("waves", [0, 1])
+@pytest.mark.parametrize("waves", list(XSTEP))
 def test_edge_grids_match_oracle(waves):
-    note(f"edge grids, xstep_waves {waves}")
+    note(f"edge grids, x-step {waves}")
     cases = []
     # two buses, one branch, one generator; ragged sizes; shunts and taps
     g = gridgen(2, 1, 1, 1.0, 31)
@@ -146,7 +151,7 @@ def test_edge_grids_match_oracle(waves):
         orc = O.Oracle(g, oparams(p))
         orc.solve(30)
         with A.Solver(g, p) as s:
-            s.set_tuning(xstep_waves=waves)
+            s.set_tuning(**XSTEP[waves])
             s.solve(A.COLD, 30)
             compare(s, orc, tol=1e-9, label=name)
 
@@ -210,15 +215,15 @@ def test_warm_start_matches_oracle():
         np.testing.assert_array_equal(s.get("pd"), pd)
 
 
-@pytest.mark.parametrize("waves", [0, 1])
+@pytest.mark.parametrize("waves", list(XSTEP))
 def test_70k_one_iteration_from_gpu_state(waves):
     """Full-size grid: GPU state after 3 iterations is loaded into the oracle;
     one more iteration on both sides must agree on every vector."""
-    note(f"parity c3 70k: one iteration from GPU state, xstep_waves {waves}")
+    note(f"parity c3 70k: one iteration from GPU state, x-step {waves}")
     g = config_grid("c3_70kbus")
     p = A.Params(rho_pq=400.0, rho_va=40000.0)
     with A.Solver(g, p) as s:
-        s.set_tuning(xstep_waves=waves)
+        s.set_tuning(**XSTEP[waves])
         s.solve(A.COLD, 3)
         orc = O.Oracle(g, oparams(p))
         for k in VECS + ("rtil",):
