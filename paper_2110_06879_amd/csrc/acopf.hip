@@ -76,9 +76,15 @@ constexpr int kChunk = 16;      // iterations between control readbacks
 // kernels
 // ---------------------------------------------------------------------------
 
+// One bus tile: buses [b0, b1) of grid `grid`, their branch ends [e0, e1)
+// and generators [g0, g1) in the device orders.
+struct TileDesc {
+  int b0, b1, e0, e1, g0, g1, grid, pad;
+};
+
 struct BusArgs {
   int64_t nb, ng, ne;
-  const int* tile;  // [n_tiles + 1] bus ranges; a tile never spans two grids
+  const TileDesc* tdesc;  // [n_tiles]; a tile never spans two grids
   const int* bus_grid;
   GridCtl* ctl;
   const int *gptr, *eptr;
@@ -120,15 +126,15 @@ __device__ inline int tile_bus_of(const int* ptr, int b0, int nbt, int base, int
 //      c_k = rho_k (u_k + z_k) + y_k of the tile's couplings into LDS
 //      (coalesced: the tile's couplings are contiguous in every block);
 //   2. lane per bus: the sums over its couplings in their fixed order, read
-//      from LDS, and the 2x2 solve;
+//      from LDS, and the 2x2 solve (its bus data loaded during phase 1);
 //   3. lane per branch end / generator: new v, z, y and the residuals.
 // Ends or generators beyond the LDS capacity (a bus of very high degree) are
 // recomputed from global memory with the same operations.
 __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
   extern __shared__ double sm[];
   const int t = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-  const int b0 = A.tile[t], b1 = A.tile[t + 1], nbt = b1 - b0;
-  const int grid = A.bus_grid[b0];
+  const TileDesc D = A.tdesc[t];
+  const int b0 = D.b0, nbt = D.b1 - D.b0, grid = D.grid;
   if (A.ctl[grid].done) return;  // uniform: the tile lies in one grid
   const int ecap = A.ecap, gcap = A.gcap, tb = A.tbmax;
   double* cE = sm;              // [4][ecap] targets of end blocks p, q, w, theta
@@ -139,11 +145,24 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
   const int64_t ng = A.ng, ne = A.ne;
   const int64_t kP = 2 * ng, kQ = kP + ne, kW = kQ + ne, kT = kW + ne;
   const double rpq = A.rho_pq, rva = A.rho_va;
-  const int E0 = A.eptr[b0], E1 = A.eptr[b1];
-  const int G0 = A.gptr[b0], G1 = A.gptr[b1];
-  const int net = E1 - E0, ngt = G1 - G0;
+  const int E0 = D.e0, G0 = D.g0;
+  const int net = D.e1 - D.e0, ngt = D.g1 - D.g0;
   auto target = [&](int64_t k, double rho) { return rho * (A.u[k] + A.z[k]) + A.y[k]; };
-  // ---- phase 1
+  // ---- phase 1 (and the bus data of phase 2, so that its loads are in flight)
+  int be0 = 0, be1 = 0, bg0 = 0, bg1 = 0, bref = 0;
+  double bgs = 0.0, bbs = 0.0, bpd = 0.0, bqd = 0.0;
+  if (tid < nbt) {
+    const int i = b0 + tid;
+    be0 = A.eptr[i] - E0;
+    be1 = A.eptr[i + 1] - E0;
+    bg0 = A.gptr[i] - G0;
+    bg1 = A.gptr[i + 1] - G0;
+    bgs = A.gs[i];
+    bbs = A.bs[i];
+    bpd = A.pd[i];
+    bqd = A.qd[i];
+    bref = A.isref[i];
+  }
   for (int e = tid; e < net && e < ecap; e += nt) {
     const int64_t k = E0 + e;
     cE[0 * ecap + e] = target(kP + k, rpq);
@@ -167,30 +186,27 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
   };
   // ---- phase 2
   if (tid < nbt) {
-    const int i = b0 + tid;
-    const int e0 = A.eptr[i] - E0, e1 = A.eptr[i + 1] - E0;
-    const int g0 = A.gptr[i] - G0, g1 = A.gptr[i + 1] - G0;
     // shared w and theta of the bus
     double Qw = 0.0, cw = 0.0, Qt = 0.0, ct = 0.0;
-    for (int e = e0; e < e1; ++e) {
+    for (int e = be0; e < be1; ++e) {
       Qw += rva;
       cw += cend(2, e);
       Qt += rva;
       ct += cend(3, e);
       if (e < ecap) emap[e] = (unsigned short)tid;
     }
-    const double awP = -A.gs[i], awQ = A.bs[i];
+    const double awP = -bgs, awQ = bbs;
     double M00 = awP * awP / Qw, M01 = awP * awQ / Qw, M11 = awQ * awQ / Qw;
-    double r0 = awP * cw / Qw - A.pd[i], r1 = awQ * cw / Qw - A.qd[i];
+    double r0 = awP * cw / Qw - bpd, r1 = awQ * cw / Qw - bqd;
     const double inv_pq = 1.0 / rpq;
-    for (int g = g0; g < g1; ++g) {
+    for (int g = bg0; g < bg1; ++g) {
       M00 += inv_pq;
       r0 += cgen(0, g) / rpq;
       M11 += inv_pq;
       r1 += cgen(1, g) / rpq;
       if (g < gcap) gmap[g] = (unsigned short)tid;
     }
-    for (int e = e0; e < e1; ++e) {
+    for (int e = be0; e < be1; ++e) {
       M00 += inv_pq;
       r0 += -cend(0, e) / rpq;
       M11 += inv_pq;
@@ -202,7 +218,7 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
     bv[tid] = mu0;
     bv[tb + tid] = mu1;
     bv[2 * tb + tid] = (cw - awP * mu0 - awQ * mu1) / Qw;
-    bv[3 * tb + tid] = A.isref[i] ? 0.0 : ct / Qt;
+    bv[3 * tb + tid] = bref ? 0.0 : ct / Qt;
   }
   __syncthreads();
   // ---- phase 3
@@ -573,7 +589,7 @@ struct acopf_s {
   double *u, *v, *z, *y, *lam, *bx, *ltil, *rtil;
   int *gptr, *eptr, *isref;
   std::vector<int> gptr_h, eptr_h;  // host copies, for the bus tiles
-  int* tile = nullptr;               // [nb + 1] bus tiles of the bus kernel
+  TileDesc* tdesc = nullptr;         // [nb] bus tiles of the bus kernel
   int n_tiles = 0, tile_block = 0, ecap = 0, gcap = 0, tbmax = 0;
   double *pd, *qd, *gs, *bs;
   GridCtl* ctl;
@@ -668,29 +684,32 @@ int build_tiles(acopf_s* h, int block) {
   const int gcap = std::max(16, tb);
   int ecap = (budget - gcap * (16 + 2)) / (32 + 2);
   ecap = std::max(1, std::min(ecap, 8 * tb));
-  std::vector<int> tiles, grid_tile;
+  std::vector<TileDesc> tiles;
+  std::vector<int> grid_tile;
   tiles.reserve(h->nb / 8 + h->G + 1);
-  for (const HostGrid& H : h->grids) {
+  for (int g = 0; g < h->G; ++g) {
+    const HostGrid& H = h->grids[g];
     grid_tile.push_back((int)tiles.size());
     int64_t b = H.bus_off;
     const int64_t bend = H.bus_off + H.nb;
     while (b < bend) {
-      tiles.push_back((int)b);
       int64_t c = b;
       while (c < bend && c - b < tb &&
              h->eptr_h[c + 1] - h->eptr_h[b] <= ecap && h->gptr_h[c + 1] - h->gptr_h[b] <= gcap)
         ++c;
-      b = std::max(c, b + 1);
+      c = std::max(c, b + 1);
+      tiles.push_back(TileDesc{(int)b, (int)c, h->eptr_h[b], h->eptr_h[c], h->gptr_h[b],
+                               h->gptr_h[c], g, 0});
+      b = c;
     }
   }
   grid_tile.push_back((int)tiles.size());
-  tiles.push_back((int)h->nb);
-  HIP_TRY(hipMemcpyAsync(h->tile, tiles.data(), sizeof(int) * tiles.size(),
+  HIP_TRY(hipMemcpyAsync(h->tdesc, tiles.data(), sizeof(TileDesc) * tiles.size(),
                          hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipMemcpyAsync(h->grid_tile, grid_tile.data(), sizeof(int) * grid_tile.size(),
                          hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
-  h->n_tiles = (int)tiles.size() - 1;
+  h->n_tiles = (int)tiles.size();
   h->tile_block = block;
   h->ecap = ecap;
   h->gcap = gcap;
@@ -713,7 +732,7 @@ void launch_iteration(acopf_s* h, int slot) {
     acopf_dev::launch_xstep(ba, h->n6, h->tune.xstep_block, h->tune.xstep_per_lane,
                             4 * h->n_cu, s);
   mark(1);
-  BusArgs bu{h->nb, h->ng, h->ne, h->tile, h->bus_grid, h->ctl, h->gptr, h->eptr,
+  BusArgs bu{h->nb, h->ng, h->ne, h->tdesc, h->bus_grid, h->ctl, h->gptr, h->eptr,
              h->pd, h->qd, h->gs, h->bs, h->isref, h->u, h->lam, h->v, h->z, h->y,
              h->P.rho_pq, h->P.rho_va, h->tmax, h->ecap, h->gcap, h->tbmax};
   const int bb = h->tile_block;
@@ -1058,7 +1077,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   double** cp_d[] = {&h->u, &h->v, &h->z, &h->y, &h->lam};
   for (double** p : cp_d) HIP_TRY(D.alloc(p, m));
   HIP_TRY(D.alloc(&h->gptr, nb + 1));
-  HIP_TRY(D.alloc(&h->tile, nb + 1));
+  HIP_TRY(D.alloc(&h->tdesc, nb));
   HIP_TRY(D.alloc(&h->eptr, nb + 1));
   HIP_TRY(D.alloc(&h->isref, nb));
   double** bus_d[] = {&h->pd, &h->qd, &h->gs, &h->bs};
