@@ -229,6 +229,19 @@ int acopf_get_sizes(acopf_handle h, int32_t grid, int64_t* out4);
  * Errors: EINVAL, EDEVICE. */
 int acopf_set_profiling(acopf_handle h, int32_t on);
 
+/* Solution quality of grid `grid` at its current state (Sec. IV-A): the
+ * ADMM solution is the generator outputs of the generator problems and w,
+ * theta of the bus problems (from the bus's first branch end), with the flows
+ * recomputed from them by eqs. (pij)-(qji). out6 (p.u.): [0] ||c(x)||_inf
+ * over eq. (acopf), the largest of the rest; [1] max |residual of eq. (pg)|;
+ * [2] of eq. (qg); [3] max excess sqrt(p^2 + q^2) - rate of eqs.
+ * (ij-limit)-(ji-limit) on the unscaled rating; [4] max excess of v = sqrt(w)
+ * over [vmin, vmax]; [5] max excess of |theta| over 2 pi. A NaN in the state
+ * shows as NaN. Generator bounds hold by construction. Synchronous on the
+ * handle's stream; allocates its scratch on the first call.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+int acopf_quality(acopf_handle h, int32_t grid, double* out6);
+
 /* Average device time (ms) per launch over every iteration run with
  * profiling on since the handle was created: out[0] x-step (generators and
  * branches), out[1] bus/z/y/residual step, out[2] control (which also

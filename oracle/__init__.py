@@ -40,6 +40,10 @@ def build(verbose: bool = False) -> str:
     return _LIB_PATH
 
 
+QUALITY_NAMES = ("max_violation", "balance_p", "balance_q", "line_limit", "voltage_limit",
+                 "angle_limit")
+
+
 class _Params(C.Structure):
     _fields_ = [
         ("rho_pq", C.c_double), ("rho_va", C.c_double),
@@ -130,6 +134,8 @@ def load() -> C.CDLL:
         getattr(lib, name).restype = None
     lib.ora_objective.argtypes = [vp]
     lib.ora_objective.restype = C.c_double
+    lib.ora_quality.argtypes = [vp, dp]
+    lib.ora_quality.restype = None
     lib.ora_iterate.argtypes = [vp, ip]
     lib.ora_iterate.restype = ip
     lib.ora_solve.argtypes = [vp, ip]
@@ -279,6 +285,13 @@ class Oracle:
 
     def objective(self) -> float:
         return float(self.lib.ora_objective(self.h))
+
+    def quality(self) -> dict:
+        """||c(x)||_inf over eq. acopf at the current ADMM solution and its
+        parts (power balance p and q, line limits, voltage and angle limits)."""
+        out = np.zeros(6)
+        self.lib.ora_quality(self.h, _dp(out))
+        return dict(zip(QUALITY_NAMES, out.tolist()))
 
     def iterate(self, fixed: bool = False) -> bool:
         return bool(self.lib.ora_iterate(self.h, int(fixed)))

@@ -740,6 +740,7 @@ struct Oracle {
   std::vector<int> from, to;
   // admittances (Sec. II-A, below eq. acopf) and squared scaled ratings
   std::vector<double> gii, bii, gij, bij, gji, bji, gjj, bjj, rate2;
+  std::vector<double> rate;  // unscaled rating (p.u.), <= 0 unlimited
   std::vector<int> rated;
   // couplings
   std::vector<double> u, v, z, y, lam, rho, vprev;
@@ -797,7 +798,7 @@ void* ora_create(const ora_grid* G, const ora_params* P) {
   const int nl = o->nl;
   o->gii.resize(nl); o->bii.resize(nl); o->gij.resize(nl); o->bij.resize(nl);
   o->gji.resize(nl); o->bji.resize(nl); o->gjj.resize(nl); o->bjj.resize(nl);
-  o->rate2.resize(nl); o->rated.resize(nl);
+  o->rate2.resize(nl); o->rated.resize(nl); o->rate.resize(nl);
   for (int l = 0; l < nl; ++l) {
     // series admittance y = 1/(r + jx), shunt j b/2 per end, a = tap e^{j shift}
     double r = G->r[l], xx = G->x[l];
@@ -821,6 +822,7 @@ void* ora_create(const ora_grid* G, const ora_params* P) {
     double rs = G->rate[l] * P->rate_scale;
     o->rated[l] = G->rate[l] > 0.0 ? 1 : 0;
     o->rate2[l] = o->rated[l] ? rs * rs : 0.0;
+    o->rate[l] = G->rate[l];
   }
   o->bus_gens.assign(o->nb, {});
   o->bus_from.assign(o->nb, {});
@@ -1085,6 +1087,78 @@ void ora_outer_step(void* h) {
   o->znorm_prev = o->r_z;
   o->outer += 1;
   o->inner_in_outer = 0;
+}
+
+// Solution quality, Sec. IV-A: the ADMM solution is the generator outputs of
+// the generator problems and w_i, theta_i of the bus problems (taken from the
+// bus's first branch end: from-ends, then to-ends, in input order); the flows
+// are recomputed from w, theta with eqs. (pij)-(qji), w^R = v_i v_j cos,
+// w^I = v_i v_j sin, v = sqrt(w). out6 receives ||c(x)||_inf over eq. acopf
+// and its parts: max |residual of (pg)|, of (qg), max excess of the line
+// limits (ij-limit)-(ji-limit) on the unscaled rating, of the voltage limits
+// (v = sqrt(w) within [vmin, vmax]) and of |theta| <= 2 pi. Generator
+// outputs are within their bounds by construction (projection).
+// maximum that keeps a NaN once one appears, so that a broken state shows
+static inline double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
+void ora_quality(void* h, double* out6) {
+  auto* o = static_cast<Oracle*>(h);
+  const int ng = o->ng;
+  std::vector<double> bw(o->nb), bt(o->nb);
+  for (int i = 0; i < o->nb; ++i) {
+    const int k = !o->bus_from[i].empty() ? 2 * ng + 8 * o->bus_from[i][0] + 4
+                                          : 2 * ng + 8 * o->bus_to[i][0] + 6;
+    bw[i] = o->v[k];
+    bt[i] = o->v[k + 1];
+  }
+  std::vector<double> pij(o->nl), qij(o->nl), pji(o->nl), qji(o->nl);
+  double line = 0.0;
+  for (int l = 0; l < o->nl; ++l) {
+    const int i = o->from[l], j = o->to[l];
+    const double wi = bw[i], wj = bw[j];
+    double sn, cs;
+    series_sincos(bt[i] - bt[j], &sn, &cs);
+    const double vv = std::sqrt(wi) * std::sqrt(wj);
+    const double WR = vv * cs, WI = vv * sn;
+    pij[l] = std::fma(o->bij[l], WI, std::fma(o->gij[l], WR, o->gii[l] * wi));
+    qij[l] = std::fma(o->gij[l], WI, std::fma(-o->bij[l], WR, -o->bii[l] * wi));
+    pji[l] = std::fma(-o->bji[l], WI, std::fma(o->gji[l], WR, o->gjj[l] * wj));
+    qji[l] = std::fma(-o->gji[l], WI, std::fma(-o->bji[l], WR, -o->bjj[l] * wj));
+    if (o->rate[l] > 0.0) {
+      const double sf = std::sqrt(std::fma(pij[l], pij[l], qij[l] * qij[l]));
+      const double st = std::sqrt(std::fma(pji[l], pji[l], qji[l] * qji[l]));
+      line = nanmax(line, nanmax(sf - o->rate[l], st - o->rate[l]));
+    }
+  }
+  double balp = 0.0, balq = 0.0, volt = 0.0, ang = 0.0;
+  for (int i = 0; i < o->nb; ++i) {
+    double sp = 0.0, sq = 0.0;
+    for (int g : o->bus_gens[i]) {
+      sp = sp + o->u[2 * g];
+      sq = sq + o->u[2 * g + 1];
+    }
+    sp = std::fma(-o->gs[i], bw[i], sp - o->pd[i]);
+    sq = std::fma(o->bs[i], bw[i], sq - o->qd[i]);
+    for (int l : o->bus_from[i]) {
+      sp = sp - pij[l];
+      sq = sq - qij[l];
+    }
+    for (int l : o->bus_to[i]) {
+      sp = sp - pji[l];
+      sq = sq - qji[l];
+    }
+    balp = nanmax(balp, std::fabs(sp));
+    balq = nanmax(balq, std::fabs(sq));
+    const double vm = bw[i] > 0.0 ? std::sqrt(bw[i]) : 0.0;
+    volt = nanmax(volt, nanmax(o->vmin[i] - vm, vm - o->vmax[i]));
+    ang = nanmax(ang, std::fabs(bt[i]) - TWO_PI);
+  }
+  out6[1] = balp;
+  out6[2] = balq;
+  out6[3] = line;
+  out6[4] = volt;
+  out6[5] = ang;
+  out6[0] = nanmax(nanmax(nanmax(balp, balq), nanmax(line, volt)), ang);
 }
 
 double ora_objective(void* h) {

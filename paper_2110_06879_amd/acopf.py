@@ -32,7 +32,9 @@ EXPORTS = ("acopf_default_params", "acopf_create", "acopf_solve", "acopf_update_
            "acopf_get_state", "acopf_set_state", "acopf_get_sizes", "acopf_set_profiling",
            "acopf_get_timing", "acopf_destroy", "acopf_last_error", "acopf_start",
            "acopf_run", "acopf_poll", "acopf_copy_grid", "acopf_snapshot",
-           "acopf_set_tuning", "acopf_get_tuning", "acopf_autotune")
+           "acopf_set_tuning", "acopf_get_tuning", "acopf_autotune", "acopf_quality")
+QUALITY_NAMES = ("max_violation", "balance_p", "balance_q", "line_limit", "voltage_limit",
+                 "angle_limit")
 
 
 class AcopfError(RuntimeError):
@@ -145,6 +147,7 @@ def load(path: str | None = None) -> C.CDLL:
     lib.acopf_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     lib.acopf_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     lib.acopf_autotune.argtypes = [vp, i32, C.POINTER(_Tuning)]
+    lib.acopf_quality.argtypes = [vp, i32, dp]
     lib.acopf_destroy.argtypes = [vp]
     lib.acopf_destroy.restype = None
     lib.acopf_last_error.restype = C.c_char_p
@@ -152,7 +155,7 @@ def load(path: str | None = None) -> C.CDLL:
                  "acopf_set_state", "acopf_get_sizes", "acopf_get_timing",
                  "acopf_set_profiling", "acopf_start", "acopf_run", "acopf_poll",
                  "acopf_copy_grid", "acopf_snapshot", "acopf_set_tuning",
-                 "acopf_get_tuning", "acopf_autotune"):
+                 "acopf_get_tuning", "acopf_autotune", "acopf_quality"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -298,6 +301,13 @@ class Solver:
         t = _Tuning()
         self._check(self.lib.acopf_get_tuning(self.h, C.byref(t)))
         return t.as_dict()
+
+    def quality(self, grid: int = 0) -> dict:
+        """||c(x)||_inf over eq. acopf at the grid's current ADMM solution and
+        its parts (power balance p and q, line, voltage and angle limits)."""
+        out = np.zeros(6)
+        self._check(self.lib.acopf_quality(self.h, grid, _dp(out)))
+        return dict(zip(QUALITY_NAMES, out.tolist()))
 
     def autotune(self, iters: int = 32) -> dict:
         t = _Tuning()

@@ -586,12 +586,17 @@ struct acopf_s {
   int *ef = nullptr, *et = nullptr;
   double *pmin, *pmax, *qmin, *qmax, *c2q, *c1l, *c2, *c1, *c0;
   double *adm, *vlo_i, *vhi_i, *vlo_j, *vhi_j, *rate2;
+  double* rate = nullptr;     // [nl] unscaled ratings (solution quality)
+  int* end_bus = nullptr;     // [2 nl] bus of each branch end
+  double* qscratch = nullptr; // [2 nb + 4 nl] quality scratch (lazy)
+  unsigned long long* qual = nullptr;  // [6 G] quality maxima (lazy)
   double *u, *v, *z, *y, *lam, *bx, *ltil, *rtil;
   int *gptr, *eptr, *isref;
   std::vector<int> gptr_h, eptr_h;  // host copies, for the bus tiles
   TileDesc* tdesc = nullptr;         // [nb] bus tiles of the bus kernel
   int n_tiles = 0, tile_block = 0, ecap = 0, gcap = 0, tbmax = 0;
   double *pd, *qd, *gs, *bs;
+  double *vmin_b, *vmax_b;  // [nb] voltage limits (solution quality)
   GridCtl* ctl;
   GridCtl* h_ctl = nullptr;  // pinned
   unsigned long long* stats;
@@ -852,6 +857,8 @@ void acopf_destroy(acopf_handle h) {
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
   for (void* p : h->snap) (void)hipFree(p);
+  if (h->qscratch) (void)hipFree(h->qscratch);
+  if (h->qual) (void)hipFree(h->qual);
   h->buf.release();
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -994,8 +1001,9 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   std::vector<int> gen_grid(ng), bus_grid(nb), isref(nb, 0);
   std::vector<double> pmin(ng), pmax(ng), qmin(ng), qmax(ng), c2q(ng), c1l(ng), c2(ng),
       c1(ng), c0(ng);
-  std::vector<double> adm(8 * nl), vlo_i(nl), vhi_i(nl), vlo_j(nl), vhi_j(nl), rate2(nl);
-  std::vector<double> pd(nb), qd(nb), gs(nb), bs(nb);
+  std::vector<double> adm(8 * nl), vlo_i(nl), vhi_i(nl), vlo_j(nl), vhi_j(nl), rate2(nl),
+      rate(nl);
+  std::vector<double> pd(nb), qd(nb), gs(nb), bs(nb), vmin_b(nb), vmax_b(nb);
   std::vector<int64_t> gen_off(n_grids + 1, 0);
   std::vector<double> base(n_grids);
   const double s = params->obj_scale;
@@ -1025,6 +1033,8 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
       pd[d] = G.pd[i];
       qd[d] = G.qd[i];
       gs[d] = G.gs[i];
+      vmin_b[d] = G.vmin[i];
+      vmax_b[d] = G.vmax[i];
       bs[d] = G.bs[i];
       isref[d] = i == G.ref_bus;
     }
@@ -1056,6 +1066,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
       vhi_j[d] = G.vmax[j];
       const double rs = G.rate[l] * params->rate_scale;
       rate2[d] = G.rate[l] > 0.0 ? rs * rs : 0.0;
+      rate[d] = G.rate[l];
     }
   }
   // ---- device allocation and upload
@@ -1070,8 +1081,10 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   double** gen_d[] = {&h->pmin, &h->pmax, &h->qmin, &h->qmax, &h->c2q, &h->c1l, &h->c2, &h->c1, &h->c0};
   for (double** p : gen_d) HIP_TRY(D.alloc(p, ng));
   HIP_TRY(D.alloc(&h->adm, 8 * nl));
-  double** br_d[] = {&h->vlo_i, &h->vhi_i, &h->vlo_j, &h->vhi_j, &h->rate2, &h->rtil};
+  double** br_d[] = {&h->vlo_i, &h->vhi_i, &h->vlo_j, &h->vhi_j, &h->rate2, &h->rtil,
+                     &h->rate};
   for (double** p : br_d) HIP_TRY(D.alloc(p, nl));
+  HIP_TRY(D.alloc(&h->end_bus, 2 * nl));
   HIP_TRY(D.alloc(&h->bx, 6 * nl));
   HIP_TRY(D.alloc(&h->ltil, 2 * nl));
   double** cp_d[] = {&h->u, &h->v, &h->z, &h->y, &h->lam};
@@ -1080,7 +1093,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(D.alloc(&h->tdesc, nb));
   HIP_TRY(D.alloc(&h->eptr, nb + 1));
   HIP_TRY(D.alloc(&h->isref, nb));
-  double** bus_d[] = {&h->pd, &h->qd, &h->gs, &h->bs};
+  double** bus_d[] = {&h->pd, &h->qd, &h->gs, &h->bs, &h->vmin_b, &h->vmax_b};
   for (double** p : bus_d) HIP_TRY(D.alloc(p, nb));
   HIP_TRY(D.alloc(&h->ctl, n_grids));
   HIP_TRY(D.alloc(&h->tmax, 3 * (nb + 1)));
@@ -1113,6 +1126,13 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(up(h->vlo_j, vlo_j.data(), sizeof(double) * nl));
   HIP_TRY(up(h->vhi_j, vhi_j.data(), sizeof(double) * nl));
   HIP_TRY(up(h->rate2, rate2.data(), sizeof(double) * nl));
+  HIP_TRY(up(h->rate, rate.data(), sizeof(double) * nl));
+  {
+    std::vector<int> end_bus(2 * nl);
+    for (int64_t b = 0; b < nb; ++b)
+      for (int e = eptr[b]; e < eptr[b + 1]; ++e) end_bus[e] = (int)b;
+    HIP_TRY(up(h->end_bus, end_bus.data(), sizeof(int) * 2 * nl));
+  }
   HIP_TRY(up(h->gptr, gptr.data(), sizeof(int) * (nb + 1)));
   h->gptr_h = gptr;
   h->eptr_h = eptr;
@@ -1122,6 +1142,8 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(up(h->qd, qd.data(), sizeof(double) * nb));
   HIP_TRY(up(h->gs, gs.data(), sizeof(double) * nb));
   HIP_TRY(up(h->bs, bs.data(), sizeof(double) * nb));
+  HIP_TRY(up(h->vmin_b, vmin_b.data(), sizeof(double) * nb));
+  HIP_TRY(up(h->vmax_b, vmax_b.data(), sizeof(double) * nb));
   HIP_TRY(up(h->gen_off_d, gen_off.data(), sizeof(int64_t) * (n_grids + 1)));
   std::vector<int64_t> end_off(n_grids + 1);
   for (int g = 0; g < n_grids; ++g) end_off[g] = h->grids[g].e0;
@@ -1729,6 +1751,39 @@ int acopf_set_profiling(acopf_handle h, int32_t on) {
     for (auto& e : h->ev) HIP_TRY(hipEventCreate(&e));
   }
   h->profile = on != 0;
+  return ACOPF_OK;
+}
+
+int acopf_quality(acopf_handle h, int32_t grid, double* out6) {
+  if (!h || !out6) return fail(ACOPF_EINVAL, "null argument");
+  if (grid < 0 || grid >= h->G) return fail(ACOPF_EINVAL, "grid index out of range");
+  HIP_TRY(hipSetDevice(h->device));
+  if (!h->qscratch) {
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(double) * (2 * h->nb + 2 * h->ne)) != hipSuccess)
+      return fail(ACOPF_ENOMEM, "quality scratch allocation failed");
+    h->qscratch = static_cast<double*>(p);
+    if (hipMalloc(&p, sizeof(unsigned long long) * 6 * h->G) != hipSuccess)
+      return fail(ACOPF_ENOMEM, "quality scratch allocation failed");
+    h->qual = static_cast<unsigned long long*>(p);
+  }
+  hipStream_t st = h->stream;
+  HIP_TRY(hipMemsetAsync(h->qual, 0, sizeof(unsigned long long) * 6 * h->G, st));
+  acopf_dev::QualityArgs Q{h->nb, h->ng, h->nl, h->ne, h->bus_grid, h->br_grid, h->gen_grid,
+                           h->gptr, h->eptr, h->ef, h->et, h->end_bus, h->adm, h->rate, h->u,
+                           h->v, h->pd, h->qd, h->gs, h->bs, h->vmin_b, h->vmax_b,
+                           h->qscratch, h->qscratch + h->nb, h->qscratch + 2 * h->nb,
+                           h->qscratch + 2 * h->nb + h->ne, h->qual};
+  acopf_dev::launch_quality(Q, st);
+  HIP_TRY(hipGetLastError());
+  unsigned long long bits[6];
+  HIP_TRY(hipMemcpyAsync(bits, h->qual + 6 * grid, sizeof(bits), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double q[6];
+  for (int k = 0; k < 6; ++k) std::memcpy(&q[k], &bits[k], sizeof(double));
+  auto nanmax = [](double a, double b) { return (b > a || b != b) ? b : a; };
+  out6[0] = nanmax(nanmax(nanmax(q[1], q[2]), nanmax(q[3], q[4])), q[5]);
+  for (int k = 1; k < 6; ++k) out6[k] = q[k];
   return ACOPF_OK;
 }
 

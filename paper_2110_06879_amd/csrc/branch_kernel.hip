@@ -1268,4 +1268,110 @@ void launch_xstep(const BranchArgs& A, int64_t n6, int block, int per_lane, int 
   hipLaunchKernelGGL(xstep_kernel, dim3(bg + b6 + b4), dim3(block), 0, s, A, n6, bg, b6, b4, k4);
 }
 
+// ---------------------------------------------------------------------------
+// Solution quality, Sec. IV-A: the ADMM solution is the generator outputs of
+// the generator problems (u) and w_i, theta_i of the bus problems (v of the
+// bus's first branch end in the bus CSR order: from-ends, then to-ends);
+// flows are recomputed from w, theta with eqs. (pij)-(qji), w^R = v_i v_j cos,
+// w^I = v_i v_j sin, v = sqrt(w), with the same operations as the branch
+// evaluation. Maxima per grid (slot order): ||c||_inf, |residual of (pg)|,
+// |of (qg)|, line-limit excess on the unscaled rating, voltage-limit excess,
+// |theta| - 2 pi excess.
+// ---------------------------------------------------------------------------
+__device__ inline double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
+// maximum into qmax[grid][slot]: one atomic per wavefront when its lanes share
+// the grid, else one per lane
+__device__ void quality_max(unsigned long long* qmax, int grid, int slot, double val) {
+  const int g0 = __shfl(grid, 0, 64);
+  const bool uniform = __ballot(grid != g0) == 0ull;
+  if (uniform) {
+    for (int off = 32; off > 0; off >>= 1) val = nanmax(val, __shfl_xor(val, off, 64));
+    if ((threadIdx.x & 63) == 0 && g0 >= 0)
+      atomicMax(&qmax[6 * g0 + slot], (unsigned long long)__double_as_longlong(val));
+  } else if (grid >= 0) {
+    atomicMax(&qmax[6 * grid + slot], (unsigned long long)__double_as_longlong(val));
+  }
+}
+
+__global__ __launch_bounds__(256) void quality_values_kernel(QualityArgs Q) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Q.nb) return;
+  const int64_t e = Q.eptr[i];
+  Q.bw[i] = Q.v[2 * Q.ng + 2 * Q.ne + e];
+  Q.bt[i] = Q.v[2 * Q.ng + 3 * Q.ne + e];
+}
+
+__global__ __launch_bounds__(256) void quality_flow_kernel(QualityArgs Q) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int grid = -1;
+  double line = 0.0;
+  if (l < Q.nl) {
+    grid = Q.br_grid[l];
+    const int64_t ef = Q.ef[l], et = Q.et[l];
+    const int i = Q.end_bus[ef], j = Q.end_bus[et];
+    const int64_t nl = Q.nl;
+    const double gii = Q.adm[0 * nl + l], bii = Q.adm[1 * nl + l], gij = Q.adm[2 * nl + l],
+                 bij = Q.adm[3 * nl + l], gji = Q.adm[4 * nl + l], bji = Q.adm[5 * nl + l],
+                 gjj = Q.adm[6 * nl + l], bjj = Q.adm[7 * nl + l];
+    const double wi = Q.bw[i], wj = Q.bw[j];
+    double sn, cs;
+    series_sincos(Q.bt[i] - Q.bt[j], &sn, &cs);
+    const double vv = sqrt(wi) * sqrt(wj);
+    const double WR = vv * cs, WI = vv * sn;
+    const double pij = fma(bij, WI, fma(gij, WR, gii * wi));
+    const double qij = fma(gij, WI, fma(-bij, WR, -bii * wi));
+    const double pji = fma(-bji, WI, fma(gji, WR, gjj * wj));
+    const double qji = fma(-gji, WI, fma(-bji, WR, -bjj * wj));
+    Q.pe[ef] = pij;
+    Q.qe[ef] = qij;
+    Q.pe[et] = pji;
+    Q.qe[et] = qji;
+    const double r = Q.rate[l];
+    if (r > 0.0) {
+      const double sf = sqrt(fma(pij, pij, qij * qij));
+      const double st = sqrt(fma(pji, pji, qji * qji));
+      line = nanmax(line, nanmax(sf - r, st - r));
+    }
+  }
+  quality_max(Q.qmax, grid, 3, line);
+}
+
+__global__ __launch_bounds__(256) void quality_bus_kernel(QualityArgs Q) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int grid = -1;
+  double balp = 0.0, balq = 0.0, volt = 0.0, ang = 0.0;
+  if (i < Q.nb) {
+    grid = Q.bus_grid[i];
+    double sp = 0.0, sq = 0.0;
+    for (int g = Q.gptr[i]; g < Q.gptr[i + 1]; ++g) {
+      sp = sp + Q.u[g];
+      sq = sq + Q.u[Q.ng + g];
+    }
+    const double w = Q.bw[i];
+    sp = fma(-Q.gs[i], w, sp - Q.pd[i]);
+    sq = fma(Q.bs[i], w, sq - Q.qd[i]);
+    for (int e = Q.eptr[i]; e < Q.eptr[i + 1]; ++e) {
+      sp = sp - Q.pe[e];
+      sq = sq - Q.qe[e];
+    }
+    balp = nanmax(balp, fabs(sp));
+    balq = nanmax(balq, fabs(sq));
+    const double vm = w > 0.0 ? sqrt(w) : 0.0;
+    volt = nanmax(volt, nanmax(Q.vmin[i] - vm, vm - Q.vmax[i]));
+    ang = nanmax(ang, fabs(Q.bt[i]) - kTwoPi);
+  }
+  quality_max(Q.qmax, grid, 1, balp);
+  quality_max(Q.qmax, grid, 2, balq);
+  quality_max(Q.qmax, grid, 4, volt);
+  quality_max(Q.qmax, grid, 5, ang);
+}
+
+void launch_quality(const QualityArgs& Q, hipStream_t s) {
+  const int bs = 256;
+  hipLaunchKernelGGL(quality_values_kernel, dim3((Q.nb + bs - 1) / bs), dim3(bs), 0, s, Q);
+  hipLaunchKernelGGL(quality_flow_kernel, dim3((Q.nl + bs - 1) / bs), dim3(bs), 0, s, Q);
+  hipLaunchKernelGGL(quality_bus_kernel, dim3((Q.nb + bs - 1) / bs), dim3(bs), 0, s, Q);
+}
+
 }  // namespace acopf_dev

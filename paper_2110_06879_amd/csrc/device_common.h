@@ -54,6 +54,18 @@ struct BranchArgs {
 // One launch for the whole x-step with `block` threads per block (a multiple
 // of 64): blocks [0, b6) solve rated branches [0, n6), blocks [b6, b6 + b4)
 // unlimited branches [n6, nl), the remaining blocks the generators.
+// Solution quality (||c(x)||_inf over eq. acopf at the ADMM solution): see
+// launch_quality. qmax holds six maxima per grid as bit patterns of
+// non-negative doubles (or NaN), combined with integer atomicMax.
+struct QualityArgs {
+  int64_t nb, ng, nl, ne;
+  const int *bus_grid, *br_grid, *gen_grid, *gptr, *eptr, *ef, *et, *end_bus;
+  const double *adm, *rate, *u, *v, *pd, *qd, *gs, *bs, *vmin, *vmax;
+  double *bw, *bt, *pe, *qe;  // scratch [nb], [nb], [ne], [ne]
+  unsigned long long* qmax;   // [G][6], zeroed before the launch
+};
+void launch_quality(const QualityArgs& Q, hipStream_t s);
+
 // Lane-per-branch x-step; per_lane unlimited branches per lane (0: choose it
 // so that every branch wavefront fits the device's `slots` SIMD slots).
 void launch_xstep(const BranchArgs& A, int64_t n6, int block, int per_lane, int slots,

@@ -233,3 +233,51 @@ def test_70k_one_iteration_from_gpu_state(waves):
         s.solve(A.CONTINUE, 1)
         orc.solve(1)
         compare(s, orc, tol=1e-9, label="70k+1")
+
+
+def assert_quality_equal(qg, qo, label):
+    note(f"{label} gpu {qg}")
+    note(f"{label} oracle {qo}")
+    for k, vo in qo.items():
+        assert abs(qg[k] - vo) <= 1e-13 * max(1.0, abs(vo)), (label, k, qg[k], vo)
+
+
+def test_quality_matches_oracle():
+    """||c(x)||_inf over eq. acopf (Sec. IV-A solution: generator outputs and
+    bus voltages, flows recomputed) on the GPU against the oracle: the 2k grid
+    after 50 iterations, and a three-grid batch including taps, phase shifters
+    and shunts, each grid against its own oracle."""
+    note("quality: c2 after 50 iterations")
+    g = config_grid("c2_2kbus")
+    p = A.Params()
+    orc = O.Oracle(g, oparams(p))
+    orc.solve(50)
+    with A.Solver(g, p) as s:
+        s.solve(A.COLD, 50)
+        assert_quality_equal(s.quality(), orc.quality(), "c2")
+    note("quality: three-grid batch with taps and shunts")
+    gs = [gridgen(67, 9, 70, 0.5, 32, load_factor=0.2), gridgen(130, 20, 200, 0.0, 33),
+          gridgen(90, 12, 120, 1.0, 34, load_factor=0.2)]
+    rng = np.random.default_rng(0)
+    gs[0].gs = rng.uniform(0, 0.02, gs[0].n_bus)
+    gs[0].bs = rng.uniform(-0.02, 0.02, gs[0].n_bus)
+    gs[0].tap = rng.uniform(0.95, 1.05, gs[0].n_branch)
+    gs[0].shift = rng.uniform(-0.1, 0.1, gs[0].n_branch)
+    with A.Solver(gs, p) as s:
+        s.solve(A.COLD, 30)
+        for k, gk in enumerate(gs):
+            orc = O.Oracle(gk, oparams(p))
+            orc.solve(30)
+            assert_quality_equal(s.quality(k), orc.quality(), f"batch grid {k}")
+
+
+def test_quality_70k_from_gpu_state():
+    note("quality: 70k grid after 20 iterations, state loaded into the oracle")
+    g = config_grid("c3_70kbus")
+    p = A.Params()
+    with A.Solver(g, p) as s:
+        s.solve(A.COLD, 20)
+        orc = O.Oracle(g, oparams(p))
+        for k in ("u", "v"):
+            orc.set(k, s.get(k))
+        assert_quality_equal(s.quality(), orc.quality(), "70k")

@@ -307,3 +307,83 @@ def test_three_bus_admm_converges_to_dense_acopf():
     f_admm = o.objective()
     f_ref = float(np.sum(g.c2 * (100 * p_ref) ** 2 + g.c1 * 100 * p_ref))
     assert abs(f_admm - f_ref) <= 1e-5 * f_ref
+
+
+def ybus_quality(g, v, u):
+    """||c(x)||_inf over eq. acopf from the textbook bus-injection form: complex
+    voltages V = sqrt(w) e^{j theta}, branch currents through the pi model with
+    a = tap e^{j shift} (series 1/(r + jx), charging jb/2 per end), S = V conj(I),
+    bus shunts (g_s - j b_s) |V|^2. v and u are canonical coupling vectors."""
+    ng, nl, nb = g.n_gen, g.n_branch, g.n_bus
+    w = np.empty(nb)
+    th = np.empty(nb)
+    first = {}
+    for l in range(nl):   # first incident end per bus: from-ends, then to-ends
+        first.setdefault(("f", g.br_from[l]), l)
+    for l in range(nl):
+        first.setdefault(("t", g.br_to[l]), l)
+    for i in range(nb):
+        if ("f", i) in first:
+            k = 2 * ng + 8 * first[("f", i)] + 4
+        else:
+            k = 2 * ng + 8 * first[("t", i)] + 6
+        w[i], th[i] = v[k], v[k + 1]
+    V = np.sqrt(w) * np.exp(1j * th)
+    inj = np.zeros(nb, dtype=complex)
+    line = 0.0
+    for l in range(nl):
+        i, j = g.br_from[l], g.br_to[l]
+        ys = 1.0 / (g.r[l] + 1j * g.x[l])
+        a = g.tap[l] * np.exp(1j * g.shift[l])
+        yff = (ys + 0.5j * g.b[l]) / abs(a) ** 2
+        yft = -ys / np.conj(a)
+        ytf = -ys / a
+        ytt = ys + 0.5j * g.b[l]
+        Sf = V[i] * np.conj(yff * V[i] + yft * V[j])
+        St = V[j] * np.conj(ytf * V[i] + ytt * V[j])
+        inj[i] += Sf
+        inj[j] += St
+        if g.rate[l] > 0:
+            line = max(line, abs(Sf) - g.rate[l], abs(St) - g.rate[l])
+    inj += (g.gs - 1j * g.bs) * np.abs(V) ** 2
+    sg = np.zeros(nb, dtype=complex)
+    for k in range(ng):
+        sg[g.gen_bus[k]] += u[2 * k] + 1j * u[2 * k + 1]
+    mis = sg - (g.pd + 1j * g.qd) - inj
+    vm = np.abs(V)
+    volt = max(0.0, float(np.max(np.maximum(g.vmin - vm, vm - g.vmax))))
+    ang = max(0.0, float(np.max(np.abs(th) - 2 * np.pi)))
+    parts = [float(np.max(np.abs(mis.real))), float(np.max(np.abs(mis.imag))), max(line, 0.0),
+             volt, ang]
+    return [max(parts)] + parts
+
+
+def test_quality_matches_bus_injection_form():
+    """The oracle's solution-quality evaluator (Sec. IV-A: flows recomputed from
+    the bus voltages) against S = V conj(I) with complex admittances, on a grid
+    with taps, phase shifters, bus shunts and rated branches, at an ADMM
+    iterate and at a perturbed state where every limit is violated."""
+    g = gridgen(67, 9, 70, 0.5, 32, load_factor=0.2)
+    rng = np.random.default_rng(7)
+    g.gs = rng.uniform(0, 0.02, g.n_bus)
+    g.bs = rng.uniform(-0.02, 0.02, g.n_bus)
+    g.tap = rng.uniform(0.95, 1.05, g.n_branch)
+    g.shift = rng.uniform(-0.1, 0.1, g.n_branch)
+    o = O.Oracle(g, O.OracleParams(rho_pq=400.0, rho_va=4000.0))
+    o.solve(40)
+    names = O.QUALITY_NAMES
+    for case in ("iterate", "perturbed"):
+        if case == "perturbed":
+            v = o.get("v")
+            m0 = 2 * g.n_gen
+            for l in range(g.n_branch):   # push voltages out of range, angles past 2 pi
+                v[m0 + 8 * l + 4] *= 1.3
+                v[m0 + 8 * l + 5] += 7.0
+            o.set("v", v)
+        q = o.quality()
+        ref = ybus_quality(g, o.get("v"), o.get("u"))
+        for name, r in zip(names, ref):
+            assert abs(q[name] - r) <= 1e-11 * max(1.0, abs(r)), (case, name, q[name], r)
+        if case == "perturbed":
+            assert q["voltage_limit"] > 0.1 and q["angle_limit"] > 0.5 and q["line_limit"] > 0
+        assert q["max_violation"] == max(q[n] for n in names[1:])
