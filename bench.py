@@ -63,7 +63,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--trials", type=int, default=20, help="warm-start trials")
+    ap.add_argument("--trials", type=int, default=100, help="warm-start trials (seeds 3001...)")
     ap.add_argument("--cpu-iters", type=int, default=30, help="oracle iterations for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
@@ -142,9 +142,10 @@ def main():
 
     # ---- cold solve to convergence and warm-start latency
     cold = s.solve(A.COLD)[0]
+    cold_quality = s.quality()
     base = {k: s.get(k) for k in ("u", "v", "z", "y", "lam", "bx", "ltil", "rtil")}
     base_sc = s.get("scalars")
-    lat, iters, statuses = [], [], []
+    lat, iters, statuses, viol = [], [], [], []
     for t in range(args.trials):
         for k, v in base.items():
             s.set(k, v)
@@ -158,6 +159,7 @@ def main():
         lat.append((tb - ta) * 1e3)
         iters.append(r["inner_iters"])
         statuses.append(r["status"])
+        viol.append(s.quality()["max_violation"])
     s.update_loads(0, g.pd, g.qd)
 
     # ---- CPU baseline: the oracle, serial, from the GPU state after warmup
@@ -210,11 +212,13 @@ def main():
         "cold_solve": {"status": cold["status"], "inner_iters": cold["inner_iters"],
                        "outer_iters": cold["outer_iters"], "seconds": cold["seconds"],
                        "r_pri": cold["r_pri"], "r_dual": cold["r_dual"], "r_z": cold["r_z"],
-                       "objective": cold["objective"]},
+                       "objective": cold["objective"], "quality": cold_quality},
         "warm_start": {"p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
                        "trials": args.trials, "perturbation": "+-2% per bus",
                        "mean_iters": float(np.mean(iters)), "max_iters": int(np.max(iters)),
-                       "converged": int(sum(1 for x in statuses if x == 0))},
+                       "converged": int(sum(1 for x in statuses if x == 0)),
+                       "max_violation_p50": percentile(viol, 50),
+                       "max_violation_max": float(np.max(viol))},
         "cpu_baseline": cpu,
         "device": dev_name,
     }

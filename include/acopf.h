@@ -169,6 +169,14 @@ int acopf_create(const acopf_grid* grids, int32_t n_grids,
 int acopf_solve(acopf_handle h, int32_t mode, int32_t fixed_iters,
                 acopf_result* results);
 
+/* Replace the real-power bounds of grid `grid`'s generators (input order,
+ * p.u.), e.g. the ramp-limited bounds max(pmin, p_t - r), min(pmax, p_t + r)
+ * of a tracking horizon (Sec. IV-C); the generator step of the next
+ * iterations projects onto them. Errors: EINVAL (index, NaN/Inf,
+ * pmin > pmax), EDEVICE. */
+int acopf_update_gen_bounds(acopf_handle h, int32_t grid, const double* pmin,
+                            const double* pmax);
+
 /* Replace the loads of grid `grid` (H2D copy of 2 n_bus doubles); the next
  * ACOPF_WARM solve tracks the new optimum from the resident state (Sec. IV-C).
  * Errors: EINVAL (index, NaN/Inf), EDEVICE. */

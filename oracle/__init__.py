@@ -141,6 +141,8 @@ def load() -> C.CDLL:
     lib.ora_solve.argtypes = [vp, ip]
     lib.ora_solve.restype = ip
     lib.ora_update_loads.argtypes = [vp, dp, dp]
+    lib.ora_update_gen_bounds.argtypes = [vp, dp, dp]
+    lib.ora_update_gen_bounds.restype = None
     lib.ora_get.argtypes = [vp, ip, dp, C.c_int64]
     lib.ora_get.restype = ip
     lib.ora_set.argtypes = [vp, ip, dp, C.c_int64]
@@ -298,6 +300,11 @@ class Oracle:
 
     def solve(self, fixed_iters: int = 0) -> int:
         return int(self.lib.ora_solve(self.h, int(fixed_iters)))
+
+    def update_gen_bounds(self, pmin, pmax):
+        lo = np.ascontiguousarray(pmin, dtype=np.float64)
+        hi = np.ascontiguousarray(pmax, dtype=np.float64)
+        self.lib.ora_update_gen_bounds(self.h, _dp(lo), _dp(hi))
 
     def update_loads(self, pd, qd, warm_reset: bool = True):
         pd = np.ascontiguousarray(pd, dtype=np.float64)

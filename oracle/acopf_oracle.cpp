@@ -1216,6 +1216,16 @@ void ora_update_loads(void* h, const double* pd, const double* qd) {
   }
 }
 
+// New real-power bounds of the generators (tracking with ramp limits,
+// Sec. IV-C); the generator step projects onto them.
+void ora_update_gen_bounds(void* h, const double* pmin, const double* pmax) {
+  auto* o = static_cast<Oracle*>(h);
+  for (int g = 0; g < o->ng; ++g) {
+    o->pmin[g] = pmin[g];
+    o->pmax[g] = pmax[g];
+  }
+}
+
 void ora_warm_reset(void* h) {
   auto* o = static_cast<Oracle*>(h);
   o->beta = o->p.beta0;

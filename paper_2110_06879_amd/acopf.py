@@ -32,7 +32,8 @@ EXPORTS = ("acopf_default_params", "acopf_create", "acopf_solve", "acopf_update_
            "acopf_get_state", "acopf_set_state", "acopf_get_sizes", "acopf_set_profiling",
            "acopf_get_timing", "acopf_destroy", "acopf_last_error", "acopf_start",
            "acopf_run", "acopf_poll", "acopf_copy_grid", "acopf_snapshot",
-           "acopf_set_tuning", "acopf_get_tuning", "acopf_autotune", "acopf_quality")
+           "acopf_set_tuning", "acopf_get_tuning", "acopf_autotune", "acopf_quality",
+           "acopf_update_gen_bounds")
 QUALITY_NAMES = ("max_violation", "balance_p", "balance_q", "line_limit", "voltage_limit",
                  "angle_limit")
 
@@ -148,6 +149,7 @@ def load(path: str | None = None) -> C.CDLL:
     lib.acopf_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     lib.acopf_autotune.argtypes = [vp, i32, C.POINTER(_Tuning)]
     lib.acopf_quality.argtypes = [vp, i32, dp]
+    lib.acopf_update_gen_bounds.argtypes = [vp, i32, dp, dp]
     lib.acopf_destroy.argtypes = [vp]
     lib.acopf_destroy.restype = None
     lib.acopf_last_error.restype = C.c_char_p
@@ -155,7 +157,8 @@ def load(path: str | None = None) -> C.CDLL:
                  "acopf_set_state", "acopf_get_sizes", "acopf_get_timing",
                  "acopf_set_profiling", "acopf_start", "acopf_run", "acopf_poll",
                  "acopf_copy_grid", "acopf_snapshot", "acopf_set_tuning",
-                 "acopf_get_tuning", "acopf_autotune", "acopf_quality"):
+                 "acopf_get_tuning", "acopf_autotune", "acopf_quality",
+                 "acopf_update_gen_bounds"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -228,6 +231,11 @@ class Solver:
         res = (_Result * len(self.grids))()
         self._check(self.lib.acopf_solve(self.h, mode, fixed_iters, res))
         return [r.as_dict() for r in res]
+
+    def update_gen_bounds(self, grid: int, pmin, pmax):
+        lo = np.ascontiguousarray(pmin, dtype=np.float64)
+        hi = np.ascontiguousarray(pmax, dtype=np.float64)
+        self._check(self.lib.acopf_update_gen_bounds(self.h, grid, _dp(lo), _dp(hi)))
 
     def update_loads(self, grid: int, pd, qd):
         pd = np.ascontiguousarray(pd, dtype=np.float64)

@@ -3,6 +3,7 @@ one-grid-per-launch method on the same device and inputs.
 
   python -m paper_2110_06879_amd.bench_systems --batch   # 64 uneven grids, cold, to 1e-4
   python -m paper_2110_06879_amd.bench_systems --serve   # Poisson tracking requests
+  python -m paper_2110_06879_amd.bench_systems --track   # 30-period horizon, ramp limits
 
 Prints one JSON line per experiment.
 """
@@ -17,7 +18,8 @@ import numpy as np
 
 from . import acopf as A
 from . import serve as S
-from .gridgen import batch_grids, serving_grids
+from . import tracking as T
+from .gridgen import batch_grids, config_grid, serving_grids
 
 
 def batch(n_grids: int, tune_iters: int) -> dict:
@@ -77,6 +79,29 @@ def serve(duration: float, rate: float, with_70k: bool, baseline: bool) -> dict:
     return res
 
 
+def track(names, periods: int) -> dict:
+    out = {"experiment": "tracking", "periods": periods, "drift": 0.05, "ramp": 0.02,
+           "grids": {}}
+    for name in names:
+        g = config_grid(name)
+        with A.Solver(g) as s:
+            recs = T.track(s, g, 0, periods=periods)
+        warm = recs[1:]
+        secs = np.array([r["seconds"] for r in warm])
+        out["grids"][name] = {
+            "n_bus": g.n_bus, "cold_seconds": recs[0]["seconds"],
+            "cold_iters": recs[0]["inner_iters"],
+            "warm_seconds_p50": float(np.percentile(secs, 50)) if secs.size else None,
+            "warm_seconds_max": float(secs.max()) if secs.size else None,
+            "horizon_seconds": float(sum(r["seconds"] for r in recs)),
+            "warm_iters_mean": float(np.mean([r["inner_iters"] for r in warm])) if warm else None,
+            "converged": int(sum(1 for r in recs if r["status"] == A.CONVERGED)),
+            "max_violation_max": float(max(r["max_violation"] for r in recs)),
+            "ramp_ratio_max": float(max(r["ramp_ratio"] for r in recs)),
+            "periods": recs}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--batch", action="store_true")
@@ -87,12 +112,16 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--no-70k", action="store_true")
     ap.add_argument("--no-baseline", action="store_true")
+    ap.add_argument("--track", action="store_true")
+    ap.add_argument("--periods", type=int, default=30)
     args = ap.parse_args()
     if args.batch:
         print(json.dumps(batch(args.grids, args.tune_iters)), flush=True)
     if args.serve:
         print(json.dumps(serve(args.duration, args.rate, not args.no_70k,
                                not args.no_baseline)), flush=True)
+    if args.track:
+        print(json.dumps(track(["c2_2kbus", "c3_70kbus"], args.periods)), flush=True)
 
 
 if __name__ == "__main__":

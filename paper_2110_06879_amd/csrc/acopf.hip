@@ -1395,6 +1395,30 @@ int acopf_update_loads(acopf_handle h, int32_t grid, const double* pd, const dou
   return ACOPF_OK;
 }
 
+int acopf_update_gen_bounds(acopf_handle h, int32_t grid, const double* pmin,
+                            const double* pmax) {
+  if (!h) return fail(ACOPF_EINVAL, "null handle");
+  if (grid < 0 || grid >= h->G) return fail(ACOPF_EINVAL, "grid index out of range");
+  const HostGrid& H = h->grids[grid];
+  if (H.ng == 0) return ACOPF_OK;
+  if (!pmin || !pmax) return fail(ACOPF_EINVAL, "null bound array");
+  if (!finite_all(pmin, H.ng) || !finite_all(pmax, H.ng))
+    return fail(ACOPF_EINVAL, "non-finite generator bound");
+  std::vector<double> lo(H.ng), hi(H.ng);
+  for (int64_t k = 0; k < H.ng; ++k) {
+    if (pmin[k] > pmax[k]) return fail(ACOPF_EINVAL, "empty generator bound interval");
+    lo[H.gen_dev[k] - H.gen_off] = pmin[k];
+    hi[H.gen_dev[k] - H.gen_off] = pmax[k];
+  }
+  HIP_TRY(hipSetDevice(h->device));
+  HIP_TRY(hipMemcpyAsync(h->pmin + H.gen_off, lo.data(), sizeof(double) * H.ng,
+                         hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(h->pmax + H.gen_off, hi.data(), sizeof(double) * H.ng,
+                         hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return ACOPF_OK;
+}
+
 static int64_t state_size(const HostGrid& H, int what) {
   const int64_t m = 2 * H.ng + 8 * H.nl;
   switch (what) {

@@ -281,3 +281,35 @@ def test_quality_70k_from_gpu_state():
         for k in ("u", "v"):
             orc.set(k, s.get(k))
         assert_quality_equal(s.quality(), orc.quality(), "70k")
+
+
+def test_tracking_horizon_matches_oracle():
+    """Four periods of the tracking horizon (Sec. IV-C: loads drift, warm
+    start, ramp-limited generator bounds) on the GPU and in the oracle: the
+    same inner iterations and solution quality per period, the same final
+    state, and ramp limits respected."""
+    from paper_2110_06879_amd import tracking as T
+    note("tracking: 60-bus grid, 4 periods")
+    g = gridgen(60, 12, 80, 0.5, 71, load_factor=0.2)
+    p = A.Params()
+    with A.Solver(g, p) as s:
+        recs = T.track(s, g, 0, periods=4)
+        orc = O.Oracle(g, oparams(p))
+        factor = T.load_profile(4, 0.05)
+        p_prev = None
+        for t in range(4):
+            if t == 0:
+                orc.update_gen_bounds(g.pmin, g.pmax)
+            else:
+                lo, hi = T.ramp_bounds(g.pmin, g.pmax, p_prev, 0.02)
+                orc.update_gen_bounds(lo, hi)
+            orc.update_loads(g.pd * factor[t], g.qd * factor[t], warm_reset=t > 0)
+            orc.solve(0)
+            sc = orc.scalars()
+            note(f"period {t}: gpu {recs[t]['inner_iters']} iters, oracle {int(sc['inner_total'])}")
+            assert recs[t]["inner_iters"] == int(sc["inner_total"]), t
+            qo = orc.quality()["max_violation"]
+            assert abs(recs[t]["max_violation"] - qo) <= 1e-13 * max(1.0, qo), t
+            assert recs[t]["ramp_ratio"] <= 1.0 + 1e-12
+            p_prev = T.generator_p(orc.get("u"), g.n_gen)
+        compare(s, orc, label="tracking final")
