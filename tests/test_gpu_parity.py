@@ -313,3 +313,20 @@ def test_tracking_horizon_matches_oracle():
             assert recs[t]["ramp_ratio"] <= 1.0 + 1e-12
             p_prev = T.generator_p(orc.get("u"), g.n_gen)
         compare(s, orc, label="tracking final")
+
+
+def test_matpower_case_matches_oracle():
+    """A grid read from a MATPOWER case file (hand-made 5-bus case with a
+    phase-shifting transformer, a shunt, two generators on one bus and
+    out-of-service elements) on the GPU against the oracle."""
+    import os
+    from paper_2110_06879_amd import matpower as M
+    note("MATPOWER case: 100 iterations")
+    g = M.load_case(os.path.join(os.path.dirname(__file__), "golden", "case5_handmade.m"))
+    p = A.Params(rho_pq=400.0, rho_va=4000.0)
+    orc = O.Oracle(g, oparams(p))
+    orc.solve(100)
+    with A.Solver(g, p) as s:
+        s.solve(A.COLD, 100)
+        compare(s, orc, label="case5")
+        assert_quality_equal(s.quality(), orc.quality(), "case5")
