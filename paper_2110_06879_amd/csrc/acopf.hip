@@ -582,7 +582,7 @@ struct acopf_s {
   DevBuf buf;
   // device arrays
   int64_t ne = 0;
-  int *gen_grid = nullptr, *br_grid = nullptr, *bus_grid = nullptr, *end_grid = nullptr;
+  int *gen_grid = nullptr, *br_grid = nullptr, *bus_grid = nullptr;
   int *ef = nullptr, *et = nullptr;
   double *pmin, *pmax, *qmin, *qmax, *c2q, *c1l, *c2, *c1, *c0;
   double *adm, *vlo_i, *vhi_i, *vlo_j, *vhi_j, *rate2;
@@ -933,7 +933,6 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   }
   // generators: device order sorted by (grid, bus, input index); ends: per bus,
   // from-ends then to-ends, each in input order
-  std::vector<int> end_grid(2 * nl);
   {
     std::vector<int> gpos(gptr.begin(), gptr.end() - 1), fpos(nb), tpos(nb);
     for (int64_t b = 0; b < nb; ++b) {
@@ -950,8 +949,6 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
       for (int l = 0; l < G.n_branch; ++l) {
         H.end_f[l] = fpos[H.bus_off + G.br_from[l]]++;
         H.end_t[l] = tpos[H.bus_off + G.br_to[l]]++;
-        end_grid[H.end_f[l]] = g;
-        end_grid[H.end_t[l]] = g;
       }
       // each grid's generators occupy [gen_off, gen_off + ng) of the device order
     }
@@ -1075,7 +1072,6 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(D.alloc(&h->gen_grid, ng));
   HIP_TRY(D.alloc(&h->br_grid, nl));
   HIP_TRY(D.alloc(&h->bus_grid, nb));
-  HIP_TRY(D.alloc(&h->end_grid, 2 * nl));
   HIP_TRY(D.alloc(&h->ef, nl));
   HIP_TRY(D.alloc(&h->et, nl));
   double** gen_d[] = {&h->pmin, &h->pmax, &h->qmin, &h->qmax, &h->c2q, &h->c1l, &h->c2, &h->c1, &h->c0};
@@ -1115,7 +1111,6 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(up(h->gen_grid, gen_grid.data(), sizeof(int) * ng));
   HIP_TRY(up(h->br_grid, dev_grid.data(), sizeof(int) * nl));
   HIP_TRY(up(h->bus_grid, bus_grid.data(), sizeof(int) * nb));
-  HIP_TRY(up(h->end_grid, end_grid.data(), sizeof(int) * 2 * nl));
   HIP_TRY(up(h->ef, ef.data(), sizeof(int) * nl));
   HIP_TRY(up(h->et, et.data(), sizeof(int) * nl));
   const std::vector<double>* gen_h[] = {&pmin, &pmax, &qmin, &qmax, &c2q, &c1l, &c2, &c1, &c0};

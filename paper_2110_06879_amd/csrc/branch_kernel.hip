@@ -2,15 +2,22 @@
 // (eq. branch, Sec. II-C) solved by a trust-region Newton method (Lin & More
 // 1999) inside an augmented-Lagrangian loop on the line limits, all in FP64.
 //
-// Launch layout: one lane per branch, 64 branches per wavefront. The whole
+// Launch layout: one lane per branch solve, 64 per wavefront. The whole
 // solve state of a branch (x, gradient, Hessian, Cholesky factor, trust
 // region) lives in that lane's registers; the variable count N (4 for
 // unlimited lines, 6 for rated lines with the two slacks) is a template
 // constant so every small dense loop unrolls into register code. Rated and
 // unlimited branches sit in separate contiguous ranges, so a wavefront never
-// mixes the two shapes. Branch data and coupling vectors are structure-of-
-// arrays: lane l reads element l of each array, so every load and store of a
-// wavefront is a contiguous 512-byte access.
+// mixes the two shapes; a lane of the unlimited range may solve several
+// branches one after another, so that every branch wavefront is resident on
+// the device from the start. Branch data are structure-of-arrays (lane l
+// reads element l); the coupling values of a branch's two ends are gathered
+// from the bus-major coupling vectors.
+//
+// Arithmetic is a fixed IEEE operation sequence shared with the CPU oracle:
+// no implicit contraction, fused multiply-adds written out where the oracle
+// writes them, reciprocal pivots in the Cholesky factor, norm tests in
+// squares, and a series sin/cos.
 //
 // The free set of a subspace step is handled with a mask over all N
 // variables instead of compressed indices (fixed rows and columns act as
