@@ -118,13 +118,20 @@ def main():
         return
 
     # ---- roofline pass: the same iterations again (cold start, W warmup,
-    # then K iterations) with per-kernel HIP events on the solver's stream
+    # then K iterations), once with the kernels' flop counting on to get the
+    # exact algorithmic flops of those launches, and once as timed above
+    # (counting off) with per-kernel HIP events on the solver's stream. The
+    # iterates are bitwise the same in both.
     s.solve(A.COLD, args.warmup)
+    s.set_counting(True)
     st0 = s.stats()
+    s.solve(A.CONTINUE, args.steps)
+    st1 = s.stats()
+    s.set_counting(False)
+    s.solve(A.COLD, args.warmup)
     s.set_profiling(True)
     s.solve(A.CONTINUE, args.steps)
     s.set_profiling(False)
-    st1 = s.stats()
     tim = s.timing()
     flops = st1["flops"] - st0["flops"]
     solves = st1["branch_solves"] - st0["branch_solves"]

@@ -68,8 +68,13 @@ enum { /* acopf_get_state / acopf_set_state: what */
   ACOPF_QD = 10,       /* [n_bus] */
   ACOPF_HISTORY = 11,  /* get only: [6 inner_total] per inner iteration of
                           the last solve: r_pri, r_dual, r_z, 0, beta, outer */
-  ACOPF_STATS = 12     /* get only: [16] branch-solve event counters summed
-                          over all solves (see acopf_stats_names)            */
+  ACOPF_STATS = 12     /* get only: [16] branch-solve counters summed over
+                          the iterations run with acopf_set_counting on:
+                          solves, algorithmic flops, sin/cos, TRON calls,
+                          TRON iterations, f/g/H and f evaluations, Cauchy
+                          trials, CG iterations, Cholesky attempts, search
+                          trials, AL rounds, TRON converged / at the cap /
+                          stalled, then 0; the same for every grid index    */
 };
 
 /* Coupling order (m = 2 n_gen + 8 n_branch), the same in every vector:
@@ -249,6 +254,14 @@ int acopf_set_profiling(acopf_handle h, int32_t on);
  * handle's stream; allocates its scratch on the first call.
  * Errors: EINVAL, ENOMEM, EDEVICE. */
 int acopf_quality(acopf_handle h, int32_t grid, double* out6);
+
+/* Turn counting on or off (default off): with it, the branch kernel also
+ * counts the algorithmic flops of every branch solve (as the plain serial
+ * algorithm performs them: + - * / sqrt one each, fused multiply-add two)
+ * and its TRON events into ACOPF_STATS, at a few percent of its speed;
+ * without it those counters are not touched. Results are the same either
+ * way. Errors: EINVAL. */
+int acopf_set_counting(acopf_handle h, int32_t on);
 
 /* Average device time (ms) per launch over every iteration run with
  * profiling on since the handle was created: out[0] x-step (generators and

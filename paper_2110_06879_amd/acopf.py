@@ -33,7 +33,7 @@ EXPORTS = ("acopf_default_params", "acopf_create", "acopf_solve", "acopf_update_
            "acopf_get_timing", "acopf_destroy", "acopf_last_error", "acopf_start",
            "acopf_run", "acopf_poll", "acopf_copy_grid", "acopf_snapshot",
            "acopf_set_tuning", "acopf_get_tuning", "acopf_autotune", "acopf_quality",
-           "acopf_update_gen_bounds")
+           "acopf_update_gen_bounds", "acopf_set_counting")
 QUALITY_NAMES = ("max_violation", "balance_p", "balance_q", "line_limit", "voltage_limit",
                  "angle_limit")
 
@@ -150,6 +150,7 @@ def load(path: str | None = None) -> C.CDLL:
     lib.acopf_autotune.argtypes = [vp, i32, C.POINTER(_Tuning)]
     lib.acopf_quality.argtypes = [vp, i32, dp]
     lib.acopf_update_gen_bounds.argtypes = [vp, i32, dp, dp]
+    lib.acopf_set_counting.argtypes = [vp, i32]
     lib.acopf_destroy.argtypes = [vp]
     lib.acopf_destroy.restype = None
     lib.acopf_last_error.restype = C.c_char_p
@@ -158,7 +159,7 @@ def load(path: str | None = None) -> C.CDLL:
                  "acopf_set_profiling", "acopf_start", "acopf_run", "acopf_poll",
                  "acopf_copy_grid", "acopf_snapshot", "acopf_set_tuning",
                  "acopf_get_tuning", "acopf_autotune", "acopf_quality",
-                 "acopf_update_gen_bounds"):
+                 "acopf_update_gen_bounds", "acopf_set_counting"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -321,6 +322,10 @@ class Solver:
         t = _Tuning()
         self._check(self.lib.acopf_autotune(self.h, iters, C.byref(t)))
         return t.as_dict()
+
+    def set_counting(self, on: bool = True):
+        """Count algorithmic flops and TRON events into stats() (slower)."""
+        self._check(self.lib.acopf_set_counting(self.h, 1 if on else 0))
 
     def set_profiling(self, on: bool = True):
         self._check(self.lib.acopf_set_profiling(self.h, int(on)))

@@ -611,6 +611,7 @@ struct acopf_s {
   double *base_d, *obj_d;
   bool solved = false;
   bool profile = false;
+  bool count_stats = false;  // branch kernels count flops and events (slower)
   acopf_tuning tune{64, 256, 16, 1, 0, 0};
   hipGraphExec_t graph = nullptr;
   int graph_chunk = 0;
@@ -732,10 +733,11 @@ void launch_iteration(acopf_s* h, int slot) {
   BranchArgs ba = branch_args(h);
   mark(0);
   if (h->tune.xstep_waves > 0)
-    acopf_dev::launch_xstep_persistent(ba, h->n6, h->tune.xstep_waves * 4 * h->n_cu, s);
+    acopf_dev::launch_xstep_persistent(ba, h->n6, h->tune.xstep_waves * 4 * h->n_cu,
+                                       h->count_stats, s);
   else
     acopf_dev::launch_xstep(ba, h->n6, h->tune.xstep_block, h->tune.xstep_per_lane,
-                            4 * h->n_cu, s);
+                            4 * h->n_cu, h->count_stats, s);
   mark(1);
   BusArgs bu{h->nb, h->ng, h->ne, h->tdesc, h->bus_grid, h->ctl, h->gptr, h->eptr,
              h->pd, h->qd, h->gs, h->bs, h->isref, h->u, h->lam, h->v, h->z, h->y,
@@ -1759,6 +1761,15 @@ int acopf_autotune(acopf_handle h, int32_t iters, acopf_tuning* out) {
   h->t_end = te0;
   h->profile = prof;
   if (out) *out = best;
+  return ACOPF_OK;
+}
+
+int acopf_set_counting(acopf_handle h, int32_t on) {
+  if (!h) return fail(ACOPF_EINVAL, "null handle");
+  if ((on != 0) != h->count_stats) {
+    drop_graph(h);
+    h->count_stats = on != 0;
+  }
   return ACOPF_OK;
 }
 

@@ -1152,8 +1152,11 @@ __device__ void run_pool(const BranchArgs& A, int64_t begin, int64_t end, unsign
 }
 
 // Persistent x-step: a fixed number of 64-lane blocks drain the rated pool,
-// then the unlimited pool, then the generators (pool counters are reset by
-// the control kernel of the same iteration).
+// then the unlimited pool, then the generators; the last block to finish
+// rearms the pool counters. With kStats the lanes also count algorithmic
+// flops and TRON events into A.stats; without it the counters are never read
+// and the compiler drops their arithmetic.
+template <bool kStats>
 __global__ __launch_bounds__(64) void xstep_persistent_kernel(BranchArgs A, int64_t n6) {
   Counters cnt = {};
   uint32_t solves = 0;
@@ -1163,21 +1166,23 @@ __global__ __launch_bounds__(64) void xstep_persistent_kernel(BranchArgs A, int6
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < A.ng; g += nthreads)
     if (A.ctl[A.gen_grid[g]].done == 0) solve_generator(A, g);
-  uint64_t v[15] = {(uint64_t)solves, flops + cnt.flops, (uint64_t)cnt.trig, cnt.tron_calls,
-                    cnt.tron_iters, cnt.n_fgh, cnt.n_f, cnt.cauchy, cnt.cg, cnt.chol,
-                    cnt.ps, cnt.al, cnt.conv, cnt.maxit, cnt.stall};
+  if (kStats) {
+    uint64_t v[15] = {(uint64_t)solves, flops + cnt.flops, (uint64_t)cnt.trig, cnt.tron_calls,
+                      cnt.tron_iters, cnt.n_fgh, cnt.n_f, cnt.cauchy, cnt.cg, cnt.chol,
+                      cnt.ps, cnt.al, cnt.conv, cnt.maxit, cnt.stall};
 #pragma unroll
-  for (int q = 0; q < 15; ++q) {
-    uint64_t t = v[q];
+    for (int q = 0; q < 15; ++q) {
+      uint64_t t = v[q];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-    v[q] = t;
-  }
-  if (threadIdx.x == 0) {
-    if (v[0] != 0) {
+      for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+      v[q] = t;
+    }
+    if (threadIdx.x == 0 && v[0] != 0) {
 #pragma unroll
       for (int q = 0; q < 15; ++q) atomicAdd(&A.stats[q], (unsigned long long)v[q]);
     }
+  }
+  if (threadIdx.x == 0) {
     // the last block to finish rearms the pools for the next launch: every
     // other block has taken its final index before it counted itself done
     __threadfence();
@@ -1189,9 +1194,13 @@ __global__ __launch_bounds__(64) void xstep_persistent_kernel(BranchArgs A, int6
   }
 }
 
-void launch_xstep_persistent(const BranchArgs& A, int64_t n6, int blocks, hipStream_t s) {
+void launch_xstep_persistent(const BranchArgs& A, int64_t n6, int blocks, bool stats,
+                             hipStream_t s) {
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(xstep_persistent_kernel, dim3(blocks), dim3(64), 0, s, A, n6);
+  if (stats)
+    hipLaunchKernelGGL(xstep_persistent_kernel<true>, dim3(blocks), dim3(64), 0, s, A, n6);
+  else
+    hipLaunchKernelGGL(xstep_persistent_kernel<false>, dim3(blocks), dim3(64), 0, s, A, n6);
 }
 
 #ifndef ACOPF_XSTEP_WAVES_PER_EU
@@ -1204,7 +1213,9 @@ void launch_xstep_persistent(const BranchArgs& A, int64_t n6, int blocks, hipStr
 // the other (branch base + j * b4 * blockDim for j < k4). With k4 chosen so
 // that every branch wavefront is resident from the start, the cheap unlimited
 // branches finish inside the span of the expensive rated ones instead of
-// waiting for a second round of SIMD slots.
+// waiting for a second round of SIMD slots. kStats: as for the persistent
+// kernel.
+template <bool kStats>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ACOPF_XSTEP_WAVES_PER_EU)))
 void xstep_kernel(BranchArgs A, int64_t n6, int bg, int b6, int b4, int k4) {
   Counters cnt = {};
@@ -1238,6 +1249,7 @@ void xstep_kernel(BranchArgs A, int64_t n6, int bg, int b6, int b4, int k4) {
       }
     }
   }
+  if (!kStats) return;
   // wave-level reduction of the counters, one atomic per counter per wavefront
   uint64_t v[15] = {(uint64_t)solves, (uint64_t)cnt.flops, (uint64_t)cnt.trig, cnt.tron_calls,
                     cnt.tron_iters, cnt.n_fgh, cnt.n_f, cnt.cauchy, cnt.cg, cnt.chol,
@@ -1256,7 +1268,7 @@ void xstep_kernel(BranchArgs A, int64_t n6, int bg, int b6, int b4, int k4) {
 }
 
 void launch_xstep(const BranchArgs& A, int64_t n6, int block, int per_lane, int slots,
-                  hipStream_t s) {
+                  bool stats, hipStream_t s) {
   const int64_t n4 = A.nl - n6;
   const int bg = (int)((A.ng + block - 1) / block);
   const int b6 = (int)((n6 + block - 1) / block);
@@ -1272,7 +1284,12 @@ void launch_xstep(const BranchArgs& A, int64_t n6, int block, int per_lane, int 
   }
   const int b4 = (int)((n4 + (int64_t)block * k4 - 1) / ((int64_t)block * k4));
   if (bg + b6 + b4 == 0) return;
-  hipLaunchKernelGGL(xstep_kernel, dim3(bg + b6 + b4), dim3(block), 0, s, A, n6, bg, b6, b4, k4);
+  if (stats)
+    hipLaunchKernelGGL(xstep_kernel<true>, dim3(bg + b6 + b4), dim3(block), 0, s, A, n6, bg, b6,
+                       b4, k4);
+  else
+    hipLaunchKernelGGL(xstep_kernel<false>, dim3(bg + b6 + b4), dim3(block), 0, s, A, n6, bg, b6,
+                       b4, k4);
 }
 
 // ---------------------------------------------------------------------------

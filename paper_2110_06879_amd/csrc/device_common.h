@@ -68,11 +68,13 @@ void launch_quality(const QualityArgs& Q, hipStream_t s);
 
 // Lane-per-branch x-step; per_lane unlimited branches per lane (0: choose it
 // so that every branch wavefront fits the device's `slots` SIMD slots).
+// stats: also count algorithmic flops and TRON events into A.stats.
 void launch_xstep(const BranchArgs& A, int64_t n6, int block, int per_lane, int slots,
-                  hipStream_t s);
+                  bool stats, hipStream_t s);
 
 // Persistent x-step on `blocks` 64-lane blocks; the pool counters must be
 // zero at launch and are zero again when it ends.
-void launch_xstep_persistent(const BranchArgs& A, int64_t n6, int blocks, hipStream_t s);
+void launch_xstep_persistent(const BranchArgs& A, int64_t n6, int blocks, bool stats,
+                             hipStream_t s);
 
 }  // namespace acopf_dev

@@ -58,6 +58,8 @@ def test_xstep_variants_equal_lane_per_branch(variant):
     with A.Solver(gs) as s1, A.Solver(gs) as s2:
         s1.set_tuning(xstep_waves=0, xstep_per_lane=1)
         s2.set_tuning(**variant)
+        s1.set_counting(True)
+        s2.set_counting(True)
         r1 = s1.solve(A.COLD)
         r2 = s2.solve(A.COLD)
         for a, b in zip(r1, r2):
@@ -67,6 +69,24 @@ def test_xstep_variants_equal_lane_per_branch(variant):
         for k in range(len(gs)):
             assert_same(states(s1, k), states(s2, k))
         assert s1.stats() == s2.stats()
+
+
+@pytest.mark.parametrize("waves", [0, 1])
+def test_counting_leaves_results_unchanged(waves):
+    """Counting flops and events (acopf_set_counting) only adds integer
+    counters: every state is bitwise the same with and without it, and
+    without it the counters stay zero."""
+    note(f"counting on vs off, xstep_waves {waves}")
+    g = config_grid("c2_2kbus")
+    with A.Solver(g) as s1, A.Solver(g) as s2:
+        s1.set_tuning(xstep_waves=waves)
+        s2.set_tuning(xstep_waves=waves)
+        s1.set_counting(True)
+        s1.solve(A.COLD, 40)
+        s2.solve(A.COLD, 40)
+        assert_same(states(s1), states(s2))
+        assert s1.stats()["branch_solves"] == 40 * g.n_branch
+        assert all(v == 0 for v in s2.stats().values())
 
 
 def test_staggered_starts_equal_alone():

@@ -66,6 +66,7 @@ def test_fixed_iterations_match_oracle(name, iters, waves):
     orc.solve(iters)
     with A.Solver(g, p) as s:
         s.set_tuning(**XSTEP[waves])
+        s.set_counting(True)
         res = s.solve(A.COLD, iters)[0]
         assert res["inner_iters"] == iters
         compare(s, orc, label=name)
