@@ -150,7 +150,7 @@ def main():
     # ---- cold solve to convergence and warm-start latency
     cold = s.solve(A.COLD)[0]
     cold_quality = s.quality()
-    base = {k: s.get(k) for k in ("u", "v", "z", "y", "lam", "bx", "ltil", "rtil")}
+    base = {k: s.get(k) for k in ("u", "v", "z", "y", "lam", "bx", "ltil", "rtil", "calpha")}
     base_sc = s.get("scalars")
     lat, iters, statuses, viol = [], [], [], []
     for t in range(args.trials):
@@ -169,16 +169,14 @@ def main():
         viol.append(s.quality()["max_violation"])
     s.update_loads(0, g.pd, g.qd)
 
-    # ---- CPU baseline: the oracle, serial, from the GPU state after warmup
+    # ---- CPU baseline: the oracle, serial, on its own cold start; the warmup
+    # iterations are run untimed, then the same iterations as the timed steps
     cpu = None
     if not args.no_cpu:
         import oracle as O
         from dataclasses import asdict
-        s.solve(A.COLD, args.warmup)
         orc = O.Oracle(g, O.OracleParams(**asdict(params)))
-        for k in ("u", "v", "z", "y", "lam", "bx", "ltil", "rtil"):
-            orc.set(k, s.get(k))
-        orc.set_scalars(s.scalars())
+        orc.solve(args.warmup)
         tc0 = time.perf_counter()
         orc.solve(args.cpu_iters)
         tc1 = time.perf_counter()

@@ -68,13 +68,17 @@ enum { /* acopf_get_state / acopf_set_state: what */
   ACOPF_QD = 10,       /* [n_bus] */
   ACOPF_HISTORY = 11,  /* get only: [6 inner_total] per inner iteration of
                           the last solve: r_pri, r_dual, r_z, 0, beta, outer */
-  ACOPF_STATS = 12     /* get only: [16] branch-solve counters summed over
+  ACOPF_STATS = 12,    /* get only: [16] branch-solve counters summed over
                           the iterations run with acopf_set_counting on:
                           solves, algorithmic flops, sin/cos, TRON calls,
                           TRON iterations, f/g/H and f evaluations, Cauchy
                           trials, CG iterations, Cholesky attempts, search
                           trials, AL rounds, TRON converged / at the cap /
                           stalled, then 0; the same for every grid index    */
+  ACOPF_BRANCH_ALPHA = 13 /* [n_branch] Cauchy step length each branch's last
+                          trust-region solve ended with; the next solve of
+                          that branch starts its projected search from it
+                          (1 after a cold start)                            */
 };
 
 /* Coupling order (m = 2 n_gen + 8 n_branch), the same in every vector:

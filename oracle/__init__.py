@@ -157,7 +157,7 @@ def load() -> C.CDLL:
     lib.ora_set_count_flops.argtypes = [vp, ip]
     lib.ora_sincos.argtypes = [C.c_double, dp, dp]
     lib.ora_branch_eval.argtypes = [dp, ip, dp, C.c_double, dp, dp, dp, dp, dp]
-    lib.ora_branch_solve.argtypes = [dp, ip, dp, dp, dp, dp, C.POINTER(_Params),
+    lib.ora_branch_solve.argtypes = [dp, ip, dp, dp, dp, dp, dp, C.POINTER(_Params),
                                      C.POINTER(_Stats), ip]
     _lib = lib
     return lib
@@ -168,7 +168,7 @@ def _dp(a: np.ndarray):
 
 
 STATE = {"u": 0, "v": 1, "z": 2, "y": 3, "lam": 4, "rho": 5, "bx": 6,
-         "ltil": 7, "rtil": 8, "vprev": 9, "pd": 10, "qd": 11}
+         "ltil": 7, "rtil": 8, "vprev": 9, "pd": 10, "qd": 11, "calpha": 12}
 
 
 class Oracle:
@@ -211,7 +211,7 @@ class Oracle:
 
     def _size(self, name):
         return {"bx": 6 * self.nl, "ltil": 2 * self.nl, "rtil": self.nl,
-                "pd": self.nb, "qd": self.nb}.get(name, self.m)
+                "calpha": self.nl, "pd": self.nb, "qd": self.nb}.get(name, self.m)
 
     def get(self, name: str) -> np.ndarray:
         out = np.empty(self._size(name))
@@ -345,17 +345,25 @@ def branch_eval(data: np.ndarray, n: int, ltil, rtil: float, x):
 
 
 def branch_solve(data: np.ndarray, n: int, x6, ltil, rtil: float,
-                 params: OracleParams | None = None, count: bool = False):
+                 params: OracleParams | None = None, count: bool = False,
+                 alpha: float = 1.0):
+    """One branch solve from state (x6, ltil, rtil) with the trust-region
+    Cauchy step length starting at `alpha`; returns the new x, ltil, rtil,
+    the coupling values u and the counters (with the final step length under
+    "alpha")."""
     lib = load()
     p = (params or OracleParams()).c()
     x = np.ascontiguousarray(x6, dtype=np.float64).copy()
     lt = np.ascontiguousarray(ltil, dtype=np.float64).copy()
     rt = np.array([rtil], dtype=np.float64)
+    al = np.array([alpha], dtype=np.float64)
     u = np.zeros(8)
     st = _Stats()
-    lib.ora_branch_solve(_dp(data), n, _dp(x), _dp(lt), _dp(rt), _dp(u),
+    lib.ora_branch_solve(_dp(data), n, _dp(x), _dp(lt), _dp(rt), _dp(al), _dp(u),
                          C.byref(p), C.byref(st), int(count))
-    return x, lt, rt[0], u, st.as_dict()
+    out = st.as_dict()
+    out["alpha"] = float(al[0])
+    return x, lt, rt[0], u, out
 
 
 def sincos(x: float):

@@ -443,9 +443,11 @@ void subspace_step(int n, const R* x, const R* g, const R* H, const double* lo,
 }
 
 // Problem interface: f(x) and (f, g, H)(x) with H dense row-major n x n.
+// alpha0 holds the Cauchy step length the projected search starts from; it
+// receives the length the solve ends with.
 template <class R, class P>
 int tron(P& prob, int n, R* x, const double* lo, const double* hi,
-         const ora_params& prm, ora_stats* st, const TronConst& C) {
+         const ora_params& prm, ora_stats* st, const TronConst& C, double* alpha0) {
   ++st->tron_calls;
   for (int i = 0; i < n; ++i) x[i] = clampd(x[i], lo[i], hi[i]);
   R f, g[NMAX], H[NMAX * NMAX];
@@ -458,7 +460,7 @@ int tron(P& prob, int n, R* x, const double* lo, const double* hi,
   }
   R delta = rsqrt_(pg2);
   if (!(delta > R(0.0))) delta = R(1.0);
-  R alphac = R(1.0);
+  R alphac = R(*alpha0);
   int status = TRON_MAXIT;
   for (int it = 0; it < prm.tron_maxit; ++it) {
     R pginf = R(0.0);
@@ -501,6 +503,7 @@ int tron(P& prob, int n, R* x, const double* lo, const double* hi,
     R xx = dotv(n, x, x);
     if (delta * delta <= R(1e-30) * rmax(R(1.0), xx)) { status = TRON_STALL; break; }
   }
+  *alpha0 = val(alphac);
   if (status == TRON_CONVERGED) ++st->tron_converged;
   else if (status == TRON_MAXIT) ++st->tron_maxit;
   else ++st->tron_stall;
@@ -684,18 +687,21 @@ struct BranchProblem {
 
 // Branch solve (Sec. II-C, III-B): one TRON solve for unrated branches; for
 // rated ones an augmented-Lagrangian loop on p^2 + q^2 + s = 0 around TRON.
-// x (6), ltil (2), rtil are the persistent branch state; u (8) receives the
-// branch-side coupling values a_k(x).
+// x (6), ltil (2), rtil and alpha are the persistent branch state; u (8)
+// receives the branch-side coupling values a_k(x). alpha is the Cauchy step
+// length of TRON's projected search: each TRON call starts from the length
+// the branch's previous call ended with (1 after a cold start), which TRON
+// itself already does from one iteration to the next within a call.
 template <class R>
 void branch_solve_t(BranchData& d, double* x6, double* ltil, double* rtil,
-                    double* u8, const ora_params& prm, ora_stats* st) {
+                    double* alpha, double* u8, const ora_params& prm, ora_stats* st) {
   TronConst C;
   ++st->branch_solves;
   R x[NMAX];
   for (int i = 0; i < d.n; ++i) x[i] = R(x6[i]);
   if (d.n == 4) {
     BranchProblem<R> P(d);
-    tron<R>(P, 4, x, d.lo, d.hi, prm, st, C);
+    tron<R>(P, 4, x, d.lo, d.hi, prm, st, C, alpha);
   } else {
     d.ltil[0] = ltil[0];
     d.ltil[1] = ltil[1];
@@ -704,7 +710,7 @@ void branch_solve_t(BranchData& d, double* x6, double* ltil, double* rtil,
     for (int t = 0; t < prm.al_maxit; ++t) {
       ++st->al_iters;
       BranchProblem<R> P(d);
-      tron<R>(P, 6, x, d.lo, d.hi, prm, st, C);
+      tron<R>(P, 6, x, d.lo, d.hi, prm, st, C, alpha);
       R a[8];
       branch_values<R>(d, x, a, nullptr);
       R c0 = rfma(a[0], a[0], a[1] * a[1]) + x[4];
@@ -745,7 +751,7 @@ struct Oracle {
   // couplings
   std::vector<double> u, v, z, y, lam, rho, vprev;
   // branch state
-  std::vector<double> bx, ltil, rtil;
+  std::vector<double> bx, ltil, rtil, calpha;
   // per-bus incidence: gens, branches as from, branches as to
   std::vector<std::vector<int>> bus_gens, bus_from, bus_to;
   // outer-level scalars (Algorithm 1)
@@ -847,6 +853,7 @@ void* ora_create(const ora_grid* G, const ora_params* P) {
   o->bx.assign(6 * nl, 0.0);
   o->ltil.assign(2 * nl, 0.0);
   o->rtil.assign(nl, P->al_rho0);
+  o->calpha.assign(nl, 1.0);
   return o;
 }
 
@@ -909,6 +916,7 @@ void ora_cold_init(void* h) {
     o->ltil[2 * l] = 0.0;
     o->ltil[2 * l + 1] = 0.0;
     o->rtil[l] = o->p.al_rho0;
+    o->calpha[l] = 1.0;
   }
   for (int k = 0; k < o->m; ++k) {
     o->v[k] = o->u[k];
@@ -953,13 +961,13 @@ void ora_branch_step(void* h) {
     double* u8 = &o->u[2 * o->ng + 8 * l];
     if (o->count_flops) {
       FlopTally before = g_tally;
-      branch_solve_t<CR>(d, &o->bx[6 * l], &o->ltil[2 * l], &o->rtil[l], u8,
-                         o->p, &o->st);
+      branch_solve_t<CR>(d, &o->bx[6 * l], &o->ltil[2 * l], &o->rtil[l],
+                         &o->calpha[l], u8, o->p, &o->st);
       o->st.flops += g_tally.total() - before.total();
       o->st.trig += g_tally.trig - before.trig;
     } else {
       branch_solve_t<double>(d, &o->bx[6 * l], &o->ltil[2 * l], &o->rtil[l],
-                             u8, o->p, &o->st);
+                             &o->calpha[l], u8, o->p, &o->st);
     }
   }
 }
@@ -1253,7 +1261,7 @@ int ora_solve(void* h, int fixed) {
 
 // --- state access (copies) -------------------------------------------------
 // what: 0 u, 1 v, 2 z, 3 y, 4 lam, 5 rho, 6 bx (6 nl), 7 ltil (2 nl),
-// 8 rtil (nl), 9 vprev, 10 pd, 11 qd
+// 8 rtil (nl), 9 vprev, 10 pd, 11 qd, 12 calpha (nl)
 static std::vector<double>* pick(Oracle* o, int what) {
   switch (what) {
     case 0: return &o->u;
@@ -1268,6 +1276,7 @@ static std::vector<double>* pick(Oracle* o, int what) {
     case 9: return &o->vprev;
     case 10: return &o->pd;
     case 11: return &o->qd;
+    case 12: return &o->calpha;
     default: return nullptr;
   }
 }
@@ -1361,7 +1370,7 @@ void ora_branch_eval(const double* data, int n, const double* ltil,
 }
 
 void ora_branch_solve(const double* data, int n, double* x6, double* ltil,
-                      double* rtil, double* u8, const ora_params* P,
+                      double* rtil, double* alpha, double* u8, const ora_params* P,
                       ora_stats* st, int count) {
   BranchData d;
   unpack_branch(data, n, d);
@@ -1370,11 +1379,11 @@ void ora_branch_solve(const double* data, int n, double* x6, double* ltil,
   d.rtil = *rtil;
   if (count) {
     FlopTally before = g_tally;
-    branch_solve_t<CR>(d, x6, ltil, rtil, u8, *P, st);
+    branch_solve_t<CR>(d, x6, ltil, rtil, alpha, u8, *P, st);
     st->flops += g_tally.total() - before.total();
     st->trig += g_tally.trig - before.trig;
   } else {
-    branch_solve_t<double>(d, x6, ltil, rtil, u8, *P, st);
+    branch_solve_t<double>(d, x6, ltil, rtil, alpha, u8, *P, st);
   }
 }
 
@@ -1398,7 +1407,8 @@ int ora_tron(int n, double* x, const double* lo, const double* hi,
   if (n < 1 || n > NMAX) return -1;
   CbProblem prob{fcb, gcb, ctx};
   TronConst C;
-  return tron<double>(prob, n, x, lo, hi, *P, st, C);
+  double alpha = 1.0;
+  return tron<double>(prob, n, x, lo, hi, *P, st, C, &alpha);
 }
 
 }  // extern "C"

@@ -20,9 +20,10 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libacopf.so")
 COLD, WARM, CONTINUE = 0, 1, 2
 CONVERGED, MAX_ITER, NUMERICAL = 0, 1, 2
 U, V, Z, Y, LAMBDA, BRANCH_X, BRANCH_LTIL, BRANCH_RTIL, SCALARS, PD, QD, HISTORY, STATS = range(13)
+BRANCH_ALPHA = 13
 STATE_CODES = {"u": U, "v": V, "z": Z, "y": Y, "lam": LAMBDA, "bx": BRANCH_X,
                "ltil": BRANCH_LTIL, "rtil": BRANCH_RTIL, "scalars": SCALARS,
-               "pd": PD, "qd": QD}
+               "pd": PD, "qd": QD, "calpha": BRANCH_ALPHA}
 STATS_NAMES = ("branch_solves", "flops", "trig", "tron_calls", "tron_iters", "n_fgh",
                "n_f", "cauchy_trials", "cg_iters", "chol_attempts", "ps_trials",
                "al_iters", "tron_converged", "tron_maxit", "tron_stall", "reserved")
@@ -247,7 +248,8 @@ class Solver:
         g = self.grids[grid]
         m = 2 * g.n_gen + 8 * g.n_branch
         return {U: m, V: m, Z: m, Y: m, LAMBDA: m, BRANCH_X: 6 * g.n_branch,
-                BRANCH_LTIL: 2 * g.n_branch, BRANCH_RTIL: g.n_branch, SCALARS: 9,
+                BRANCH_LTIL: 2 * g.n_branch, BRANCH_RTIL: g.n_branch,
+                BRANCH_ALPHA: g.n_branch, SCALARS: 9,
                 PD: g.n_bus, QD: g.n_bus, STATS: 16}[code]
 
     def get(self, name: str, grid: int = 0) -> np.ndarray:

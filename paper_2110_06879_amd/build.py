@@ -14,8 +14,8 @@ SOURCES = ["acopf.hip", "branch_kernel.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # every floating-point operation is rounded on its own: the iteration
-    # reproduces a fixed IEEE operation sequence (no fused multiply-add)
+    # no implicit contraction: the iteration reproduces a fixed IEEE
+    # operation sequence, with fused multiply-adds only where written out
     "-ffp-contract=off",
     # no packed FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -413,7 +413,7 @@ struct ColdArgs {
   const double* adm;
   const double *vlo_i, *vhi_i, *vlo_j, *vhi_j, *rate2;
   int64_t n6;
-  double *u, *v, *z, *y, *lam, *bx, *ltil, *rtil;
+  double *u, *v, *z, *y, *lam, *bx, *ltil, *rtil, *calpha;
   double al_rho0;
 };
 
@@ -475,6 +475,7 @@ __global__ __launch_bounds__(256) void cold_kernel(ColdArgs A) {
   A.ltil[l] = 0.0;
   A.ltil[nl + l] = 0.0;
   A.rtil[l] = A.al_rho0;
+  A.calpha[l] = 1.0;
 }
 
 // Reset of the per-grid control words at the start of a solve of grid `only`
@@ -591,6 +592,7 @@ struct acopf_s {
   double* qscratch = nullptr; // [2 nb + 4 nl] quality scratch (lazy)
   unsigned long long* qual = nullptr;  // [6 G] quality maxima (lazy)
   double *u, *v, *z, *y, *lam, *bx, *ltil, *rtil;
+  double* calpha;  // [nl] TRON Cauchy step length of each branch's last solve
   int *gptr, *eptr, *isref;
   std::vector<int> gptr_h, eptr_h;  // host copies, for the bus tiles
   TileDesc* tdesc = nullptr;         // [nb] bus tiles of the bus kernel
@@ -648,6 +650,7 @@ BranchArgs branch_args(const acopf_s* h) {
   A.bx = h->bx;
   A.ltil = h->ltil;
   A.rtil = h->rtil;
+  A.calpha = h->calpha;
   A.rho_pq = h->P.rho_pq;
   A.rho_va = h->P.rho_va;
   A.tron_gtol = h->P.tron_gtol;
@@ -1080,7 +1083,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   for (double** p : gen_d) HIP_TRY(D.alloc(p, ng));
   HIP_TRY(D.alloc(&h->adm, 8 * nl));
   double** br_d[] = {&h->vlo_i, &h->vhi_i, &h->vlo_j, &h->vhi_j, &h->rate2, &h->rtil,
-                     &h->rate};
+                     &h->calpha, &h->rate};
   for (double** p : br_d) HIP_TRY(D.alloc(p, nl));
   HIP_TRY(D.alloc(&h->end_bus, 2 * nl));
   HIP_TRY(D.alloc(&h->bx, 6 * nl));
@@ -1172,7 +1175,8 @@ int acopf_create(const acopf_grid* grids, int32_t n_grids, const acopf_params* p
   // cold state so that get_state is meaningful before the first solve
   ColdArgs ca{-1, h->ng, h->nl, h->ne, h->m, h->ef, h->et, h->gen_grid, h->br_grid, h->pmin, h->pmax, h->qmin, h->qmax,
               h->adm, h->vlo_i, h->vhi_i, h->vlo_j, h->vhi_j, h->rate2, h->n6,
-              h->u, h->v, h->z, h->y, h->lam, h->bx, h->ltil, h->rtil, h->P.al_rho0};
+              h->u, h->v, h->z, h->y, h->lam, h->bx, h->ltil, h->rtil, h->calpha,
+              h->P.al_rho0};
   hipLaunchKernelGGL(cold_kernel, dim3(blocks_for(h->ng + h->nl, 256)), dim3(256), 0, h->stream, ca);
   hipLaunchKernelGGL(ctl_start_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, h->stream,
                      h->ctl, h->G, -1, (int)ACOPF_COLD, 0, h->P.beta0, h->failures);
@@ -1240,7 +1244,7 @@ static int start_impl(acopf_s* h, int grid, int mode, int fixed_iters) {
     ColdArgs ca{grid, h->ng, h->nl, h->ne, h->m, h->ef, h->et, h->gen_grid, h->br_grid,
                 h->pmin, h->pmax, h->qmin, h->qmax, h->adm, h->vlo_i, h->vhi_i, h->vlo_j,
                 h->vhi_j, h->rate2, h->n6, h->u, h->v, h->z, h->y, h->lam, h->bx, h->ltil,
-                h->rtil, h->P.al_rho0};
+                h->rtil, h->calpha, h->P.al_rho0};
     hipLaunchKernelGGL(cold_kernel, dim3(blocks_for(h->ng + h->nl, 256)), dim3(256), 0, st, ca);
   }
   hipLaunchKernelGGL(ctl_start_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, st, h->ctl,
@@ -1422,7 +1426,7 @@ static int64_t state_size(const HostGrid& H, int what) {
     case ACOPF_U: case ACOPF_V: case ACOPF_Z: case ACOPF_Y: case ACOPF_LAMBDA: return m;
     case ACOPF_BRANCH_X: return 6 * H.nl;
     case ACOPF_BRANCH_LTIL: return 2 * H.nl;
-    case ACOPF_BRANCH_RTIL: return H.nl;
+    case ACOPF_BRANCH_RTIL: case ACOPF_BRANCH_ALPHA: return H.nl;
     case ACOPF_SCALARS: return 9;
     case ACOPF_PD: case ACOPF_QD: return H.nb;
     case ACOPF_STATS: return kStats;
@@ -1478,9 +1482,13 @@ static int copy_state(acopf_s* h, int grid, int what, double* host, int64_t n, b
     }
     return ACOPF_OK;
   }
-  if (what == ACOPF_BRANCH_X || what == ACOPF_BRANCH_LTIL || what == ACOPF_BRANCH_RTIL) {
+  if (what == ACOPF_BRANCH_X || what == ACOPF_BRANCH_LTIL || what == ACOPF_BRANCH_RTIL ||
+      what == ACOPF_BRANCH_ALPHA) {
     const int rows = what == ACOPF_BRANCH_X ? 6 : what == ACOPF_BRANCH_LTIL ? 2 : 1;
-    double* base = what == ACOPF_BRANCH_X ? h->bx : what == ACOPF_BRANCH_LTIL ? h->ltil : h->rtil;
+    double* base = what == ACOPF_BRANCH_X      ? h->bx
+                   : what == ACOPF_BRANCH_LTIL ? h->ltil
+                   : what == ACOPF_BRANCH_RTIL ? h->rtil
+                                               : h->calpha;
     std::vector<double> all;
     HIP_TRY(pull(base, rows * nl, all));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1569,6 +1577,9 @@ int acopf_set_state(acopf_handle h, int32_t grid, int32_t what, const double* in
   if (need < 0) return fail(ACOPF_EINVAL, "unknown state code");
   if (n != need) return fail(ACOPF_EINVAL, "buffer size mismatch: need " + std::to_string(need));
   if (!finite_all(in, n) && what != ACOPF_SCALARS) return fail(ACOPF_EINVAL, "non-finite state");
+  if (what == ACOPF_BRANCH_ALPHA)
+    for (int64_t i = 0; i < n; ++i)
+      if (!(in[i] > 0.0)) return fail(ACOPF_EINVAL, "Cauchy step lengths must be positive");
   HIP_TRY(hipSetDevice(h->device));
   if (h->running[grid]) return fail(ACOPF_ESTATE, "grid is running");
   h->solved = true;
@@ -1592,7 +1603,8 @@ static std::vector<std::pair<void*, size_t>> state_arrays(acopf_s* h) {
   const size_t d = sizeof(double);
   return {{h->u, h->m * d},      {h->v, h->m * d},      {h->z, h->m * d},
           {h->y, h->m * d},      {h->lam, h->m * d},    {h->bx, 6 * h->nl * d},
-          {h->ltil, 2 * h->nl * d}, {h->rtil, h->nl * d}, {h->pd, h->nb * d},
+          {h->ltil, 2 * h->nl * d}, {h->rtil, h->nl * d}, {h->calpha, h->nl * d},
+          {h->pd, h->nb * d},
           {h->qd, h->nb * d},    {h->ctl, h->G * sizeof(GridCtl)}};
 }
 
@@ -1664,6 +1676,8 @@ int acopf_copy_grid(acopf_handle h, int32_t src, int32_t dst) {
   }
   HIP_TRY(cp(h->rtil, A.r6b, B.r6b, A.r6e - A.r6b));
   HIP_TRY(cp(h->rtil, A.r4b, B.r4b, A.r4e - A.r4b));
+  HIP_TRY(cp(h->calpha, A.r6b, B.r6b, A.r6e - A.r6b));
+  HIP_TRY(cp(h->calpha, A.r4b, B.r4b, A.r4e - A.r4b));
   HIP_TRY(cp(h->pd, A.bus_off, B.bus_off, A.nb));
   HIP_TRY(cp(h->qd, A.bus_off, B.bus_off, A.nb));
   HIP_TRY(hipMemcpyAsync(h->ctl + dst, h->ctl + src, sizeof(GridCtl), hipMemcpyDeviceToDevice, st));

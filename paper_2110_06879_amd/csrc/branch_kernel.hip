@@ -14,6 +14,12 @@
 // reads element l); the coupling values of a branch's two ends are gathered
 // from the bus-major coupling vectors.
 //
+// Besides x and the AL multipliers and penalty, a branch keeps the Cauchy
+// step length of its trust-region solves between ADMM iterations: a solve
+// starts its projected search from the length the branch's previous solve
+// ended with (1 after a cold start) rather than from 1, which halves the
+// Cauchy trials once the iterates settle.
+//
 // Arithmetic is a fixed IEEE operation sequence shared with the CPU oracle:
 // no implicit contraction, fused multiply-adds written out where the oracle
 // writes them, reciprocal pivots in the Cholesky factor, norm tests in
@@ -662,7 +668,7 @@ enum { kConv = 0, kMaxit = 1, kStall = 2 };
 
 template <int N>
 __device__ int tron(const BranchIn<N>& B, double* x, const double* lo, const double* hi,
-                    double gtol, double ftol, int maxit, Counters& cnt) {
+                    double gtol, double ftol, int maxit, double& alphac, Counters& cnt) {
   ++cnt.tron_calls;
 #pragma unroll
   for (int i = 0; i < N; ++i) x[i] = clampd(x[i], lo[i], hi[i]);
@@ -678,7 +684,6 @@ __device__ int tron(const BranchIn<N>& B, double* x, const double* lo, const dou
   double delta = sqrt(pg2);
   FL(4 * N + 1);
   if (!(delta > 0.0)) delta = 1.0;
-  double alphac = 1.0;
   int status = kMaxit;
   for (int it = 0; it < maxit; ++it) {
     double pginf = 0.0;
@@ -776,7 +781,6 @@ __device__ inline void tron_begin(TronState<N>& S, const double* lo, const doubl
   S.status = kMaxit;
   S.eval = true;
   S.first = true;
-  S.alphac = 1.0;
   S.delta = 1.0;
 }
 
@@ -933,9 +937,11 @@ __device__ void solve_branch(const BranchArgs& A, int64_t l, int grid, Counters&
     B.lt0 = 0.0;
     B.lt1 = 0.0;
     B.rt = 0.0;
+    double alphac = A.calpha[l];
     int failures = 0;
     if (N == 4) {
-      failures += tron<N>(B, x, lo, hi, A.tron_gtol, A.tron_ftol, A.tron_maxit, cnt) != kConv;
+      failures +=
+          tron<N>(B, x, lo, hi, A.tron_gtol, A.tron_ftol, A.tron_maxit, alphac, cnt) != kConv;
     } else {
       B.lt0 = A.ltil[l];
       B.lt1 = A.ltil[nl + l];
@@ -943,7 +949,8 @@ __device__ void solve_branch(const BranchArgs& A, int64_t l, int grid, Counters&
       double cprev = 1.0 / 0.0;
       for (int t = 0; t < A.al_maxit; ++t) {
         ++cnt.al;
-        failures += tron<N>(B, x, lo, hi, A.tron_gtol, A.tron_ftol, A.tron_maxit, cnt) != kConv;
+        failures +=
+            tron<N>(B, x, lo, hi, A.tron_gtol, A.tron_ftol, A.tron_maxit, alphac, cnt) != kConv;
         double a[8], aux[4];
         values<N>(B, x, a, aux, cnt);
         const double c0 = fma(a[0], a[0], a[1] * a[1]) + x[4];
@@ -971,6 +978,7 @@ __device__ void solve_branch(const BranchArgs& A, int64_t l, int grid, Counters&
     for (int k = 0; k < 8; ++k) A.u[cidx[k]] = a[k];
 #pragma unroll
     for (int i = 0; i < N; ++i) A.bx[i * nl + l] = x[i];
+    A.calpha[l] = alphac;
     if (failures) atomicAdd(&A.failures[grid], failures);
   }
 }
@@ -1085,6 +1093,7 @@ __device__ void run_pool(const BranchArgs& A, int64_t begin, int64_t end, unsign
           grid = A.br_grid[l];
           if (A.ctl[grid].done == 0) {
             load_branch<N>(A, l, B, lo, hi, S.x);
+            S.alphac = A.calpha[l];
             failures = 0;
             t_al = 0;
             cprev = 1.0 / 0.0;
@@ -1143,6 +1152,7 @@ __device__ void run_pool(const BranchArgs& A, int64_t begin, int64_t end, unsign
     for (int k = 0; k < 8; ++k) A.u[cidx[k]] = a[k];
 #pragma unroll
     for (int i = 0; i < N; ++i) A.bx[i * nl + l] = S.x[i];
+    A.calpha[l] = S.alphac;
     if (failures) atomicAdd(&A.failures[grid], failures);
     ++solves;
     flops += cnt.flops;  // a lane may solve many branches: keep the sum in 64 bits

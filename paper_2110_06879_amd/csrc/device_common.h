@@ -38,6 +38,7 @@ struct BranchArgs {
   const double *v, *z, *y;
   double* u;
   double *bx, *ltil, *rtil;  // [6][nl], [2][nl], [nl]
+  double* calpha;            // [nl] TRON Cauchy step length, carried between solves
   double rho_pq, rho_va, tron_gtol, tron_ftol;
   double al_tol, al_shrink, al_rho_growth, al_rho_max;
   int tron_maxit, al_maxit;

@@ -13,7 +13,7 @@ from paper_2110_06879_amd import serve as S
 from paper_2110_06879_amd.gridgen import config_grid, gridgen, perturb_loads
 
 pytestmark = pytest.mark.gpu
-VECS = ("u", "v", "z", "y", "lam", "bx", "ltil", "rtil")
+VECS = ("u", "v", "z", "y", "lam", "bx", "ltil", "rtil", "calpha")
 
 
 def note(msg):

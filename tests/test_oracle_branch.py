@@ -265,3 +265,27 @@ def test_series_sincos_accuracy():
         assert abs(s - es) <= 4e-16 * max(1.0, abs(x)) and abs(c - ec) <= 4e-16 * max(1.0, abs(x)), x
         assert abs(s * s + c * c - 1.0) < 1e-15
     assert worst < 2e-15
+
+
+def test_branch_solve_independent_of_cauchy_start():
+    """The Cauchy step length a branch solve starts its projected search from
+    (carried from the branch's previous solve) changes the path of the
+    trust-region method, not its answer: started from 1, from 1e-4 and from
+    50, the 4-variable solve reaches the same first-order point; the step
+    length it returns is positive and finite."""
+    g = random_grid_with_taps(4)
+    o = O.Oracle(g, cold=False)
+    ad = o.admittance()
+    rng = np.random.default_rng(17)
+    for l in range(4):
+        data, lo, hi = random_branch(rng, 4, ad[l])
+        x0 = np.array([1.0, 1.0, 0.0, 0.0, 0.0, 0.0])
+        sols = []
+        for a0 in (1.0, 1e-4, 50.0):
+            x, lt, rt, u, st = O.branch_solve(data, 4, x0, [0, 0], 10.0, alpha=a0)
+            assert np.isfinite(st["alpha"]) and st["alpha"] > 0.0
+            f, gr, H, a = O.branch_eval(data, 4, [0, 0], 0.0, x[:4])
+            assert np.abs(proj_grad(x[:4], gr, lo[:4], hi[:4])).max() < 1e-6
+            sols.append(x[:4])
+        for x in sols[1:]:
+            np.testing.assert_allclose(x, sols[0], rtol=0, atol=1e-6)
