@@ -165,9 +165,10 @@ enum { TRON_CONVERGED = 0, TRON_MAXIT = 1, TRON_STALL = 2 };
 // steps by preconditioned conjugate gradients with Steihaug's treatment of
 // negative curvature and the trust-region boundary, each followed by a
 // projected search; the trust-region ratio test decides acceptance.
-// Dense Cholesky of the scaled free Hessian (shifted when not positive
-// definite) is the preconditioner: for n <= 6 the incomplete factorization
-// of Lin & More is the complete one.
+// A dense Cholesky factorization of the scaled free Hessian (shifted when
+// not positive definite), in its square-root-free form L E L', is the
+// preconditioner: for n <= 6 the incomplete factorization of Lin & More is
+// the complete one.
 // ---------------------------------------------------------------------------
 struct TronConst {
   double eta0 = 1e-4, eta1 = 0.25, eta2 = 0.75;
@@ -275,43 +276,51 @@ void cauchy_step(int n, const R* x, const R* g, const R* H, const double* lo,
   }
 }
 
-// Dense Cholesky A = L L' (lower, row-major, m x m), column by column; as in
-// LAPACK's unblocked factorization the column below a pivot is scaled by the
-// pivot's reciprocal, which is kept in rd for the triangular solves. Returns
-// false when a pivot is not positive.
+// Square-root-free Cholesky A = L E L' (L unit lower, E diagonal; row-major,
+// m x m), column by column: with v_k = L_jk e_k, the pivot is
+// e_j = A_jj - sum_k L_jk v_k and the column below it is
+// L_ij = (A_ij - sum_k L_ik v_k) / e_j, the division done as a multiplication
+// by the reciprocal pivot, which is kept in rd for the solve. The same
+// factorization as L~ L~' with L~ = L E^(1/2), without square roots.
+// Returns false when a pivot is not positive.
 template <class R>
-bool cholesky(int m, const R* A, R* L, R* rd) {
+bool ldlt(int m, const R* A, R* L, R* rd) {
+  R e[NMAX];
   for (int i = 0; i < m * m; ++i) L[i] = R(0.0);
   for (int j = 0; j < m; ++j) {
+    R v[NMAX];
+    for (int k = 0; k < j; ++k) v[k] = L[j * m + k] * e[k];
     R d = A[j * m + j];
-    for (int k = 0; k < j; ++k) d = rfma(-L[j * m + k], L[j * m + k], d);
+    for (int k = 0; k < j; ++k) d = rfma(-L[j * m + k], v[k], d);
     if (!(d > R(0.0))) return false;
-    R ljj = rsqrt_(d);
-    L[j * m + j] = ljj;
-    R rj = R(1.0) / ljj;
+    e[j] = d;
+    L[j * m + j] = R(1.0);
+    R rj = R(1.0) / d;
     rd[j] = rj;
     for (int i = j + 1; i < m; ++i) {
       R t = A[i * m + j];
-      for (int k = 0; k < j; ++k) t = rfma(-L[i * m + k], L[j * m + k], t);
+      for (int k = 0; k < j; ++k) t = rfma(-L[i * m + k], v[k], t);
       L[i * m + j] = t * rj;
     }
   }
   return true;
 }
 
-// z = M^{-1} r with M = D^{-1} L L' D^{-1}; rd holds the reciprocal pivots.
+// z = M^{-1} r with M = D^{-1} L E L' D^{-1}; rd holds the reciprocal pivots
+// 1/e: forward solve with L, scaling by rd, backward solve with L'.
 template <class R>
 void precond(int m, const R* L, const R* rd, const R* D, const R* r, R* z) {
   R t[NMAX];
   for (int i = 0; i < m; ++i) {
     R a = D[i] * r[i];
     for (int k = 0; k < i; ++k) a = rfma(-L[i * m + k], t[k], a);
-    t[i] = a * rd[i];
+    t[i] = a;
   }
+  for (int i = 0; i < m; ++i) t[i] = t[i] * rd[i];
   for (int i = m - 1; i >= 0; --i) {
     R a = t[i];
     for (int k = i + 1; k < m; ++k) a = rfma(-L[k * m + i], z[k], a);
-    z[i] = a * rd[i];
+    z[i] = a;
   }
   for (int i = 0; i < m; ++i) z[i] = D[i] * z[i];
 }
@@ -342,7 +351,8 @@ void subspace_step(int n, const R* x, const R* g, const R* H, const double* lo,
     }
     R rr0 = dotv(nf, r, r);  // squared norm of the initial residual
     if (!(rr0 > R(0.0))) break;
-    // preconditioner: Cholesky of D B D + shift I, D = diag(1/sqrt|B_aa|)
+    // preconditioner: L E L' factorization of D B D + shift I,
+    // D = diag(1/sqrt|B_aa|)
     R D[NMAX], Bs[NMAX * NMAX], L[NMAX * NMAX], rd[NMAX];
     for (int a = 0; a < nf; ++a) {
       R baa = rabs(B[a * nf + a]);
@@ -360,7 +370,7 @@ void subspace_step(int n, const R* x, const R* g, const R* H, const double* lo,
       for (int q = 0; q < nf * nf; ++q) A[q] = Bs[q];
       for (int a = 0; a < nf; ++a) A[a * nf + a] = A[a * nf + a] + shift;
       ++st->chol_attempts;
-      if (cholesky(nf, A, L, rd)) { ok = true; break; }
+      if (ldlt(nf, A, L, rd)) { ok = true; break; }
       shift = rmax(R(2.0) * shift, R(C.shift_min));
     }
     if (!ok) {

@@ -22,8 +22,8 @@
 //
 // Arithmetic is a fixed IEEE operation sequence shared with the CPU oracle:
 // no implicit contraction, fused multiply-adds written out where the oracle
-// writes them, reciprocal pivots in the Cholesky factor, norm tests in
-// squares, and a series sin/cos.
+// writes them, a square-root-free Cholesky factor with reciprocal pivots,
+// norm tests in squares, and a series sin/cos.
 //
 // The free set of a subspace step is handled with a mask over all N
 // variables instead of compressed indices (fixed rows and columns act as
@@ -410,7 +410,8 @@ __device__ void cauchy(const double* x, const double* g, const Sym<N>& H,
 }
 
 // Preconditioner application on the free variables (mask fr):
-// z = D L^-T L^-1 D r with the reciprocal pivots rd; counted as 2 nf^2 + 2 nf.
+// z = D L^-T E^-1 L^-1 D r with L unit lower and the reciprocal pivots
+// rd = 1/E; counted as 2 nf^2 + nf.
 template <int N>
 __device__ inline void precond(const Sym<N>& L, const double* rd, const double* D,
                                const bool* fr, const double* r, double* z) {
@@ -420,57 +421,64 @@ __device__ inline void precond(const Sym<N>& L, const double* rd, const double* 
     double a = D[i] * r[i];
 #pragma unroll
     for (int k = 0; k < i; ++k) a = fma(-L(i, k), t[k], a);
-    t[i] = fr[i] ? a * rd[i] : 0.0;
+    t[i] = fr[i] ? a : 0.0;
   }
+#pragma unroll
+  for (int i = 0; i < N; ++i) t[i] = t[i] * rd[i];
 #pragma unroll
   for (int i = N - 1; i >= 0; --i) {
     double a = t[i];
 #pragma unroll
     for (int k = i + 1; k < N; ++k) a = fma(-L(k, i), z[k], a);
-    z[i] = fr[i] ? a * rd[i] : 0.0;
+    z[i] = fr[i] ? a : 0.0;
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) z[i] = D[i] * z[i];
 }
 
-// Dense Cholesky of the scaled, shifted free Hessian D H D + shift I (fixed
-// rows/columns act as identity), formed element by element as the
-// factorization needs it; the column below a pivot is scaled by the pivot's
-// reciprocal (kept in rd for the triangular solves), as in LAPACK's unblocked
-// factorization. Returns false at the first non-positive free pivot; flops
-// are counted as on the compressed nf x nf matrix.
+// Square-root-free Cholesky factorization L E L' (L unit lower, E diagonal)
+// of the scaled, shifted free Hessian D H D + shift I (fixed rows/columns act
+// as identity), formed element by element as the factorization needs it.
+// Column j: v_k = L_jk e_k, pivot e_j = a_jj - sum_k L_jk v_k, and
+// L_ij = (a_ij - sum_k L_ik v_k) times the reciprocal pivot, which is kept in
+// rd for the solves. Returns false at the first non-positive free pivot;
+// flops are counted as on the compressed nf x nf matrix.
 template <int N>
-__device__ inline bool cholesky(const Sym<N>& H, const double* D, double shift,
-                                const bool* fr, int nf, Sym<N>& L, double* rd,
-                                Counters& cnt) {
+__device__ inline bool ldlt(const Sym<N>& H, const double* D, double shift,
+                            const bool* fr, int nf, Sym<N>& L, double* rd,
+                            Counters& cnt) {
 #pragma unroll
   for (int q = 0; q < N * (N + 1) / 2; ++q) L.t[q] = 0.0;
+  double e[N];
   int jc = 0;  // compressed column index
 #pragma unroll
   for (int j = 0; j < N; ++j) {
+    L(j, j) = 1.0;
     if (!fr[j]) {
-      L(j, j) = 1.0;
+      e[j] = 1.0;
       rd[j] = 1.0;
       continue;
     }
+    double v[N];
+#pragma unroll
+    for (int k = 0; k < j; ++k) v[k] = L(j, k) * e[k];
     double d = D[j] * H(j, j) * D[j] + shift;
 #pragma unroll
-    for (int k = 0; k < j; ++k) d = fma(-L(j, k), L(j, k), d);
-    FL(2 * jc);
+    for (int k = 0; k < j; ++k) d = fma(-L(j, k), v[k], d);
+    FL(3 * jc);
     if (!(d > 0.0)) return false;
-    const double ljj = sqrt(d);
-    L(j, j) = ljj;
-    const double rj = 1.0 / ljj;
+    e[j] = d;
+    const double rj = 1.0 / d;
     rd[j] = rj;
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {
       if (!fr[i]) continue;
       double t = D[i] * H(i, j) * D[j];
 #pragma unroll
-      for (int k = 0; k < j; ++k) t = fma(-L(i, k), L(j, k), t);
+      for (int k = 0; k < j; ++k) t = fma(-L(i, k), v[k], t);
       L(i, j) = t * rj;
     }
-    FL(2 + (nf - 1 - jc) * (2 * jc + 1));
+    FL(1 + (nf - 1 - jc) * (2 * jc + 1));
     ++jc;
   }
   return true;
@@ -540,7 +548,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
     for (int att = 0; att < kMaxChol; ++att) {
       FL(nf);
       ++cnt.chol;
-      if (cholesky<N>(H, D, shift, fr, nf, L, rd, cnt)) {
+      if (ldlt<N>(H, D, shift, fr, nf, L, rd, cnt)) {
         ok = true;
         break;
       }
@@ -564,7 +572,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       res[i] = r[i];
     }
     precond<N>(L, rd, D, fr, res, zz);
-    FL(2 * nf * nf + 2 * nf);
+    FL(2 * nf * nf + nf);
 #pragma unroll
     for (int i = 0; i < N; ++i) p[i] = zz[i];
     double rz = dotN<N>(res, zz);
@@ -621,7 +629,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       rz = rzn;
 #pragma unroll
       for (int i = 0; i < N; ++i) p[i] = fma(bcg, p[i], zz[i]);
-      FL(2 * nf * nf + 2 * nf + 2 * nf + 1 + 2 * nf);
+      FL(2 * nf * nf + nf + 2 * nf + 1 + 2 * nf);
     }
     // projected search along d from w
     const double qw = model<N>(g, H, s, cnt);
