@@ -306,13 +306,13 @@ bool ldlt(int m, const R* A, R* L, R* rd) {
   return true;
 }
 
-// z = M^{-1} r with M = D^{-1} L E L' D^{-1}; rd holds the reciprocal pivots
-// 1/e: forward solve with L, scaling by rd, backward solve with L'.
+// z = M^{-1} r with M = L E L'; rd holds the reciprocal pivots 1/e: forward
+// solve with L, scaling by rd, backward solve with L'.
 template <class R>
-void precond(int m, const R* L, const R* rd, const R* D, const R* r, R* z) {
+void precond(int m, const R* L, const R* rd, const R* r, R* z) {
   R t[NMAX];
   for (int i = 0; i < m; ++i) {
-    R a = D[i] * r[i];
+    R a = r[i];
     for (int k = 0; k < i; ++k) a = rfma(-L[i * m + k], t[k], a);
     t[i] = a;
   }
@@ -322,7 +322,6 @@ void precond(int m, const R* L, const R* rd, const R* D, const R* r, R* z) {
     for (int k = i + 1; k < m; ++k) a = rfma(-L[k * m + i], z[k], a);
     z[i] = a;
   }
-  for (int i = 0; i < m; ++i) z[i] = D[i] * z[i];
 }
 
 // Subspace steps from the Cauchy point w (in/out). s = w - x on exit.
@@ -351,36 +350,38 @@ void subspace_step(int n, const R* x, const R* g, const R* H, const double* lo,
     }
     R rr0 = dotv(nf, r, r);  // squared norm of the initial residual
     if (!(rr0 > R(0.0))) break;
-    // preconditioner: L E L' factorization of D B D + shift I,
-    // D = diag(1/sqrt|B_aa|)
-    R D[NMAX], Bs[NMAX * NMAX], L[NMAX * NMAX], rd[NMAX];
-    for (int a = 0; a < nf; ++a) {
-      R baa = rabs(B[a * nf + a]);
-      D[a] = baa > R(0.0) ? R(1.0) / rsqrt_(baa) : R(1.0);
-    }
+    // preconditioner: Lin & More factor D B D + shift I with the scaling
+    // D = diag(|B_aa|^(-1/2)) (1 where B_aa = 0), so that the preconditioner
+    // is M = D^-1 (D B D + shift I) D^-1 = B + shift D^-2. It is formed here
+    // as that matrix directly: the L E L' factorization of B + shift S with
+    // S = diag(|B_aa|, or 1 where B_aa = 0). The scaled diagonal entries
+    // D_a B_aa D_a are the signs of B_aa, whose minimum sets the shift.
+    R Sd[NMAX], L[NMAX * NMAX], rd[NMAX];
     R mind = R(INF);
     for (int a = 0; a < nf; ++a) {
-      for (int b = 0; b < nf; ++b) Bs[a * nf + b] = D[a] * B[a * nf + b] * D[b];
-      mind = rmin(mind, Bs[a * nf + a]);
+      R baa = B[a * nf + a];
+      Sd[a] = baa == R(0.0) ? R(1.0) : rabs(baa);
+      R sgn = baa > R(0.0) ? R(1.0) : (baa < R(0.0) ? R(-1.0) : R(0.0));
+      mind = rmin(mind, sgn);
     }
     R shift = mind > R(0.0) ? R(0.0) : R(C.shift_min) - mind;
     bool ok = false;
     for (int att = 0; att < C.max_chol; ++att) {
       R A[NMAX * NMAX];
-      for (int q = 0; q < nf * nf; ++q) A[q] = Bs[q];
-      for (int a = 0; a < nf; ++a) A[a * nf + a] = A[a * nf + a] + shift;
+      for (int q = 0; q < nf * nf; ++q) A[q] = B[q];
+      for (int a = 0; a < nf; ++a) A[a * nf + a] = rfma(shift, Sd[a], A[a * nf + a]);
       ++st->chol_attempts;
       if (ldlt(nf, A, L, rd)) { ok = true; break; }
       shift = rmax(R(2.0) * shift, R(C.shift_min));
     }
     if (!ok) {
       for (int q = 0; q < nf * nf; ++q) L[q] = R(0.0);
-      for (int a = 0; a < nf; ++a) { L[a * nf + a] = R(1.0); rd[a] = R(1.0); D[a] = R(1.0); }
+      for (int a = 0; a < nf; ++a) { L[a * nf + a] = R(1.0); rd[a] = R(1.0); }
     }
     // Steihaug PCG on min 1/2 d'Bd - r'd  s.t. ||s + d|| <= delta
     R d[NMAX], res[NMAX], zz[NMAX], p[NMAX], Bp[NMAX];
     for (int a = 0; a < nf; ++a) { d[a] = R(0.0); res[a] = r[a]; }
-    precond(nf, L, rd, D, res, zz);
+    precond(nf, L, rd, res, zz);
     for (int a = 0; a < nf; ++a) p[a] = zz[a];
     R rz = dotv(nf, res, zz);
     bool boundary = false;
@@ -416,7 +417,7 @@ void subspace_step(int n, const R* x, const R* g, const R* H, const double* lo,
         res[a] = rfma(-alpha, Bp[a], res[a]);
       }
       if (dotv(nf, res, res) <= R(C.cgtol * C.cgtol) * rr0) break;
-      precond(nf, L, rd, D, res, zz);
+      precond(nf, L, rd, res, zz);
       R rzn = dotv(nf, res, zz);
       R bcg = rzn / rz;
       rz = rzn;
@@ -567,38 +568,43 @@ void branch_values(const BranchData& d, const R* x, R* a, R* aux) {
 constexpr int UT_P[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
 constexpr int UT_Q[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
 
-// Gradients (over v_i, v_j, theta_i, theta_j) and upper-triangular Hessians
-// of the four flows. A flow is cw w_own + cR w^R + cI w^I with
-// w^R = v_i v_j cos(theta_i - theta_j) and w^I = v_i v_j sin(...).
+// Derivatives over (v_i, v_j, theta_i, theta_j). Each flow is linear in
+// three quantities: a_k = cw_k w_own + cR_k w^R + cI_k w^I, with
+// w^R = v_i v_j cos(theta_i - theta_j), w^I = v_i v_j sin(...) and w_own the
+// squared magnitude at the flow's own end (v_i^2 for p_ij, q_ij; v_j^2 for
+// p_ji, q_ji). W holds the gradients of w^R, w^I (dWR, dWI) and their
+// upper-triangular Hessians (hWR, hWI, entries ordered as UT_P/UT_Q); ga the
+// flow gradients.
 template <class R>
-void flow_derivs(const BranchData& d, const R* x, const R* aux, R (*ga)[4],
-                 R (*Ha)[10]) {
+struct WDerivs {
+  R dWR[4], dWI[4], hWR[10], hWI[10];
+  R cw[4], cR[4], cI[4];
+};
+
+template <class R>
+void flow_derivs(const BranchData& d, const R* x, const R* aux, WDerivs<R>& W, R (*ga)[4]) {
   R vi = x[0], vj = x[1];
   R cs = aux[0], sn = aux[1], WR = aux[2], WI = aux[3];
   R jc = vj * cs, ic = vi * cs, js = vj * sn, is = vi * sn;
   R twvi = R(2.0) * vi, twvj = R(2.0) * vj;
-  R dWR[4] = {jc, ic, -WI, WI};
-  R dWI[4] = {js, is, WR, -WR};
-  R hWR[10] = {R(0.0), cs, -js, js, R(0.0), -is, is, -WR, WR, -WR};
-  R hWI[10] = {R(0.0), sn, jc, -jc, R(0.0), ic, -ic, -WI, WI, -WI};
-  R coef[4][3] = {{R(d.gii), R(d.gij), R(d.bij)},
-                  {-R(d.bii), -R(d.bij), R(d.gij)},
-                  {R(d.gjj), R(d.gji), -R(d.bji)},
-                  {-R(d.bjj), -R(d.bji), -R(d.gji)}};
+  const R dWR[4] = {jc, ic, -WI, WI};
+  const R dWI[4] = {js, is, WR, -WR};
+  const R hWR[10] = {R(0.0), cs, -js, js, R(0.0), -is, is, -WR, WR, -WR};
+  const R hWI[10] = {R(0.0), sn, jc, -jc, R(0.0), ic, -ic, -WI, WI, -WI};
+  const R cw[4] = {R(d.gii), -R(d.bii), R(d.gjj), -R(d.bjj)};
+  const R cR[4] = {R(d.gij), -R(d.bij), R(d.gji), -R(d.bji)};
+  const R cI[4] = {R(d.bij), R(d.gij), -R(d.bji), -R(d.gji)};
+  for (int p = 0; p < 4; ++p) { W.dWR[p] = dWR[p]; W.dWI[p] = dWI[p]; }
+  for (int t = 0; t < 10; ++t) { W.hWR[t] = hWR[t]; W.hWI[t] = hWI[t]; }
+  for (int k = 0; k < 4; ++k) { W.cw[k] = cw[k]; W.cR[k] = cR[k]; W.cI[k] = cI[k]; }
   for (int k = 0; k < 4; ++k) {
     int own = k < 2 ? 0 : 1;
     R tw = k < 2 ? twvi : twvj;
     for (int p = 0; p < 4; ++p) {
       if (p == own)
-        ga[k][p] = rfma(coef[k][2], dWI[p], rfma(coef[k][1], dWR[p], coef[k][0] * tw));
+        ga[k][p] = rfma(cI[k], dWI[p], rfma(cR[k], dWR[p], cw[k] * tw));
       else
-        ga[k][p] = rfma(coef[k][2], dWI[p], coef[k][1] * dWR[p]);
-    }
-    for (int t = 0; t < 10; ++t) {
-      if (t == 0 || t == 4)  // (0,0), (1,1): only the w_own term
-        Ha[k][t] = (t == 0) == (own == 0) ? R(2.0) * coef[k][0] : R(0.0);
-      else
-        Ha[k][t] = rfma(coef[k][2], hWI[t], coef[k][1] * hWR[t]);
+        ga[k][p] = rfma(cI[k], dWI[p], cR[k] * dWR[p]);
     }
   }
 }
@@ -627,37 +633,102 @@ struct BranchProblem {
     return F;
   }
 
-  // F, its gradient and its Hessian (dense row-major n x n). With
-  // m_k = y_k + rho_k r_k:  grad F = sum_k m_k grad a_k + AL terms and
-  // hess F = sum_k rho_k grad a_k grad a_k' + m_k hess a_k + AL terms.
+  // F, its gradient and its Hessian (dense row-major n x n), by the chain
+  // rule through the coupling values. With m_k = y_k + rho_k r_k for the
+  // flows and, on rated branches, m_e = ltil_e + rtil c_e for the two line
+  // limits (c_e = p_e^2 + q_e^2 + s_e, whose gradient is
+  // 2 p_e grad p_e + 2 q_e grad q_e + e_s):
+  //   grad F = sum_k mu_k grad a_k + (w, theta couplings) + m_e e_s,
+  //   hess F = sum_k nu_k grad a_k grad a_k' + sum_k mu_k hess a_k
+  //            + rtil grad c_e grad c_e' + (w, theta couplings),
+  // where mu_k = m_k + 2 m_e a_k and nu_k = rho_k + 2 m_e for a flow k at
+  // end e (mu_k = m_k, nu_k = rho_k without line limits). As the flows are
+  // linear in (w_own, w^R, w^I), sum_k mu_k grad a_k and sum_k mu_k hess a_k
+  // reduce to MR (grad, hess) w^R + MI (grad, hess) w^I + the w_own terms,
+  // with MR = sum_k mu_k cR_k, MI = sum_k mu_k cI_k, O_i = mu_0 cw_0 +
+  // mu_1 cw_1 (end i), O_j = mu_2 cw_2 + mu_3 cw_3 (end j).
   void fgh(const R* x, R& F, R* g, R* H) {
     const int n = d.n;
-    R a[8], aux[4], ga[4][4], Ha[4][10];
+    R a[8], aux[4], ga[4][4];
+    WDerivs<R> W;
     branch_values<R>(d, x, a, aux);
-    flow_derivs<R>(d, x, aux, ga, Ha);
+    flow_derivs<R>(d, x, aux, W, ga);
     F = R(0.0);
+    // the four flow couplings
+    R mu[4], nu[4];
+    for (int k = 0; k < 4; ++k) {
+      R r = a[k] - R(d.vb[k]) + R(d.z[k]);
+      F = rfma(R(0.5) * R(d.rho[k]) * r, r, rfma(R(d.y[k]), r, F));
+      mu[k] = rfma(R(d.rho[k]), r, R(d.y[k]));
+      nu[k] = R(d.rho[k]);
+    }
+    // w_i = v_i^2 (variable 0), theta_i (2), w_j = v_j^2 (1), theta_j (3)
+    const int var[4] = {0, 2, 1, 3};
+    R mv[4];
+    for (int k = 4; k < 8; ++k) {
+      R r = a[k] - R(d.vb[k]) + R(d.z[k]);
+      F = rfma(R(0.5) * R(d.rho[k]) * r, r, rfma(R(d.y[k]), r, F));
+      mv[k - 4] = rfma(R(d.rho[k]), r, R(d.y[k]));
+    }
+    // augmented Lagrangian on the line limits (eq. branch, last two lines)
+    R gc[2][4], me[2];
+    if (n == 6) {
+      for (int e = 0; e < 2; ++e) {
+        int kp = 2 * e, kq = 2 * e + 1, s = 4 + e;
+        R c = rfma(a[kp], a[kp], a[kq] * a[kq]) + x[s];
+        F = rfma(R(0.5) * R(d.rtil) * c, c, rfma(R(d.ltil[e]), c, F));
+        me[e] = rfma(R(d.rtil), c, R(d.ltil[e]));
+        R tm = R(2.0) * me[e];
+        mu[kp] = rfma(tm, a[kp], mu[kp]);
+        mu[kq] = rfma(tm, a[kq], mu[kq]);
+        nu[kp] = nu[kp] + tm;
+        nu[kq] = nu[kq] + tm;
+        for (int p = 0; p < 4; ++p)
+          gc[e][p] = R(2.0) * rfma(a[kp], ga[kp][p], a[kq] * ga[kq][p]);
+      }
+    }
+    R MR = rfma(mu[3], W.cR[3], rfma(mu[2], W.cR[2], rfma(mu[1], W.cR[1], mu[0] * W.cR[0])));
+    R MI = rfma(mu[3], W.cI[3], rfma(mu[2], W.cI[2], rfma(mu[1], W.cI[1], mu[0] * W.cI[0])));
+    R Oi = rfma(mu[1], W.cw[1], mu[0] * W.cw[0]);
+    R Oj = rfma(mu[3], W.cw[3], mu[2] * W.cw[2]);
     for (int i = 0; i < n; ++i) {
       g[i] = R(0.0);
       for (int j = 0; j < n; ++j) H[i * n + j] = R(0.0);
     }
-    // the four flow couplings
-    for (int k = 0; k < 4; ++k) {
-      R r = a[k] - R(d.vb[k]) + R(d.z[k]);
-      F = rfma(R(0.5) * R(d.rho[k]) * r, r, rfma(R(d.y[k]), r, F));
-      R m = rfma(R(d.rho[k]), r, R(d.y[k]));
-      for (int p = 0; p < 4; ++p) g[p] = rfma(m, ga[k][p], g[p]);
-      for (int t = 0; t < 10; ++t) {
-        int p = UT_P[t], q = UT_Q[t];
-        H[p * n + q] = rfma(m, Ha[k][t], rfma(R(d.rho[k]) * ga[k][p], ga[k][q], H[p * n + q]));
+    for (int p = 0; p < 4; ++p) g[p] = rfma(MI, W.dWI[p], MR * W.dWR[p]);
+    g[0] = rfma(R(2.0) * x[0], Oi, g[0]);
+    g[1] = rfma(R(2.0) * x[1], Oj, g[1]);
+    // Hessian block over (v_i, v_j, theta_i, theta_j), upper triangle
+    R ng[4][4];
+    for (int k = 0; k < 4; ++k)
+      for (int p = 0; p < 4; ++p) ng[k][p] = nu[k] * ga[k][p];
+    R rg[2][4];
+    if (n == 6)
+      for (int e = 0; e < 2; ++e)
+        for (int p = 0; p < 4; ++p) rg[e][p] = R(d.rtil) * gc[e][p];
+    for (int t = 0; t < 10; ++t) {
+      int p = UT_P[t], q = UT_Q[t];
+      R h;
+      if (t == 0) h = R(2.0) * Oi;          // d2 w_i / dv_i^2 = 2
+      else if (t == 4) h = R(2.0) * Oj;     // d2 w_j / dv_j^2 = 2
+      else h = rfma(MI, W.hWI[t], MR * W.hWR[t]);
+      for (int k = 0; k < 4; ++k) h = rfma(ng[k][p], ga[k][q], h);
+      if (n == 6)
+        for (int e = 0; e < 2; ++e) h = rfma(rg[e][p], gc[e][q], h);
+      H[p * n + q] = h;
+    }
+    if (n == 6) {
+      for (int e = 0; e < 2; ++e) {
+        int s = 4 + e;
+        g[s] = me[e];
+        for (int p = 0; p < 4; ++p) H[p * 6 + s] = rg[e][p];
+        H[s * 6 + s] = R(d.rtil);
       }
     }
-    // w_i = v_i^2 (variable 0), theta_i (2), w_j = v_j^2 (1), theta_j (3)
-    const int var[4] = {0, 2, 1, 3};
+    // the w and theta couplings act on single variables
     for (int k = 4; k < 8; ++k) {
       int p = var[k - 4];
-      R r = a[k] - R(d.vb[k]) + R(d.z[k]);
-      F = rfma(R(0.5) * R(d.rho[k]) * r, r, rfma(R(d.y[k]), r, F));
-      R m = rfma(R(d.rho[k]), r, R(d.y[k]));
+      R m = mv[k - 4];
       if (k == 4 || k == 6) {  // d(v^2)/dv = 2v, d2(v^2)/dv2 = 2
         R gv = R(2.0) * x[p];
         g[p] = rfma(m, gv, g[p]);
@@ -665,29 +736,6 @@ struct BranchProblem {
       } else {  // angle copy: gradient 1, no curvature
         g[p] = g[p] + m;
         H[p * n + p] = H[p * n + p] + R(d.rho[k]);
-      }
-    }
-    // augmented Lagrangian on the line limits (eq. branch, last two lines)
-    if (n == 6) {
-      for (int e = 0; e < 2; ++e) {
-        int kp = 2 * e, kq = 2 * e + 1, s = 4 + e;
-        R c = rfma(a[kp], a[kp], a[kq] * a[kq]) + x[s];
-        F = rfma(R(0.5) * R(d.rtil) * c, c, rfma(R(d.ltil[e]), c, F));
-        R m = rfma(R(d.rtil), c, R(d.ltil[e]));
-        R gc[4];
-        for (int p = 0; p < 4; ++p)
-          gc[p] = R(2.0) * rfma(a[kp], ga[kp][p], a[kq] * ga[kq][p]);
-        for (int p = 0; p < 4; ++p) g[p] = rfma(m, gc[p], g[p]);
-        g[s] = g[s] + m;
-        for (int t = 0; t < 10; ++t) {
-          int p = UT_P[t], q = UT_Q[t];
-          R hc = R(2.0) * rfma(a[kq], Ha[kq][t],
-                               rfma(ga[kq][p], ga[kq][q],
-                                    rfma(a[kp], Ha[kp][t], ga[kp][p] * ga[kp][q])));
-          H[p * 6 + q] = rfma(m, hc, rfma(R(d.rtil) * gc[p], gc[q], H[p * 6 + q]));
-        }
-        for (int p = 0; p < 4; ++p) H[p * 6 + s] = rfma(R(d.rtil), gc[p], H[p * 6 + s]);
-        H[s * 6 + s] = H[s * 6 + s] + R(d.rtil);
       }
     }
     for (int p = 0; p < n; ++p)

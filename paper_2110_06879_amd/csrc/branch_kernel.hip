@@ -183,6 +183,14 @@ __device__ double fval(const BranchIn<N>& B, const double* x, Counters& cnt) {
 __device__ constexpr int kUP[10] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
 __device__ constexpr int kUQ[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
 
+// F, gradient and Hessian by the chain rule through the coupling values.
+// m_k = y_k + rho_k r_k for every coupling and, on rated branches,
+// m_e = ltil_e + rtil c_e for the line limit at end e. The flow terms are
+// gathered per flow k (at end e) as mu_k = m_k + 2 m_e a_k (gradient and
+// curvature weight) and nu_k = rho_k + 2 m_e (weight of grad a_k grad a_k').
+// Every flow is linear in (w_own, w^R, w^I), so sum_k mu_k grad a_k and
+// sum_k mu_k hess a_k reduce to MR, MI times the derivatives of w^R, w^I plus
+// the w_own terms O_i, O_j. F is accumulated in the order of fval.
 template <int N>
 __device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
                     double* g, Sym<N>& H, Counters& cnt) {
@@ -199,7 +207,7 @@ __device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
   const double cw[4] = {B.gii, -B.bii, B.gjj, -B.bjj};
   const double cR[4] = {B.gij, -B.bij, B.gji, -B.bji};
   const double cI[4] = {B.bij, B.gij, -B.bji, -B.gji};
-  double ga[4][4], Ha[4][10];
+  double ga[4][4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int own = k < 2 ? 0 : 1;
@@ -208,55 +216,28 @@ __device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
     for (int p = 0; p < 4; ++p)
       ga[k][p] = p == own ? fma(cI[k], dWI[p], fma(cR[k], dWR[p], cw[k] * tw))
                           : fma(cI[k], dWI[p], cR[k] * dWR[p]);
-#pragma unroll
-    for (int t = 0; t < 10; ++t) {
-      if (t == 0 || t == 4)
-        Ha[k][t] = ((t == 0) == (own == 0)) ? 2.0 * cw[k] : 0.0;
-      else
-        Ha[k][t] = fma(cI[k], hWI[t], cR[k] * hWR[t]);
-    }
   }
-  FL(162);
+  FL(62);
   F = 0.0;
-#pragma unroll
-  for (int i = 0; i < N; ++i) g[i] = 0.0;
-#pragma unroll
-  for (int q = 0; q < N * (N + 1) / 2; ++q) H.t[q] = 0.0;
+  double mu[4], nu[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const double rk = B.rho(k);
     const double r = (a[k] - B.vb[k]) + B.zc[k];
     F = fma(0.5 * rk * r, r, fma(B.yc[k], r, F));
-    const double m = fma(rk, r, B.yc[k]);
-#pragma unroll
-    for (int p = 0; p < 4; ++p) g[p] = fma(m, ga[k][p], g[p]);
-#pragma unroll
-    for (int t = 0; t < 10; ++t) {
-      const int p = kUP[t], q = kUQ[t];
-      H(p, q) = fma(m, Ha[k][t], fma(rk * ga[k][p], ga[k][q], H(p, q)));
-    }
+    mu[k] = fma(rk, r, B.yc[k]);
+    nu[k] = rk;
   }
-  FL(272);
-  {  // voltage-magnitude and angle couplings: w_i, th_i, w_j, th_j
-    const int var[4] = {0, 2, 1, 3};
+  double mv[4];  // voltage-magnitude and angle couplings: w_i, th_i, w_j, th_j
 #pragma unroll
-    for (int k = 4; k < 8; ++k) {
-      const int p = var[k - 4];
-      const double rk = B.rva;
-      const double r = (a[k] - B.vb[k]) + B.zc[k];
-      F = fma(0.5 * rk * r, r, fma(B.yc[k], r, F));
-      const double m = fma(rk, r, B.yc[k]);
-      if (k == 4 || k == 6) {
-        const double gv = 2.0 * x[p];
-        g[p] = fma(m, gv, g[p]);
-        H(p, p) = fma(m, 2.0, fma(rk * gv, gv, H(p, p)));
-      } else {
-        g[p] = g[p] + m;
-        H(p, p) = H(p, p) + rk;
-      }
-    }
-    FL(60);
+  for (int k = 4; k < 8; ++k) {
+    const double rk = B.rva;
+    const double r = (a[k] - B.vb[k]) + B.zc[k];
+    F = fma(0.5 * rk * r, r, fma(B.yc[k], r, F));
+    mv[k - 4] = fma(rk, r, B.yc[k]);
   }
+  FL(80);
+  double gc[2][4], me[2];
   if (N == 6) {
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -264,26 +245,86 @@ __device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
       const double lt = e == 0 ? B.lt0 : B.lt1;
       const double c = fma(a[kp], a[kp], a[kq] * a[kq]) + x[s];
       F = fma(0.5 * B.rt * c, c, fma(lt, c, F));
-      const double m = fma(B.rt, c, lt);
-      double gc[4];
+      me[e] = fma(B.rt, c, lt);
+      const double tm = 2.0 * me[e];
+      mu[kp] = fma(tm, a[kp], mu[kp]);
+      mu[kq] = fma(tm, a[kq], mu[kq]);
+      nu[kp] = nu[kp] + tm;
+      nu[kq] = nu[kq] + tm;
 #pragma unroll
-      for (int p = 0; p < 4; ++p) gc[p] = 2.0 * fma(a[kp], ga[kp][p], a[kq] * ga[kq][p]);
-#pragma unroll
-      for (int p = 0; p < 4; ++p) g[p] = fma(m, gc[p], g[p]);
-      g[s] = g[s] + m;
-#pragma unroll
-      for (int t = 0; t < 10; ++t) {
-        const int p = kUP[t], q = kUQ[t];
-        const double hc = 2.0 * fma(a[kq], Ha[kq][t],
-                                    fma(ga[kq][p], ga[kq][q],
-                                        fma(a[kp], Ha[kp][t], ga[kp][p] * ga[kp][q])));
-        H(p, q) = fma(m, hc, fma(B.rt * gc[p], gc[q], H(p, q)));
-      }
-#pragma unroll
-      for (int p = 0; p < 4; ++p) H(p, s) = fma(B.rt, gc[p], H(p, s));
-      H(s, s) = H(s, s) + B.rt;
+      for (int p = 0; p < 4; ++p) gc[e][p] = 2.0 * fma(a[kp], ga[kp][p], a[kq] * ga[kq][p]);
     }
-    FL(352);
+    FL(70);
+  }
+  const double MR = fma(mu[3], cR[3], fma(mu[2], cR[2], fma(mu[1], cR[1], mu[0] * cR[0])));
+  const double MI = fma(mu[3], cI[3], fma(mu[2], cI[2], fma(mu[1], cI[1], mu[0] * cI[0])));
+  const double Oi = fma(mu[1], cw[1], mu[0] * cw[0]);
+  const double Oj = fma(mu[3], cw[3], mu[2] * cw[2]);
+#pragma unroll
+  for (int p = 0; p < 4; ++p) g[p] = fma(MI, dWI[p], MR * dWR[p]);
+  g[0] = fma(2.0 * x[0], Oi, g[0]);
+  g[1] = fma(2.0 * x[1], Oj, g[1]);
+  double ng[4][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) ng[k][p] = nu[k] * ga[k][p];
+  FL(54);
+  double rg[2][4];
+  if (N == 6) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) rg[e][p] = B.rt * gc[e][p];
+    FL(8);
+  }
+#pragma unroll
+  for (int t = 0; t < 10; ++t) {
+    const int p = kUP[t], q = kUQ[t];
+    double h;
+    if (t == 0)
+      h = 2.0 * Oi;
+    else if (t == 4)
+      h = 2.0 * Oj;
+    else
+      h = fma(MI, hWI[t], MR * hWR[t]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) h = fma(ng[k][p], ga[k][q], h);
+    if (N == 6) {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) h = fma(rg[e][p], gc[e][q], h);
+    }
+    H(p, q) = h;
+  }
+  FL(106);
+  if (N == 6) {
+    FL(40);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int s = 4 + e;
+      g[s] = me[e];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) H(p, s) = rg[e][p];
+      H(s, s) = B.rt;
+    }
+    H(4, 5) = 0.0;
+  }
+  {
+    const int var[4] = {0, 2, 1, 3};
+#pragma unroll
+    for (int k = 4; k < 8; ++k) {
+      const int p = var[k - 4];
+      const double m = mv[k - 4];
+      if (k == 4 || k == 6) {
+        const double gv = 2.0 * x[p];
+        g[p] = fma(m, gv, g[p]);
+        H(p, p) = fma(m, 2.0, fma(B.rva * gv, gv, H(p, p)));
+      } else {
+        g[p] = g[p] + m;
+        H(p, p) = H(p, p) + B.rva;
+      }
+    }
+    FL(20);
   }
   ++cnt.n_fgh;
 }
@@ -410,15 +451,15 @@ __device__ void cauchy(const double* x, const double* g, const Sym<N>& H,
 }
 
 // Preconditioner application on the free variables (mask fr):
-// z = D L^-T E^-1 L^-1 D r with L unit lower and the reciprocal pivots
-// rd = 1/E; counted as 2 nf^2 + nf.
+// z = L^-T E^-1 L^-1 r with L unit lower and the reciprocal pivots rd = 1/E;
+// counted as 2 nf^2 - nf.
 template <int N>
-__device__ inline void precond(const Sym<N>& L, const double* rd, const double* D,
-                               const bool* fr, const double* r, double* z) {
+__device__ inline void precond(const Sym<N>& L, const double* rd, const bool* fr,
+                               const double* r, double* z) {
   double t[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    double a = D[i] * r[i];
+    double a = r[i];
 #pragma unroll
     for (int k = 0; k < i; ++k) a = fma(-L(i, k), t[k], a);
     t[i] = fr[i] ? a : 0.0;
@@ -432,19 +473,17 @@ __device__ inline void precond(const Sym<N>& L, const double* rd, const double* 
     for (int k = i + 1; k < N; ++k) a = fma(-L(k, i), z[k], a);
     z[i] = fr[i] ? a : 0.0;
   }
-#pragma unroll
-  for (int i = 0; i < N; ++i) z[i] = D[i] * z[i];
 }
 
 // Square-root-free Cholesky factorization L E L' (L unit lower, E diagonal)
-// of the scaled, shifted free Hessian D H D + shift I (fixed rows/columns act
-// as identity), formed element by element as the factorization needs it.
+// of the shifted free Hessian H + shift diag(Sd) (fixed rows/columns act as
+// identity), formed element by element as the factorization needs it.
 // Column j: v_k = L_jk e_k, pivot e_j = a_jj - sum_k L_jk v_k, and
 // L_ij = (a_ij - sum_k L_ik v_k) times the reciprocal pivot, which is kept in
 // rd for the solves. Returns false at the first non-positive free pivot;
 // flops are counted as on the compressed nf x nf matrix.
 template <int N>
-__device__ inline bool ldlt(const Sym<N>& H, const double* D, double shift,
+__device__ inline bool ldlt(const Sym<N>& H, const double* Sd, double shift,
                             const bool* fr, int nf, Sym<N>& L, double* rd,
                             Counters& cnt) {
 #pragma unroll
@@ -462,7 +501,7 @@ __device__ inline bool ldlt(const Sym<N>& H, const double* D, double shift,
     double v[N];
 #pragma unroll
     for (int k = 0; k < j; ++k) v[k] = L(j, k) * e[k];
-    double d = D[j] * H(j, j) * D[j] + shift;
+    double d = fma(shift, Sd[j], H(j, j));
 #pragma unroll
     for (int k = 0; k < j; ++k) d = fma(-L(j, k), v[k], d);
     FL(3 * jc);
@@ -473,7 +512,7 @@ __device__ inline bool ldlt(const Sym<N>& H, const double* D, double shift,
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {
       if (!fr[i]) continue;
-      double t = D[i] * H(i, j) * D[j];
+      double t = H(i, j);
 #pragma unroll
       for (int k = 0; k < j; ++k) t = fma(-L(i, k), v[k], t);
       L(i, j) = t * rj;
@@ -517,26 +556,21 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
     const double rr0 = dotN<N>(r, r);  // squared norm of the initial residual
     FL(2 * nf);
     if (!(rr0 > 0.0)) break;
-    double D[N];
+    // Lin & More's scaled matrix D H D + shift I, D = diag(|H_ii|^(-1/2)),
+    // gives the preconditioner H + shift D^-2; it is factored in that form,
+    // H + shift Sd with Sd = |H_ii| (1 where H_ii = 0). The scaled diagonal
+    // entries are the signs of H_ii; their minimum sets the shift.
+    double Sd[N];
     double mind = 1.0 / 0.0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      D[i] = 1.0;
+      const double b = H(i, i);
+      Sd[i] = b == 0.0 ? 1.0 : fabs(b);
       if (fr[i]) {
-        const double b = fabs(H(i, i));
-        if (b > 0.0) {
-          D[i] = 1.0 / sqrt(b);
-          FL(2);
-        }
+        const double sgn = b > 0.0 ? 1.0 : (b < 0.0 ? -1.0 : 0.0);
+        mind = sgn < mind ? sgn : mind;
       }
     }
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-      if (fr[i]) {
-        const double aii = D[i] * H(i, i) * D[i];
-        mind = aii < mind ? aii : mind;
-      }
-    FL(2 * nf * nf);
     double shift = 0.0;
     if (!(mind > 0.0)) {
       shift = kShiftMin - mind;
@@ -546,9 +580,9 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
     double rd[N];
     bool ok = false;
     for (int att = 0; att < kMaxChol; ++att) {
-      FL(nf);
+      FL(2 * nf);
       ++cnt.chol;
-      if (ldlt<N>(H, D, shift, fr, nf, L, rd, cnt)) {
+      if (ldlt<N>(H, Sd, shift, fr, nf, L, rd, cnt)) {
         ok = true;
         break;
       }
@@ -558,7 +592,6 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
     if (!ok) {
 #pragma unroll
       for (int i = 0; i < N; ++i) {
-        D[i] = 1.0;
         rd[i] = 1.0;
 #pragma unroll
         for (int j = 0; j <= i; ++j) L(i, j) = i == j ? 1.0 : 0.0;
@@ -571,8 +604,8 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       d[i] = 0.0;
       res[i] = r[i];
     }
-    precond<N>(L, rd, D, fr, res, zz);
-    FL(2 * nf * nf + nf);
+    precond<N>(L, rd, fr, res, zz);
+    FL(2 * nf * nf - nf);
 #pragma unroll
     for (int i = 0; i < N; ++i) p[i] = zz[i];
     double rz = dotN<N>(res, zz);
@@ -623,13 +656,13 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       const double rr = dotN<N>(res, res);  // ||r|| <= tol ||r0||, in squares
       FL(4 * nf + 2 * nf + 1);
       if (rr <= (kCgTol * kCgTol) * rr0) break;
-      precond<N>(L, rd, D, fr, res, zz);
+      precond<N>(L, rd, fr, res, zz);
       const double rzn = dotN<N>(res, zz);
       const double bcg = rzn / rz;
       rz = rzn;
 #pragma unroll
       for (int i = 0; i < N; ++i) p[i] = fma(bcg, p[i], zz[i]);
-      FL(2 * nf * nf + nf + 2 * nf + 1 + 2 * nf);
+      FL(2 * nf * nf - nf + 2 * nf + 1 + 2 * nf);
     }
     // projected search along d from w
     const double qw = model<N>(g, H, s, cnt);
