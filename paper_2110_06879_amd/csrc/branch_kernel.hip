@@ -38,6 +38,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.h"
 
@@ -56,10 +57,21 @@ constexpr double kCgTol = 0.1;
 constexpr double kShiftMin = 1e-3;
 constexpr int kMaxChol = 20;
 
-struct Counters {
-  uint32_t flops, trig;  // per branch solve: far below 2^32
-  uint32_t tron_calls, tron_iters, n_fgh, n_f, cauchy, cg, chol, ps, al,
-      conv, maxit, stall;
+// A counter that counts nothing: the uncounted kernels use it in place of
+// uint32_t, so that no counting arithmetic is left in their code.
+struct NoTally {
+  __device__ NoTally& operator+=(uint32_t) { return *this; }
+  __device__ NoTally& operator++() { return *this; }
+  __device__ NoTally& operator=(uint32_t) { return *this; }
+  __device__ operator uint32_t() const { return 0u; }
+};
+
+// Per-lane event and flop counters; CountersT<false> holds NoTally members.
+template <bool kOn>
+struct CountersT {
+  using T = typename std::conditional<kOn, uint32_t, NoTally>::type;
+  T flops, trig;  // per branch solve: far below 2^32
+  T tron_calls, tron_iters, n_fgh, n_f, cauchy, cg, chol, ps, al, conv, maxit, stall;
 };
 
 #define FL(n) (cnt.flops += (uint32_t)(n))
@@ -131,9 +143,9 @@ __device__ inline double clampd(double t, double lo, double hi) {
 }
 
 // Flows and coupling values a_k(x); aux = (cos, sin, w^R, w^I).
-template <int N>
+template <int N, class Cnt>
 __device__ inline void values(const BranchIn<N>& B, const double* x, double* a,
-                              double* aux, Counters& cnt) {
+                              double* aux, Cnt& cnt) {
   const double vi = x[0], vj = x[1], ti = x[2], tj = x[3];
   const double dt = ti - tj;
   double sn, cs;
@@ -157,8 +169,8 @@ __device__ inline void values(const BranchIn<N>& B, const double* x, double* a,
   cnt.trig += 2;
 }
 
-template <int N>
-__device__ double fval(const BranchIn<N>& B, const double* x, Counters& cnt) {
+template <int N, class Cnt>
+__device__ double fval(const BranchIn<N>& B, const double* x, Cnt& cnt) {
   double a[8], aux[4];
   values<N>(B, x, a, aux, cnt);
   double F = 0.0;
@@ -191,9 +203,9 @@ __device__ constexpr int kUQ[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
 // Every flow is linear in (w_own, w^R, w^I), so sum_k mu_k grad a_k and
 // sum_k mu_k hess a_k reduce to MR, MI times the derivatives of w^R, w^I plus
 // the w_own terms O_i, O_j. F is accumulated in the order of fval.
-template <int N>
+template <int N, class Cnt>
 __device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
-                    double* g, Sym<N>& H, Counters& cnt) {
+                    double* g, Sym<N>& H, Cnt& cnt) {
   double a[8], aux[4];
   values<N>(B, x, a, aux, cnt);
   const double vi = x[0], vj = x[1];
@@ -338,9 +350,9 @@ __device__ inline double dotN(const double* a, const double* b) {
 }
 
 // q(s) = g's + 1/2 s'Hs ; counted as 2N^2 + 4N + 2
-template <int N>
+template <int N, class Cnt>
 __device__ inline double model(const double* g, const Sym<N>& H, const double* s,
-                               Counters& cnt) {
+                               Cnt& cnt) {
   double gs = 0.0, sHs = 0.0;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
@@ -355,9 +367,9 @@ __device__ inline double model(const double* g, const Sym<N>& H, const double* s
 }
 
 // tau >= 0 with ||a + tau p|| = delta
-template <int N>
+template <int N, class Cnt>
 __device__ inline double to_boundary(const double* a, const double* p, double delta,
-                                     Counters& cnt) {
+                                     Cnt& cnt) {
   const double ap = dotN<N>(a, p), pp = dotN<N>(p, p), aa = dotN<N>(a, a);
   double dd = delta * delta - aa;
   if (dd < 0.0) dd = 0.0;
@@ -382,9 +394,9 @@ __device__ inline double to_boundary(const double* a, const double* p, double de
 }
 
 // Cauchy-search acceptance: ||s|| <= delta and q(s) <= mu0 g's.
-template <int N>
+template <int N, class Cnt>
 __device__ inline bool cauchy_ok(const double* g, const Sym<N>& H, const double* s,
-                                 double delta, Counters& cnt) {
+                                 double delta, Cnt& cnt) {
   const double ss = dotN<N>(s, s);  // ||s|| <= delta, compared in squares
   FL(2 * N + 1);
   if (ss > delta * delta) return false;
@@ -394,10 +406,10 @@ __device__ inline bool cauchy_ok(const double* g, const Sym<N>& H, const double*
   return q <= kMu0 * gts;
 }
 
-template <int N>
+template <int N, class Cnt>
 __device__ inline void cauchy_trial(const double* x, const double* g, const double* lo,
                                     const double* hi, double a, double* w, double* s,
-                                    Counters& cnt) {
+                                    Cnt& cnt) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     w[i] = clampd(fma(-a, g[i], x[i]), lo[i], hi[i]);
@@ -406,10 +418,10 @@ __device__ inline void cauchy_trial(const double* x, const double* g, const doub
   FL(3 * N);
 }
 
-template <int N>
+template <int N, class Cnt>
 __device__ void cauchy(const double* x, const double* g, const Sym<N>& H,
                        const double* lo, const double* hi, double delta,
-                       double& alpha, double* w, Counters& cnt) {
+                       double& alpha, double* w, Cnt& cnt) {
   double brpt = 0.0;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
@@ -482,10 +494,10 @@ __device__ inline void precond(const Sym<N>& L, const double* rd, const bool* fr
 // L_ij = (a_ij - sum_k L_ik v_k) times the reciprocal pivot, which is kept in
 // rd for the solves. Returns false at the first non-positive free pivot;
 // flops are counted as on the compressed nf x nf matrix.
-template <int N>
+template <int N, class Cnt>
 __device__ inline bool ldlt(const Sym<N>& H, const double* Sd, double shift,
                             const bool* fr, int nf, Sym<N>& L, double* rd,
-                            Counters& cnt) {
+                            Cnt& cnt) {
 #pragma unroll
   for (int q = 0; q < N * (N + 1) / 2; ++q) L.t[q] = 0.0;
   double e[N];
@@ -526,10 +538,10 @@ __device__ inline bool ldlt(const Sym<N>& H, const double* Sd, double shift,
 // Subspace steps from the Cauchy point w (in/out), Lin & More Sec. 4:
 // Steihaug PCG on the free variables, projected search, repeat while a new
 // bound becomes active and CG ended inside the trust region.
-template <int N>
+template <int N, class Cnt>
 __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
                          const double* lo, const double* hi, double delta,
-                         double* w, Counters& cnt) {
+                         double* w, Cnt& cnt) {
   double s[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) s[i] = w[i] - x[i];
@@ -707,9 +719,9 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
 
 enum { kConv = 0, kMaxit = 1, kStall = 2 };
 
-template <int N>
+template <int N, class Cnt>
 __device__ int tron(const BranchIn<N>& B, double* x, const double* lo, const double* hi,
-                    double gtol, double ftol, int maxit, double& alphac, Counters& cnt) {
+                    double gtol, double ftol, int maxit, double& alphac, Cnt& cnt) {
   ++cnt.tron_calls;
 #pragma unroll
   for (int i = 0; i < N; ++i) x[i] = clampd(x[i], lo[i], hi[i]);
@@ -812,9 +824,9 @@ struct TronState {
   bool eval, first;
 };
 
-template <int N>
+template <int N, class Cnt>
 __device__ inline void tron_begin(TronState<N>& S, const double* lo, const double* hi,
-                                  Counters& cnt) {
+                                  Cnt& cnt) {
   ++cnt.tron_calls;
 #pragma unroll
   for (int i = 0; i < N; ++i) S.x[i] = clampd(S.x[i], lo[i], hi[i]);
@@ -826,10 +838,10 @@ __device__ inline void tron_begin(TronState<N>& S, const double* lo, const doubl
 }
 
 // Returns true when the solve has ended (S.status is then set).
-template <int N>
+template <int N, class Cnt>
 __device__ bool tron_advance(TronState<N>& S, const BranchIn<N>& B, const double* lo,
                              const double* hi, double gtol, double ftol, int maxit,
-                             Counters& cnt) {
+                             Cnt& cnt) {
   if (S.eval) {
     fgh<N>(B, S.x, S.f, S.g, S.H, cnt);
     S.eval = false;
@@ -923,8 +935,8 @@ __device__ bool tron_advance(TronState<N>& S, const BranchIn<N>& B, const double
 #undef FL
 
 // Branch l of the device order with N variables: solve, write u and state.
-template <int N>
-__device__ void solve_branch(const BranchArgs& A, int64_t l, int grid, Counters& cnt) {
+template <int N, class Cnt>
+__device__ void solve_branch(const BranchArgs& A, int64_t l, int grid, Cnt& cnt) {
   {
     const int64_t nl = A.nl;
     BranchIn<N> B;
@@ -1104,9 +1116,9 @@ __device__ inline void load_branch(const BranchArgs& A, int64_t l, BranchIn<N>& 
 // when it ends, takes the next branch index from the pool counter (one atomic
 // per wavefront per trip). The loop ends when the pool is exhausted and every
 // lane of the wavefront has finished.
-template <int N>
+template <int N, class Cnt>
 __device__ void run_pool(const BranchArgs& A, int64_t begin, int64_t end, unsigned* ctr,
-                         Counters& cnt, uint32_t& solves, uint64_t& flops) {
+                         Cnt& cnt, uint32_t& solves, uint64_t& flops) {
   const int lane = threadIdx.x & 63;
   enum { kFetch = 0, kRun = 1, kDone = 2 };
   int phase = kFetch;
@@ -1209,7 +1221,7 @@ __device__ void run_pool(const BranchArgs& A, int64_t begin, int64_t end, unsign
 // and the compiler drops their arithmetic.
 template <bool kStats>
 __global__ __launch_bounds__(64) void xstep_persistent_kernel(BranchArgs A, int64_t n6) {
-  Counters cnt = {};
+  CountersT<kStats> cnt = {};
   uint32_t solves = 0;
   uint64_t flops = 0;
   run_pool<6>(A, 0, n6, &A.pool[0], cnt, solves, flops);
@@ -1269,7 +1281,7 @@ void launch_xstep_persistent(const BranchArgs& A, int64_t n6, int blocks, bool s
 template <bool kStats>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ACOPF_XSTEP_WAVES_PER_EU)))
 void xstep_kernel(BranchArgs A, int64_t n6, int bg, int b6, int b4, int k4) {
-  Counters cnt = {};
+  CountersT<kStats> cnt = {};
   uint32_t solves = 0;
   const int b = blockIdx.x;
   const int bs = blockDim.x;
