@@ -935,10 +935,15 @@ __device__ bool tron_advance(TronState<N>& S, const BranchIn<N>& B, const double
 #undef FL
 
 // Branch l of the device order with N variables: solve, write u and state.
+// Every input load is issued before the grid's done flag is tested, so that
+// the lane waits for two rounds of memory accesses (branch data and end
+// positions, then the gathered coupling values and the flag) before it
+// computes. Returns false, without solving, when the grid has finished.
 template <int N, class Cnt>
-__device__ void solve_branch(const BranchArgs& A, int64_t l, int grid, Cnt& cnt) {
+__device__ bool solve_branch(const BranchArgs& A, int64_t l, Cnt& cnt) {
   {
     const int64_t nl = A.nl;
+    const int grid = A.br_grid[l];
     BranchIn<N> B;
     B.gii = A.adm[0 * nl + l];
     B.bii = A.adm[1 * nl + l];
@@ -991,14 +996,17 @@ __device__ void solve_branch(const BranchArgs& A, int64_t l, int grid, Cnt& cnt)
     B.lt1 = 0.0;
     B.rt = 0.0;
     double alphac = A.calpha[l];
+    if (N == 6) {
+      B.lt0 = A.ltil[l];
+      B.lt1 = A.ltil[nl + l];
+      B.rt = A.rtil[l];
+    }
+    if (A.ctl[grid].done != 0) return false;
     int failures = 0;
     if (N == 4) {
       failures +=
           tron<N>(B, x, lo, hi, A.tron_gtol, A.tron_ftol, A.tron_maxit, alphac, cnt) != kConv;
     } else {
-      B.lt0 = A.ltil[l];
-      B.lt1 = A.ltil[nl + l];
-      B.rt = A.rtil[l];
       double cprev = 1.0 / 0.0;
       for (int t = 0; t < A.al_maxit; ++t) {
         ++cnt.al;
@@ -1034,6 +1042,7 @@ __device__ void solve_branch(const BranchArgs& A, int64_t l, int grid, Cnt& cnt)
     A.calpha[l] = alphac;
     if (failures) atomicAdd(&A.failures[grid], failures);
   }
+  return true;
 }
 
 // eq. (qp-bound) for generator g: p and q are couplings g and n_gen + g.
@@ -1292,24 +1301,14 @@ void xstep_kernel(BranchArgs A, int64_t n6, int bg, int b6, int b4, int k4) {
   }
   if (b < bg + b6) {
     const int64_t l = (int64_t)(b - bg) * bs + threadIdx.x;
-    if (l < n6) {
-      const int grid = A.br_grid[l];
-      if (A.ctl[grid].done == 0) {
-        ++solves;
-        solve_branch<6>(A, l, grid, cnt);
-      }
-    }
+    if (l < n6 && solve_branch<6>(A, l, cnt)) ++solves;
   } else {
     const int64_t base = n6 + (int64_t)(b - bg - b6) * bs + threadIdx.x;
     const int64_t stride = (int64_t)b4 * bs;
     for (int j = 0; j < k4; ++j) {
       const int64_t l = base + j * stride;
       if (l >= A.nl) break;
-      const int grid = A.br_grid[l];
-      if (A.ctl[grid].done == 0) {
-        ++solves;
-        solve_branch<4>(A, l, grid, cnt);
-      }
+      if (solve_branch<4>(A, l, cnt)) ++solves;
     }
   }
   if (!kStats) return;
