@@ -142,8 +142,9 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
   double* bv = cG + 2 * gcap;   // [4][tb]   mu0, mu1, w, theta per bus
   unsigned short* emap = reinterpret_cast<unsigned short*>(bv + 4 * tb);  // [ecap]
   unsigned short* gmap = emap + ecap;                                     // [gcap]
-  const int64_t ng = A.ng, ne = A.ne;
-  const int64_t kP = 2 * ng, kQ = kP + ne, kW = kQ + ne, kT = kW + ne;
+  const int64_t ng = A.ng;
+  // end couplings: 2 ng + 4 e + kind (kind 0 p, 1 q, 2 w, 3 theta)
+  auto ec = [&](int64_t e, int kind) { return 2 * ng + 4 * e + kind; };
   const double rpq = A.rho_pq, rva = A.rho_va;
   const int E0 = D.e0, G0 = D.g0;
   const int net = D.e1 - D.e0, ngt = D.g1 - D.g0;
@@ -165,10 +166,10 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
   }
   for (int e = tid; e < net && e < ecap; e += nt) {
     const int64_t k = E0 + e;
-    cE[0 * ecap + e] = target(kP + k, rpq);
-    cE[1 * ecap + e] = target(kQ + k, rpq);
-    cE[2 * ecap + e] = target(kW + k, rva);
-    cE[3 * ecap + e] = target(kT + k, rva);
+    cE[0 * ecap + e] = target(ec(k, 0), rpq);
+    cE[1 * ecap + e] = target(ec(k, 1), rpq);
+    cE[2 * ecap + e] = target(ec(k, 2), rva);
+    cE[3 * ecap + e] = target(ec(k, 3), rva);
   }
   for (int g = tid; g < ngt && g < gcap; g += nt) {
     cG[g] = target(G0 + g, rpq);
@@ -177,8 +178,7 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
   __syncthreads();
   auto cend = [&](int blk, int e) {
     if (e < ecap) return cE[blk * ecap + e];
-    const int64_t base = blk == 0 ? kP : blk == 1 ? kQ : blk == 2 ? kW : kT;
-    return target(base + E0 + e, blk < 2 ? rpq : rva);
+    return target(ec(E0 + e, blk), blk < 2 ? rpq : rva);
   };
   auto cgen = [&](int blk, int g) {
     if (g < gcap) return cG[blk * gcap + g];
@@ -245,10 +245,10 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
   for (int e = tid; e < net; e += nt) {
     const int b = e < ecap ? emap[e] : tile_bus_of(A.eptr, b0, nbt, E0, e);
     const int64_t k = E0 + e;
-    finish(kP + k, (cend(0, e) + bv[b]) / rpq, rpq);
-    finish(kQ + k, (cend(1, e) + bv[tb + b]) / rpq, rpq);
-    finish(kW + k, bv[2 * tb + b], rva);
-    finish(kT + k, bv[3 * tb + b], rva);
+    finish(ec(k, 0), (cend(0, e) + bv[b]) / rpq, rpq);
+    finish(ec(k, 1), (cend(1, e) + bv[tb + b]) / rpq, rpq);
+    finish(ec(k, 2), bv[2 * tb + b], rva);
+    finish(ec(k, 3), bv[3 * tb + b], rva);
   }
   // tile maxima (wavefront, then across the block's wavefronts), written to
   // the tile's own slot: no atomics, and the control kernel reduces a grid's
@@ -400,8 +400,9 @@ __global__ __launch_bounds__(kCtlBlock) void ctl_kernel(CtlArgs A) {
     update(k);
     update(A.ng + k);
   }
-  for (int64_t e = A.end_off[g] + tid; e < A.end_off[g + 1]; e += kCtlBlock)
-    for (int b = 0; b < 4; ++b) update(2 * A.ng + b * A.ne + e);
+  for (int64_t k = 2 * A.ng + 4 * A.end_off[g] + tid; k < 2 * A.ng + 4 * A.end_off[g + 1];
+       k += kCtlBlock)
+    update(k);
 }
 
 struct ColdArgs {
@@ -1663,8 +1664,7 @@ int acopf_copy_grid(acopf_handle h, int32_t src, int32_t dst) {
   for (double* v : vecs) {
     HIP_TRY(cp(v, A.gen_off, B.gen_off, A.ng));
     HIP_TRY(cp(v, ng + A.gen_off, ng + B.gen_off, A.ng));
-    for (int k = 0; k < 4; ++k)
-      HIP_TRY(cp(v, 2 * ng + k * ne + A.e0, 2 * ng + k * ne + B.e0, A.e1 - A.e0));
+    HIP_TRY(cp(v, 2 * ng + 4 * A.e0, 2 * ng + 4 * B.e0, 4 * (A.e1 - A.e0)));
   }
   for (int r = 0; r < 6; ++r) {
     HIP_TRY(cp(h->bx, r * nl + A.r6b, r * nl + B.r6b, A.r6e - A.r6b));

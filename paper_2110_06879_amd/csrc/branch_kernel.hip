@@ -1384,8 +1384,8 @@ __global__ __launch_bounds__(256) void quality_values_kernel(QualityArgs Q) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Q.nb) return;
   const int64_t e = Q.eptr[i];
-  Q.bw[i] = Q.v[2 * Q.ng + 2 * Q.ne + e];
-  Q.bt[i] = Q.v[2 * Q.ng + 3 * Q.ne + e];
+  Q.bw[i] = Q.v[end_coupling(Q.ng, Q.ne, 2, e)];
+  Q.bt[i] = Q.v[end_coupling(Q.ng, Q.ne, 3, e)];
 }
 
 __global__ __launch_bounds__(256) void quality_flow_kernel(QualityArgs Q) {

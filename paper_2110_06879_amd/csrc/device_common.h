@@ -19,12 +19,14 @@ struct GridCtl {
 };
 
 // Coupling vectors (u, v, z, y, lambda) are laid out bus-major: generator
-// p [n_gen], generator q [n_gen] (generators sorted by bus), then for the
-// 2 n_branch branch ends in bus CSR order four blocks p, q, w, theta of
-// 2 n_branch each. A branch finds its eight couplings through the positions
-// ef (from end) and et (to end) of its two ends.
+// p [n_gen], generator q [n_gen] (generators sorted by bus), then the
+// 2 n_branch branch ends in bus CSR order, four consecutive couplings per
+// end (p, q, w, theta), so that the couplings of one end share 32 bytes of
+// each vector. A branch finds its eight couplings through the positions ef
+// (from end) and et (to end) of its two ends.
 __host__ __device__ inline int64_t end_coupling(int64_t ng, int64_t ne, int kind, int64_t e) {
-  return 2 * ng + (int64_t)kind * ne + e;  // kind 0 p, 1 q, 2 w, 3 theta
+  (void)ne;
+  return 2 * ng + 4 * e + kind;  // kind 0 p, 1 q, 2 w, 3 theta
 }
 
 struct BranchArgs {
