@@ -182,9 +182,9 @@ struct TronConst {
 
 template <class R>
 inline R clampd(R t, double lo, double hi) {
-  if (t < R(lo)) return R(lo);
-  if (t > R(hi)) return R(hi);
-  return t;
+  // projection onto [lo, hi] (lo <= hi), as fmin(fmax(t, lo), hi): the same
+  // value as comparing with the bounds; a NaN t gives lo
+  return R(std::fmin(std::fmax(val(t), lo), hi));
 }
 
 // q(s) = g's + 1/2 s'Hs

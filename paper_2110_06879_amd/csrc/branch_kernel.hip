@@ -138,8 +138,10 @@ __device__ inline void series_sincos(double x, double* s, double* c) {
   *c = q == 0 ? cv[0] : q == 1 ? cv[1] : q == 2 ? cv[2] : cv[3];
 }
 
+// Projection onto [lo, hi] (lo <= hi) as max then min: two instructions.
+// A NaN t gives lo, as in the oracle.
 __device__ inline double clampd(double t, double lo, double hi) {
-  return t < lo ? lo : (t > hi ? hi : t);
+  return fmin(fmax(t, lo), hi);
 }
 
 // Flows and coupling values a_k(x); aux = (cos, sin, w^R, w^I).
@@ -422,23 +424,26 @@ template <int N, class Cnt>
 __device__ void cauchy(const double* x, const double* g, const Sym<N>& H,
                        const double* lo, const double* hi, double delta,
                        double& alpha, double* w, Cnt& cnt) {
-  double brpt = 0.0;
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    double bp = 0.0;
-    if (g[i] > 0.0) {
-      bp = (x[i] - lo[i]) / g[i];
-      FL(2);
-    } else if (g[i] < 0.0) {
-      bp = (x[i] - hi[i]) / g[i];
-      FL(2);
-    }
-    brpt = brpt < bp ? bp : brpt;
-  }
+  // The largest breakpoint of the projected path is only needed to stop an
+  // extrapolation, so it is formed on that branch; the other branch counts
+  // its flops all the same, as the algorithm forms it before the first trial.
   double s[N], wt[N], st[N];
   cauchy_trial<N>(x, g, lo, hi, alpha, w, s, cnt);
   ++cnt.cauchy;
   if (cauchy_ok<N>(g, H, s, delta, cnt)) {
+    double brpt = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double bp = 0.0;
+      if (g[i] > 0.0) {
+        bp = (x[i] - lo[i]) / g[i];
+        FL(2);
+      } else if (g[i] < 0.0) {
+        bp = (x[i] - hi[i]) / g[i];
+        FL(2);
+      }
+      brpt = brpt < bp ? bp : brpt;
+    }
     // extrapolate while the conditions hold and the path still bends
     for (int t = 0; t < kMaxTrials; ++t) {
       if (alpha > brpt) break;
@@ -452,6 +457,9 @@ __device__ void cauchy(const double* x, const double* g, const Sym<N>& H,
       for (int i = 0; i < N; ++i) w[i] = wt[i];
     }
   } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (g[i] > 0.0 || g[i] < 0.0) FL(2);
     for (int t = 0; t < kMaxTrials; ++t) {
       alpha = alpha * kInterp;
       FL(1);
