@@ -633,11 +633,13 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
     bool boundary = false;
     for (int k = 0; k < nf; ++k) {
       ++cnt.cg;
+      // p is exactly zero on the fixed variables, so their columns add
+      // zeros and the free terms accumulate in the compressed order
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         double t = 0.0;
 #pragma unroll
-        for (int j = 0; j < N; ++j) t = fr[j] ? fma(H(i, j), p[j], t) : t;
+        for (int j = 0; j < N; ++j) t = fma(H(i, j), p[j], t);
         Bp[i] = fr[i] ? t : 0.0;
       }
       const double pBp = dotN<N>(p, Bp);
@@ -681,7 +683,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       const double bcg = rzn / rz;
       rz = rzn;
 #pragma unroll
-      for (int i = 0; i < N; ++i) p[i] = fma(bcg, p[i], zz[i]);
+      for (int i = 0; i < N; ++i) p[i] = fr[i] ? fma(bcg, p[i], zz[i]) : 0.0;
       FL(2 * nf * nf - nf + 2 * nf + 1 + 2 * nf);
     }
     // projected search along d from w
