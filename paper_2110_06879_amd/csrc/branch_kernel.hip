@@ -171,9 +171,11 @@ __device__ inline void values(const BranchIn<N>& B, const double* x, double* a,
   cnt.trig += 2;
 }
 
+// F alone; the coupling values and (cos, sin, w^R, w^I) at x are left in a
+// and aux for an f/g/H evaluation at the same point.
 template <int N, class Cnt>
-__device__ double fval(const BranchIn<N>& B, const double* x, Cnt& cnt) {
-  double a[8], aux[4];
+__device__ double fval(const BranchIn<N>& B, const double* x, double* a, double* aux,
+                       Cnt& cnt) {
   values<N>(B, x, a, aux, cnt);
   double F = 0.0;
 #pragma unroll
@@ -206,10 +208,8 @@ __device__ constexpr int kUQ[10] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3};
 // sum_k mu_k hess a_k reduce to MR, MI times the derivatives of w^R, w^I plus
 // the w_own terms O_i, O_j. F is accumulated in the order of fval.
 template <int N, class Cnt>
-__device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
-                    double* g, Sym<N>& H, Cnt& cnt) {
-  double a[8], aux[4];
-  values<N>(B, x, a, aux, cnt);
+__device__ void fgh_at(const BranchIn<N>& B, const double* x, const double* a,
+                       const double* aux, double& F, double* g, Sym<N>& H, Cnt& cnt) {
   const double vi = x[0], vj = x[1];
   const double cs = aux[0], sn = aux[1], WR = aux[2], WI = aux[3];
   const double jc = vj * cs, ic = vi * cs, js = vj * sn, is = vi * sn;
@@ -341,6 +341,25 @@ __device__ void fgh(const BranchIn<N>& B, const double* x, double& F,
     FL(20);
   }
   ++cnt.n_fgh;
+}
+
+// f/g/H at x. fgh_reuse does the same from the values an f evaluation at x
+// left behind, and counts the skipped evaluation of the values, which the
+// algorithm performs again.
+template <int N, class Cnt>
+__device__ void fgh(const BranchIn<N>& B, const double* x, double& F, double* g, Sym<N>& H,
+                    Cnt& cnt) {
+  double a[8], aux[4];
+  values<N>(B, x, a, aux, cnt);
+  fgh_at<N>(B, x, a, aux, F, g, H, cnt);
+}
+
+template <int N, class Cnt>
+__device__ void fgh_reuse(const BranchIn<N>& B, const double* x, const double* a,
+                          const double* aux, double& F, double* g, Sym<N>& H, Cnt& cnt) {
+  FL(26);
+  cnt.trig += 2;
+  fgh_at<N>(B, x, a, aux, F, g, H, cnt);
 }
 
 template <int N>
@@ -783,7 +802,8 @@ __device__ int tron(const BranchIn<N>& B, double* x, const double* lo, const dou
         break;
       }
     }
-    const double fw = fval<N>(B, w, cnt);
+    double aw[8], auxw[4];
+    const double fw = fval<N>(B, w, aw, auxw, cnt);
     const double actred = f - fw;
     const double ratio = actred / prered;
     FL(2);
@@ -803,7 +823,7 @@ __device__ int tron(const BranchIn<N>& B, double* x, const double* lo, const dou
     if (ratio > kEta0) {
 #pragma unroll
       for (int i = 0; i < N; ++i) x[i] = w[i];
-      fgh<N>(B, x, f, g, H, cnt);
+      fgh_reuse<N>(B, x, aw, auxw, f, g, H, cnt);
     }
     const double xx = dotN<N>(x, x);  // delta <= 1e-15 max(1, ||x||), in squares
     FL(2 * N + 2);
@@ -914,7 +934,8 @@ __device__ bool tron_advance(TronState<N>& S, const BranchIn<N>& B, const double
       return true;
     }
   }
-  const double fw = fval<N>(B, w, cnt);
+  double aw[8], auxw[4];
+  const double fw = fval<N>(B, w, aw, auxw, cnt);
   const double actred = S.f - fw;
   const double ratio = actred / prered;
   FL(2);
