@@ -70,7 +70,8 @@ constexpr int kHistCap = 1 << 15;  // per grid, inner iterations kept in history
 constexpr int kStats = 16;
 constexpr int kEvPerIter = 4;   // events per profiled iteration
 constexpr int kTimed = 3;       // kernels timed per iteration (x-step, bus, ctl)
-constexpr int kChunk = 16;      // iterations between control readbacks
+constexpr int kChunk = 16;      // iterations between control readbacks (default)
+constexpr int kMaxChunk = 64;   // largest chunk acopf_set_tuning accepts
 
 // ---------------------------------------------------------------------------
 // kernels
@@ -615,7 +616,7 @@ struct acopf_s {
   bool solved = false;
   bool profile = false;
   bool count_stats = false;  // branch kernels count flops and events (slower)
-  acopf_tuning tune{64, 256, 16, 1, 0, 0};
+  acopf_tuning tune{64, 256, kChunk, 1, 0, 0};
   hipGraphExec_t graph = nullptr;
   int graph_chunk = 0;
   std::vector<double> t_start;         // host clock at each grid's start
@@ -1692,7 +1693,7 @@ static int check_tuning(const acopf_tuning& t) {
     return fail(ACOPF_EINVAL, "xstep_block must be 64, 128 or 256");
   if (t.bus_block < 64 || t.bus_block > 1024 || t.bus_block % 64)
     return fail(ACOPF_EINVAL, "bus_block must be a multiple of 64 in [64, 1024]");
-  if (t.chunk < 1 || t.chunk > kChunk * 4) return fail(ACOPF_EINVAL, "chunk must be in [1, 64]");
+  if (t.chunk < 1 || t.chunk > kMaxChunk) return fail(ACOPF_EINVAL, "chunk must be in [1, 64]");
   if (t.xstep_waves < 0 || t.xstep_waves > 4)
     return fail(ACOPF_EINVAL, "xstep_waves must be in [0, 4]");
   if (t.xstep_per_lane < 0 || t.xstep_per_lane > 8)
@@ -1791,7 +1792,7 @@ int acopf_set_profiling(acopf_handle h, int32_t on) {
   if (!h) return fail(ACOPF_EINVAL, "null handle");
   HIP_TRY(hipSetDevice(h->device));
   if (on && h->ev.empty()) {
-    h->ev.resize((size_t)kEvPerIter * kChunk);
+    h->ev.resize((size_t)kEvPerIter * kMaxChunk);  // one set per iteration of any chunk
     for (auto& e : h->ev) HIP_TRY(hipEventCreate(&e));
   }
   h->profile = on != 0;

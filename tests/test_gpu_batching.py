@@ -45,6 +45,26 @@ def test_graph_replay_equals_plain_launches():
         assert_same(states(s1), states(s2))
 
 
+def test_profiling_with_chunks_up_to_the_maximum():
+    """Per-launch timing with the longest chunks set_tuning accepts (32 and
+    64 iterations between readbacks): every iteration of a chunk has its own
+    events, the timing comes back positive, and the iterates equal those of
+    the default chunk."""
+    note("profiling with chunks 32 and 64, 2k grid, 130 iterations")
+    g = config_grid("c2_2kbus")
+    with A.Solver(g) as ref:
+        ref.solve(A.COLD, 130)
+        want = states(ref)
+    for chunk in (32, 64):
+        with A.Solver(g) as s:
+            s.set_tuning(chunk=chunk)
+            s.set_profiling(True)
+            s.solve(A.COLD, 130)
+            t = s.timing()
+            assert t["iters"] >= 130 and t["xstep_ms"] > 0.0 and t["bus_ms"] > 0.0, t
+            assert_same(states(s), want)
+
+
 @pytest.mark.parametrize("variant", [dict(xstep_waves=1), dict(xstep_waves=2),
                                      dict(xstep_per_lane=3), dict(xstep_per_lane=8, xstep_block=128)])
 def test_xstep_variants_equal_lane_per_branch(variant):
