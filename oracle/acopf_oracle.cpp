@@ -190,11 +190,15 @@ inline R clampd(R t, double lo, double hi) {
 // q(s) = g's + 1/2 s'Hs
 template <class R>
 R model_q(int n, const R* g, const R* H, const R* s) {
+  // q(s) = g's + s'Hs / 2 with H symmetric: s'Hs = sum_i s_i (H_ii s_i +
+  // sum_{j<i} H_ij (2 s_j)), doubling being exact
+  R t[NMAX];
+  for (int j = 0; j < n; ++j) t[j] = R(2.0) * s[j];
   R gs = R(0.0), sHs = R(0.0);
   for (int i = 0; i < n; ++i) {
     gs = rfma(g[i], s[i], gs);
-    R hi = R(0.0);
-    for (int j = 0; j < n; ++j) hi = rfma(H[i * n + j], s[j], hi);
+    R hi = H[i * n + i] * s[i];
+    for (int j = 0; j < i; ++j) hi = rfma(H[i * n + j], t[j], hi);
     sHs = rfma(s[i], hi, sHs);
   }
   return rfma(R(0.5), sHs, gs);

@@ -373,17 +373,23 @@ __device__ inline double dotN(const double* a, const double* b) {
 // q(s) = g's + 1/2 s'Hs ; counted as 2N^2 + 4N + 2
 template <int N, class Cnt>
 __device__ inline double model(const double* g, const Sym<N>& H, const double* s,
-                               Cnt& cnt) {
+                               Cnt& cnt, double* gs_out = nullptr) {
+  // s'Hs = sum_i s_i (H_ii s_i + sum_{j<i} H_ij (2 s_j)): the lower triangle
+  // only, doubling being exact. g's is returned in gs_out when asked for.
+  double t[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) t[j] = 2.0 * s[j];
   double gs = 0.0, sHs = 0.0;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     gs = fma(g[i], s[i], gs);
-    double hi = 0.0;
+    double hi = H(i, i) * s[i];
 #pragma unroll
-    for (int j = 0; j < N; ++j) hi = fma(H(i, j), s[j], hi);
+    for (int j = 0; j < i; ++j) hi = fma(H(i, j), t[j], hi);
     sHs = fma(s[i], hi, sHs);
   }
-  FL(2 * N * N + 4 * N + 2);
+  FL(N * N + 5 * N + 2);
+  if (gs_out) *gs_out = gs;
   return fma(0.5, sHs, gs);
 }
 
@@ -421,8 +427,9 @@ __device__ inline bool cauchy_ok(const double* g, const Sym<N>& H, const double*
   const double ss = dotN<N>(s, s);  // ||s|| <= delta, compared in squares
   FL(2 * N + 1);
   if (ss > delta * delta) return false;
-  const double q = model<N>(g, H, s, cnt);
-  const double gts = dotN<N>(g, s);
+  // g's is the dot product the model forms first, in the same order
+  double gts;
+  const double q = model<N>(g, H, s, cnt, &gts);
   FL(2 * N + 1);
   return q <= kMu0 * gts;
 }
@@ -772,7 +779,7 @@ __device__ int tron(const BranchIn<N>& B, double* x, const double* lo, const dou
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const double t = fabs(clampd(x[i] - g[i], lo[i], hi[i]) - x[i]);
-      pginf = pginf < t ? t : pginf;
+      pginf = fmax(pginf, t);  // t >= 0 or NaN; a NaN t leaves pginf, as comparing does
     }
     FL(2 * N);
     if (pginf <= gtol) {
@@ -904,7 +911,7 @@ __device__ bool tron_advance(TronState<N>& S, const BranchIn<N>& B, const double
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     const double t = fabs(clampd(S.x[i] - S.g[i], lo[i], hi[i]) - S.x[i]);
-    pginf = pginf < t ? t : pginf;
+    pginf = fmax(pginf, t);
   }
   FL(2 * N);
   if (pginf <= gtol) {
