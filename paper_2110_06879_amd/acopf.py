@@ -7,6 +7,7 @@ been built, loading raises.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 from dataclasses import asdict, dataclass
 
@@ -73,6 +74,9 @@ class _Tuning(C.Structure):
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+TUNING_FIELDS = tuple(n for n, _ in _Tuning._fields_)
 
 
 class _Result(C.Structure):
@@ -174,6 +178,47 @@ def default_params() -> dict:
     p = _Params()
     load().acopf_default_params(C.byref(p))
     return {n: getattr(p, n) for n, _ in p._fields_}
+
+
+def tuning_key(grids) -> str:
+    """Workload shape that a launch tuning is chosen for: number of grids and
+    their total buses, branches and rated branches."""
+    gs = [grids] if isinstance(grids, Grid) else list(grids)
+    nb = sum(int(g.n_bus) for g in gs)
+    nl = sum(int(g.n_branch) for g in gs)
+    n6 = sum(int(np.count_nonzero(np.asarray(g.rate) > 0)) for g in gs)
+    return f"grids={len(gs)} buses={nb} branches={nl} rated={n6}"
+
+
+def load_tuning(path: str, key: str) -> dict | None:
+    """The tuning stored for `key` in the JSON file at `path`, or None (no
+    file, no entry, or an entry without the tuning fields)."""
+    try:
+        with open(path) as fh:
+            table = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    t = table.get(key) if isinstance(table, dict) else None
+    if not isinstance(t, dict) or any(k not in t for k in TUNING_FIELDS):
+        return None
+    return {k: int(t[k]) for k in TUNING_FIELDS}
+
+
+def save_tuning(path: str, key: str, tuning: dict) -> None:
+    """Store `tuning` under `key` in the JSON file at `path`, keeping the other
+    entries; written to a temporary file and renamed into place."""
+    try:
+        with open(path) as fh:
+            table = json.load(fh)
+        if not isinstance(table, dict):
+            table = {}
+    except (OSError, ValueError):
+        table = {}
+    table[key] = {k: int(tuning[k]) for k in TUNING_FIELDS}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
 
 
 class Solver:
@@ -320,10 +365,23 @@ class Solver:
         self._check(self.lib.acopf_quality(self.h, grid, _dp(out)))
         return dict(zip(QUALITY_NAMES, out.tolist()))
 
-    def autotune(self, iters: int = 32) -> dict:
+    def autotune(self, iters: int = 32, cache: str | None = None) -> dict:
+        """Measure the launch-shape candidates on this handle's grids and keep
+        the fastest (state unchanged). With `cache`, a JSON file of earlier
+        results keyed by the workload's shape (tuning_key): a hit applies
+        the stored tuning without measuring, a miss measures and stores."""
+        key = tuning_key(self.grids)
+        if cache is not None:
+            hit = load_tuning(cache, key)
+            if hit is not None:
+                self.set_tuning(**hit)
+                return self.tuning()
         t = _Tuning()
         self._check(self.lib.acopf_autotune(self.h, iters, C.byref(t)))
-        return t.as_dict()
+        out = t.as_dict()
+        if cache is not None:
+            save_tuning(cache, key, out)
+        return out
 
     def set_counting(self, on: bool = True):
         """Count algorithmic flops and TRON events into stats() (slower)."""

@@ -164,6 +164,21 @@ def test_autotune_leaves_state_unchanged():
             assert_same(states(s), states(r))
 
 
+def test_autotune_cache_round_trip(tmp_path):
+    """autotune(cache=...) measures and stores on a miss; a second handle for
+    the same workload applies the stored tuning without measuring."""
+    note("autotune cache")
+    g = config_grid("c2_2kbus")
+    path = str(tmp_path / "tune.json")
+    with A.Solver(g) as s:
+        t1 = s.autotune(4, cache=path)
+        assert A.load_tuning(path, A.tuning_key(g)) == t1
+    with A.Solver(g) as r:
+        r.set_tuning(xstep_block=256, chunk=8)
+        t2 = r.autotune(4, cache=path)
+        assert t2 == t1 and r.tuning() == t1
+
+
 def test_serving_results_same_alone_and_in_mix():
     note("serving: alone vs mix")
     gs = [gridgen(250 + 40 * k, 50 + 8 * k, 325 + 52 * k, 1.0, 80 + k, load_factor=0.2)
