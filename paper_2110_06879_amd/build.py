@@ -19,6 +19,11 @@ HIPCC_FLAGS = [
     "-ffp-contract=off",
     # no packed FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # LLVM's iterative ILP-oriented machine scheduler: the branch kernel runs
+    # at one wavefront per SIMD, where instruction-level parallelism within
+    # a lane is what hides latency (3% faster x-step on the 70k grid; the
+    # operations and their order are unchanged)
+    "-mllvm", "-amdgpu-sched-strategy=iterative-ilp",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 
