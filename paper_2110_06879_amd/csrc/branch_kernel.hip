@@ -499,7 +499,7 @@ __device__ void cauchy(const double* x, const double* g, const Sym<N>& H,
 // Preconditioner application on the free variables (mask fr):
 // z = L^-T E^-1 L^-1 r with L unit lower and the reciprocal pivots rd = 1/E;
 // counted as 2 nf^2 - nf.
-template <int N>
+template <int N, bool kAll>
 __device__ inline void precond(const Sym<N>& L, const double* rd, const bool* fr,
                                const double* r, double* z) {
   double t[N];
@@ -508,7 +508,7 @@ __device__ inline void precond(const Sym<N>& L, const double* rd, const bool* fr
     double a = r[i];
 #pragma unroll
     for (int k = 0; k < i; ++k) a = fma(-L(i, k), t[k], a);
-    t[i] = fr[i] ? a : 0.0;
+    t[i] = (kAll || fr[i]) ? a : 0.0;
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) t[i] = t[i] * rd[i];
@@ -517,7 +517,7 @@ __device__ inline void precond(const Sym<N>& L, const double* rd, const bool* fr
     double a = t[i];
 #pragma unroll
     for (int k = i + 1; k < N; ++k) a = fma(-L(k, i), z[k], a);
-    z[i] = fr[i] ? a : 0.0;
+    z[i] = (kAll || fr[i]) ? a : 0.0;
   }
 }
 
@@ -528,7 +528,7 @@ __device__ inline void precond(const Sym<N>& L, const double* rd, const bool* fr
 // L_ij = (a_ij - sum_k L_ik v_k) times the reciprocal pivot, which is kept in
 // rd for the solves. Returns false at the first non-positive free pivot;
 // flops are counted as on the compressed nf x nf matrix.
-template <int N, class Cnt>
+template <int N, bool kAll, class Cnt>
 __device__ inline bool ldlt(const Sym<N>& H, const double* Sd, double shift,
                             const bool* fr, int nf, Sym<N>& L, double* rd,
                             Cnt& cnt) {
@@ -539,7 +539,7 @@ __device__ inline bool ldlt(const Sym<N>& H, const double* Sd, double shift,
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     L(j, j) = 1.0;
-    if (!fr[j]) {
+    if (!(kAll || fr[j])) {
       e[j] = 1.0;
       rd[j] = 1.0;
       continue;
@@ -557,7 +557,7 @@ __device__ inline bool ldlt(const Sym<N>& H, const double* Sd, double shift,
     rd[j] = rj;
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {
-      if (!fr[i]) continue;
+      if (!(kAll || fr[i])) continue;
       double t = H(i, j);
 #pragma unroll
       for (int k = 0; k < j; ++k) t = fma(-L(i, k), v[k], t);
@@ -572,23 +572,13 @@ __device__ inline bool ldlt(const Sym<N>& H, const double* Sd, double shift,
 // Subspace steps from the Cauchy point w (in/out), Lin & More Sec. 4:
 // Steihaug PCG on the free variables, projected search, repeat while a new
 // bound becomes active and CG ended inside the trust region.
-template <int N, class Cnt>
-__device__ void subspace(const double* x, const double* g, const Sym<N>& H,
-                         const double* lo, const double* hi, double delta,
-                         double* w, Cnt& cnt) {
-  double s[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) s[i] = w[i] - x[i];
-  FL(N);
-  for (int pass = 0; pass < N; ++pass) {
-    bool fr[N];
-    int nf = 0;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      fr[i] = w[i] > lo[i] && w[i] < hi[i];
-      nf += fr[i] ? 1 : 0;
-    }
-    if (nf == 0) break;
+// One pass on the free set fr (nf free variables) at the current Cauchy or
+// search point w, with s = w - x; returns true when the passes end. With
+// kAll every variable is free, and the free-set tests compile away.
+template <int N, bool kAll, class Cnt>
+__device__ bool subspace_pass(const double* x, const double* g, const Sym<N>& H,
+                              const double* lo, const double* hi, double delta, double* w,
+                              double* s, const bool* fr, int nf, Cnt& cnt) {
     double gq[N], r[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -596,12 +586,12 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
 #pragma unroll
       for (int j = 0; j < N; ++j) t = fma(H(i, j), s[j], t);
       gq[i] = t;
-      r[i] = fr[i] ? -t : 0.0;
+      r[i] = (kAll || fr[i]) ? -t : 0.0;
     }
     FL(2 * N * N);
     const double rr0 = dotN<N>(r, r);  // squared norm of the initial residual
     FL(2 * nf);
-    if (!(rr0 > 0.0)) break;
+    if (!(rr0 > 0.0)) return true;
     // Lin & More's scaled matrix D H D + shift I, D = diag(|H_ii|^(-1/2)),
     // gives the preconditioner H + shift D^-2; it is factored in that form,
     // H + shift Sd with Sd = |H_ii| (1 where H_ii = 0). The scaled diagonal
@@ -612,7 +602,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
     for (int i = 0; i < N; ++i) {
       const double b = H(i, i);
       Sd[i] = b == 0.0 ? 1.0 : fabs(b);
-      if (fr[i]) {
+      if ((kAll || fr[i])) {
         const double sgn = b > 0.0 ? 1.0 : (b < 0.0 ? -1.0 : 0.0);
         mind = sgn < mind ? sgn : mind;
       }
@@ -628,7 +618,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
     for (int att = 0; att < kMaxChol; ++att) {
       FL(2 * nf);
       ++cnt.chol;
-      if (ldlt<N>(H, Sd, shift, fr, nf, L, rd, cnt)) {
+      if (ldlt<N, kAll>(H, Sd, shift, fr, nf, L, rd, cnt)) {
         ok = true;
         break;
       }
@@ -650,7 +640,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       d[i] = 0.0;
       res[i] = r[i];
     }
-    precond<N>(L, rd, fr, res, zz);
+    precond<N, kAll>(L, rd, fr, res, zz);
     FL(2 * nf * nf - nf);
 #pragma unroll
     for (int i = 0; i < N; ++i) p[i] = zz[i];
@@ -666,7 +656,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
         double t = 0.0;
 #pragma unroll
         for (int j = 0; j < N; ++j) t = fma(H(i, j), p[j], t);
-        Bp[i] = fr[i] ? t : 0.0;
+        Bp[i] = (kAll || fr[i]) ? t : 0.0;
       }
       const double pBp = dotN<N>(p, Bp);
       FL(2 * nf * nf + 2 * nf);
@@ -704,12 +694,12 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       const double rr = dotN<N>(res, res);  // ||r|| <= tol ||r0||, in squares
       FL(4 * nf + 2 * nf + 1);
       if (rr <= (kCgTol * kCgTol) * rr0) break;
-      precond<N>(L, rd, fr, res, zz);
+      precond<N, kAll>(L, rd, fr, res, zz);
       const double rzn = dotN<N>(res, zz);
       const double bcg = rzn / rz;
       rz = rzn;
 #pragma unroll
-      for (int i = 0; i < N; ++i) p[i] = fr[i] ? fma(bcg, p[i], zz[i]) : 0.0;
+      for (int i = 0; i < N; ++i) p[i] = (kAll || fr[i]) ? fma(bcg, p[i], zz[i]) : 0.0;
       FL(2 * nf * nf - nf + 2 * nf + 1 + 2 * nf);
     }
     // projected search along d from w
@@ -721,7 +711,7 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       ++cnt.ps;
 #pragma unroll
       for (int i = 0; i < N; ++i)
-        wt[i] = fr[i] ? clampd(fma(beta, d[i], w[i]), lo[i], hi[i]) : w[i];
+        wt[i] = (kAll || fr[i]) ? clampd(fma(beta, d[i], w[i]), lo[i], hi[i]) : w[i];
       double dw[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) {
@@ -739,17 +729,40 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       beta = beta * 0.5;
       FL(1);
     }
-    if (!acc) break;
+    if (!acc) return true;
     bool hit = false;
 #pragma unroll
     for (int i = 0; i < N; ++i)
-      if (fr[i] && (wt[i] == lo[i] || wt[i] == hi[i])) hit = true;
+      if ((kAll || fr[i]) && (wt[i] == lo[i] || wt[i] == hi[i])) hit = true;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       w[i] = wt[i];
       s[i] = stv[i];
     }
-    if (boundary || !hit) break;
+    if (boundary || !hit) return true;
+    return false;
+}
+
+template <int N, class Cnt>
+__device__ void subspace(const double* x, const double* g, const Sym<N>& H,
+                         const double* lo, const double* hi, double delta,
+                         double* w, Cnt& cnt) {
+  double s[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) s[i] = w[i] - x[i];
+  FL(N);
+  for (int pass = 0; pass < N; ++pass) {
+    bool fr[N];
+    int nf = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      fr[i] = w[i] > lo[i] && w[i] < hi[i];
+      nf += fr[i] ? 1 : 0;
+    }
+    if (nf == 0) break;
+    const bool stop = nf == N ? subspace_pass<N, true>(x, g, H, lo, hi, delta, w, s, fr, nf, cnt)
+                              : subspace_pass<N, false>(x, g, H, lo, hi, delta, w, s, fr, nf, cnt);
+    if (stop) break;
   }
 }
 
