@@ -420,18 +420,26 @@ __device__ inline double to_boundary(const double* a, const double* p, double de
   return tau;
 }
 
-// Cauchy-search acceptance: ||s|| <= delta and q(s) <= mu0 g's.
+// Cauchy-search acceptance: ||s|| <= delta and q(s) <= mu0 g's. q receives
+// q(s) whenever it is evaluated (always, when the trial is accepted).
 template <int N, class Cnt>
 __device__ inline bool cauchy_ok(const double* g, const Sym<N>& H, const double* s,
-                                 double delta, Cnt& cnt) {
+                                 double delta, double& q, Cnt& cnt) {
   const double ss = dotN<N>(s, s);  // ||s|| <= delta, compared in squares
   FL(2 * N + 1);
   if (ss > delta * delta) return false;
   // g's is the dot product the model forms first, in the same order
   double gts;
-  const double q = model<N>(g, H, s, cnt, &gts);
+  q = model<N>(g, H, s, cnt, &gts);
   FL(2 * N + 1);
   return q <= kMu0 * gts;
+}
+
+// The model's flops, counted where the algorithm evaluates q(s) again at a
+// point whose value the kernel already holds.
+template <int N, class Cnt>
+__device__ inline void count_model(Cnt& cnt) {
+  FL(N * N + 5 * N + 2);
 }
 
 template <int N, class Cnt>
@@ -449,14 +457,19 @@ __device__ inline void cauchy_trial(const double* x, const double* g, const doub
 template <int N, class Cnt>
 __device__ void cauchy(const double* x, const double* g, const Sym<N>& H,
                        const double* lo, const double* hi, double delta,
-                       double& alpha, double* w, Cnt& cnt) {
+                       double& alpha, double* w, double& qw, bool& qok, Cnt& cnt) {
+  // On return qw = q(w - x) and qok is true, unless no trial was accepted.
   // The largest breakpoint of the projected path is only needed to stop an
   // extrapolation, so it is formed on that branch; the other branch counts
   // its flops all the same, as the algorithm forms it before the first trial.
   double s[N], wt[N], st[N];
   cauchy_trial<N>(x, g, lo, hi, alpha, w, s, cnt);
   ++cnt.cauchy;
-  if (cauchy_ok<N>(g, H, s, delta, cnt)) {
+  double q;
+  qok = false;
+  if (cauchy_ok<N>(g, H, s, delta, q, cnt)) {
+    qw = q;
+    qok = true;
     double brpt = 0.0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -477,8 +490,9 @@ __device__ void cauchy(const double* x, const double* g, const Sym<N>& H,
       FL(1);
       cauchy_trial<N>(x, g, lo, hi, a2, wt, st, cnt);
       ++cnt.cauchy;
-      if (!cauchy_ok<N>(g, H, st, delta, cnt)) break;
+      if (!cauchy_ok<N>(g, H, st, delta, q, cnt)) break;
       alpha = a2;
+      qw = q;
 #pragma unroll
       for (int i = 0; i < N; ++i) w[i] = wt[i];
     }
@@ -491,7 +505,11 @@ __device__ void cauchy(const double* x, const double* g, const Sym<N>& H,
       FL(1);
       cauchy_trial<N>(x, g, lo, hi, alpha, w, s, cnt);
       ++cnt.cauchy;
-      if (cauchy_ok<N>(g, H, s, delta, cnt)) break;
+      if (cauchy_ok<N>(g, H, s, delta, q, cnt)) {
+        qw = q;
+        qok = true;
+        break;
+      }
     }
   }
 }
@@ -578,7 +596,8 @@ __device__ inline bool ldlt(const Sym<N>& H, const double* Sd, double shift,
 template <int N, bool kAll, class Cnt>
 __device__ bool subspace_pass(const double* x, const double* g, const Sym<N>& H,
                               const double* lo, const double* hi, double delta, double* w,
-                              double* s, const bool* fr, int nf, Cnt& cnt) {
+                              double* s, const bool* fr, int nf, double& qcur, bool& qok,
+                              Cnt& cnt) {
     double gq[N], r[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -703,9 +722,18 @@ __device__ bool subspace_pass(const double* x, const double* g, const Sym<N>& H,
       FL(2 * nf * nf - nf + 2 * nf + 1 + 2 * nf);
     }
     // projected search along d from w
-    const double qw = model<N>(g, H, s, cnt);
+    // q(s) at the pass's start point: known when that point was accepted by
+    // the Cauchy search or by the previous pass's search
+    double qw;
+    if (qok) {
+      qw = qcur;
+      count_model<N>(cnt);
+    } else {
+      qw = model<N>(g, H, s, cnt);
+    }
     double beta = 1.0;
     bool acc = false;
+    double qt_acc = 0.0;
     double wt[N], stv[N];
     for (int t = 0; t < kMaxTrials; ++t) {
       ++cnt.ps;
@@ -724,6 +752,7 @@ __device__ bool subspace_pass(const double* x, const double* g, const Sym<N>& H,
       FL(2 * N + 2);
       if (qt <= lhs) {
         acc = true;
+        qt_acc = qt;
         break;
       }
       beta = beta * 0.5;
@@ -739,6 +768,8 @@ __device__ bool subspace_pass(const double* x, const double* g, const Sym<N>& H,
       w[i] = wt[i];
       s[i] = stv[i];
     }
+    qcur = qt_acc;
+    qok = true;
     if (boundary || !hit) return true;
     return false;
 }
@@ -746,7 +777,7 @@ __device__ bool subspace_pass(const double* x, const double* g, const Sym<N>& H,
 template <int N, class Cnt>
 __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
                          const double* lo, const double* hi, double delta,
-                         double* w, Cnt& cnt) {
+                         double* w, double& qcur, bool& qok, Cnt& cnt) {
   double s[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) s[i] = w[i] - x[i];
@@ -760,8 +791,9 @@ __device__ void subspace(const double* x, const double* g, const Sym<N>& H,
       nf += fr[i] ? 1 : 0;
     }
     if (nf == 0) break;
-    const bool stop = nf == N ? subspace_pass<N, true>(x, g, H, lo, hi, delta, w, s, fr, nf, cnt)
-                              : subspace_pass<N, false>(x, g, H, lo, hi, delta, w, s, fr, nf, cnt);
+    const bool stop =
+        nf == N ? subspace_pass<N, true>(x, g, H, lo, hi, delta, w, s, fr, nf, qcur, qok, cnt)
+                : subspace_pass<N, false>(x, g, H, lo, hi, delta, w, s, fr, nf, qcur, qok, cnt);
     if (stop) break;
   }
 }
@@ -801,12 +833,21 @@ __device__ int tron(const BranchIn<N>& B, double* x, const double* lo, const dou
     }
     ++cnt.tron_iters;
     double w[N], s[N];
-    cauchy<N>(x, g, H, lo, hi, delta, alphac, w, cnt);
-    subspace<N>(x, g, H, lo, hi, delta, w, cnt);
+    double qcur = 0.0;
+    bool qok = false;
+    cauchy<N>(x, g, H, lo, hi, delta, alphac, w, qcur, qok, cnt);
+    subspace<N>(x, g, H, lo, hi, delta, w, qcur, qok, cnt);
 #pragma unroll
     for (int i = 0; i < N; ++i) s[i] = w[i] - x[i];
     FL(N);
-    const double prered = -model<N>(g, H, s, cnt);
+    double qs;
+    if (qok) {
+      qs = qcur;
+      count_model<N>(cnt);
+    } else {
+      qs = model<N>(g, H, s, cnt);
+    }
+    const double prered = -qs;
     const double snorm = sqrt(dotN<N>(s, s));
     FL(2 * N + 1);
     if (!(prered > 0.0)) {
@@ -933,12 +974,21 @@ __device__ bool tron_advance(TronState<N>& S, const BranchIn<N>& B, const double
   }
   ++cnt.tron_iters;
   double w[N], s[N];
-  cauchy<N>(S.x, S.g, S.H, lo, hi, S.delta, S.alphac, w, cnt);
-  subspace<N>(S.x, S.g, S.H, lo, hi, S.delta, w, cnt);
+  double qcur = 0.0;
+  bool qok = false;
+  cauchy<N>(S.x, S.g, S.H, lo, hi, S.delta, S.alphac, w, qcur, qok, cnt);
+  subspace<N>(S.x, S.g, S.H, lo, hi, S.delta, w, qcur, qok, cnt);
 #pragma unroll
   for (int i = 0; i < N; ++i) s[i] = w[i] - S.x[i];
   FL(N);
-  const double prered = -model<N>(S.g, S.H, s, cnt);
+  double qs;
+  if (qok) {
+    qs = qcur;
+    count_model<N>(cnt);
+  } else {
+    qs = model<N>(S.g, S.H, s, cnt);
+  }
+  const double prered = -qs;
   const double snorm = sqrt(dotN<N>(s, s));
   FL(2 * N + 1);
   if (!(prered > 0.0)) {
