@@ -28,11 +28,20 @@
 // The free set of a subspace step is handled with a mask over all N
 // variables instead of compressed indices (fixed rows and columns act as
 // identity), which keeps indexing static; the nonzero arithmetic is the same
-// as on the compressed system.
+// as on the compressed system. A pass in which every variable is free runs
+// an instantiation without the mask.
 //
-// Each lane also counts the algorithmic flops of the method as the plain
+// The heavy solves run alone in their wavefront at the end of a launch, one
+// wavefront per SIMD, so a lane's time is its instruction count: values the
+// lane already holds are not formed again (the model value at the current
+// point, the coupling values of an accepted trial point, g's in the Cauchy
+// test), with the flops counted as the algorithm performs them.
+//
+// Each lane can also count the algorithmic flops of the method as the plain
 // serial algorithm performs them (+ - * / sqrt one each, sin and cos apart),
-// step by step, so that achieved FP64 throughput can be reported exactly.
+// step by step, so that achieved FP64 throughput can be reported exactly;
+// the counter type is a template parameter, and the default kernels carry
+// counters that do nothing.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
