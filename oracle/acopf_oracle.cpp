@@ -8,8 +8,11 @@
 // constant with the HIP library: it is written from the paper (and from Lin &
 // More 1999 for the trust-region Newton method) on its own.
 //
-// Build: g++ -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, IEEE
-// division and square root; sin/cos of branch angles by the series below).
+// Build: g++ -O2 -ffp-contract=off -fno-fast-math -mfma -fPIC -shared: no
+// implicit contraction; the fused multiply-adds written out below (std::fma)
+// are correctly rounded whether done by the FMA instruction or the library;
+// IEEE division and square root; sin/cos of branch angles by the series
+// below.
 //
 // Layout of the coupling vectors (canonical order, shared with the library's
 // get_state only as a documented convention): generator g owns couplings
