@@ -216,3 +216,24 @@ def test_serving_budget_without_slots_runs_on_home():
     assert out["requests"] == 3 and out["converged"] == 3
     with pytest.raises(ValueError):
         S.TrackingServer(gs, hbm_budget_bytes=budget * 0.1)
+
+
+def test_step_length_state_round_trip_and_validation():
+    """The per-branch Cauchy step length is state like x and the AL terms:
+    set_state/get_state round-trip positive values exactly, a new handle's
+    cold state holds 1, and non-positive or non-finite values are refused."""
+    note("calpha state: round trip and validation")
+    g = config_grid("c1_30bus")
+    with A.Solver(g) as s:
+        s.solve(A.COLD, 5)
+        a = s.get("calpha")
+        assert a.shape == (g.n_branch,) and np.all(a > 0.0)
+        want = np.linspace(0.25, 40.0, g.n_branch)
+        s.set("calpha", want)
+        np.testing.assert_array_equal(s.get("calpha"), want)
+        for bad in (np.zeros(g.n_branch), -want, np.full(g.n_branch, np.nan)):
+            with pytest.raises(A.AcopfError):
+                s.set("calpha", bad)
+        np.testing.assert_array_equal(s.get("calpha"), want)
+    with A.Solver(g) as r:
+        np.testing.assert_array_equal(r.get("calpha"), np.ones(g.n_branch))
