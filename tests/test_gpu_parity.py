@@ -282,6 +282,29 @@ def test_quality_matches_oracle():
             assert_quality_equal(s.quality(k), orc.quality(), f"batch grid {k}")
 
 
+def test_70k_default_launch_25_iterations_matches_oracle():
+    """The 70k-bus grid in the launch configuration the benchmark times
+    (default tuning: graph chunks of 16, automatic branches per lane), 25
+    iterations from the same cold start: every state vector, the residual
+    history and the TRON event counts equal the oracle's."""
+    note("parity c3 70k: 25 iterations from cold, default launch, counting on")
+    g = config_grid("c3_70kbus")
+    p = A.Params(rho_pq=400.0, rho_va=4000.0)
+    orc = O.Oracle(g, oparams(p))
+    orc.count_flops(True)
+    orc.solve(25)
+    with A.Solver(g, p) as s:
+        s.set_counting(True)
+        s.solve(A.COLD, 25)
+        compare(s, orc, tol=1e-9, label="70k cold+25")
+        np.testing.assert_array_equal(s.get("rtil"), orc.get("rtil"))
+        hg, ho = s.history(), orc.history()
+        np.testing.assert_array_equal(hg[:, [0, 1, 2]], ho[:, [0, 1, 2]])
+        sg, so = s.stats(), orc.stats()
+        for k in ("branch_solves", "tron_iters", "cauchy_trials", "cg_iters", "al_iters", "flops"):
+            assert sg[k] == so[k], (k, sg[k], so[k])
+
+
 def test_quality_70k_matches_oracle():
     note("quality: 70k grid after 6 iterations from cold, GPU and oracle")
     g = config_grid("c3_70kbus")
