@@ -157,6 +157,12 @@ def load() -> C.CDLL:
     lib.ora_set_count_flops.argtypes = [vp, ip]
     lib.ora_sincos.argtypes = [C.c_double, dp, dp]
     lib.ora_branch_eval.argtypes = [dp, ip, dp, C.c_double, dp, dp, dp, dp, dp]
+    lib.ora_ldlt.argtypes = [ip, dp, dp, dp]
+    lib.ora_ldlt.restype = ip
+    lib.ora_ldlt_solve.argtypes = [ip, dp, dp, dp, dp]
+    lib.ora_ldlt_solve.restype = ip
+    lib.ora_model.argtypes = [ip, dp, dp, dp]
+    lib.ora_model.restype = C.c_double
     lib.ora_branch_solve.argtypes = [dp, ip, dp, dp, dp, dp, dp, C.POINTER(_Params),
                                      C.POINTER(_Stats), ip]
     _lib = lib
@@ -364,6 +370,39 @@ def branch_solve(data: np.ndarray, n: int, x6, ltil, rtil: float,
     out = st.as_dict()
     out["alpha"] = float(al[0])
     return x, lt, rt[0], u, out
+
+
+def ldlt(A):
+    """The trust-region method's square-root-free Cholesky factorization of a
+    symmetric matrix: (L unit lower, reciprocal pivots 1/e), or None at a
+    non-positive pivot."""
+    lib = load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    L = np.zeros((n, n))
+    rd = np.zeros(n)
+    ok = lib.ora_ldlt(n, _dp(A), _dp(L), _dp(rd))
+    return (L, rd) if ok == 1 else None
+
+
+def ldlt_solve(L, rd, r):
+    """z = (L E L')^-1 r from the factors of ldlt."""
+    lib = load()
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    rd = np.ascontiguousarray(rd, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    z = np.zeros_like(r)
+    lib.ora_ldlt_solve(len(r), _dp(L), _dp(rd), _dp(r), _dp(z))
+    return z
+
+
+def model(g, H, s):
+    """The trust-region model q(s) = g's + s'Hs/2 as the oracle forms it."""
+    lib = load()
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    return lib.ora_model(len(g), _dp(g), _dp(H), _dp(s))
 
 
 def sincos(x: float):

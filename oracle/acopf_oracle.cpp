@@ -1466,6 +1466,25 @@ struct CbProblem {
   void fgh(const double* x, double& F, double* g, double* H) { gcb(x, &F, g, H, ctx); }
 };
 
+// Building blocks of the trust-region method, for the CPU tests: the L E L'
+// factorization (returns 1, or 0 at a non-positive pivot), the solve with it,
+// and the quadratic model q(s) = g's + s'Hs/2. Matrices are dense row-major
+// n x n (1 <= n <= 8).
+int ora_ldlt(int n, const double* A, double* L, double* rd) {
+  if (n < 1 || n > NMAX) return -1;
+  return ldlt<double>(n, A, L, rd) ? 1 : 0;
+}
+
+int ora_ldlt_solve(int n, const double* L, const double* rd, const double* r, double* z) {
+  if (n < 1 || n > NMAX) return -1;
+  precond<double>(n, L, rd, r, z);
+  return 0;
+}
+
+double ora_model(int n, const double* g, const double* H, const double* s) {
+  return model_q<double>(n, g, H, s);
+}
+
 int ora_tron(int n, double* x, const double* lo, const double* hi,
              ora_f_cb fcb, ora_fgh_cb gcb, void* ctx, const ora_params* P,
              ora_stats* st) {

@@ -7,7 +7,12 @@
   second-order (free Hessian positive semidefinite) conditions at the result,
   and a brute-force grid check of local minimality;
 * Rosenbrock's function in a box containing (1, 1): the known minimizer;
-  and in a box excluding it: the KKT conditions.
+  and in a box excluding it: the KKT conditions;
+* its building blocks on their own: the square-root-free Cholesky factors
+  L E L' against numpy's Cholesky (L sqrt(E)) and the matrix itself, the
+  solve with them against numpy.linalg.solve, a non-positive pivot reported
+  for indefinite and singular matrices, and the quadratic model against
+  g's + s'Hs/2 evaluated by numpy.
 """
 import itertools
 
@@ -146,3 +151,58 @@ def test_tron_starting_at_solution_takes_no_step():
                                    np.array([-5.0, -5.0]), np.array([5.0, 5.0]))
     assert status == 0 and st["tron_iters"] == 0
     np.testing.assert_array_equal(x, [1.0, 1.0])
+
+
+def spd(rng, n, cond=1e3):
+    Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    ev = np.exp(rng.uniform(0.0, np.log(cond), n))
+    return (Q * ev) @ Q.T
+
+
+def test_ldlt_factors_match_cholesky_and_solve():
+    rng = np.random.default_rng(31)
+    for n in range(1, 7):
+        for _ in range(20):
+            A = spd(rng, n)
+            A = 0.5 * (A + A.T)
+            out = O.ldlt(A)
+            assert out is not None
+            L, rd = out
+            e = 1.0 / rd
+            assert np.all(e > 0.0)
+            np.testing.assert_array_equal(np.diag(L), np.ones(n))
+            assert np.all(np.triu(L, 1) == 0.0)
+            np.testing.assert_allclose(L @ np.diag(e) @ L.T, A, rtol=1e-12,
+                                       atol=1e-12 * np.abs(A).max())
+            C = np.linalg.cholesky(A)
+            np.testing.assert_allclose(L * np.sqrt(e), C, rtol=1e-10, atol=1e-12 * np.abs(C).max())
+            r = rng.normal(size=n)
+            z = O.ldlt_solve(L, rd, r)
+            np.testing.assert_allclose(z, np.linalg.solve(A, r), rtol=1e-9,
+                                       atol=1e-12 * np.abs(z).max())
+
+
+def test_ldlt_reports_non_positive_pivots():
+    rng = np.random.default_rng(32)
+    for n in range(2, 7):
+        Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+        ev = rng.uniform(0.5, 2.0, n)
+        ev[rng.integers(n)] = -0.3          # one negative eigenvalue
+        A = (Q * ev) @ Q.T
+        assert O.ldlt(0.5 * (A + A.T)) is None
+        B = np.zeros((n, n))
+        B[0, 0] = 1.0                       # singular: zero pivot at column 1
+        assert O.ldlt(B) is None
+
+
+def test_model_matches_quadratic_form():
+    rng = np.random.default_rng(33)
+    for n in range(1, 7):
+        for _ in range(20):
+            H = rng.normal(size=(n, n))
+            H = H + H.T
+            g = rng.normal(size=n)
+            s = rng.normal(size=n)
+            want = g @ s + 0.5 * s @ H @ s
+            got = O.model(g, H, s)
+            assert abs(got - want) <= 1e-13 * (abs(g) @ abs(s) + abs(s) @ abs(H) @ abs(s))
