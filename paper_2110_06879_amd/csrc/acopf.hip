@@ -165,14 +165,40 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
     bqd = A.qd[i];
     bref = A.isref[i];
   }
-  for (int e = tid; e < net && e < ecap; e += nt) {
+  // The lane's first end (e = tid) and first generator (g = tid) load their
+  // phase-3 operands v and lambda here, so those loads are in flight with
+  // phase 1's instead of after the second barrier (u and y, read again in
+  // phase 3, are then cache hits; keeping them too costs occupancy). Nothing
+  // writes these words before phase 3, where this lane owns them.
+  const bool own_e = tid < net && tid < ecap, own_g = tid < ngt && tid < gcap;
+  double ev[4], el[4], gv[2], gl[2];
+  if (own_e) {
+    const int64_t k = E0 + tid;
+#pragma unroll
+    for (int kind = 0; kind < 4; ++kind) {
+      const int64_t c = ec(k, kind);
+      ev[kind] = A.v[c];
+      el[kind] = A.lam[c];
+      cE[kind * ecap + tid] = target(c, kind < 2 ? rpq : rva);
+    }
+  }
+  if (own_g) {
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+      const int64_t c = (blk ? ng : 0) + G0 + tid;
+      gv[blk] = A.v[c];
+      gl[blk] = A.lam[c];
+      cG[blk * gcap + tid] = target(c, rpq);
+    }
+  }
+  for (int e = tid + nt; e < net && e < ecap; e += nt) {
     const int64_t k = E0 + e;
     cE[0 * ecap + e] = target(ec(k, 0), rpq);
     cE[1 * ecap + e] = target(ec(k, 1), rpq);
     cE[2 * ecap + e] = target(ec(k, 2), rva);
     cE[3 * ecap + e] = target(ec(k, 3), rva);
   }
-  for (int g = tid; g < ngt && g < gcap; g += nt) {
+  for (int g = tid + nt; g < ngt && g < gcap; g += nt) {
     cG[g] = target(G0 + g, rpq);
     cG[gcap + g] = target(ng + G0 + g, rpq);
   }
@@ -225,11 +251,9 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
   // ---- phase 3
   const double beta = A.ctl[grid].beta;
   double rp = 0.0, rd = 0.0, rz = 0.0;
-  auto finish = [&](int64_t k, double vnew, double rho) {
-    const double vold = A.v[k];
-    const double uk = A.u[k];
-    const double yold = A.y[k];
-    const double zk = -(A.lam[k] + yold + rho * (uk - vnew)) / (beta + rho);
+  auto finish_with = [&](int64_t k, double vnew, double rho, double vold, double uk,
+                         double yold, double lamk) {
+    const double zk = -(lamk + yold + rho * (uk - vnew)) / (beta + rho);
     const double yk = yold + rho * (uk - vnew + zk);
     A.v[k] = vnew;
     A.z[k] = zk;
@@ -238,12 +262,28 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
     rd = fmax(rd, fabs(vnew - vold));
     rz = fmax(rz, fabs(zk));
   };
-  for (int g = tid; g < ngt; g += nt) {
+  auto finish = [&](int64_t k, double vnew, double rho) {
+    finish_with(k, vnew, rho, A.v[k], A.u[k], A.y[k], A.lam[k]);
+  };
+  if (own_g) {
+    const int b = gmap[tid];
+    finish_with(G0 + tid, (cgen(0, tid) - bv[b]) / rpq, rpq, gv[0], A.u[G0 + tid], A.y[G0 + tid], gl[0]);
+    finish_with(ng + G0 + tid, (cgen(1, tid) - bv[tb + b]) / rpq, rpq, gv[1], A.u[ng + G0 + tid], A.y[ng + G0 + tid], gl[1]);
+  }
+  for (int g = own_g ? tid + nt : tid; g < ngt; g += nt) {
     const int b = g < gcap ? gmap[g] : tile_bus_of(A.gptr, b0, nbt, G0, g);
     finish(G0 + g, (cgen(0, g) - bv[b]) / rpq, rpq);
     finish(ng + G0 + g, (cgen(1, g) - bv[tb + b]) / rpq, rpq);
   }
-  for (int e = tid; e < net; e += nt) {
+  if (own_e) {
+    const int b = emap[tid];
+    const int64_t k = E0 + tid;
+    finish_with(ec(k, 0), (cend(0, tid) + bv[b]) / rpq, rpq, ev[0], A.u[ec(k, 0)], A.y[ec(k, 0)], el[0]);
+    finish_with(ec(k, 1), (cend(1, tid) + bv[tb + b]) / rpq, rpq, ev[1], A.u[ec(k, 1)], A.y[ec(k, 1)], el[1]);
+    finish_with(ec(k, 2), bv[2 * tb + b], rva, ev[2], A.u[ec(k, 2)], A.y[ec(k, 2)], el[2]);
+    finish_with(ec(k, 3), bv[3 * tb + b], rva, ev[3], A.u[ec(k, 3)], A.y[ec(k, 3)], el[3]);
+  }
+  for (int e = own_e ? tid + nt : tid; e < net; e += nt) {
     const int b = e < ecap ? emap[e] : tile_bus_of(A.eptr, b0, nbt, E0, e);
     const int64_t k = E0 + e;
     finish(ec(k, 0), (cend(0, e) + bv[b]) / rpq, rpq);
@@ -357,15 +397,21 @@ __global__ __launch_bounds__(kCtlBlock) void ctl_kernel(CtlArgs A) {
   const int g = blockIdx.x;
   const int tid = threadIdx.x;
   GridCtl& c = A.ctl[g];
-  if (c.done) {
-    if (tid == 0) c.do_outer = 0;
-    return;
-  }
+  // The tile maxima and lane 0's copy of the control record are loaded
+  // before the done test, so their latencies overlap instead of adding up
+  // (a finished grid's stale maxima are read and ignored).
+  GridCtl cc;
+  if (tid == 0) cc = c;
+  const int done = c.done;
   double rp = 0.0, rd = 0.0, rz = 0.0;
   for (int t = A.grid_tile[g] + tid; t < A.grid_tile[g + 1]; t += kCtlBlock) {
     rp = fmax(rp, A.tmax[3 * t + 0]);
     rd = fmax(rd, A.tmax[3 * t + 1]);
     rz = fmax(rz, A.tmax[3 * t + 2]);
+  }
+  if (done) {
+    if (tid == 0) c.do_outer = 0;
+    return;
   }
   for (int off = 32; off > 0; off >>= 1) {
     rp = fmax(rp, __shfl_xor(rp, off, 64));
@@ -387,8 +433,9 @@ __global__ __launch_bounds__(kCtlBlock) void ctl_kernel(CtlArgs A) {
       rd = fmax(rd, red[1][w]);
       rz = fmax(rz, red[2][w]);
     }
-    s_outer = ctl_decide(A, g, c, rp, rd, rz);
-    s_beta = c.beta_lam;
+    s_outer = ctl_decide(A, g, cc, rp, rd, rz);
+    s_beta = cc.beta_lam;
+    c = cc;
   }
   __syncthreads();
   if (!s_outer) return;
