@@ -72,9 +72,9 @@ def main():
                     help="one elementwise copy of 256 MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "the multi-GPU design is described in DESIGN.md but not implemented.",
-              file=sys.stderr)
+        print(f"bench.py: this solver runs on one GPU only (asked for {args.gpus}); "
+              "sharding across GPUs (by grid for batches, by bus ranges for one "
+              "grid) is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch  # device memory/stream plumbing only; the kernels are in libacopf.so
