@@ -22,8 +22,9 @@
 // and v the bus side (Section II-B, II-C).
 //
 // Parity status per function (what the CPU tests pin it to) is listed in the
-// test files; nothing here is "parity unpinned" except the warm-start load
-// perturbation, which has no closed form.
+// test files; every function here is pinned there. (The random load changes
+// of warm-start workloads are drawn by the shared input generators, not
+// here.)
 
 #include <algorithm>
 #include <cmath>

@@ -11,11 +11,12 @@
 * invariants of Algorithm 1: cold start has u = v and z = 0, bounds hold at
   every iterate;
 * whole ADMM on a 3-bus grid: converges to the solution of the dense NLP
-  (scipy SLSQP on polar power flow);
+  (scipy SLSQP on polar power flow), also when warm-started after new loads;
 * the Cauchy step length carried between a branch's trust-region solves:
   the same iterations and objective as restarting it at 1 (the method's own
   start) before every ADMM iteration, with about half the Cauchy trials.
 """
+import dataclasses
 import json
 import os
 
@@ -310,6 +311,41 @@ def test_three_bus_admm_converges_to_dense_acopf():
     f_admm = o.objective()
     f_ref = float(np.sum(g.c2 * (100 * p_ref) ** 2 + g.c1 * 100 * p_ref))
     assert abs(f_admm - f_ref) <= 1e-5 * f_ref
+
+
+@pytest.mark.slow
+def test_three_bus_warm_start_reaches_the_new_dense_optimum():
+    """Warm start (Sec. IV-C): after new loads the oracle keeps its primal and
+    dual state, restarts beta and the outer counter, and iterates to the
+    solution of the ACOPF with the new loads (dense SLSQP), not the old one."""
+    g = load_three_bus()
+    p = O.OracleParams(rho_pq=400.0, rho_va=4000.0, obj_scale=0.01,
+                       eps_pri=1e-7, eps_dual=1e-7, eps_z=1e-7,
+                       max_inner=20000, max_outer=40)
+    o = O.Oracle(g, p)
+    o.solve(0)
+    assert o.scalars()["status"] == 0
+    p_old = o.get("u")[0:2 * g.n_gen:2].copy()
+    x_old = o.get("bx").copy()
+    pd2, qd2 = g.pd * 1.04, g.qd * 0.97
+    g2 = dataclasses.replace(g, pd=pd2, qd=qd2)
+    p_ref, _, vm_ref, _ = dense_acopf(g2)
+    assert np.max(np.abs(p_ref - p_old)) > 1e-3   # the optimum moves
+    o.update_loads(pd2, qd2)
+    s = o.scalars()
+    assert s["outer"] == 0 and s["inner_total"] == 0 and s["beta"] == p.beta0
+    np.testing.assert_array_equal(o.get("bx"), x_old)   # state kept
+    o.solve(0)
+    s = o.scalars()
+    assert s["status"] == 0, s
+    ng = g.n_gen
+    u, v = o.get("u"), o.get("v")
+    np.testing.assert_allclose(u[0:2 * ng:2], p_ref, atol=1e-4)
+    vm = np.zeros(g.n_bus)
+    for l in range(g.n_branch):
+        vm[g.br_from[l]] = np.sqrt(v[2 * ng + 8 * l + 4])
+        vm[g.br_to[l]] = np.sqrt(v[2 * ng + 8 * l + 6])
+    np.testing.assert_allclose(vm, vm_ref, atol=1e-4)
 
 
 def ybus_quality(g, v, u):
