@@ -106,8 +106,8 @@ class Params:
     eps_z: float = 1e-4
     max_outer: int = 20
     max_inner: int = 1000
-    tron_gtol: float = 1e-8
-    tron_ftol: float = 1e-14
+    tron_gtol: float = 1e-6
+    tron_ftol: float = 1e-12
     tron_maxit: int = 50
     al_rho0: float = 10.0
     al_rho_growth: float = 10.0

@@ -891,8 +891,8 @@ void acopf_default_params(acopf_params* p) {
   p->eps_z = 1e-4;
   p->max_outer = 20;
   p->max_inner = 1000;
-  p->tron_gtol = 1e-8;
-  p->tron_ftol = 1e-14;
+  p->tron_gtol = 1e-6;
+  p->tron_ftol = 1e-12;
   p->tron_maxit = 50;
   p->al_rho0 = 10.0;
   p->al_rho_growth = 10.0;
