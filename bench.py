@@ -64,7 +64,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--trials", type=int, default=100, help="warm-start trials (seeds 3001...)")
-    ap.add_argument("--cpu-iters", type=int, default=30, help="oracle iterations for cpu_baseline")
+    ap.add_argument("--cpu-iters", type=int, default=100, help="oracle iterations for cpu_baseline (about 10 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="warmup + timed steps only (short run for rocprofv3)")
