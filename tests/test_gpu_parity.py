@@ -315,6 +315,29 @@ def test_quality_70k_matches_oracle():
         assert_quality_equal(s.quality(), orc.quality(), "70k")
 
 
+def test_70k_cold_solve_converges_with_default_parameters():
+    """The benchmark's grid from a cold start to the termination test of
+    Algorithm 1 with the library's default parameters (including the branch
+    solver's tolerance readings): converged, residuals within the
+    tolerances, the reported objective equal to the generator costs at the
+    generator-side outputs, and a small constraint violation (Sec. IV-A)."""
+    note("70k grid: cold solve to convergence with default parameters")
+    g = config_grid("c3_70kbus")
+    p = A.Params()
+    with A.Solver(g, p) as s:
+        res = s.solve(A.COLD)[0]
+        assert res["status"] == A.CONVERGED, res
+        assert res["r_pri"] <= p.eps_pri and res["r_dual"] <= p.eps_dual and res["r_z"] <= p.eps_z
+        assert res["inner_iters"] < p.max_outer * p.max_inner
+        u = s.get("u")
+        pg = u[0:2 * g.n_gen:2] * g.base_mva
+        cost = float(np.sum(g.c2 * pg * pg + g.c1 * pg + g.c0))
+        assert abs(res["objective"] - cost) <= 1e-9 * abs(cost)
+        q = s.quality()
+        assert q["max_violation"] <= 1e-2, q
+        assert q["line_limit"] <= 1e-6 and q["voltage_limit"] <= 1e-12, q
+
+
 def test_tracking_horizon_matches_oracle():
     """Four periods of the tracking horizon (Sec. IV-C: loads drift, warm
     start, ramp-limited generator bounds) on the GPU and in the oracle: the
