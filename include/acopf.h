@@ -281,6 +281,23 @@ void acopf_destroy(acopf_handle h);
 /* Message of the last failing call on this thread ("" if none). */
 const char* acopf_last_error(void);
 
+/* Measurement helpers, not part of the method: the achievable rates of the
+ * calling thread's current device, which a benchmark reports beside the
+ * published peaks. Each allocates its own device buffers, stream and events,
+ * synchronizes, and releases them before returning.
+ * acopf_peak_hbm: a streaming copy of `bytes` bytes (>= 1 MiB, 16-byte
+ *   vectors) into a second buffer, `iters` times after one warm-up copy;
+ *   *gbs = bytes read plus bytes written, per second, in GB/s.
+ * acopf_peak_fp64: eight wavefronts per SIMD, each lane running 8
+ *   independent FP64 fused multiply-add chains for `iters` steps, timed
+ *   after one untimed run of the same length;
+ *   *tflops = 2 flops per fused multiply-add, per second, in TFLOP/s.
+ * Return 0, ACOPF_EINVAL for invalid arguments, ACOPF_ENOMEM or
+ * ACOPF_EDEVICE. */
+int acopf_peak_hbm(int64_t bytes, int32_t iters, double* gbs);
+int acopf_peak_fp64(int32_t iters, double* tflops);
+
+
 #ifdef __cplusplus
 }
 #endif

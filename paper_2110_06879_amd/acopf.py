@@ -35,7 +35,8 @@ EXPORTS = ("acopf_default_params", "acopf_create", "acopf_solve", "acopf_update_
            "acopf_get_timing", "acopf_destroy", "acopf_last_error", "acopf_start",
            "acopf_run", "acopf_poll", "acopf_copy_grid", "acopf_snapshot",
            "acopf_set_tuning", "acopf_get_tuning", "acopf_autotune", "acopf_quality",
-           "acopf_update_gen_bounds", "acopf_set_counting")
+           "acopf_update_gen_bounds", "acopf_set_counting", "acopf_peak_hbm",
+           "acopf_peak_fp64")
 QUALITY_NAMES = ("max_violation", "balance_p", "balance_q", "line_limit", "voltage_limit",
                  "angle_limit")
 
@@ -159,12 +160,15 @@ def load(path: str | None = None) -> C.CDLL:
     lib.acopf_destroy.argtypes = [vp]
     lib.acopf_destroy.restype = None
     lib.acopf_last_error.restype = C.c_char_p
+    lib.acopf_peak_hbm.argtypes = [i64, i32, dp]
+    lib.acopf_peak_fp64.argtypes = [i32, dp]
     for name in ("acopf_create", "acopf_solve", "acopf_update_loads", "acopf_get_state",
                  "acopf_set_state", "acopf_get_sizes", "acopf_get_timing",
                  "acopf_set_profiling", "acopf_start", "acopf_run", "acopf_poll",
                  "acopf_copy_grid", "acopf_snapshot", "acopf_set_tuning",
                  "acopf_get_tuning", "acopf_autotune", "acopf_quality",
-                 "acopf_update_gen_bounds", "acopf_set_counting"):
+                 "acopf_update_gen_bounds", "acopf_set_counting", "acopf_peak_hbm",
+                 "acopf_peak_fp64"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -172,6 +176,28 @@ def load(path: str | None = None) -> C.CDLL:
 
 def _dp(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def peak_hbm(nbytes: int = 1 << 30, iters: int = 20) -> float:
+    """Achievable streaming-copy bandwidth of the current device, GB/s (read
+    plus written bytes): a measurement helper, not part of the method."""
+    lib = load()
+    out = C.c_double(0.0)
+    rc = lib.acopf_peak_hbm(int(nbytes), int(iters), C.byref(out))
+    if rc != 0:
+        raise AcopfError(f"acopf error {rc}: {lib.acopf_last_error().decode()}")
+    return out.value
+
+
+def peak_fp64(iters: int = 200000) -> float:
+    """Achievable FP64 fused multiply-add rate of the current device,
+    TFLOP/s: a measurement helper, not part of the method."""
+    lib = load()
+    out = C.c_double(0.0)
+    rc = lib.acopf_peak_fp64(int(iters), C.byref(out))
+    if rc != 0:
+        raise AcopfError(f"acopf error {rc}: {lib.acopf_last_error().decode()}")
+    return out.value
 
 
 def default_params() -> dict:

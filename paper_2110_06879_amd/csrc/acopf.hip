@@ -1889,3 +1889,120 @@ int acopf_get_timing(acopf_handle h, double* out5) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Measurement helpers: the device's achievable streaming bandwidth and FP64
+// vector rate, reported beside the published peaks. Not part of the method.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Streaming copy in 16-byte vectors, grid-stride.
+__global__ __launch_bounds__(256) void peak_copy_kernel(const double2* __restrict__ src,
+                                                        double2* __restrict__ dst, int64_t n2) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride)
+    dst[i] = src[i];
+}
+
+// Eight independent FP64 fused multiply-add chains per lane. Each chain
+// a <- a*b + (1 - b) contracts towards 1, so nothing overflows or becomes
+// subnormal; b differs per lane so the chains cannot be folded.
+__global__ __launch_bounds__(256) void peak_fma_kernel(double* out, int iters) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const double b = 0.999999 + 1e-9 * (double)(t & 7);
+  const double c = 1.0 - b;
+  double a[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k] = 1.0 + 0.001 * k + 1e-7 * (double)(t & 63);
+#pragma unroll 4
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = fma(a[k], b, c);
+  }
+  double sum = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sum += a[k];
+  out[t] = sum;
+}
+
+// Buffers, stream and events of one measurement, released on every exit.
+struct PeakScratch {
+  void* a = nullptr;
+  void* b = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~PeakScratch() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+  }
+};
+
+int peak_setup(PeakScratch& P, int* n_cu) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_TRY(hipStreamCreate(&P.s));
+  HIP_TRY(hipEventCreate(&P.e0));
+  HIP_TRY(hipEventCreate(&P.e1));
+  return ACOPF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int acopf_peak_hbm(int64_t bytes, int32_t iters, double* gbs) {
+  if (!gbs || bytes < (int64_t)1 << 20 || iters < 1)
+    return fail(ACOPF_EINVAL, "peak_hbm: needs bytes >= 1 MiB, iters >= 1 and an output");
+  PeakScratch P;
+  int n_cu = 0;
+  const int rc = peak_setup(P, &n_cu);
+  if (rc != ACOPF_OK) return rc;
+  const int64_t n2 = bytes / 16;
+  if (hipMalloc(&P.a, (size_t)n2 * 16) != hipSuccess || hipMalloc(&P.b, (size_t)n2 * 16) != hipSuccess)
+    return fail(ACOPF_ENOMEM, "peak_hbm: buffer allocation failed");
+  HIP_TRY(hipMemsetAsync(P.a, 0, (size_t)n2 * 16, P.s));
+  const dim3 grid(8 * n_cu), block(256);
+  const double2* src = static_cast<const double2*>(P.a);
+  double2* dst = static_cast<double2*>(P.b);
+  hipLaunchKernelGGL(peak_copy_kernel, grid, block, 0, P.s, src, dst, n2);  // warm-up
+  HIP_TRY(hipEventRecord(P.e0, P.s));
+  for (int i = 0; i < iters; ++i) hipLaunchKernelGGL(peak_copy_kernel, grid, block, 0, P.s, src, dst, n2);
+  HIP_TRY(hipEventRecord(P.e1, P.s));
+  HIP_TRY(hipEventSynchronize(P.e1));
+  HIP_TRY(hipGetLastError());
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, P.e0, P.e1));
+  if (!(ms > 0.0f)) return fail(ACOPF_EDEVICE, "peak_hbm: no elapsed time");
+  *gbs = 2.0 * 16.0 * (double)n2 * iters / (ms * 1e-3) / 1e9;
+  return ACOPF_OK;
+}
+
+int acopf_peak_fp64(int32_t iters, double* tflops) {
+  if (!tflops || iters < 1) return fail(ACOPF_EINVAL, "peak_fp64: needs iters >= 1 and an output");
+  PeakScratch P;
+  int n_cu = 0;
+  const int rc = peak_setup(P, &n_cu);
+  if (rc != ACOPF_OK) return rc;
+  const int blocks = 8 * n_cu, threads = 256;  // 8 wavefronts per SIMD
+  if (hipMalloc(&P.a, sizeof(double) * (size_t)blocks * threads) != hipSuccess)
+    return fail(ACOPF_ENOMEM, "peak_fp64: output allocation failed");
+  double* out = static_cast<double*>(P.a);
+  // warm-up of the same length, so the timed run starts at a steady clock
+  hipLaunchKernelGGL(peak_fma_kernel, dim3(blocks), dim3(threads), 0, P.s, out, iters);
+  HIP_TRY(hipEventRecord(P.e0, P.s));
+  hipLaunchKernelGGL(peak_fma_kernel, dim3(blocks), dim3(threads), 0, P.s, out, iters);
+  HIP_TRY(hipEventRecord(P.e1, P.s));
+  HIP_TRY(hipEventSynchronize(P.e1));
+  HIP_TRY(hipGetLastError());
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, P.e0, P.e1));
+  if (!(ms > 0.0f)) return fail(ACOPF_EDEVICE, "peak_fp64: no elapsed time");
+  *tflops = 2.0 * 8.0 * (double)blocks * threads * (double)iters / (ms * 1e-3) / 1e12;
+  return ACOPF_OK;
+}
+
+}  // extern "C"
