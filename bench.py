@@ -39,6 +39,18 @@ def sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def host_cpu_model() -> str:
+    """Model name of the host CPU (Linux), for the CPU baseline's record."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def measured_traffic():
     """HBM bytes per x-step launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, calibrated on a copy kernel), or None
@@ -188,7 +200,8 @@ def main():
                "cores": 1, "kind": "oracle",
                "sample": f"{args.cpu_iters} inner ADMM iterations of the 70k-bus grid "
                          f"(iterations {args.warmup + 1}-{args.warmup + args.cpu_iters}), "
-                         f"serial g++ -O2 oracle, {tc1 - tc0:.1f} s"}
+                         f"serial g++ -O2 oracle, {tc1 - tc0:.1f} s",
+               "cpu_model": host_cpu_model(), "host_threads": os.cpu_count()}
     s.close()
 
     out = {
