@@ -113,7 +113,7 @@ class Params:
     al_rho0: float = 10.0
     al_rho_growth: float = 10.0
     al_rho_max: float = 1e8
-    al_tol: float = 1e-7
+    al_tol: float = 1e-6
     al_shrink: float = 0.25
     al_maxit: int = 20
 

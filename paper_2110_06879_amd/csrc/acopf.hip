@@ -897,7 +897,7 @@ void acopf_default_params(acopf_params* p) {
   p->al_rho0 = 10.0;
   p->al_rho_growth = 10.0;
   p->al_rho_max = 1e8;
-  p->al_tol = 1e-7;
+  p->al_tol = 1e-6;
   p->al_shrink = 0.25;
   p->al_maxit = 20;
 }

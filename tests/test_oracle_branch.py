@@ -211,13 +211,16 @@ def test_branch_solve_6var_al_kkt_and_feasible_bruteforce():
     c = np.array([u[0] ** 2 + u[1] ** 2 + x[4], u[2] ** 2 + u[3] ** 2 + x[5]])
     assert np.abs(c).max() <= params.al_tol
     # constrained KKT: grad of the ADMM terms + mu * grad(p^2+q^2) = 0 on the
-    # voltage variables with mu = ltil >= 0 where the limit binds
+    # voltage variables, mu >= 0 where the limit binds. The AL subproblem's
+    # stationary point has mu = ltil + rtil c, the first-order multiplier
+    # estimate (the loop stops before applying that update to ltil).
+    mu = lt + rt * c
     f0, g0, _, a = O.branch_eval(data, 4, [0, 0], 0.0, x[:4])
-    assert lt.min() >= -1e-6
+    assert mu.min() >= -1e-6
     binding = x[4:] <= -rate2 + 1e-12
     assert binding.any()
-    _, g6, _, _ = O.branch_eval(data, 6, lt, 0.0, x)
-    # with rtil = 0 the gradient of F is grad(ADMM terms) + ltil grad(c)
+    _, g6, _, _ = O.branch_eval(data, 6, mu, 0.0, x)
+    # with rtil = 0 the gradient of F is grad(ADMM terms) + mu grad(c)
     assert np.abs(proj_grad(x[:4], g6[:4], lo[:4], hi[:4])).max() < 1e-5 * (1 + np.abs(g0).max())
     # brute force over feasible voltage points near the solution
     d = np.linspace(-3e-3, 3e-3, 17)
