@@ -165,6 +165,17 @@ def load() -> C.CDLL:
     lib.ora_model.restype = C.c_double
     lib.ora_branch_solve.argtypes = [dp, ip, dp, dp, dp, dp, dp, C.POINTER(_Params),
                                      C.POINTER(_Stats), ip]
+    lib.ora_set_textbook.argtypes = [vp, ip]
+    lib.ora_set_textbook.restype = None
+    lib.ora_branch_eval_textbook.argtypes = [dp, ip, dp, C.c_double, dp, dp, dp, dp, dp]
+    lib.ora_branch_eval_textbook.restype = None
+    lib.ora_branch_solve_textbook.argtypes = [dp, ip, dp, dp, dp, dp, dp,
+                                              C.POINTER(_Params), C.POINTER(_Stats)]
+    lib.ora_branch_solve_textbook.restype = None
+    lib.ora_chol_textbook.argtypes = [ip, dp, dp]
+    lib.ora_chol_textbook.restype = ip
+    lib.ora_precond_textbook.argtypes = [ip, dp, dp, dp, dp]
+    lib.ora_precond_textbook.restype = ip
     _lib = lib
     return lib
 
@@ -266,6 +277,12 @@ class Oracle:
     def count_flops(self, on: bool = True):
         self.lib.ora_set_count_flops(self.h, int(on))
 
+    def set_textbook(self, on: bool = True):
+        """Solve the branch subproblems by the textbook path (eq. branch
+        summed term by term, libm sin/cos, plain arithmetic, Lin & More's
+        scaled Cholesky preconditioner) instead of the fixed-sequence path."""
+        self.lib.ora_set_textbook(self.h, int(on))
+
     # stages of one inner iteration (Algorithm 1)
     def cold_init(self):
         self.lib.ora_cold_init(self.h)
@@ -337,7 +354,9 @@ def pack_branch(adm8, lo6, hi6, vb8, z8, y8, rho8) -> np.ndarray:
         [adm8, lo6, hi6, vb8, z8, y8, rho8]).astype(np.float64))
 
 
-def branch_eval(data: np.ndarray, n: int, ltil, rtil: float, x):
+def branch_eval(data: np.ndarray, n: int, ltil, rtil: float, x, textbook: bool = False):
+    """f, g, H and the coupling values a of eq. (branch) at x, on the
+    fixed-sequence path or (textbook=True) on the textbook path."""
     lib = load()
     x = np.ascontiguousarray(x, dtype=np.float64)
     lt = np.ascontiguousarray(ltil, dtype=np.float64)
@@ -345,18 +364,18 @@ def branch_eval(data: np.ndarray, n: int, ltil, rtil: float, x):
     g = np.zeros(n)
     H = np.zeros(n * n)
     a = np.zeros(8)
-    lib.ora_branch_eval(_dp(data), n, _dp(lt), float(rtil), _dp(x), _dp(f),
-                        _dp(g), _dp(H), _dp(a))
+    fn = lib.ora_branch_eval_textbook if textbook else lib.ora_branch_eval
+    fn(_dp(data), n, _dp(lt), float(rtil), _dp(x), _dp(f), _dp(g), _dp(H), _dp(a))
     return f[0], g, H.reshape(n, n), a
 
 
 def branch_solve(data: np.ndarray, n: int, x6, ltil, rtil: float,
                  params: OracleParams | None = None, count: bool = False,
-                 alpha: float = 1.0):
+                 alpha: float = 1.0, textbook: bool = False):
     """One branch solve from state (x6, ltil, rtil) with the trust-region
     Cauchy step length starting at `alpha`; returns the new x, ltil, rtil,
     the coupling values u and the counters (with the final step length under
-    "alpha")."""
+    "alpha"). textbook=True takes the textbook path (no flop counting)."""
     lib = load()
     p = (params or OracleParams()).c()
     x = np.ascontiguousarray(x6, dtype=np.float64).copy()
@@ -365,8 +384,12 @@ def branch_solve(data: np.ndarray, n: int, x6, ltil, rtil: float,
     al = np.array([alpha], dtype=np.float64)
     u = np.zeros(8)
     st = _Stats()
-    lib.ora_branch_solve(_dp(data), n, _dp(x), _dp(lt), _dp(rt), _dp(al), _dp(u),
-                         C.byref(p), C.byref(st), int(count))
+    if textbook:
+        lib.ora_branch_solve_textbook(_dp(data), n, _dp(x), _dp(lt), _dp(rt), _dp(al),
+                                      _dp(u), C.byref(p), C.byref(st))
+    else:
+        lib.ora_branch_solve(_dp(data), n, _dp(x), _dp(lt), _dp(rt), _dp(al), _dp(u),
+                             C.byref(p), C.byref(st), int(count))
     out = st.as_dict()
     out["alpha"] = float(al[0])
     return x, lt, rt[0], u, out
@@ -396,6 +419,28 @@ def ldlt_solve(L, rd, r):
     return z
 
 
+def chol_textbook(A):
+    """The textbook path's Cholesky factor L (A = L L'), or None at a
+    non-positive pivot."""
+    lib = load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    L = np.zeros((n, n))
+    ok = lib.ora_chol_textbook(n, _dp(A), _dp(L))
+    return L if ok == 1 else None
+
+
+def precond_textbook(L, D, r):
+    """z = D L'^-1 L^-1 D r, the textbook path's preconditioner solve."""
+    lib = load()
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    z = np.zeros_like(r)
+    lib.ora_precond_textbook(len(r), _dp(L), _dp(D), _dp(r), _dp(z))
+    return z
+
+
 def model(g, H, s):
     """The trust-region model q(s) = g's + s'Hs/2 as the oracle forms it."""
     lib = load()
@@ -419,8 +464,10 @@ _G_CB = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.POINTER(C.c_double),
                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p)
 
 
-def tron_generic(f, fgh, x0, lo, hi, params: OracleParams | None = None):
-    """Run the oracle's TRON on Python callbacks f(x) and fgh(x)->(f,g,H)."""
+def tron_generic(f, fgh, x0, lo, hi, params: OracleParams | None = None,
+                 textbook: bool = False):
+    """Run the oracle's TRON on Python callbacks f(x) and fgh(x)->(f,g,H),
+    on the fixed-sequence path or (textbook=True) on the textbook path."""
     lib = load()
     n = len(x0)
 
@@ -444,11 +491,13 @@ def tron_generic(f, fgh, x0, lo, hi, params: OracleParams | None = None):
                              _F_CB, _G_CB, C.c_void_p, C.POINTER(_Params),
                              C.POINTER(_Stats)]
     lib.ora_tron.restype = C.c_int
+    lib.ora_tron_textbook.argtypes = lib.ora_tron.argtypes
+    lib.ora_tron_textbook.restype = C.c_int
     x = np.ascontiguousarray(x0, dtype=np.float64).copy()
     lo = np.ascontiguousarray(lo, dtype=np.float64)
     hi = np.ascontiguousarray(hi, dtype=np.float64)
     p = (params or OracleParams()).c()
     st = _Stats()
-    status = lib.ora_tron(n, _dp(x), _dp(lo), _dp(hi), fcb, gcb, None,
-                          C.byref(p), C.byref(st))
+    fn = lib.ora_tron_textbook if textbook else lib.ora_tron
+    status = fn(n, _dp(x), _dp(lo), _dp(hi), fcb, gcb, None, C.byref(p), C.byref(st))
     return x, int(status), st.as_dict()

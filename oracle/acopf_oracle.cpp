@@ -782,9 +782,12 @@ void branch_solve_t(BranchData& d, double* x6, double* ltil, double* rtil,
       R c0 = rfma(a[0], a[0], a[1] * a[1]) + x[4];
       R c1 = rfma(a[2], a[2], a[3] * a[3]) + x[5];
       R cn = rmax(rabs(c0), rabs(c1));
-      if (cn <= R(prm.al_tol)) break;
+      // first-order multiplier estimate after every round, the last one
+      // included, so that the persisted ltil is the multiplier of the
+      // subproblem just solved
       d.ltil[0] = val(R(d.ltil[0]) + R(d.rtil) * c0);
       d.ltil[1] = val(R(d.ltil[1]) + R(d.rtil) * c1);
+      if (cn <= R(prm.al_tol)) break;
       if (cn > R(prm.al_shrink) * cprev)
         d.rtil = val(rmin(R(d.rtil) * R(prm.al_rho_growth), R(prm.al_rho_max)));
       cprev = cn;
@@ -798,6 +801,466 @@ void branch_solve_t(BranchData& d, double* x6, double* ltil, double* rtil,
   for (int k = 0; k < 8; ++k) u8[k] = val(a[k]);
   for (int i = 0; i < d.n; ++i) x6[i] = val(x[i]);
 }
+
+// ---------------------------------------------------------------------------
+// Textbook path: the same method evaluated a second way, in the form in which
+// the paper and Lin & More state it, so that the path above (which fixes one
+// IEEE operation sequence) can be checked against it by the CPU tests:
+//   * eq. (branch) summed term by term: F = sum_k y_k r_k + rho_k/2 r_k^2
+//     + sum_e ltil_e c_e + rtil/2 c_e^2, with the gradient and Hessian of
+//     each coupling value a_k written out from eqs. (pij)-(qji) and the chain
+//     rule applied per term (no grouping of terms);
+//   * sin and cos from the C library;
+//   * plain products and sums (no fused multiply-adds; the library is built
+//     without contraction), divisions, and square roots in the norm tests;
+//   * the full quadratic model g's + s'(Hs)/2;
+//   * the Lin & More preconditioner as they define it: the Cholesky factor
+//     L L' = D H_FF D + alpha I with D = diag(|H_ii|^(-1/2)) (1 where
+//     H_ii = 0), applied as z = D L'^-1 L^-1 D r.
+// The decisions of the method (Cauchy extrapolation or interpolation,
+// free sets, CG exits, the ratio test, the augmented-Lagrangian rounds) are
+// the same rules; only the arithmetic that feeds them differs, by rounding.
+// ---------------------------------------------------------------------------
+namespace tb {
+
+// Value, gradient and Hessian of one coupling quantity over the four voltage
+// variables (v_i, v_j, theta_i, theta_j).
+struct Quantity {
+  double a;
+  double g[4];
+  double H[4][4];
+};
+
+// One flow of eqs. (pij)-(qji) in the form
+//   a = alpha v_own^2 + v_i v_j (beta cos(theta_i - theta_j)
+//                                + gamma sin(theta_i - theta_j)),
+// own = 0 (v_i) or 1 (v_j): p_ij = g_ii w_i + g_ij w^R + b_ij w^I, etc.
+void flow(double alpha, double beta, double gamma, int own, const double* x,
+          Quantity& q) {
+  const double vi = x[0], vj = x[1];
+  const double d = x[2] - x[3];
+  const double c = std::cos(d), s = std::sin(d);
+  const double T = beta * c + gamma * s;    // d-part of the bracket
+  const double Td = -beta * s + gamma * c;  // its derivative in d
+  const double vo = own == 0 ? vi : vj;
+  q.a = alpha * vo * vo + vi * vj * T;
+  // first derivatives; d/dtheta_i = +d/dd, d/dtheta_j = -d/dd
+  q.g[0] = vj * T;
+  q.g[1] = vi * T;
+  q.g[2] = vi * vj * Td;
+  q.g[3] = -(vi * vj * Td);
+  q.g[own] = q.g[own] + 2.0 * alpha * vo;
+  // second derivatives (d2T/dd2 = -T)
+  for (int p = 0; p < 4; ++p)
+    for (int r = 0; r < 4; ++r) q.H[p][r] = 0.0;
+  q.H[0][1] = T;
+  q.H[0][2] = vj * Td;
+  q.H[0][3] = -(vj * Td);
+  q.H[1][2] = vi * Td;
+  q.H[1][3] = -(vi * Td);
+  q.H[2][2] = -(vi * vj * T);
+  q.H[2][3] = vi * vj * T;
+  q.H[3][3] = -(vi * vj * T);
+  for (int p = 0; p < 4; ++p)
+    for (int r = 0; r < p; ++r) q.H[p][r] = q.H[r][p];
+  q.H[own][own] = q.H[own][own] + 2.0 * alpha;
+}
+
+// The eight coupling quantities of branch (i, j): p_ij, q_ij, p_ji, q_ji
+// (eqs. pij-qji, with w^I_ji = -w^I_ij), then w_i = v_i^2, theta_i,
+// w_j = v_j^2, theta_j.
+void quantities(const BranchData& d, const double* x, Quantity* Q) {
+  flow(d.gii, d.gij, d.bij, 0, x, Q[0]);
+  flow(-d.bii, -d.bij, d.gij, 0, x, Q[1]);
+  flow(d.gjj, d.gji, -d.bji, 1, x, Q[2]);
+  flow(-d.bjj, -d.bji, -d.gji, 1, x, Q[3]);
+  for (int k = 4; k < 8; ++k) {
+    Q[k].a = 0.0;
+    for (int p = 0; p < 4; ++p) {
+      Q[k].g[p] = 0.0;
+      for (int r = 0; r < 4; ++r) Q[k].H[p][r] = 0.0;
+    }
+  }
+  Q[4].a = x[0] * x[0];
+  Q[4].g[0] = 2.0 * x[0];
+  Q[4].H[0][0] = 2.0;
+  Q[5].a = x[2];
+  Q[5].g[2] = 1.0;
+  Q[6].a = x[1] * x[1];
+  Q[6].g[1] = 2.0 * x[1];
+  Q[6].H[1][1] = 2.0;
+  Q[7].a = x[3];
+  Q[7].g[3] = 1.0;
+}
+
+// Eq. (branch) and, when g is non-null, its gradient and Hessian (row-major
+// n x n), summed term by term.
+double branch_fgh(const BranchData& d, const double* x, double* g, double* H) {
+  const int n = d.n;
+  Quantity Q[8];
+  quantities(d, x, Q);
+  double F = 0.0;
+  if (g)
+    for (int i = 0; i < n; ++i) {
+      g[i] = 0.0;
+      for (int j = 0; j < n; ++j) H[i * n + j] = 0.0;
+    }
+  // ADMM terms y_k r_k + rho_k/2 r_k^2, r_k = a_k - v_k + z_k
+  for (int k = 0; k < 8; ++k) {
+    const double r = Q[k].a - d.vb[k] + d.z[k];
+    F = F + d.y[k] * r + 0.5 * d.rho[k] * r * r;
+    if (!g) continue;
+    const double m = d.y[k] + d.rho[k] * r;  // dF/da_k
+    for (int p = 0; p < 4; ++p) {
+      g[p] = g[p] + m * Q[k].g[p];
+      for (int q = 0; q < 4; ++q)
+        H[p * n + q] = H[p * n + q] + d.rho[k] * Q[k].g[p] * Q[k].g[q] + m * Q[k].H[p][q];
+    }
+  }
+  if (n == 6) {
+    // line limits: c_e = p_e^2 + q_e^2 + s_e with ltil_e c_e + rtil/2 c_e^2
+    for (int e = 0; e < 2; ++e) {
+      const Quantity& P = Q[2 * e];
+      const Quantity& R = Q[2 * e + 1];
+      const int sv = 4 + e;
+      const double c = P.a * P.a + R.a * R.a + x[sv];
+      F = F + d.ltil[e] * c + 0.5 * d.rtil * c * c;
+      if (!g) continue;
+      const double m = d.ltil[e] + d.rtil * c;  // dF/dc_e
+      double gc[6] = {0, 0, 0, 0, 0, 0};
+      for (int p = 0; p < 4; ++p) gc[p] = 2.0 * P.a * P.g[p] + 2.0 * R.a * R.g[p];
+      gc[sv] = 1.0;
+      for (int p = 0; p < 6; ++p) {
+        g[p] = g[p] + m * gc[p];
+        for (int q = 0; q < 6; ++q) {
+          double hc = 0.0;  // Hessian of c_e (zero in the slack rows)
+          if (p < 4 && q < 4)
+            hc = 2.0 * P.g[p] * P.g[q] + 2.0 * P.a * P.H[p][q] +
+                 2.0 * R.g[p] * R.g[q] + 2.0 * R.a * R.H[p][q];
+          H[p * 6 + q] = H[p * 6 + q] + d.rtil * gc[p] * gc[q] + m * hc;
+        }
+      }
+    }
+  }
+  return F;
+}
+
+double proj(double t, double lo, double hi) { return t < lo ? lo : (t > hi ? hi : t); }
+
+double dot(int n, const double* a, const double* b) {
+  double t = 0.0;
+  for (int i = 0; i < n; ++i) t = t + a[i] * b[i];
+  return t;
+}
+
+double norm2(int n, const double* a) { return std::sqrt(dot(n, a, a)); }
+
+// q(s) = g's + s'(Hs)/2
+double model(int n, const double* g, const double* H, const double* s) {
+  double Hs[NMAX];
+  for (int i = 0; i < n; ++i) Hs[i] = dot(n, &H[i * n], s);
+  return dot(n, g, s) + 0.5 * dot(n, s, Hs);
+}
+
+// tau >= 0 with ||a + tau p|| = delta, in the cancellation-free form of
+// Lin & More's trust-region CG
+double to_boundary(int n, const double* a, const double* p, double delta) {
+  const double ap = dot(n, a, p), pp = dot(n, p, p), aa = dot(n, a, a);
+  double dd = delta * delta - aa;
+  if (dd < 0.0) dd = 0.0;
+  const double sq = std::sqrt(ap * ap + pp * dd);
+  if (ap >= 0.0) return ap + sq > 0.0 ? dd / (ap + sq) : 0.0;
+  return (sq - ap) / pp;
+}
+
+// Cholesky A = L L' (L lower, row-major m x m); false at a non-positive pivot.
+bool cholesky(int m, const double* A, double* L) {
+  for (int i = 0; i < m * m; ++i) L[i] = 0.0;
+  for (int j = 0; j < m; ++j) {
+    double d = A[j * m + j];
+    for (int k = 0; k < j; ++k) d = d - L[j * m + k] * L[j * m + k];
+    if (!(d > 0.0)) return false;
+    const double ljj = std::sqrt(d);
+    L[j * m + j] = ljj;
+    for (int i = j + 1; i < m; ++i) {
+      double t = A[i * m + j];
+      for (int k = 0; k < j; ++k) t = t - L[i * m + k] * L[j * m + k];
+      L[i * m + j] = t / ljj;
+    }
+  }
+  return true;
+}
+
+// z = M^-1 r for M = D^-1 L L' D^-1: z = D L'^-1 L^-1 D r.
+void precondition(int m, const double* L, const double* Dg, const double* r, double* z) {
+  double t[NMAX];
+  for (int i = 0; i < m; ++i) {
+    double a = Dg[i] * r[i];
+    for (int k = 0; k < i; ++k) a = a - L[i * m + k] * t[k];
+    t[i] = a / L[i * m + i];
+  }
+  for (int i = m - 1; i >= 0; --i) {
+    double a = t[i];
+    for (int k = i + 1; k < m; ++k) a = a - L[k * m + i] * z[k];
+    z[i] = a / L[i * m + i];
+  }
+  for (int i = 0; i < m; ++i) z[i] = Dg[i] * z[i];
+}
+
+void cauchy(int n, const double* x, const double* g, const double* H, const double* lo,
+            const double* hi, double delta, double& alpha, double* w, ora_stats* st,
+            const TronConst& C) {
+  // the projected path x(alpha) = P(x - alpha g) bends at its breakpoints;
+  // extrapolation stops beyond the largest one
+  double brpt = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double bp = 0.0;
+    if (g[i] > 0.0) bp = lo[i] == -INF ? INF : (x[i] - lo[i]) / g[i];
+    else if (g[i] < 0.0) bp = hi[i] == INF ? INF : (x[i] - hi[i]) / g[i];
+    if (bp > brpt) brpt = bp;
+  }
+  auto step = [&](double a, double* wo, double* so) {
+    for (int i = 0; i < n; ++i) {
+      wo[i] = proj(x[i] - a * g[i], lo[i], hi[i]);
+      so[i] = wo[i] - x[i];
+    }
+  };
+  // sufficient decrease of the model inside the trust region
+  auto ok = [&](const double* s) {
+    if (norm2(n, s) > delta) return false;
+    return model(n, g, H, s) <= C.mu0 * dot(n, g, s);
+  };
+  double s[NMAX], wt[NMAX], s2[NMAX];
+  step(alpha, w, s);
+  ++st->cauchy_trials;
+  if (ok(s)) {
+    for (int t = 0; t < C.max_trials; ++t) {
+      if (alpha > brpt) break;
+      const double a2 = alpha * C.extrapf;
+      step(a2, wt, s2);
+      ++st->cauchy_trials;
+      if (!ok(s2)) break;
+      alpha = a2;
+      for (int i = 0; i < n; ++i) w[i] = wt[i];
+    }
+  } else {
+    for (int t = 0; t < C.max_trials; ++t) {
+      alpha = alpha * C.interpf;
+      step(alpha, w, s);
+      ++st->cauchy_trials;
+      if (ok(s)) break;
+    }
+  }
+}
+
+void subspace(int n, const double* x, const double* g, const double* H, const double* lo,
+              const double* hi, double delta, double* w, ora_stats* st, const TronConst& C) {
+  double s[NMAX];
+  for (int i = 0; i < n; ++i) s[i] = w[i] - x[i];
+  for (int pass = 0; pass < n; ++pass) {
+    int F[NMAX], nf = 0;
+    for (int i = 0; i < n; ++i)
+      if (w[i] > lo[i] && w[i] < hi[i]) F[nf++] = i;
+    if (nf == 0) break;
+    // gradient of the model at w: g + H s
+    double gq[NMAX];
+    for (int i = 0; i < n; ++i) gq[i] = g[i] + dot(n, &H[i * n], s);
+    double r[NMAX], B[NMAX * NMAX];
+    for (int a = 0; a < nf; ++a) {
+      r[a] = -gq[F[a]];
+      for (int b = 0; b < nf; ++b) B[a * nf + b] = H[F[a] * n + F[b]];
+    }
+    const double r0 = norm2(nf, r);
+    if (!(r0 > 0.0)) break;
+    // Lin & More: L L' = D B D + shift I, D = diag(|B_aa|^(-1/2))
+    double Dg[NMAX], DBD[NMAX * NMAX], L[NMAX * NMAX];
+    for (int a = 0; a < nf; ++a) {
+      const double baa = B[a * nf + a];
+      Dg[a] = baa == 0.0 ? 1.0 : 1.0 / std::sqrt(std::fabs(baa));
+    }
+    double mind = INF;
+    for (int a = 0; a < nf; ++a)
+      for (int b = 0; b < nf; ++b) DBD[a * nf + b] = Dg[a] * B[a * nf + b] * Dg[b];
+    for (int a = 0; a < nf; ++a) mind = std::min(mind, DBD[a * nf + a]);
+    double shift = mind > 0.0 ? 0.0 : C.shift_min - mind;
+    bool fact = false;
+    for (int att = 0; att < C.max_chol; ++att) {
+      double A[NMAX * NMAX];
+      for (int q = 0; q < nf * nf; ++q) A[q] = DBD[q];
+      for (int a = 0; a < nf; ++a) A[a * nf + a] = A[a * nf + a] + shift;
+      ++st->chol_attempts;
+      if (cholesky(nf, A, L)) { fact = true; break; }
+      shift = std::max(2.0 * shift, C.shift_min);
+    }
+    if (!fact) {  // no factorization: unpreconditioned CG
+      for (int q = 0; q < nf * nf; ++q) L[q] = 0.0;
+      for (int a = 0; a < nf; ++a) { L[a * nf + a] = 1.0; Dg[a] = 1.0; }
+    }
+    // Steihaug's preconditioned CG on min d'Bd/2 - r'd within ||s + d|| <= delta
+    double d[NMAX], res[NMAX], zz[NMAX], p[NMAX], Bp[NMAX];
+    for (int a = 0; a < nf; ++a) { d[a] = 0.0; res[a] = r[a]; }
+    precondition(nf, L, Dg, res, zz);
+    for (int a = 0; a < nf; ++a) p[a] = zz[a];
+    double rz = dot(nf, res, zz);
+    bool boundary = false;
+    for (int k = 0; k < nf; ++k) {
+      ++st->cg_iters;
+      for (int a = 0; a < nf; ++a) Bp[a] = dot(nf, &B[a * nf], p);
+      const double pBp = dot(nf, p, Bp);
+      double sd[NMAX], pf[NMAX];  // s + d and p in the full space
+      for (int i = 0; i < n; ++i) { sd[i] = s[i]; pf[i] = 0.0; }
+      for (int a = 0; a < nf; ++a) { sd[F[a]] = s[F[a]] + d[a]; pf[F[a]] = p[a]; }
+      if (!(pBp > 0.0)) {  // negative curvature: to the boundary
+        const double tau = to_boundary(n, sd, pf, delta);
+        for (int a = 0; a < nf; ++a) d[a] = d[a] + tau * p[a];
+        boundary = true;
+        break;
+      }
+      const double alpha = rz / pBp;
+      double tr[NMAX];
+      for (int i = 0; i < n; ++i) tr[i] = sd[i] + alpha * pf[i];
+      if (norm2(n, tr) >= delta) {  // leaves the region: stop on the boundary
+        const double tau = to_boundary(n, sd, pf, delta);
+        for (int a = 0; a < nf; ++a) d[a] = d[a] + tau * p[a];
+        boundary = true;
+        break;
+      }
+      for (int a = 0; a < nf; ++a) {
+        d[a] = d[a] + alpha * p[a];
+        res[a] = res[a] - alpha * Bp[a];
+      }
+      if (norm2(nf, res) <= C.cgtol * r0) break;
+      precondition(nf, L, Dg, res, zz);
+      const double rzn = dot(nf, res, zz);
+      const double bcg = rzn / rz;
+      rz = rzn;
+      for (int a = 0; a < nf; ++a) p[a] = zz[a] + bcg * p[a];
+    }
+    // projected search along d from w, backtracking by halves
+    const double qw = model(n, g, H, s);
+    double beta = 1.0;
+    bool acc = false;
+    double wt[NMAX], stv[NMAX];
+    for (int t = 0; t < C.max_trials; ++t) {
+      ++st->ps_trials;
+      for (int i = 0; i < n; ++i) wt[i] = w[i];
+      for (int a = 0; a < nf; ++a) wt[F[a]] = proj(w[F[a]] + beta * d[a], lo[F[a]], hi[F[a]]);
+      double dw[NMAX];
+      for (int i = 0; i < n; ++i) { stv[i] = wt[i] - x[i]; dw[i] = wt[i] - w[i]; }
+      if (model(n, g, H, stv) <= qw + C.mu0 * dot(n, gq, dw)) { acc = true; break; }
+      beta = beta * 0.5;
+    }
+    if (!acc) break;
+    bool hit = false;  // a new bound became active
+    for (int a = 0; a < nf; ++a)
+      if (wt[F[a]] == lo[F[a]] || wt[F[a]] == hi[F[a]]) hit = true;
+    for (int i = 0; i < n; ++i) { w[i] = wt[i]; s[i] = stv[i]; }
+    if (boundary || !hit) break;
+  }
+}
+
+// Lin & More's trust-region Newton method for a bound-constrained problem
+// with f and (f, g, H) callbacks; alpha0 carries the Cauchy step length.
+template <class P>
+int tron(P& prob, int n, double* x, const double* lo, const double* hi,
+         const ora_params& prm, ora_stats* st, const TronConst& C, double* alpha0) {
+  ++st->tron_calls;
+  for (int i = 0; i < n; ++i) x[i] = proj(x[i], lo[i], hi[i]);
+  double f, g[NMAX], H[NMAX * NMAX];
+  prob.fgh(x, f, g, H);
+  ++st->n_fgh;
+  double pg[NMAX];
+  for (int i = 0; i < n; ++i) pg[i] = proj(x[i] - g[i], lo[i], hi[i]) - x[i];
+  double delta = norm2(n, pg);
+  if (!(delta > 0.0)) delta = 1.0;
+  double alphac = *alpha0;
+  int status = TRON_MAXIT;
+  for (int it = 0; it < prm.tron_maxit; ++it) {
+    double pginf = 0.0;  // infinity norm of the projected gradient
+    for (int i = 0; i < n; ++i)
+      pginf = std::max(pginf, std::fabs(proj(x[i] - g[i], lo[i], hi[i]) - x[i]));
+    if (pginf <= prm.tron_gtol) { status = TRON_CONVERGED; break; }
+    ++st->tron_iters;
+    double w[NMAX], s[NMAX];
+    cauchy(n, x, g, H, lo, hi, delta, alphac, w, st, C);
+    subspace(n, x, g, H, lo, hi, delta, w, st, C);
+    for (int i = 0; i < n; ++i) s[i] = w[i] - x[i];
+    const double prered = -model(n, g, H, s);
+    const double snorm = norm2(n, s);
+    if (!(prered > 0.0)) { status = TRON_STALL; break; }
+    if (snorm < delta && prered <= prm.tron_ftol * (1.0 + std::fabs(f))) {
+      for (int i = 0; i < n; ++i) x[i] = w[i];
+      status = TRON_CONVERGED;
+      break;
+    }
+    const double fw = prob.f(w);
+    ++st->n_f;
+    const double ratio = (f - fw) / prered;
+    if (ratio <= C.eta0) delta = C.sigma2 * std::min(snorm, delta);
+    else if (ratio <= C.eta1) delta = std::max(C.sigma1 * delta, C.sigma2 * std::min(snorm, delta));
+    else if (ratio >= C.eta2) delta = std::min(C.sigma3 * delta, std::max(delta, C.sigma3 * snorm));
+    if (ratio > C.eta0) {
+      for (int i = 0; i < n; ++i) x[i] = w[i];
+      prob.fgh(x, f, g, H);
+      ++st->n_fgh;
+    }
+    if (delta <= 1e-15 * std::max(1.0, norm2(n, x))) { status = TRON_STALL; break; }
+  }
+  *alpha0 = alphac;
+  if (status == TRON_CONVERGED) ++st->tron_converged;
+  else if (status == TRON_MAXIT) ++st->tron_maxit;
+  else ++st->tron_stall;
+  return status;
+}
+
+struct Problem {
+  const BranchData& d;
+  double f(const double* x) { return branch_fgh(d, x, nullptr, nullptr); }
+  void fgh(const double* x, double& F, double* g, double* H) { F = branch_fgh(d, x, g, H); }
+};
+
+// The branch solve of Sec. II-C and III-B as above (one trust-region solve,
+// or the augmented-Lagrangian rounds on the line limits around it).
+void branch_solve(BranchData& d, double* x6, double* ltil, double* rtil, double* alpha,
+                  double* u8, const ora_params& prm, ora_stats* st) {
+  TronConst C;
+  ++st->branch_solves;
+  double x[NMAX];
+  for (int i = 0; i < d.n; ++i) x[i] = x6[i];
+  if (d.n == 4) {
+    Problem P{d};
+    tron(P, 4, x, d.lo, d.hi, prm, st, C, alpha);
+  } else {
+    d.ltil[0] = ltil[0];
+    d.ltil[1] = ltil[1];
+    d.rtil = *rtil;
+    double cprev = INF;
+    for (int t = 0; t < prm.al_maxit; ++t) {
+      ++st->al_iters;
+      Problem P{d};
+      tron(P, 6, x, d.lo, d.hi, prm, st, C, alpha);
+      Quantity Q[8];
+      quantities(d, x, Q);
+      const double c0 = Q[0].a * Q[0].a + Q[1].a * Q[1].a + x[4];
+      const double c1 = Q[2].a * Q[2].a + Q[3].a * Q[3].a + x[5];
+      const double cn = std::max(std::fabs(c0), std::fabs(c1));
+      d.ltil[0] = d.ltil[0] + d.rtil * c0;
+      d.ltil[1] = d.ltil[1] + d.rtil * c1;
+      if (cn <= prm.al_tol) break;
+      if (cn > prm.al_shrink * cprev) d.rtil = std::min(d.rtil * prm.al_rho_growth, prm.al_rho_max);
+      cprev = cn;
+    }
+    ltil[0] = d.ltil[0];
+    ltil[1] = d.ltil[1];
+    *rtil = d.rtil;
+  }
+  Quantity Q[8];
+  quantities(d, x, Q);
+  for (int k = 0; k < 8; ++k) u8[k] = Q[k].a;
+  for (int i = 0; i < d.n; ++i) x6[i] = x[i];
+}
+
+}  // namespace tb
 
 // ---------------------------------------------------------------------------
 // Whole-grid state
@@ -827,6 +1290,7 @@ struct Oracle {
   std::vector<double> hist;  // per inner iteration: r_pri r_dual r_z obj beta outer
   ora_stats st{};
   bool count_flops = false;
+  bool textbook = false;  // branch solves by the textbook path (namespace tb)
 };
 
 int coupling_gen(int g, int k) { return 2 * g + k; }
@@ -1025,7 +1489,10 @@ void ora_branch_step(void* h) {
     BranchData d;
     fill_branch_data(o, l, d);
     double* u8 = &o->u[2 * o->ng + 8 * l];
-    if (o->count_flops) {
+    if (o->textbook) {
+      tb::branch_solve(d, &o->bx[6 * l], &o->ltil[2 * l], &o->rtil[l], &o->calpha[l], u8,
+                       o->p, &o->st);
+    } else if (o->count_flops) {
       FlopTally before = g_tally;
       branch_solve_t<CR>(d, &o->bx[6 * l], &o->ltil[2 * l], &o->rtil[l],
                          &o->calpha[l], u8, o->p, &o->st);
@@ -1402,6 +1869,9 @@ void ora_get_admittance(void* h, double* out9nl) {
 void ora_get_stats(void* h, ora_stats* out) { *out = static_cast<Oracle*>(h)->st; }
 void ora_reset_stats(void* h) { static_cast<Oracle*>(h)->st = ora_stats{}; }
 void ora_set_count_flops(void* h, int on) { static_cast<Oracle*>(h)->count_flops = on != 0; }
+// Branch solves of the whole-grid iteration by the textbook path (on != 0) or
+// by the fixed-sequence path (0, the default).
+void ora_set_textbook(void* h, int on) { static_cast<Oracle*>(h)->textbook = on != 0; }
 
 // --- single-branch entry points for tests ----------------------------------
 // data layout (doubles): [gii bii gij bij gji bji gjj bjj, lo[6], hi[6],
@@ -1433,6 +1903,30 @@ void ora_branch_eval(const double* data, int n, const double* ltil,
   P.fgh(x, F, g, H);
   *f = F;
   if (a8) branch_values<double>(d, x, a8, nullptr);
+}
+
+// The same two entry points on the textbook path.
+void ora_branch_eval_textbook(const double* data, int n, const double* ltil, double rtil,
+                              const double* x, double* f, double* g, double* H, double* a8) {
+  BranchData d;
+  unpack_branch(data, n, d);
+  d.ltil[0] = ltil[0];
+  d.ltil[1] = ltil[1];
+  d.rtil = rtil;
+  *f = tb::branch_fgh(d, x, g, H);
+  if (a8) {
+    tb::Quantity Q[8];
+    tb::quantities(d, x, Q);
+    for (int k = 0; k < 8; ++k) a8[k] = Q[k].a;
+  }
+}
+
+void ora_branch_solve_textbook(const double* data, int n, double* x6, double* ltil,
+                               double* rtil, double* alpha, double* u8, const ora_params* P,
+                               ora_stats* st) {
+  BranchData d;
+  unpack_branch(data, n, d);
+  tb::branch_solve(d, x6, ltil, rtil, alpha, u8, *P, st);
 }
 
 void ora_branch_solve(const double* data, int n, double* x6, double* ltil,
@@ -1486,6 +1980,19 @@ double ora_model(int n, const double* g, const double* H, const double* s) {
   return model_q<double>(n, g, H, s);
 }
 
+// The textbook path's Cholesky factor (returns 1, or 0 at a non-positive
+// pivot) and its preconditioner z = D L'^-1 L^-1 D r.
+int ora_chol_textbook(int n, const double* A, double* L) {
+  if (n < 1 || n > NMAX) return -1;
+  return tb::cholesky(n, A, L) ? 1 : 0;
+}
+
+int ora_precond_textbook(int n, const double* L, const double* D, const double* r, double* z) {
+  if (n < 1 || n > NMAX) return -1;
+  tb::precondition(n, L, D, r, z);
+  return 0;
+}
+
 int ora_tron(int n, double* x, const double* lo, const double* hi,
              ora_f_cb fcb, ora_fgh_cb gcb, void* ctx, const ora_params* P,
              ora_stats* st) {
@@ -1494,6 +2001,15 @@ int ora_tron(int n, double* x, const double* lo, const double* hi,
   TronConst C;
   double alpha = 1.0;
   return tron<double>(prob, n, x, lo, hi, *P, st, C, &alpha);
+}
+
+int ora_tron_textbook(int n, double* x, const double* lo, const double* hi, ora_f_cb fcb,
+                      ora_fgh_cb gcb, void* ctx, const ora_params* P, ora_stats* st) {
+  if (n < 1 || n > NMAX) return -1;
+  CbProblem prob{fcb, gcb, ctx};
+  TronConst C;
+  double alpha = 1.0;
+  return tb::tron(prob, n, x, lo, hi, *P, st, C, &alpha);
 }
 
 }  // extern "C"

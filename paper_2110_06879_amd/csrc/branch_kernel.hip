@@ -1128,10 +1128,12 @@ __device__ bool solve_branch(const BranchArgs& A, int64_t l, Cnt& cnt) {
         const double c1 = fma(a[2], a[2], a[3] * a[3]) + x[5];
         cnt.flops += 8;
         const double cn = fabs(c0) > fabs(c1) ? fabs(c0) : fabs(c1);
-        if (cn <= A.al_tol) break;
+        // multiplier estimate after every round, the last one included
         B.lt0 = B.lt0 + B.rt * c0;
         B.lt1 = B.lt1 + B.rt * c1;
-        cnt.flops += 5;
+        cnt.flops += 4;
+        if (cn <= A.al_tol) break;
+        cnt.flops += 1;
         if (cn > A.al_shrink * cprev) {
           const double gr = B.rt * A.al_rho_growth;
           B.rt = gr < A.al_rho_max ? gr : A.al_rho_max;
@@ -1291,10 +1293,11 @@ __device__ void run_pool(const BranchArgs& A, int64_t begin, int64_t end, unsign
       const double c1 = fma(a[2], a[2], a[3] * a[3]) + S.x[5];
       cnt.flops += 8;
       const double cn = fabs(c0) > fabs(c1) ? fabs(c0) : fabs(c1);
+      B.lt0 = B.lt0 + B.rt * c0;
+      B.lt1 = B.lt1 + B.rt * c1;
+      cnt.flops += 4;
       if (!(cn <= A.al_tol)) {
-        B.lt0 = B.lt0 + B.rt * c0;
-        B.lt1 = B.lt1 + B.rt * c1;
-        cnt.flops += 5;
+        cnt.flops += 1;
         if (cn > A.al_shrink * cprev) {
           const double gr = B.rt * A.al_rho_growth;
           B.rt = gr < A.al_rho_max ? gr : A.al_rho_max;

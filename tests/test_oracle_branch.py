@@ -211,10 +211,10 @@ def test_branch_solve_6var_al_kkt_and_feasible_bruteforce():
     c = np.array([u[0] ** 2 + u[1] ** 2 + x[4], u[2] ** 2 + u[3] ** 2 + x[5]])
     assert np.abs(c).max() <= params.al_tol
     # constrained KKT: grad of the ADMM terms + mu * grad(p^2+q^2) = 0 on the
-    # voltage variables, mu >= 0 where the limit binds. The AL subproblem's
-    # stationary point has mu = ltil + rtil c, the first-order multiplier
-    # estimate (the loop stops before applying that update to ltil).
-    mu = lt + rt * c
+    # voltage variables, mu >= 0 where the limit binds. The stored ltil is
+    # the first-order multiplier estimate ltil + rtil c of the last AL round
+    # (the update is applied after every round, the last one included).
+    mu = lt
     f0, g0, _, a = O.branch_eval(data, 4, [0, 0], 0.0, x[:4])
     assert mu.min() >= -1e-6
     binding = x[4:] <= -rate2 + 1e-12

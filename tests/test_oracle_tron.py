@@ -8,6 +8,8 @@
   and a brute-force grid check of local minimality;
 * Rosenbrock's function in a box containing (1, 1): the known minimizer;
   and in a box excluding it: the KKT conditions;
+* every one of the above on both the fixed-sequence path and the textbook
+  path of the oracle;
 * its building blocks on their own: the square-root-free Cholesky factors
   L E L' against numpy's Cholesky (L sqrt(E)) and the matrix itself, the
   solve with them against numpy.linalg.solve, a non-positive pivot reported
@@ -62,8 +64,9 @@ def quad_cbs(Q, c):
     return f, fgh
 
 
+@pytest.mark.parametrize("textbook", [False, True])
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
-def test_tron_matches_exact_box_qp(n):
+def test_tron_matches_exact_box_qp(n, textbook):
     rng = np.random.default_rng(100 + n)
     p = O.OracleParams(tron_gtol=1e-12, tron_ftol=1e-16)
     for trial in range(6):
@@ -77,13 +80,14 @@ def test_tron_matches_exact_box_qp(n):
         x_star = exact_box_qp(Q, c, lo, hi)
         f, fgh = quad_cbs(Q, c)
         x0 = rng.uniform(lo, hi)
-        x, status, st = O.tron_generic(f, fgh, x0, lo, hi, p)
+        x, status, st = O.tron_generic(f, fgh, x0, lo, hi, p, textbook=textbook)
         assert status == 0
         scale = 1 + np.abs(x_star).max()
         np.testing.assert_allclose(x, x_star, rtol=0, atol=1e-7 * scale)
 
 
-def test_tron_nonconvex_quadratic_local_min():
+@pytest.mark.parametrize("textbook", [False, True])
+def test_tron_nonconvex_quadratic_local_min(textbook):
     rng = np.random.default_rng(7)
     n = 5
     p = O.OracleParams(tron_gtol=1e-11, tron_ftol=1e-16)
@@ -93,7 +97,7 @@ def test_tron_nonconvex_quadratic_local_min():
         c = rng.normal(size=n)
         lo, hi = -np.ones(n), np.ones(n)
         f, fgh = quad_cbs(Q, c)
-        x, status, st = O.tron_generic(f, fgh, np.zeros(n), lo, hi, p)
+        x, status, st = O.tron_generic(f, fgh, np.zeros(n), lo, hi, p, textbook=textbook)
         assert status in (0, 2)
         g = Q @ x + c
         pg = np.clip(x - g, lo, hi) - x
@@ -124,31 +128,37 @@ def rosen_fgh(x):
     return rosen(x), g, H
 
 
-def test_tron_rosenbrock_interior_minimum():
+@pytest.mark.parametrize("textbook", [False, True])
+def test_tron_rosenbrock_interior_minimum(textbook):
     p = O.OracleParams(tron_gtol=1e-10, tron_ftol=1e-18, tron_maxit=500)
     x, status, st = O.tron_generic(rosen, rosen_fgh, np.array([-1.2, 1.0]),
-                                   np.array([-2.0, -2.0]), np.array([2.0, 2.0]), p)
+                                   np.array([-2.0, -2.0]), np.array([2.0, 2.0]), p,
+                                   textbook=textbook)
     assert status == 0
     np.testing.assert_allclose(x, [1.0, 1.0], atol=1e-8)
 
 
-def test_tron_rosenbrock_bound_active():
+@pytest.mark.parametrize("textbook", [False, True])
+def test_tron_rosenbrock_bound_active(textbook):
     # box excludes (1,1): x0 <= 0.5. KKT: at x0 = 0.5 the minimizer over x1
     # is x1 = 0.25 and df/dx0 there must be <= 0.
     p = O.OracleParams(tron_gtol=1e-10, tron_ftol=1e-18, tron_maxit=500)
     lo, hi = np.array([-2.0, -2.0]), np.array([0.5, 2.0])
-    x, status, st = O.tron_generic(rosen, rosen_fgh, np.array([-1.2, 1.0]), lo, hi, p)
+    x, status, st = O.tron_generic(rosen, rosen_fgh, np.array([-1.2, 1.0]), lo, hi, p,
+                                   textbook=textbook)
     np.testing.assert_allclose(x, [0.5, 0.25], atol=1e-8)
     g = rosen_fgh(x)[1]
     assert g[0] <= 0.0
 
 
-def test_tron_starting_at_solution_takes_no_step():
+@pytest.mark.parametrize("textbook", [False, True])
+def test_tron_starting_at_solution_takes_no_step(textbook):
     Q = np.diag([2.0, 3.0])
     c = np.array([-2.0, -3.0])
     f, fgh = quad_cbs(Q, c)
     x, status, st = O.tron_generic(f, fgh, np.array([1.0, 1.0]),
-                                   np.array([-5.0, -5.0]), np.array([5.0, 5.0]))
+                                   np.array([-5.0, -5.0]), np.array([5.0, 5.0]),
+                                   textbook=textbook)
     assert status == 0 and st["tron_iters"] == 0
     np.testing.assert_array_equal(x, [1.0, 1.0])
 
