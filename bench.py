@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--trials", type=int, default=100, help="warm-start trials (seeds 3001...)")
     ap.add_argument("--cpu-iters", type=int, default=100, help="oracle iterations for cpu_baseline (about 10 s)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-full-load", action="store_true",
+                    help="skip the record at the stated load distribution")
     ap.add_argument("--profile-only", action="store_true",
                     help="warmup + timed steps only (short run for rocprofv3)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -147,15 +149,28 @@ def main():
     tim = s.timing()
     flops = st1["flops"] - st0["flops"]
     solves = st1["branch_solves"] - st0["branch_solves"]
+    al_rounds = st1["al_iters"] - st0["al_iters"]
     launches = tim["iters"]
     x_ms = tim["xstep_ms"]
     flops_per_launch = flops / max(launches, 1)
     achieved_tflops = flops_per_launch / (x_ms * 1e-3) / 1e12
+    # algorithmic bytes of one x-step launch (each array once): 32 B per
+    # coupling (read v, z, y; write u), 96 B per branch of data (8
+    # admittances, 4 voltage bounds) + 8 B per rated branch (its rating),
+    # branch state read and written (x, ltil, rtil: 144 B per rated branch,
+    # x: 64 B per unlimited branch), 48 B per generator (6 parameters)
+    m = g.n_coupling
+    x_bytes = (32 * m + 96 * n_branch + 8 * g.n_rated + 144 * g.n_rated
+               + 64 * (n_branch - g.n_rated) + 48 * g.n_gen)
+    x_gbs = x_bytes / (x_ms * 1e-3) / 1e9
+    intensity = flops_per_launch / x_bytes
+    ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    frac_hbm = x_gbs / HBM_PEAK_GBS
+    frac_fp64 = achieved_tflops / FP64_PEAK_TFLOPS
     # algorithmic bytes of the bus/z/y step (HBM bound), per launch: every
     # coupling reads u, z, y, v, lambda and writes v, z, y (64 B); every bus
     # reads p_d, q_d, g_s, b_s, its reference flag, grid id and two CSR
     # offsets (48 B)
-    m = g.n_coupling
     bus_bytes = 64 * m + 48 * g.n_bus
     bus_gbs = bus_bytes / (tim["bus_ms"] * 1e-3) / 1e9
 
@@ -185,22 +200,67 @@ def main():
     hbm_meas = A.peak_hbm(1 << 30, 20)
     fp64_meas = A.peak_fp64(200000)
 
-    # ---- CPU baseline: the oracle, serial, on its own cold start; the warmup
-    # iterations are run untimed, then the same iterations as the timed steps
+    # ---- the same workload at the stated load distribution (load factor 1,
+    # 0.75 guard): fixed iterations, where line limits bind
+    full = None
+    if not args.no_full_load:
+        s.close()
+        gf = config_grid("c3_70kbus_full")
+        s = A.Solver(gf, params, device=0)
+        s.solve(A.COLD, args.warmup)
+        torch.cuda.synchronize()
+        tf0 = time.perf_counter()
+        s.solve(A.CONTINUE, args.steps)
+        torch.cuda.synchronize()
+        tf1 = time.perf_counter()
+        s.solve(A.COLD, args.warmup)
+        s.set_counting(True)
+        sf0 = s.stats()
+        s.solve(A.CONTINUE, args.steps)
+        sf1 = s.stats()
+        s.set_counting(False)
+        s.solve(A.COLD, args.warmup)
+        s.set_profiling(True)
+        s.solve(A.CONTINUE, args.steps)
+        s.set_profiling(False)
+        timf = s.timing()
+        full = {"workload": "the 70k-bus grid at the stated load distribution Pd ~ U(0, 0.5) "
+                            "(load factor 1, then the 0.75 total-load guard: x"
+                            f"{gf.load_scale:.4f}); iterations {args.warmup + 1}-"
+                            f"{args.warmup + args.steps} from the cold start",
+                "value": gf.n_branch * args.steps / (tf1 - tf0), "unit": "branch solves/s",
+                "ms_per_step": (tf1 - tf0) / args.steps * 1e3, "per_kernel_ms": timf,
+                "xstep_flops_per_launch": (sf1["flops"] - sf0["flops"]) / args.steps,
+                "al_rounds_per_rated_solve": (sf1["al_iters"] - sf0["al_iters"])
+                / (gf.n_rated * args.steps)}
+
+    # ---- CPU baseline: the oracle on its own cold start; the warmup
+    # iterations are run untimed, then the timed iterations, once on all the
+    # host threads this process may use (OpenMP over the generator, branch,
+    # bus and coupling loops, bitwise the serial results) and once serially
     cpu = None
     if not args.no_cpu:
         import oracle as O
         from dataclasses import asdict
+        threads = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
         orc = O.Oracle(g, O.OracleParams(**asdict(params)))
+        orc.set_threads(threads)
         orc.solve(args.warmup)
         tc0 = time.perf_counter()
         orc.solve(args.cpu_iters)
         tc1 = time.perf_counter()
+        orc = O.Oracle(g, O.OracleParams(**asdict(params)))
+        orc.solve(args.warmup)
+        ts0 = time.perf_counter()
+        orc.solve(args.cpu_iters)
+        ts1 = time.perf_counter()
         cpu = {"value": n_branch * args.cpu_iters / (tc1 - tc0), "unit": "branch solves/s",
-               "cores": 1, "kind": "oracle",
+               "cores": threads, "kind": "oracle",
                "sample": f"{args.cpu_iters} inner ADMM iterations of the 70k-bus grid "
                          f"(iterations {args.warmup + 1}-{args.warmup + args.cpu_iters}), "
-                         f"serial g++ -O2 oracle, {tc1 - tc0:.1f} s",
+                         f"g++ -O2 oracle, OpenMP over {threads} threads, {tc1 - tc0:.2f} s",
+               "serial": {"value": n_branch * args.cpu_iters / (ts1 - ts0), "cores": 1,
+                          "seconds": ts1 - ts0},
                "cpu_model": host_cpu_model(), "host_threads": os.cpu_count()}
     s.close()
 
@@ -222,14 +282,25 @@ def main():
                    "n_bus": g.n_bus, "n_gen": g.n_gen, "n_branch": n_branch,
                    "n_rated": g.n_rated, "step": "one inner ADMM iteration (all kernels)",
                    "tuning": tuning},
-        "roofline": {"bound": "alu", "kernel": "xstep_kernel (branch TRON + generators)",
-                     "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / FP64_PEAK_TFLOPS, "traffic": measured_traffic(),
-                     "traffic_unit": "bytes per launch", "kernel_sources": sources_hash(),
-                     "flops_per_launch": flops_per_launch, "launch_ms": x_ms,
+        "roofline": {"bound": "hbm" if intensity < ridge else "alu",
+                     "kernel": "xstep_kernel (branch TRON + generators)",
+                     "achieved": x_gbs if intensity < ridge else achieved_tflops,
+                     "peak": HBM_PEAK_GBS if intensity < ridge else FP64_PEAK_TFLOPS,
+                     "unit": "GB/s" if intensity < ridge else "TFLOP/s",
+                     "frac": frac_hbm if intensity < ridge else frac_fp64,
+                     "traffic": measured_traffic(), "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes": x_bytes, "flops_per_launch": flops_per_launch,
+                     "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
+                     "frac_hbm": frac_hbm, "frac_fp64": frac_fp64,
+                     "achieved_GBs": x_gbs, "achieved_TFLOPs": achieved_tflops,
+                     "kernel_sources": sources_hash(), "launch_ms": x_ms,
                      "launches": launches, "branch_solves_per_launch": solves / max(launches, 1),
-                     "measured_peak": fp64_meas, "frac_of_measured": achieved_tflops / fp64_meas},
+                     "al_rounds_per_rated_solve": al_rounds / max(g.n_rated * launches, 1),
+                     "measured_peaks": {"hbm_GBs": hbm_meas, "fp64_TFLOPs": fp64_meas},
+                     "frac_of_measured_hbm": x_gbs / hbm_meas,
+                     "frac_of_measured_fp64": achieved_tflops / fp64_meas},
         "per_kernel_ms": tim,
+        "kernel_sum_ms": tim["xstep_ms"] + tim["bus_ms"] + tim["ctl_ms"],
         "branch_kernel_solves_per_s": solves / max(launches, 1) / (x_ms * 1e-3),
         "bus_step": {"bound": "hbm", "algorithmic_bytes": bus_bytes, "ms": tim["bus_ms"],
                      "achieved_GBs": bus_gbs, "frac": bus_gbs / HBM_PEAK_GBS,
@@ -248,6 +319,7 @@ def main():
                        "converged": int(sum(1 for x in statuses if x == 0)),
                        "max_violation_p50": percentile(viol, 50),
                        "max_violation_max": float(np.max(viol))},
+        "full_load": full,
         "cpu_baseline": cpu,
         "device": dev_name,
     }

@@ -30,7 +30,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
     tmp = _LIB_PATH + ".tmp"
     cmd = ["g++", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c++17",
-           "-mfma", "-fPIC", "-shared", "-o", tmp, _SRC]
+           "-mfma", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC]
     out = subprocess.run(cmd, capture_output=True, text=True)
     if out.returncode != 0:
         raise RuntimeError("oracle build failed:\n" + out.stderr)
@@ -165,6 +165,8 @@ def load() -> C.CDLL:
     lib.ora_model.restype = C.c_double
     lib.ora_branch_solve.argtypes = [dp, ip, dp, dp, dp, dp, dp, C.POINTER(_Params),
                                      C.POINTER(_Stats), ip]
+    lib.ora_set_threads.argtypes = [vp, ip]
+    lib.ora_set_threads.restype = None
     lib.ora_set_textbook.argtypes = [vp, ip]
     lib.ora_set_textbook.restype = None
     lib.ora_branch_eval_textbook.argtypes = [dp, ip, dp, C.c_double, dp, dp, dp, dp, dp]
@@ -276,6 +278,12 @@ class Oracle:
 
     def count_flops(self, on: bool = True):
         self.lib.ora_set_count_flops(self.h, int(on))
+
+    def set_threads(self, n: int):
+        """OpenMP threads for the loops over generators, branches, buses and
+        couplings (1: serial, the default). Results are bitwise the same for
+        any count."""
+        self.lib.ora_set_threads(self.h, int(n))
 
     def set_textbook(self, on: bool = True):
         """Solve the branch subproblems by the textbook path (eq. branch

@@ -8,9 +8,11 @@
 // constant with the HIP library: it is written from the paper (and from Lin &
 // More 1999 for the trust-region Newton method) on its own.
 //
-// Build: g++ -O2 -ffp-contract=off -fno-fast-math -mfma -fPIC -shared: no
-// implicit contraction; the fused multiply-adds written out below (std::fma)
-// are correctly rounded whether done by the FMA instruction or the library;
+// Build: g++ -O2 -ffp-contract=off -fno-fast-math -mfma -fopenmp -fPIC
+// -shared: no implicit contraction; OpenMP only for the optional parallel
+// loops over independent elements (ora_set_threads; serial by default); the
+// fused multiply-adds written out below (std::fma) are correctly rounded
+// whether done by the FMA instruction or the library;
 // IEEE division and square root; sin/cos of branch angles by the series
 // below.
 //
@@ -32,6 +34,9 @@
 #include <cstring>
 #include <limits>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace {
 
@@ -1291,6 +1296,7 @@ struct Oracle {
   ora_stats st{};
   bool count_flops = false;
   bool textbook = false;  // branch solves by the textbook path (namespace tb)
+  int threads = 1;        // OpenMP threads of the per-element loops (1: serial)
 };
 
 int coupling_gen(int g, int k) { return 2 * g + k; }
@@ -1470,6 +1476,7 @@ void ora_cold_init(void* h) {
 void ora_gen_step(void* h) {
   auto* o = static_cast<Oracle*>(h);
   const double B = o->base, s = o->p.obj_scale;
+#pragma omp parallel for num_threads(o->threads) if (o->threads > 1) schedule(static)
   for (int g = 0; g < o->ng; ++g) {
     int kp = 2 * g, kq = 2 * g + 1;
     double Qp = 2.0 * s * o->c2[g] * B * B + o->rho[kp];
@@ -1483,8 +1490,45 @@ void ora_gen_step(void* h) {
   }
 }
 
+static void add_stats(ora_stats& a, const ora_stats& b) {
+  a.branch_solves += b.branch_solves; a.tron_calls += b.tron_calls;
+  a.tron_iters += b.tron_iters; a.n_fgh += b.n_fgh; a.n_f += b.n_f;
+  a.cauchy_trials += b.cauchy_trials; a.cg_iters += b.cg_iters;
+  a.chol_attempts += b.chol_attempts; a.ps_trials += b.ps_trials;
+  a.al_iters += b.al_iters; a.tron_converged += b.tron_converged;
+  a.tron_maxit += b.tron_maxit; a.tron_stall += b.tron_stall;
+  a.flops += b.flops; a.trig += b.trig;
+}
+
 void ora_branch_step(void* h) {
   auto* o = static_cast<Oracle*>(h);
+  if (o->threads > 1 && !o->count_flops) {
+    // branches are independent: each thread keeps its own event counters,
+    // which are integer sums (the same totals in any order)
+    std::vector<ora_stats> part(o->threads, ora_stats{});
+#pragma omp parallel num_threads(o->threads)
+    {
+#ifdef _OPENMP
+      ora_stats& st = part[omp_get_thread_num()];
+#else
+      ora_stats& st = part[0];
+#endif
+#pragma omp for schedule(dynamic, 64)
+      for (int l = 0; l < o->nl; ++l) {
+        BranchData d;
+        fill_branch_data(o, l, d);
+        double* u8 = &o->u[2 * o->ng + 8 * l];
+        if (o->textbook)
+          tb::branch_solve(d, &o->bx[6 * l], &o->ltil[2 * l], &o->rtil[l], &o->calpha[l], u8,
+                           o->p, &st);
+        else
+          branch_solve_t<double>(d, &o->bx[6 * l], &o->ltil[2 * l], &o->rtil[l],
+                                 &o->calpha[l], u8, o->p, &st);
+      }
+    }
+    for (const ora_stats& st : part) add_stats(o->st, st);
+    return;
+  }
   for (int l = 0; l < o->nl; ++l) {
     BranchData d;
     fill_branch_data(o, l, d);
@@ -1514,6 +1558,7 @@ void ora_branch_step(void* h) {
 void ora_bus_step(void* h) {
   auto* o = static_cast<Oracle*>(h);
   const int ng = o->ng;
+#pragma omp parallel for num_threads(o->threads) if (o->threads > 1) schedule(dynamic, 256)
   for (int i = 0; i < o->nb; ++i) {
     // variable list: index into couplings, row-P coefficient, row-Q coefficient
     std::vector<int> kidx;
@@ -1588,6 +1633,7 @@ void ora_bus_step(void* h) {
 // lambda z + beta/2 z^2 + y (u - v + z) + rho/2 (u - v + z)^2.
 void ora_z_step(void* h) {
   auto* o = static_cast<Oracle*>(h);
+#pragma omp parallel for num_threads(o->threads) if (o->threads > 1) schedule(static)
   for (int k = 0; k < o->m; ++k)
     o->z[k] = -(o->lam[k] + o->y[k] + o->rho[k] * (o->u[k] - o->v[k])) /
               (o->beta + o->rho[k]);
@@ -1596,6 +1642,7 @@ void ora_z_step(void* h) {
 // Inner multiplier update y <- y + rho (Ax + B xbar + z) (Sec. III-B).
 void ora_y_step(void* h) {
   auto* o = static_cast<Oracle*>(h);
+#pragma omp parallel for num_threads(o->threads) if (o->threads > 1) schedule(static)
   for (int k = 0; k < o->m; ++k)
     o->y[k] = o->y[k] + o->rho[k] * (o->u[k] - o->v[k] + o->z[k]);
 }
@@ -1604,6 +1651,9 @@ void ora_y_step(void* h) {
 void ora_residuals(void* h) {
   auto* o = static_cast<Oracle*>(h);
   double rp = 0.0, rd = 0.0, rz = 0.0;
+  // maxima: the same value in any order
+#pragma omp parallel for num_threads(o->threads) if (o->threads > 1) schedule(static) \
+    reduction(max : rp, rd, rz)
   for (int k = 0; k < o->m; ++k) {
     rp = std::max(rp, std::fabs(o->u[k] - o->v[k] + o->z[k]));
     rd = std::max(rd, std::fabs(o->v[k] - o->vprev[k]));
@@ -1869,6 +1919,11 @@ void ora_get_admittance(void* h, double* out9nl) {
 void ora_get_stats(void* h, ora_stats* out) { *out = static_cast<Oracle*>(h)->st; }
 void ora_reset_stats(void* h) { static_cast<Oracle*>(h)->st = ora_stats{}; }
 void ora_set_count_flops(void* h, int on) { static_cast<Oracle*>(h)->count_flops = on != 0; }
+// Threads of the per-element loops (generators, branches, buses, couplings);
+// 1 runs them serially. Results do not depend on it: the elements are
+// independent and the only reductions are maxima and integer counts.
+void ora_set_threads(void* h, int n) { static_cast<Oracle*>(h)->threads = n < 1 ? 1 : n; }
+
 // Branch solves of the whole-grid iteration by the textbook path (on != 0) or
 // by the fixed-sequence path (0, the default).
 void ora_set_textbook(void* h, int on) { static_cast<Oracle*>(h)->textbook = on != 0; }

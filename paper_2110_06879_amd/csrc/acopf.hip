@@ -1207,6 +1207,8 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   return build_tiles(h, h->tune.bus_block);
 }
 
+static int ensure_graph(acopf_s* h);
+
 int acopf_create(const acopf_grid* grids, int32_t n_grids, const acopf_params* params,
                  int32_t device, void* hip_stream, acopf_handle* out) {
   if (!out) return fail(ACOPF_EINVAL, "out is null");
@@ -1240,6 +1242,13 @@ int acopf_create(const acopf_grid* grids, int32_t n_grids, const acopf_params* p
     acopf_destroy(h);
     return fail(ACOPF_EDEVICE, std::string("cold start: ") + hipGetErrorString(e));
   }
+  rc = ensure_graph(h);
+  if (rc) {
+    std::string msg = g_err;
+    acopf_destroy(h);
+    g_err = msg;
+    return rc;
+  }
   *out = h;
   return ACOPF_OK;
 }
@@ -1261,24 +1270,40 @@ static void drop_graph(acopf_s* h) {
   h->graph_chunk = 0;
 }
 
+// Captures one chunk of the tuned length as a hipGraph (without per-launch
+// timing events) if graphs are on and none is held. Called when the launch
+// shape or the kernel variant changes, so that capture and instantiation
+// happen outside the solves that replay the graph.
+static int ensure_graph(acopf_s* h) {
+  const int k = h->tune.chunk;
+  if (!h->tune.use_graph || (h->graph && h->graph_chunk == k)) return ACOPF_OK;
+  drop_graph(h);
+  const bool prof = h->profile;
+  h->profile = false;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    for (int c = 0; c < k; ++c) launch_iteration(h, c);
+    e = hipStreamEndCapture(h->stream, &g);
+  }
+  h->profile = prof;
+  if (e != hipSuccess) return fail(ACOPF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    h->graph = nullptr;
+    return fail(ACOPF_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  h->graph_chunk = k;
+  return ACOPF_OK;
+}
+
 // k inner iterations: one replay of the captured chunk when k equals the
 // tuned chunk and timing is off, else plain launches.
 static int launch_chunk(acopf_s* h, int k) {
   if (!h->profile && h->tune.use_graph && k == h->tune.chunk) {
-    if (!h->graph || h->graph_chunk != k) {
-      drop_graph(h);
-      hipGraph_t g = nullptr;
-      HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-      for (int c = 0; c < k; ++c) launch_iteration(h, c);
-      HIP_TRY(hipStreamEndCapture(h->stream, &g));
-      hipError_t e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (e != hipSuccess) {
-        h->graph = nullptr;
-        return fail(ACOPF_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-      }
-      h->graph_chunk = k;
-    }
+    int rc = ensure_graph(h);
+    if (rc) return rc;
     HIP_TRY(hipGraphLaunch(h->graph, h->stream));
     return ACOPF_OK;
   }
@@ -1763,7 +1788,8 @@ int acopf_set_tuning(acopf_handle h, const acopf_tuning* t) {
   int rc = check_tuning(*t);
   if (rc) return rc;
   HIP_TRY(hipSetDevice(h->device));
-  return apply_tuning(h, *t);
+  rc = apply_tuning(h, *t);
+  return rc ? rc : ensure_graph(h);
 }
 
 int acopf_get_tuning(acopf_handle h, acopf_tuning* t) {
@@ -1829,8 +1855,10 @@ int acopf_autotune(acopf_handle h, int32_t iters, acopf_tuning* out) {
 int acopf_set_counting(acopf_handle h, int32_t on) {
   if (!h) return fail(ACOPF_EINVAL, "null handle");
   if ((on != 0) != h->count_stats) {
+    HIP_TRY(hipSetDevice(h->device));
     drop_graph(h);
     h->count_stats = on != 0;
+    return ensure_graph(h);
   }
   return ACOPF_OK;
 }

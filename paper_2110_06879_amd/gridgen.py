@@ -194,6 +194,13 @@ CONFIGS = {
                      load_factor=LOAD_FACTOR),
     "c3_70kbus": dict(n_bus=70000, n_gen=10000, n_branch=88000, rated_frac=0.3, seed=3,
                       load_factor=LOAD_FACTOR),
+    # the same grids at the stated load distribution Pd ~ U(0, 0.5) (load
+    # factor 1, then the 0.75 total-load guard): remote radial pockets are
+    # voltage-infeasible at this level, so these serve fixed-iteration runs
+    "c2_2kbus_full": dict(n_bus=2000, n_gen=400, n_branch=2600, rated_frac=1.0, seed=2,
+                          load_factor=1.0),
+    "c3_70kbus_full": dict(n_bus=70000, n_gen=10000, n_branch=88000, rated_frac=0.3, seed=3,
+                           load_factor=1.0),
 }
 
 

@@ -190,18 +190,62 @@ def test_serving_results_same_alone_and_in_mix():
             reqs.append(S.Request(len(reqs), k, 0.0, pd, qd))
     srv = S.TrackingServer(gs, max_slots_per_grid=2)
     out = srv.serve(reqs, realtime=False)
-    srv.close()
     assert out["requests"] == len(reqs)
     mix = {r.rid: r for r in out["done"]}
+    # every request was admitted at once into its own slot, so each slot
+    # still holds its request's final state
+    assert len({r.slot for r in out["done"]}) == len(reqs)
+    mixed_states = {r.rid: states(srv.solver, r.slot) for r in out["done"]}
+    srv.close()
     for r in reqs:
         alone = S.TrackingServer(gs, max_slots_per_grid=2)
         one = S.Request(r.rid, r.grid, 0.0, r.pd, r.qd)
         o = alone.serve([one], realtime=False)["done"][0]
-        got = {k: alone.solver.get(k, r.grid) for k in ("u", "v", "z", "y", "bx")}
+        got = states(alone.solver, o.slot)
         alone.close()
-        assert o.result["inner_iters"] == mix[r.rid].result["inner_iters"]
-        assert o.result["objective"] == mix[r.rid].result["objective"]
-        assert o.result["r_pri"] == mix[r.rid].result["r_pri"]
+        for k in ("status", "inner_iters", "outer_iters", "objective", "r_pri", "r_dual", "r_z"):
+            assert o.result[k] == mix[r.rid].result[k], (r.rid, k)
+        assert_same(got, mixed_states[r.rid])
+
+
+def test_served_request_matches_oracle_warm_start():
+    """A served tracking request against the oracle: the server's resident
+    state of a grid is its cold solve to convergence (bitwise the oracle's),
+    a request warm-starts a copy of it with new loads (Sec. IV-C), and the
+    result must equal the oracle's warm start from the same base state: the
+    same iteration count and status, the objective within 1e-6, and every
+    state vector within 1e-9."""
+    import oracle as O
+    from dataclasses import asdict
+    note("serving: served warm start against the oracle")
+    gs = [gridgen(300, 60, 390, 1.0, 85, load_factor=0.2),
+          gridgen(420, 84, 546, 0.3, 86, load_factor=0.2)]
+    p = A.Params()
+    reqs = []
+    for k in range(2):
+        pd, qd = perturb_loads(gs[k], 0.03, 960 + k)
+        reqs.append(S.Request(k, k, 0.0, pd, qd))
+    srv = S.TrackingServer(gs, p, max_slots_per_grid=1)
+    out = srv.serve(reqs, realtime=False)
+    done = {r.rid: r for r in out["done"]}
+    try:
+        for k, g in enumerate(gs):
+            orc = O.Oracle(g, O.OracleParams(**asdict(p)))
+            n_cold = orc.solve(0)
+            assert n_cold == srv.cold[k]["inner_iters"]
+            orc.update_loads(reqs[k].pd, reqs[k].qd)
+            n = orc.solve(0)
+            r = done[k]
+            note(f"grid {k}: served {r.result['inner_iters']} iterations, oracle {n}")
+            assert r.result["status"] == A.CONVERGED and orc.scalars()["status"] == 0
+            assert r.result["inner_iters"] == n
+            assert abs(r.result["objective"] - orc.objective()) <= 1e-6 * abs(orc.objective())
+            for name in VECS:
+                a, b = srv.solver.get(name, r.slot), orc.get(name)
+                err = np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+                assert err <= 1e-9, (k, name, err)
+    finally:
+        srv.close()
 
 
 def test_serving_budget_without_slots_runs_on_home():

@@ -282,21 +282,24 @@ def test_quality_matches_oracle():
             assert_quality_equal(s.quality(k), orc.quality(), f"batch grid {k}")
 
 
-def test_70k_default_launch_25_iterations_matches_oracle():
+@pytest.mark.parametrize("name", ["c3_70kbus", "c3_70kbus_full"])
+def test_70k_default_launch_50_iterations_matches_oracle(name):
     """The 70k-bus grid in the launch configuration the benchmark times
-    (default tuning: graph chunks of 16, automatic branches per lane), 25
-    iterations from the same cold start: every state vector, the residual
-    history and the TRON event counts equal the oracle's."""
-    note("parity c3 70k: 25 iterations from cold, default launch, counting on")
-    g = config_grid("c3_70kbus")
-    p = A.Params(rho_pq=400.0, rho_va=4000.0)
+    (default parameters and tuning: graph chunks of 16, automatic branches
+    per lane), 50 iterations from the same cold start: every state vector,
+    the residual history and the TRON event counts equal the oracle's. Also
+    at the stated load distribution (load factor 1 and the 0.75 guard), where
+    line limits bind and the branch AL loop takes extra rounds."""
+    note(f"parity {name}: 50 iterations from cold, default launch, counting on")
+    g = config_grid(name)
+    p = A.Params()
     orc = O.Oracle(g, oparams(p))
     orc.count_flops(True)
-    orc.solve(25)
+    orc.solve(50)
     with A.Solver(g, p) as s:
         s.set_counting(True)
-        s.solve(A.COLD, 25)
-        compare(s, orc, tol=1e-9, label="70k cold+25")
+        s.solve(A.COLD, 50)
+        compare(s, orc, tol=1e-9, label=f"{name} cold+50")
         np.testing.assert_array_equal(s.get("rtil"), orc.get("rtil"))
         hg, ho = s.history(), orc.history()
         np.testing.assert_array_equal(hg[:, [0, 1, 2]], ho[:, [0, 1, 2]])
@@ -385,3 +388,116 @@ def test_matpower_case_matches_oracle():
         s.solve(A.COLD, 100)
         compare(s, orc, label="case5")
         assert_quality_equal(s.quality(), orc.quality(), "case5")
+
+
+def test_beta_growth_and_lambda_clamp_match_oracle():
+    """The outer level of Algorithm 1 (eq. two-level) with the beta rule
+    active: beta0 = 1e3 below beta_max = 2e4, an outer step every ten inner
+    iterations (max_inner = 10), and lambda_max = 20 so that the projection
+    of lambda binds. After 60 iterations beta has grown twice (the second
+    time to the cap), lambda sits at the clamp on some couplings, and every
+    vector and the beta/outer history equal the oracle's."""
+    note("parity c2: beta growth and lambda clamp, 60 iterations")
+    g = config_grid("c2_2kbus")
+    p = A.Params(beta0=1e3, beta_max=2e4, max_inner=10, lambda_max=20.0)
+    orc = O.Oracle(g, oparams(p))
+    orc.solve(60)
+    ho = orc.history()
+    betas = np.unique(ho[:, 4])
+    assert list(betas) == [1e3, 6e3, 2e4], betas
+    lam = orc.get("lam")
+    assert (np.abs(lam) == 20.0).sum() > 100
+    with A.Solver(g, p) as s:
+        res = s.solve(A.COLD, 60)[0]
+        compare(s, orc, label="c2 beta/lambda")
+        hg = s.history()
+        np.testing.assert_array_equal(hg[:, 4], ho[:, 4])
+        np.testing.assert_array_equal(hg[:, 5], ho[:, 5])
+        np.testing.assert_array_equal(s.get("lam"), lam)
+        assert res["beta"] == orc.scalars()["beta"] == 2e4
+
+
+def test_2k_cold_solve_to_convergence_matches_oracle():
+    """A cold solve of the 2k-bus grid to the termination tests of Algorithm
+    1: the same inner and outer iteration counts, the objective within 1e-6
+    of the oracle's at that count, and the final state within 1e-9."""
+    note("parity c2: cold solve to convergence")
+    g = config_grid("c2_2kbus")
+    p = A.Params()
+    orc = O.Oracle(g, oparams(p))
+    n = orc.solve(0)
+    sc = orc.scalars()
+    assert sc["status"] == 0
+    with A.Solver(g, p) as s:
+        res = s.solve(A.COLD)[0]
+        note(f"gpu {res['inner_iters']} iterations, oracle {n}")
+        assert res["status"] == A.CONVERGED
+        assert res["inner_iters"] == n and res["outer_iters"] == int(sc["outer"])
+        assert abs(res["objective"] - orc.objective()) <= 1e-6 * abs(orc.objective())
+        compare(s, orc, label="c2 converged")
+
+
+def tightened(name, factor):
+    g = config_grid(name)
+    g.rate = g.rate * factor
+    return g
+
+
+@pytest.mark.parametrize("name", ["c2_2kbus_tight", "c2_2kbus_full"])
+def test_binding_line_limits_match_oracle(name):
+    """Grids where line limits bind, so that the augmented-Lagrangian loop of
+    eq. (branch) takes several rounds and its multipliers and penalties
+    move: the 2k-bus grid with every rating scaled by 0.15, and the 2k-bus
+    grid at the stated load distribution. 50 iterations from the cold start,
+    element-wise against the oracle, with the AL event counts equal."""
+    note(f"parity {name}: binding line limits, 50 iterations")
+    g = tightened("c2_2kbus", 0.15) if name == "c2_2kbus_tight" else config_grid(name)
+    p = A.Params()
+    orc = O.Oracle(g, oparams(p))
+    orc.solve(50)
+    lt, rt = orc.get("ltil"), orc.get("rtil")
+    n_bind = int((np.abs(lt) > 1e-3).sum())
+    n_grow = int((rt > p.al_rho0).sum())
+    note(f"{name}: {n_bind} binding multipliers, {n_grow} grown penalties")
+    assert n_bind >= 10 and n_grow >= 20
+    with A.Solver(g, p) as s:
+        s.set_counting(True)
+        s.solve(A.COLD, 50)
+        compare(s, orc, label=name)
+        np.testing.assert_array_equal(s.get("rtil"), rt)
+        assert s.stats()["al_iters"] == orc.stats()["al_iters"] > 50 * g.n_branch
+
+
+def uneven_batch():
+    """Eight grids of uneven size (500 to 5,000 buses, log-spaced), with
+    rated fractions 1, 0.3 and 0 mixed, at the default load factor."""
+    sizes = np.round(np.exp(np.linspace(np.log(500), np.log(5000), 8))).astype(int)
+    rf = [1.0, 0.3, 0.0, 1.0, 0.3, 1.0, 0.0, 0.3]
+    out = []
+    for k, nb in enumerate(sizes.tolist()):
+        out.append(gridgen(nb, max(1, round(0.2 * nb)), round(1.3 * nb), rf[k], 600 + k,
+                           load_factor=0.2))
+    return out
+
+
+def test_uneven_batch_with_staggered_starts_matches_oracles():
+    """Batched launch (one handle, the same kernels for all grids) of eight
+    uneven grids started at different iterations: each grid runs exactly 30
+    iterations from its cold start, and every state vector of every grid
+    equals its own oracle's."""
+    note("batch of 8 uneven grids, staggered starts, each against its oracle")
+    gs = uneven_batch()
+    p = A.Params()
+    with A.Solver(gs, p) as sb:
+        for k in range(len(gs)):
+            sb.start(k, A.COLD, 30)
+            sb.run(5 + 3 * k)
+        while sb.run(64) > 0:
+            pass
+        for k, g in enumerate(gs):
+            running, res = sb.poll(k)
+            assert not running and res["inner_iters"] == 30
+            orc = O.Oracle(g, oparams(p))
+            orc.solve(30)
+            compare(sb, orc, grid=k, label=f"batch grid {k} ({g.n_bus} buses)")
+            np.testing.assert_array_equal(sb.get("rtil", k), orc.get("rtil"))
