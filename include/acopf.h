@@ -75,10 +75,20 @@ enum { /* acopf_get_state / acopf_set_state: what */
                           trials, CG iterations, Cholesky attempts, search
                           trials, AL rounds, TRON converged / at the cap /
                           stalled, then 0; the same for every grid index    */
-  ACOPF_BRANCH_ALPHA = 13 /* [n_branch] Cauchy step length each branch's last
+  ACOPF_BRANCH_ALPHA = 13, /* [n_branch] Cauchy step length each branch's last
                           trust-region solve ended with; the next solve of
                           that branch starts its projected search from it
                           (1 after a cold start)                            */
+  ACOPF_SOLUTION = 14  /* get only: the ADMM solution of Sec. IV-A,
+                          [2 n_gen + 2 n_bus + 4 n_branch] in input order:
+                          p_g [n_gen] and q_g [n_gen] of the generator
+                          problems; |V| = sqrt(w) [n_bus] and theta [n_bus]
+                          of the bus problems (from each bus's first branch
+                          end: from-ends, then to-ends, in input order);
+                          p_ij, q_ij, p_ji, q_ji [n_branch each] recomputed
+                          from those voltages by eqs. (pij)-(qji). Runs the
+                          recovery kernels on the handle's stream; allocates
+                          their scratch on first use                         */
 };
 
 /* Coupling order (m = 2 n_gen + 8 n_branch), the same in every vector:
@@ -228,13 +238,21 @@ int acopf_get_tuning(acopf_handle h, acopf_tuning* t);
 int acopf_autotune(acopf_handle h, int32_t iters, acopf_tuning* out);
 
 /* Copy one state vector of grid `grid` to the host buffer out[n] (n must
- * equal the size listed with the ACOPF_* `what` codes, in canonical order).
- * Errors: EINVAL (index, size, code), EDEVICE. */
+ * equal the size listed with the ACOPF_* `what` codes, in canonical order):
+ * the primal and dual iterates of Algorithm 1 (Sec. III: u = x side, v = xbar
+ * side, z, y, lambda), the branch subproblem state of eq. (branch) (x,
+ * ltil, rtil, Cauchy step length), the control scalars, loads, residual
+ * history, counters, or the recovered solution (ACOPF_SOLUTION, Sec. IV-A).
+ * The caller owns out. Synchronous on the handle's stream.
+ * Errors: EINVAL (index, size, code), ENOMEM (solution scratch), EDEVICE. */
 int acopf_get_state(acopf_handle h, int32_t grid, int32_t what, double* out,
                     int64_t n);
 
-/* Overwrite one state vector (checkpoint/resume); HISTORY and STATS are
- * read-only. Errors: EINVAL, EDEVICE. */
+/* Overwrite one state vector (checkpoint/resume of Algorithm 1's iterates,
+ * or warm-start data for the tracking use of Sec. IV-C); HISTORY, STATS and
+ * SOLUTION are read-only. in[n] is borrowed for the call. Not allowed while
+ * the grid is running. Errors: EINVAL (size, code, non-finite values,
+ * non-positive step lengths), ESTATE (grid running), EDEVICE. */
 int acopf_set_state(acopf_handle h, int32_t grid, int32_t what,
                     const double* in, int64_t n);
 

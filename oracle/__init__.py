@@ -136,6 +136,8 @@ def load() -> C.CDLL:
     lib.ora_objective.restype = C.c_double
     lib.ora_quality.argtypes = [vp, dp]
     lib.ora_quality.restype = None
+    lib.ora_solution.argtypes = [vp, dp]
+    lib.ora_solution.restype = None
     lib.ora_iterate.argtypes = [vp, ip]
     lib.ora_iterate.restype = ip
     lib.ora_solve.argtypes = [vp, ip]
@@ -325,6 +327,16 @@ class Oracle:
         out = np.zeros(6)
         self.lib.ora_quality(self.h, _dp(out))
         return dict(zip(QUALITY_NAMES, out.tolist()))
+
+    def solution(self) -> dict:
+        """The ADMM solution of Sec. IV-A: generator outputs (pg, qg), bus
+        voltage magnitudes and angles (vm = sqrt(w), va), and the branch flows
+        recomputed from those voltages (pij, qij, pji, qji), input order."""
+        nb, ng, nl = self.nb, self.ng, self.nl
+        out = np.zeros(2 * ng + 2 * nb + 4 * nl)
+        self.lib.ora_solution(self.h, _dp(out))
+        parts = np.split(out, np.cumsum([ng, ng, nb, nb, nl, nl, nl, nl])[:-1])
+        return dict(zip(("pg", "qg", "vm", "va", "pij", "qij", "pji", "qji"), parts))
 
     def iterate(self, fixed: bool = False) -> bool:
         return bool(self.lib.ora_iterate(self.h, int(fixed)))

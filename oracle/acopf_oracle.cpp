@@ -1692,29 +1692,67 @@ void ora_outer_step(void* h) {
 // maximum that keeps a NaN once one appears, so that a broken state shows
 static inline double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
 
-void ora_quality(void* h, double* out6) {
-  auto* o = static_cast<Oracle*>(h);
+// The solution itself: bus w, theta and the recomputed flows.
+struct Recovered {
+  std::vector<double> bw, bt, pij, qij, pji, qji;
+};
+
+static void recover(const Oracle* o, Recovered& R) {
   const int ng = o->ng;
-  std::vector<double> bw(o->nb), bt(o->nb);
+  R.bw.resize(o->nb);
+  R.bt.resize(o->nb);
   for (int i = 0; i < o->nb; ++i) {
     const int k = !o->bus_from[i].empty() ? 2 * ng + 8 * o->bus_from[i][0] + 4
                                           : 2 * ng + 8 * o->bus_to[i][0] + 6;
-    bw[i] = o->v[k];
-    bt[i] = o->v[k + 1];
+    R.bw[i] = o->v[k];
+    R.bt[i] = o->v[k + 1];
   }
-  std::vector<double> pij(o->nl), qij(o->nl), pji(o->nl), qji(o->nl);
-  double line = 0.0;
+  R.pij.resize(o->nl);
+  R.qij.resize(o->nl);
+  R.pji.resize(o->nl);
+  R.qji.resize(o->nl);
   for (int l = 0; l < o->nl; ++l) {
     const int i = o->from[l], j = o->to[l];
-    const double wi = bw[i], wj = bw[j];
+    const double wi = R.bw[i], wj = R.bw[j];
     double sn, cs;
-    series_sincos(bt[i] - bt[j], &sn, &cs);
+    series_sincos(R.bt[i] - R.bt[j], &sn, &cs);
     const double vv = std::sqrt(wi) * std::sqrt(wj);
     const double WR = vv * cs, WI = vv * sn;
-    pij[l] = std::fma(o->bij[l], WI, std::fma(o->gij[l], WR, o->gii[l] * wi));
-    qij[l] = std::fma(o->gij[l], WI, std::fma(-o->bij[l], WR, -o->bii[l] * wi));
-    pji[l] = std::fma(-o->bji[l], WI, std::fma(o->gji[l], WR, o->gjj[l] * wj));
-    qji[l] = std::fma(-o->gji[l], WI, std::fma(-o->bji[l], WR, -o->bjj[l] * wj));
+    R.pij[l] = std::fma(o->bij[l], WI, std::fma(o->gij[l], WR, o->gii[l] * wi));
+    R.qij[l] = std::fma(o->gij[l], WI, std::fma(-o->bij[l], WR, -o->bii[l] * wi));
+    R.pji[l] = std::fma(-o->bji[l], WI, std::fma(o->gji[l], WR, o->gjj[l] * wj));
+    R.qji[l] = std::fma(-o->gji[l], WI, std::fma(-o->bji[l], WR, -o->bjj[l] * wj));
+  }
+}
+
+// out[2 ng + 2 nb + 4 nl]: p_g, q_g, |V| = sqrt(w), theta, p_ij, q_ij, p_ji,
+// q_ji (input order).
+void ora_solution(void* h, double* out) {
+  auto* o = static_cast<Oracle*>(h);
+  Recovered R;
+  recover(o, R);
+  double* p = out;
+  for (int g = 0; g < o->ng; ++g) p[g] = o->u[2 * g];
+  p += o->ng;
+  for (int g = 0; g < o->ng; ++g) p[g] = o->u[2 * g + 1];
+  p += o->ng;
+  for (int i = 0; i < o->nb; ++i) p[i] = R.bw[i] > 0.0 ? std::sqrt(R.bw[i]) : 0.0;
+  p += o->nb;
+  for (int i = 0; i < o->nb; ++i) p[i] = R.bt[i];
+  p += o->nb;
+  const std::vector<double>* fl[4] = {&R.pij, &R.qij, &R.pji, &R.qji};
+  for (int k = 0; k < 4; ++k, p += o->nl)
+    for (int l = 0; l < o->nl; ++l) p[l] = (*fl[k])[l];
+}
+
+void ora_quality(void* h, double* out6) {
+  auto* o = static_cast<Oracle*>(h);
+  Recovered R;
+  recover(o, R);
+  const std::vector<double>&bw = R.bw, &bt = R.bt, &pij = R.pij, &qij = R.qij, &pji = R.pji,
+                           &qji = R.qji;
+  double line = 0.0;
+  for (int l = 0; l < o->nl; ++l) {
     if (o->rate[l] > 0.0) {
       const double sf = std::sqrt(std::fma(pij[l], pij[l], qij[l] * qij[l]));
       const double st = std::sqrt(std::fma(pji[l], pji[l], qji[l] * qji[l]));

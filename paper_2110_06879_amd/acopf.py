@@ -22,6 +22,7 @@ COLD, WARM, CONTINUE = 0, 1, 2
 CONVERGED, MAX_ITER, NUMERICAL = 0, 1, 2
 U, V, Z, Y, LAMBDA, BRANCH_X, BRANCH_LTIL, BRANCH_RTIL, SCALARS, PD, QD, HISTORY, STATS = range(13)
 BRANCH_ALPHA = 13
+SOLUTION = 14
 STATE_CODES = {"u": U, "v": V, "z": Z, "y": Y, "lam": LAMBDA, "bx": BRANCH_X,
                "ltil": BRANCH_LTIL, "rtil": BRANCH_RTIL, "scalars": SCALARS,
                "pd": PD, "qd": QD, "calpha": BRANCH_ALPHA}
@@ -321,7 +322,8 @@ class Solver:
         return {U: m, V: m, Z: m, Y: m, LAMBDA: m, BRANCH_X: 6 * g.n_branch,
                 BRANCH_LTIL: 2 * g.n_branch, BRANCH_RTIL: g.n_branch,
                 BRANCH_ALPHA: g.n_branch, SCALARS: 9,
-                PD: g.n_bus, QD: g.n_bus, STATS: 16}[code]
+                PD: g.n_bus, QD: g.n_bus, STATS: 16,
+                SOLUTION: 2 * g.n_gen + 2 * g.n_bus + 4 * g.n_branch}[code]
 
     def get(self, name: str, grid: int = 0) -> np.ndarray:
         code = STATE_CODES[name]
@@ -333,6 +335,18 @@ class Solver:
         code = STATE_CODES[name]
         a = np.ascontiguousarray(val, dtype=np.float64)
         self._check(self.lib.acopf_set_state(self.h, grid, code, _dp(a), a.size))
+
+    def solution(self, grid: int = 0) -> dict:
+        """The recovered ADMM solution (Sec. IV-A) of one grid, input order:
+        generator outputs pg, qg; bus voltage magnitudes vm and angles va;
+        branch flows pij, qij, pji, qji recomputed from the bus voltages."""
+        g = self.grids[grid]
+        out = np.empty(self._size(grid, SOLUTION))
+        self._check(self.lib.acopf_get_state(self.h, grid, SOLUTION, _dp(out), out.size))
+        ng, nb, nl = g.n_gen, g.n_bus, g.n_branch
+        cut = np.cumsum([ng, ng, nb, nb, nl, nl, nl, nl])[:-1]
+        parts = np.split(out, cut)
+        return dict(zip(("pg", "qg", "vm", "va", "pij", "qij", "pji", "qji"), parts))
 
     def scalars(self, grid: int = 0) -> dict:
         return dict(zip(SCALAR_NAMES, self.get("scalars", grid).tolist()))

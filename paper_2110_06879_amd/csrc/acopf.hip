@@ -73,6 +73,7 @@ constexpr int kTimed = 3;       // kernels timed per iteration (x-step, bus, ctl
 constexpr int kChunk = 16;      // iterations between control readbacks (default)
 constexpr int kMaxChunk = 64;   // largest chunk acopf_set_tuning accepts
 
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
@@ -1504,8 +1505,41 @@ static int64_t state_size(const HostGrid& H, int what) {
     case ACOPF_SCALARS: return 9;
     case ACOPF_PD: case ACOPF_QD: return H.nb;
     case ACOPF_STATS: return kStats;
+    case ACOPF_SOLUTION: return 2 * H.ng + 2 * H.nb + 4 * H.nl;
     default: return -1;
   }
+}
+
+// Scratch of the solution recovery (bus w and theta, flows per branch end)
+// and of the quality maxima, allocated on first use.
+static int quality_scratch(acopf_s* h) {
+  if (h->qscratch) return ACOPF_OK;
+  void* p = nullptr;
+  if (hipMalloc(&p, sizeof(double) * (2 * h->nb + 2 * h->ne)) != hipSuccess)
+    return fail(ACOPF_ENOMEM, "quality scratch allocation failed");
+  h->qscratch = static_cast<double*>(p);
+  if (hipMalloc(&p, sizeof(unsigned long long) * 6 * h->G) != hipSuccess)
+    return fail(ACOPF_ENOMEM, "quality scratch allocation failed");
+  h->qual = static_cast<unsigned long long*>(p);
+  return ACOPF_OK;
+}
+
+// Recovers the solution of Sec. IV-A into the scratch (bus w, theta; flows
+// of every branch end from the bus voltages) and the quality maxima per
+// grid into h->qual (zeroed by a fill kernel first).
+static int launch_recovery(acopf_s* h) {
+  int rc = quality_scratch(h);
+  if (rc) return rc;
+  hipStream_t st = h->stream;
+  acopf_dev::launch_fill_u64(h->qual, (int64_t)6 * h->G, st);
+  acopf_dev::QualityArgs Q{h->nb, h->ng, h->nl, h->ne, h->bus_grid, h->br_grid, h->gen_grid,
+                           h->gptr, h->eptr, h->ef, h->et, h->end_bus, h->adm, h->rate, h->u,
+                           h->v, h->pd, h->qd, h->gs, h->bs, h->vmin_b, h->vmax_b,
+                           h->qscratch, h->qscratch + h->nb, h->qscratch + 2 * h->nb,
+                           h->qscratch + 2 * h->nb + h->ne, h->qual};
+  acopf_dev::launch_quality(Q, st);
+  HIP_TRY(hipGetLastError());
+  return ACOPF_OK;
 }
 
 // canonical <-> device permutations of the per-grid vectors
@@ -1612,6 +1646,39 @@ static int copy_state(acopf_s* h, int grid, int what, double* host, int64_t n, b
     }
     return ACOPF_OK;
   }
+  if (what == ACOPF_SOLUTION && to_host) {
+    // generator outputs from the generator problems, |V| = sqrt(w) and
+    // theta from the bus problems, flows recomputed from those voltages
+    int rc = launch_recovery(h);
+    if (rc) return rc;
+    std::vector<double> uu, bw, bt, pe, qe;
+    HIP_TRY(pull(h->u, 2 * ng, uu));
+    HIP_TRY(pull(h->qscratch + H.bus_off, H.nb, bw));
+    HIP_TRY(pull(h->qscratch + h->nb + H.bus_off, H.nb, bt));
+    HIP_TRY(pull(h->qscratch + 2 * h->nb, h->ne, pe));
+    HIP_TRY(pull(h->qscratch + 2 * h->nb + h->ne, h->ne, qe));
+    HIP_TRY(hipStreamSynchronize(st));
+    double* pg = host;
+    double* qg = pg + H.ng;
+    double* vm = qg + H.ng;
+    double* va = vm + H.nb;
+    double* fl = va + H.nb;
+    for (int64_t k = 0; k < H.ng; ++k) {
+      pg[k] = uu[H.gen_dev[k]];
+      qg[k] = uu[ng + H.gen_dev[k]];
+    }
+    for (int64_t i = 0; i < H.nb; ++i) {
+      vm[i] = bw[i] > 0.0 ? std::sqrt(bw[i]) : 0.0;
+      va[i] = bt[i];
+    }
+    for (int64_t l = 0; l < H.nl; ++l) {
+      fl[l] = pe[H.end_f[l]];
+      fl[H.nl + l] = qe[H.end_f[l]];
+      fl[2 * H.nl + l] = pe[H.end_t[l]];
+      fl[3 * H.nl + l] = qe[H.end_t[l]];
+    }
+    return ACOPF_OK;
+  }
   if (what == ACOPF_STATS && to_host) {
     unsigned long long s[kStats];
     HIP_TRY(hipMemcpyAsync(s, h->stats, sizeof(s), hipMemcpyDeviceToHost, st));
@@ -1646,7 +1713,8 @@ int acopf_set_state(acopf_handle h, int32_t grid, int32_t what, const double* in
   if (!h) return fail(ACOPF_EINVAL, "null handle");
   if (grid < 0 || grid >= h->G) return fail(ACOPF_EINVAL, "grid index out of range");
   if (!in) return fail(ACOPF_EINVAL, "null input");
-  if (what == ACOPF_HISTORY || what == ACOPF_STATS) return fail(ACOPF_EINVAL, "read-only state");
+  if (what == ACOPF_HISTORY || what == ACOPF_STATS || what == ACOPF_SOLUTION)
+    return fail(ACOPF_EINVAL, "read-only state");
   const int64_t need = state_size(h->grids[grid], what);
   if (need < 0) return fail(ACOPF_EINVAL, "unknown state code");
   if (n != need) return fail(ACOPF_EINVAL, "buffer size mismatch: need " + std::to_string(need));
@@ -1878,24 +1946,9 @@ int acopf_quality(acopf_handle h, int32_t grid, double* out6) {
   if (!h || !out6) return fail(ACOPF_EINVAL, "null argument");
   if (grid < 0 || grid >= h->G) return fail(ACOPF_EINVAL, "grid index out of range");
   HIP_TRY(hipSetDevice(h->device));
-  if (!h->qscratch) {
-    void* p = nullptr;
-    if (hipMalloc(&p, sizeof(double) * (2 * h->nb + 2 * h->ne)) != hipSuccess)
-      return fail(ACOPF_ENOMEM, "quality scratch allocation failed");
-    h->qscratch = static_cast<double*>(p);
-    if (hipMalloc(&p, sizeof(unsigned long long) * 6 * h->G) != hipSuccess)
-      return fail(ACOPF_ENOMEM, "quality scratch allocation failed");
-    h->qual = static_cast<unsigned long long*>(p);
-  }
+  int rc = launch_recovery(h);
+  if (rc) return rc;
   hipStream_t st = h->stream;
-  HIP_TRY(hipMemsetAsync(h->qual, 0, sizeof(unsigned long long) * 6 * h->G, st));
-  acopf_dev::QualityArgs Q{h->nb, h->ng, h->nl, h->ne, h->bus_grid, h->br_grid, h->gen_grid,
-                           h->gptr, h->eptr, h->ef, h->et, h->end_bus, h->adm, h->rate, h->u,
-                           h->v, h->pd, h->qd, h->gs, h->bs, h->vmin_b, h->vmax_b,
-                           h->qscratch, h->qscratch + h->nb, h->qscratch + 2 * h->nb,
-                           h->qscratch + 2 * h->nb + h->ne, h->qual};
-  acopf_dev::launch_quality(Q, st);
-  HIP_TRY(hipGetLastError());
   unsigned long long bits[6];
   HIP_TRY(hipMemcpyAsync(bits, h->qual + 6 * grid, sizeof(bits), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));

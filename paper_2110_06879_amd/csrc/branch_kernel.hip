@@ -1566,6 +1566,14 @@ __global__ __launch_bounds__(256) void quality_bus_kernel(QualityArgs Q) {
   quality_max(Q.qmax, grid, 5, ang);
 }
 
+__global__ __launch_bounds__(256) void fill_u64_kernel(unsigned long long* p, int64_t n) {
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
+}
+
+void launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(256), 0, s, p, n);
+}
+
 void launch_quality(const QualityArgs& Q, hipStream_t s) {
   const int bs = 256;
   hipLaunchKernelGGL(quality_values_kernel, dim3((Q.nb + bs - 1) / bs), dim3(bs), 0, s, Q);

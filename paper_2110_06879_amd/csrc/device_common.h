@@ -68,6 +68,8 @@ struct QualityArgs {
   unsigned long long* qmax;   // [G][6], zeroed before the launch
 };
 void launch_quality(const QualityArgs& Q, hipStream_t s);
+// Zeroes n 64-bit words with one block (a kernel rather than hipMemset).
+void launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s);
 
 // Lane-per-branch x-step; per_lane unlimited branches per lane (0: choose it
 // so that every branch wavefront fits the device's `slots` SIMD slots).

@@ -501,3 +501,30 @@ def test_uneven_batch_with_staggered_starts_matches_oracles():
             orc.solve(30)
             compare(sb, orc, grid=k, label=f"batch grid {k} ({g.n_bus} buses)")
             np.testing.assert_array_equal(sb.get("rtil", k), orc.get("rtil"))
+
+
+def test_solution_view_matches_oracle():
+    """acopf_get_state(ACOPF_SOLUTION): the ADMM solution of Sec. IV-A
+    (generator outputs, |V| and theta from the bus problems, flows
+    recomputed from the bus voltages) of each grid of a batch (taps, phase
+    shifters and shunts on one of them) against the oracle's recovery."""
+    note("solution view: 3-grid batch after 30 iterations")
+    gs = [gridgen(67, 9, 70, 0.5, 32, load_factor=0.2), gridgen(130, 20, 200, 0.0, 33),
+          gridgen(90, 12, 120, 1.0, 34, load_factor=0.2)]
+    rng = np.random.default_rng(0)
+    gs[0].gs = rng.uniform(0, 0.02, gs[0].n_bus)
+    gs[0].bs = rng.uniform(-0.02, 0.02, gs[0].n_bus)
+    gs[0].tap = rng.uniform(0.95, 1.05, gs[0].n_branch)
+    gs[0].shift = rng.uniform(-0.1, 0.1, gs[0].n_branch)
+    p = A.Params()
+    with A.Solver(gs, p) as s:
+        s.solve(A.COLD, 30)
+        for k, gk in enumerate(gs):
+            orc = O.Oracle(gk, oparams(p))
+            orc.solve(30)
+            sg, so = s.solution(k), orc.solution()
+            for name, want in so.items():
+                got = sg[name]
+                assert got.shape == want.shape, name
+                err = np.abs(got - want).max() / max(np.abs(want).max(), 1e-30)
+                assert err <= 1e-13, (k, name, err)

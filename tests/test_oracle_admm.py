@@ -453,3 +453,31 @@ def test_carried_cauchy_step_matches_restart_at_one():
     assert ca["cauchy_trials"] / ca["tron_iters"] < 0.7 * cb["cauchy_trials"] / cb["tron_iters"]
     al = a.get("calpha")
     assert np.all(np.isfinite(al)) and np.all(al > 0.0)
+
+
+def test_solution_recovery_matches_phasor_flows():
+    """The oracle's solution of Sec. IV-A: generator outputs are the
+    generator-side couplings, |V|^2 and theta are the bus copies w and theta
+    of each bus's first branch end, and the branch flows equal the complex
+    power S = V conj(I) of the pi model (numpy complex arithmetic) at those
+    voltages, with taps and phase shifters."""
+    from test_oracle_branch import phasor_flows, pi_model, random_grid_with_taps
+    g = random_grid_with_taps(19)
+    o = O.Oracle(g, O.OracleParams(rho_va=4000.0))
+    o.solve(30)
+    sol = o.solution()
+    u, v = o.get("u"), o.get("v")
+    np.testing.assert_array_equal(sol["pg"], u[0:2 * g.n_gen:2])
+    np.testing.assert_array_equal(sol["qg"], u[1:2 * g.n_gen:2])
+    base = 2 * g.n_gen
+    for i in range(g.n_bus):
+        frm = np.nonzero(g.br_from == i)[0]
+        to = np.nonzero(g.br_to == i)[0]
+        k = base + 8 * frm[0] + 4 if len(frm) else base + 8 * to[0] + 6
+        assert sol["vm"][i] == np.sqrt(v[k]) and sol["va"][i] == v[k + 1]
+    for l in range(g.n_branch):
+        i, j = g.br_from[l], g.br_to[l]
+        Y = pi_model(g.r[l], g.x[l], g.b[l], g.tap[l], g.shift[l])
+        Sij, Sji = phasor_flows(Y, sol["vm"][i], sol["vm"][j], sol["va"][i], sol["va"][j])
+        np.testing.assert_allclose([sol["pij"][l], sol["qij"][l], sol["pji"][l], sol["qji"][l]],
+                                   [Sij.real, Sij.imag, Sji.real, Sji.imag], rtol=0, atol=1e-12)
