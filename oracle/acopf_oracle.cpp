@@ -544,6 +544,10 @@ struct BranchData {
   double lo[6], hi[6];
   int n;  // 4 or 6
   double vb[8], z[8], y[8], rho[8];
+  // target of each coupling value: the residual is r_k = a_k - cv_k with
+  // cv_k = v_k - z_k (formed once per ADMM iteration, by the bus step's
+  // data; the textbook path uses a_k - v_k + z_k instead)
+  double cv[8];
   double ltil[2], rtil;
 };
 
@@ -628,13 +632,14 @@ struct BranchProblem {
   explicit BranchProblem(const BranchData& dd) : d(dd) {}
 
   // F(x) = sum_k y_k r_k + rho_k/2 r_k^2 + sum_e ltil_e c_e + rtil/2 c_e^2
-  // with r_k = a_k(x) - v_k + z_k and c_e = p_e^2 + q_e^2 + s_e.
+  // with r_k = a_k(x) - v_k + z_k, formed as a_k - (v_k - z_k), and
+  // c_e = p_e^2 + q_e^2 + s_e.
   R f(const R* x) {
     R a[8];
     branch_values<R>(d, x, a, nullptr);
     R F = R(0.0);
     for (int k = 0; k < 8; ++k) {
-      R r = a[k] - R(d.vb[k]) + R(d.z[k]);
+      R r = a[k] - R(d.cv[k]);
       F = rfma(R(0.5) * R(d.rho[k]) * r, r, rfma(R(d.y[k]), r, F));
     }
     if (d.n == 6) {
@@ -670,7 +675,7 @@ struct BranchProblem {
     // the four flow couplings
     R mu[4], nu[4];
     for (int k = 0; k < 4; ++k) {
-      R r = a[k] - R(d.vb[k]) + R(d.z[k]);
+      R r = a[k] - R(d.cv[k]);
       F = rfma(R(0.5) * R(d.rho[k]) * r, r, rfma(R(d.y[k]), r, F));
       mu[k] = rfma(R(d.rho[k]), r, R(d.y[k]));
       nu[k] = R(d.rho[k]);
@@ -679,7 +684,7 @@ struct BranchProblem {
     const int var[4] = {0, 2, 1, 3};
     R mv[4];
     for (int k = 4; k < 8; ++k) {
-      R r = a[k] - R(d.vb[k]) + R(d.z[k]);
+      R r = a[k] - R(d.cv[k]);
       F = rfma(R(0.5) * R(d.rho[k]) * r, r, rfma(R(d.y[k]), r, F));
       mv[k - 4] = rfma(R(d.rho[k]), r, R(d.y[k]));
     }
@@ -1410,6 +1415,7 @@ static void fill_branch_data(const Oracle* o, int l, BranchData& d) {
   for (int k = 0; k < 8; ++k) {
     d.vb[k] = o->v[b0 + k];
     d.z[k] = o->z[b0 + k];
+    d.cv[k] = d.vb[k] - d.z[k];
     d.y[k] = o->y[b0 + k];
     d.rho[k] = o->rho[b0 + k];
   }
@@ -1976,6 +1982,7 @@ static void unpack_branch(const double* in, int n, BranchData& d) {
   for (int k = 0; k < 8; ++k) {
     d.vb[k] = in[20 + k];
     d.z[k] = in[28 + k];
+    d.cv[k] = d.vb[k] - d.z[k];
     d.y[k] = in[36 + k];
     d.rho[k] = in[44 + k];
   }

@@ -99,7 +99,18 @@ struct BusArgs {
   double* tmax;              // [n_tiles][3] residual maxima of each tile
   int ecap, gcap;            // branch ends / generators of a tile staged in LDS
   int tbmax;                 // buses per tile at most (a quarter of the block)
+  const int* erec;           // [ne] record half of each end: 2 l + (0 from, 1 to)
+  double* brec;              // [nl][16] branch records for the next x-step
 };
+
+// Half of a branch record (64 bytes): the pairs (v_k - z_k, y_k) of one
+// end's four couplings p, q, w, theta, written by the step that produced
+// v, z and y, so that the branch step reads its inputs as one line.
+__device__ inline void store_record_half(double* brec, int half, const double2* rec) {
+  double2* dst = reinterpret_cast<double2*>(brec) + 4 * (int64_t)half;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) dst[t] = rec[t];
+}
 
 // LDS bytes of one bus tile of at most `tb` buses and the given capacities.
 __host__ __device__ inline size_t bus_lds_bytes(int tb, int ecap, int gcap) {
@@ -173,8 +184,10 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
   // writes these words before phase 3, where this lane owns them.
   const bool own_e = tid < net && tid < ecap, own_g = tid < ngt && tid < gcap;
   double ev[4], el[4], gv[2], gl[2];
+  int ehalf = 0;
   if (own_e) {
     const int64_t k = E0 + tid;
+    ehalf = A.erec[k];
 #pragma unroll
     for (int kind = 0; kind < 4; ++kind) {
       const int64_t c = ec(k, kind);
@@ -262,9 +275,10 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
     rp = fmax(rp, fabs(uk - vnew + zk));
     rd = fmax(rd, fabs(vnew - vold));
     rz = fmax(rz, fabs(zk));
+    return make_double2(vnew - zk, yk);
   };
   auto finish = [&](int64_t k, double vnew, double rho) {
-    finish_with(k, vnew, rho, A.v[k], A.u[k], A.y[k], A.lam[k]);
+    return finish_with(k, vnew, rho, A.v[k], A.u[k], A.y[k], A.lam[k]);
   };
   if (own_g) {
     const int b = gmap[tid];
@@ -279,18 +293,22 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
   if (own_e) {
     const int b = emap[tid];
     const int64_t k = E0 + tid;
-    finish_with(ec(k, 0), (cend(0, tid) + bv[b]) / rpq, rpq, ev[0], A.u[ec(k, 0)], A.y[ec(k, 0)], el[0]);
-    finish_with(ec(k, 1), (cend(1, tid) + bv[tb + b]) / rpq, rpq, ev[1], A.u[ec(k, 1)], A.y[ec(k, 1)], el[1]);
-    finish_with(ec(k, 2), bv[2 * tb + b], rva, ev[2], A.u[ec(k, 2)], A.y[ec(k, 2)], el[2]);
-    finish_with(ec(k, 3), bv[3 * tb + b], rva, ev[3], A.u[ec(k, 3)], A.y[ec(k, 3)], el[3]);
+    double2 rec[4];
+    rec[0] = finish_with(ec(k, 0), (cend(0, tid) + bv[b]) / rpq, rpq, ev[0], A.u[ec(k, 0)], A.y[ec(k, 0)], el[0]);
+    rec[1] = finish_with(ec(k, 1), (cend(1, tid) + bv[tb + b]) / rpq, rpq, ev[1], A.u[ec(k, 1)], A.y[ec(k, 1)], el[1]);
+    rec[2] = finish_with(ec(k, 2), bv[2 * tb + b], rva, ev[2], A.u[ec(k, 2)], A.y[ec(k, 2)], el[2]);
+    rec[3] = finish_with(ec(k, 3), bv[3 * tb + b], rva, ev[3], A.u[ec(k, 3)], A.y[ec(k, 3)], el[3]);
+    store_record_half(A.brec, ehalf, rec);
   }
   for (int e = own_e ? tid + nt : tid; e < net; e += nt) {
     const int b = e < ecap ? emap[e] : tile_bus_of(A.eptr, b0, nbt, E0, e);
     const int64_t k = E0 + e;
-    finish(ec(k, 0), (cend(0, e) + bv[b]) / rpq, rpq);
-    finish(ec(k, 1), (cend(1, e) + bv[tb + b]) / rpq, rpq);
-    finish(ec(k, 2), bv[2 * tb + b], rva);
-    finish(ec(k, 3), bv[3 * tb + b], rva);
+    double2 rec[4];
+    rec[0] = finish(ec(k, 0), (cend(0, e) + bv[b]) / rpq, rpq);
+    rec[1] = finish(ec(k, 1), (cend(1, e) + bv[tb + b]) / rpq, rpq);
+    rec[2] = finish(ec(k, 2), bv[2 * tb + b], rva);
+    rec[3] = finish(ec(k, 3), bv[3 * tb + b], rva);
+    store_record_half(A.brec, A.erec[k], rec);
   }
   // tile maxima (wavefront, then across the block's wavefronts), written to
   // the tile's own slot: no atomics, and the control kernel reduces a grid's
@@ -318,6 +336,24 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
     A.tmax[3 * t + 1] = rd;
     A.tmax[3 * t + 2] = rz;
   }
+}
+
+// Branch records of the ends [e0, e1) from the current v, z and y (after a
+// cold start or any change of the state from the host): the same values the
+// bus step writes.
+__global__ __launch_bounds__(256) void record_kernel(int64_t ng, int64_t e0, int64_t e1,
+                                                     const int* erec, const double* v,
+                                                     const double* z, const double* y,
+                                                     double* brec) {
+  const int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= e1) return;
+  double2 rec[4];
+#pragma unroll
+  for (int kind = 0; kind < 4; ++kind) {
+    const int64_t k = 2 * ng + 4 * e + kind;
+    rec[kind] = make_double2(v[k] - z[k], y[k]);
+  }
+  store_record_half(brec, erec[e], rec);
 }
 
 struct CtlArgs {
@@ -643,6 +679,8 @@ struct acopf_s {
   unsigned long long* qual = nullptr;  // [6 G] quality maxima (lazy)
   double *u, *v, *z, *y, *lam, *bx, *ltil, *rtil;
   double* calpha;  // [nl] TRON Cauchy step length of each branch's last solve
+  double* brec = nullptr;  // [nl][16] branch records (v - z, y per coupling)
+  int* erec = nullptr;     // [ne] record half of each branch end
   int *gptr, *eptr, *isref;
   std::vector<int> gptr_h, eptr_h;  // host copies, for the bus tiles
   TileDesc* tdesc = nullptr;         // [nb] bus tiles of the bus kernel
@@ -696,6 +734,7 @@ BranchArgs branch_args(const acopf_s* h) {
   A.v = h->v;
   A.z = h->z;
   A.y = h->y;
+  A.brec = h->brec;
   A.u = h->u;
   A.bx = h->bx;
   A.ltil = h->ltil;
@@ -794,7 +833,7 @@ void launch_iteration(acopf_s* h, int slot) {
   mark(1);
   BusArgs bu{h->nb, h->ng, h->ne, h->tdesc, h->bus_grid, h->ctl, h->gptr, h->eptr,
              h->pd, h->qd, h->gs, h->bs, h->isref, h->u, h->lam, h->v, h->z, h->y,
-             h->P.rho_pq, h->P.rho_va, h->tmax, h->ecap, h->gcap, h->tbmax};
+             h->P.rho_pq, h->P.rho_va, h->tmax, h->ecap, h->gcap, h->tbmax, h->erec, h->brec};
   const int bb = h->tile_block;
   hipLaunchKernelGGL(bus_kernel, dim3(h->n_tiles), dim3(bb),
                      bus_lds_bytes(h->tbmax, h->ecap, h->gcap), s, bu);
@@ -1137,6 +1176,8 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   for (double** p : br_d) HIP_TRY(D.alloc(p, nl));
   HIP_TRY(D.alloc(&h->end_bus, 2 * nl));
   HIP_TRY(D.alloc(&h->bx, 6 * nl));
+  HIP_TRY(D.alloc(&h->brec, 16 * nl));
+  HIP_TRY(D.alloc(&h->erec, 2 * nl));
   HIP_TRY(D.alloc(&h->ltil, 2 * nl));
   double** cp_d[] = {&h->u, &h->v, &h->z, &h->y, &h->lam};
   for (double** p : cp_d) HIP_TRY(D.alloc(p, m));
@@ -1168,6 +1209,12 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(up(h->bus_grid, bus_grid.data(), sizeof(int) * nb));
   HIP_TRY(up(h->ef, ef.data(), sizeof(int) * nl));
   HIP_TRY(up(h->et, et.data(), sizeof(int) * nl));
+  std::vector<int> erec(2 * nl);
+  for (int64_t d = 0; d < nl; ++d) {
+    erec[ef[d]] = (int)(2 * d);
+    erec[et[d]] = (int)(2 * d + 1);
+  }
+  HIP_TRY(up(h->erec, erec.data(), sizeof(int) * 2 * nl));
   const std::vector<double>* gen_h[] = {&pmin, &pmax, &qmin, &qmax, &c2q, &c1l, &c2, &c1, &c0};
   for (int q = 0; q < 9; ++q) HIP_TRY(up(*gen_d[q], gen_h[q]->data(), sizeof(double) * ng));
   HIP_TRY(up(h->adm, adm.data(), sizeof(double) * 8 * nl));
@@ -1322,6 +1369,12 @@ static int start_impl(acopf_s* h, int grid, int mode, int fixed_iters) {
                 h->rtil, h->calpha, h->P.al_rho0};
     hipLaunchKernelGGL(cold_kernel, dim3(blocks_for(h->ng + h->nl, 256)), dim3(256), 0, st, ca);
   }
+  // branch records from the state the solve starts from (the host may have
+  // changed v, z or y since the last bus step)
+  const int64_t e0 = grid < 0 ? 0 : h->grids[grid].e0, e1 = grid < 0 ? h->ne : h->grids[grid].e1;
+  if (e1 > e0)
+    hipLaunchKernelGGL(record_kernel, dim3(blocks_for(e1 - e0, 256)), dim3(256), 0, st, h->ng,
+                       e0, e1, h->erec, h->v, h->z, h->y, h->brec);
   hipLaunchKernelGGL(ctl_start_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, st, h->ctl,
                      h->G, grid, mode, fixed_iters, h->P.beta0, h->failures);
   HIP_TRY(hipGetLastError());
@@ -1746,7 +1799,7 @@ static std::vector<std::pair<void*, size_t>> state_arrays(acopf_s* h) {
   return {{h->u, h->m * d},      {h->v, h->m * d},      {h->z, h->m * d},
           {h->y, h->m * d},      {h->lam, h->m * d},    {h->bx, 6 * h->nl * d},
           {h->ltil, 2 * h->nl * d}, {h->rtil, h->nl * d}, {h->calpha, h->nl * d},
-          {h->pd, h->nb * d},
+          {h->brec, 16 * h->nl * d}, {h->pd, h->nb * d},
           {h->qd, h->nb * d},    {h->ctl, h->G * sizeof(GridCtl)}};
 }
 

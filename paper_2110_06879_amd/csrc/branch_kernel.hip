@@ -101,7 +101,7 @@ struct Sym {
 template <int N>
 struct BranchIn {
   double gii, bii, gij, bij, gji, bji, gjj, bjj;
-  double vb[8], zc[8], yc[8];
+  double cv[8], yc[8];  // per coupling: target v_k - z_k and multiplier y_k
   double rpq, rva;
   double lt0, lt1, rt;
   __device__ double rho(int k) const { return k < 4 ? rpq : rva; }
@@ -189,10 +189,10 @@ __device__ double fval(const BranchIn<N>& B, const double* x, double* a, double*
   double F = 0.0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const double r = (a[k] - B.vb[k]) + B.zc[k];
+    const double r = a[k] - B.cv[k];
     F = fma(0.5 * B.rho(k) * r, r, fma(B.yc[k], r, F));
   }
-  FL(64);
+  FL(56);
   if (N == 6) {
     const double c0 = fma(a[0], a[0], a[1] * a[1]) + x[4];
     F = fma(0.5 * B.rt * c0, c0, fma(B.lt0, c0, F));
@@ -246,7 +246,7 @@ __device__ void fgh_at(const BranchIn<N>& B, const double* x, const double* a,
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const double rk = B.rho(k);
-    const double r = (a[k] - B.vb[k]) + B.zc[k];
+    const double r = a[k] - B.cv[k];
     F = fma(0.5 * rk * r, r, fma(B.yc[k], r, F));
     mu[k] = fma(rk, r, B.yc[k]);
     nu[k] = rk;
@@ -255,11 +255,11 @@ __device__ void fgh_at(const BranchIn<N>& B, const double* x, const double* a,
 #pragma unroll
   for (int k = 4; k < 8; ++k) {
     const double rk = B.rva;
-    const double r = (a[k] - B.vb[k]) + B.zc[k];
+    const double r = a[k] - B.cv[k];
     F = fma(0.5 * rk * r, r, fma(B.yc[k], r, F));
     mv[k - 4] = fma(rk, r, B.yc[k]);
   }
-  FL(80);
+  FL(72);
   double gc[2][4], me[2];
   if (N == 6) {
 #pragma unroll
@@ -1044,11 +1044,44 @@ __device__ bool tron_advance(TronState<N>& S, const BranchIn<N>& B, const double
 
 #undef FL
 
+// Coupling positions k = 0..7 of branch l: p_ij q_ij p_ji q_ji w_i th_i w_j th_j.
+__device__ inline void branch_couplings(const BranchArgs& A, int64_t l, int64_t* cidx) {
+  const int64_t ef = A.ef[l], et = A.et[l];
+  cidx[0] = end_coupling(A.ng, A.ne, 0, ef);
+  cidx[1] = end_coupling(A.ng, A.ne, 1, ef);
+  cidx[2] = end_coupling(A.ng, A.ne, 0, et);
+  cidx[3] = end_coupling(A.ng, A.ne, 1, et);
+  cidx[4] = end_coupling(A.ng, A.ne, 2, ef);
+  cidx[5] = end_coupling(A.ng, A.ne, 3, ef);
+  cidx[6] = end_coupling(A.ng, A.ne, 2, et);
+  cidx[7] = end_coupling(A.ng, A.ne, 3, et);
+}
+
+// The branch's record (written by the bus step, 128 bytes): per end (from,
+// to) and per coupling kind (p, q, w, theta) the pair (v_k - z_k, y_k),
+// read as eight 16-byte loads of one 128-byte line.
+template <int N>
+__device__ inline void load_record(const BranchArgs& A, int64_t l, BranchIn<N>& B) {
+  const double2* rec = reinterpret_cast<const double2*>(A.brec) + 8 * l;
+  double2 q[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) q[t] = rec[t];
+  // record slot (end * 4 + kind) -> coupling k = 0..7: p_ij q_ij p_ji q_ji
+  // w_i th_i w_j th_j
+  constexpr int kOf[8] = {0, 1, 4, 5, 2, 3, 6, 7};
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    B.cv[kOf[t]] = q[t].x;
+    B.yc[kOf[t]] = q[t].y;
+  }
+}
+
 // Branch l of the device order with N variables: solve, write u and state.
-// Every input load is issued before the grid's done flag is tested, so that
-// the lane waits for two rounds of memory accesses (branch data and end
-// positions, then the gathered coupling values and the flag) before it
-// computes. Returns false, without solving, when the grid has finished.
+// Every input load (branch data, its record, its state and the grid's done
+// flag) is issued before the flag is tested, so that the lane waits for one
+// round of memory accesses before it computes; the end positions are needed
+// only for the stores of u. Returns false, without solving, when the grid has
+// finished.
 template <int N, class Cnt>
 __device__ bool solve_branch(const BranchArgs& A, int64_t l, Cnt& cnt) {
   {
@@ -1078,25 +1111,7 @@ __device__ bool solve_branch(const BranchArgs& A, int64_t l, Cnt& cnt) {
       lo[5] = -A.rate2[l];
       hi[5] = 0.0;
     }
-    // couplings k = 0..7: p_ij q_ij p_ji q_ji w_i th_i w_j th_j
-    int64_t cidx[8];
-    {
-      const int64_t ef = A.ef[l], et = A.et[l];
-      cidx[0] = end_coupling(A.ng, A.ne, 0, ef);
-      cidx[1] = end_coupling(A.ng, A.ne, 1, ef);
-      cidx[2] = end_coupling(A.ng, A.ne, 0, et);
-      cidx[3] = end_coupling(A.ng, A.ne, 1, et);
-      cidx[4] = end_coupling(A.ng, A.ne, 2, ef);
-      cidx[5] = end_coupling(A.ng, A.ne, 3, ef);
-      cidx[6] = end_coupling(A.ng, A.ne, 2, et);
-      cidx[7] = end_coupling(A.ng, A.ne, 3, et);
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      B.vb[k] = A.v[cidx[k]];
-      B.zc[k] = A.z[cidx[k]];
-      B.yc[k] = A.y[cidx[k]];
-    }
+    load_record(A, l, B);
     B.rpq = A.rho_pq;
     B.rva = A.rho_va;
     double x[N];
@@ -1147,6 +1162,8 @@ __device__ bool solve_branch(const BranchArgs& A, int64_t l, Cnt& cnt) {
     }
     double a[8], aux[4];
     values<N>(B, x, a, aux, cnt);
+    int64_t cidx[8];
+    branch_couplings(A, l, cidx);
 #pragma unroll
     for (int k = 0; k < 8; ++k) A.u[cidx[k]] = a[k];
 #pragma unroll
@@ -1170,18 +1187,6 @@ __device__ inline void solve_generator(const BranchArgs& A, int64_t g) {
   A.u[kq] = fmax(A.qmin[g], fmin(A.qmax[g], xq));
 }
 
-// Coupling positions k = 0..7 of branch l: p_ij q_ij p_ji q_ji w_i th_i w_j th_j.
-__device__ inline void branch_couplings(const BranchArgs& A, int64_t l, int64_t* cidx) {
-  const int64_t ef = A.ef[l], et = A.et[l];
-  cidx[0] = end_coupling(A.ng, A.ne, 0, ef);
-  cidx[1] = end_coupling(A.ng, A.ne, 1, ef);
-  cidx[2] = end_coupling(A.ng, A.ne, 0, et);
-  cidx[3] = end_coupling(A.ng, A.ne, 1, et);
-  cidx[4] = end_coupling(A.ng, A.ne, 2, ef);
-  cidx[5] = end_coupling(A.ng, A.ne, 3, ef);
-  cidx[6] = end_coupling(A.ng, A.ne, 2, et);
-  cidx[7] = end_coupling(A.ng, A.ne, 3, et);
-}
 
 // Loads branch l: data, bounds, coupling values and the persistent state.
 template <int N>
@@ -1210,14 +1215,7 @@ __device__ inline void load_branch(const BranchArgs& A, int64_t l, BranchIn<N>& 
     lo[5] = -A.rate2[l];
     hi[5] = 0.0;
   }
-  int64_t cidx[8];
-  branch_couplings(A, l, cidx);
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    B.vb[k] = A.v[cidx[k]];
-    B.zc[k] = A.z[cidx[k]];
-    B.yc[k] = A.y[cidx[k]];
-  }
+  load_record(A, l, B);
   B.rpq = A.rho_pq;
   B.rva = A.rho_va;
 #pragma unroll

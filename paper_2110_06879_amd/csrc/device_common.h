@@ -38,6 +38,7 @@ struct BranchArgs {
   const double* adm;         // [8][nl] gii bii gij bij gji bji gjj bjj
   const double *vlo_i, *vhi_i, *vlo_j, *vhi_j, *rate2;
   const double *v, *z, *y;
+  const double* brec;        // [nl][16] branch records written by the bus step
   double* u;
   double *bx, *ltil, *rtil;  // [6][nl], [2][nl], [nl]
   double* calpha;            // [nl] TRON Cauchy step length, carried between solves

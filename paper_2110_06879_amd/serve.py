@@ -40,8 +40,9 @@ def instance_bytes(g: Grid) -> int:
     """Device footprint of one grid instance in the library's layout."""
     m = g.n_coupling
     nb, ng, nl = g.n_bus, g.n_gen, g.n_branch
-    doubles = 5 * m + 9 * nl + 8 * nl + 5 * nl + 9 * ng + 4 * nb
-    ints = 2 * nl + nl + 2 * nl + ng + 3 * nb + 2
+    # coupling vectors; branch data, state and records; generators; buses
+    doubles = 5 * m + 9 * nl + 8 * nl + 5 * nl + 16 * nl + 9 * ng + 6 * nb
+    ints = 2 * nl + nl + 2 * nl + 2 * nl + ng + 3 * nb + 2
     return 8 * doubles + 4 * ints + 6 * 8 * (1 << 15)  # + residual history
 
 
