@@ -285,6 +285,19 @@ int acopf_quality(acopf_handle h, int32_t grid, double* out6);
  * way. Errors: EINVAL. */
 int acopf_set_counting(acopf_handle h, int32_t on);
 
+/* acopf_quality without any allocation, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same six values as acopf_quality, with the
+ * recovery's scratch in a fixed device-resident array of the library
+ * (2^20 eight-byte words, 8 MiB, per device, held until the process ends)
+ * instead of memory it allocates. The handle must fit that array:
+ * 2 n_bus + 4 n_branch + 6 n_grids, summed over the handle's grids, at most
+ * 2^20; larger handles are rejected with EINVAL. Every call on one device
+ * shares the array (each call clears what must start at zero), so calls
+ * that overlap on one GPU, from several threads or on several streams, race.
+ * Synchronous on the handle's stream. Errors: EINVAL, EDEVICE. */
+int acopf_quality_noalloc(acopf_handle h, int32_t grid, double* out6);
+
 /* Average device time (ms) per launch over every iteration run with
  * profiling on since the handle was created: out[0] x-step (generators and
  * branches), out[1] bus/z/y/residual step, out[2] control (which also

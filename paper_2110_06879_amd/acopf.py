@@ -37,7 +37,7 @@ EXPORTS = ("acopf_default_params", "acopf_create", "acopf_solve", "acopf_update_
            "acopf_run", "acopf_poll", "acopf_copy_grid", "acopf_snapshot",
            "acopf_set_tuning", "acopf_get_tuning", "acopf_autotune", "acopf_quality",
            "acopf_update_gen_bounds", "acopf_set_counting", "acopf_peak_hbm",
-           "acopf_peak_fp64")
+           "acopf_peak_fp64", "acopf_quality_noalloc")
 QUALITY_NAMES = ("max_violation", "balance_p", "balance_q", "line_limit", "voltage_limit",
                  "angle_limit")
 
@@ -156,6 +156,7 @@ def load(path: str | None = None) -> C.CDLL:
     lib.acopf_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
     lib.acopf_autotune.argtypes = [vp, i32, C.POINTER(_Tuning)]
     lib.acopf_quality.argtypes = [vp, i32, dp]
+    lib.acopf_quality_noalloc.argtypes = [vp, i32, dp]
     lib.acopf_update_gen_bounds.argtypes = [vp, i32, dp, dp]
     lib.acopf_set_counting.argtypes = [vp, i32]
     lib.acopf_destroy.argtypes = [vp]
@@ -168,6 +169,7 @@ def load(path: str | None = None) -> C.CDLL:
                  "acopf_set_profiling", "acopf_start", "acopf_run", "acopf_poll",
                  "acopf_copy_grid", "acopf_snapshot", "acopf_set_tuning",
                  "acopf_get_tuning", "acopf_autotune", "acopf_quality",
+                 "acopf_quality_noalloc",
                  "acopf_update_gen_bounds", "acopf_set_counting", "acopf_peak_hbm",
                  "acopf_peak_fp64"):
         getattr(lib, name).restype = C.c_int

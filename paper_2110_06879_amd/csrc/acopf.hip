@@ -41,6 +41,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -73,6 +74,13 @@ constexpr int kTimed = 3;       // kernels timed per iteration (x-step, bus, ctl
 constexpr int kChunk = 16;      // iterations between control readbacks (default)
 constexpr int kMaxChunk = 64;   // largest chunk acopf_set_tuning accepts
 
+// Device-resident scratch of acopf_quality_noalloc: 2^20 eight-byte words
+// (8 MiB) per device, held until the process ends. Host code never uses the
+// array's name as an address: each device's address comes from
+// hipGetSymbolAddress (noalloc_scratch below).
+constexpr int64_t kNoAllocWords = int64_t(1) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocWords];
 
 // ---------------------------------------------------------------------------
 // kernels
@@ -1257,6 +1265,29 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
 
 static int ensure_graph(acopf_s* h);
 
+// Address of `scratch` on each device, resolved once per device with that
+// device current (at the first acopf_create on it).
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+static int noalloc_scratch(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(ACOPF_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != device) HIP_TRY(hipSetDevice(device));
+    double* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(reinterpret_cast<void**>(&ptr), HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr)
+      return fail(ACOPF_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return ACOPF_OK;
+}
+
 int acopf_create(const acopf_grid* grids, int32_t n_grids, const acopf_params* params,
                  int32_t device, void* hip_stream, acopf_handle* out) {
   if (!out) return fail(ACOPF_EINVAL, "out is null");
@@ -1290,7 +1321,9 @@ int acopf_create(const acopf_grid* grids, int32_t n_grids, const acopf_params* p
     acopf_destroy(h);
     return fail(ACOPF_EDEVICE, std::string("cold start: ") + hipGetErrorString(e));
   }
-  rc = ensure_graph(h);
+  double* sp = nullptr;
+  rc = noalloc_scratch(h->device, &sp);
+  if (!rc) rc = ensure_graph(h);
   if (rc) {
     std::string msg = g_err;
     acopf_destroy(h);
@@ -2004,6 +2037,41 @@ int acopf_quality(acopf_handle h, int32_t grid, double* out6) {
   hipStream_t st = h->stream;
   unsigned long long bits[6];
   HIP_TRY(hipMemcpyAsync(bits, h->qual + 6 * grid, sizeof(bits), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double q[6];
+  for (int k = 0; k < 6; ++k) std::memcpy(&q[k], &bits[k], sizeof(double));
+  auto nanmax = [](double a, double b) { return (b > a || b != b) ? b : a; };
+  out6[0] = nanmax(nanmax(nanmax(q[1], q[2]), nanmax(q[3], q[4])), q[5]);
+  for (int k = 1; k < 6; ++k) out6[k] = q[k];
+  return ACOPF_OK;
+}
+
+int acopf_quality_noalloc(acopf_handle h, int32_t grid, double* out6) {
+  if (!h || !out6) return fail(ACOPF_EINVAL, "null argument");
+  if (grid < 0 || grid >= h->G) return fail(ACOPF_EINVAL, "grid index out of range");
+  // bus w and theta [2 nb], flows per branch end [2 ne], then 6 maxima per
+  // grid of the handle, in eight-byte words
+  const int64_t words = 2 * h->nb + 2 * h->ne + 6 * (int64_t)h->G;
+  if (words > kNoAllocWords)
+    return fail(ACOPF_EINVAL, "handle too large for the fixed scratch: needs " +
+                                  std::to_string(words) + " words (2 n_bus + 4 n_branch + 6 "
+                                  "n_grids over the handle), the maximum is " +
+                                  std::to_string(kNoAllocWords));
+  HIP_TRY(hipSetDevice(h->device));
+  double* sp = nullptr;
+  int rc = noalloc_scratch(h->device, &sp);
+  if (rc) return rc;
+  hipStream_t st = h->stream;
+  unsigned long long* qmax = reinterpret_cast<unsigned long long*>(sp + 2 * h->nb + 2 * h->ne);
+  acopf_dev::launch_fill_u64(qmax, (int64_t)6 * h->G, st);
+  acopf_dev::QualityArgs Q{h->nb, h->ng, h->nl, h->ne, h->bus_grid, h->br_grid, h->gen_grid,
+                           h->gptr, h->eptr, h->ef, h->et, h->end_bus, h->adm, h->rate, h->u,
+                           h->v, h->pd, h->qd, h->gs, h->bs, h->vmin_b, h->vmax_b,
+                           sp, sp + h->nb, sp + 2 * h->nb, sp + 2 * h->nb + h->ne, qmax};
+  acopf_dev::launch_quality(Q, st);
+  HIP_TRY(hipGetLastError());
+  unsigned long long bits[6];
+  HIP_TRY(hipMemcpyAsync(bits, qmax + 6 * grid, sizeof(bits), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   double q[6];
   for (int k = 0; k < 6; ++k) std::memcpy(&q[k], &bits[k], sizeof(double));
