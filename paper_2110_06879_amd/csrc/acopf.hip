@@ -6,7 +6,8 @@
 //                   and the generator closed form, eq. (qp-bound)   lane/gen
 //   bus_kernel      bus closed form eq. (qp-bus), then z and y and
 //                   the residual maxima of every coupling it owns  block/tile
-//                                                                  of buses
+//                   (tiles of a bus too large for one block in a   of buses,
+//                   second launch, only when there are such buses) lane/pair
 //   ctl_kernel      termination tests and the outer beta rule       block/grid
 //                   and, when an outer step ends, lambda <- proj(lambda
 //                   + beta z) over the grid's couplings
@@ -89,7 +90,7 @@ static __device__ __align__(256) double scratch[kNoAllocWords];
 // One bus tile: buses [b0, b1) of grid `grid`, their branch ends [e0, e1)
 // and generators [g0, g1) in the device orders.
 struct TileDesc {
-  int b0, b1, e0, e1, g0, g1, grid, pad;
+  int b0, b1, e0, e1, g0, g1, grid, hub;  // hub: more pairs than lanes
 };
 
 struct BusArgs {
@@ -105,10 +106,9 @@ struct BusArgs {
   double *v, *z, *y;
   double rho_pq, rho_va;
   double* tmax;              // [n_tiles][3] residual maxima of each tile
-  int ecap, gcap;            // branch ends / generators of a tile staged in LDS
-  int tbmax;                 // buses per tile at most (a quarter of the block)
   const int* erec;           // [ne] record half of each end: 2 l + (0 from, 1 to)
   double* brec;              // [nl][16] branch records for the next x-step
+  const int* hub_tile;       // [n_hub] tiles of the hub launch
 };
 
 // Half of a branch record (64 bytes): the pairs (v_k - z_k, y_k) of one
@@ -120,21 +120,86 @@ __device__ inline void store_record_half(double* brec, int half, const double2* 
   for (int t = 0; t < 4; ++t) dst[t] = rec[t];
 }
 
-// LDS bytes of one bus tile of at most `tb` buses and the given capacities.
-__host__ __device__ inline size_t bus_lds_bytes(int tb, int ecap, int gcap) {
-  return sizeof(double) * (4 * (size_t)ecap + 2 * (size_t)gcap + 4 * (size_t)tb) +
-         sizeof(unsigned short) * ((size_t)ecap + gcap);
+// LDS bytes of one bus tile of `nt` lanes: per coupling (two per lane) its
+// target and its quotient by rho_pq, per lane the local bus of its pair, per
+// bus (at most nt / 2) four results.
+__host__ __device__ inline size_t bus_lds_bytes(int nt) {
+  return sizeof(double) * (4 * (size_t)nt + 4 * (size_t)(nt / 2)) + sizeof(unsigned short) * (size_t)nt;
 }
 
-// Local bus (0-based in the tile) of local element `e` of a CSR range.
-__device__ inline int tile_bus_of(const int* ptr, int b0, int nbt, int base, int e) {
-  int lo = 0, hi = nbt - 1;  // largest local bus with ptr[b0 + bus] - base <= e
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (ptr[b0 + mid] - base <= e) lo = mid;
-    else hi = mid - 1;
+// Phase 2 of the bus step for one bus (lane per bus): the sums over its
+// couplings in their fixed order and the 2x2 solve. Slot 2 j and 2 j + 1 of
+// `val` and `quo` are the two couplings of pair j (generator g is pair
+// 2 n_ends + g: slots nce + 2 g for p, nce + 2 g + 1 for q). kHub: the tile is a
+// single bus with more couplings than its LDS holds, and values past the
+// LDS are recomputed from global memory by `val` and `quo`.
+template <bool kHub, class Val, class Quo>
+__device__ inline void bus_solve(int tid, int be0, int be1, int bg0, int bg1, int nce, int ngt,
+                                 double bgs, double bbs, double bpd, double bqd, int bref,
+                                 double rpq, double rva, const Val& val, const Quo& quo,
+                                 unsigned short* cb, int ncap, double* bv, int tb) {
+  // Each loop reads four terms at a time (a clamped index reads a valid slot
+  // whose value is not used), so that the reads overlap; the sums still add
+  // one term at a time in their fixed order.
+  double Qw = 0.0, cw = 0.0, Qt = 0.0, ctt = 0.0;
+  for (int e = be0; e < be1; e += 4) {
+    double w4[4], t4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int ek = e + k < be1 ? e + k : e;
+      w4[k] = val(4 * ek + 2);
+      t4[k] = val(4 * ek + 3);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (e + k < be1) {
+        Qw += rva;
+        cw += w4[k];
+        Qt += rva;
+        ctt += t4[k];
+        if (!kHub || 2 * (e + k) + 1 < ncap) {
+          cb[2 * (e + k)] = (unsigned short)tid;
+          cb[2 * (e + k) + 1] = (unsigned short)tid;
+        }
+      }
+    }
   }
-  return lo;
+  const double awP = -bgs, awQ = bbs;
+  double M00 = awP * awP / Qw, M01 = awP * awQ / Qw, M11 = awQ * awQ / Qw;
+  double r0 = awP * cw / Qw - bpd, r1 = awQ * cw / Qw - bqd;
+  const double inv_pq = 1.0 / rpq;
+  for (int g = bg0; g < bg1; ++g) {
+    M00 += inv_pq;
+    r0 += quo(nce + 2 * g);
+    M11 += inv_pq;
+    r1 += quo(nce + 2 * g + 1);
+    if (!kHub || nce / 2 + g < ncap) cb[nce / 2 + g] = (unsigned short)tid;
+  }
+  for (int e = be0; e < be1; e += 4) {
+    double p4[4], q4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int ek = e + k < be1 ? e + k : e;
+      p4[k] = quo(4 * ek);
+      q4[k] = quo(4 * ek + 1);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (e + k < be1) {
+        M00 += inv_pq;
+        r0 += -p4[k];
+        M11 += inv_pq;
+        r1 += -q4[k];
+      }
+    }
+  }
+  const double det = M00 * M11 - M01 * M01;
+  const double mu0 = (M11 * r0 - M01 * r1) / det;
+  const double mu1 = (M00 * r1 - M01 * r0) / det;
+  bv[tid] = mu0;
+  bv[tb + tid] = mu1;
+  bv[2 * tb + tid] = (cw - awP * mu0 - awQ * mu1) / Qw;
+  bv[3 * tb + tid] = bref ? 0.0 : ctt / Qt;
 }
 
 // eq. (qp-bus) for every bus of one tile of consecutive buses: minimize
@@ -142,35 +207,37 @@ __device__ inline int tile_bus_of(const int* ptr, int b0, int nbt, int base, int
 // leaving the bus, w) subject to the two balance rows of eqs. (pg)-(qg);
 // closed form through the 2x2 matrix M = A Q^-1 A'. Then z (eq. qp-bound
 // with no bounds) and y for every coupling of the tile, and their residual
-// maxima. Three phases over one workgroup of four lanes per bus:
-//   1. lane per branch end / generator: the prox targets
-//      c_k = rho_k (u_k + z_k) + y_k of the tile's couplings into LDS
-//      (coalesced: the tile's couplings are contiguous in every block);
+// maxima. A tile's couplings are its end couplings (contiguous, p q w theta
+// per end) followed by its generators' p and q couplings; each lane owns a
+// pair of couplings: an end's (p, q) or (w, theta), or a generator's (p, q).
+//   1. lane per pair: the prox targets c_k = rho_k (u_k + z_k) + y_k and,
+//      for p and q couplings, c_k / rho_pq, into LDS (16-byte loads);
 //   2. lane per bus: the sums over its couplings in their fixed order, read
-//      from LDS, and the 2x2 solve (its bus data loaded during phase 1);
-//   3. lane per branch end / generator: new v, z, y and the residuals.
-// Ends or generators beyond the LDS capacity (a bus of very high degree) are
-// recomputed from global memory with the same operations.
+//      from LDS, and the 2x2 solve;
+//   3. lane per pair: new v, z, y, the branch record pairs and the residuals.
+// Every load a lane needs is issued before the grid's done flag is tested.
+// A single bus with more couplings than the tile holds (a hub) gets a tile of
+// its own; pairs past the lane count are recomputed from global memory with
+// the same operations.
+template <bool kHub>
 __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
   extern __shared__ double sm[];
-  const int t = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int t = kHub ? A.hub_tile[blockIdx.x] : (int)blockIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
   const TileDesc D = A.tdesc[t];
+  if (!kHub && D.hub) return;  // a tile of its own launch
   const int b0 = D.b0, nbt = D.b1 - D.b0, grid = D.grid;
-  if (A.ctl[grid].done) return;  // uniform: the tile lies in one grid
-  const int ecap = A.ecap, gcap = A.gcap, tb = A.tbmax;
-  double* cE = sm;              // [4][ecap] targets of end blocks p, q, w, theta
-  double* cG = cE + 4 * ecap;   // [2][gcap] targets of generator p, q
-  double* bv = cG + 2 * gcap;   // [4][tb]   mu0, mu1, w, theta per bus
-  unsigned short* emap = reinterpret_cast<unsigned short*>(bv + 4 * tb);  // [ecap]
-  unsigned short* gmap = emap + ecap;                                     // [gcap]
+  const int tb = nt >> 1, ncap = nt;  // buses and pairs held in LDS
+  double* cT = sm;                 // [2 nt] targets
+  double* cQ = cT + 2 * nt;        // [2 nt] targets / rho_pq (p and q couplings)
+  double* bv = cQ + 2 * nt;        // [4][tb] mu0, mu1, w, theta per bus
+  unsigned short* cb = reinterpret_cast<unsigned short*>(bv + 4 * tb);  // [nt] local bus per pair
   const int64_t ng = A.ng;
-  // end couplings: 2 ng + 4 e + kind (kind 0 p, 1 q, 2 w, 3 theta)
-  auto ec = [&](int64_t e, int kind) { return 2 * ng + 4 * e + kind; };
   const double rpq = A.rho_pq, rva = A.rho_va;
   const int E0 = D.e0, G0 = D.g0;
   const int net = D.e1 - D.e0, ngt = D.g1 - D.g0;
-  auto target = [&](int64_t k, double rho) { return rho * (A.u[k] + A.z[k]) + A.y[k]; };
-  // ---- phase 1 (and the bus data of phase 2, so that its loads are in flight)
+  const int nce = 4 * net, npe = 2 * net, np = npe + ngt;
+  // ---- loads: bus data (phase 2), the lane's pair, the grid's control word
   int be0 = 0, be1 = 0, bg0 = 0, bg1 = 0, bref = 0;
   double bgs = 0.0, bbs = 0.0, bpd = 0.0, bqd = 0.0;
   if (tid < nbt) {
@@ -185,138 +252,132 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
     bqd = A.qd[i];
     bref = A.isref[i];
   }
-  // The lane's first end (e = tid) and first generator (g = tid) load their
-  // phase-3 operands v and lambda here, so those loads are in flight with
-  // phase 1's instead of after the second barrier (u and y, read again in
-  // phase 3, are then cache hits; keeping them too costs occupancy). Nothing
-  // writes these words before phase 3, where this lane owns them.
-  const bool own_e = tid < net && tid < ecap, own_g = tid < ngt && tid < gcap;
-  double ev[4], el[4], gv[2], gl[2];
-  int ehalf = 0;
-  if (own_e) {
-    const int64_t k = E0 + tid;
-    ehalf = A.erec[k];
-#pragma unroll
-    for (int kind = 0; kind < 4; ++kind) {
-      const int64_t c = ec(k, kind);
-      ev[kind] = A.v[c];
-      el[kind] = A.lam[c];
-      cE[kind * ecap + tid] = target(c, kind < 2 ? rpq : rva);
+  // pair j: j < npe end pair (end j / 2, kinds 2 (j & 1) and 2 (j & 1) + 1),
+  // else generator j - npe (p and q)
+  double2 cu{0.0, 0.0}, cz{0.0, 0.0}, cy{0.0, 0.0}, cv{0.0, 0.0}, cl{0.0, 0.0};
+  int half = 0;
+  auto load_pair = [&](int j, double2& u_, double2& z_, double2& y_, double2& v_, double2& l_, int& hf) {
+    if (j < npe) {
+      const int64_t k = 2 * ng + 4 * (int64_t)E0 + 2 * j;
+      u_ = *reinterpret_cast<const double2*>(A.u + k);
+      z_ = *reinterpret_cast<const double2*>(A.z + k);
+      y_ = *reinterpret_cast<const double2*>(A.y + k);
+      v_ = *reinterpret_cast<const double2*>(A.v + k);
+      l_ = *reinterpret_cast<const double2*>(A.lam + k);
+      hf = A.erec[E0 + (j >> 1)];
+    } else {
+      const int64_t kp = (int64_t)G0 + (j - npe), kq = ng + kp;
+      u_ = make_double2(A.u[kp], A.u[kq]);
+      z_ = make_double2(A.z[kp], A.z[kq]);
+      y_ = make_double2(A.y[kp], A.y[kq]);
+      v_ = make_double2(A.v[kp], A.v[kq]);
+      l_ = make_double2(A.lam[kp], A.lam[kq]);
     }
-  }
-  if (own_g) {
-#pragma unroll
-    for (int blk = 0; blk < 2; ++blk) {
-      const int64_t c = (blk ? ng : 0) + G0 + tid;
-      gv[blk] = A.v[c];
-      gl[blk] = A.lam[c];
-      cG[blk * gcap + tid] = target(c, rpq);
+  };
+  const bool own = tid < np;
+  if (own) load_pair(tid, cu, cz, cy, cv, cl, half);
+  const GridCtl* C = A.ctl + grid;
+  const int done = C->done;
+  const double beta = C->beta;
+  if (done) return;  // uniform: the tile lies in one grid
+  // ---- phase 1
+  auto is_va = [&](int j) { return j < npe && (j & 1); };  // (w, theta) pair
+  if (own) {
+    const double rho = is_va(tid) ? rva : rpq;
+    const double c0 = rho * (cu.x + cz.x) + cy.x, c1 = rho * (cu.y + cz.y) + cy.y;
+    // LDS slots 2 j and 2 j + 1 hold the targets of pair j
+    cT[2 * tid] = c0;
+    cT[2 * tid + 1] = c1;
+    if (!is_va(tid)) {
+      cQ[2 * tid] = c0 / rpq;
+      cQ[2 * tid + 1] = c1 / rpq;
     }
-  }
-  for (int e = tid + nt; e < net && e < ecap; e += nt) {
-    const int64_t k = E0 + e;
-    cE[0 * ecap + e] = target(ec(k, 0), rpq);
-    cE[1 * ecap + e] = target(ec(k, 1), rpq);
-    cE[2 * ecap + e] = target(ec(k, 2), rva);
-    cE[3 * ecap + e] = target(ec(k, 3), rva);
-  }
-  for (int g = tid + nt; g < ngt && g < gcap; g += nt) {
-    cG[g] = target(G0 + g, rpq);
-    cG[gcap + g] = target(ng + G0 + g, rpq);
   }
   __syncthreads();
-  auto cend = [&](int blk, int e) {
-    if (e < ecap) return cE[blk * ecap + e];
-    return target(ec(E0 + e, blk), blk < 2 ? rpq : rva);
-  };
-  auto cgen = [&](int blk, int g) {
-    if (g < gcap) return cG[blk * gcap + g];
-    return target((blk ? ng : 0) + G0 + g, rpq);
-  };
   // ---- phase 2
   if (tid < nbt) {
-    // shared w and theta of the bus
-    double Qw = 0.0, cw = 0.0, Qt = 0.0, ct = 0.0;
-    for (int e = be0; e < be1; ++e) {
-      Qw += rva;
-      cw += cend(2, e);
-      Qt += rva;
-      ct += cend(3, e);
-      if (e < ecap) emap[e] = (unsigned short)tid;
+    if (!kHub) {
+      auto val = [&](int i) { return cT[i]; };
+      auto quo = [&](int i) { return cQ[i]; };
+      bus_solve<false>(tid, be0, be1, bg0, bg1, nce, ngt, bgs, bbs, bpd, bqd, bref, rpq, rva,
+                       val, quo, cb, ncap, bv, tb);
+    } else {
+      // a hub: slot i (pair i / 2) is held in LDS when its pair is below ncap
+      auto pair_of = [&](int i) { return i >> 1; };
+      auto gidx = [&](int i) -> int64_t {
+        if (i < nce) return 2 * ng + 4 * (int64_t)E0 + i;
+        const int j = i - nce;
+        return (int64_t)G0 + (j >> 1) + ((j & 1) ? ng : 0);
+      };
+      auto val = [&](int i) {
+        if (pair_of(i) < ncap) return cT[i];
+        const int64_t k = gidx(i);
+        const double rho = (i < nce && (i & 3) >= 2) ? rva : rpq;
+        return rho * (A.u[k] + A.z[k]) + A.y[k];
+      };
+      auto quo = [&](int i) {
+        if (pair_of(i) < ncap) return cQ[i];
+        const int64_t k = gidx(i);
+        return (rpq * (A.u[k] + A.z[k]) + A.y[k]) / rpq;
+      };
+      bus_solve<true>(tid, be0, be1, bg0, bg1, nce, ngt, bgs, bbs, bpd, bqd, bref, rpq, rva,
+                      val, quo, cb, ncap, bv, tb);
     }
-    const double awP = -bgs, awQ = bbs;
-    double M00 = awP * awP / Qw, M01 = awP * awQ / Qw, M11 = awQ * awQ / Qw;
-    double r0 = awP * cw / Qw - bpd, r1 = awQ * cw / Qw - bqd;
-    const double inv_pq = 1.0 / rpq;
-    for (int g = bg0; g < bg1; ++g) {
-      M00 += inv_pq;
-      r0 += cgen(0, g) / rpq;
-      M11 += inv_pq;
-      r1 += cgen(1, g) / rpq;
-      if (g < gcap) gmap[g] = (unsigned short)tid;
-    }
-    for (int e = be0; e < be1; ++e) {
-      M00 += inv_pq;
-      r0 += -cend(0, e) / rpq;
-      M11 += inv_pq;
-      r1 += -cend(1, e) / rpq;
-    }
-    const double det = M00 * M11 - M01 * M01;
-    const double mu0 = (M11 * r0 - M01 * r1) / det;
-    const double mu1 = (M00 * r1 - M01 * r0) / det;
-    bv[tid] = mu0;
-    bv[tb + tid] = mu1;
-    bv[2 * tb + tid] = (cw - awP * mu0 - awQ * mu1) / Qw;
-    bv[3 * tb + tid] = bref ? 0.0 : ct / Qt;
   }
   __syncthreads();
   // ---- phase 3
-  const double beta = A.ctl[grid].beta;
   double rp = 0.0, rd = 0.0, rz = 0.0;
-  auto finish_with = [&](int64_t k, double vnew, double rho, double vold, double uk,
-                         double yold, double lamk) {
-    const double zk = -(lamk + yold + rho * (uk - vnew)) / (beta + rho);
-    const double yk = yold + rho * (uk - vnew + zk);
-    A.v[k] = vnew;
-    A.z[k] = zk;
-    A.y[k] = yk;
+  auto fin = [&](double vnew, double rho, double vold, double uk, double yold, double lamk,
+                 double& zk, double& yk) {
+    zk = -(lamk + yold + rho * (uk - vnew)) / (beta + rho);
+    yk = yold + rho * (uk - vnew + zk);
     rp = fmax(rp, fabs(uk - vnew + zk));
     rd = fmax(rd, fabs(vnew - vold));
     rz = fmax(rz, fabs(zk));
-    return make_double2(vnew - zk, yk);
   };
-  auto finish = [&](int64_t k, double vnew, double rho) {
-    return finish_with(k, vnew, rho, A.v[k], A.u[k], A.y[k], A.lam[k]);
-  };
-  if (own_g) {
-    const int b = gmap[tid];
-    finish_with(G0 + tid, (cgen(0, tid) - bv[b]) / rpq, rpq, gv[0], A.u[G0 + tid], A.y[G0 + tid], gl[0]);
-    finish_with(ng + G0 + tid, (cgen(1, tid) - bv[tb + b]) / rpq, rpq, gv[1], A.u[ng + G0 + tid], A.y[ng + G0 + tid], gl[1]);
-  }
-  for (int g = own_g ? tid + nt : tid; g < ngt; g += nt) {
-    const int b = g < gcap ? gmap[g] : tile_bus_of(A.gptr, b0, nbt, G0, g);
-    finish(G0 + g, (cgen(0, g) - bv[b]) / rpq, rpq);
-    finish(ng + G0 + g, (cgen(1, g) - bv[tb + b]) / rpq, rpq);
-  }
-  if (own_e) {
-    const int b = emap[tid];
-    const int64_t k = E0 + tid;
-    double2 rec[4];
-    rec[0] = finish_with(ec(k, 0), (cend(0, tid) + bv[b]) / rpq, rpq, ev[0], A.u[ec(k, 0)], A.y[ec(k, 0)], el[0]);
-    rec[1] = finish_with(ec(k, 1), (cend(1, tid) + bv[tb + b]) / rpq, rpq, ev[1], A.u[ec(k, 1)], A.y[ec(k, 1)], el[1]);
-    rec[2] = finish_with(ec(k, 2), bv[2 * tb + b], rva, ev[2], A.u[ec(k, 2)], A.y[ec(k, 2)], el[2]);
-    rec[3] = finish_with(ec(k, 3), bv[3 * tb + b], rva, ev[3], A.u[ec(k, 3)], A.y[ec(k, 3)], el[3]);
-    store_record_half(A.brec, ehalf, rec);
-  }
-  for (int e = own_e ? tid + nt : tid; e < net; e += nt) {
-    const int b = e < ecap ? emap[e] : tile_bus_of(A.eptr, b0, nbt, E0, e);
-    const int64_t k = E0 + e;
-    double2 rec[4];
-    rec[0] = finish(ec(k, 0), (cend(0, e) + bv[b]) / rpq, rpq);
-    rec[1] = finish(ec(k, 1), (cend(1, e) + bv[tb + b]) / rpq, rpq);
-    rec[2] = finish(ec(k, 2), bv[2 * tb + b], rva);
-    rec[3] = finish(ec(k, 3), bv[3 * tb + b], rva);
-    store_record_half(A.brec, A.erec[k], rec);
+  for (int j = tid; j < np; j += (kHub ? nt : np)) {
+    double2 u_ = cu, z_ = cz, y_ = cy, v_ = cv, l_ = cl;
+    int hf = half;
+    if (kHub && j != tid) load_pair(j, u_, z_, y_, v_, l_, hf);  // hub overflow
+    const int b = !kHub || j < ncap ? cb[j] : 0;
+    const bool va = is_va(j);
+    const double rho = va ? rva : rpq;
+    // the targets of phase 1 (the same operations again for a hub's overflow)
+    const double c0 = (kHub && j != tid) ? rho * (u_.x + z_.x) + y_.x : cT[2 * j];
+    const double c1 = (kHub && j != tid) ? rho * (u_.y + z_.y) + y_.y : cT[2 * j + 1];
+    double n0, n1;
+    if (j < npe) {
+      if (va) {
+        n0 = bv[2 * tb + b];
+        n1 = bv[3 * tb + b];
+      } else {
+        n0 = (c0 + bv[b]) / rpq;
+        n1 = (c1 + bv[tb + b]) / rpq;
+      }
+    } else {
+      n0 = (c0 - bv[b]) / rpq;
+      n1 = (c1 - bv[tb + b]) / rpq;
+    }
+    double z0, y0, z1, y1;
+    fin(n0, rho, v_.x, u_.x, y_.x, l_.x, z0, y0);
+    fin(n1, rho, v_.y, u_.y, y_.y, l_.y, z1, y1);
+    if (j < npe) {
+      const int64_t k = 2 * ng + 4 * (int64_t)E0 + 2 * j;
+      *reinterpret_cast<double2*>(A.v + k) = make_double2(n0, n1);
+      *reinterpret_cast<double2*>(A.z + k) = make_double2(z0, z1);
+      *reinterpret_cast<double2*>(A.y + k) = make_double2(y0, y1);
+      double2* rec = reinterpret_cast<double2*>(A.brec) + 4 * (int64_t)hf + 2 * (j & 1);
+      rec[0] = make_double2(n0 - z0, y0);
+      rec[1] = make_double2(n1 - z1, y1);
+    } else {
+      const int64_t kp = (int64_t)G0 + (j - npe), kq = ng + kp;
+      A.v[kp] = n0;
+      A.z[kp] = z0;
+      A.y[kp] = y0;
+      A.v[kq] = n1;
+      A.z[kq] = z1;
+      A.y[kq] = y1;
+    }
   }
   // tile maxima (wavefront, then across the block's wavefronts), written to
   // the tile's own slot: no atomics, and the control kernel reduces a grid's
@@ -692,7 +753,9 @@ struct acopf_s {
   int *gptr, *eptr, *isref;
   std::vector<int> gptr_h, eptr_h;  // host copies, for the bus tiles
   TileDesc* tdesc = nullptr;         // [nb] bus tiles of the bus kernel
-  int n_tiles = 0, tile_block = 0, ecap = 0, gcap = 0, tbmax = 0;
+  int* hub_tile = nullptr;           // [nb] tiles with more pairs than lanes
+  int n_hub = 0;
+  int n_tiles = 0, tile_block = 0;
   double *pd, *qd, *gs, *bs;
   double *vmin_b, *vmax_b;  // [nb] voltage limits (solution quality)
   GridCtl* ctl;
@@ -780,18 +843,15 @@ double now_s() {
 }
 
 // Bus tiles for workgroups of `block` lanes: runs of consecutive buses of one
-// grid, at most block / 4 buses (four lanes per bus in the per-coupling
-// phases), whose branch ends and generators fit the LDS capacities (a single
-// bus beyond them gets a tile of its own and the kernel's global-memory
-// path). LDS per tile stays within 64 KiB.
+// grid, at most block / 2 buses, whose coupling pairs (two per branch end,
+// one per generator) fit the block's lanes. A single bus with more pairs
+// than lanes (a hub) gets a tile of its own, flagged for the hub launch, which
+// recomputes the pairs past the lanes from global memory. LDS per tile is
+// 50 bytes per lane (51,200 at 1,024 lanes).
 int build_tiles(acopf_s* h, int block) {
-  const int tb = std::max(1, block / 4);
-  const int budget = 65536 - 4 * 8 * tb;  // minus the per-bus results
-  const int gcap = std::max(16, tb);
-  int ecap = (budget - gcap * (16 + 2)) / (32 + 2);
-  ecap = std::max(1, std::min(ecap, 8 * tb));
+  const int tb = std::max(1, block / 2);
   std::vector<TileDesc> tiles;
-  std::vector<int> grid_tile;
+  std::vector<int> grid_tile, hubs;
   tiles.reserve(h->nb / 8 + h->G + 1);
   for (int g = 0; g < h->G; ++g) {
     const HostGrid& H = h->grids[g];
@@ -801,11 +861,15 @@ int build_tiles(acopf_s* h, int block) {
     while (b < bend) {
       int64_t c = b;
       while (c < bend && c - b < tb &&
-             h->eptr_h[c + 1] - h->eptr_h[b] <= ecap && h->gptr_h[c + 1] - h->gptr_h[b] <= gcap)
+             2 * (int64_t)(h->eptr_h[c + 1] - h->eptr_h[b]) +
+                     (int64_t)(h->gptr_h[c + 1] - h->gptr_h[b]) <= block)
         ++c;
       c = std::max(c, b + 1);
+      const int64_t pairs = 2 * (int64_t)(h->eptr_h[c] - h->eptr_h[b]) +
+                            (int64_t)(h->gptr_h[c] - h->gptr_h[b]);
+      if (pairs > block) hubs.push_back((int)tiles.size());
       tiles.push_back(TileDesc{(int)b, (int)c, h->eptr_h[b], h->eptr_h[c], h->gptr_h[b],
-                               h->gptr_h[c], g, 0});
+                               h->gptr_h[c], g, pairs > block ? 1 : 0});
       b = c;
     }
   }
@@ -814,12 +878,13 @@ int build_tiles(acopf_s* h, int block) {
                          hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipMemcpyAsync(h->grid_tile, grid_tile.data(), sizeof(int) * grid_tile.size(),
                          hipMemcpyHostToDevice, h->stream));
+  if (!hubs.empty())
+    HIP_TRY(hipMemcpyAsync(h->hub_tile, hubs.data(), sizeof(int) * hubs.size(),
+                           hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
+  h->n_hub = (int)hubs.size();
   h->n_tiles = (int)tiles.size();
   h->tile_block = block;
-  h->ecap = ecap;
-  h->gcap = gcap;
-  h->tbmax = tb;
   return ACOPF_OK;
 }
 
@@ -841,10 +906,14 @@ void launch_iteration(acopf_s* h, int slot) {
   mark(1);
   BusArgs bu{h->nb, h->ng, h->ne, h->tdesc, h->bus_grid, h->ctl, h->gptr, h->eptr,
              h->pd, h->qd, h->gs, h->bs, h->isref, h->u, h->lam, h->v, h->z, h->y,
-             h->P.rho_pq, h->P.rho_va, h->tmax, h->ecap, h->gcap, h->tbmax, h->erec, h->brec};
+             h->P.rho_pq, h->P.rho_va, h->tmax, h->erec, h->brec,
+             h->hub_tile};
   const int bb = h->tile_block;
-  hipLaunchKernelGGL(bus_kernel, dim3(h->n_tiles), dim3(bb),
-                     bus_lds_bytes(h->tbmax, h->ecap, h->gcap), s, bu);
+  hipLaunchKernelGGL(bus_kernel<false>, dim3(h->n_tiles), dim3(bb),
+                     bus_lds_bytes(h->tile_block), s, bu);
+  if (h->n_hub > 0)
+    hipLaunchKernelGGL(bus_kernel<true>, dim3(h->n_hub), dim3(bb),
+                       bus_lds_bytes(h->tile_block), s, bu);
   mark(2);
   CtlArgs ca{h->G, h->ctl, h->tmax, h->grid_tile, h->gen_off_d, h->end_off_d, h->ng, h->ne,
              h->z, h->lam, h->P.lambda_max, h->hist, h->P.eps_pri, h->P.eps_dual, h->P.eps_z,
@@ -1191,6 +1260,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   for (double** p : cp_d) HIP_TRY(D.alloc(p, m));
   HIP_TRY(D.alloc(&h->gptr, nb + 1));
   HIP_TRY(D.alloc(&h->tdesc, nb));
+  HIP_TRY(D.alloc(&h->hub_tile, nb));
   HIP_TRY(D.alloc(&h->eptr, nb + 1));
   HIP_TRY(D.alloc(&h->isref, nb));
   double** bus_d[] = {&h->pd, &h->qd, &h->gs, &h->bs, &h->vmin_b, &h->vmax_b};
