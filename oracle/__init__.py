@@ -91,7 +91,7 @@ class OracleParams:
     beta0: float = 1e4
     beta_gamma: float = 6.0
     beta_omega: float = 0.8
-    beta_max: float = 1e4
+    beta_max: float = 1e5
     lambda_max: float = 1e12
     eps_pri: float = 1e-4
     eps_dual: float = 1e-4

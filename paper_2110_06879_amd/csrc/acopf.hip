@@ -1001,7 +1001,7 @@ void acopf_default_params(acopf_params* p) {
   p->beta0 = 1e4;
   p->beta_gamma = 6.0;
   p->beta_omega = 0.8;
-  p->beta_max = 1e4;
+  p->beta_max = 1e5;
   p->lambda_max = 1e12;
   p->eps_pri = 1e-4;
   p->eps_dual = 1e-4;
