@@ -328,6 +328,11 @@ const char* acopf_last_error(void);
 int acopf_peak_hbm(int64_t bytes, int32_t iters, double* gbs);
 int acopf_peak_fp64(int32_t iters, double* tflops);
 
+/* Free and total device memory of device `device` in bytes (out2[0], out2[1])
+ * for sizing a serving budget by HBM footprint (the tracking service's
+ * admission). Errors: EINVAL (null output), EDEVICE. */
+int acopf_device_memory(int32_t device, int64_t* out2);
+
 
 #ifdef __cplusplus
 }

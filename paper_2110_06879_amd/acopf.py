@@ -37,7 +37,7 @@ EXPORTS = ("acopf_default_params", "acopf_create", "acopf_solve", "acopf_update_
            "acopf_run", "acopf_poll", "acopf_copy_grid", "acopf_snapshot",
            "acopf_set_tuning", "acopf_get_tuning", "acopf_autotune", "acopf_quality",
            "acopf_update_gen_bounds", "acopf_set_counting", "acopf_peak_hbm",
-           "acopf_peak_fp64", "acopf_quality_noalloc")
+           "acopf_peak_fp64", "acopf_quality_noalloc", "acopf_device_memory")
 QUALITY_NAMES = ("max_violation", "balance_p", "balance_q", "line_limit", "voltage_limit",
                  "angle_limit")
 
@@ -164,6 +164,7 @@ def load(path: str | None = None) -> C.CDLL:
     lib.acopf_last_error.restype = C.c_char_p
     lib.acopf_peak_hbm.argtypes = [i64, i32, dp]
     lib.acopf_peak_fp64.argtypes = [i32, dp]
+    lib.acopf_device_memory.argtypes = [i32, C.POINTER(C.c_int64)]
     for name in ("acopf_create", "acopf_solve", "acopf_update_loads", "acopf_get_state",
                  "acopf_set_state", "acopf_get_sizes", "acopf_get_timing",
                  "acopf_set_profiling", "acopf_start", "acopf_run", "acopf_poll",
@@ -171,7 +172,7 @@ def load(path: str | None = None) -> C.CDLL:
                  "acopf_get_tuning", "acopf_autotune", "acopf_quality",
                  "acopf_quality_noalloc",
                  "acopf_update_gen_bounds", "acopf_set_counting", "acopf_peak_hbm",
-                 "acopf_peak_fp64"):
+                 "acopf_peak_fp64", "acopf_device_memory"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -190,6 +191,16 @@ def peak_hbm(nbytes: int = 1 << 30, iters: int = 20) -> float:
     if rc != 0:
         raise AcopfError(f"acopf error {rc}: {lib.acopf_last_error().decode()}")
     return out.value
+
+
+def device_memory(device: int = 0) -> tuple[int, int]:
+    """(free, total) bytes of device memory (hipMemGetInfo)."""
+    lib = load()
+    out = (C.c_int64 * 2)()
+    rc = lib.acopf_device_memory(device, out)
+    if rc != 0:
+        raise AcopfError(f"acopf_device_memory: {lib.acopf_last_error().decode()}")
+    return int(out[0]), int(out[1])
 
 
 def peak_fp64(iters: int = 200000) -> float:

@@ -60,10 +60,11 @@ def batch(n_grids: int, tune_iters: int) -> dict:
             "speedup": tp / tb}
 
 
-def serve(duration: float, rate: float, with_70k: bool, baseline: bool) -> dict:
+def serve(duration: float, rate: float, with_70k: bool, baseline: bool,
+          chunk: int | None = None) -> dict:
     grids = serving_grids(with_70k=with_70k)
     reqs = S.poisson_requests(grids, rate, duration)
-    srv = S.TrackingServer(grids)
+    srv = S.TrackingServer(grids, chunk=chunk)
     tuning = srv.solver.tuning()
     out = srv.serve(reqs, realtime=True)
     slots = srv.slots_per_grid
@@ -112,6 +113,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--no-70k", action="store_true")
     ap.add_argument("--no-baseline", action="store_true")
+    ap.add_argument("--chunk", type=int, default=None,
+                    help="serving: iterations between admissions (default: the tuned chunk)")
     ap.add_argument("--track", action="store_true")
     ap.add_argument("--periods", type=int, default=30)
     args = ap.parse_args()
@@ -119,7 +122,7 @@ def main():
         print(json.dumps(batch(args.grids, args.tune_iters)), flush=True)
     if args.serve:
         print(json.dumps(serve(args.duration, args.rate, not args.no_70k,
-                               not args.no_baseline)), flush=True)
+                               not args.no_baseline, args.chunk)), flush=True)
     if args.track:
         print(json.dumps(track(["c2_2kbus", "c3_70kbus"], args.periods)), flush=True)
 

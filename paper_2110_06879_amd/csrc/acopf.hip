@@ -90,12 +90,14 @@ static __device__ __align__(256) double scratch[kNoAllocWords];
 // One bus tile: buses [b0, b1) of grid `grid`, their branch ends [e0, e1)
 // and generators [g0, g1) in the device orders.
 struct TileDesc {
-  int b0, b1, e0, e1, g0, g1, grid, hub;  // hub: more pairs than lanes
+  int b0, b1, e0, e1, g0, g1, grid, id;  // id: tile index (tmax slot), -1: none
 };
 
 struct BusArgs {
   int64_t nb, ng, ne;
-  const TileDesc* tdesc;  // [n_tiles]; a tile never spans two grids
+  const TileDesc* tile_list;  // tiles of the launch (of running grids); a tile
+                              // never spans two grids
+  const TileDesc* hub_list;   // tiles of the hub launch
   const int* bus_grid;
   GridCtl* ctl;
   const int *gptr, *eptr;
@@ -108,7 +110,6 @@ struct BusArgs {
   double* tmax;              // [n_tiles][3] residual maxima of each tile
   const int* erec;           // [ne] record half of each end: 2 l + (0 from, 1 to)
   double* brec;              // [nl][16] branch records for the next x-step
-  const int* hub_tile;       // [n_hub] tiles of the hub launch
 };
 
 // Half of a branch record (64 bytes): the pairs (v_k - z_k, y_k) of one
@@ -222,10 +223,10 @@ __device__ inline void bus_solve(int tid, int be0, int be1, int bg0, int bg1, in
 template <bool kHub>
 __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
   extern __shared__ double sm[];
-  const int t = kHub ? A.hub_tile[blockIdx.x] : (int)blockIdx.x;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const TileDesc D = A.tdesc[t];
-  if (!kHub && D.hub) return;  // a tile of its own launch
+  const TileDesc D = (kHub ? A.hub_list : A.tile_list)[blockIdx.x];
+  const int t = D.id;
+  if (t < 0) return;  // the placeholder of an empty list
   const int b0 = D.b0, nbt = D.b1 - D.b0, grid = D.grid;
   const int tb = nt >> 1, ncap = nt;  // buses and pairs held in LDS
   double* cT = sm;                 // [2 nt] targets
@@ -427,6 +428,7 @@ __global__ __launch_bounds__(256) void record_kernel(int64_t ng, int64_t e0, int
 
 struct CtlArgs {
   int G;
+  const int* glist;      // grids of the launch (the running ones)
   GridCtl* ctl;
   const double* tmax;     // [n_tiles][3] residual maxima per bus tile
   const int* grid_tile;   // [G + 1] tiles of each grid
@@ -500,7 +502,7 @@ __device__ int ctl_decide(const CtlArgs& A, int g, GridCtl& c, double rp, double
 // couplings by the same block, so no launch is spent on it otherwise.
 constexpr int kCtlBlock = 1024;
 __global__ __launch_bounds__(kCtlBlock) void ctl_kernel(CtlArgs A) {
-  const int g = blockIdx.x;
+  const int g = A.glist[blockIdx.x];
   const int tid = threadIdx.x;
   GridCtl& c = A.ctl[g];
   // The tile maxima and lane 0's copy of the control record are loaded
@@ -666,6 +668,41 @@ __global__ void ctl_idle_kernel(GridCtl* ctl, int G) {
   }
 }
 
+// Device-side copy of up to kCopySegs ranges of doubles and one control
+// block in one launch: a grid's state into another instance of the same grid.
+// Block row y copies range y; the control block arrives marked idle.
+constexpr int kCopySegs = 40;
+struct CopySegs {
+  int n;
+  const double* src[kCopySegs];
+  double* dst[kCopySegs];
+  int64_t len[kCopySegs];
+  const GridCtl* csrc;
+  GridCtl* cdst;
+};
+__global__ __launch_bounds__(256) void copy_kernel(CopySegs C) {
+  const int s = blockIdx.y;
+  const double* src = C.src[0];
+  double* dst = C.dst[0];
+  int64_t n = C.len[0];
+#pragma unroll
+  for (int q = 1; q < kCopySegs; ++q)  // selects, so the argument is not indexed
+    if (q == s) {
+      src = C.src[q];
+      dst = C.dst[q];
+      n = C.len[q];
+    }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+  if (s == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+    GridCtl c = *C.csrc;
+    c.done = 1;
+    c.do_outer = 0;
+    *C.cdst = c;
+  }
+}
+
 // Objective sum_g c2 P^2 + c1 P + c0 with P = base p_g (Sec. IV-A), one block
 // per grid, fixed-order tree reduction.
 __global__ __launch_bounds__(256) void objective_kernel(const int64_t* gen_off,
@@ -752,9 +789,26 @@ struct acopf_s {
   int* erec = nullptr;     // [ne] record half of each branch end
   int *gptr, *eptr, *isref;
   std::vector<int> gptr_h, eptr_h;  // host copies, for the bus tiles
-  TileDesc* tdesc = nullptr;         // [nb] bus tiles of the bus kernel
-  int* hub_tile = nullptr;           // [nb] tiles with more pairs than lanes
-  int n_hub = 0;
+  std::vector<TileDesc> tiles_h;     // every bus tile of the handle
+  std::vector<char> tile_hub;        // tile with more pairs than lanes
+  int n_hub = 0;                     // hub tiles of the handle
+  // Work lists of the grids that run: x-step items, bus tiles, hub tiles and
+  // grids, in one device block filled from a pinned host copy.
+  char* lists = nullptr;
+  char* stage = nullptr;
+  size_t off_t = 0, off_h = 0, off_g = 0;
+  int64_t xcap = 0;
+  int n_x = 0, n_t = 0, n_hl = 0, n_gl = 0;
+  acopf_dev::XPlan xplan{};          // the x-step's blocks (kernel argument)
+  BranchArgs xba{};                  // the x-step's other argument, as captured
+  std::vector<char> active_for;      // the running set the lists describe
+  bool lists_dirty = true;
+  // kernel nodes of the captured chunk, with the list each one's grid size
+  // follows (0 x-step, 1 bus tiles, 2 hub tiles, 3 grids, -1 fixed)
+  hipGraph_t gtmpl = nullptr;
+  std::vector<hipGraphNode_t> gnode;
+  std::vector<int> grole;
+  std::vector<hipKernelNodeParams> gparam;
   int n_tiles = 0, tile_block = 0;
   double *pd, *qd, *gs, *bs;
   double *vmin_b, *vmax_b;  // [nb] voltage limits (solution quality)
@@ -869,22 +923,21 @@ int build_tiles(acopf_s* h, int block) {
                             (int64_t)(h->gptr_h[c] - h->gptr_h[b]);
       if (pairs > block) hubs.push_back((int)tiles.size());
       tiles.push_back(TileDesc{(int)b, (int)c, h->eptr_h[b], h->eptr_h[c], h->gptr_h[b],
-                               h->gptr_h[c], g, pairs > block ? 1 : 0});
+                               h->gptr_h[c], g, (int)tiles.size()});
       b = c;
     }
   }
   grid_tile.push_back((int)tiles.size());
-  HIP_TRY(hipMemcpyAsync(h->tdesc, tiles.data(), sizeof(TileDesc) * tiles.size(),
-                         hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipMemcpyAsync(h->grid_tile, grid_tile.data(), sizeof(int) * grid_tile.size(),
                          hipMemcpyHostToDevice, h->stream));
-  if (!hubs.empty())
-    HIP_TRY(hipMemcpyAsync(h->hub_tile, hubs.data(), sizeof(int) * hubs.size(),
-                           hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
+  h->tile_hub.assign(tiles.size(), 0);
+  for (int t : hubs) h->tile_hub[t] = 1;
+  h->tiles_h = std::move(tiles);
   h->n_hub = (int)hubs.size();
-  h->n_tiles = (int)tiles.size();
+  h->n_tiles = (int)h->tiles_h.size();
   h->tile_block = block;
+  h->lists_dirty = true;
   return ACOPF_OK;
 }
 
@@ -901,25 +954,24 @@ void launch_iteration(acopf_s* h, int slot) {
     acopf_dev::launch_xstep_persistent(ba, h->n6, h->tune.xstep_waves * 4 * h->n_cu,
                                        h->count_stats, s);
   else
-    acopf_dev::launch_xstep(ba, h->n6, h->tune.xstep_block, h->tune.xstep_per_lane,
-                            4 * h->n_cu, h->count_stats, s);
+    acopf_dev::launch_xstep(ba, h->xplan, h->n_x, h->tune.xstep_block, h->count_stats, s);
   mark(1);
-  BusArgs bu{h->nb, h->ng, h->ne, h->tdesc, h->bus_grid, h->ctl, h->gptr, h->eptr,
-             h->pd, h->qd, h->gs, h->bs, h->isref, h->u, h->lam, h->v, h->z, h->y,
-             h->P.rho_pq, h->P.rho_va, h->tmax, h->erec, h->brec,
-             h->hub_tile};
+  BusArgs bu{h->nb, h->ng, h->ne, reinterpret_cast<const TileDesc*>(h->lists + h->off_t),
+             reinterpret_cast<const TileDesc*>(h->lists + h->off_h), h->bus_grid, h->ctl,
+             h->gptr, h->eptr, h->pd, h->qd, h->gs, h->bs, h->isref, h->u, h->lam, h->v, h->z,
+             h->y, h->P.rho_pq, h->P.rho_va, h->tmax, h->erec, h->brec};
   const int bb = h->tile_block;
-  hipLaunchKernelGGL(bus_kernel<false>, dim3(h->n_tiles), dim3(bb),
-                     bus_lds_bytes(h->tile_block), s, bu);
+  hipLaunchKernelGGL(bus_kernel<false>, dim3(h->n_t), dim3(bb), bus_lds_bytes(h->tile_block), s,
+                     bu);
   if (h->n_hub > 0)
-    hipLaunchKernelGGL(bus_kernel<true>, dim3(h->n_hub), dim3(bb),
-                       bus_lds_bytes(h->tile_block), s, bu);
+    hipLaunchKernelGGL(bus_kernel<true>, dim3(h->n_hl), dim3(bb), bus_lds_bytes(h->tile_block),
+                       s, bu);
   mark(2);
-  CtlArgs ca{h->G, h->ctl, h->tmax, h->grid_tile, h->gen_off_d, h->end_off_d, h->ng, h->ne,
+  CtlArgs ca{h->G, reinterpret_cast<const int*>(h->lists + h->off_g), h->ctl, h->tmax, h->grid_tile, h->gen_off_d, h->end_off_d, h->ng, h->ne,
              h->z, h->lam, h->P.lambda_max, h->hist, h->P.eps_pri, h->P.eps_dual, h->P.eps_z,
              h->P.beta_gamma, h->P.beta_omega, h->P.beta_max, h->P.max_outer,
              h->P.max_inner};
-  hipLaunchKernelGGL(ctl_kernel, dim3(h->G), dim3(kCtlBlock), 0, s, ca);
+  hipLaunchKernelGGL(ctl_kernel, dim3(h->n_gl), dim3(kCtlBlock), 0, s, ca);
   mark(3);
 }
 
@@ -1027,11 +1079,13 @@ void acopf_destroy(acopf_handle h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  if (h->gtmpl) (void)hipGraphDestroy(h->gtmpl);
   for (void* p : h->snap) (void)hipFree(p);
   if (h->qscratch) (void)hipFree(h->qscratch);
   if (h->qual) (void)hipFree(h->qual);
   h->buf.release();
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
+  if (h->stage) (void)hipHostFree(h->stage);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
 }
@@ -1259,8 +1313,19 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   double** cp_d[] = {&h->u, &h->v, &h->z, &h->y, &h->lam};
   for (double** p : cp_d) HIP_TRY(D.alloc(p, m));
   HIP_TRY(D.alloc(&h->gptr, nb + 1));
-  HIP_TRY(D.alloc(&h->tdesc, nb));
-  HIP_TRY(D.alloc(&h->hub_tile, nb));
+  {
+    // work lists: x-step items (a block of at least 64 lanes per item, plus
+    // a partial item per class and grid), bus and hub tiles (at most one tile
+    // per bus, plus a placeholder), grids
+    auto up16 = [](size_t b) { return (b + 15) & ~size_t(15); };
+    h->xcap = (ng + nl) / 64 + 3 * (int64_t)n_grids + 8;
+    h->off_t = up16(sizeof(acopf_dev::XWork) * (size_t)h->xcap);
+    h->off_h = h->off_t + up16(sizeof(TileDesc) * (size_t)(nb + 1));
+    h->off_g = h->off_h + up16(sizeof(TileDesc) * (size_t)(nb + 1));
+    const size_t bytes = h->off_g + up16(sizeof(int) * (size_t)n_grids);
+    HIP_TRY(D.alloc(&h->lists, bytes));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->stage), bytes, hipHostMallocDefault));
+  }
   HIP_TRY(D.alloc(&h->eptr, nb + 1));
   HIP_TRY(D.alloc(&h->isref, nb));
   double** bus_d[] = {&h->pd, &h->qd, &h->gs, &h->bs, &h->vmin_b, &h->vmax_b};
@@ -1417,18 +1482,158 @@ static void accumulate_timing(acopf_s* h, int used) {
 
 static void drop_graph(acopf_s* h) {
   if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  if (h->gtmpl) (void)hipGraphDestroy(h->gtmpl);
   h->graph = nullptr;
+  h->gtmpl = nullptr;
   h->graph_chunk = 0;
+  h->gnode.clear();
+  h->grole.clear();
+  h->gparam.clear();
+}
+
+// Grid size of a captured kernel node of the given role under the current
+// work lists.
+static unsigned role_blocks(const acopf_s* h, int role) {
+  switch (role) {
+    case 0: return (unsigned)h->n_x;
+    case 1: return (unsigned)h->n_t;
+    case 2: return (unsigned)h->n_hl;
+    default: return (unsigned)h->n_gl;
+  }
+}
+
+// Work lists of the grids that are running (of all grids when none is: the
+// shape a chunk is captured with): x-step items over the generator, rated
+// and unlimited ranges of those grids (adjacent ranges merged, so that with
+// every grid running the items are those of one contiguous range per class),
+// their bus tiles and hub tiles, and the grids themselves. The kernel nodes of
+// a captured chunk take the new grid sizes in place; their arguments point to
+// the lists and do not change.
+static int build_active(acopf_s* h) {
+  std::vector<char> act = h->running;
+  if (std::find(act.begin(), act.end(), 1) == act.end()) std::fill(act.begin(), act.end(), 1);
+  if (!h->lists_dirty && act == h->active_for) return ACOPF_OK;
+  HIP_TRY(hipStreamSynchronize(h->stream));  // the last copy from `stage` has landed
+  using acopf_dev::XWork;
+  XWork* xw = reinterpret_cast<XWork*>(h->stage);
+  int nx = 0;
+  auto ranges = [&](auto lo, auto hi) {
+    std::vector<std::pair<int64_t, int64_t>> r;
+    for (int g = 0; g < h->G; ++g) {
+      if (!act[g]) continue;
+      const int64_t a = lo(g), b = hi(g);
+      if (b <= a) continue;
+      if (!r.empty() && r.back().second == a) r.back().second = b;
+      else r.emplace_back(a, b);
+    }
+    return r;
+  };
+  const auto rg = ranges([&](int g) { return h->grids[g].gen_off; },
+                         [&](int g) { return h->grids[g].gen_off + h->grids[g].ng; });
+  const auto r6 = ranges([&](int g) { return h->grids[g].r6b; }, [&](int g) { return h->grids[g].r6e; });
+  const auto r4 = ranges([&](int g) { return h->grids[g].r4b; }, [&](int g) { return h->grids[g].r4e; });
+  const int bs = h->tune.xstep_block;
+  for (const auto& r : rg)
+    for (int64_t x = r.first; x < r.second; x += bs)
+      xw[nx++] = XWork{(int)x, (int)r.second, 0, (short)acopf_dev::kXGen, 1};
+  int64_t waves6 = 0, n4 = 0;
+  for (const auto& r : r6)
+    for (int64_t x = r.first; x < r.second; x += bs) {
+      xw[nx++] = XWork{(int)x, (int)r.second, 0, (short)acopf_dev::kXRated, 1};
+      waves6 += (bs + 63) / 64;
+    }
+  for (const auto& r : r4) n4 += r.second - r.first;
+  // unlimited branches per lane: as many as it takes for every branch
+  // wavefront to be resident at once (one per SIMD slot), unless tuned
+  const int64_t slots = 4 * (int64_t)h->n_cu;
+  int k4 = h->tune.xstep_per_lane;
+  if (k4 <= 0) {
+    const int64_t free_lanes = (slots - waves6) * 64;
+    k4 = 1;
+    if (free_lanes >= slots * 8)
+      k4 = (int)std::min<int64_t>(8, std::max<int64_t>(1, (n4 + free_lanes - 1) / free_lanes));
+  }
+  for (const auto& r : r4) {
+    const int64_t nb4 = (r.second - r.first + (int64_t)bs * k4 - 1) / ((int64_t)bs * k4);
+    for (int64_t i = 0; i < nb4; ++i)
+      xw[nx++] = XWork{(int)(r.first + i * bs), (int)r.second, (int)(nb4 * bs),
+                       (short)acopf_dev::kXUnlimited, (short)k4};
+  }
+  if (nx > h->xcap) return fail(ACOPF_EDEVICE, "x-step work list overflow");
+  // segments: runs of items whose ranges start one block apart
+  acopf_dev::XPlan& P = h->xplan;
+  P = acopf_dev::XPlan{};
+  P.list = reinterpret_cast<const XWork*>(h->lists);
+  for (int i = 0; i < nx; ++i) {
+    const XWork& w = xw[i];
+    const int s = P.n_seg - 1;
+    if (s >= 0 && w.end == P.end[s] && w.stride == P.stride[s] && w.kind == P.kind[s] &&
+        w.per_lane == P.per_lane[s] && w.begin == P.begin[s] + (i - P.first[s]) * bs)
+      continue;
+    if (P.n_seg == acopf_dev::kXSegs) {  // too many: the kernel reads the list
+      P.n_seg = 0;
+      break;
+    }
+    P.first[P.n_seg] = i;
+    P.begin[P.n_seg] = w.begin;
+    P.end[P.n_seg] = w.end;
+    P.stride[P.n_seg] = w.stride;
+    P.kind[P.n_seg] = w.kind;
+    P.per_lane[P.n_seg] = w.per_lane;
+    ++P.n_seg;
+  }
+  TileDesc* tl = reinterpret_cast<TileDesc*>(h->stage + h->off_t);
+  TileDesc* hl = reinterpret_cast<TileDesc*>(h->stage + h->off_h);
+  int* gl = reinterpret_cast<int*>(h->stage + h->off_g);
+  int nt = 0, nh = 0, ngl = 0;
+  std::vector<int> grid_tile_h;
+  for (int g = 0; g < h->G; ++g) {
+    if (!act[g]) continue;
+    gl[ngl++] = g;
+  }
+  for (int t = 0; t < h->n_tiles; ++t) {
+    const TileDesc& D = h->tiles_h[t];
+    if (!act[D.grid]) continue;
+    if (h->tile_hub[t]) hl[nh++] = D;
+    else tl[nt++] = D;
+  }
+  const TileDesc none{0, 0, 0, 0, 0, 0, 0, -1};
+  if (nt == 0) tl[nt++] = none;  // a launch needs one block; it returns at once
+  if (nh == 0) hl[nh++] = none;
+  hipStream_t st = h->stream;
+  HIP_TRY(hipMemcpyAsync(h->lists, h->stage, sizeof(XWork) * nx, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(h->lists + h->off_t, tl, sizeof(TileDesc) * nt, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(h->lists + h->off_h, hl, sizeof(TileDesc) * nh, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(h->lists + h->off_g, gl, sizeof(int) * ngl, hipMemcpyHostToDevice, st));
+  h->n_x = nx;
+  h->n_t = nt;
+  h->n_hl = nh;
+  h->n_gl = ngl;
+  h->active_for = act;
+  h->lists_dirty = false;
+  h->xba = branch_args(h);
+  void* xargs[2] = {&h->xba, &h->xplan};
+  for (size_t i = 0; h->graph && i < h->gnode.size(); ++i) {
+    if (h->grole[i] < 0) continue;
+    hipKernelNodeParams p = h->gparam[i];
+    p.gridDim = dim3(role_blocks(h, h->grole[i]));
+    if (h->grole[i] == 0) p.kernelParams = xargs;
+    HIP_TRY(hipGraphExecKernelNodeSetParams(h->graph, h->gnode[i], &p));
+  }
+  return ACOPF_OK;
 }
 
 // Captures one chunk of the tuned length as a hipGraph (without per-launch
 // timing events) if graphs are on and none is held. Called when the launch
 // shape or the kernel variant changes, so that capture and instantiation
-// happen outside the solves that replay the graph.
+// happen outside the solves that replay the graph. Its kernel nodes are kept
+// so that build_active can resize them to the running grids.
 static int ensure_graph(acopf_s* h) {
   const int k = h->tune.chunk;
   if (!h->tune.use_graph || (h->graph && h->graph_chunk == k)) return ACOPF_OK;
   drop_graph(h);
+  int rc = build_active(h);
+  if (rc) return rc;
   const bool prof = h->profile;
   h->profile = false;
   hipGraph_t g = nullptr;
@@ -1439,12 +1644,34 @@ static int ensure_graph(acopf_s* h) {
   }
   h->profile = prof;
   if (e != hipSuccess) return fail(ACOPF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-  e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (e != hipSuccess) {
-    h->graph = nullptr;
-    return fail(ACOPF_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  size_t n = 0;
+  e = hipGraphGetNodes(g, nullptr, &n);
+  std::vector<hipGraphNode_t> nodes(n);
+  if (e == hipSuccess && n) e = hipGraphGetNodes(g, nodes.data(), &n);
+  for (size_t i = 0; e == hipSuccess && i < n; ++i) {
+    hipGraphNodeType ty;
+    e = hipGraphNodeGetType(nodes[i], &ty);
+    if (e != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
+    hipKernelNodeParams p;
+    e = hipGraphKernelNodeGetParams(nodes[i], &p);
+    if (e != hipSuccess) break;
+    int role = -1;
+    if (acopf_dev::is_xstep_kernel(p.func)) role = 0;
+    else if (p.func == reinterpret_cast<void*>(&bus_kernel<false>)) role = 1;
+    else if (p.func == reinterpret_cast<void*>(&bus_kernel<true>)) role = 2;
+    else if (p.func == reinterpret_cast<void*>(&ctl_kernel)) role = 3;
+    h->gnode.push_back(nodes[i]);
+    h->grole.push_back(role);
+    h->gparam.push_back(p);
   }
+  if (e == hipSuccess) e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    h->graph = nullptr;
+    drop_graph(h);
+    return fail(ACOPF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  h->gtmpl = g;
   h->graph_chunk = k;
   return ACOPF_OK;
 }
@@ -1500,7 +1727,9 @@ static int run_impl(acopf_s* h, int64_t max_iters, bool stop_on_first, int64_t* 
     for (int g = 0; g < h->G; ++g) nrun += h->running[g];
     if (nrun == 0) break;
     const int k = (int)std::min<int64_t>(h->tune.chunk, max_iters - issued);
-    int rc = launch_chunk(h, k);
+    int rc = build_active(h);
+    if (rc) return rc;
+    rc = launch_chunk(h, k);
     if (rc) return rc;
     issued += k;
     HIP_TRY(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(GridCtl) * h->G, hipMemcpyDeviceToHost,
@@ -1951,35 +2180,42 @@ int acopf_copy_grid(acopf_handle h, int32_t src, int32_t dst) {
     return fail(ACOPF_EINVAL, "grids differ in size");
   if (h->running[dst]) return fail(ACOPF_ESTATE, "destination grid is running");
   HIP_TRY(hipSetDevice(h->device));
-  hipStream_t st = h->stream;
+  CopySegs C{};
+  int64_t longest = 0;
   auto cp = [&](double* base, int64_t from, int64_t to, int64_t n) {
-    if (n <= 0) return hipSuccess;
-    return hipMemcpyAsync(base + to, base + from, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+    if (n <= 0) return;
+    C.src[C.n] = base + from;
+    C.dst[C.n] = base + to;
+    C.len[C.n] = n;
+    longest = std::max(longest, n);
+    ++C.n;
   };
-  const int64_t ng = h->ng, ne = h->ne, nl = h->nl;
+  const int64_t ng = h->ng, nl = h->nl;
   double* vecs[] = {h->u, h->v, h->z, h->y, h->lam};
   for (double* v : vecs) {
-    HIP_TRY(cp(v, A.gen_off, B.gen_off, A.ng));
-    HIP_TRY(cp(v, ng + A.gen_off, ng + B.gen_off, A.ng));
-    HIP_TRY(cp(v, 2 * ng + 4 * A.e0, 2 * ng + 4 * B.e0, 4 * (A.e1 - A.e0)));
+    cp(v, A.gen_off, B.gen_off, A.ng);
+    cp(v, ng + A.gen_off, ng + B.gen_off, A.ng);
+    cp(v, 2 * ng + 4 * A.e0, 2 * ng + 4 * B.e0, 4 * (A.e1 - A.e0));
   }
   for (int r = 0; r < 6; ++r) {
-    HIP_TRY(cp(h->bx, r * nl + A.r6b, r * nl + B.r6b, A.r6e - A.r6b));
-    HIP_TRY(cp(h->bx, r * nl + A.r4b, r * nl + B.r4b, A.r4e - A.r4b));
+    cp(h->bx, r * nl + A.r6b, r * nl + B.r6b, A.r6e - A.r6b);
+    cp(h->bx, r * nl + A.r4b, r * nl + B.r4b, A.r4e - A.r4b);
   }
   for (int r = 0; r < 2; ++r) {
-    HIP_TRY(cp(h->ltil, r * nl + A.r6b, r * nl + B.r6b, A.r6e - A.r6b));
-    HIP_TRY(cp(h->ltil, r * nl + A.r4b, r * nl + B.r4b, A.r4e - A.r4b));
+    cp(h->ltil, r * nl + A.r6b, r * nl + B.r6b, A.r6e - A.r6b);
+    cp(h->ltil, r * nl + A.r4b, r * nl + B.r4b, A.r4e - A.r4b);
   }
-  HIP_TRY(cp(h->rtil, A.r6b, B.r6b, A.r6e - A.r6b));
-  HIP_TRY(cp(h->rtil, A.r4b, B.r4b, A.r4e - A.r4b));
-  HIP_TRY(cp(h->calpha, A.r6b, B.r6b, A.r6e - A.r6b));
-  HIP_TRY(cp(h->calpha, A.r4b, B.r4b, A.r4e - A.r4b));
-  HIP_TRY(cp(h->pd, A.bus_off, B.bus_off, A.nb));
-  HIP_TRY(cp(h->qd, A.bus_off, B.bus_off, A.nb));
-  HIP_TRY(hipMemcpyAsync(h->ctl + dst, h->ctl + src, sizeof(GridCtl), hipMemcpyDeviceToDevice, st));
-  hipLaunchKernelGGL(ctl_idle_kernel, dim3(1), dim3(64), 0, st, h->ctl + dst, 1);
-  HIP_TRY(hipStreamSynchronize(st));
+  cp(h->rtil, A.r6b, B.r6b, A.r6e - A.r6b);
+  cp(h->rtil, A.r4b, B.r4b, A.r4e - A.r4b);
+  cp(h->calpha, A.r6b, B.r6b, A.r6e - A.r6b);
+  cp(h->calpha, A.r4b, B.r4b, A.r4e - A.r4b);
+  cp(h->pd, A.bus_off, B.bus_off, A.nb);
+  cp(h->qd, A.bus_off, B.bus_off, A.nb);
+  C.csrc = h->ctl + src;
+  C.cdst = h->ctl + dst;
+  const int bx = (int)std::min<int64_t>(256, std::max<int64_t>(1, (longest + 255) / 256));
+  hipLaunchKernelGGL(copy_kernel, dim3(bx, std::max(1, C.n)), dim3(256), 0, h->stream, C);
+  HIP_TRY(hipGetLastError());
   h->started_once[dst] = h->started_once[src] || h->solved;
   return ACOPF_OK;
 }
@@ -2004,6 +2240,7 @@ static int apply_tuning(acopf_s* h, const acopf_tuning& t) {
     if (rc) return rc;
   }
   h->tune = t;
+  h->lists_dirty = true;  // x-step items depend on the block and per-lane count
   return ACOPF_OK;
 }
 
@@ -2250,6 +2487,16 @@ int acopf_peak_hbm(int64_t bytes, int32_t iters, double* gbs) {
   HIP_TRY(hipEventElapsedTime(&ms, P.e0, P.e1));
   if (!(ms > 0.0f)) return fail(ACOPF_EDEVICE, "peak_hbm: no elapsed time");
   *gbs = 2.0 * 16.0 * (double)n2 * iters / (ms * 1e-3) / 1e9;
+  return ACOPF_OK;
+}
+
+int acopf_device_memory(int32_t device, int64_t* out2) {
+  if (!out2) return fail(ACOPF_EINVAL, "device_memory: null output");
+  HIP_TRY(hipSetDevice(device));
+  size_t fr = 0, tot = 0;
+  HIP_TRY(hipMemGetInfo(&fr, &tot));
+  out2[0] = (int64_t)fr;
+  out2[1] = (int64_t)tot;
   return ACOPF_OK;
 }
 

@@ -1390,35 +1390,53 @@ void launch_xstep_persistent(const BranchArgs& A, int64_t n6, int blocks, bool s
 #define ACOPF_XSTEP_WAVES_PER_EU 1
 #endif
 
-// Lane-per-branch x-step. Blocks [0, bg) take the generators (short, so
-// their SIMD slots free up at once), blocks [bg, bg + b6) one rated branch per
-// lane, and the remaining b4 blocks k4 unlimited branches per lane, one after
-// the other (branch base + j * b4 * blockDim for j < k4). With k4 chosen so
-// that every branch wavefront is resident from the start, the cheap unlimited
-// branches finish inside the span of the expensive rated ones instead of
-// waiting for a second round of SIMD slots. kStats: as for the persistent
-// kernel.
+// Lane-per-branch x-step over the work items of a plan, one per block (built
+// by the host for the grids that are running): generator items (one generator
+// per lane) come first, so their short blocks free their SIMD slots at once,
+// then rated items (one rated branch per lane), then unlimited items, whose
+// lanes solve per_lane branches one after the other (begin + lane + j stride
+// for j < per_lane while below end; stride interleaves the blocks of one
+// range). With per_lane chosen so that every branch wavefront is resident
+// from the start, the cheap unlimited branches finish inside the span of the
+// expensive rated ones instead of waiting for a second round of SIMD slots.
+// kStats: as for the persistent kernel.
 template <bool kStats>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ACOPF_XSTEP_WAVES_PER_EU)))
-void xstep_kernel(BranchArgs A, int64_t n6, int bg, int b6, int b4, int k4) {
+void xstep_kernel(BranchArgs A, XPlan P) {
   CountersT<kStats> cnt = {};
   uint32_t solves = 0;
   const int b = blockIdx.x;
-  const int bs = blockDim.x;
-  if (b < bg) {
-    const int64_t g = (int64_t)b * bs + threadIdx.x;
-    if (g < A.ng && A.ctl[A.gen_grid[g]].done == 0) solve_generator(A, g);
+  XWork W;
+  if (P.n_seg > 0) {
+    // the segment of this block, by selects over the argument values (no
+    // indexed access, so the plan stays in scalar registers)
+    int s = 0;
+#pragma unroll
+    for (int q = 1; q < kXSegs; ++q)
+      if (q < P.n_seg && b >= P.first[q]) s = q;
+    W = XWork{P.begin[0], P.end[0], P.stride[0], P.kind[0], P.per_lane[0]};
+    int f = P.first[0];
+#pragma unroll
+    for (int q = 1; q < kXSegs; ++q)
+      if (s == q) {
+        W = XWork{P.begin[q], P.end[q], P.stride[q], P.kind[q], P.per_lane[q]};
+        f = P.first[q];
+      }
+    W.begin += (b - f) * (int)blockDim.x;
+  } else {
+    W = P.list[b];
+  }
+  const int64_t first = (int64_t)W.begin + threadIdx.x;
+  if (W.kind == kXGen) {
+    if (first < W.end && A.ctl[A.gen_grid[first]].done == 0) solve_generator(A, first);
     return;  // whole block is generators: no branch counters
   }
-  if (b < bg + b6) {
-    const int64_t l = (int64_t)(b - bg) * bs + threadIdx.x;
-    if (l < n6 && solve_branch<6>(A, l, cnt)) ++solves;
+  if (W.kind == kXRated) {
+    if (first < W.end && solve_branch<6>(A, first, cnt)) ++solves;
   } else {
-    const int64_t base = n6 + (int64_t)(b - bg - b6) * bs + threadIdx.x;
-    const int64_t stride = (int64_t)b4 * bs;
-    for (int j = 0; j < k4; ++j) {
-      const int64_t l = base + j * stride;
-      if (l >= A.nl) break;
+    for (int j = 0; j < W.per_lane; ++j) {
+      const int64_t l = first + (int64_t)j * W.stride;
+      if (l >= W.end) break;
       if (solve_branch<4>(A, l, cnt)) ++solves;
     }
   }
@@ -1440,29 +1458,18 @@ void xstep_kernel(BranchArgs A, int64_t n6, int bg, int b6, int b4, int k4) {
   }
 }
 
-void launch_xstep(const BranchArgs& A, int64_t n6, int block, int per_lane, int slots,
-                  bool stats, hipStream_t s) {
-  const int64_t n4 = A.nl - n6;
-  const int bg = (int)((A.ng + block - 1) / block);
-  const int b6 = (int)((n6 + block - 1) / block);
-  int k4 = per_lane;
-  if (k4 <= 0) {
-    // automatic: as many unlimited branches per lane as it takes for every
-    // branch wavefront to be resident at once (one per SIMD slot)
-    const int64_t waves6 = (int64_t)b6 * ((block + 63) / 64);
-    const int64_t free_lanes = ((int64_t)slots - waves6) * 64;
-    k4 = 1;
-    if (free_lanes >= (int64_t)slots * 8)
-      k4 = (int)std::min<int64_t>(8, std::max<int64_t>(1, (n4 + free_lanes - 1) / free_lanes));
-  }
-  const int b4 = (int)((n4 + (int64_t)block * k4 - 1) / ((int64_t)block * k4));
-  if (bg + b6 + b4 == 0) return;
+void launch_xstep(const BranchArgs& A, const XPlan& P, int n_blocks, int block, bool stats,
+                  hipStream_t s) {
+  if (n_blocks <= 0) return;
   if (stats)
-    hipLaunchKernelGGL(xstep_kernel<true>, dim3(bg + b6 + b4), dim3(block), 0, s, A, n6, bg, b6,
-                       b4, k4);
+    hipLaunchKernelGGL(xstep_kernel<true>, dim3(n_blocks), dim3(block), 0, s, A, P);
   else
-    hipLaunchKernelGGL(xstep_kernel<false>, dim3(bg + b6 + b4), dim3(block), 0, s, A, n6, bg, b6,
-                       b4, k4);
+    hipLaunchKernelGGL(xstep_kernel<false>, dim3(n_blocks), dim3(block), 0, s, A, P);
+}
+
+bool is_xstep_kernel(const void* f) {
+  return f == reinterpret_cast<const void*>(&xstep_kernel<false>) ||
+         f == reinterpret_cast<const void*>(&xstep_kernel<true>);
 }
 
 // ---------------------------------------------------------------------------

@@ -72,11 +72,34 @@ void launch_quality(const QualityArgs& Q, hipStream_t s);
 // Zeroes n 64-bit words with one block (a kernel rather than hipMemset).
 void launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s);
 
-// Lane-per-branch x-step; per_lane unlimited branches per lane (0: choose it
-// so that every branch wavefront fits the device's `slots` SIMD slots).
+// One block of the lane-per-branch x-step: generators (one per lane), rated
+// branches (one per lane) or unlimited branches, of which lane i solves
+// begin + i + j stride for j < per_lane while below end.
+enum { kXGen = 0, kXRated = 1, kXUnlimited = 2 };
+struct XWork {
+  int begin, end, stride;
+  short kind, per_lane;
+};
+
+// The blocks of one x-step launch, passed by value: up to kXSegs segments of
+// consecutive blocks, block first[s] + k taking begin[s] + k * blockDim of
+// its segment's range (each range of running grids is one segment), or, when
+// n_seg is 0, one work item per block read from `list`.
+constexpr int kXSegs = 12;
+struct XPlan {
+  int n_seg;
+  int first[kXSegs];
+  int begin[kXSegs], end[kXSegs], stride[kXSegs];
+  short kind[kXSegs], per_lane[kXSegs];
+  const XWork* list;
+};
+
+// Lane-per-branch x-step over n_blocks blocks of `block` lanes each.
 // stats: also count algorithmic flops and TRON events into A.stats.
-void launch_xstep(const BranchArgs& A, int64_t n6, int block, int per_lane, int slots,
-                  bool stats, hipStream_t s);
+void launch_xstep(const BranchArgs& A, const XPlan& P, int n_blocks, int block, bool stats,
+                  hipStream_t s);
+// Whether f is one of the kernels launch_xstep launches (graph node updates).
+bool is_xstep_kernel(const void* f);
 
 // Persistent x-step on `blocks` 64-lane blocks; the pool counters must be
 // zero at launch and are zero again when it ends.

@@ -6,18 +6,20 @@ solution. This module serves a stream of such requests over several resident
 grids. Every step of every solve runs in the HIP kernels of libacopf.so; this
 file only schedules.
 
-Layout: one acopf handle holds, for every resident grid j, a *home* instance
-(its last committed ADMM state) and k_j *slot* instances (copies of the same
-grid data) that requests run in. The k_j are chosen so that the device
-footprint of all instances fits the HBM budget.
+Layout: one acopf handle holds, for every resident grid j, 1 + k_j instances
+of the same grid data. One of them is the grid's *home* (its last committed
+ADMM state); the others are free slots that requests run in. The k_j are
+chosen so that the device footprint of all instances fits the HBM budget,
+which defaults to 90% of the device memory free when the server starts.
 
 A request (grid j, new loads) is admitted between iteration chunks as soon as
 a slot of grid j is free: the home state is copied into the slot on the
-device, the loads are set, and a WARM start joins the running batch, so its
-inner iterations overlap with those of every other request in flight. When it
-finishes, its state is committed back to the home instance (the next request
-for the grid warm-starts from it) and the slot is freed. A grid whose budget
-allows no slot runs its requests on the home instance, one at a time.
+device (one launch), the loads are set, and a WARM start joins the running
+batch, so its inner iterations overlap with those of every other request in
+flight. When it finishes, its slot becomes the grid's home (the next request
+for the grid warm-starts from it) and the previous home becomes a free slot:
+a completion copies nothing. A grid whose budget allows no slot runs its
+requests on its home instance, one at a time.
 
 Because every grid of a handle is an independent problem whose arithmetic
 does not depend on the other grids in the launch, a request's result is
@@ -46,6 +48,12 @@ def instance_bytes(g: Grid) -> int:
     return 8 * doubles + 4 * ints + 6 * 8 * (1 << 15)  # + residual history
 
 
+def device_free_bytes(device: int = 0) -> float:
+    """90% of the device memory free now, the default HBM budget."""
+    free, _ = A.device_memory(device)
+    return 0.9 * free
+
+
 @dataclass
 class Request:
     rid: int
@@ -64,12 +72,12 @@ class TrackingServer:
 
     def __init__(self, grids: list[Grid], params: A.Params | None = None,
                  hbm_budget_bytes: float | None = None, max_slots_per_grid: int = 4,
-                 device: int = 0, cold_start: bool = True):
+                 device: int = 0, cold_start: bool = True, chunk: int | None = None):
         self.grids = list(grids)
         n = len(self.grids)
         sizes = [instance_bytes(g) for g in self.grids]
         homes = sum(sizes)
-        budget = hbm_budget_bytes if hbm_budget_bytes is not None else 32e9
+        budget = hbm_budget_bytes if hbm_budget_bytes is not None else device_free_bytes(device)
         if homes > budget:
             raise ValueError(f"HBM budget {budget:.3g} B cannot hold the {n} resident grids "
                              f"({homes:.3g} B)")
@@ -97,7 +105,10 @@ class TrackingServer:
                 inst.append(self.grids[j])
             self.slot_ids.append(ids)
         self.solver = A.Solver(inst, params, device=device)
+        if chunk is not None:  # iterations between admissions (graph replay length)
+            self.solver.set_tuning(chunk=int(chunk))
         self.free = [deque(ids) for ids in self.slot_ids]
+        self.home = list(range(n))   # the instance holding each grid's committed state
         self.home_busy = [False] * n
         self.queue: list[deque] = [deque() for _ in range(n)]
         self.cold = None
@@ -119,11 +130,11 @@ class TrackingServer:
             if not self.free[j]:
                 return False
             slot = self.free[j].popleft()
-            s.copy_grid(j, slot)
+            s.copy_grid(self.home[j], slot)
         else:
             if self.home_busy[j]:
                 return False
-            slot = j
+            slot = self.home[j]
             self.home_busy[j] = True
         s.update_loads(slot, req.pd, req.qd)
         s.start(slot, A.WARM)
@@ -137,9 +148,10 @@ class TrackingServer:
         _, res = s.poll(req.slot)
         req.result = res
         req.finished = now
-        if req.slot != j:
-            s.copy_grid(req.slot, j)   # commit: next request for j starts here
-            self.free[j].append(req.slot)
+        if self.slot_ids[j]:
+            # commit: the finished slot is the new home, the old home is free
+            self.free[j].append(self.home[j])
+            self.home[j] = req.slot
         else:
             self.home_busy[j] = False
 

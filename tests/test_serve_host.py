@@ -1,5 +1,6 @@
 """CPU tests of the serving scheduler (paper_2110_06879_amd.serve): slot
-allocation under the HBM budget, admission, commit order and the home-only
+allocation under the HBM budget, admission, commits (the finished slot becomes
+the home) and the home-only
 path, with a stand-in for the device solver that only counts iterations.
 The arithmetic of a solve is covered by the GPU tests; here only the host
 logic runs."""
@@ -110,19 +111,24 @@ def test_every_request_served_and_committed_in_order(fake):
     for r in done:
         assert r.finished >= r.admitted >= 0.0
         assert r.result["loads"] == 100.0 + r.rid   # solved with its own loads
-        assert r.slot in srv.slot_ids[r.grid]
+        assert r.slot in [r.grid] + srv.slot_ids[r.grid]
     log = srv.solver.log
-    # every admission copies the home into a free slot before starting it, and
-    # every completion commits the slot back to the home
+    # every admission copies the grid's home into another instance of the
+    # grid before starting it; a completion makes its instance the new home
+    # and copies nothing, so there is exactly one copy per request
+    grid_of = {i: j for j in range(3) for i in [j] + srv.slot_ids[j]}
     for k, e in enumerate(log):
         if e[0] == "start" and e[2] == A.WARM:
             slot = e[1]
-            home = next(j for j in range(3) if slot in srv.slot_ids[j])
-            assert ("copy", home, slot) in log[:k]
-    commits = [e for e in log if e[0] == "copy" and e[2] < 3]
-    assert len(commits) == 30
-    # all slots free again
-    assert all(len(srv.free[j]) == 2 for j in range(3))
+            copies = [c for c in log[:k] if c[0] == "copy" and c[2] == slot]
+            assert copies and copies[-1][1] != slot and grid_of[copies[-1][1]] == grid_of[slot]
+    assert len([e for e in log if e[0] == "copy"]) == 30
+    # the home of each grid is the instance of its last finished request, and
+    # every other instance is free again
+    for j in range(3):
+        last = [r for r in done if r.grid == j][-1]   # `done` is in completion order
+        assert srv.home[j] == last.slot
+        assert sorted(list(srv.free[j]) + [srv.home[j]]) == sorted([j] + srv.slot_ids[j])
 
 
 def test_grid_without_slots_runs_on_home_one_at_a_time(fake):
