@@ -281,3 +281,40 @@ def test_step_length_state_round_trip_and_validation():
         np.testing.assert_array_equal(s.get("calpha"), want)
     with A.Solver(g) as r:
         np.testing.assert_array_equal(r.get("calpha"), np.ones(g.n_branch))
+
+
+def test_launches_over_running_subsets_equal_alone():
+    """Launches sized to the running grids only: with every other grid of a
+    16-grid batch running, the x-step takes its blocks from the work-item list
+    (more than 12 segments), with three adjacent grids running from argument
+    segments, and after each change of the running set the captured chunk's
+    nodes are resized. Every grid's iterates equal those of the grid solved
+    alone, and grids that did not run are untouched."""
+    note("batch of 16: alternate grids, then three adjacent ones, against alone runs")
+    gs = [gridgen(60 + 9 * k, 10 + k % 5, 80 + 12 * k, 0.5, 300 + k, load_factor=0.2)
+          for k in range(16)]
+    p = A.Params()
+    want = {}
+    for k, g in enumerate(gs):
+        with A.Solver(g, p) as s:
+            s.solve(A.COLD, 20)
+            want[k] = states(s)
+    with A.Solver(gs, p) as sb:
+        sb.set_tuning(chunk=8)
+        sb.solve(A.COLD, 1)  # every grid solved once, so WARM/CONTINUE starts are allowed
+        before = {k: states(sb, k) for k in range(16)}
+        for k in range(0, 16, 2):
+            sb.start(k, A.COLD, 20)
+        while sb.run(8) > 0:
+            pass
+        for k in range(16):
+            if k % 2 == 0:
+                assert_same(states(sb, k), want[k])
+            else:
+                assert_same(states(sb, k), before[k])
+        for k in (5, 6, 7):
+            sb.start(k, A.COLD, 20)
+        while sb.run(8) > 0:
+            pass
+        for k in (5, 6, 7):
+            assert_same(states(sb, k), want[k])
