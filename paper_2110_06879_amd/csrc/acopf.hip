@@ -799,7 +799,8 @@ struct acopf_s {
   size_t off_t = 0, off_h = 0, off_g = 0;
   int64_t xcap = 0;
   int n_x = 0, n_t = 0, n_hl = 0, n_gl = 0;
-  acopf_dev::XPlan xplan{};          // the x-step's blocks (kernel argument)
+  acopf_dev::XLayout xlay{};         // x-step block layout (kernel arguments)
+  const int* xlist = nullptr;        // x-step blocks to run (null: all of them)
   BranchArgs xba{};                  // the x-step's other argument, as captured
   std::vector<char> active_for;      // the running set the lists describe
   bool lists_dirty = true;
@@ -954,7 +955,8 @@ void launch_iteration(acopf_s* h, int slot) {
     acopf_dev::launch_xstep_persistent(ba, h->n6, h->tune.xstep_waves * 4 * h->n_cu,
                                        h->count_stats, s);
   else
-    acopf_dev::launch_xstep(ba, h->xplan, h->n_x, h->tune.xstep_block, h->count_stats, s);
+    acopf_dev::launch_xstep(ba, h->xlay, h->xlist, h->n_x, h->tune.xstep_block, h->count_stats,
+                            s);
   mark(1);
   BusArgs bu{h->nb, h->ng, h->ne, reinterpret_cast<const TileDesc*>(h->lists + h->off_t),
              reinterpret_cast<const TileDesc*>(h->lists + h->off_h), h->bus_grid, h->ctl,
@@ -1314,12 +1316,12 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   for (double** p : cp_d) HIP_TRY(D.alloc(p, m));
   HIP_TRY(D.alloc(&h->gptr, nb + 1));
   {
-    // work lists: x-step items (a block of at least 64 lanes per item, plus
-    // a partial item per class and grid), bus and hub tiles (at most one tile
-    // per bus, plus a placeholder), grids
+    // work lists: x-step blocks (at least 64 lanes per block, plus a partial
+    // block per class), bus and hub tiles (at most one tile per bus, plus a
+    // placeholder), grids
     auto up16 = [](size_t b) { return (b + 15) & ~size_t(15); };
     h->xcap = (ng + nl) / 64 + 3 * (int64_t)n_grids + 8;
-    h->off_t = up16(sizeof(acopf_dev::XWork) * (size_t)h->xcap);
+    h->off_t = up16(sizeof(int) * (size_t)h->xcap);
     h->off_h = h->off_t + up16(sizeof(TileDesc) * (size_t)(nb + 1));
     h->off_g = h->off_h + up16(sizeof(TileDesc) * (size_t)(nb + 1));
     const size_t bytes = h->off_g + up16(sizeof(int) * (size_t)n_grids);
@@ -1514,37 +1516,23 @@ static int build_active(acopf_s* h) {
   if (std::find(act.begin(), act.end(), 1) == act.end()) std::fill(act.begin(), act.end(), 1);
   if (!h->lists_dirty && act == h->active_for) return ACOPF_OK;
   HIP_TRY(hipStreamSynchronize(h->stream));  // the last copy from `stage` has landed
-  using acopf_dev::XWork;
-  XWork* xw = reinterpret_cast<XWork*>(h->stage);
-  int nx = 0;
-  auto ranges = [&](auto lo, auto hi) {
-    std::vector<std::pair<int64_t, int64_t>> r;
-    for (int g = 0; g < h->G; ++g) {
-      if (!act[g]) continue;
-      const int64_t a = lo(g), b = hi(g);
-      if (b <= a) continue;
-      if (!r.empty() && r.back().second == a) r.back().second = b;
-      else r.emplace_back(a, b);
-    }
-    return r;
-  };
-  const auto rg = ranges([&](int g) { return h->grids[g].gen_off; },
-                         [&](int g) { return h->grids[g].gen_off + h->grids[g].ng; });
-  const auto r6 = ranges([&](int g) { return h->grids[g].r6b; }, [&](int g) { return h->grids[g].r6e; });
-  const auto r4 = ranges([&](int g) { return h->grids[g].r4b; }, [&](int g) { return h->grids[g].r4e; });
+  // x-step: the block layout over the handle's ranges, with the unlimited
+  // branches per lane chosen for the running grids (as many as it takes for
+  // every branch wavefront to be resident at once, one per SIMD slot, unless
+  // tuned), and the layout blocks that touch a running grid
   const int bs = h->tune.xstep_block;
-  for (const auto& r : rg)
-    for (int64_t x = r.first; x < r.second; x += bs)
-      xw[nx++] = XWork{(int)x, (int)r.second, 0, (short)acopf_dev::kXGen, 1};
+  const int64_t n4_all = h->nl - h->n6;
   int64_t waves6 = 0, n4 = 0;
-  for (const auto& r : r6)
-    for (int64_t x = r.first; x < r.second; x += bs) {
-      xw[nx++] = XWork{(int)x, (int)r.second, 0, (short)acopf_dev::kXRated, 1};
-      waves6 += (bs + 63) / 64;
+  bool all = true;
+  for (int g = 0; g < h->G; ++g) {
+    if (!act[g]) {
+      all = false;
+      continue;
     }
-  for (const auto& r : r4) n4 += r.second - r.first;
-  // unlimited branches per lane: as many as it takes for every branch
-  // wavefront to be resident at once (one per SIMD slot), unless tuned
+    const HostGrid& H = h->grids[g];
+    waves6 += (H.r6e - H.r6b + bs - 1) / bs * ((bs + 63) / 64);
+    n4 += H.r4e - H.r4b;
+  }
   const int64_t slots = 4 * (int64_t)h->n_cu;
   int k4 = h->tune.xstep_per_lane;
   if (k4 <= 0) {
@@ -1553,35 +1541,41 @@ static int build_active(acopf_s* h) {
     if (free_lanes >= slots * 8)
       k4 = (int)std::min<int64_t>(8, std::max<int64_t>(1, (n4 + free_lanes - 1) / free_lanes));
   }
-  for (const auto& r : r4) {
-    const int64_t nb4 = (r.second - r.first + (int64_t)bs * k4 - 1) / ((int64_t)bs * k4);
-    for (int64_t i = 0; i < nb4; ++i)
-      xw[nx++] = XWork{(int)(r.first + i * bs), (int)r.second, (int)(nb4 * bs),
-                       (short)acopf_dev::kXUnlimited, (short)k4};
-  }
-  if (nx > h->xcap) return fail(ACOPF_EDEVICE, "x-step work list overflow");
-  // segments: runs of items whose ranges start one block apart
-  acopf_dev::XPlan& P = h->xplan;
-  P = acopf_dev::XPlan{};
-  P.list = reinterpret_cast<const XWork*>(h->lists);
-  for (int i = 0; i < nx; ++i) {
-    const XWork& w = xw[i];
-    const int s = P.n_seg - 1;
-    if (s >= 0 && w.end == P.end[s] && w.stride == P.stride[s] && w.kind == P.kind[s] &&
-        w.per_lane == P.per_lane[s] && w.begin == P.begin[s] + (i - P.first[s]) * bs)
-      continue;
-    if (P.n_seg == acopf_dev::kXSegs) {  // too many: the kernel reads the list
-      P.n_seg = 0;
-      break;
+  acopf_dev::XLayout& L = h->xlay;
+  L.n6 = h->n6;
+  L.bg = (int)((h->ng + bs - 1) / bs);
+  L.b6 = (int)((h->n6 + bs - 1) / bs);
+  L.b4 = (int)((n4_all + (int64_t)bs * k4 - 1) / ((int64_t)bs * k4));
+  L.k4 = k4;
+  int nx = L.bg + L.b6 + L.b4;
+  h->xlist = nullptr;
+  if (!all) {
+    std::vector<char> use((size_t)nx, 0);
+    auto mark = [&](int64_t off, int64_t a, int64_t e) {  // blocks off + [a / bs, (e - 1) / bs]
+      for (int64_t k = a / bs; a < e && k <= (e - 1) / bs; ++k) use[(size_t)(off + k)] = 1;
+    };
+    const int64_t span = (int64_t)L.b4 * bs;  // branches between a lane's unlimited solves
+    for (int g = 0; g < h->G; ++g) {
+      if (!act[g]) continue;
+      const HostGrid& H = h->grids[g];
+      mark(0, H.gen_off, H.gen_off + H.ng);
+      mark(L.bg, H.r6b, H.r6e);
+      // unlimited offsets o = l - n6: block u holds o = u bs + [0, bs) + j span
+      int64_t a = H.r4b - h->n6, e = H.r4e - h->n6;
+      if (e - a >= span) a = 0, e = span;
+      for (int64_t o = a; o < e;) {
+        const int64_t q = o % span, stop = std::min(e, o + (span - q));
+        mark(L.bg + L.b6, q, q + (stop - o));
+        o = stop;
+      }
     }
-    P.first[P.n_seg] = i;
-    P.begin[P.n_seg] = w.begin;
-    P.end[P.n_seg] = w.end;
-    P.stride[P.n_seg] = w.stride;
-    P.kind[P.n_seg] = w.kind;
-    P.per_lane[P.n_seg] = w.per_lane;
-    ++P.n_seg;
+    int* xl = reinterpret_cast<int*>(h->stage);
+    nx = 0;
+    for (size_t k = 0; k < use.size(); ++k)
+      if (use[k]) xl[nx++] = (int)k;
+    h->xlist = reinterpret_cast<const int*>(h->lists);
   }
+  if (nx > h->xcap) return fail(ACOPF_EDEVICE, "x-step block list overflow");
   TileDesc* tl = reinterpret_cast<TileDesc*>(h->stage + h->off_t);
   TileDesc* hl = reinterpret_cast<TileDesc*>(h->stage + h->off_h);
   int* gl = reinterpret_cast<int*>(h->stage + h->off_g);
@@ -1601,7 +1595,8 @@ static int build_active(acopf_s* h) {
   if (nt == 0) tl[nt++] = none;  // a launch needs one block; it returns at once
   if (nh == 0) hl[nh++] = none;
   hipStream_t st = h->stream;
-  HIP_TRY(hipMemcpyAsync(h->lists, h->stage, sizeof(XWork) * nx, hipMemcpyHostToDevice, st));
+  if (h->xlist)
+    HIP_TRY(hipMemcpyAsync(h->lists, h->stage, sizeof(int) * nx, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(h->lists + h->off_t, tl, sizeof(TileDesc) * nt, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(h->lists + h->off_h, hl, sizeof(TileDesc) * nh, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(h->lists + h->off_g, gl, sizeof(int) * ngl, hipMemcpyHostToDevice, st));
@@ -1612,7 +1607,7 @@ static int build_active(acopf_s* h) {
   h->active_for = act;
   h->lists_dirty = false;
   h->xba = branch_args(h);
-  void* xargs[2] = {&h->xba, &h->xplan};
+  void* xargs[7] = {&h->xba, &L.n6, &L.bg, &L.b6, &L.b4, &L.k4, &h->xlist};
   for (size_t i = 0; h->graph && i < h->gnode.size(); ++i) {
     if (h->grole[i] < 0) continue;
     hipKernelNodeParams p = h->gparam[i];

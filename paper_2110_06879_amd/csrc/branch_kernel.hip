@@ -1390,53 +1390,38 @@ void launch_xstep_persistent(const BranchArgs& A, int64_t n6, int blocks, bool s
 #define ACOPF_XSTEP_WAVES_PER_EU 1
 #endif
 
-// Lane-per-branch x-step over the work items of a plan, one per block (built
-// by the host for the grids that are running): generator items (one generator
-// per lane) come first, so their short blocks free their SIMD slots at once,
-// then rated items (one rated branch per lane), then unlimited items, whose
-// lanes solve per_lane branches one after the other (begin + lane + j stride
-// for j < per_lane while below end; stride interleaves the blocks of one
-// range). With per_lane chosen so that every branch wavefront is resident
-// from the start, the cheap unlimited branches finish inside the span of the
-// expensive rated ones instead of waiting for a second round of SIMD slots.
-// kStats: as for the persistent kernel.
+// Lane-per-branch x-step. Blocks [0, bg) of the layout take the generators
+// (short, so their SIMD slots free up at once), blocks [bg, bg + b6) one rated
+// branch per lane, and the remaining b4 blocks k4 unlimited branches per
+// lane, one after the other (branch base + j * b4 * blockDim for j < k4).
+// With k4 chosen so that every branch wavefront is resident from the start,
+// the cheap unlimited branches finish inside the span of the expensive rated
+// ones instead of waiting for a second round of SIMD slots. When only some
+// grids run, the launch has one block per layout block that touches them
+// (vblock); lanes on branches of finished grids return at once. kStats: as
+// for the persistent kernel.
 template <bool kStats>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ACOPF_XSTEP_WAVES_PER_EU)))
-void xstep_kernel(BranchArgs A, XPlan P) {
+void xstep_kernel(BranchArgs A, int64_t n6, int bg, int b6, int b4, int k4,
+                  const int* __restrict__ vblock) {
   CountersT<kStats> cnt = {};
   uint32_t solves = 0;
-  const int b = blockIdx.x;
-  XWork W;
-  if (P.n_seg > 0) {
-    // the segment of this block, by selects over the argument values (no
-    // indexed access, so the plan stays in scalar registers)
-    int s = 0;
-#pragma unroll
-    for (int q = 1; q < kXSegs; ++q)
-      if (q < P.n_seg && b >= P.first[q]) s = q;
-    W = XWork{P.begin[0], P.end[0], P.stride[0], P.kind[0], P.per_lane[0]};
-    int f = P.first[0];
-#pragma unroll
-    for (int q = 1; q < kXSegs; ++q)
-      if (s == q) {
-        W = XWork{P.begin[q], P.end[q], P.stride[q], P.kind[q], P.per_lane[q]};
-        f = P.first[q];
-      }
-    W.begin += (b - f) * (int)blockDim.x;
-  } else {
-    W = P.list[b];
-  }
-  const int64_t first = (int64_t)W.begin + threadIdx.x;
-  if (W.kind == kXGen) {
-    if (first < W.end && A.ctl[A.gen_grid[first]].done == 0) solve_generator(A, first);
+  const int b = vblock ? vblock[blockIdx.x] : (int)blockIdx.x;
+  const int bs = blockDim.x;
+  if (b < bg) {
+    const int64_t g = (int64_t)b * bs + threadIdx.x;
+    if (g < A.ng && A.ctl[A.gen_grid[g]].done == 0) solve_generator(A, g);
     return;  // whole block is generators: no branch counters
   }
-  if (W.kind == kXRated) {
-    if (first < W.end && solve_branch<6>(A, first, cnt)) ++solves;
+  if (b < bg + b6) {
+    const int64_t l = (int64_t)(b - bg) * bs + threadIdx.x;
+    if (l < n6 && solve_branch<6>(A, l, cnt)) ++solves;
   } else {
-    for (int j = 0; j < W.per_lane; ++j) {
-      const int64_t l = first + (int64_t)j * W.stride;
-      if (l >= W.end) break;
+    const int64_t base = n6 + (int64_t)(b - bg - b6) * bs + threadIdx.x;
+    const int64_t stride = (int64_t)b4 * bs;
+    for (int j = 0; j < k4; ++j) {
+      const int64_t l = base + j * stride;
+      if (l >= A.nl) break;
       if (solve_branch<4>(A, l, cnt)) ++solves;
     }
   }
@@ -1458,13 +1443,15 @@ void xstep_kernel(BranchArgs A, XPlan P) {
   }
 }
 
-void launch_xstep(const BranchArgs& A, const XPlan& P, int n_blocks, int block, bool stats,
-                  hipStream_t s) {
+void launch_xstep(const BranchArgs& A, const XLayout& L, const int* vblock, int n_blocks,
+                  int block, bool stats, hipStream_t s) {
   if (n_blocks <= 0) return;
   if (stats)
-    hipLaunchKernelGGL(xstep_kernel<true>, dim3(n_blocks), dim3(block), 0, s, A, P);
+    hipLaunchKernelGGL(xstep_kernel<true>, dim3(n_blocks), dim3(block), 0, s, A, L.n6, L.bg, L.b6,
+                       L.b4, L.k4, vblock);
   else
-    hipLaunchKernelGGL(xstep_kernel<false>, dim3(n_blocks), dim3(block), 0, s, A, P);
+    hipLaunchKernelGGL(xstep_kernel<false>, dim3(n_blocks), dim3(block), 0, s, A, L.n6, L.bg,
+                       L.b6, L.b4, L.k4, vblock);
 }
 
 bool is_xstep_kernel(const void* f) {

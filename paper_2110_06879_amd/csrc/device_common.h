@@ -72,32 +72,22 @@ void launch_quality(const QualityArgs& Q, hipStream_t s);
 // Zeroes n 64-bit words with one block (a kernel rather than hipMemset).
 void launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s);
 
-// One block of the lane-per-branch x-step: generators (one per lane), rated
-// branches (one per lane) or unlimited branches, of which lane i solves
-// begin + i + j stride for j < per_lane while below end.
-enum { kXGen = 0, kXRated = 1, kXUnlimited = 2 };
-struct XWork {
-  int begin, end, stride;
-  short kind, per_lane;
+// Block layout of the lane-per-branch x-step over a handle's index ranges:
+// blocks [0, bg) take generators [0, ng), one per lane; blocks [bg, bg + b6)
+// rated branches [0, n6), one per lane; the remaining b4 blocks unlimited
+// branches [n6, nl), k4 per lane, block u's lane i taking branch n6 + u bs + i
+// + j b4 bs for j < k4 (bs lanes per block).
+struct XLayout {
+  int64_t n6;
+  int bg, b6, b4, k4;
 };
 
-// The blocks of one x-step launch, passed by value: up to kXSegs segments of
-// consecutive blocks, block first[s] + k taking begin[s] + k * blockDim of
-// its segment's range (each range of running grids is one segment), or, when
-// n_seg is 0, one work item per block read from `list`.
-constexpr int kXSegs = 12;
-struct XPlan {
-  int n_seg;
-  int first[kXSegs];
-  int begin[kXSegs], end[kXSegs], stride[kXSegs];
-  short kind[kXSegs], per_lane[kXSegs];
-  const XWork* list;
-};
-
-// Lane-per-branch x-step over n_blocks blocks of `block` lanes each.
+// Lane-per-branch x-step: n_blocks blocks of `block` lanes. With vblock null
+// every block of the layout runs (n_blocks = bg + b6 + b4); otherwise block
+// k runs layout block vblock[k] (the blocks that touch running grids).
 // stats: also count algorithmic flops and TRON events into A.stats.
-void launch_xstep(const BranchArgs& A, const XPlan& P, int n_blocks, int block, bool stats,
-                  hipStream_t s);
+void launch_xstep(const BranchArgs& A, const XLayout& L, const int* vblock, int n_blocks,
+                  int block, bool stats, hipStream_t s);
 // Whether f is one of the kernels launch_xstep launches (graph node updates).
 bool is_xstep_kernel(const void* f);
 
