@@ -1558,14 +1558,14 @@ static int build_active(acopf_s* h) {
     for (int g = 0; g < h->G; ++g) {
       if (!act[g]) continue;
       const HostGrid& H = h->grids[g];
-      mark(0, H.gen_off, H.gen_off + H.ng);
-      mark(L.bg, H.r6b, H.r6e);
+      mark(L.b6 + L.b4, H.gen_off, H.gen_off + H.ng);
+      mark(0, H.r6b, H.r6e);
       // unlimited offsets o = l - n6: block u holds o = u bs + [0, bs) + j span
       int64_t a = H.r4b - h->n6, e = H.r4e - h->n6;
       if (e - a >= span) a = 0, e = span;
       for (int64_t o = a; o < e;) {
         const int64_t q = o % span, stop = std::min(e, o + (span - q));
-        mark(L.bg + L.b6, q, q + (stop - o));
+        mark(L.b6, q, q + (stop - o));
         o = stop;
       }
     }

@@ -1390,16 +1390,17 @@ void launch_xstep_persistent(const BranchArgs& A, int64_t n6, int blocks, bool s
 #define ACOPF_XSTEP_WAVES_PER_EU 1
 #endif
 
-// Lane-per-branch x-step. Blocks [0, bg) of the layout take the generators
-// (short, so their SIMD slots free up at once), blocks [bg, bg + b6) one rated
-// branch per lane, and the remaining b4 blocks k4 unlimited branches per
-// lane, one after the other (branch base + j * b4 * blockDim for j < k4).
-// With k4 chosen so that every branch wavefront is resident from the start,
-// the cheap unlimited branches finish inside the span of the expensive rated
-// ones instead of waiting for a second round of SIMD slots. When only some
-// grids run, the launch has one block per layout block that touches them
-// (vblock); lanes on branches of finished grids return at once. kStats: as
-// for the persistent kernel.
+// Lane-per-branch x-step. Blocks [0, b6) of the layout take one rated branch
+// per lane, the next b4 blocks k4 unlimited branches per lane, one after the
+// other (branch base + j * b4 * blockDim for j < k4), and the last bg blocks
+// the generators. With k4 chosen so that every branch wavefront is resident
+// from the start, the cheap unlimited branches finish inside the span of the
+// expensive rated ones instead of waiting for a second round of SIMD slots;
+// the short generator blocks come last, so that they take the SIMD slots the
+// branch wavefronts leave free instead of delaying some of those wavefronts.
+// When only some grids run, the launch has one block per layout block that
+// touches them (vblock); lanes on branches of finished grids return at once.
+// kStats: as for the persistent kernel.
 template <bool kStats>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ACOPF_XSTEP_WAVES_PER_EU)))
 void xstep_kernel(BranchArgs A, int64_t n6, int bg, int b6, int b4, int k4,
@@ -1408,16 +1409,16 @@ void xstep_kernel(BranchArgs A, int64_t n6, int bg, int b6, int b4, int k4,
   uint32_t solves = 0;
   const int b = vblock ? vblock[blockIdx.x] : (int)blockIdx.x;
   const int bs = blockDim.x;
-  if (b < bg) {
-    const int64_t g = (int64_t)b * bs + threadIdx.x;
+  if (b >= b6 + b4) {
+    const int64_t g = (int64_t)(b - b6 - b4) * bs + threadIdx.x;
     if (g < A.ng && A.ctl[A.gen_grid[g]].done == 0) solve_generator(A, g);
     return;  // whole block is generators: no branch counters
   }
-  if (b < bg + b6) {
-    const int64_t l = (int64_t)(b - bg) * bs + threadIdx.x;
+  if (b < b6) {
+    const int64_t l = (int64_t)b * bs + threadIdx.x;
     if (l < n6 && solve_branch<6>(A, l, cnt)) ++solves;
   } else {
-    const int64_t base = n6 + (int64_t)(b - bg - b6) * bs + threadIdx.x;
+    const int64_t base = n6 + (int64_t)(b - b6) * bs + threadIdx.x;
     const int64_t stride = (int64_t)b4 * bs;
     for (int j = 0; j < k4; ++j) {
       const int64_t l = base + j * stride;

@@ -73,10 +73,10 @@ void launch_quality(const QualityArgs& Q, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t s);
 
 // Block layout of the lane-per-branch x-step over a handle's index ranges:
-// blocks [0, bg) take generators [0, ng), one per lane; blocks [bg, bg + b6)
-// rated branches [0, n6), one per lane; the remaining b4 blocks unlimited
-// branches [n6, nl), k4 per lane, block u's lane i taking branch n6 + u bs + i
-// + j b4 bs for j < k4 (bs lanes per block).
+// blocks [0, b6) take rated branches [0, n6), one per lane; the next b4
+// blocks unlimited branches [n6, nl), k4 per lane, block u's lane i taking
+// branch n6 + u bs + i + j b4 bs for j < k4 (bs lanes per block); the last bg
+// blocks generators [0, ng), one per lane.
 struct XLayout {
   int64_t n6;
   int bg, b6, b4, k4;
