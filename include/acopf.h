@@ -36,7 +36,9 @@ enum {
                          empty bound interval, r = x = 0, isolated bus)     */
   ACOPF_ENOMEM = -2,  /* device or host allocation failed                  */
   ACOPF_EDEVICE = -3, /* a HIP runtime call failed (text in last_error)     */
-  ACOPF_ESTATE = -4   /* call not valid in the handle's current state       */
+  ACOPF_ESTATE = -4,  /* call not valid in the handle's current state       */
+  ACOPF_EBUDGET = -5  /* serving: the HBM budget cannot hold the resident
+                         grids                                              */
 };
 
 enum { /* acopf_result.status */
@@ -333,6 +335,66 @@ int acopf_peak_fp64(int32_t iters, double* tflops);
  * admission). Errors: EINVAL (null output), EDEVICE. */
 int acopf_device_memory(int32_t device, int64_t* out2);
 
+
+/* ------------------------------------------------------------------------
+ * Tracking service (Sec. I and Sec. IV-C: the ACOPF optimum followed as loads
+ * change, each new load picture solved warm from the previous solution), with
+ * continuous batching on one GPU. A server keeps n_grids grids resident in one
+ * handle: per grid a home instance holding its committed ADMM state and k_j
+ * slot instances within an HBM budget. A request (grid, new loads) is
+ * admitted between iteration chunks as soon as one of its grid's slots is
+ * free: the home state is copied into the slot on the device, the loads are
+ * set, and a warm start joins the running launches. A finished slot becomes
+ * its grid's home and the old home a free slot. A grid with no slot runs its
+ * requests on its home, one at a time. Not thread-safe; one server per host
+ * thread.
+ * ---------------------------------------------------------------------- */
+typedef struct acopf_server_s* acopf_server;
+
+typedef struct {
+  int64_t request_id;  /* as submitted                                      */
+  int32_t grid;        /* resident grid                                     */
+  int32_t instance;    /* handle instance that ran it (the grid's new home) */
+  double submitted, admitted, finished; /* host steady-clock seconds        */
+  acopf_result result; /* as acopf_poll reports it                          */
+} acopf_served;
+
+/* Slots per grid for a budget (no device needed): the footprint of an
+ * instance is estimated from its sizes (coupling vectors, branch data, state
+ * and records, generator and bus arrays, indices, residual history); the
+ * homes must fit, then slots are added round robin over the grids, smallest
+ * first, up to max_slots each, while the budget allows. slots_out[n_grids],
+ * *bytes_used the planned footprint. Errors: EINVAL, EBUDGET (the homes
+ * alone exceed budget_bytes). */
+int acopf_serving_plan(const acopf_grid* grids, int32_t n_grids, double budget_bytes,
+                       int32_t max_slots, int32_t* slots_out, double* bytes_used);
+
+/* Create a server: plan the slots (budget_bytes <= 0: 90% of the device's
+ * free memory), create the handle of homes and slots, set its chunk length
+ * (iterations between admissions; 0: the default) and solve every home cold
+ * to convergence. Grid arrays are borrowed for the call. Errors: EINVAL,
+ * EBUDGET, ENOMEM, EDEVICE. */
+int acopf_server_create(const acopf_grid* grids, int32_t n_grids, const acopf_params* params,
+                        double budget_bytes, int32_t max_slots, int32_t chunk, int32_t device,
+                        acopf_server* out);
+/* Queue a request for `grid` with new loads pd, qd [that grid's n_bus],
+ * copied. Errors: EINVAL (index, null or non-finite loads). */
+int acopf_server_submit(acopf_server s, int32_t grid, const double* pd, const double* qd,
+                        int64_t request_id);
+/* Admit queued requests into free instances, run one chunk of iterations for
+ * every request in flight, and retire the finished ones. *in_flight and
+ * *queued (nullable) report the requests running and waiting afterwards.
+ * Errors: as the handle calls it makes. */
+int acopf_server_step(acopf_server s, int32_t* in_flight, int32_t* queued);
+/* Move up to max finished requests, oldest first, into out[max]; *n = how
+ * many. */
+int acopf_server_poll(acopf_server s, acopf_served* out, int32_t max, int32_t* n);
+/* Slots per grid and current home instance [n_grids each], the homes' cold
+ * solves [n_grids], the planned footprint and the handle (whose state vectors
+ * acopf_get_state reads; the server owns it). Every output is nullable. */
+int acopf_server_info(acopf_server s, int32_t* slots_per_grid, int32_t* home_instance,
+                      acopf_result* cold, double* bytes_used, acopf_handle* handle);
+void acopf_server_destroy(acopf_server s);
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libacopf.so")
 
 COLD, WARM, CONTINUE = 0, 1, 2
 CONVERGED, MAX_ITER, NUMERICAL = 0, 1, 2
+EINVAL, ENOMEM, EDEVICE, ESTATE, EBUDGET = -1, -2, -3, -4, -5
 U, V, Z, Y, LAMBDA, BRANCH_X, BRANCH_LTIL, BRANCH_RTIL, SCALARS, PD, QD, HISTORY, STATS = range(13)
 BRANCH_ALPHA = 13
 SOLUTION = 14
@@ -37,7 +38,10 @@ EXPORTS = ("acopf_default_params", "acopf_create", "acopf_solve", "acopf_update_
            "acopf_run", "acopf_poll", "acopf_copy_grid", "acopf_snapshot",
            "acopf_set_tuning", "acopf_get_tuning", "acopf_autotune", "acopf_quality",
            "acopf_update_gen_bounds", "acopf_set_counting", "acopf_peak_hbm",
-           "acopf_peak_fp64", "acopf_quality_noalloc", "acopf_device_memory")
+           "acopf_peak_fp64", "acopf_quality_noalloc", "acopf_device_memory",
+           "acopf_serving_plan", "acopf_server_create", "acopf_server_submit",
+           "acopf_server_step", "acopf_server_poll", "acopf_server_info",
+           "acopf_server_destroy")
 QUALITY_NAMES = ("max_violation", "balance_p", "balance_q", "line_limit", "voltage_limit",
                  "angle_limit")
 
@@ -89,6 +93,12 @@ class _Result(C.Structure):
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class _Served(C.Structure):
+    _fields_ = [("request_id", C.c_int64), ("grid", C.c_int32), ("instance", C.c_int32),
+                ("submitted", C.c_double), ("admitted", C.c_double), ("finished", C.c_double),
+                ("result", _Result)]
 
 
 @dataclass
@@ -165,6 +175,17 @@ def load(path: str | None = None) -> C.CDLL:
     lib.acopf_peak_hbm.argtypes = [i64, i32, dp]
     lib.acopf_peak_fp64.argtypes = [i32, dp]
     lib.acopf_device_memory.argtypes = [i32, C.POINTER(C.c_int64)]
+    lib.acopf_serving_plan.argtypes = [C.POINTER(_Grid), i32, C.c_double, i32,
+                                       C.POINTER(i32), dp]
+    lib.acopf_server_create.argtypes = [C.POINTER(_Grid), i32, C.POINTER(_Params), C.c_double,
+                                        i32, i32, i32, C.POINTER(vp)]
+    lib.acopf_server_submit.argtypes = [vp, i32, dp, dp, i64]
+    lib.acopf_server_step.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+    lib.acopf_server_poll.argtypes = [vp, C.POINTER(_Served), i32, C.POINTER(i32)]
+    lib.acopf_server_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(_Result),
+                                      dp, C.POINTER(vp)]
+    lib.acopf_server_destroy.argtypes = [vp]
+    lib.acopf_server_destroy.restype = None
     for name in ("acopf_create", "acopf_solve", "acopf_update_loads", "acopf_get_state",
                  "acopf_set_state", "acopf_get_sizes", "acopf_get_timing",
                  "acopf_set_profiling", "acopf_start", "acopf_run", "acopf_poll",
@@ -172,7 +193,9 @@ def load(path: str | None = None) -> C.CDLL:
                  "acopf_get_tuning", "acopf_autotune", "acopf_quality",
                  "acopf_quality_noalloc",
                  "acopf_update_gen_bounds", "acopf_set_counting", "acopf_peak_hbm",
-                 "acopf_peak_fp64", "acopf_device_memory"):
+                 "acopf_peak_fp64", "acopf_device_memory", "acopf_serving_plan",
+                 "acopf_server_create", "acopf_server_submit", "acopf_server_step",
+                 "acopf_server_poll", "acopf_server_info"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -261,6 +284,25 @@ def save_tuning(path: str, key: str, tuning: dict) -> None:
     os.replace(tmp, path)
 
 
+def grid_structs(grids: list[Grid]):
+    """acopf_grid structs of the grids, and the arrays they point into (keep
+    them alive for the call)."""
+    keep = []
+    cg = (_Grid * len(grids))()
+    for k, g in enumerate(grids):
+        arrs = {}
+        for n in ("pd", "qd", "gs", "bs", "vmin", "vmax", "pmin", "pmax", "qmin",
+                  "qmax", "c2", "c1", "c0", "r", "x", "b", "tap", "shift", "rate"):
+            arrs[n] = np.ascontiguousarray(getattr(g, n), dtype=np.float64)
+        for n in ("gen_bus", "br_from", "br_to"):
+            arrs[n] = np.ascontiguousarray(getattr(g, n), dtype=np.int32)
+        keep.append(arrs)
+        cg[k] = _Grid(n_bus=g.n_bus, n_gen=g.n_gen, n_branch=g.n_branch,
+                      ref_bus=g.ref_bus, base_mva=g.base_mva,
+                      **{n: a.ctypes.data for n, a in arrs.items()})
+    return cg, keep
+
+
 class Solver:
     """A handle over one or more grids resident on one GPU."""
 
@@ -269,19 +311,7 @@ class Solver:
         self.lib = load()
         self.grids = [grids] if isinstance(grids, Grid) else list(grids)
         self.params = params or Params()
-        self._keep = []
-        cg = (_Grid * len(self.grids))()
-        for k, g in enumerate(self.grids):
-            arrs = {}
-            for n in ("pd", "qd", "gs", "bs", "vmin", "vmax", "pmin", "pmax", "qmin",
-                      "qmax", "c2", "c1", "c0", "r", "x", "b", "tap", "shift", "rate"):
-                arrs[n] = np.ascontiguousarray(getattr(g, n), dtype=np.float64)
-            for n in ("gen_bus", "br_from", "br_to"):
-                arrs[n] = np.ascontiguousarray(getattr(g, n), dtype=np.int32)
-            self._keep.append(arrs)
-            cg[k] = _Grid(n_bus=g.n_bus, n_gen=g.n_gen, n_branch=g.n_branch,
-                          ref_bus=g.ref_bus, base_mva=g.base_mva,
-                          **{n: a.ctypes.data for n, a in arrs.items()})
+        cg, self._keep = grid_structs(self.grids)
         sp = None
         if stream is not None:
             sp = C.c_void_p(int(getattr(stream, "cuda_stream", stream)))
@@ -292,6 +322,20 @@ class Solver:
         self._check(rc)
         self.h = h
         self._keep = None
+        self._owned = True
+
+    @classmethod
+    def view(cls, handle, grids: list[Grid], params: Params | None = None) -> "Solver":
+        """A Solver over a handle owned elsewhere (a tracking server's): its
+        calls act on that handle, and closing it leaves the handle alone."""
+        self = cls.__new__(cls)
+        self.lib = load()
+        self.grids = list(grids)
+        self.params = params or Params()
+        self._keep = None
+        self.h = handle
+        self._owned = False
+        return self
 
     def _check(self, rc: int):
         if rc != 0:
@@ -299,7 +343,8 @@ class Solver:
 
     def close(self):
         if getattr(self, "h", None):
-            self.lib.acopf_destroy(self.h)
+            if getattr(self, "_owned", True):
+                self.lib.acopf_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -764,6 +764,12 @@ bool finite_all(const double* a, int64_t n) {
 
 }  // namespace
 
+namespace acopf_dev {
+// The thread's last error message for codes returned by other translation
+// units of the library (the tracking server).
+int report_error(int code, const char* msg) { return fail(code, msg); }
+}  // namespace acopf_dev
+
 struct acopf_s {
   int device = 0;
   hipStream_t stream = nullptr;

@@ -1,25 +1,16 @@
-"""Warm-start tracking service with continuous batching on one GPU.
+"""Warm-start tracking service with continuous batching on one GPU: the
+Python side of the library's tracking server (acopf_server_* in acopf.h).
 
 The paper motivates fast tracking of the ACOPF optimum under load changes
 (Sec. I, Sec. IV-C): each new load picture is solved warm from the previous
-solution. This module serves a stream of such requests over several resident
-grids. Every step of every solve runs in the HIP kernels of libacopf.so; this
-file only schedules.
-
-Layout: one acopf handle holds, for every resident grid j, 1 + k_j instances
-of the same grid data. One of them is the grid's *home* (its last committed
-ADMM state); the others are free slots that requests run in. The k_j are
-chosen so that the device footprint of all instances fits the HBM budget,
-which defaults to 90% of the device memory free when the server starts.
-
-A request (grid j, new loads) is admitted between iteration chunks as soon as
-a slot of grid j is free: the home state is copied into the slot on the
-device (one launch), the loads are set, and a WARM start joins the running
-batch, so its inner iterations overlap with those of every other request in
-flight. When it finishes, its slot becomes the grid's home (the next request
-for the grid warm-starts from it) and the previous home becomes a free slot:
-a completion copies nothing. A grid whose budget allows no slot runs its
-requests on its home instance, one at a time.
+solution. The server, native code in the library, keeps several grids
+resident and serves a stream of such requests: per grid a home instance (its
+last committed ADMM state) and slot instances within an HBM budget; a request
+is admitted between iteration chunks into a free slot (a one-launch device
+copy of the home state, its loads, a warm start) and joins the running
+launches; a finished slot becomes the grid's home. This module only
+marshals requests and results and replays a timed request stream; every step
+of a solve runs in the HIP kernels of libacopf.so.
 
 Because every grid of a handle is an independent problem whose arithmetic
 does not depend on the other grids in the launch, a request's result is
@@ -27,6 +18,7 @@ bitwise the same alone and in the mix (tested).
 """
 from __future__ import annotations
 
+import ctypes as C
 import math
 import time
 from collections import deque
@@ -38,20 +30,26 @@ from . import acopf as A
 from .gridgen import Grid
 
 
-def instance_bytes(g: Grid) -> int:
-    """Device footprint of one grid instance in the library's layout."""
-    m = g.n_coupling
-    nb, ng, nl = g.n_bus, g.n_gen, g.n_branch
-    # coupling vectors; branch data, state and records; generators; buses
-    doubles = 5 * m + 9 * nl + 8 * nl + 5 * nl + 16 * nl + 9 * ng + 6 * nb
-    ints = 2 * nl + nl + 2 * nl + 2 * nl + ng + 3 * nb + 2
-    return 8 * doubles + 4 * ints + 6 * 8 * (1 << 15)  # + residual history
+def serving_plan(grids: list[Grid], budget_bytes: float, max_slots_per_grid: int = 4):
+    """Slots per grid and the planned footprint for a budget (the library's
+    acopf_serving_plan; no device needed). Raises ValueError when the budget
+    cannot hold the resident grids (ACOPF_EBUDGET)."""
+    lib = A.load()
+    cg, keep = A.grid_structs(grids)
+    slots = (C.c_int32 * len(grids))()
+    used = C.c_double(0.0)
+    rc = lib.acopf_serving_plan(cg, len(grids), float(budget_bytes), int(max_slots_per_grid),
+                                slots, C.byref(used))
+    if rc == A.EBUDGET:
+        raise ValueError(lib.acopf_last_error().decode())
+    if rc != 0:
+        raise A.AcopfError(f"acopf error {rc}: {lib.acopf_last_error().decode()}")
+    return list(slots), used.value
 
 
-def device_free_bytes(device: int = 0) -> float:
-    """90% of the device memory free now, the default HBM budget."""
-    free, _ = A.device_memory(device)
-    return 0.9 * free
+def instance_bytes(g: Grid) -> float:
+    """The library's estimate of one instance's device footprint."""
+    return serving_plan([g], 1e30, 0)[1]
 
 
 @dataclass
@@ -61,132 +59,120 @@ class Request:
     arrival: float          # seconds after the start of the stream
     pd: np.ndarray
     qd: np.ndarray
-    admitted: float = math.nan
-    finished: float = math.nan
+    submit_delay: float = 0.0   # from the scheduled arrival to the submission
+    latency: float = math.nan   # seconds from arrival to the result being seen
     result: dict = field(default_factory=dict)
-    slot: int = -1
+    slot: int = -1              # handle instance that ran it (its grid's new home)
 
 
 class TrackingServer:
-    """Continuous-batching warm-start server over resident grids."""
+    """Continuous-batching warm-start server over resident grids (the
+    library's acopf_server)."""
 
     def __init__(self, grids: list[Grid], params: A.Params | None = None,
                  hbm_budget_bytes: float | None = None, max_slots_per_grid: int = 4,
-                 device: int = 0, cold_start: bool = True, chunk: int | None = None):
+                 device: int = 0, chunk: int | None = None):
+        self.lib = A.load()
         self.grids = list(grids)
+        self.params = params or A.Params()
+        cg, keep = A.grid_structs(self.grids)
+        p = self.params.c()
+        srv = C.c_void_p()
+        rc = self.lib.acopf_server_create(cg, len(self.grids), C.byref(p),
+                                          float(hbm_budget_bytes or 0.0),
+                                          int(max_slots_per_grid), int(chunk or 0), device,
+                                          C.byref(srv))
+        if rc == A.EBUDGET:
+            raise ValueError(self.lib.acopf_last_error().decode())
+        if rc != 0:
+            raise A.AcopfError(f"acopf error {rc}: {self.lib.acopf_last_error().decode()}")
+        self.srv = srv
         n = len(self.grids)
-        sizes = [instance_bytes(g) for g in self.grids]
-        homes = sum(sizes)
-        budget = hbm_budget_bytes if hbm_budget_bytes is not None else device_free_bytes(device)
-        if homes > budget:
-            raise ValueError(f"HBM budget {budget:.3g} B cannot hold the {n} resident grids "
-                             f"({homes:.3g} B)")
-        # slots: round robin, smallest grids first, while the budget allows
-        slots = [0] * n
-        left = budget - homes
-        order = sorted(range(n), key=lambda j: sizes[j])
-        grew = True
-        while grew:
-            grew = False
-            for j in order:
-                if slots[j] < max_slots_per_grid and sizes[j] <= left:
-                    slots[j] += 1
-                    left -= sizes[j]
-                    grew = True
-        self.slots_per_grid = slots
-        self.bytes_used = budget - left
-        # handle layout: homes 0..n-1, then the slots of each grid
+        slots = (C.c_int32 * n)()
+        cold = (A._Result * n)()
+        used = C.c_double(0.0)
+        h = C.c_void_p()
+        self._check(self.lib.acopf_server_info(self.srv, slots, None, cold, C.byref(used),
+                                               C.byref(h)))
+        self.slots_per_grid = list(slots)
+        self.bytes_used = used.value
+        self.cold = [c.as_dict() for c in cold]
+        # instances: the homes 0..n-1, then each grid's slots
         inst = list(self.grids)
-        self.slot_ids: list[list[int]] = []
         for j in range(n):
-            ids = []
-            for _ in range(slots[j]):
-                ids.append(len(inst))
-                inst.append(self.grids[j])
-            self.slot_ids.append(ids)
-        self.solver = A.Solver(inst, params, device=device)
-        if chunk is not None:  # iterations between admissions (graph replay length)
-            self.solver.set_tuning(chunk=int(chunk))
-        self.free = [deque(ids) for ids in self.slot_ids]
-        self.home = list(range(n))   # the instance holding each grid's committed state
-        self.home_busy = [False] * n
-        self.queue: list[deque] = [deque() for _ in range(n)]
-        self.cold = None
-        if cold_start:
-            for j in range(n):
-                self.solver.start(j, A.COLD)
-            while self.solver.run(1 << 16) > 0:
-                pass
-            self.cold = [self.solver.poll(j)[1] for j in range(n)]
+            inst += [self.grids[j]] * self.slots_per_grid[j]
+        self.solver = A.Solver.view(h, inst, self.params)
+
+    def _check(self, rc: int):
+        if rc != 0:
+            raise A.AcopfError(f"acopf error {rc}: {self.lib.acopf_last_error().decode()}")
 
     def close(self):
-        self.solver.close()
+        if getattr(self, "srv", None):
+            self.lib.acopf_server_destroy(self.srv)
+            self.srv = None
 
-    # ------------------------------------------------------------------
-    def _admit(self, req: Request, now: float) -> bool:
-        j = req.grid
-        s = self.solver
-        if self.slot_ids[j]:
-            if not self.free[j]:
-                return False
-            slot = self.free[j].popleft()
-            s.copy_grid(self.home[j], slot)
-        else:
-            if self.home_busy[j]:
-                return False
-            slot = self.home[j]
-            self.home_busy[j] = True
-        s.update_loads(slot, req.pd, req.qd)
-        s.start(slot, A.WARM)
-        req.slot = slot
-        req.admitted = now
-        return True
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
-    def _complete(self, req: Request, now: float):
-        j = req.grid
-        s = self.solver
-        _, res = s.poll(req.slot)
-        req.result = res
-        req.finished = now
-        if self.slot_ids[j]:
-            # commit: the finished slot is the new home, the old home is free
-            self.free[j].append(self.home[j])
-            self.home[j] = req.slot
-        else:
-            self.home_busy[j] = False
+    def home(self) -> list[int]:
+        """The instance holding each grid's committed state."""
+        out = (C.c_int32 * len(self.grids))()
+        self._check(self.lib.acopf_server_info(self.srv, None, out, None, None, None))
+        return list(out)
 
-    def serve(self, requests: list[Request], chunk: int | None = None,
-              realtime: bool = True) -> dict:
+    def submit(self, req: Request):
+        pd = np.ascontiguousarray(req.pd, dtype=np.float64)
+        qd = np.ascontiguousarray(req.qd, dtype=np.float64)
+        self._check(self.lib.acopf_server_submit(self.srv, req.grid, A._dp(pd), A._dp(qd),
+                                                 req.rid))
+
+    def step(self) -> tuple[int, int]:
+        """Admit, run one chunk, retire; returns (in flight, queued)."""
+        f, q = C.c_int32(), C.c_int32()
+        self._check(self.lib.acopf_server_step(self.srv, C.byref(f), C.byref(q)))
+        return f.value, q.value
+
+    def finished(self) -> list:
+        out = []
+        buf = (A._Served * 64)()
+        while True:
+            n = C.c_int32()
+            self._check(self.lib.acopf_server_poll(self.srv, buf, 64, C.byref(n)))
+            out += [buf[k] for k in range(n.value)]
+            if n.value < 64:
+                return out
+
+    def serve(self, requests: list[Request], realtime: bool = True) -> dict:
         """Replay a request stream; arrival times are honoured in wall-clock
         time when realtime, else every request is available at once."""
-        s = self.solver
-        chunk = chunk or s.tuning()["chunk"]
         pending = deque(sorted(requests, key=lambda r: r.arrival))
-        inflight: dict[int, Request] = {}
+        by_id = {r.rid: r for r in requests}
         done: list[Request] = []
-        iters = 0
+        in_flight = queued = 0
         t0 = time.perf_counter()
-        while pending or inflight or any(self.queue):
+        while pending or in_flight or queued:
             now = time.perf_counter() - t0
             while pending and (not realtime or pending[0].arrival <= now):
                 r = pending.popleft()
-                self.queue[r.grid].append(r)
-            for j in range(len(self.grids)):
-                while self.queue[j] and self._admit(self.queue[j][0], now):
-                    r = self.queue[j].popleft()
-                    inflight[r.slot] = r
-            if inflight:
-                s.run(chunk)
-                iters += chunk
-                now = time.perf_counter() - t0
-                for slot in [k for k in inflight if not s.is_running(k)]:
-                    r = inflight.pop(slot)
-                    self._complete(r, now)
+                r.submit_delay = max(0.0, now - r.arrival) if realtime else 0.0
+                self.submit(r)
+                queued += 1
+            if in_flight or queued:
+                in_flight, queued = self.step()
+                for d in self.finished():
+                    r = by_id[d.request_id]
+                    r.result = d.result.as_dict()
+                    r.slot = d.instance
+                    r.latency = r.submit_delay + (d.finished - d.submitted)
                     done.append(r)
             elif pending and realtime:
                 time.sleep(max(0.0, min(pending[0].arrival - now, 0.002)))
         wall = time.perf_counter() - t0
-        lat = np.array([r.finished - r.arrival for r in done]) * 1e3
+        lat = np.array([r.latency for r in done]) * 1e3
         its = np.array([r.result["inner_iters"] for r in done])
         conv = sum(1 for r in done if r.result["status"] == A.CONVERGED)
         solves = sum(r.result["inner_iters"] * self.grids[r.grid].n_branch for r in done)
@@ -198,7 +184,7 @@ class TrackingServer:
                 "mean_iters": float(its.mean()) if len(its) else math.nan,
                 "converged": conv, "requests_per_s": len(done) / wall,
                 "branch_solves_per_s": solves / wall, "worst_residual": worst,
-                "chunks": iters // max(chunk, 1), "done": done}
+                "done": done}
 
 
 def poisson_requests(grids: list[Grid], rate: float, duration: float, seed: int = 5000,
@@ -240,12 +226,12 @@ def serve_one_at_a_time(grids: list[Grid], requests: list[Request],
         s.update_loads(0, r.pd, r.qd)
         res = s.solve(A.WARM)[0]
         r.result = res
-        r.finished = time.perf_counter() - t0
+        r.latency = time.perf_counter() - t0 - r.arrival
         done.append(r)
     wall = time.perf_counter() - t0
     for s in solvers:
         s.close()
-    lat = np.array([r.finished - r.arrival for r in done]) * 1e3
+    lat = np.array([r.latency for r in done]) * 1e3
     solves = sum(r.result["inner_iters"] * grids[r.grid].n_branch for r in done)
     return {"requests": len(done), "wall_s": wall,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),

@@ -318,3 +318,49 @@ def test_launches_over_running_subsets_equal_alone():
             pass
         for k in (5, 6, 7):
             assert_same(states(sb, k), want[k])
+
+
+def test_server_commits_each_finished_slot_as_home():
+    """The native tracking server: 30 requests over 3 grids with 2 slots
+    each, all available at once. Every request converges on an instance of
+    its own grid; the instance of each grid's last finished request is that
+    grid's home afterwards; and a further request for a grid warm-starts from
+    that home (its result equals a warm start of the same loads on a plain
+    handle holding the home's state)."""
+    note("native server: 30 requests, homes follow the finished slots")
+    gs = [gridgen(120 + 30 * k, 20 + 4 * k, 156 + 39 * k, 0.5, 70 + k, load_factor=0.2)
+          for k in range(3)]
+    srv = S.TrackingServer(gs, max_slots_per_grid=2)
+    try:
+        assert srv.slots_per_grid == [2, 2, 2]
+        inst = {j: [j] + [3 + 2 * j, 4 + 2 * j] for j in range(3)}
+        reqs = []
+        for r in range(30):
+            j = r % 3
+            pd, qd = perturb_loads(gs[j], 0.02, 700 + r)
+            reqs.append(S.Request(r, j, 0.0, pd, qd))
+        out = srv.serve(reqs, realtime=False)
+        assert out["requests"] == 30 and out["converged"] == 30
+        done = out["done"]
+        for r in done:
+            assert r.slot in inst[r.grid]
+        home = srv.home()
+        for j in range(3):
+            assert home[j] == [r for r in done if r.grid == j][-1].slot
+        # one more request for grid 1 starts from its home's state
+        base = states(srv.solver, home[1])
+        pd, qd = perturb_loads(gs[1], 0.02, 799)
+        last = srv.serve([S.Request(99, 1, 0.0, pd, qd)], realtime=False)["done"][0]
+        assert last.slot != home[1]
+        with A.Solver(gs[1]) as ref:
+            ref.solve(A.COLD, 1)
+            for k, v in base.items():
+                ref.set(k, v)
+            ref.set("scalars", srv.solver.get("scalars", home[1]))
+            ref.update_loads(0, pd, qd)
+            want = ref.solve(A.WARM)[0]
+            assert want["inner_iters"] == last.result["inner_iters"]
+            assert want["objective"] == last.result["objective"]
+            assert_same(states(ref), states(srv.solver, last.slot))
+    finally:
+        srv.close()
