@@ -302,10 +302,11 @@ int acopf_quality_noalloc(acopf_handle h, int32_t grid, double* out6);
 
 /* Average device time (ms) per launch over every iteration run with
  * profiling on since the handle was created: out[0] x-step (generators and
- * branches), out[1] bus/z/y/residual step, out[2] control (which also
- * applies the outer multiplier step when one ends), out[3] = 0 (kept for
- * layout: the outer step has no launch of its own); out[4] = number of
- * iterations timed. Errors: EINVAL. */
+ * branches), out[1] bus/z/y/residual step (which also applies an outer
+ * multiplier step that the previous iteration decided), out[2] control
+ * (tests, outer step decision, beta rule), out[3] = 0 (kept for layout: the
+ * outer step has no launch of its own); out[4] = number of iterations timed.
+ * Errors: EINVAL. */
 int acopf_get_timing(acopf_handle h, double* out5);
 
 /* Free everything the handle owns. NULL is a no-op. */

@@ -4,22 +4,27 @@
 // One inner iteration of Algorithm 1 is three launches on one stream:
 //   xstep_kernel    branch subproblems, eq. (branch), TRON + AL     lane/branch
 //                   and the generator closed form, eq. (qp-bound)   lane/gen
-//   bus_kernel      bus closed form eq. (qp-bus), then z and y and
-//                   the residual maxima of every coupling it owns  block/tile
-//                   (tiles of a bus too large for one block in a   of buses,
-//                   second launch, only when there are such buses) lane/pair
-//   ctl_kernel      termination tests and the outer beta rule       block/grid
-//                   and, when an outer step ends, lambda <- proj(lambda
-//                   + beta z) over the grid's couplings
+//   bus_kernel      a pending outer multiplier step lambda <-      block/tile
+//                   proj(lambda + beta z), the bus closed form     of buses,
+//                   eq. (qp-bus), then z and y and the residual    lane/pair
+//                   maxima of every coupling it owns (tiles of a
+//                   bus too large for one block in a second
+//                   launch, only when there are such buses)
+//   ctl_kernel      termination tests, the outer step decision     block/grid
+//                   and the beta rule
 // The generator and branch steps read only the previous iteration's v, z, y
 // and so could run in any order; the bus step owns each coupling exactly once
 // (every coupling has one bus side), which makes the z and y updates and the
 // residual maxima a fused, race-free pass. Each bus tile writes its residual
 // maxima to a slot of its own and the control kernel takes the maximum over
 // a grid's tiles: exact and independent of order, with no atomics contending
-// on one address. Kernels return at once for grids that
-// have finished, so a chunk of launches can overshoot convergence harmlessly;
-// the host reads the per-grid control words once per chunk.
+// on one address. An outer step decided at iteration t is applied by the
+// bus step of iteration t + 1 before it uses lambda (the branch step does
+// not read lambda); one still pending when the host regains control (the
+// grid finished, or the run stopped) is applied then. Kernels return at once
+// for grids that have finished, so a chunk of launches can overshoot
+// convergence harmlessly; the host reads the per-grid control words once per
+// chunk.
 //
 // Device layout (structure of arrays, FP64), chosen for the HBM-bound bus
 // step: every bus owns a contiguous range of generators and of branch ends,
@@ -104,12 +109,13 @@ struct BusArgs {
   const double *pd, *qd, *gs, *bs;
   const int* isref;
   const double* u;
-  const double* lam;
+  double* lam;               // written by the outer multiplier step
   double *v, *z, *y;
   double rho_pq, rho_va;
   double* tmax;              // [n_tiles][3] residual maxima of each tile
   const int* erec;           // [ne] record half of each end: 2 l + (0 from, 1 to)
   double* brec;              // [nl][16] branch records for the next x-step
+  double lambda_max;         // projection bound of the outer multiplier step
 };
 
 // Half of a branch record (64 bytes): the pairs (v_k - z_k, y_k) of one
@@ -211,6 +217,8 @@ __device__ inline void bus_solve(int tid, int be0, int be1, int bg0, int bg1, in
 // maxima. A tile's couplings are its end couplings (contiguous, p q w theta
 // per end) followed by its generators' p and q couplings; each lane owns a
 // pair of couplings: an end's (p, q) or (w, theta), or a generator's (p, q).
+//   0. lane per pair: the outer multiplier step, when the previous
+//      iteration's decision left one pending;
 //   1. lane per pair: the prox targets c_k = rho_k (u_k + z_k) + y_k and,
 //      for p and q couplings, c_k / rho_pq, into LDS (16-byte loads);
 //   2. lane per bus: the sums over its couplings in their fixed order, read
@@ -280,7 +288,24 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
   const GridCtl* C = A.ctl + grid;
   const int done = C->done;
   const double beta = C->beta;
+  const int do_outer = C->do_outer;
+  const double bl = C->beta_lam, lm = A.lambda_max;
   if (done) return;  // uniform: the tile lies in one grid
+  // The previous iteration ended an outer step (Sec. III-B): the multiplier
+  // step lambda <- proj_[-lmax, lmax](lambda + beta z) on this tile's
+  // couplings, with the z that iteration produced, before z is updated.
+  auto outer_step = [&](int j, double2& l_, const double2& z_) {
+    l_.x = fmax(-lm, fmin(lm, l_.x + bl * z_.x));
+    l_.y = fmax(-lm, fmin(lm, l_.y + bl * z_.y));
+    if (j < npe) {
+      *reinterpret_cast<double2*>(A.lam + 2 * ng + 4 * (int64_t)E0 + 2 * j) = l_;
+    } else {
+      const int64_t kp = (int64_t)G0 + (j - npe);
+      A.lam[kp] = l_.x;
+      A.lam[ng + kp] = l_.y;
+    }
+  };
+  if (do_outer && own) outer_step(tid, cl, cz);
   // ---- phase 1
   auto is_va = [&](int j) { return j < npe && (j & 1); };  // (w, theta) pair
   if (own) {
@@ -339,7 +364,10 @@ __global__ __launch_bounds__(1024) void bus_kernel(BusArgs A) {
   for (int j = tid; j < np; j += (kHub ? nt : np)) {
     double2 u_ = cu, z_ = cz, y_ = cy, v_ = cv, l_ = cl;
     int hf = half;
-    if (kHub && j != tid) load_pair(j, u_, z_, y_, v_, l_, hf);  // hub overflow
+    if (kHub && j != tid) {  // hub overflow
+      load_pair(j, u_, z_, y_, v_, l_, hf);
+      if (do_outer) outer_step(j, l_, z_);
+    }
     const int b = !kHub || j < ncap ? cb[j] : 0;
     const bool va = is_va(j);
     const double rho = va ? rva : rpq;
@@ -426,18 +454,16 @@ __global__ __launch_bounds__(256) void record_kernel(int64_t ng, int64_t e0, int
   store_record_half(brec, erec[e], rec);
 }
 
+// A grid of a control launch: its index and the range [t0, t1) of its bus
+// tiles' residual slots.
+struct GridItem {
+  int g, t0, t1, pad;
+};
+
 struct CtlArgs {
-  int G;
-  const int* glist;      // grids of the launch (the running ones)
+  const GridItem* items;  // the running grids, one block each
   GridCtl* ctl;
   const double* tmax;     // [n_tiles][3] residual maxima per bus tile
-  const int* grid_tile;   // [G + 1] tiles of each grid
-  const int64_t* gen_off; // [G + 1] generators of each grid
-  const int64_t* end_off; // [G + 1] branch ends of each grid
-  int64_t ng, ne;
-  const double* z;
-  double* lam;
-  double lambda_max;
   double* hist;  // [G][kHistCap][6]
   double eps_pri, eps_dual, eps_z, beta_gamma, beta_omega, beta_max;
   int max_outer, max_inner;
@@ -495,31 +521,39 @@ __device__ int ctl_decide(const CtlArgs& A, int g, GridCtl& c, double rp, double
   return c.do_outer;
 }
 
-// Control of Algorithm 1 per grid, one block of kCtlBlock lanes per grid:
-// the residual maxima over the grid's bus tiles, the decisions above, and,
-// on the (rare) iterations that end an outer step, the multiplier update
-// lambda <- proj_[-lmax, lmax](lambda + beta z) of Sec. III-B over the grid's
-// couplings by the same block, so no launch is spent on it otherwise.
-constexpr int kCtlBlock = 1024;
+// Control of Algorithm 1 per grid, one block of kCtlBlock lanes per running
+// grid: the residual maxima over the grid's bus tiles and the decisions
+// above. A grid that has finished stays as it is, with an outer step that
+// its last decision left pending (the host applies that one).
+constexpr int kCtlBlock = 256;
 __global__ __launch_bounds__(kCtlBlock) void ctl_kernel(CtlArgs A) {
-  const int g = A.glist[blockIdx.x];
+  const GridItem it = A.items[blockIdx.x];
+  const int g = it.g;
   const int tid = threadIdx.x;
-  GridCtl& c = A.ctl[g];
   // The tile maxima and lane 0's copy of the control record are loaded
-  // before the done test, so their latencies overlap instead of adding up
-  // (a finished grid's stale maxima are read and ignored).
+  // together, so that their latencies overlap (a finished grid's maxima are
+  // read and ignored); each lane issues the loads of up to kU tiles before it
+  // combines them, so that one round covers kU kCtlBlock tiles.
   GridCtl cc;
-  if (tid == 0) cc = c;
-  const int done = c.done;
+  if (tid == 0) cc = A.ctl[g];
   double rp = 0.0, rd = 0.0, rz = 0.0;
-  for (int t = A.grid_tile[g] + tid; t < A.grid_tile[g + 1]; t += kCtlBlock) {
-    rp = fmax(rp, A.tmax[3 * t + 0]);
-    rd = fmax(rd, A.tmax[3 * t + 1]);
-    rz = fmax(rz, A.tmax[3 * t + 2]);
-  }
-  if (done) {
-    if (tid == 0) c.do_outer = 0;
-    return;
+  constexpr int kU = 8;
+  for (int t = it.t0 + tid; t < it.t1; t += kU * kCtlBlock) {
+    double m[kU][3];
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      const int tk = t + k * kCtlBlock;
+      const bool in = tk < it.t1;
+      m[k][0] = in ? A.tmax[3 * tk + 0] : 0.0;
+      m[k][1] = in ? A.tmax[3 * tk + 1] : 0.0;
+      m[k][2] = in ? A.tmax[3 * tk + 2] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      rp = fmax(rp, m[k][0]);
+      rd = fmax(rd, m[k][1]);
+      rz = fmax(rz, m[k][2]);
+    }
   }
   for (int off = 32; off > 0; off >>= 1) {
     rp = fmax(rp, __shfl_xor(rp, off, 64));
@@ -527,38 +561,39 @@ __global__ __launch_bounds__(kCtlBlock) void ctl_kernel(CtlArgs A) {
     rz = fmax(rz, __shfl_xor(rz, off, 64));
   }
   __shared__ double red[3][kCtlBlock / 64];
-  __shared__ int s_outer;
-  __shared__ double s_beta;
   if ((tid & 63) == 0) {
     red[0][tid >> 6] = rp;
     red[1][tid >> 6] = rd;
     red[2][tid >> 6] = rz;
   }
   __syncthreads();
-  if (tid == 0) {
-    for (int w = 1; w < kCtlBlock / 64; ++w) {
-      rp = fmax(rp, red[0][w]);
-      rd = fmax(rd, red[1][w]);
-      rz = fmax(rz, red[2][w]);
-    }
-    s_outer = ctl_decide(A, g, cc, rp, rd, rz);
-    s_beta = cc.beta_lam;
-    c = cc;
+  if (tid != 0 || cc.done) return;
+  for (int w = 1; w < kCtlBlock / 64; ++w) {
+    rp = fmax(rp, red[0][w]);
+    rd = fmax(rd, red[1][w]);
+    rz = fmax(rz, red[2][w]);
   }
-  __syncthreads();
-  if (!s_outer) return;
-  const double bl = s_beta, lm = A.lambda_max;
-  auto update = [&](int64_t k) {
-    const double t = A.lam[k] + bl * A.z[k];
-    A.lam[k] = fmax(-lm, fmin(lm, t));
-  };
-  for (int64_t k = A.gen_off[g] + tid; k < A.gen_off[g + 1]; k += kCtlBlock) {
-    update(k);
-    update(A.ng + k);
+  ctl_decide(A, g, cc, rp, rd, rz);
+  A.ctl[g] = cc;
+}
+
+// An outer multiplier step of grid g (Sec. III-B) still pending when the
+// host regains control: lambda <- proj_[-lmax, lmax](lambda + beta z), with
+// the beta of the step (bl), over the grid's generator couplings [g0, g1) (p,
+// and q at ng + k) and end couplings [c0, c1); the flag is cleared. Grid-
+// stride, so any number of blocks covers the grid.
+__global__ __launch_bounds__(256) void outer_step_kernel(GridCtl* ctl, int g, int64_t ng,
+                                                         int64_t g0, int64_t g1, int64_t c0,
+                                                         int64_t c1, double bl, double lm,
+                                                         const double* z, double* lam) {
+  const int64_t n_gen = g1 - g0, n = 2 * n_gen + (c1 - c0);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t k = i < n_gen ? g0 + i
+                                : (i < 2 * n_gen ? ng + g0 + (i - n_gen) : c0 + (i - 2 * n_gen));
+    lam[k] = fmax(-lm, fmin(lm, lam[k] + bl * z[k]));
   }
-  for (int64_t k = 2 * A.ng + 4 * A.end_off[g] + tid; k < 2 * A.ng + 4 * A.end_off[g + 1];
-       k += kCtlBlock)
-    update(k);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl[g].do_outer = 0;
 }
 
 struct ColdArgs {
@@ -823,7 +858,7 @@ struct acopf_s {
   GridCtl* h_ctl = nullptr;  // pinned
   unsigned long long* stats;
   double* tmax;          // [nb + 1][3] residual maxima per bus tile
-  int* grid_tile;        // [G + 1] tile range of each grid
+  std::vector<int> grid_tile_h;  // [G + 1] tile range of each grid
   int* failures;
   unsigned* pool;  // persistent x-step pool counters
   int n_cu = 0;
@@ -935,9 +970,7 @@ int build_tiles(acopf_s* h, int block) {
     }
   }
   grid_tile.push_back((int)tiles.size());
-  HIP_TRY(hipMemcpyAsync(h->grid_tile, grid_tile.data(), sizeof(int) * grid_tile.size(),
-                         hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->grid_tile_h = std::move(grid_tile);
   h->tile_hub.assign(tiles.size(), 0);
   for (int t : hubs) h->tile_hub[t] = 1;
   h->tiles_h = std::move(tiles);
@@ -967,7 +1000,7 @@ void launch_iteration(acopf_s* h, int slot) {
   BusArgs bu{h->nb, h->ng, h->ne, reinterpret_cast<const TileDesc*>(h->lists + h->off_t),
              reinterpret_cast<const TileDesc*>(h->lists + h->off_h), h->bus_grid, h->ctl,
              h->gptr, h->eptr, h->pd, h->qd, h->gs, h->bs, h->isref, h->u, h->lam, h->v, h->z,
-             h->y, h->P.rho_pq, h->P.rho_va, h->tmax, h->erec, h->brec};
+             h->y, h->P.rho_pq, h->P.rho_va, h->tmax, h->erec, h->brec, h->P.lambda_max};
   const int bb = h->tile_block;
   hipLaunchKernelGGL(bus_kernel<false>, dim3(h->n_t), dim3(bb), bus_lds_bytes(h->tile_block), s,
                      bu);
@@ -975,8 +1008,8 @@ void launch_iteration(acopf_s* h, int slot) {
     hipLaunchKernelGGL(bus_kernel<true>, dim3(h->n_hl), dim3(bb), bus_lds_bytes(h->tile_block),
                        s, bu);
   mark(2);
-  CtlArgs ca{h->G, reinterpret_cast<const int*>(h->lists + h->off_g), h->ctl, h->tmax, h->grid_tile, h->gen_off_d, h->end_off_d, h->ng, h->ne,
-             h->z, h->lam, h->P.lambda_max, h->hist, h->P.eps_pri, h->P.eps_dual, h->P.eps_z,
+  CtlArgs ca{reinterpret_cast<const GridItem*>(h->lists + h->off_g), h->ctl, h->tmax, h->hist,
+             h->P.eps_pri, h->P.eps_dual, h->P.eps_z,
              h->P.beta_gamma, h->P.beta_omega, h->P.beta_max, h->P.max_outer,
              h->P.max_inner};
   hipLaunchKernelGGL(ctl_kernel, dim3(h->n_gl), dim3(kCtlBlock), 0, s, ca);
@@ -1330,7 +1363,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
     h->off_t = up16(sizeof(int) * (size_t)h->xcap);
     h->off_h = h->off_t + up16(sizeof(TileDesc) * (size_t)(nb + 1));
     h->off_g = h->off_h + up16(sizeof(TileDesc) * (size_t)(nb + 1));
-    const size_t bytes = h->off_g + up16(sizeof(int) * (size_t)n_grids);
+    const size_t bytes = h->off_g + up16(sizeof(GridItem) * (size_t)n_grids);
     HIP_TRY(D.alloc(&h->lists, bytes));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->stage), bytes, hipHostMallocDefault));
   }
@@ -1340,7 +1373,6 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   for (double** p : bus_d) HIP_TRY(D.alloc(p, nb));
   HIP_TRY(D.alloc(&h->ctl, n_grids));
   HIP_TRY(D.alloc(&h->tmax, 3 * (nb + 1)));
-  HIP_TRY(D.alloc(&h->grid_tile, n_grids + 1));
   HIP_TRY(D.alloc(&h->stats, kStats));
   HIP_TRY(D.alloc(&h->failures, n_grids));
   HIP_TRY(D.alloc(&h->pool, 3));
@@ -1584,12 +1616,11 @@ static int build_active(acopf_s* h) {
   if (nx > h->xcap) return fail(ACOPF_EDEVICE, "x-step block list overflow");
   TileDesc* tl = reinterpret_cast<TileDesc*>(h->stage + h->off_t);
   TileDesc* hl = reinterpret_cast<TileDesc*>(h->stage + h->off_h);
-  int* gl = reinterpret_cast<int*>(h->stage + h->off_g);
+  GridItem* gl = reinterpret_cast<GridItem*>(h->stage + h->off_g);
   int nt = 0, nh = 0, ngl = 0;
-  std::vector<int> grid_tile_h;
   for (int g = 0; g < h->G; ++g) {
     if (!act[g]) continue;
-    gl[ngl++] = g;
+    gl[ngl++] = GridItem{g, h->grid_tile_h[g], h->grid_tile_h[g + 1], 0};
   }
   for (int t = 0; t < h->n_tiles; ++t) {
     const TileDesc& D = h->tiles_h[t];
@@ -1605,7 +1636,8 @@ static int build_active(acopf_s* h) {
     HIP_TRY(hipMemcpyAsync(h->lists, h->stage, sizeof(int) * nx, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(h->lists + h->off_t, tl, sizeof(TileDesc) * nt, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(h->lists + h->off_h, hl, sizeof(TileDesc) * nh, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(h->lists + h->off_g, gl, sizeof(int) * ngl, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(h->lists + h->off_g, gl, sizeof(GridItem) * ngl, hipMemcpyHostToDevice,
+                         st));
   h->n_x = nx;
   h->n_t = nt;
   h->n_hl = nh;
@@ -1721,6 +1753,31 @@ static int start_impl(acopf_s* h, int grid, int mode, int fixed_iters) {
 
 // Iterate until some running grid finishes (stop_on_first) or all have
 // finished, or max_iters iterations ran. Returns the iterations issued.
+// Applies the outer multiplier steps still pending after a run (decided by
+// a grid's last iteration before it finished or the run stopped), so that
+// between calls no step is pending and lambda is what Algorithm 1 holds. The
+// control words were read after the run's last chunk.
+static int settle_outer(acopf_s* h) {
+  bool any = false;
+  for (int g = 0; g < h->G; ++g) {
+    const GridCtl& c = h->h_ctl[g];
+    if (!c.do_outer) continue;
+    const HostGrid& H = h->grids[g];
+    const int64_t c0 = 2 * h->ng + 4 * H.e0, c1 = 2 * h->ng + 4 * H.e1;
+    const int64_t n = 2 * H.ng + (c1 - c0);
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4 * (int64_t)h->n_cu);
+    hipLaunchKernelGGL(outer_step_kernel, dim3(blocks), dim3(256), 0, h->stream, h->ctl, g,
+                       h->ng, H.gen_off, H.gen_off + H.ng, c0, c1, c.beta_lam, h->P.lambda_max,
+                       h->z, h->lam);
+    any = true;
+  }
+  if (!any) return ACOPF_OK;
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (int g = 0; g < h->G; ++g) h->h_ctl[g].do_outer = 0;
+  return ACOPF_OK;
+}
+
 static int run_impl(acopf_s* h, int64_t max_iters, bool stop_on_first, int64_t* issued_out) {
   int64_t issued = 0;
   while (issued < max_iters) {
@@ -1748,7 +1805,7 @@ static int run_impl(acopf_s* h, int64_t max_iters, bool stop_on_first, int64_t* 
     if (stop_on_first && finished_one) break;
   }
   if (issued_out) *issued_out = issued;
-  return ACOPF_OK;
+  return settle_outer(h);
 }
 
 static int result_impl(acopf_s* h, int g, acopf_result* r) {
@@ -2393,7 +2450,7 @@ int acopf_get_timing(acopf_handle h, double* out5) {
   if (!h || !out5) return fail(ACOPF_EINVAL, "null argument");
   const double n = h->t_iters > 0 ? (double)h->t_iters : 1.0;
   for (int k = 0; k < kTimed; ++k) out5[k] = h->t_ms[k] / n;
-  out5[3] = 0.0;  // the outer multiplier step runs inside ctl_kernel
+  out5[3] = 0.0;  // the outer multiplier step runs inside the bus step
   out5[4] = (double)h->t_iters;
   return ACOPF_OK;
 }

@@ -104,6 +104,35 @@ def test_outer_steps_match_oracle():
         np.testing.assert_array_equal(s.history()[:, 4], orc.history()[:, 4])
 
 
+def test_outer_steps_across_chunks_and_calls():
+    """An outer step decided by an iteration's control is applied to lambda
+    by the next bus step; one decided by the last iteration of a chunk waits
+    for the next chunk, and one decided by the last iteration of a call is
+    applied before the call returns. With max_inner = 8 and 16 iterations per
+    chunk, outer steps fall on chunk ends (16, 32), and a run split after
+    iteration 24 (an outer step) equals one run of 40 bit for bit and the
+    oracle."""
+    note("parity c2: outer steps on chunk ends and call ends")
+    g = config_grid("c2_2kbus")
+    p = A.Params(max_inner=8)
+    orc = O.Oracle(g, oparams(p))
+    orc.solve(24)
+    with A.Solver(g, p) as s:
+        assert s.tuning()["chunk"] == 16
+        s.solve(A.COLD, 24)
+        compare(s, orc, label="c2 outer x24")
+        np.testing.assert_array_equal(s.history()[:, 5], orc.history()[:, 5])
+        orc.solve(16)
+        s.solve(A.CONTINUE, 16)
+        compare(s, orc, label="c2 outer x24+16")
+        np.testing.assert_array_equal(s.history()[:, 5], orc.history()[:, 5])
+        split = {k: s.get(k) for k in VECS}
+        s.solve(A.COLD, 40)
+        for k in VECS:
+            np.testing.assert_array_equal(s.get(k), split[k], err_msg=k)
+    assert orc.history()[-1, 5] == 4  # outer steps at 8, 16, 24 and 32 before the 40th
+
+
 def test_c1_200_iterations_objective():
     note("parity c1 200 iterations objective")
     g = config_grid("c1_30bus")
