@@ -1,30 +1,36 @@
 // Host runtime and the closed-form kernels of the two-level component ADMM
 // for ACOPF (Kim & Kim, PSCC 2022) on gfx950, behind the C ABI of acopf.h.
 //
-// One inner iteration of Algorithm 1 is three launches on one stream:
+// One inner iteration of Algorithm 1 is two launches on one stream, and a
+// chunk of iterations ends with a third:
 //   xstep_kernel    branch subproblems, eq. (branch), TRON + AL     lane/branch
-//                   and the generator closed form, eq. (qp-bound)   lane/gen
+//                   and the generator closed form, eq. (qp-bound);  lane/gen
+//                   in its first blocks, the previous iteration's   block/grid
+//                   control decision (tests, outer step, beta rule)
 //   bus_kernel      a pending outer multiplier step lambda <-      block/tile
 //                   proj(lambda + beta z), the bus closed form     of buses,
 //                   eq. (qp-bus), then z and y and the residual    lane/pair
 //                   maxima of every coupling it owns (tiles of a
 //                   bus too large for one block in a second
 //                   launch, only when there are such buses)
-//   ctl_kernel      termination tests, the outer step decision     block/grid
-//                   and the beta rule
+//   ctl_kernel      the decision of the chunk's last iteration      block/grid
 // The generator and branch steps read only the previous iteration's v, z, y
 // and so could run in any order; the bus step owns each coupling exactly once
 // (every coupling has one bus side), which makes the z and y updates and the
 // residual maxima a fused, race-free pass. Each bus tile writes its residual
-// maxima to a slot of its own and the control kernel takes the maximum over
-// a grid's tiles: exact and independent of order, with no atomics contending
-// on one address. An outer step decided at iteration t is applied by the
-// bus step of iteration t + 1 before it uses lambda (the branch step does
-// not read lambda); one still pending when the host regains control (the
-// grid finished, or the run stopped) is applied then. Kernels return at once
-// for grids that have finished, so a chunk of launches can overshoot
-// convergence harmlessly; the host reads the per-grid control words once per
-// chunk.
+// maxima to a slot of its own and the decision takes the maximum over a
+// grid's tiles: exact and independent of order, with no atomics contending
+// on one address. The decision of iteration t runs beside the branch solves
+// of iteration t + 1, which read their state from one of two buffers and
+// write the other: if it finishes the grid, those solves overwrite only the
+// older buffer, the bus step of t + 1 skips the grid, and the host moves the
+// grid's state to the first buffer after the chunk. An outer step decided at
+// iteration t is applied by the bus step of iteration t + 1 before it uses
+// lambda (the branch step does not read lambda); one still pending when the
+// host regains control (the grid finished, or the run stopped) is applied
+// then. Kernels return at once for grids that have finished, so a chunk of
+// launches can overshoot convergence harmlessly; the host reads the per-grid
+// control words once per chunk.
 //
 // Device layout (structure of arrays, FP64), chosen for the HBM-bound bus
 // step: every bus owns a contiguous range of generators and of branch ends,
@@ -55,7 +61,9 @@
 #include "device_common.h"
 
 using acopf_dev::BranchArgs;
+using acopf_dev::DecideArgs;
 using acopf_dev::GridCtl;
+using acopf_dev::GridItem;
 
 namespace {
 
@@ -454,127 +462,14 @@ __global__ __launch_bounds__(256) void record_kernel(int64_t ng, int64_t e0, int
   store_record_half(brec, erec[e], rec);
 }
 
-// A grid of a control launch: its index and the range [t0, t1) of its bus
-// tiles' residual slots.
-struct GridItem {
-  int g, t0, t1, pad;
-};
-
-struct CtlArgs {
-  const GridItem* items;  // the running grids, one block each
-  GridCtl* ctl;
-  const double* tmax;     // [n_tiles][3] residual maxima per bus tile
-  double* hist;  // [G][kHistCap][6]
-  double eps_pri, eps_dual, eps_z, beta_gamma, beta_omega, beta_max;
-  int max_outer, max_inner;
-};
-
-// Termination tests, outer step decision and beta rule of Algorithm 1 for
-// grid g, given its residual maxima; returns whether the outer step is due.
-__device__ int ctl_decide(const CtlArgs& A, int g, GridCtl& c, double rp, double rd, double rz) {
-  c.do_outer = 0;
-  c.r_pri = rp;
-  c.r_dual = rd;
-  c.r_z = rz;
-  if (c.inner_total < kHistCap) {
-    double* h = A.hist + ((int64_t)g * kHistCap + c.inner_total) * 6;
-    h[0] = rp;
-    h[1] = rd;
-    h[2] = rz;
-    h[3] = 0.0;
-    h[4] = c.beta;
-    h[5] = (double)c.outer;
-  }
-  c.inner_total += 1;
-  c.inner_in_outer += 1;
-  if (!isfinite(rp) || !isfinite(rd) || !isfinite(rz)) {
-    c.status = ACOPF_NUMERICAL;
-    c.done = 1;
-    return 0;
-  }
-  const bool inner_ok = rp <= A.eps_pri && rd <= A.eps_dual;
-  const bool fixed = c.fixed_mode != 0;
-  if (!fixed && inner_ok && rz <= A.eps_z) {
-    c.status = ACOPF_CONVERGED;
-    c.done = 1;
-    return 0;
-  }
-  if (inner_ok || c.inner_in_outer >= A.max_inner) {
-    c.do_outer = 1;
-    c.beta_lam = c.beta;
-    if (rz > A.beta_omega * c.znorm_prev) {
-      const double b = A.beta_gamma * c.beta;
-      c.beta = b < A.beta_max ? b : A.beta_max;
-    }
-    c.znorm_prev = rz;
-    c.outer += 1;
-    c.inner_in_outer = 0;
-    if (!fixed && c.outer >= A.max_outer) {
-      c.status = ACOPF_MAX_ITER;
-      c.done = 1;
-    }
-  }
-  if (fixed && c.inner_total >= c.fixed_target) {
-    c.status = ACOPF_MAX_ITER;
-    c.done = 1;
-  }
-  return c.do_outer;
-}
-
 // Control of Algorithm 1 per grid, one block of kCtlBlock lanes per running
-// grid: the residual maxima over the grid's bus tiles and the decisions
-// above. A grid that has finished stays as it is, with an outer step that
-// its last decision left pending (the host applies that one).
+// grid: the decision of decide_grid for x-step results in buffer cur. It
+// takes the last decision of a chunk (the decision blocks of the x-step take
+// the others), or every decision when the x-step runs without decision
+// blocks (the persistent kernel, and with counting on).
 constexpr int kCtlBlock = 256;
-__global__ __launch_bounds__(kCtlBlock) void ctl_kernel(CtlArgs A) {
-  const GridItem it = A.items[blockIdx.x];
-  const int g = it.g;
-  const int tid = threadIdx.x;
-  // The tile maxima and lane 0's copy of the control record are loaded
-  // together, so that their latencies overlap (a finished grid's maxima are
-  // read and ignored); each lane issues the loads of up to kU tiles before it
-  // combines them, so that one round covers kU kCtlBlock tiles.
-  GridCtl cc;
-  if (tid == 0) cc = A.ctl[g];
-  double rp = 0.0, rd = 0.0, rz = 0.0;
-  constexpr int kU = 8;
-  for (int t = it.t0 + tid; t < it.t1; t += kU * kCtlBlock) {
-    double m[kU][3];
-#pragma unroll
-    for (int k = 0; k < kU; ++k) {
-      const int tk = t + k * kCtlBlock;
-      const bool in = tk < it.t1;
-      m[k][0] = in ? A.tmax[3 * tk + 0] : 0.0;
-      m[k][1] = in ? A.tmax[3 * tk + 1] : 0.0;
-      m[k][2] = in ? A.tmax[3 * tk + 2] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < kU; ++k) {
-      rp = fmax(rp, m[k][0]);
-      rd = fmax(rd, m[k][1]);
-      rz = fmax(rz, m[k][2]);
-    }
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    rp = fmax(rp, __shfl_xor(rp, off, 64));
-    rd = fmax(rd, __shfl_xor(rd, off, 64));
-    rz = fmax(rz, __shfl_xor(rz, off, 64));
-  }
-  __shared__ double red[3][kCtlBlock / 64];
-  if ((tid & 63) == 0) {
-    red[0][tid >> 6] = rp;
-    red[1][tid >> 6] = rd;
-    red[2][tid >> 6] = rz;
-  }
-  __syncthreads();
-  if (tid != 0 || cc.done) return;
-  for (int w = 1; w < kCtlBlock / 64; ++w) {
-    rp = fmax(rp, red[0][w]);
-    rd = fmax(rd, red[1][w]);
-    rz = fmax(rz, red[2][w]);
-  }
-  ctl_decide(A, g, cc, rp, rd, rz);
-  A.ctl[g] = cc;
+__global__ __launch_bounds__(kCtlBlock) void ctl_kernel(DecideArgs A, int cur) {
+  acopf_dev::decide_grid(A, blockIdx.x, cur);
 }
 
 // An outer multiplier step of grid g (Sec. III-B) still pending when the
@@ -673,7 +568,7 @@ __global__ __launch_bounds__(256) void cold_kernel(ColdArgs A) {
 // Reset of the per-grid control words at the start of a solve of grid `only`
 // (all grids when only < 0).
 __global__ void ctl_start_kernel(GridCtl* ctl, int G, int only, int mode, int fixed,
-                                 double beta0, int* failures) {
+                                 double beta0, int* failures, int* failures_it) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G || (only >= 0 && g != only)) return;
   GridCtl& c = ctl[g];
@@ -688,10 +583,12 @@ __global__ void ctl_start_kernel(GridCtl* ctl, int G, int only, int mode, int fi
   c.status = ACOPF_MAX_ITER;
   c.done = 0;
   c.do_outer = 0;
-  c.numerical = 0;
+  c.cur = 0;
   c.fixed_mode = fixed > 0 ? 1 : 0;
   c.fixed_target = fixed > 0 ? c.inner_total + fixed : 0x7fffffff;
   failures[g] = 0;
+  failures_it[g] = 0;
+  failures_it[G + g] = 0;
 }
 
 // Marks every grid idle (done) without touching its state.
@@ -712,8 +609,9 @@ struct CopySegs {
   const double* src[kCopySegs];
   double* dst[kCopySegs];
   int64_t len[kCopySegs];
-  const GridCtl* csrc;
+  const GridCtl* csrc;  // with cdst: the control block, arriving marked idle
   GridCtl* cdst;
+  GridCtl* cur_clear;   // or: a control block whose state is now in buffer 0
 };
 __global__ __launch_bounds__(256) void copy_kernel(CopySegs C) {
   const int s = blockIdx.y;
@@ -731,10 +629,13 @@ __global__ __launch_bounds__(256) void copy_kernel(CopySegs C) {
        i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
   if (s == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
-    GridCtl c = *C.csrc;
-    c.done = 1;
-    c.do_outer = 0;
-    *C.cdst = c;
+    if (C.csrc) {
+      GridCtl c = *C.csrc;
+      c.done = 1;
+      c.do_outer = 0;
+      *C.cdst = c;
+    }
+    if (C.cur_clear) C.cur_clear->cur = 0;
   }
 }
 
@@ -826,6 +727,11 @@ struct acopf_s {
   unsigned long long* qual = nullptr;  // [6 G] quality maxima (lazy)
   double *u, *v, *z, *y, *lam, *bx, *ltil, *rtil;
   double* calpha;  // [nl] TRON Cauchy step length of each branch's last solve
+  // the second buffer of the x-step's results (u, branch state); between
+  // chunks every grid's state is in the first
+  double *u1 = nullptr, *bx1 = nullptr, *ltil1 = nullptr, *rtil1 = nullptr;
+  double* calpha1 = nullptr;
+  int* failures_it = nullptr;  // [2][G] branch failures of the results in each buffer
   double* brec = nullptr;  // [nl][16] branch records (v - z, y per coupling)
   int* erec = nullptr;     // [ne] record half of each branch end
   int *gptr, *eptr, *isref;
@@ -842,7 +748,8 @@ struct acopf_s {
   int n_x = 0, n_t = 0, n_hl = 0, n_gl = 0;
   acopf_dev::XLayout xlay{};         // x-step block layout (kernel arguments)
   const int* xlist = nullptr;        // x-step blocks to run (null: all of them)
-  BranchArgs xba{};                  // the x-step's other argument, as captured
+  DecideArgs* dec = nullptr;         // device copy of the decision arguments
+  BranchArgs xba[2] = {};            // the x-step's other argument at even and odd positions
   std::vector<char> active_for;      // the running set the lists describe
   bool lists_dirty = true;
   // kernel nodes of the captured chunk, with the list each one's grid size
@@ -884,7 +791,9 @@ struct acopf_s {
 
 namespace {
 
-BranchArgs branch_args(const acopf_s* h) {
+// The x-step's arguments, reading the branch state from buffer `in` and
+// writing u and the branch state to buffer `out` (0 or 1).
+BranchArgs branch_args(const acopf_s* h, int in, int out) {
   BranchArgs A{};
   A.nl = h->nl;
   A.ne = h->ne;
@@ -902,11 +811,15 @@ BranchArgs branch_args(const acopf_s* h) {
   A.z = h->z;
   A.y = h->y;
   A.brec = h->brec;
-  A.u = h->u;
-  A.bx = h->bx;
-  A.ltil = h->ltil;
-  A.rtil = h->rtil;
-  A.calpha = h->calpha;
+  A.u = out ? h->u1 : h->u;
+  A.bx_in = in ? h->bx1 : h->bx;
+  A.ltil_in = in ? h->ltil1 : h->ltil;
+  A.rtil_in = in ? h->rtil1 : h->rtil;
+  A.calpha_in = in ? h->calpha1 : h->calpha;
+  A.bx = out ? h->bx1 : h->bx;
+  A.ltil = out ? h->ltil1 : h->ltil;
+  A.rtil = out ? h->rtil1 : h->rtil;
+  A.calpha = out ? h->calpha1 : h->calpha;
   A.rho_pq = h->P.rho_pq;
   A.rho_va = h->P.rho_va;
   A.tron_gtol = h->P.tron_gtol;
@@ -917,7 +830,7 @@ BranchArgs branch_args(const acopf_s* h) {
   A.al_rho_max = h->P.al_rho_max;
   A.tron_maxit = h->P.tron_maxit;
   A.al_maxit = h->P.al_maxit;
-  A.failures = h->failures;
+  A.failures = h->failures_it + (size_t)out * h->G;
   A.stats = h->stats;
   A.pool = h->pool;
   A.ng = h->ng;
@@ -981,26 +894,50 @@ int build_tiles(acopf_s* h, int block) {
   return ACOPF_OK;
 }
 
-// Launch one inner iteration; with profiling, events bracket each launch.
-void launch_iteration(acopf_s* h, int slot) {
+// The control decision's arguments (the device copy is h->dec).
+DecideArgs decide_args(const acopf_s* h) {
+  return DecideArgs{h->ctl, h->tmax, reinterpret_cast<const GridItem*>(h->lists + h->off_g),
+                    h->hist, h->failures, h->failures_it, h->P.eps_pri, h->P.eps_dual,
+                    h->P.eps_z, h->P.beta_gamma, h->P.beta_omega, h->P.beta_max,
+                    h->P.max_outer, h->P.max_inner, kHistCap, h->G};
+}
+
+// Whether the x-step takes the control decisions inside a chunk (its
+// decision blocks); otherwise the control kernel takes every one. Counting
+// mode keeps the control kernel, so that no branch solve past a grid's
+// finish enters the counters.
+bool fused_control(const acopf_s* h) { return h->tune.xstep_waves == 0 && !h->count_stats; }
+
+// Launch inner iteration `slot` of a chunk (its position); with profiling,
+// events bracket each launch. The lane-per-branch x-step at position q reads
+// the branch state from buffer q & 1 and writes its results to the other;
+// with fused control it takes the previous iteration's decision in its first
+// blocks at positions >= 1, and the control kernel takes the chunk's last one
+// (`last`). The persistent x-step works in place (buffer 0), with the control
+// kernel after every iteration.
+void launch_iteration(acopf_s* h, int slot, bool last) {
   hipStream_t s = h->stream;
   hipEvent_t* E = h->profile ? &h->ev[(size_t)slot * kEvPerIter] : nullptr;
   auto mark = [&](int k) {
     if (E) (void)hipEventRecord(E[k], s);
   };
-  BranchArgs ba = branch_args(h);
+  const bool persistent = h->tune.xstep_waves > 0, fused = fused_control(h);
+  const int in = persistent ? 0 : (slot & 1), out = persistent ? 0 : ((slot + 1) & 1);
+  BranchArgs ba = branch_args(h, in, out);
   mark(0);
-  if (h->tune.xstep_waves > 0)
+  if (persistent)
     acopf_dev::launch_xstep_persistent(ba, h->n6, h->tune.xstep_waves * 4 * h->n_cu,
                                        h->count_stats, s);
   else
-    acopf_dev::launch_xstep(ba, h->xlay, h->xlist, h->n_x, h->tune.xstep_block, h->count_stats,
-                            s);
+    acopf_dev::launch_xstep(ba, h->xlay, h->xlist, h->n_x, h->dec,
+                            fused && slot > 0 ? h->n_gl : 0, slot, h->tune.xstep_block,
+                            h->count_stats, s);
   mark(1);
   BusArgs bu{h->nb, h->ng, h->ne, reinterpret_cast<const TileDesc*>(h->lists + h->off_t),
              reinterpret_cast<const TileDesc*>(h->lists + h->off_h), h->bus_grid, h->ctl,
-             h->gptr, h->eptr, h->pd, h->qd, h->gs, h->bs, h->isref, h->u, h->lam, h->v, h->z,
-             h->y, h->P.rho_pq, h->P.rho_va, h->tmax, h->erec, h->brec, h->P.lambda_max};
+             h->gptr, h->eptr, h->pd, h->qd, h->gs, h->bs, h->isref, out ? h->u1 : h->u, h->lam,
+             h->v, h->z, h->y, h->P.rho_pq, h->P.rho_va, h->tmax, h->erec, h->brec,
+             h->P.lambda_max};
   const int bb = h->tile_block;
   hipLaunchKernelGGL(bus_kernel<false>, dim3(h->n_t), dim3(bb), bus_lds_bytes(h->tile_block), s,
                      bu);
@@ -1008,11 +945,8 @@ void launch_iteration(acopf_s* h, int slot) {
     hipLaunchKernelGGL(bus_kernel<true>, dim3(h->n_hl), dim3(bb), bus_lds_bytes(h->tile_block),
                        s, bu);
   mark(2);
-  CtlArgs ca{reinterpret_cast<const GridItem*>(h->lists + h->off_g), h->ctl, h->tmax, h->hist,
-             h->P.eps_pri, h->P.eps_dual, h->P.eps_z,
-             h->P.beta_gamma, h->P.beta_omega, h->P.beta_max, h->P.max_outer,
-             h->P.max_inner};
-  hipLaunchKernelGGL(ctl_kernel, dim3(h->n_gl), dim3(kCtlBlock), 0, s, ca);
+  if (last || !fused)
+    hipLaunchKernelGGL(ctl_kernel, dim3(h->n_gl), dim3(kCtlBlock), 0, s, decide_args(h), out);
   mark(3);
 }
 
@@ -1351,8 +1285,12 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(D.alloc(&h->brec, 16 * nl));
   HIP_TRY(D.alloc(&h->erec, 2 * nl));
   HIP_TRY(D.alloc(&h->ltil, 2 * nl));
-  double** cp_d[] = {&h->u, &h->v, &h->z, &h->y, &h->lam};
+  double** cp_d[] = {&h->u, &h->v, &h->z, &h->y, &h->lam, &h->u1};
   for (double** p : cp_d) HIP_TRY(D.alloc(p, m));
+  HIP_TRY(D.alloc(&h->bx1, 6 * nl));
+  HIP_TRY(D.alloc(&h->ltil1, 2 * nl));
+  HIP_TRY(D.alloc(&h->rtil1, nl));
+  HIP_TRY(D.alloc(&h->calpha1, nl));
   HIP_TRY(D.alloc(&h->gptr, nb + 1));
   {
     // work lists: x-step blocks (at least 64 lanes per block, plus a partial
@@ -1375,6 +1313,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(D.alloc(&h->tmax, 3 * (nb + 1)));
   HIP_TRY(D.alloc(&h->stats, kStats));
   HIP_TRY(D.alloc(&h->failures, n_grids));
+  HIP_TRY(D.alloc(&h->failures_it, 2 * (size_t)n_grids));
   HIP_TRY(D.alloc(&h->pool, 3));
   HIP_TRY(D.alloc(&h->hist, (size_t)n_grids * kHistCap * 6));
   HIP_TRY(D.alloc(&h->gen_off_d, n_grids + 1));
@@ -1434,6 +1373,11 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(hipMemsetAsync(h->pool, 0, sizeof(unsigned) * 3, st));
   HIP_TRY(hipMemsetAsync(h->hist, 0, sizeof(double) * (size_t)n_grids * kHistCap * 6, st));
   HIP_TRY(hipMemsetAsync(h->ctl, 0, sizeof(GridCtl) * n_grids, st));
+  HIP_TRY(D.alloc(&h->dec, 1));
+  {
+    const DecideArgs dv = decide_args(h);
+    HIP_TRY(hipMemcpyAsync(h->dec, &dv, sizeof(dv), hipMemcpyHostToDevice, st));
+  }
   HIP_TRY(hipStreamSynchronize(st));
   return build_tiles(h, h->tune.bus_block);
 }
@@ -1484,7 +1428,8 @@ int acopf_create(const acopf_grid* grids, int32_t n_grids, const acopf_params* p
               h->P.al_rho0};
   hipLaunchKernelGGL(cold_kernel, dim3(blocks_for(h->ng + h->nl, 256)), dim3(256), 0, h->stream, ca);
   hipLaunchKernelGGL(ctl_start_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, h->stream,
-                     h->ctl, h->G, -1, (int)ACOPF_COLD, 0, h->P.beta0, h->failures);
+                     h->ctl, h->G, -1, (int)ACOPF_COLD, 0, h->P.beta0, h->failures,
+                     h->failures_it);
   hipLaunchKernelGGL(ctl_idle_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, h->stream,
                      h->ctl, h->G);
   h->t_start.assign(h->G, 0.0);
@@ -1644,13 +1589,24 @@ static int build_active(acopf_s* h) {
   h->n_gl = ngl;
   h->active_for = act;
   h->lists_dirty = false;
-  h->xba = branch_args(h);
-  void* xargs[7] = {&h->xba, &L.n6, &L.bg, &L.b6, &L.b4, &L.k4, &h->xlist};
+  h->xba[0] = branch_args(h, 0, 1);
+  h->xba[1] = branch_args(h, 1, 0);
   for (size_t i = 0; h->graph && i < h->gnode.size(); ++i) {
     if (h->grole[i] < 0) continue;
     hipKernelNodeParams p = h->gparam[i];
     p.gridDim = dim3(role_blocks(h, h->grole[i]));
-    if (h->grole[i] == 0) p.kernelParams = xargs;
+    // an x-step node keeps its chunk position; its decision blocks follow
+    // the running grids
+    int pos = 0, n_dec = 0;
+    void* xargs[10] = {nullptr, &L.n6, &L.bg, &L.b6, &L.b4, &L.k4, &h->xlist, &h->dec, &n_dec,
+                       &pos};
+    if (h->grole[i] == 0) {
+      pos = *static_cast<const int*>(h->gparam[i].kernelParams[9]);
+      n_dec = pos > 0 && fused_control(h) ? h->n_gl : 0;
+      xargs[0] = &h->xba[pos & 1];
+      p.gridDim = dim3((unsigned)(n_dec + h->n_x));
+      p.kernelParams = xargs;
+    }
     HIP_TRY(hipGraphExecKernelNodeSetParams(h->graph, h->gnode[i], &p));
   }
   return ACOPF_OK;
@@ -1672,7 +1628,7 @@ static int ensure_graph(acopf_s* h) {
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    for (int c = 0; c < k; ++c) launch_iteration(h, c);
+    for (int c = 0; c < k; ++c) launch_iteration(h, c, c == k - 1);
     e = hipStreamEndCapture(h->stream, &g);
   }
   h->profile = prof;
@@ -1718,7 +1674,7 @@ static int launch_chunk(acopf_s* h, int k) {
     HIP_TRY(hipGraphLaunch(h->graph, h->stream));
     return ACOPF_OK;
   }
-  for (int c = 0; c < k; ++c) launch_iteration(h, c);
+  for (int c = 0; c < k; ++c) launch_iteration(h, c, c == k - 1);
   HIP_TRY(hipGetLastError());
   return ACOPF_OK;
 }
@@ -1739,7 +1695,7 @@ static int start_impl(acopf_s* h, int grid, int mode, int fixed_iters) {
     hipLaunchKernelGGL(record_kernel, dim3(blocks_for(e1 - e0, 256)), dim3(256), 0, st, h->ng,
                        e0, e1, h->erec, h->v, h->z, h->y, h->brec);
   hipLaunchKernelGGL(ctl_start_kernel, dim3(blocks_for(h->G, 64)), dim3(64), 0, st, h->ctl,
-                     h->G, grid, mode, fixed_iters, h->P.beta0, h->failures);
+                     h->G, grid, mode, fixed_iters, h->P.beta0, h->failures, h->failures_it);
   HIP_TRY(hipGetLastError());
   const double t = now_s();
   for (int g = 0; g < h->G; ++g)
@@ -1778,6 +1734,46 @@ static int settle_outer(acopf_s* h) {
   return ACOPF_OK;
 }
 
+// Moves the x-step results (u and the branch state) of every grid whose last
+// accepted iteration wrote the second buffer (a grid that finished at an odd
+// chunk position, or every running grid after a chunk of odd length) into
+// the first, where the next chunk and every other part of the library read
+// them. The control words were read after the chunk.
+static int settle_buffers(acopf_s* h) {
+  for (int g = 0; g < h->G; ++g) {
+    if (!h->h_ctl[g].cur) continue;
+    const HostGrid& H = h->grids[g];
+    CopySegs C{};
+    int64_t longest = 0;
+    auto cp = [&](const double* src, double* dst, int64_t from, int64_t n) {
+      if (n <= 0) return;
+      C.src[C.n] = src + from;
+      C.dst[C.n] = dst + from;
+      C.len[C.n] = n;
+      longest = std::max(longest, n);
+      ++C.n;
+    };
+    const int64_t ng = h->ng, nl = h->nl;
+    cp(h->u1, h->u, H.gen_off, H.ng);
+    cp(h->u1, h->u, ng + H.gen_off, H.ng);
+    cp(h->u1, h->u, 2 * ng + 4 * H.e0, 4 * (H.e1 - H.e0));
+    for (int r = 0; r < 6; ++r) {  // the slacks (rows 4, 5) of rated branches only
+      cp(h->bx1, h->bx, r * nl + H.r6b, H.r6e - H.r6b);
+      if (r < 4) cp(h->bx1, h->bx, r * nl + H.r4b, H.r4e - H.r4b);
+    }
+    for (int r = 0; r < 2; ++r) cp(h->ltil1, h->ltil, r * nl + H.r6b, H.r6e - H.r6b);
+    cp(h->rtil1, h->rtil, H.r6b, H.r6e - H.r6b);
+    cp(h->calpha1, h->calpha, H.r6b, H.r6e - H.r6b);
+    cp(h->calpha1, h->calpha, H.r4b, H.r4e - H.r4b);
+    C.cur_clear = h->ctl + g;
+    const int bx = (int)std::min<int64_t>(256, std::max<int64_t>(1, (longest + 255) / 256));
+    hipLaunchKernelGGL(copy_kernel, dim3(bx, std::max(1, C.n)), dim3(256), 0, h->stream, C);
+    HIP_TRY(hipGetLastError());
+    h->h_ctl[g].cur = 0;
+  }
+  return ACOPF_OK;
+}
+
 static int run_impl(acopf_s* h, int64_t max_iters, bool stop_on_first, int64_t* issued_out) {
   int64_t issued = 0;
   while (issued < max_iters) {
@@ -1793,6 +1789,8 @@ static int run_impl(acopf_s* h, int64_t max_iters, bool stop_on_first, int64_t* 
     HIP_TRY(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(GridCtl) * h->G, hipMemcpyDeviceToHost,
                            h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
+    rc = settle_buffers(h);
+    if (rc) return rc;
     if (h->profile) accumulate_timing(h, k);
     const double t = now_s();
     bool finished_one = false;

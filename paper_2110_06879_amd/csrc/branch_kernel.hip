@@ -1116,15 +1116,15 @@ __device__ bool solve_branch(const BranchArgs& A, int64_t l, Cnt& cnt) {
     B.rva = A.rho_va;
     double x[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) x[i] = A.bx[i * nl + l];
+    for (int i = 0; i < N; ++i) x[i] = A.bx_in[i * nl + l];
     B.lt0 = 0.0;
     B.lt1 = 0.0;
     B.rt = 0.0;
-    double alphac = A.calpha[l];
+    double alphac = A.calpha_in[l];
     if (N == 6) {
-      B.lt0 = A.ltil[l];
-      B.lt1 = A.ltil[nl + l];
-      B.rt = A.rtil[l];
+      B.lt0 = A.ltil_in[l];
+      B.lt1 = A.ltil_in[nl + l];
+      B.rt = A.rtil_in[l];
     }
     if (A.ctl[grid].done != 0) return false;
     int failures = 0;
@@ -1219,14 +1219,14 @@ __device__ inline void load_branch(const BranchArgs& A, int64_t l, BranchIn<N>& 
   B.rpq = A.rho_pq;
   B.rva = A.rho_va;
 #pragma unroll
-  for (int i = 0; i < N; ++i) x[i] = A.bx[i * nl + l];
+  for (int i = 0; i < N; ++i) x[i] = A.bx_in[i * nl + l];
   B.lt0 = 0.0;
   B.lt1 = 0.0;
   B.rt = 0.0;
   if (N == 6) {
-    B.lt0 = A.ltil[l];
-    B.lt1 = A.ltil[nl + l];
-    B.rt = A.rtil[l];
+    B.lt0 = A.ltil_in[l];
+    B.lt1 = A.ltil_in[nl + l];
+    B.rt = A.rtil_in[l];
   }
 }
 
@@ -1265,7 +1265,7 @@ __device__ void run_pool(const BranchArgs& A, int64_t begin, int64_t end, unsign
           grid = A.br_grid[l];
           if (A.ctl[grid].done == 0) {
             load_branch<N>(A, l, B, lo, hi, S.x);
-            S.alphac = A.calpha[l];
+            S.alphac = A.calpha_in[l];
             failures = 0;
             t_al = 0;
             cprev = 1.0 / 0.0;
@@ -1400,14 +1400,24 @@ void launch_xstep_persistent(const BranchArgs& A, int64_t n6, int blocks, bool s
 // branch wavefronts leave free instead of delaying some of those wavefronts.
 // When only some grids run, the launch has one block per layout block that
 // touches them (vblock); lanes on branches of finished grids return at once.
+// At chunk positions pos >= 1 the first n_dec blocks take the previous
+// iteration's control decision of the running grids while the others solve
+// (the state is double-buffered, so that branch solves that run past a
+// grid's finish overwrite only the older buffer).
 // kStats: as for the persistent kernel.
 template <bool kStats>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ACOPF_XSTEP_WAVES_PER_EU)))
 void xstep_kernel(BranchArgs A, int64_t n6, int bg, int b6, int b4, int k4,
-                  const int* __restrict__ vblock) {
+                  const int* __restrict__ vblock, const DecideArgs* __restrict__ dec, int n_dec,
+                  int pos) {
+  if ((int)blockIdx.x < n_dec) {  // the previous iteration's decision for one grid
+    decide_grid(*dec, blockIdx.x, pos & 1);
+    return;
+  }
   CountersT<kStats> cnt = {};
   uint32_t solves = 0;
-  const int b = vblock ? vblock[blockIdx.x] : (int)blockIdx.x;
+  const int k = (int)blockIdx.x - n_dec;
+  const int b = vblock ? vblock[k] : k;
   const int bs = blockDim.x;
   if (b >= b6 + b4) {
     const int64_t g = (int64_t)(b - b6 - b4) * bs + threadIdx.x;
@@ -1445,14 +1455,15 @@ void xstep_kernel(BranchArgs A, int64_t n6, int bg, int b6, int b4, int k4,
 }
 
 void launch_xstep(const BranchArgs& A, const XLayout& L, const int* vblock, int n_blocks,
-                  int block, bool stats, hipStream_t s) {
-  if (n_blocks <= 0) return;
+                  const DecideArgs* dec, int n_dec, int pos, int block, bool stats,
+                  hipStream_t s) {
+  if (n_blocks + n_dec <= 0) return;
   if (stats)
-    hipLaunchKernelGGL(xstep_kernel<true>, dim3(n_blocks), dim3(block), 0, s, A, L.n6, L.bg, L.b6,
-                       L.b4, L.k4, vblock);
+    hipLaunchKernelGGL(xstep_kernel<true>, dim3(n_dec + n_blocks), dim3(block), 0, s, A, L.n6,
+                       L.bg, L.b6, L.b4, L.k4, vblock, dec, n_dec, pos);
   else
-    hipLaunchKernelGGL(xstep_kernel<false>, dim3(n_blocks), dim3(block), 0, s, A, L.n6, L.bg,
-                       L.b6, L.b4, L.k4, vblock);
+    hipLaunchKernelGGL(xstep_kernel<false>, dim3(n_dec + n_blocks), dim3(block), 0, s, A, L.n6,
+                       L.bg, L.b6, L.b4, L.k4, vblock, dec, n_dec, pos);
 }
 
 bool is_xstep_kernel(const void* f) {

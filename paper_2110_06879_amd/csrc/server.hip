@@ -46,13 +46,15 @@ double now_seconds() {
 }
 
 // Device footprint of one grid instance in the library's layout: the coupling
-// vectors, the branch data, state and records, the generator and bus arrays,
-// their indices and the residual history.
+// vectors, the branch data, state and records, the second buffer of the
+// branch step's results, the generator and bus arrays, their indices and the
+// residual history.
 double instance_bytes(const acopf_grid& g) {
   const double nb = g.n_bus, ng = g.n_gen, nl = g.n_branch;
   const double m = 2 * ng + 8 * nl;
-  const double doubles = 5 * m + 9 * nl + 8 * nl + 5 * nl + 16 * nl + 9 * ng + 6 * nb;
-  const double ints = 2 * nl + nl + 2 * nl + 2 * nl + ng + 3 * nb + 2;
+  const double doubles =
+      5 * m + 9 * nl + 8 * nl + 5 * nl + 16 * nl + (m + 10 * nl) + 9 * ng + 6 * nb;
+  const double ints = 2 * nl + nl + 2 * nl + 2 * nl + ng + 3 * nb + 4;
   return 8 * doubles + 4 * ints + 6.0 * 8 * (1 << 15);
 }
 
