@@ -70,6 +70,7 @@ def serve(duration: float, rate: float, with_70k: bool, baseline: bool,
     slots = srv.slots_per_grid
     srv.close()
     out.pop("done")
+    print(f"continuous batching: {len(reqs)} requests served", file=sys.stderr, flush=True)
     res = {"experiment": "served", "grids": len(grids),
            "buses": [g.n_bus for g in grids], "rate_per_s": rate, "duration_s": duration,
            "slots_per_grid": slots, "tuning": tuning, "continuous_batching": out}
@@ -77,6 +78,7 @@ def serve(duration: float, rate: float, with_70k: bool, baseline: bool,
         reqs2 = S.poisson_requests(grids, rate, duration)
         b = S.serve_one_at_a_time(grids, reqs2, realtime=True)
         res["one_request_at_a_time"] = b
+        print(f"one at a time: {len(reqs2)} requests served", file=sys.stderr, flush=True)
     return res
 
 
