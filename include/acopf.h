@@ -300,13 +300,15 @@ int acopf_set_counting(acopf_handle h, int32_t on);
  * Synchronous on the handle's stream. Errors: EINVAL, EDEVICE. */
 int acopf_quality_noalloc(acopf_handle h, int32_t grid, double* out6);
 
-/* Average device time (ms) per launch over every iteration run with
- * profiling on since the handle was created: out[0] x-step (generators and
- * branches), out[1] bus/z/y/residual step (which also applies an outer
- * multiplier step that the previous iteration decided), out[2] control
- * (tests, outer step decision, beta rule), out[3] = 0 (kept for layout: the
- * outer step has no launch of its own); out[4] = number of iterations timed.
- * Errors: EINVAL. */
+/* Average device time (ms) per iteration over every iteration run with
+ * profiling on since the handle was created: out[0] x-step launch
+ * (generators, branches, and from a chunk's second iteration on the previous
+ * iteration's control decision), out[1] bus/z/y/residual step (which also
+ * applies an outer multiplier step that the previous iteration decided),
+ * out[2] control kernel (it runs after a chunk's last iteration, or after
+ * every iteration with counting on or the persistent x-step), out[3] = 0
+ * (kept for layout: the outer step has no launch of its own); out[4] =
+ * number of iterations timed. Errors: EINVAL. */
 int acopf_get_timing(acopf_handle h, double* out5);
 
 /* Free everything the handle owns. NULL is a no-op. */

@@ -786,6 +786,7 @@ struct acopf_s {
   std::vector<void*> snap;             // device snapshot buffers (lazy)
   std::vector<hipEvent_t> ev;
   double t_ms[kTimed] = {0, 0, 0};
+  bool ev_ctl[kMaxChunk] = {};  // a control kernel ran in the profiled slot
   int64_t t_iters = 0;
 };
 
@@ -945,9 +946,11 @@ void launch_iteration(acopf_s* h, int slot, bool last) {
     hipLaunchKernelGGL(bus_kernel<true>, dim3(h->n_hl), dim3(bb), bus_lds_bytes(h->tile_block),
                        s, bu);
   mark(2);
-  if (last || !fused)
+  const bool ctl = last || !fused;
+  if (ctl)
     hipLaunchKernelGGL(ctl_kernel, dim3(h->n_gl), dim3(kCtlBlock), 0, s, decide_args(h), out);
   mark(3);
+  if (E) h->ev_ctl[slot] = ctl;
 }
 
 int validate_grid(const acopf_grid& g, int idx) {
@@ -1458,6 +1461,7 @@ static void accumulate_timing(acopf_s* h, int used) {
   for (int s = 0; s < used; ++s) {
     hipEvent_t* E = &h->ev[(size_t)s * kEvPerIter];
     for (int k = 0; k < kTimed; ++k) {
+      if (k == 2 && !h->ev_ctl[s]) continue;  // no control kernel after this iteration
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, E[k], E[k + 1]) == hipSuccess) h->t_ms[k] += ms;
     }
