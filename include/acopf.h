@@ -165,6 +165,14 @@ typedef struct {
                           solved one after another by each lane, 1..8; 0:
                           automatic, the fewest for which every branch
                           wavefront fits the device's SIMDs at once        */
+  int32_t lanes;       /* launch lanes, 1..4 (at most the handle's grids;
+                          more are reduced to that): the grids are split
+                          into this many groups of about equal branch
+                          count, each launched on a stream of its own, so
+                          that one group's issue-bound branch step overlaps
+                          another's memory-bound bus step (same results).
+                          Default: 2 for a handle of several grids, else 1;
+                          the persistent branch kernel runs as one lane   */
 } acopf_tuning;
 
 typedef struct acopf_s* acopf_handle;
@@ -234,7 +242,9 @@ int acopf_snapshot(acopf_handle h, int32_t what);
  * Candidates: x-step {lane per branch at xstep_block 64, 128, 256 with
  * xstep_per_lane automatic or 1; persistent at xstep_waves 1, 2} x
  * bus_block {128, 256, 512, 1024} x
- * chunk {8, 16, 32}, graphs on. Errors: EINVAL, ENOMEM, EDEVICE. */
+ * chunk {8, 16, 32}, graphs on, at the current lanes; then lanes {1, 2, 4}
+ * (up to the number of grids) for the best of those. Errors: EINVAL,
+ * ENOMEM, EDEVICE. */
 int acopf_set_tuning(acopf_handle h, const acopf_tuning* t);
 int acopf_get_tuning(acopf_handle h, acopf_tuning* t);
 int acopf_autotune(acopf_handle h, int32_t iters, acopf_tuning* out);

@@ -76,7 +76,7 @@ class _Params(C.Structure):
 class _Tuning(C.Structure):
     _fields_ = [("xstep_block", C.c_int32), ("bus_block", C.c_int32),
                 ("chunk", C.c_int32), ("use_graph", C.c_int32), ("xstep_waves", C.c_int32),
-                ("xstep_per_lane", C.c_int32)]
+                ("xstep_per_lane", C.c_int32), ("lanes", C.c_int32)]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

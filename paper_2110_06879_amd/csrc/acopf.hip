@@ -87,6 +87,7 @@ constexpr int kEvPerIter = 4;   // events per profiled iteration
 constexpr int kTimed = 3;       // kernels timed per iteration (x-step, bus, ctl)
 constexpr int kChunk = 16;      // iterations between control readbacks (default)
 constexpr int kMaxChunk = 64;   // largest chunk acopf_set_tuning accepts
+constexpr int kMaxLanes = 4;    // largest number of launch lanes
 
 // Device-resident scratch of acopf_quality_noalloc: 2^20 eight-byte words
 // (8 MiB) per device, held until the process ends. Host code never uses the
@@ -706,6 +707,37 @@ namespace acopf_dev {
 int report_error(int code, const char* msg) { return fail(code, msg); }
 }  // namespace acopf_dev
 
+// A launch lane: a subset of the handle's grids with its own stream, work
+// lists and captured chunk. The chunks of all lanes are launched back to back
+// and run concurrently, so that the issue-bound x-step of one lane overlaps
+// the memory-bound bus step of another; the grids of different lanes share
+// no data, so the results are those of one launch for all of them.
+struct Lane {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipEvent_t end = nullptr;          // end of the lane's chunk, for the handle's stream
+  // Work lists of the lane's grids that run: x-step items, bus tiles, hub
+  // tiles and grid items, in one device block filled from a pinned copy.
+  char* lists = nullptr;
+  char* stage = nullptr;
+  int n_x = 0, n_t = 0, n_hl = 0, n_gl = 0;
+  acopf_dev::XLayout xlay{};         // x-step block layout (kernel arguments)
+  const int* xlist = nullptr;        // x-step blocks to run (null: all of them)
+  DecideArgs* dec = nullptr;         // device copy of the decision arguments
+  unsigned* pool = nullptr;          // persistent x-step pool counters [3]
+  BranchArgs xba[2] = {};            // the x-step's other argument at even and odd positions
+  std::vector<char> active_for;      // the running set the lists describe
+  bool lists_dirty = true;
+  // the captured chunk and its kernel nodes, with the list each one's grid
+  // size follows (0 x-step, 1 bus tiles, 2 hub tiles, 3 grids, -1 fixed)
+  hipGraph_t gtmpl = nullptr;
+  hipGraphExec_t graph = nullptr;
+  int graph_chunk = 0;
+  std::vector<hipGraphNode_t> gnode;
+  std::vector<int> grole;
+  std::vector<hipKernelNodeParams> gparam;
+};
+
 struct acopf_s {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -739,25 +771,14 @@ struct acopf_s {
   std::vector<TileDesc> tiles_h;     // every bus tile of the handle
   std::vector<char> tile_hub;        // tile with more pairs than lanes
   int n_hub = 0;                     // hub tiles of the handle
-  // Work lists of the grids that run: x-step items, bus tiles, hub tiles and
-  // grids, in one device block filled from a pinned host copy.
-  char* lists = nullptr;
-  char* stage = nullptr;
-  size_t off_t = 0, off_h = 0, off_g = 0;
+  // layout of a lane's work lists (byte offsets of the tile, hub and grid
+  // lists; room for xcap x-step items), the same for every lane
+  size_t off_t = 0, off_h = 0, off_g = 0, list_bytes = 0;
   int64_t xcap = 0;
-  int n_x = 0, n_t = 0, n_hl = 0, n_gl = 0;
-  acopf_dev::XLayout xlay{};         // x-step block layout (kernel arguments)
-  const int* xlist = nullptr;        // x-step blocks to run (null: all of them)
-  DecideArgs* dec = nullptr;         // device copy of the decision arguments
-  BranchArgs xba[2] = {};            // the x-step's other argument at even and odd positions
-  std::vector<char> active_for;      // the running set the lists describe
-  bool lists_dirty = true;
-  // kernel nodes of the captured chunk, with the list each one's grid size
-  // follows (0 x-step, 1 bus tiles, 2 hub tiles, 3 grids, -1 fixed)
-  hipGraph_t gtmpl = nullptr;
-  std::vector<hipGraphNode_t> gnode;
-  std::vector<int> grole;
-  std::vector<hipKernelNodeParams> gparam;
+  std::vector<Lane> lanes;           // tune.lanes of them; lane 0 runs on `stream`
+  std::vector<int> lane_of;          // [G] lane of each grid
+  int* lane_of_d = nullptr;          // its device copy
+  hipEvent_t join = nullptr;         // orders the lanes after work on `stream`
   int n_tiles = 0, tile_block = 0;
   double *pd, *qd, *gs, *bs;
   double *vmin_b, *vmax_b;  // [nb] voltage limits (solution quality)
@@ -767,7 +788,6 @@ struct acopf_s {
   double* tmax;          // [nb + 1][3] residual maxima per bus tile
   std::vector<int> grid_tile_h;  // [G + 1] tile range of each grid
   int* failures;
-  unsigned* pool;  // persistent x-step pool counters
   int n_cu = 0;
   double* hist;
   int64_t* gen_off_d;
@@ -776,9 +796,7 @@ struct acopf_s {
   bool solved = false;
   bool profile = false;
   bool count_stats = false;  // branch kernels count flops and events (slower)
-  acopf_tuning tune{64, 256, kChunk, 1, 0, 0};
-  hipGraphExec_t graph = nullptr;
-  int graph_chunk = 0;
+  acopf_tuning tune{64, 256, kChunk, 1, 0, 0, 1};
   std::vector<double> t_start;         // host clock at each grid's start
   std::vector<double> t_end;           // host clock when it finished
   std::vector<char> running;           // started and not yet seen finished
@@ -786,21 +804,23 @@ struct acopf_s {
   std::vector<void*> snap;             // device snapshot buffers (lazy)
   std::vector<hipEvent_t> ev;
   double t_ms[kTimed] = {0, 0, 0};
-  bool ev_ctl[kMaxChunk] = {};  // a control kernel ran in the profiled slot
+  bool ev_ctl[kMaxLanes][kMaxChunk] = {};  // a control kernel ran in the profiled slot
   int64_t t_iters = 0;
 };
 
 namespace {
 
-// The x-step's arguments, reading the branch state from buffer `in` and
-// writing u and the branch state to buffer `out` (0 or 1).
-BranchArgs branch_args(const acopf_s* h, int in, int out) {
+// The x-step's arguments for a lane, reading the branch state from buffer
+// `in` and writing u and the branch state to buffer `out` (0 or 1).
+BranchArgs branch_args(const acopf_s* h, const Lane& L, int in, int out) {
   BranchArgs A{};
   A.nl = h->nl;
   A.ne = h->ne;
   A.ef = h->ef;
   A.et = h->et;
   A.br_grid = h->br_grid;
+  A.lane_of = h->lanes.size() > 1 ? h->lane_of_d : nullptr;
+  A.lane = (int)(&L - h->lanes.data());
   A.ctl = h->ctl;
   A.adm = h->adm;
   A.vlo_i = h->vlo_i;
@@ -833,7 +853,7 @@ BranchArgs branch_args(const acopf_s* h, int in, int out) {
   A.al_maxit = h->P.al_maxit;
   A.failures = h->failures_it + (size_t)out * h->G;
   A.stats = h->stats;
-  A.pool = h->pool;
+  A.pool = L.pool;
   A.ng = h->ng;
   A.gen_grid = h->gen_grid;
   A.pmin = h->pmin;
@@ -891,13 +911,13 @@ int build_tiles(acopf_s* h, int block) {
   h->n_hub = (int)hubs.size();
   h->n_tiles = (int)h->tiles_h.size();
   h->tile_block = block;
-  h->lists_dirty = true;
+  for (Lane& L : h->lanes) L.lists_dirty = true;
   return ACOPF_OK;
 }
 
-// The control decision's arguments (the device copy is h->dec).
-DecideArgs decide_args(const acopf_s* h) {
-  return DecideArgs{h->ctl, h->tmax, reinterpret_cast<const GridItem*>(h->lists + h->off_g),
+// A lane's control decision arguments (its device copy is the lane's `dec`).
+DecideArgs decide_args(const acopf_s* h, const Lane& L) {
+  return DecideArgs{h->ctl, h->tmax, reinterpret_cast<const GridItem*>(L.lists + h->off_g),
                     h->hist, h->failures, h->failures_it, h->P.eps_pri, h->P.eps_dual,
                     h->P.eps_z, h->P.beta_gamma, h->P.beta_omega, h->P.beta_max,
                     h->P.max_outer, h->P.max_inner, kHistCap, h->G};
@@ -909,48 +929,50 @@ DecideArgs decide_args(const acopf_s* h) {
 // finish enters the counters.
 bool fused_control(const acopf_s* h) { return h->tune.xstep_waves == 0 && !h->count_stats; }
 
-// Launch inner iteration `slot` of a chunk (its position); with profiling,
-// events bracket each launch. The lane-per-branch x-step at position q reads
+// Launch inner iteration `slot` of a chunk (its position) for the grids of
+// one lane, on the lane's stream; with profiling, events bracket each launch. The lane-per-branch x-step at position q reads
 // the branch state from buffer q & 1 and writes its results to the other;
 // with fused control it takes the previous iteration's decision in its first
 // blocks at positions >= 1, and the control kernel takes the chunk's last one
 // (`last`). The persistent x-step works in place (buffer 0), with the control
 // kernel after every iteration.
-void launch_iteration(acopf_s* h, int slot, bool last) {
-  hipStream_t s = h->stream;
-  hipEvent_t* E = h->profile ? &h->ev[(size_t)slot * kEvPerIter] : nullptr;
+void launch_iteration(acopf_s* h, int lane, int slot, bool last) {
+  Lane& L = h->lanes[lane];
+  hipStream_t s = L.stream;
+  hipEvent_t* E =
+      h->profile ? &h->ev[((size_t)lane * kMaxChunk + slot) * kEvPerIter] : nullptr;
   auto mark = [&](int k) {
     if (E) (void)hipEventRecord(E[k], s);
   };
   const bool persistent = h->tune.xstep_waves > 0, fused = fused_control(h);
   const int in = persistent ? 0 : (slot & 1), out = persistent ? 0 : ((slot + 1) & 1);
-  BranchArgs ba = branch_args(h, in, out);
+  BranchArgs ba = branch_args(h, L, in, out);
   mark(0);
   if (persistent)
     acopf_dev::launch_xstep_persistent(ba, h->n6, h->tune.xstep_waves * 4 * h->n_cu,
                                        h->count_stats, s);
   else
-    acopf_dev::launch_xstep(ba, h->xlay, h->xlist, h->n_x, h->dec,
-                            fused && slot > 0 ? h->n_gl : 0, slot, h->tune.xstep_block,
+    acopf_dev::launch_xstep(ba, L.xlay, L.xlist, L.n_x, L.dec,
+                            fused && slot > 0 ? L.n_gl : 0, slot, h->tune.xstep_block,
                             h->count_stats, s);
   mark(1);
-  BusArgs bu{h->nb, h->ng, h->ne, reinterpret_cast<const TileDesc*>(h->lists + h->off_t),
-             reinterpret_cast<const TileDesc*>(h->lists + h->off_h), h->bus_grid, h->ctl,
+  BusArgs bu{h->nb, h->ng, h->ne, reinterpret_cast<const TileDesc*>(L.lists + h->off_t),
+             reinterpret_cast<const TileDesc*>(L.lists + h->off_h), h->bus_grid, h->ctl,
              h->gptr, h->eptr, h->pd, h->qd, h->gs, h->bs, h->isref, out ? h->u1 : h->u, h->lam,
              h->v, h->z, h->y, h->P.rho_pq, h->P.rho_va, h->tmax, h->erec, h->brec,
              h->P.lambda_max};
   const int bb = h->tile_block;
-  hipLaunchKernelGGL(bus_kernel<false>, dim3(h->n_t), dim3(bb), bus_lds_bytes(h->tile_block), s,
+  hipLaunchKernelGGL(bus_kernel<false>, dim3(L.n_t), dim3(bb), bus_lds_bytes(h->tile_block), s,
                      bu);
   if (h->n_hub > 0)
-    hipLaunchKernelGGL(bus_kernel<true>, dim3(h->n_hl), dim3(bb), bus_lds_bytes(h->tile_block),
+    hipLaunchKernelGGL(bus_kernel<true>, dim3(L.n_hl), dim3(bb), bus_lds_bytes(h->tile_block),
                        s, bu);
   mark(2);
   const bool ctl = last || !fused;
   if (ctl)
-    hipLaunchKernelGGL(ctl_kernel, dim3(h->n_gl), dim3(kCtlBlock), 0, s, decide_args(h), out);
+    hipLaunchKernelGGL(ctl_kernel, dim3(L.n_gl), dim3(kCtlBlock), 0, s, decide_args(h, L), out);
   mark(3);
-  if (E) h->ev_ctl[slot] = ctl;
+  if (E) h->ev_ctl[lane][slot] = ctl;
 }
 
 int validate_grid(const acopf_grid& g, int idx) {
@@ -1051,19 +1073,93 @@ void acopf_default_params(acopf_params* p) {
 
 const char* acopf_last_error(void) { return g_err.c_str(); }
 
+// Releases the last lane (its graph, lists, stream).
+static void free_lane(acopf_s* h) {
+  Lane& L = h->lanes.back();
+  if (L.stream) (void)hipStreamSynchronize(L.stream);
+  if (L.graph) (void)hipGraphExecDestroy(L.graph);
+  if (L.gtmpl) (void)hipGraphDestroy(L.gtmpl);
+  if (L.lists) (void)hipFree(L.lists);
+  if (L.stage) (void)hipHostFree(L.stage);
+  if (L.dec) (void)hipFree(L.dec);
+  if (L.pool) (void)hipFree(L.pool);
+  if (L.end) (void)hipEventDestroy(L.end);
+  if (L.own_stream && L.stream) (void)hipStreamDestroy(L.stream);
+  h->lanes.pop_back();
+}
+
+// A new lane: the first runs on the handle's stream, the others on streams
+// of their own (default priority); each has its work lists, decision
+// arguments and pool counters.
+static int add_lane(acopf_s* h) {
+  h->lanes.emplace_back();
+  Lane& L = h->lanes.back();
+  if (h->lanes.size() == 1) {
+    L.stream = h->stream;
+  } else {
+    HIP_TRY(hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
+    L.own_stream = true;
+    HIP_TRY(hipEventCreateWithFlags(&L.end, hipEventDisableTiming));
+  }
+  HIP_TRY(hipMalloc(reinterpret_cast<void**>(&L.lists), h->list_bytes));
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&L.stage), h->list_bytes, hipHostMallocDefault));
+  HIP_TRY(hipMalloc(reinterpret_cast<void**>(&L.dec), sizeof(DecideArgs)));
+  HIP_TRY(hipMalloc(reinterpret_cast<void**>(&L.pool), 3 * sizeof(unsigned)));
+  const DecideArgs dv = decide_args(h, L);
+  HIP_TRY(hipMemcpyAsync(L.dec, &dv, sizeof(dv), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipMemsetAsync(L.pool, 0, 3 * sizeof(unsigned), h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return ACOPF_OK;
+}
+
+// Grids to lanes: largest first (by branches, then buses) to the lane with
+// the fewest branches so far.
+static int assign_lanes(acopf_s* h) {
+  const int nlanes = (int)h->lanes.size();
+  std::vector<int> order(h->G);
+  for (int g = 0; g < h->G; ++g) order[g] = g;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const HostGrid &A = h->grids[a], &B = h->grids[b];
+    return A.nl != B.nl ? A.nl > B.nl : A.nb > B.nb;
+  });
+  std::vector<int64_t> load(nlanes, 0);
+  h->lane_of.assign(h->G, 0);
+  for (int g : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    h->lane_of[g] = k;
+    load[k] += h->grids[g].nl + 1;
+  }
+  for (Lane& L : h->lanes) L.lists_dirty = true;
+  HIP_TRY(hipMemcpyAsync(h->lane_of_d, h->lane_of.data(), sizeof(int) * h->G,
+                         hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return ACOPF_OK;
+}
+
+// Sets the number of lanes (at most the number of grids) and reassigns the
+// grids to them.
+static int set_lanes(acopf_s* h, int n) {
+  n = std::max(1, std::min(n, h->G));
+  while ((int)h->lanes.size() > n) free_lane(h);
+  while ((int)h->lanes.size() < n) {
+    int rc = add_lane(h);
+    if (rc) return rc;
+  }
+  return assign_lanes(h);
+}
+
 void acopf_destroy(acopf_handle h) {
   if (!h) return;
   if (h->device >= 0) (void)hipSetDevice(h->device);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
-  if (h->graph) (void)hipGraphExecDestroy(h->graph);
-  if (h->gtmpl) (void)hipGraphDestroy(h->gtmpl);
+  while (!h->lanes.empty()) free_lane(h);
+  if (h->join) (void)hipEventDestroy(h->join);
   for (void* p : h->snap) (void)hipFree(p);
   if (h->qscratch) (void)hipFree(h->qscratch);
   if (h->qual) (void)hipFree(h->qual);
   h->buf.release();
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
-  if (h->stage) (void)hipHostFree(h->stage);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
 }
@@ -1304,9 +1400,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
     h->off_t = up16(sizeof(int) * (size_t)h->xcap);
     h->off_h = h->off_t + up16(sizeof(TileDesc) * (size_t)(nb + 1));
     h->off_g = h->off_h + up16(sizeof(TileDesc) * (size_t)(nb + 1));
-    const size_t bytes = h->off_g + up16(sizeof(GridItem) * (size_t)n_grids);
-    HIP_TRY(D.alloc(&h->lists, bytes));
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->stage), bytes, hipHostMallocDefault));
+    h->list_bytes = h->off_g + up16(sizeof(GridItem) * (size_t)n_grids);
   }
   HIP_TRY(D.alloc(&h->eptr, nb + 1));
   HIP_TRY(D.alloc(&h->isref, nb));
@@ -1317,7 +1411,7 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(D.alloc(&h->stats, kStats));
   HIP_TRY(D.alloc(&h->failures, n_grids));
   HIP_TRY(D.alloc(&h->failures_it, 2 * (size_t)n_grids));
-  HIP_TRY(D.alloc(&h->pool, 3));
+  HIP_TRY(D.alloc(&h->lane_of_d, n_grids));
   HIP_TRY(D.alloc(&h->hist, (size_t)n_grids * kHistCap * 6));
   HIP_TRY(D.alloc(&h->gen_off_d, n_grids + 1));
   HIP_TRY(D.alloc(&h->end_off_d, n_grids + 1));
@@ -1373,15 +1467,14 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(up(h->end_off_d, end_off.data(), sizeof(int64_t) * (n_grids + 1)));
   HIP_TRY(up(h->base_d, base.data(), sizeof(double) * n_grids));
   HIP_TRY(hipMemsetAsync(h->stats, 0, sizeof(unsigned long long) * kStats, st));
-  HIP_TRY(hipMemsetAsync(h->pool, 0, sizeof(unsigned) * 3, st));
   HIP_TRY(hipMemsetAsync(h->hist, 0, sizeof(double) * (size_t)n_grids * kHistCap * 6, st));
   HIP_TRY(hipMemsetAsync(h->ctl, 0, sizeof(GridCtl) * n_grids, st));
-  HIP_TRY(D.alloc(&h->dec, 1));
-  {
-    const DecideArgs dv = decide_args(h);
-    HIP_TRY(hipMemcpyAsync(h->dec, &dv, sizeof(dv), hipMemcpyHostToDevice, st));
-  }
   HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipEventCreateWithFlags(&h->join, hipEventDisableTiming));
+  // two lanes for a handle of several grids, one for a single grid
+  h->tune.lanes = n_grids > 1 ? 2 : 1;
+  int rc2 = set_lanes(h, h->tune.lanes);
+  if (rc2) return rc2;
   return build_tiles(h, h->tune.bus_block);
 }
 
@@ -1457,52 +1550,62 @@ int acopf_create(const acopf_grid* grids, int32_t n_grids, const acopf_params* p
   return ACOPF_OK;
 }
 
-static void accumulate_timing(acopf_s* h, int used) {
-  for (int s = 0; s < used; ++s) {
-    hipEvent_t* E = &h->ev[(size_t)s * kEvPerIter];
-    for (int k = 0; k < kTimed; ++k) {
-      if (k == 2 && !h->ev_ctl[s]) continue;  // no control kernel after this iteration
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, E[k], E[k + 1]) == hipSuccess) h->t_ms[k] += ms;
+// Adds the profiled launches of a chunk of `used` iterations of the lanes
+// that ran (one after another): per iteration, the sum over those lanes.
+static void accumulate_timing(acopf_s* h, int used, const std::vector<int>& ran) {
+  for (int lane : ran)
+    for (int s = 0; s < used; ++s) {
+      hipEvent_t* E = &h->ev[((size_t)lane * kMaxChunk + s) * kEvPerIter];
+      for (int k = 0; k < kTimed; ++k) {
+        if (k == 2 && !h->ev_ctl[lane][s]) continue;  // no control kernel after this iteration
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, E[k], E[k + 1]) == hipSuccess) h->t_ms[k] += ms;
+      }
     }
-  }
   h->t_iters += used;
 }
 
-static void drop_graph(acopf_s* h) {
-  if (h->graph) (void)hipGraphExecDestroy(h->graph);
-  if (h->gtmpl) (void)hipGraphDestroy(h->gtmpl);
-  h->graph = nullptr;
-  h->gtmpl = nullptr;
-  h->graph_chunk = 0;
-  h->gnode.clear();
-  h->grole.clear();
-  h->gparam.clear();
+static void drop_graph(Lane& L) {
+  if (L.graph) (void)hipGraphExecDestroy(L.graph);
+  if (L.gtmpl) (void)hipGraphDestroy(L.gtmpl);
+  L.graph = nullptr;
+  L.gtmpl = nullptr;
+  L.graph_chunk = 0;
+  L.gnode.clear();
+  L.grole.clear();
+  L.gparam.clear();
 }
 
-// Grid size of a captured kernel node of the given role under the current
-// work lists.
-static unsigned role_blocks(const acopf_s* h, int role) {
+static void drop_graph(acopf_s* h) {
+  for (Lane& L : h->lanes) drop_graph(L);
+}
+
+// Grid size of a captured kernel node of the given role under the lane's
+// current work lists.
+static unsigned role_blocks(const Lane& L, int role) {
   switch (role) {
-    case 0: return (unsigned)h->n_x;
-    case 1: return (unsigned)h->n_t;
-    case 2: return (unsigned)h->n_hl;
-    default: return (unsigned)h->n_gl;
+    case 0: return (unsigned)L.n_x;
+    case 1: return (unsigned)L.n_t;
+    case 2: return (unsigned)L.n_hl;
+    default: return (unsigned)L.n_gl;
   }
 }
 
-// Work lists of the grids that are running (of all grids when none is: the
-// shape a chunk is captured with): x-step items over the generator, rated
+// Work lists of a lane's grids that are running (of all its grids when none
+// is: the shape a chunk is captured with): x-step items over the generator, rated
 // and unlimited ranges of those grids (adjacent ranges merged, so that with
 // every grid running the items are those of one contiguous range per class),
 // their bus tiles and hub tiles, and the grids themselves. The kernel nodes of
 // a captured chunk take the new grid sizes in place; their arguments point to
 // the lists and do not change.
-static int build_active(acopf_s* h) {
-  std::vector<char> act = h->running;
-  if (std::find(act.begin(), act.end(), 1) == act.end()) std::fill(act.begin(), act.end(), 1);
-  if (!h->lists_dirty && act == h->active_for) return ACOPF_OK;
-  HIP_TRY(hipStreamSynchronize(h->stream));  // the last copy from `stage` has landed
+static int build_active(acopf_s* h, int lane) {
+  Lane& LN = h->lanes[lane];
+  std::vector<char> act(h->G, 0);
+  for (int g = 0; g < h->G; ++g) act[g] = h->running[g] && h->lane_of[g] == lane;
+  if (std::find(act.begin(), act.end(), 1) == act.end())
+    for (int g = 0; g < h->G; ++g) act[g] = h->lane_of[g] == lane;
+  if (!LN.lists_dirty && act == LN.active_for) return ACOPF_OK;
+  HIP_TRY(hipStreamSynchronize(LN.stream));  // the last copy from `stage` has landed
   // x-step: the block layout over the handle's ranges, with the unlimited
   // branches per lane chosen for the running grids (as many as it takes for
   // every branch wavefront to be resident at once, one per SIMD slot, unless
@@ -1528,14 +1631,14 @@ static int build_active(acopf_s* h) {
     if (free_lanes >= slots * 8)
       k4 = (int)std::min<int64_t>(8, std::max<int64_t>(1, (n4 + free_lanes - 1) / free_lanes));
   }
-  acopf_dev::XLayout& L = h->xlay;
+  acopf_dev::XLayout& L = LN.xlay;
   L.n6 = h->n6;
   L.bg = (int)((h->ng + bs - 1) / bs);
   L.b6 = (int)((h->n6 + bs - 1) / bs);
   L.b4 = (int)((n4_all + (int64_t)bs * k4 - 1) / ((int64_t)bs * k4));
   L.k4 = k4;
   int nx = L.bg + L.b6 + L.b4;
-  h->xlist = nullptr;
+  LN.xlist = nullptr;
   if (!all) {
     std::vector<char> use((size_t)nx, 0);
     auto mark = [&](int64_t off, int64_t a, int64_t e) {  // blocks off + [a / bs, (e - 1) / bs]
@@ -1556,16 +1659,16 @@ static int build_active(acopf_s* h) {
         o = stop;
       }
     }
-    int* xl = reinterpret_cast<int*>(h->stage);
+    int* xl = reinterpret_cast<int*>(LN.stage);
     nx = 0;
     for (size_t k = 0; k < use.size(); ++k)
       if (use[k]) xl[nx++] = (int)k;
-    h->xlist = reinterpret_cast<const int*>(h->lists);
+    LN.xlist = reinterpret_cast<const int*>(LN.lists);
   }
   if (nx > h->xcap) return fail(ACOPF_EDEVICE, "x-step block list overflow");
-  TileDesc* tl = reinterpret_cast<TileDesc*>(h->stage + h->off_t);
-  TileDesc* hl = reinterpret_cast<TileDesc*>(h->stage + h->off_h);
-  GridItem* gl = reinterpret_cast<GridItem*>(h->stage + h->off_g);
+  TileDesc* tl = reinterpret_cast<TileDesc*>(LN.stage + h->off_t);
+  TileDesc* hl = reinterpret_cast<TileDesc*>(LN.stage + h->off_h);
+  GridItem* gl = reinterpret_cast<GridItem*>(LN.stage + h->off_g);
   int nt = 0, nh = 0, ngl = 0;
   for (int g = 0; g < h->G; ++g) {
     if (!act[g]) continue;
@@ -1580,60 +1683,61 @@ static int build_active(acopf_s* h) {
   const TileDesc none{0, 0, 0, 0, 0, 0, 0, -1};
   if (nt == 0) tl[nt++] = none;  // a launch needs one block; it returns at once
   if (nh == 0) hl[nh++] = none;
-  hipStream_t st = h->stream;
-  if (h->xlist)
-    HIP_TRY(hipMemcpyAsync(h->lists, h->stage, sizeof(int) * nx, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(h->lists + h->off_t, tl, sizeof(TileDesc) * nt, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(h->lists + h->off_h, hl, sizeof(TileDesc) * nh, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(h->lists + h->off_g, gl, sizeof(GridItem) * ngl, hipMemcpyHostToDevice,
+  hipStream_t st = LN.stream;
+  if (LN.xlist)
+    HIP_TRY(hipMemcpyAsync(LN.lists, LN.stage, sizeof(int) * nx, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(LN.lists + h->off_t, tl, sizeof(TileDesc) * nt, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(LN.lists + h->off_h, hl, sizeof(TileDesc) * nh, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(LN.lists + h->off_g, gl, sizeof(GridItem) * ngl, hipMemcpyHostToDevice,
                          st));
-  h->n_x = nx;
-  h->n_t = nt;
-  h->n_hl = nh;
-  h->n_gl = ngl;
-  h->active_for = act;
-  h->lists_dirty = false;
-  h->xba[0] = branch_args(h, 0, 1);
-  h->xba[1] = branch_args(h, 1, 0);
-  for (size_t i = 0; h->graph && i < h->gnode.size(); ++i) {
-    if (h->grole[i] < 0) continue;
-    hipKernelNodeParams p = h->gparam[i];
-    p.gridDim = dim3(role_blocks(h, h->grole[i]));
+  LN.n_x = nx;
+  LN.n_t = nt;
+  LN.n_hl = nh;
+  LN.n_gl = ngl;
+  LN.active_for = act;
+  LN.lists_dirty = false;
+  LN.xba[0] = branch_args(h, LN, 0, 1);
+  LN.xba[1] = branch_args(h, LN, 1, 0);
+  for (size_t i = 0; LN.graph && i < LN.gnode.size(); ++i) {
+    if (LN.grole[i] < 0) continue;
+    hipKernelNodeParams p = LN.gparam[i];
+    p.gridDim = dim3(role_blocks(LN, LN.grole[i]));
     // an x-step node keeps its chunk position; its decision blocks follow
     // the running grids
     int pos = 0, n_dec = 0;
-    void* xargs[10] = {nullptr, &L.n6, &L.bg, &L.b6, &L.b4, &L.k4, &h->xlist, &h->dec, &n_dec,
+    void* xargs[10] = {nullptr, &L.n6, &L.bg, &L.b6, &L.b4, &L.k4, &LN.xlist, &LN.dec, &n_dec,
                        &pos};
-    if (h->grole[i] == 0) {
-      pos = *static_cast<const int*>(h->gparam[i].kernelParams[9]);
-      n_dec = pos > 0 && fused_control(h) ? h->n_gl : 0;
-      xargs[0] = &h->xba[pos & 1];
-      p.gridDim = dim3((unsigned)(n_dec + h->n_x));
+    if (LN.grole[i] == 0) {
+      pos = *static_cast<const int*>(LN.gparam[i].kernelParams[9]);
+      n_dec = pos > 0 && fused_control(h) ? LN.n_gl : 0;
+      xargs[0] = &LN.xba[pos & 1];
+      p.gridDim = dim3((unsigned)(n_dec + LN.n_x));
       p.kernelParams = xargs;
     }
-    HIP_TRY(hipGraphExecKernelNodeSetParams(h->graph, h->gnode[i], &p));
+    HIP_TRY(hipGraphExecKernelNodeSetParams(LN.graph, LN.gnode[i], &p));
   }
   return ACOPF_OK;
 }
 
-// Captures one chunk of the tuned length as a hipGraph (without per-launch
-// timing events) if graphs are on and none is held. Called when the launch
-// shape or the kernel variant changes, so that capture and instantiation
-// happen outside the solves that replay the graph. Its kernel nodes are kept
-// so that build_active can resize them to the running grids.
-static int ensure_graph(acopf_s* h) {
+// Captures one chunk of the tuned length of a lane as a hipGraph (without
+// per-launch timing events) if graphs are on and none is held. Called when
+// the launch shape or the kernel variant changes, so that capture and
+// instantiation happen outside the solves that replay the graph. Its kernel
+// nodes are kept so that build_active can resize them to the running grids.
+static int ensure_graph(acopf_s* h, int lane) {
+  Lane& L = h->lanes[lane];
   const int k = h->tune.chunk;
-  if (!h->tune.use_graph || (h->graph && h->graph_chunk == k)) return ACOPF_OK;
-  drop_graph(h);
-  int rc = build_active(h);
+  if (!h->tune.use_graph || (L.graph && L.graph_chunk == k)) return ACOPF_OK;
+  drop_graph(L);
+  int rc = build_active(h, lane);
   if (rc) return rc;
   const bool prof = h->profile;
   h->profile = false;
   hipGraph_t g = nullptr;
-  hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+  hipError_t e = hipStreamBeginCapture(L.stream, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    for (int c = 0; c < k; ++c) launch_iteration(h, c, c == k - 1);
-    e = hipStreamEndCapture(h->stream, &g);
+    for (int c = 0; c < k; ++c) launch_iteration(h, lane, c, c == k - 1);
+    e = hipStreamEndCapture(L.stream, &g);
   }
   h->profile = prof;
   if (e != hipSuccess) return fail(ACOPF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
@@ -1653,32 +1757,41 @@ static int ensure_graph(acopf_s* h) {
     else if (p.func == reinterpret_cast<void*>(&bus_kernel<false>)) role = 1;
     else if (p.func == reinterpret_cast<void*>(&bus_kernel<true>)) role = 2;
     else if (p.func == reinterpret_cast<void*>(&ctl_kernel)) role = 3;
-    h->gnode.push_back(nodes[i]);
-    h->grole.push_back(role);
-    h->gparam.push_back(p);
+    L.gnode.push_back(nodes[i]);
+    L.grole.push_back(role);
+    L.gparam.push_back(p);
   }
-  if (e == hipSuccess) e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+  if (e == hipSuccess) e = hipGraphInstantiate(&L.graph, g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     (void)hipGraphDestroy(g);
-    h->graph = nullptr;
-    drop_graph(h);
+    L.graph = nullptr;
+    drop_graph(L);
     return fail(ACOPF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
   }
-  h->gtmpl = g;
-  h->graph_chunk = k;
+  L.gtmpl = g;
+  L.graph_chunk = k;
   return ACOPF_OK;
 }
 
-// k inner iterations: one replay of the captured chunk when k equals the
-// tuned chunk and timing is off, else plain launches.
-static int launch_chunk(acopf_s* h, int k) {
-  if (!h->profile && h->tune.use_graph && k == h->tune.chunk) {
-    int rc = ensure_graph(h);
+static int ensure_graph(acopf_s* h) {
+  for (int lane = 0; lane < (int)h->lanes.size(); ++lane) {
+    int rc = ensure_graph(h, lane);
     if (rc) return rc;
-    HIP_TRY(hipGraphLaunch(h->graph, h->stream));
+  }
+  return ACOPF_OK;
+}
+
+// k inner iterations of a lane: one replay of its captured chunk when k
+// equals the tuned chunk and timing is off, else plain launches.
+static int launch_chunk(acopf_s* h, int lane, int k) {
+  Lane& L = h->lanes[lane];
+  if (!h->profile && h->tune.use_graph && k == h->tune.chunk) {
+    int rc = ensure_graph(h, lane);
+    if (rc) return rc;
+    HIP_TRY(hipGraphLaunch(L.graph, L.stream));
     return ACOPF_OK;
   }
-  for (int c = 0; c < k; ++c) launch_iteration(h, c, c == k - 1);
+  for (int c = 0; c < k; ++c) launch_iteration(h, lane, c, c == k - 1);
   HIP_TRY(hipGetLastError());
   return ACOPF_OK;
 }
@@ -1785,17 +1898,44 @@ static int run_impl(acopf_s* h, int64_t max_iters, bool stop_on_first, int64_t* 
     for (int g = 0; g < h->G; ++g) nrun += h->running[g];
     if (nrun == 0) break;
     const int k = (int)std::min<int64_t>(h->tune.chunk, max_iters - issued);
-    int rc = build_active(h);
-    if (rc) return rc;
-    rc = launch_chunk(h, k);
-    if (rc) return rc;
+    // every lane with a running grid launches its chunk after the work queued
+    // on the handle's stream (starts, copies, the last chunk's settling); with
+    // profiling the lanes run one after another, so that events time each
+    std::vector<int> ran;
+    int rc = ACOPF_OK;
+    std::vector<char> busy(h->lanes.size(), 0);
+    bool other = false;  // a lane on a stream of its own runs
+    for (int g = 0; g < h->G; ++g)
+      if (h->running[g]) busy[h->lane_of[g]] = 1;
+    for (size_t lane = 0; lane < busy.size(); ++lane)
+      other = other || (busy[lane] && h->lanes[lane].stream != h->stream);
+    if (other) HIP_TRY(hipEventRecord(h->join, h->stream));
+    for (int lane = 0; lane < (int)h->lanes.size(); ++lane) {
+      if (!busy[lane]) continue;
+      Lane& L = h->lanes[lane];
+      if (L.stream != h->stream) HIP_TRY(hipStreamWaitEvent(L.stream, h->join, 0));
+      rc = build_active(h, lane);
+      if (rc) return rc;
+      rc = launch_chunk(h, lane, k);
+      if (rc) return rc;
+      if (h->profile) HIP_TRY(hipStreamSynchronize(L.stream));
+      ran.push_back(lane);
+    }
+    // the control words are read on the handle's stream after every lane's
+    // chunk (queued behind them, so that the copy starts as the chunks end)
+    for (int lane : ran) {
+      Lane& L = h->lanes[lane];
+      if (L.stream == h->stream) continue;
+      HIP_TRY(hipEventRecord(L.end, L.stream));
+      HIP_TRY(hipStreamWaitEvent(h->stream, L.end, 0));
+    }
     issued += k;
     HIP_TRY(hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(GridCtl) * h->G, hipMemcpyDeviceToHost,
                            h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     rc = settle_buffers(h);
     if (rc) return rc;
-    if (h->profile) accumulate_timing(h, k);
+    if (h->profile) accumulate_timing(h, k, ran);
     const double t = now_s();
     bool finished_one = false;
     for (int g = 0; g < h->G; ++g)
@@ -2290,6 +2430,7 @@ static int check_tuning(const acopf_tuning& t) {
     return fail(ACOPF_EINVAL, "xstep_waves must be in [0, 4]");
   if (t.xstep_per_lane < 0 || t.xstep_per_lane > 8)
     return fail(ACOPF_EINVAL, "xstep_per_lane must be in [0, 8]");
+  if (t.lanes < 1 || t.lanes > kMaxLanes) return fail(ACOPF_EINVAL, "lanes must be in [1, 4]");
   return ACOPF_OK;
 }
 
@@ -2299,8 +2440,15 @@ static int apply_tuning(acopf_s* h, const acopf_tuning& t) {
     int rc = build_tiles(h, t.bus_block);
     if (rc) return rc;
   }
+  // the persistent branch kernel pools every branch of the handle: one lane
+  const int lanes = t.xstep_waves > 0 ? 1 : std::min(t.lanes, h->G);
+  if (lanes != (int)h->lanes.size()) {
+    int rc = set_lanes(h, lanes);
+    if (rc) return rc;
+  }
   h->tune = t;
-  h->lists_dirty = true;  // x-step items depend on the block and per-lane count
+  h->tune.lanes = (int)h->lanes.size();
+  for (Lane& L : h->lanes) L.lists_dirty = true;  // x-step items depend on the block and per-lane count
   return ACOPF_OK;
 }
 
@@ -2337,29 +2485,51 @@ int acopf_autotune(acopf_handle h, int32_t iters, acopf_tuning* out) {
   const int xs[7][3] = {{64, 0, 0}, {64, 0, 1}, {128, 0, 0}, {256, 0, 0},
                         {64, 1, 0}, {64, 2, 0}, {128, 0, 1}};
   const int bs[4] = {128, 256, 512, 1024}, cs[3] = {8, 16, 32};
+  // best of two timed runs of `iters` iterations from the saved state
+  auto measure = [&](const acopf_tuning& t, double* secs) -> int {
+    int r = apply_tuning(h, t);
+    if (r) return r;
+    double tmin = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {  // first pass also captures the graphs
+      r = acopf_snapshot(h, 1);
+      if (r) return r;
+      r = start_impl(h, -1, ACOPF_CONTINUE, iters);
+      if (r) return r;
+      HIP_TRY(hipStreamSynchronize(h->stream));
+      const double t0 = now_s();
+      r = run_impl(h, iters, false, nullptr);
+      if (r) return r;
+      tmin = std::min(tmin, now_s() - t0);
+    }
+    *secs = tmin;
+    return ACOPF_OK;
+  };
   for (const auto& xi : xs)
     for (int bi : bs)
       for (int ci : cs) {
-        acopf_tuning t{xi[0], bi, ci, 1, xi[1], xi[2]};
-        rc = apply_tuning(h, t);
+        acopf_tuning t{xi[0], bi, ci, 1, xi[1], xi[2], h->tune.lanes};
+        double secs = 0.0;
+        rc = measure(t, &secs);
         if (rc) return rc;
-        double tmin = 1e300;
-        for (int rep = 0; rep < 2; ++rep) {  // first pass also captures the graph
-          rc = acopf_snapshot(h, 1);
-          if (rc) return rc;
-          rc = start_impl(h, -1, ACOPF_CONTINUE, iters);
-          if (rc) return rc;
-          HIP_TRY(hipStreamSynchronize(h->stream));
-          const double t0 = now_s();
-          rc = run_impl(h, iters, false, nullptr);
-          if (rc) return rc;
-          tmin = std::min(tmin, now_s() - t0);
-        }
-        if (tmin < best_t) {
-          best_t = tmin;
+        if (secs < best_t) {
+          best_t = secs;
           best = t;
         }
       }
+  // then the number of launch lanes for the best shape
+  const acopf_tuning shape = best;
+  for (int nl : {1, 2, 4}) {
+    if (nl > h->G || nl == shape.lanes) continue;
+    acopf_tuning t = shape;
+    t.lanes = nl;
+    double secs = 0.0;
+    rc = measure(t, &secs);
+    if (rc) return rc;
+    if (secs < best_t) {
+      best_t = secs;
+      best = t;
+    }
+  }
   rc = apply_tuning(h, best);
   if (rc) return rc;
   rc = acopf_snapshot(h, 1);
@@ -2388,7 +2558,7 @@ int acopf_set_profiling(acopf_handle h, int32_t on) {
   if (!h) return fail(ACOPF_EINVAL, "null handle");
   HIP_TRY(hipSetDevice(h->device));
   if (on && h->ev.empty()) {
-    h->ev.resize((size_t)kEvPerIter * kMaxChunk);  // one set per iteration of any chunk
+    h->ev.resize((size_t)kEvPerIter * kMaxChunk * kMaxLanes);  // per lane and iteration
     for (auto& e : h->ev) HIP_TRY(hipEventCreate(&e));
   }
   h->profile = on != 0;

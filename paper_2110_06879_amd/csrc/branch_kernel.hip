@@ -1082,7 +1082,7 @@ __device__ inline void load_record(const BranchArgs& A, int64_t l, BranchIn<N>& 
 // round of memory accesses before it computes; the end positions are needed
 // only for the stores of u. Returns false, without solving, when the grid has
 // finished.
-template <int N, class Cnt>
+template <int N, bool kLanes, class Cnt>
 __device__ bool solve_branch(const BranchArgs& A, int64_t l, Cnt& cnt) {
   {
     const int64_t nl = A.nl;
@@ -1126,7 +1126,7 @@ __device__ bool solve_branch(const BranchArgs& A, int64_t l, Cnt& cnt) {
       B.lt1 = A.ltil_in[nl + l];
       B.rt = A.rtil_in[l];
     }
-    if (A.ctl[grid].done != 0) return false;
+    if (A.ctl[grid].done != 0 || (kLanes && A.lane_of[grid] != A.lane)) return false;
     int failures = 0;
     if (N == 4) {
       failures +=
@@ -1404,8 +1404,10 @@ void launch_xstep_persistent(const BranchArgs& A, int64_t n6, int blocks, bool s
 // iteration's control decision of the running grids while the others solve
 // (the state is double-buffered, so that branch solves that run past a
 // grid's finish overwrite only the older buffer).
-// kStats: as for the persistent kernel.
-template <bool kStats>
+// kStats: as for the persistent kernel. kLanes: the handle's grids are split
+// into launch lanes; a layout block can hold branches or generators of grids
+// of several lanes, and each lane's launch solves only its own grids' ones.
+template <bool kStats, bool kLanes>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ACOPF_XSTEP_WAVES_PER_EU)))
 void xstep_kernel(BranchArgs A, int64_t n6, int bg, int b6, int b4, int k4,
                   const int* __restrict__ vblock, const DecideArgs* __restrict__ dec, int n_dec,
@@ -1421,19 +1423,23 @@ void xstep_kernel(BranchArgs A, int64_t n6, int bg, int b6, int b4, int k4,
   const int bs = blockDim.x;
   if (b >= b6 + b4) {
     const int64_t g = (int64_t)(b - b6 - b4) * bs + threadIdx.x;
-    if (g < A.ng && A.ctl[A.gen_grid[g]].done == 0) solve_generator(A, g);
+    if (g < A.ng) {
+      const int grid = A.gen_grid[g];
+      if (A.ctl[grid].done == 0 && (!kLanes || A.lane_of[grid] == A.lane))
+        solve_generator(A, g);
+    }
     return;  // whole block is generators: no branch counters
   }
   if (b < b6) {
     const int64_t l = (int64_t)b * bs + threadIdx.x;
-    if (l < n6 && solve_branch<6>(A, l, cnt)) ++solves;
+    if (l < n6 && solve_branch<6, kLanes>(A, l, cnt)) ++solves;
   } else {
     const int64_t base = n6 + (int64_t)(b - b6) * bs + threadIdx.x;
     const int64_t stride = (int64_t)b4 * bs;
     for (int j = 0; j < k4; ++j) {
       const int64_t l = base + j * stride;
       if (l >= A.nl) break;
-      if (solve_branch<4>(A, l, cnt)) ++solves;
+      if (solve_branch<4, kLanes>(A, l, cnt)) ++solves;
     }
   }
   if (!kStats) return;
@@ -1458,17 +1464,18 @@ void launch_xstep(const BranchArgs& A, const XLayout& L, const int* vblock, int 
                   const DecideArgs* dec, int n_dec, int pos, int block, bool stats,
                   hipStream_t s) {
   if (n_blocks + n_dec <= 0) return;
-  if (stats)
-    hipLaunchKernelGGL(xstep_kernel<true>, dim3(n_dec + n_blocks), dim3(block), 0, s, A, L.n6,
-                       L.bg, L.b6, L.b4, L.k4, vblock, dec, n_dec, pos);
-  else
-    hipLaunchKernelGGL(xstep_kernel<false>, dim3(n_dec + n_blocks), dim3(block), 0, s, A, L.n6,
-                       L.bg, L.b6, L.b4, L.k4, vblock, dec, n_dec, pos);
+  // the lane test is compiled only into the variants for several lanes
+  auto kernel = stats ? (A.lane_of ? xstep_kernel<true, true> : xstep_kernel<true, false>)
+                      : (A.lane_of ? xstep_kernel<false, true> : xstep_kernel<false, false>);
+  hipLaunchKernelGGL(kernel, dim3(n_dec + n_blocks), dim3(block), 0, s, A, L.n6, L.bg, L.b6,
+                     L.b4, L.k4, vblock, dec, n_dec, pos);
 }
 
 bool is_xstep_kernel(const void* f) {
-  return f == reinterpret_cast<const void*>(&xstep_kernel<false>) ||
-         f == reinterpret_cast<const void*>(&xstep_kernel<true>);
+  return f == reinterpret_cast<const void*>(&xstep_kernel<false, false>) ||
+         f == reinterpret_cast<const void*>(&xstep_kernel<true, false>) ||
+         f == reinterpret_cast<const void*>(&xstep_kernel<false, true>) ||
+         f == reinterpret_cast<const void*>(&xstep_kernel<true, true>);
 }
 
 // ---------------------------------------------------------------------------

@@ -178,6 +178,10 @@ struct BranchArgs {
   int64_t ne;                // branch ends, 2 nl
   const int *ef, *et;        // [nl] end positions of each branch
   const int* br_grid;
+  const int* lane_of;        // [G] launch lane of each grid, or null (one lane): a layout
+                             // block can span grids of several lanes, and a lane
+                             // solves only its own grids' branches and generators
+  int lane;
   const GridCtl* ctl;
   const double* adm;         // [8][nl] gii bii gij bij gji bji gjj bjj
   const double *vlo_i, *vhi_i, *vlo_j, *vhi_j, *rate2;

@@ -364,3 +364,52 @@ def test_server_commits_each_finished_slot_as_home():
             assert_same(states(ref), states(srv.solver, last.slot))
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("lanes", [2, 4])
+def test_launch_lanes_equal_one_lane(lanes):
+    """Launch lanes: the grids of a handle split into groups launched on
+    streams of their own, whose chunks run concurrently. Grids of different
+    lanes share no data, so every grid's results, iterates and branch state
+    are bitwise those of one lane, through convergence at different
+    iterations, staggered starts and a running set that changes."""
+    note(f"5 uneven grids: {lanes} lanes against one")
+    gs = [gridgen(150 + 70 * k, 30 + 6 * k, 200 + 95 * k, 0.4, 700 + k, load_factor=0.2)
+          for k in range(5)]
+    with A.Solver(gs) as s1, A.Solver(gs) as s2:
+        s1.set_tuning(lanes=1)
+        s2.set_tuning(lanes=lanes)
+        assert s1.tuning()["lanes"] == 1 and s2.tuning()["lanes"] == lanes
+        r1 = s1.solve(A.COLD)
+        r2 = s2.solve(A.COLD)
+        for a, b in zip(r1, r2):
+            for k in ("status", "inner_iters", "outer_iters", "branch_failures", "objective",
+                      "r_pri", "r_dual", "r_z"):
+                assert a[k] == b[k], (k, a[k], b[k])
+        for s in (s1, s2):
+            s.start(3, A.WARM, 40)
+            s.run(16)
+            s.start(0, A.WARM, 25)
+            while s.run(64) > 0:
+                pass
+        for k in range(len(gs)):
+            assert_same(states(s1, k), states(s2, k))
+
+
+def test_launch_lanes_clamped_and_persistent_kernel_one_lane():
+    """More lanes than grids are reduced to the number of grids, and the
+    persistent branch kernel, which pools every branch of the handle, runs as
+    one lane."""
+    note("lanes clamped to the grids; persistent kernel as one lane")
+    gs = [gridgen(120 + 40 * k, 20, 160 + 50 * k, 0.3, 750 + k, load_factor=0.2)
+          for k in range(3)]
+    with A.Solver(gs) as s:
+        assert s.tuning()["lanes"] == 2
+        s.set_tuning(lanes=4)
+        assert s.tuning()["lanes"] == 3
+        s.set_tuning(xstep_waves=1)
+        assert s.tuning()["lanes"] == 1
+        with pytest.raises(A.AcopfError):
+            s.set_tuning(lanes=5)
+    with A.Solver(gs[0]) as s:
+        assert s.tuning()["lanes"] == 1

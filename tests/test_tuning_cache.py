@@ -7,7 +7,7 @@ from paper_2110_06879_amd import acopf as A
 from paper_2110_06879_amd.gridgen import gridgen
 
 TUNE = {"xstep_block": 128, "bus_block": 512, "chunk": 32, "use_graph": 1,
-        "xstep_waves": 0, "xstep_per_lane": 2}
+        "xstep_waves": 0, "xstep_per_lane": 2, "lanes": 2}
 
 
 def test_key_counts_the_workload_shape():
@@ -37,6 +37,9 @@ def test_damaged_or_incomplete_files_are_a_miss(tmp_path):
     path.write_text("{not json")
     assert A.load_tuning(str(path), "k1") is None
     path.write_text(json.dumps({"k1": {"chunk": 16}}))
+    assert A.load_tuning(str(path), "k1") is None
+    old = {k: v for k, v in TUNE.items() if k != "lanes"}  # stored before lanes existed
+    path.write_text(json.dumps({"k1": old}))
     assert A.load_tuning(str(path), "k1") is None
     path.write_text(json.dumps([1, 2, 3]))
     assert A.load_tuning(str(path), "k1") is None
