@@ -163,8 +163,8 @@ typedef struct {
                           that finish early take more work (same results) */
   int32_t xstep_per_lane; /* lane-per-branch kernel: unlimited branches
                           solved one after another by each lane, 1..8; 0:
-                          automatic, the fewest for which every branch
-                          wavefront fits the device's SIMDs at once        */
+                          automatic: 2 when that makes every branch
+                          wavefront fit the device's SIMDs at once, else 1 */
   int32_t lanes;       /* launch lanes, 1..4 (at most the handle's grids;
                           more are reduced to that): the grids are split
                           into this many groups of about equal branch
@@ -384,8 +384,9 @@ int acopf_serving_plan(const acopf_grid* grids, int32_t n_grids, double budget_b
 
 /* Create a server: plan the slots (budget_bytes <= 0: 90% of the device's
  * free memory), create the handle of homes and slots, set its chunk length
- * (iterations between admissions; 0: the default) and solve every home cold
- * to convergence. Grid arrays are borrowed for the call. Errors: EINVAL,
+ * (iterations between admissions; 0: the default) and one launch lane (its
+ * tuning can be changed through acopf_server_info's handle), and solve every
+ * home cold to convergence. Grid arrays are borrowed for the call. Errors: EINVAL,
  * EBUDGET, ENOMEM, EDEVICE. */
 int acopf_server_create(const acopf_grid* grids, int32_t n_grids, const acopf_params* params,
                         double budget_bytes, int32_t max_slots, int32_t chunk, int32_t device,

@@ -61,10 +61,12 @@ def batch(n_grids: int, tune_iters: int) -> dict:
 
 
 def serve(duration: float, rate: float, with_70k: bool, baseline: bool,
-          chunk: int | None = None) -> dict:
+          chunk: int | None = None, lanes: int | None = None) -> dict:
     grids = serving_grids(with_70k=with_70k)
     reqs = S.poisson_requests(grids, rate, duration)
     srv = S.TrackingServer(grids, chunk=chunk)
+    if lanes:
+        srv.solver.set_tuning(lanes=lanes)
     tuning = srv.solver.tuning()
     out = srv.serve(reqs, realtime=True)
     slots = srv.slots_per_grid
@@ -117,6 +119,8 @@ def main():
     ap.add_argument("--no-baseline", action="store_true")
     ap.add_argument("--chunk", type=int, default=None,
                     help="serving: iterations between admissions (default: the tuned chunk)")
+    ap.add_argument("--lanes", type=int, default=None,
+                    help="serving: launch lanes of the server's handle (default: the library's)")
     ap.add_argument("--track", action="store_true")
     ap.add_argument("--periods", type=int, default=30)
     args = ap.parse_args()
@@ -124,7 +128,7 @@ def main():
         print(json.dumps(batch(args.grids, args.tune_iters)), flush=True)
     if args.serve:
         print(json.dumps(serve(args.duration, args.rate, not args.no_70k,
-                               not args.no_baseline, args.chunk)), flush=True)
+                               not args.no_baseline, args.chunk, args.lanes)), flush=True)
     if args.track:
         print(json.dumps(track(["c2_2kbus", "c3_70kbus"], args.periods)), flush=True)
 

