@@ -4,6 +4,7 @@ one-grid-per-launch method on the same device and inputs.
   python -m paper_2110_06879_amd.bench_systems --batch   # 64 uneven grids, cold, to 1e-4
   python -m paper_2110_06879_amd.bench_systems --serve   # Poisson tracking requests
   python -m paper_2110_06879_amd.bench_systems --track   # 30-period horizon, ramp limits
+  python -m paper_2110_06879_amd.bench_systems --lanes-multigrid  # launch lanes, 1-4 x 70k grids
 
 Prints one JSON line per experiment.
 """
@@ -84,6 +85,76 @@ def serve(duration: float, rate: float, with_70k: bool, baseline: bool,
     return res
 
 
+def lanes_multigrid(iters: int = 200) -> dict:
+    """Launch lanes on handles of one to four copies of the 70k-bus grid
+    (us per grid-iteration over `iters` iterations after a 20-iteration cold
+    start, at one and two lanes), two one-grid handles run from two host
+    threads on their own streams against one after the other, and the
+    64-grid batch cold to 1e-4 at one and two lanes; every lane count's
+    iterates are compared bitwise."""
+    import hashlib
+    import threading
+    import torch
+    g = config_grid("c3_70kbus")
+
+    def digest(s, k):
+        m = hashlib.sha256()
+        for key in ("u", "v", "z", "y", "lam", "bx"):
+            m.update(s.get(key, k).tobytes())
+        return m.hexdigest()
+
+    out = {"experiment": "lanes_multigrid", "iterations": iters, "us_per_grid_iteration": {}}
+    same = True
+    for n in (1, 2, 3, 4):
+        ref = None
+        for lanes in ((1, 2) if n > 1 else (1,)):
+            with A.Solver([g] * n) as s:
+                s.set_tuning(lanes=lanes)
+                s.solve(A.COLD, 20)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s.solve(A.CONTINUE, iters)
+                t = time.perf_counter() - t0
+                out["us_per_grid_iteration"][f"{n}x70k lanes={lanes}"] = t / (iters * n) * 1e6
+                d = [digest(s, k) for k in range(n)]
+                same = same and (ref is None or d == ref)
+                ref = d
+        print(f"{n} x 70k done", file=sys.stderr, flush=True)
+    s1, s2 = A.Solver(g), A.Solver(g)
+    for s in (s1, s2):
+        s.solve(A.COLD, 20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s1.solve(A.CONTINUE, iters)
+    s2.solve(A.CONTINUE, iters)
+    seq = time.perf_counter() - t0
+    for s in (s1, s2):
+        s.solve(A.COLD, 20)
+    ts = [threading.Thread(target=lambda s=s: s.solve(A.CONTINUE, iters)) for s in (s1, s2)]
+    t0 = time.perf_counter()
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    conc = time.perf_counter() - t0
+    same = same and digest(s1, 0) == digest(s2, 0)
+    s1.close()
+    s2.close()
+    out["two_handles_us_per_grid_iteration"] = {"one_after_the_other": seq / (2 * iters) * 1e6,
+                                                "two_threads": conc / (2 * iters) * 1e6}
+    gs = batch_grids(64)
+    out["batch64_seconds"] = {}
+    for lanes in (1, 2):
+        with A.Solver(gs) as s:
+            s.set_tuning(lanes=lanes)
+            t0 = time.perf_counter()
+            r = s.solve(A.COLD)
+            out["batch64_seconds"][f"lanes={lanes}"] = time.perf_counter() - t0
+            out["batch64_converged"] = sum(1 for x in r if x["status"] == A.CONVERGED)
+    out["bitwise_equal"] = same
+    return out
+
+
 def track(names, periods: int) -> dict:
     out = {"experiment": "tracking", "periods": periods, "drift": 0.05, "ramp": 0.02,
            "grids": {}}
@@ -123,6 +194,7 @@ def main():
                     help="serving: launch lanes of the server's handle (default: the library's)")
     ap.add_argument("--track", action="store_true")
     ap.add_argument("--periods", type=int, default=30)
+    ap.add_argument("--lanes-multigrid", action="store_true")
     args = ap.parse_args()
     if args.batch:
         print(json.dumps(batch(args.grids, args.tune_iters)), flush=True)
@@ -131,6 +203,8 @@ def main():
                                not args.no_baseline, args.chunk, args.lanes)), flush=True)
     if args.track:
         print(json.dumps(track(["c2_2kbus", "c3_70kbus"], args.periods)), flush=True)
+    if args.lanes_multigrid:
+        print(json.dumps(lanes_multigrid()), flush=True)
 
 
 if __name__ == "__main__":
