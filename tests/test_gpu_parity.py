@@ -466,6 +466,30 @@ def test_2k_cold_solve_to_convergence_matches_oracle():
         compare(s, orc, label="c2 converged")
 
 
+def test_70k_cold_solve_to_convergence_matches_oracle():
+    """The benchmark's 70k-bus grid from a cold start to the termination tests
+    of Algorithm 1, against the oracle run to its own termination (OpenMP
+    over the host's threads, bitwise its serial results): the same inner and
+    outer iteration counts, the objective within 1e-6 of the oracle's, and
+    every state vector within the parity tolerance."""
+    import os
+    note("parity c3 70k: cold solve to convergence against the oracle")
+    g = config_grid("c3_70kbus")
+    p = A.Params()
+    orc = O.Oracle(g, oparams(p))
+    orc.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    n = orc.solve(0)
+    sc = orc.scalars()
+    assert sc["status"] == 0
+    with A.Solver(g, p) as s:
+        res = s.solve(A.COLD)[0]
+        note(f"gpu {res['inner_iters']} iterations, oracle {n}")
+        assert res["status"] == A.CONVERGED
+        assert res["inner_iters"] == n and res["outer_iters"] == int(sc["outer"])
+        assert abs(res["objective"] - orc.objective()) <= 1e-6 * abs(orc.objective())
+        compare(s, orc, label="c3 converged")
+
+
 def tightened(name, factor):
     g = config_grid(name)
     g.rate = g.rate * factor
