@@ -784,6 +784,11 @@ struct acopf_s {
   double *vmin_b, *vmax_b;  // [nb] voltage limits (solution quality)
   GridCtl* ctl;
   GridCtl* h_ctl = nullptr;  // pinned
+  // pinned copies for results: every grid's control word, objective and
+  // branch-failure count, read together (fetch_results)
+  GridCtl* r_ctl = nullptr;
+  double* r_obj = nullptr;
+  int* r_fail = nullptr;
   unsigned long long* stats;
   double* tmax;          // [nb + 1][3] residual maxima per bus tile
   std::vector<int> grid_tile_h;  // [G + 1] tile range of each grid
@@ -1160,6 +1165,7 @@ void acopf_destroy(acopf_handle h) {
   if (h->qual) (void)hipFree(h->qual);
   h->buf.release();
   if (h->h_ctl) (void)hipHostFree(h->h_ctl);
+  if (h->r_ctl) (void)hipHostFree(h->r_ctl);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
 }
@@ -1419,6 +1425,11 @@ static int create_impl(const acopf_grid* grids, int32_t n_grids, const acopf_par
   HIP_TRY(D.alloc(&h->obj_d, n_grids));
   HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->h_ctl), sizeof(GridCtl) * n_grids,
                         hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->r_ctl),
+                        (sizeof(GridCtl) + sizeof(double) + sizeof(int)) * n_grids,
+                        hipHostMallocDefault));
+  h->r_obj = reinterpret_cast<double*>(h->r_ctl + n_grids);
+  h->r_fail = reinterpret_cast<int*>(h->r_obj + n_grids);
   hipStream_t st = h->stream;
   auto up = [&](void* dst, const void* src, size_t bytes) {
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
@@ -1953,28 +1964,39 @@ static int run_impl(acopf_s* h, int64_t max_iters, bool stop_on_first, int64_t* 
   return settle_outer(h);
 }
 
-static int result_impl(acopf_s* h, int g, acopf_result* r) {
+// Every grid's objective (eq. (acopf)'s generation cost at u), control word
+// and branch-failure count into the pinned result copies: one launch, three
+// copies and one wait, whatever the number of grids asked for.
+static int fetch_results(acopf_s* h) {
   hipStream_t st = h->stream;
   hipLaunchKernelGGL(objective_kernel, dim3(h->G), dim3(256), 0, st, h->gen_off_d, h->c2,
                      h->c1, h->c0, h->u, h->base_d, h->obj_d);
-  double obj = 0.0;
-  int fails = 0;
-  GridCtl c;
-  HIP_TRY(hipMemcpyAsync(&obj, h->obj_d + g, sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(&fails, h->failures + g, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(&c, h->ctl + g, sizeof(GridCtl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(h->r_obj, h->obj_d, sizeof(double) * h->G, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(h->r_fail, h->failures, sizeof(int) * h->G, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(h->r_ctl, h->ctl, sizeof(GridCtl) * h->G, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  return ACOPF_OK;
+}
+
+static void fill_result(const acopf_s* h, int g, acopf_result* r) {
+  const GridCtl& c = h->r_ctl[g];
   r->status = c.done ? c.status : ACOPF_MAX_ITER;
   r->inner_iters = c.inner_total;
   r->outer_iters = c.outer;
-  r->branch_failures = fails;
-  r->objective = obj;
+  r->branch_failures = h->r_fail[g];
+  r->objective = h->r_obj[g];
   r->r_pri = c.r_pri;
   r->r_dual = c.r_dual;
   r->r_z = c.r_z;
   r->beta = c.beta;
   r->seconds = (h->running[g] ? now_s() : h->t_end[g]) - h->t_start[g];
-  return ACOPF_OK;
+}
+
+static int result_impl(acopf_s* h, int g, acopf_result* r) {
+  const int rc = fetch_results(h);
+  if (!rc) fill_result(h, g, r);
+  return rc;
 }
 
 int acopf_solve(acopf_handle h, int32_t mode, int32_t fixed_iters, acopf_result* results) {
@@ -1997,11 +2019,11 @@ int acopf_solve(acopf_handle h, int32_t mode, int32_t fixed_iters, acopf_result*
   rc = run_impl(h, cap, false, nullptr);
   if (rc) return rc;
   h->solved = true;
-  if (results)
-    for (int g = 0; g < h->G; ++g) {
-      rc = result_impl(h, g, &results[g]);
-      if (rc) return rc;
-    }
+  if (results) {
+    rc = fetch_results(h);
+    if (rc) return rc;
+    for (int g = 0; g < h->G; ++g) fill_result(h, g, &results[g]);
+  }
   return ACOPF_OK;
 }
 
