@@ -34,13 +34,15 @@
 //
 // Device layout (structure of arrays, FP64), chosen for the HBM-bound bus
 // step: every bus owns a contiguous range of generators and of branch ends,
-// so the bus kernel streams its couplings; the compute-bound branch step does
-// the scattered accesses instead (24 loads and 8 stores per branch solve).
+// so the bus kernel streams its couplings. The branch step reads its inputs
+// as one 128-byte record per branch (v - z and y of its eight couplings),
+// which the bus step writes in branch order, and does the scattered accesses
+// itself: the eight stores of its coupling values u.
 //   generators: sorted by (grid, bus, input index), range gptr[b]..gptr[b+1];
 //   branch ends: bus CSR order (per bus: from-ends, then to-ends, each in
 //     input order), range eptr[b]..eptr[b+1];
-//   couplings [m]: generator p [n_gen], generator q [n_gen], then end blocks
-//     p, q, w, theta of 2 n_branch each;
+//   couplings [m]: generator p [n_gen], generator q [n_gen], then the four
+//     couplings p, q, w, theta of each branch end, end after end;
 //   branches: rated (6-variable) first, then unlimited (4-variable), each by
 //     (grid, from bus, input index); ef[l], et[l] locate their two ends.
 
@@ -641,23 +643,26 @@ __global__ __launch_bounds__(256) void copy_kernel(CopySegs C) {
 }
 
 // Objective sum_g c2 P^2 + c1 P + c0 with P = base p_g (Sec. IV-A), one block
-// per grid, fixed-order tree reduction.
-__global__ __launch_bounds__(256) void objective_kernel(const int64_t* gen_off,
-                                                       const double* c2, const double* c1,
-                                                       const double* c0, const double* u,
-                                                       const double* base, double* out) {
-  __shared__ double sh[256];
+// of kObjBlock lanes per grid (a 70k grid's 10,000 generators take each lane
+// ten strided steps), fixed-order tree reduction.
+constexpr int kObjBlock = 1024;
+__global__ __launch_bounds__(kObjBlock) void objective_kernel(const int64_t* gen_off,
+                                                             const double* c2, const double* c1,
+                                                             const double* c0, const double* u,
+                                                             const double* base, double* out) {
+  __shared__ double sh[kObjBlock];
   const int g = blockIdx.x;
   const int64_t a = gen_off[g], b = gen_off[g + 1];
+  const double bg = base[g];
   double t = 0.0;
-  for (int64_t k = a + threadIdx.x; k < b; k += blockDim.x) {
-    const double P = base[g] * u[k];
+  for (int64_t k = a + threadIdx.x; k < b; k += kObjBlock) {
+    const double P = bg * u[k];
     t += c2[k] * P * P + c1[k] * P + c0[k];
   }
   sh[threadIdx.x] = t;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+  for (int s = kObjBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) out[g] = sh[0];
@@ -1969,7 +1974,7 @@ static int run_impl(acopf_s* h, int64_t max_iters, bool stop_on_first, int64_t* 
 // copies and one wait, whatever the number of grids asked for.
 static int fetch_results(acopf_s* h) {
   hipStream_t st = h->stream;
-  hipLaunchKernelGGL(objective_kernel, dim3(h->G), dim3(256), 0, st, h->gen_off_d, h->c2,
+  hipLaunchKernelGGL(objective_kernel, dim3(h->G), dim3(kObjBlock), 0, st, h->gen_off_d, h->c2,
                      h->c1, h->c0, h->u, h->base_d, h->obj_d);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(h->r_obj, h->obj_d, sizeof(double) * h->G, hipMemcpyDeviceToHost, st));

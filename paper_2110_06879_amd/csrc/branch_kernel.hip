@@ -11,8 +11,9 @@
 // mixes the two shapes; a lane of the unlimited range may solve several
 // branches one after another, so that every branch wavefront is resident on
 // the device from the start. Branch data are structure-of-arrays (lane l
-// reads element l); the coupling values of a branch's two ends are gathered
-// from the bus-major coupling vectors.
+// reads element l); the values of a branch's eight couplings (v - z and y)
+// come as one 128-byte record per branch that the bus step writes in branch
+// order, and only the coupling values u go back to the bus-major vectors.
 //
 // Besides x and the AL multipliers and penalty, a branch keeps the Cauchy
 // step length of its trust-region solves between ADMM iterations: a solve
@@ -20,10 +21,12 @@
 // ended with (1 after a cold start) rather than from 1, which halves the
 // Cauchy trials once the iterates settle.
 //
-// Arithmetic is a fixed IEEE operation sequence shared with the CPU oracle:
-// no implicit contraction, fused multiply-adds written out where the oracle
-// writes them, a square-root-free Cholesky factor with reciprocal pivots,
-// norm tests in squares, and a series sin/cos.
+// Arithmetic is a fixed IEEE operation sequence that the CPU oracle follows
+// too: no implicit contraction, fused multiply-adds written out where the
+// oracle writes them, a square-root-free Cholesky factor with reciprocal
+// pivots, norm tests in squares, and a series sin/cos. The oracle's textbook
+// evaluation of the same subproblem (the terms of eq. (branch) one by one,
+// Lin & More's scaled Cholesky, libm sin/cos) pins each of these transforms.
 //
 // The free set of a subspace step is handled with a mask over all N
 // variables instead of compressed indices (fixed rows and columns act as
