@@ -186,6 +186,57 @@ def test_edge_grids_match_oracle(waves):
             compare(s, orc, tol=1e-9, label=name)
 
 
+def structural_grid():
+    """A 90-bus grid with the structures a MATPOWER case can hold and the
+    synthetic recipe does not draw: eight parallel lines (half of them
+    reversed, half rated), generators with a fixed real or reactive output
+    (pmin = pmax, qmin = qmax), three generators on one bus, the reference at
+    a generator bus other than bus 0, negative loads, and a bus with
+    vmin = vmax (its w bound interval is a point)."""
+    g = gridgen(90, 12, 120, 0.5, 36, load_factor=0.2)
+    rng = np.random.default_rng(36)
+    pick = rng.choice(g.n_branch, 8, replace=False)
+    rev = np.arange(8) % 2 == 1
+    f = np.where(rev, g.br_to[pick], g.br_from[pick])
+    t = np.where(rev, g.br_from[pick], g.br_to[pick])
+    g.br_from = np.concatenate([g.br_from, f]).astype(g.br_from.dtype)
+    g.br_to = np.concatenate([g.br_to, t]).astype(g.br_to.dtype)
+    g.r = np.concatenate([g.r, rng.uniform(0.005, 0.05, 8)])
+    g.x = np.concatenate([g.x, rng.uniform(0.02, 0.2, 8)])
+    g.b = np.concatenate([g.b, rng.uniform(0.0, 0.05, 8)])
+    g.tap = np.concatenate([g.tap, np.ones(8)])
+    g.shift = np.concatenate([g.shift, np.zeros(8)])
+    g.rate = np.concatenate([g.rate, np.where(np.arange(8) < 4, rng.uniform(1, 3, 8), 0.0)])
+    g.pmin[1:4] = g.pmax[1:4] = 0.5 * g.pmax[1:4]
+    g.qmin[4] = g.qmax[4] = 0.1
+    g.gen_bus[6:8] = g.gen_bus[0]
+    g.ref_bus = int(g.gen_bus[5])
+    g.pd[10:13] = -0.05
+    g.qd[10:13] = -0.01
+    g.vmin[20] = g.vmax[20] = 1.0
+    return g
+
+
+@pytest.mark.parametrize("waves", list(XSTEP))
+def test_structural_edge_cases_match_oracle(waves):
+    note(f"structural edge cases (parallel lines, fixed outputs, shared bus, reference, "
+         f"point bounds), x-step {waves}")
+    g = structural_grid()
+    p = A.Params(rho_pq=400.0, rho_va=4000.0)
+    orc = O.Oracle(g, oparams(p))
+    orc.solve(30)
+    with A.Solver(g, p) as s:
+        s.set_tuning(**XSTEP[waves])
+        s.solve(A.COLD, 30)
+        compare(s, orc, tol=1e-9, label="structural")
+        sg, so = s.solution(), orc.solution()
+        for name, want in so.items():
+            err = np.abs(sg[name] - want).max() / max(np.abs(want).max(), 1e-30)
+            assert err <= 1e-13, (name, err)
+        # the fixed outputs are the generator step's projections onto a point
+        assert np.array_equal(sg["pg"][1:4], g.pmax[1:4]) and sg["qg"][4] == 0.1
+
+
 def star_grid(n_leaf: int, n_gen: int, seed: int):
     """One hub bus joined to n_leaf leaves, with every generator on the hub:
     at a bus block of 64 lanes the hub's branch ends and generators exceed the
