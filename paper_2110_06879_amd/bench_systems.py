@@ -5,6 +5,7 @@ one-grid-per-launch method on the same device and inputs.
   python -m paper_2110_06879_amd.bench_systems --serve   # Poisson tracking requests
   python -m paper_2110_06879_amd.bench_systems --track   # 30-period horizon, ramp limits
   python -m paper_2110_06879_amd.bench_systems --lanes-multigrid  # launch lanes, 1-4 x 70k grids
+  python -m paper_2110_06879_amd.bench_systems --grid-scaling     # 2k to 1.12M buses; 1-16 x 70k
 
 Prints one JSON line per experiment.
 """
@@ -20,7 +21,7 @@ import numpy as np
 from . import acopf as A
 from . import serve as S
 from . import tracking as T
-from .gridgen import batch_grids, config_grid, serving_grids
+from .gridgen import batch_grids, config_grid, gridgen, serving_grids
 
 
 def batch(n_grids: int, tune_iters: int) -> dict:
@@ -155,6 +156,48 @@ def lanes_multigrid(iters: int = 200) -> dict:
     return out
 
 
+def grid_scaling(iters: int = 100) -> dict:
+    """Throughput against size: single grids of the 70k recipe's proportions
+    (one generator per 7 buses, 1.257 branches per bus, 30% rated, load
+    factor 0.2) from 2,000 to 1,120,000 buses, and handles of 1, 4 and 16
+    copies of the 70k-bus grid at two launch lanes. Each point: a cold start
+    of 20 iterations, then `iters` timed iterations between two device
+    synchronizations; device memory held by the handle from the allocator's
+    free-memory counter."""
+    import torch
+    from .gridgen import LOAD_FACTOR
+
+    def point(grids, lanes):
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        with A.Solver(grids) as s:
+            if lanes:
+                s.set_tuning(lanes=lanes)
+            s.solve(A.COLD, 20)
+            torch.cuda.synchronize()
+            held = free0 - torch.cuda.mem_get_info()[0]
+            t0 = time.perf_counter()
+            s.solve(A.CONTINUE, iters)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / iters
+        nbr = sum(g.n_branch for g in grids)
+        return {"buses": int(sum(g.n_bus for g in grids)), "branches": int(nbr),
+                "us_per_iteration": t * 1e6, "branch_solves_per_s": nbr / t,
+                "device_bytes": int(held)}
+
+    out = {"experiment": "grid_scaling", "iterations": iters, "single": [], "copies_of_70k": []}
+    for k, nb in enumerate((2000, 10000, 35000, 70000, 140000, 280000, 560000, 1120000)):
+        g = gridgen(nb, nb // 7, int(round(nb * 88 / 70)), 0.3, 900 + k,
+                    load_factor=LOAD_FACTOR)
+        out["single"].append(point([g], None))
+        print(f"single grid {nb} buses done", file=sys.stderr, flush=True)
+    g = config_grid("c3_70kbus")
+    for n in (1, 4, 16):
+        out["copies_of_70k"].append({"grids": n, **point([g] * n, 2 if n > 1 else None)})
+        print(f"{n} x 70k done", file=sys.stderr, flush=True)
+    return out
+
+
 def track(names, periods: int) -> dict:
     out = {"experiment": "tracking", "periods": periods, "drift": 0.05, "ramp": 0.02,
            "grids": {}}
@@ -195,6 +238,7 @@ def main():
     ap.add_argument("--track", action="store_true")
     ap.add_argument("--periods", type=int, default=30)
     ap.add_argument("--lanes-multigrid", action="store_true")
+    ap.add_argument("--grid-scaling", action="store_true")
     args = ap.parse_args()
     if args.batch:
         print(json.dumps(batch(args.grids, args.tune_iters)), flush=True)
@@ -205,6 +249,8 @@ def main():
         print(json.dumps(track(["c2_2kbus", "c3_70kbus"], args.periods)), flush=True)
     if args.lanes_multigrid:
         print(json.dumps(lanes_multigrid()), flush=True)
+    if args.grid_scaling:
+        print(json.dumps(grid_scaling()), flush=True)
 
 
 if __name__ == "__main__":
