@@ -541,6 +541,27 @@ def test_70k_cold_solve_to_convergence_matches_oracle():
         compare(s, orc, label="c3 converged")
 
 
+def test_largest_grid_matches_oracle():
+    """The largest single grid of the size scaling, 1.12 million buses
+    (160,000 generators, 1,408,000 branches, 30% rated): the x-step puts one
+    unlimited branch on each lane and its launch holds many rounds of
+    wavefronts, and each decision block loops over thousands of tile slots.
+    One graph chunk of 16 iterations from a cold start, in the default launch
+    configuration, against the oracle (OpenMP over the host's threads)."""
+    import os
+    nb = 1120000
+    note("parity 1.12M buses: 16 iterations in one graph chunk")
+    g = gridgen(nb, nb // 7, int(round(nb * 88 / 70)), 0.3, 907, load_factor=0.2)
+    p = A.Params()
+    orc = O.Oracle(g, oparams(p))
+    orc.set_threads(max(1, min(16, os.cpu_count() or 1)))
+    orc.solve(16)
+    with A.Solver(g, p) as s:
+        assert s.tuning()["chunk"] == 16
+        s.solve(A.COLD, 16)
+        compare(s, orc, label="1.12M buses")
+
+
 def tightened(name, factor):
     g = config_grid(name)
     g.rate = g.rate * factor
