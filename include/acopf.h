@@ -193,7 +193,8 @@ int acopf_create(const acopf_grid* grids, int32_t n_grids,
 /* Run Algorithm 1 on every grid of the handle. mode: ACOPF_COLD, ACOPF_WARM
  * or ACOPF_CONTINUE. fixed_iters > 0 runs exactly that many inner
  * iterations (termination tests off; outer updates still happen when the
- * inner test passes). results: [n_grids], may be NULL.
+ * inner test passes). results: [n_grids], may be NULL; when given, every
+ * grid's result is read at the end with one objective launch and one wait.
  * Errors: EINVAL (mode), ESTATE (WARM/CONTINUE before any solve), EDEVICE. */
 int acopf_solve(acopf_handle h, int32_t mode, int32_t fixed_iters,
                 acopf_result* results);
@@ -218,7 +219,8 @@ int acopf_update_loads(acopf_handle h, int32_t grid, const double* pd,
  * them finishes or max_iters inner iterations have run, and reports how many
  * are still running; acopf_poll reads one grid's state and, once finished,
  * its result (seconds = host time from start to the readback that saw it
- * finish). Grids that are not running cost nothing in the launches.
+ * finish; with out non-NULL it waits for the handle's stream). Grids that
+ * are not running cost nothing in the launches.
  * Errors: EINVAL, ESTATE (grid already running, or WARM/CONTINUE on a grid
  * never solved), EDEVICE. */
 int acopf_start(acopf_handle h, int32_t grid, int32_t mode, int32_t fixed_iters);
