@@ -269,6 +269,25 @@ def test_fifty_iterations_agree_between_paths(case):
 
 
 @pytest.mark.slow
+def test_70k_thirty_iterations_agree_between_paths():
+    """The 70k-bus benchmark grid after 30 inner iterations from the cold
+    start: every state vector of the fixed-sequence path equals the textbook
+    path's to 1e-8 (norm-wise), both run over the host's threads."""
+    import os
+    g, p = config_grid("c3_70kbus"), O.OracleParams()
+    a = O.Oracle(g, p)
+    b = O.Oracle(g, p)
+    b.set_textbook(True)
+    for o in (a, b):
+        o.set_threads(max(1, min(8, os.cpu_count() or 1)))
+        o.solve(30)
+    for k in ("u", "v", "z", "y", "lam", "bx", "ltil", "rtil", "calpha"):
+        x, y = a.get(k), b.get(k)
+        den = max(np.abs(y).max(), PARITY_FLOOR.get(k, 1e-30))
+        assert np.abs(x - y).max() / den <= 1e-8, k
+
+
+@pytest.mark.slow
 def test_converged_2k_solve_agrees_between_paths():
     """Cold solve of the 2k-bus grid to the 1e-4 tests: the same iteration
     count (within 2%) and the same objective (1e-6 relative) on both paths."""
