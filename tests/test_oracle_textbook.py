@@ -269,12 +269,17 @@ def test_fifty_iterations_agree_between_paths(case):
 
 
 @pytest.mark.slow
-def test_70k_thirty_iterations_agree_between_paths():
+@pytest.mark.parametrize("name", ["c3_70kbus", "c3_70kbus_full"])
+def test_70k_thirty_iterations_agree_between_paths(name):
     """The 70k-bus benchmark grid after 30 inner iterations from the cold
     start: every state vector of the fixed-sequence path equals the textbook
-    path's to 1e-8 (norm-wise), both run over the host's threads."""
+    path's to 1e-8 (norm-wise), both run over the host's threads. At the
+    stated load distribution (`_full`) about 170 line limits bind and the two
+    paths take the same AL rounds; a handful of TRON decisions at rounding
+    level differ (8 of 6.8 million iterations), and the vectors still agree
+    to 4e-9."""
     import os
-    g, p = config_grid("c3_70kbus"), O.OracleParams()
+    g, p = config_grid(name), O.OracleParams()
     a = O.Oracle(g, p)
     b = O.Oracle(g, p)
     b.set_textbook(True)
@@ -285,6 +290,9 @@ def test_70k_thirty_iterations_agree_between_paths():
         x, y = a.get(k), b.get(k)
         den = max(np.abs(y).max(), PARITY_FLOOR.get(k, 1e-30))
         assert np.abs(x - y).max() / den <= 1e-8, k
+    assert a.stats()["al_iters"] == b.stats()["al_iters"]
+    if name.endswith("_full"):
+        assert (np.abs(a.get("ltil")) > 1e-3).sum() >= 100
 
 
 @pytest.mark.slow
