@@ -6,6 +6,7 @@ one-grid-per-launch method on the same device and inputs.
   python -m paper_2110_06879_amd.bench_systems --track   # 30-period horizon, ramp limits
   python -m paper_2110_06879_amd.bench_systems --lanes-multigrid  # launch lanes, 1-4 x 70k grids
   python -m paper_2110_06879_amd.bench_systems --grid-scaling     # 2k to 1.12M buses; 1-16 x 70k
+  python -m paper_2110_06879_amd.bench_systems --lanes-trace      # 2 x 70k at two lanes (for a trace)
 
 Prints one JSON line per experiment.
 """
@@ -198,6 +199,24 @@ def grid_scaling(iters: int = 100) -> dict:
     return out
 
 
+def lanes_trace(iters: int = 64) -> dict:
+    """Two copies of the 70k-bus grid in one handle at two launch lanes: a
+    cold start of 20 iterations, then `iters` iterations, for a kernel trace
+    of how the lanes' launches overlap."""
+    import torch
+    g = config_grid("c3_70kbus")
+    with A.Solver([g, g]) as s:
+        s.set_tuning(lanes=2)
+        s.solve(A.COLD, 20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.solve(A.CONTINUE, iters)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+    return {"experiment": "lanes_trace", "grids": 2, "lanes": 2, "iterations": iters,
+            "us_per_grid_iteration": t / (2 * iters) * 1e6}
+
+
 def track(names, periods: int) -> dict:
     out = {"experiment": "tracking", "periods": periods, "drift": 0.05, "ramp": 0.02,
            "grids": {}}
@@ -239,6 +258,7 @@ def main():
     ap.add_argument("--periods", type=int, default=30)
     ap.add_argument("--lanes-multigrid", action="store_true")
     ap.add_argument("--grid-scaling", action="store_true")
+    ap.add_argument("--lanes-trace", action="store_true")
     args = ap.parse_args()
     if args.batch:
         print(json.dumps(batch(args.grids, args.tune_iters)), flush=True)
@@ -251,6 +271,8 @@ def main():
         print(json.dumps(lanes_multigrid()), flush=True)
     if args.grid_scaling:
         print(json.dumps(grid_scaling()), flush=True)
+    if args.lanes_trace:
+        print(json.dumps(lanes_trace()), flush=True)
 
 
 if __name__ == "__main__":
