@@ -245,7 +245,9 @@ def main():
     ap.add_argument("--batch", action="store_true")
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--grids", type=int, default=64)
-    ap.add_argument("--tune-iters", type=int, default=16)
+    ap.add_argument("--tune-iters", type=int, default=0,
+                    help="batch: autotune the launch shape over this many iterations first "
+                         "(0: the library's defaults)")
     ap.add_argument("--duration", type=float, default=10.0)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--no-70k", action="store_true")
