@@ -366,6 +366,45 @@ def test_server_commits_each_finished_slot_as_home():
         srv.close()
 
 
+def test_two_handles_on_two_host_threads_equal_one_after_the_other():
+    """Handles are independent: two handles on their own streams, driven from
+    two host threads at once (cold solves, then warm starts after new loads),
+    end with bitwise the iterates of the same solves run one after the
+    other."""
+    import threading
+    gs = [gridgen(400 + 100 * k, 60 + 10 * k, 520 + 130 * k, 0.5, 140 + k, load_factor=0.2)
+          for k in range(2)]
+    loads = [perturb_loads(g, 0.02, 1400 + k) for k, g in enumerate(gs)]
+
+    def run(g, ld, out, k):
+        with A.Solver(g) as s:
+            s.solve(A.COLD, 40)
+            s.update_loads(0, *ld)
+            out[k] = (s.solve(A.WARM, 30)[0], states(s))
+
+    seq, par = {}, {}
+    for k in range(2):
+        run(gs[k], loads[k], seq, k)
+    errs = []
+
+    def guarded(k):
+        try:
+            run(gs[k], loads[k], par, k)
+        except Exception as e:  # surfaced below
+            errs.append(e)
+
+    ts = [threading.Thread(target=guarded, args=(k,)) for k in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errs, errs
+    for k in range(2):
+        assert seq[k][0]["inner_iters"] == par[k][0]["inner_iters"]
+        assert seq[k][0]["objective"] == par[k][0]["objective"]
+        assert_same(seq[k][1], par[k][1])
+
+
 @pytest.mark.parametrize("lanes", [2, 4])
 def test_launch_lanes_equal_one_lane(lanes):
     """Launch lanes: the grids of a handle split into groups launched on
