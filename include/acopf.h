@@ -20,6 +20,10 @@
  * Return codes: 0 on success, a negative ACOPF_E* value on error, with a
  * message available from acopf_last_error() (thread-local). Non-convergence
  * is not an error: it is reported in acopf_result.status.
+ *
+ * Threads: handles are independent, and different handles may be driven
+ * from different host threads at once (each on its own stream). The calls
+ * on one handle must not overlap; a handle has no lock of its own.
  */
 #ifndef ACOPF_H
 #define ACOPF_H
